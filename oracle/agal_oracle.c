@@ -1,0 +1,1021 @@
+/*
+ * agal_oracle.c -- plain, serial, slow CPU oracle for the near-wall
+ * mesh-adaptation path of "Towards a GPU-native adaptive mesh refinement
+ * scheme for the Lattice Boltzmann Method in complex geometries"
+ * (Jaber, Essel, Sullivan, 2025).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline leg use it.  It shares no code, header, table or constant with the
+ * HIP library.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fPIC -shared.
+ * On x86-64 every float expression below is evaluated in IEEE single
+ * precision (SSE, FLT_EVAL_METHOD == 0) with no contraction into FMA, so the
+ * FP32 parts (bins, cell centres, the separating-axis predicate) are a fixed
+ * sequence of correctly rounded operations.  Link fractions, the adjoint and
+ * the finite-difference harness run in FP64 on the FP32 inputs promoted
+ * exactly.
+ *
+ * What each part follows:
+ *  - import (index lists -> coordinate list): paper, Sec. II-B and the
+ *    index/coordinate-list figure.
+ *  - binning: paper, Sec. II-C-3 (bins of user density B over the initial
+ *    grid, three arrays: ids grouped by bin, per-bin counts, first index).
+ *    Bin membership here is the face's axis-aligned bounding box (every bin
+ *    the box touches), ids ascending inside a bin.
+ *  - flagging: paper, Sec. II-C-1/II-C-2: every cell of every block of a
+ *    level tests adjacency to the faces of its bins; a block is marked when
+ *    one of its cells is adjacent.  Adjacency is the closed-box reading: the
+ *    face meets the closed cube of half-width d centred on the cell centre,
+ *    decided by the 13-axis separating-axis test (the L-infinity form of the
+ *    paper's distance criterion; Algorithm 1 is provided separately below as
+ *    the L2 cross-check).
+ *  - refinement: Sec. II-A (forest of octrees, blocks of 4^D cells, one level
+ *    at a time) and Sec. II-C-1 (marked blocks are subdivided); 2:1 balance
+ *    across faces, edges and corners is closed by a downward ripple.
+ *  - link fractions: Sec. II-C-1 (cells find links with faces along each
+ *    lattice direction): q is the fraction of the segment x -> x + c_i dx at
+ *    which it first meets a face (closed faces, two-sided).
+ *  - adjoint: derivative of q with respect to the vertices of the hit face,
+ *    dq/dv_k = lambda_k n / (Dv . n).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAXL 8
+
+static void *xmalloc(size_t n) {
+    void *p = malloc(n ? n : 1);
+    if (!p) { fprintf(stderr, "oracle: out of memory (%zu bytes)\n", n); abort(); }
+    return p;
+}
+static void *xcalloc(size_t n, size_t s) {
+    void *p = calloc(n ? n : 1, s ? s : 1);
+    if (!p) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+    return p;
+}
+static void *xrealloc(void *p, size_t n) {
+    void *q = realloc(p, n ? n : 1);
+    if (!q) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+    return q;
+}
+
+static float fmin2(float a, float b) { return a < b ? a : b; }
+static float fmax2(float a, float b) { return a > b ? a : b; }
+static float fabs1(float a) { return a < 0.0f ? -a : a; }
+
+/* ------------------------------------------------------------------ */
+/* Lattice velocity sets.  Order: rest; axis directions in +/- pairs;   */
+/* then (3D) the 12 edge directions in +/- pairs; then (D3Q27) the 8    */
+/* corner directions in +/- pairs.  D2Q9: rest, (+-1,0), (0,+-1), then  */
+/* the diagonals in +/- pairs.                                          */
+/* ------------------------------------------------------------------ */
+static const int D2Q9_C[9][3] = {
+    {0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+static const int D3Q27_C[27][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+    {1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+    {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
+
+/* Fills c[Q][3]; returns the lattice's dimension or -1. */
+int orc_lattice(int Q, int *c) {
+    const int (*src)[3];
+    int dim;
+    if (Q == 9) { src = D2Q9_C; dim = 2; }
+    else if (Q == 19 || Q == 27) { src = D3Q27_C; dim = 3; }
+    else return -1;
+    for (int i = 0; i < Q; ++i)
+        for (int a = 0; a < 3; ++a) c[3 * i + a] = src[i][a];
+    return dim;
+}
+
+/* ------------------------------------------------------------------ */
+/* Import: index lists -> coordinate list                               */
+/* coords[(f*dim + k)*dim + a] = verts[faces[f*dim+k]*dim + a]          */
+/* ------------------------------------------------------------------ */
+void orc_gather(int dim, const float *verts, const int32_t *faces, int64_t F, float *coords) {
+    for (int64_t f = 0; f < F; ++f)
+        for (int k = 0; k < dim; ++k)
+            for (int a = 0; a < dim; ++a)
+                coords[(f * dim + k) * dim + a] = verts[(int64_t)faces[f * dim + k] * dim + a];
+}
+
+/* ------------------------------------------------------------------ */
+/* Bins (FP32)                                                          */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int dim, B;
+    float lo[3], hi[3], s[3];
+    int64_t nb, P;
+    uint32_t *count, *off;
+    int32_t *ids;
+} orc_bins;
+
+/* Bin index of coordinate x along one axis: floor((x - lo) * s), clamped to [0, B-1]
+ * (clamped in float before the integer conversion so any finite x is defined). */
+static int bin_index(float x, float lo, float s, int B) {
+    float t = (x - lo) * s;
+    float f = floorf(t);
+    if (f < 0.0f) return 0;
+    if (f > (float)(B - 1)) return B - 1;
+    return (int)f;
+}
+
+static void face_bin_range(const orc_bins *bn, const float *fc, int lo_i[3], int hi_i[3]) {
+    int dim = bn->dim;
+    for (int a = 0; a < 3; ++a) { lo_i[a] = 0; hi_i[a] = 0; }
+    for (int a = 0; a < dim; ++a) {
+        float mn = fc[a], mx = fc[a];
+        for (int k = 1; k < dim; ++k) {
+            mn = fmin2(mn, fc[k * dim + a]);
+            mx = fmax2(mx, fc[k * dim + a]);
+        }
+        lo_i[a] = bin_index(mn, bn->lo[a], bn->s[a], bn->B);
+        hi_i[a] = bin_index(mx, bn->lo[a], bn->s[a], bn->B);
+    }
+}
+
+orc_bins *orc_bin_faces(int dim, const float *coords, int64_t F, const float *lo, const float *hi, int B) {
+    orc_bins *bn = (orc_bins *)xcalloc(1, sizeof(orc_bins));
+    bn->dim = dim;
+    bn->B = B;
+    bn->nb = 1;
+    for (int a = 0; a < 3; ++a) {
+        bn->lo[a] = a < dim ? lo[a] : 0.0f;
+        bn->hi[a] = a < dim ? hi[a] : 1.0f;
+        bn->s[a] = (float)B / (bn->hi[a] - bn->lo[a]);
+        if (a < dim) bn->nb *= B;
+    }
+    bn->count = (uint32_t *)xcalloc((size_t)bn->nb, sizeof(uint32_t));
+    bn->off = (uint32_t *)xcalloc((size_t)bn->nb + 1, sizeof(uint32_t));
+    /* pass 1: count */
+    for (int64_t f = 0; f < F; ++f) {
+        int l[3], h[3];
+        face_bin_range(bn, coords + f * dim * dim, l, h);
+        for (int z = l[2]; z <= h[2]; ++z)
+            for (int y = l[1]; y <= h[1]; ++y)
+                for (int x = l[0]; x <= h[0]; ++x)
+                    bn->count[((int64_t)z * B + y) * B + x] += 1;
+    }
+    /* exclusive scan */
+    uint64_t run = 0;
+    for (int64_t b = 0; b < bn->nb; ++b) { bn->off[b] = (uint32_t)run; run += bn->count[b]; }
+    bn->off[bn->nb] = (uint32_t)run;
+    bn->P = (int64_t)run;
+    /* pass 2: append in ascending face order */
+    bn->ids = (int32_t *)xmalloc((size_t)bn->P * sizeof(int32_t));
+    uint32_t *cur = (uint32_t *)xcalloc((size_t)bn->nb, sizeof(uint32_t));
+    for (int64_t f = 0; f < F; ++f) {
+        int l[3], h[3];
+        face_bin_range(bn, coords + f * dim * dim, l, h);
+        for (int z = l[2]; z <= h[2]; ++z)
+            for (int y = l[1]; y <= h[1]; ++y)
+                for (int x = l[0]; x <= h[0]; ++x) {
+                    int64_t b = ((int64_t)z * B + y) * B + x;
+                    bn->ids[bn->off[b] + cur[b]++] = (int32_t)f;
+                }
+    }
+    free(cur);
+    return bn;
+}
+
+void orc_bins_free(orc_bins *bn) {
+    if (!bn) return;
+    free(bn->count); free(bn->off); free(bn->ids); free(bn);
+}
+int64_t orc_bins_nb(const orc_bins *bn) { return bn->nb; }
+int64_t orc_bins_P(const orc_bins *bn) { return bn->P; }
+const uint32_t *orc_bins_count(const orc_bins *bn) { return bn->count; }
+const uint32_t *orc_bins_off(const orc_bins *bn) { return bn->off; }
+const int32_t *orc_bins_ids(const orc_bins *bn) { return bn->ids; }
+
+/* ------------------------------------------------------------------ */
+/* Separating-axis predicate (FP32, closed sets).  Returns 1 when the  */
+/* face meets the closed cube [m-h, m+h]^D, 0 when an axis separates    */
+/* them (strict '>' only).                                              */
+/* ------------------------------------------------------------------ */
+static int sep_interval3(float p0, float p1, float p2, float r) {
+    float mn = fmin2(fmin2(p0, p1), p2);
+    float mx = fmax2(fmax2(p0, p1), p2);
+    return (mn > r) || (mx < -r);
+}
+
+static int sat_tri(const float *v, const float *m, float h) {
+    float A[3], Bv[3], C[3];
+    for (int a = 0; a < 3; ++a) {
+        A[a] = v[0 * 3 + a] - m[a];
+        Bv[a] = v[1 * 3 + a] - m[a];
+        C[a] = v[2 * 3 + a] - m[a];
+    }
+    /* the three box axes */
+    for (int a = 0; a < 3; ++a)
+        if (sep_interval3(A[a], Bv[a], C[a], h)) return 0;
+    float E0[3], E1[3], E2[3];
+    for (int a = 0; a < 3; ++a) {
+        E0[a] = Bv[a] - A[a];
+        E1[a] = C[a] - Bv[a];
+        E2[a] = A[a] - C[a];
+    }
+    /* the face normal N = E0 x E1 */
+    float N[3];
+    N[0] = E0[1] * E1[2] - E0[2] * E1[1];
+    N[1] = E0[2] * E1[0] - E0[0] * E1[2];
+    N[2] = E0[0] * E1[1] - E0[1] * E1[0];
+    float s = (N[0] * A[0] + N[1] * A[1]) + N[2] * A[2];
+    float r = h * ((fabs1(N[0]) + fabs1(N[1])) + fabs1(N[2]));
+    if (s > r || s < -r) return 0;
+    /* nine edge-cross-axis axes: e_k x E for k in {x,y,z}, E in {E0,E1,E2} */
+    const float *E[3] = {E0, E1, E2};
+    const float *P[3] = {A, Bv, C};
+    for (int j = 0; j < 3; ++j) {
+        const float *e = E[j];
+        for (int k = 0; k < 3; ++k) {
+            /* nonzero components (u, v) of e_k x e, in increasing axis order */
+            int iu, iv;
+            float au, av;
+            if (k == 0) { iu = 1; iv = 2; au = -e[2]; av = e[1]; }
+            else if (k == 1) { iu = 0; iv = 2; au = e[2]; av = -e[0]; }
+            else { iu = 0; iv = 1; au = -e[1]; av = e[0]; }
+            float p0 = au * P[0][iu] + av * P[0][iv];
+            float p1 = au * P[1][iu] + av * P[1][iv];
+            float p2 = au * P[2][iu] + av * P[2][iv];
+            float rr = h * (fabs1(au) + fabs1(av));
+            if (sep_interval3(p0, p1, p2, rr)) return 0;
+        }
+    }
+    return 1;
+}
+
+static int sat_seg(const float *v, const float *m, float h) {
+    float A[2], Bv[2];
+    for (int a = 0; a < 2; ++a) {
+        A[a] = v[0 * 2 + a] - m[a];
+        Bv[a] = v[1 * 2 + a] - m[a];
+    }
+    for (int a = 0; a < 2; ++a) {
+        float mn = fmin2(A[a], Bv[a]), mx = fmax2(A[a], Bv[a]);
+        if (mn > h || mx < -h) return 0;
+    }
+    float Nx = -(Bv[1] - A[1]);
+    float Ny = Bv[0] - A[0];
+    float pA = Nx * A[0] + Ny * A[1];
+    float pB = Nx * Bv[0] + Ny * Bv[1];
+    float r = h * (fabs1(Nx) + fabs1(Ny));
+    float mn = fmin2(pA, pB), mx = fmax2(pA, pB);
+    if (mn > r || mx < -r) return 0;
+    return 1;
+}
+
+int orc_sat(int dim, const float *face, const float *m, float h) {
+    return dim == 3 ? sat_tri(face, m, h) : sat_seg(face, m, h);
+}
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 1 (point within distance R of a triangle: three vertex     */
+/* spheres, three edge cylinders, one prism), FP64, closed.  2D: two    */
+/* discs and one rectangle.  Cross-check only: L2-near(d) implies the   */
+/* closed-box predicate at d, which implies L2-near(sqrt(D) d).         */
+/* ------------------------------------------------------------------ */
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double *a, const double *b, double *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+int orc_near_face_l2(int dim, const double *v, const double *p, double R) {
+    if (dim == 3) {
+        for (int k = 0; k < 3; ++k) {
+            const double *vk = v + 3 * k, *vn = v + 3 * ((k + 1) % 3);
+            double dvp[3], e[3], cr[3], dn[3];
+            for (int a = 0; a < 3; ++a) { dvp[a] = vk[a] - p[a]; e[a] = vn[a] - vk[a]; dn[a] = vn[a] - p[a]; }
+            if (dot3(dvp, dvp) <= R * R) return 1;                      /* sphere */
+            double ee = dot3(e, e);
+            if (ee > 0.0) {
+                cross3(e, dvp, cr);
+                double d2 = dot3(cr, cr) / ee;
+                double de1 = -dot3(dvp, e), de2 = dot3(dn, e);
+                if (d2 <= R * R && de1 >= 0.0 && de2 >= 0.0) return 1;  /* cylinder */
+            }
+        }
+        double e0[3], e1[3], n[3];
+        for (int a = 0; a < 3; ++a) { e0[a] = v[3 + a] - v[a]; e1[a] = v[6 + a] - v[a]; }
+        cross3(e0, e1, n);
+        double nn = sqrt(dot3(n, n));
+        if (nn == 0.0) return 0;
+        for (int a = 0; a < 3; ++a) n[a] /= nn;
+        int pos = 1, neg = 1;
+        for (int k = 0; k < 3; ++k) {
+            const double *vk = v + 3 * k, *vn = v + 3 * ((k + 1) % 3);
+            double e[3], en[3], dvp[3];
+            for (int a = 0; a < 3; ++a) { e[a] = vn[a] - vk[a]; dvp[a] = vk[a] - p[a]; }
+            cross3(e, n, en);
+            double sgn = -dot3(dvp, en);
+            if (sgn < 0.0) pos = 0;
+            if (sgn > 0.0) neg = 0;
+        }
+        double dpl[3];
+        for (int a = 0; a < 3; ++a) dpl[a] = p[a] - v[a];
+        double hgt = dot3(dpl, n);
+        return (pos || neg) && (hgt <= R && hgt >= -R);                 /* prism */
+    } else {
+        for (int k = 0; k < 2; ++k) {
+            double dx = v[2 * k] - p[0], dy = v[2 * k + 1] - p[1];
+            if (dx * dx + dy * dy <= R * R) return 1;                   /* discs */
+        }
+        double ex = v[2] - v[0], ey = v[3] - v[1];
+        double ee = ex * ex + ey * ey;
+        if (ee == 0.0) return 0;
+        double wx = p[0] - v[0], wy = p[1] - v[1];
+        double along = (wx * ex + wy * ey) / ee;
+        double cr = ex * wy - ey * wx;
+        return along >= 0.0 && along <= 1.0 && cr * cr <= R * R * ee;  /* rectangle */
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Forest of quadtrees/octrees.  Roots form an R_x x R_y (x R_z) grid;  */
+/* each tree node is a block of 4^D cells.  Block keys are hierarchical:*/
+/* a root's key is its x-fastest linear index, a child's key is          */
+/* parent_key * 2^D + child index (x-fastest), so sorting the keys of   */
+/* one level orders its blocks root by root and Morton order inside.    */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    uint32_t key;
+    int32_t c[3];       /* block coordinates at its level */
+    uint8_t leaf, mark, pass_mark;
+    uint8_t cf[64];     /* per-cell flag (tested blocks only) */
+} orc_block;
+
+typedef struct { orc_block *b; int64_t n, cap; } orc_level;
+
+typedef struct orc_forest {
+    int dim, L;
+    int roots[3];
+    float lo[3], hi[3];
+    float dx[ORC_MAXL + 1][3];
+    float d[ORC_MAXL];
+    orc_level lev[ORC_MAXL + 1];
+    int64_t tests[ORC_MAXL + 1];
+    /* exported arrays */
+    uint32_t *ek[ORC_MAXL + 1];
+    uint8_t *eleaf[ORC_MAXL + 1], *emark[ORC_MAXL + 1], *ecf[ORC_MAXL + 1];
+} orc_forest;
+
+static uint32_t key_of(const orc_forest *fo, int level, const int32_t *c) {
+    uint32_t r0 = (uint32_t)(c[0] >> level), r1 = (uint32_t)(c[1] >> level), r2 = 0;
+    if (fo->dim == 3) r2 = (uint32_t)(c[2] >> level);
+    uint32_t key = (r2 * (uint32_t)fo->roots[1] + r1) * (uint32_t)fo->roots[0] + r0;
+    for (int j = level - 1; j >= 0; --j) {
+        uint32_t ci = (uint32_t)((c[0] >> j) & 1) | ((uint32_t)((c[1] >> j) & 1) << 1);
+        if (fo->dim == 3) ci |= (uint32_t)((c[2] >> j) & 1) << 2;
+        key = key * (fo->dim == 3 ? 8u : 4u) + ci;
+    }
+    return key;
+}
+
+static void level_push(orc_level *lv, const orc_block *b) {
+    if (lv->n == lv->cap) {
+        lv->cap = lv->cap ? 2 * lv->cap : 64;
+        lv->b = (orc_block *)xrealloc(lv->b, (size_t)lv->cap * sizeof(orc_block));
+    }
+    lv->b[lv->n++] = *b;
+}
+
+static int cmp_block(const void *x, const void *y) {
+    uint32_t a = ((const orc_block *)x)->key, b = ((const orc_block *)y)->key;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+static orc_block *level_find(orc_level *lv, uint32_t key) {
+    int64_t lo = 0, hi = lv->n - 1;
+    while (lo <= hi) {
+        int64_t mid = (lo + hi) / 2;
+        uint32_t k = lv->b[mid].key;
+        if (k == key) return &lv->b[mid];
+        if (k < key) lo = mid + 1; else hi = mid - 1;
+    }
+    return NULL;
+}
+
+/* Cell centre: m_a = lo_a + (float)(2 g_a + 1) * (0.5f * dx_a) with g = 4*block + cell. */
+static void cell_center(const orc_forest *fo, int level, const int32_t *bc, int cell, float *m) {
+    int cc[3] = {cell & 3, (cell >> 2) & 3, (cell >> 4) & 3};
+    for (int a = 0; a < fo->dim; ++a) {
+        int32_t g = 4 * bc[a] + cc[a];
+        m[a] = fo->lo[a] + (float)(2 * g + 1) * (0.5f * fo->dx[level][a]);
+    }
+}
+
+static const float ORC_EPS = 9.5367431640625e-07f; /* 2^-20 */
+
+/* Does any face of the candidate set meet the closed cube [m-h, m+h]? */
+static int cell_flag(const orc_forest *fo, const float *coords, int64_t F, const orc_bins *bn,
+                     const float *m, float h, int64_t *ntests) {
+    int dim = fo->dim;
+    if (!bn) {
+        *ntests += F;
+        for (int64_t f = 0; f < F; ++f)
+            if (orc_sat(dim, coords + f * dim * dim, m, h)) return 1;
+        return 0;
+    }
+    int l[3] = {0, 0, 0}, u[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) {
+        float qlo = (m[a] - h) - ORC_EPS;
+        float qhi = (m[a] + h) + ORC_EPS;
+        l[a] = bin_index(qlo, bn->lo[a], bn->s[a], bn->B);
+        u[a] = bin_index(qhi, bn->lo[a], bn->s[a], bn->B);
+    }
+    int B = bn->B, hit = 0;
+    for (int z = l[2]; z <= u[2]; ++z)
+        for (int y = l[1]; y <= u[1]; ++y)
+            for (int x = l[0]; x <= u[0]; ++x) {
+                int64_t b = ((int64_t)z * B + y) * B + x;
+                *ntests += bn->count[b];
+                if (hit) continue;
+                for (uint32_t j = bn->off[b]; j < bn->off[b + 1]; ++j) {
+                    int32_t f = bn->ids[j];
+                    if (orc_sat(dim, coords + (int64_t)f * dim * dim, m, h)) { hit = 1; break; }
+                }
+            }
+    return hit;
+}
+
+static void forest_export(orc_forest *fo) {
+    int cells = fo->dim == 3 ? 64 : 16;
+    for (int l = 0; l <= fo->L; ++l) {
+        orc_level *lv = &fo->lev[l];
+        fo->ek[l] = (uint32_t *)xmalloc((size_t)lv->n * sizeof(uint32_t));
+        fo->eleaf[l] = (uint8_t *)xmalloc((size_t)lv->n);
+        fo->emark[l] = (uint8_t *)xmalloc((size_t)lv->n);
+        fo->ecf[l] = (uint8_t *)xmalloc((size_t)lv->n * cells);
+        for (int64_t i = 0; i < lv->n; ++i) {
+            fo->ek[l][i] = lv->b[i].key;
+            fo->eleaf[l][i] = lv->b[i].leaf;
+            fo->emark[l][i] = lv->b[i].mark;
+            memcpy(fo->ecf[l] + i * cells, lv->b[i].cf, (size_t)cells);
+        }
+    }
+}
+
+/*
+ * Level-by-level near-wall refinement.  For pass l = 0..L-1:
+ *  (i)   every cell of every block present at level l at the start of the
+ *        pass is tested with h = d[l]; the block is flagged (mark 1) when one
+ *        of its cells is;
+ *  (ii)  ripple for m = l down to 1: for each block of level m marked in this
+ *        pass and each of its 3^D - 1 neighbour positions inside the domain
+ *        with no level-m block, the covering level-(m-1) leaf is marked
+ *        (mark 2, balance);
+ *  (iii) every block marked in this pass becomes a parent of 2^D leaf
+ *        children one level down (child index x-fastest).
+ * Blocks created in pass l are not tested in pass l.
+ * bins == NULL selects the brute-force face loop.
+ */
+orc_forest *orc_refine(int dim, const float *coords, int64_t F, const orc_bins *bn, const int *roots,
+                       int L, const float *d_spec, const float *lo, const float *hi) {
+    if (L < 0 || L > ORC_MAXL) return NULL;
+    orc_forest *fo = (orc_forest *)xcalloc(1, sizeof(orc_forest));
+    fo->dim = dim;
+    fo->L = L;
+    for (int a = 0; a < 3; ++a) {
+        fo->roots[a] = a < dim ? roots[a] : 1;
+        fo->lo[a] = a < dim ? lo[a] : 0.0f;
+        fo->hi[a] = a < dim ? hi[a] : 1.0f;
+    }
+    for (int l = 0; l <= L; ++l)
+        for (int a = 0; a < 3; ++a)
+            fo->dx[l][a] = (fo->hi[a] - fo->lo[a]) / (float)(4 * fo->roots[a] * (1 << l));
+    for (int l = 0; l < L; ++l) fo->d[l] = d_spec[l];
+    int cells = dim == 3 ? 64 : 16;
+    int nch = dim == 3 ? 8 : 4;
+
+    /* level 0: all roots */
+    for (int z = 0; z < fo->roots[2]; ++z)
+        for (int y = 0; y < fo->roots[1]; ++y)
+            for (int x = 0; x < fo->roots[0]; ++x) {
+                orc_block b;
+                memset(&b, 0, sizeof b);
+                b.c[0] = x; b.c[1] = y; b.c[2] = z;
+                b.key = key_of(fo, 0, b.c);
+                b.leaf = 1;
+                level_push(&fo->lev[0], &b);
+            }
+    qsort(fo->lev[0].b, (size_t)fo->lev[0].n, sizeof(orc_block), cmp_block);
+
+    for (int l = 0; l < L; ++l) {
+        for (int m = 0; m <= l; ++m)
+            for (int64_t i = 0; i < fo->lev[m].n; ++i) fo->lev[m].b[i].pass_mark = 0;
+        /* (i) flag */
+        orc_level *lv = &fo->lev[l];
+        for (int64_t i = 0; i < lv->n; ++i) {
+            orc_block *b = &lv->b[i];
+            int any = 0;
+            for (int c = 0; c < cells; ++c) {
+                float m[3] = {0, 0, 0};
+                cell_center(fo, l, b->c, c, m);
+                b->cf[c] = (uint8_t)cell_flag(fo, coords, F, bn, m, fo->d[l], &fo->tests[l]);
+                any |= b->cf[c];
+            }
+            if (any) { b->mark = 1; b->pass_mark = 1; }
+        }
+        /* (ii) ripple */
+        for (int m = l; m >= 1; --m) {
+            orc_level *cur = &fo->lev[m];
+            for (int64_t i = 0; i < cur->n; ++i) {
+                orc_block *b = &cur->b[i];
+                if (!b->pass_mark) continue;
+                for (int dz = (dim == 3 ? -1 : 0); dz <= (dim == 3 ? 1 : 0); ++dz)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            if (!dx && !dy && !dz) continue;
+                            int32_t nc[3] = {b->c[0] + dx, b->c[1] + dy, b->c[2] + dz};
+                            int inside = 1;
+                            for (int a = 0; a < dim; ++a)
+                                if (nc[a] < 0 || nc[a] >= fo->roots[a] << m) inside = 0;
+                            if (!inside) continue;
+                            if (level_find(cur, key_of(fo, m, nc))) continue;
+                            int32_t pc[3] = {nc[0] >> 1, nc[1] >> 1, dim == 3 ? nc[2] >> 1 : 0};
+                            orc_block *p = level_find(&fo->lev[m - 1], key_of(fo, m - 1, pc));
+                            if (!p || !p->leaf) {
+                                fprintf(stderr, "oracle: forest lost 2:1 balance\n");
+                                abort();
+                            }
+                            if (!p->pass_mark) { p->pass_mark = 2; p->mark = 2; }
+                        }
+            }
+        }
+        /* (iii) children */
+        for (int m = l; m >= 0; --m) {
+            orc_level *cur = &fo->lev[m];
+            int64_t n0 = cur->n;
+            for (int64_t i = 0; i < n0; ++i) {
+                orc_block *b = &fo->lev[m].b[i];
+                if (!b->pass_mark) continue;
+                b->leaf = 0;
+                for (int ci = 0; ci < nch; ++ci) {
+                    orc_block ch;
+                    memset(&ch, 0, sizeof ch);
+                    ch.c[0] = 2 * b->c[0] + (ci & 1);
+                    ch.c[1] = 2 * b->c[1] + ((ci >> 1) & 1);
+                    ch.c[2] = dim == 3 ? 2 * b->c[2] + ((ci >> 2) & 1) : 0;
+                    ch.key = b->key * (uint32_t)nch + (uint32_t)ci;
+                    ch.leaf = 1;
+                    level_push(&fo->lev[m + 1], &ch);
+                }
+            }
+            qsort(fo->lev[m + 1].b, (size_t)fo->lev[m + 1].n, sizeof(orc_block), cmp_block);
+        }
+    }
+    forest_export(fo);
+    return fo;
+}
+
+void orc_forest_free(orc_forest *fo) {
+    if (!fo) return;
+    for (int l = 0; l <= ORC_MAXL; ++l) {
+        free(fo->lev[l].b); free(fo->ek[l]); free(fo->eleaf[l]); free(fo->emark[l]); free(fo->ecf[l]);
+    }
+    free(fo);
+}
+int64_t orc_forest_n(const orc_forest *fo, int l) { return (l < 0 || l > fo->L) ? -1 : fo->lev[l].n; }
+const uint32_t *orc_forest_keys(const orc_forest *fo, int l) { return fo->ek[l]; }
+const uint8_t *orc_forest_leaf(const orc_forest *fo, int l) { return fo->eleaf[l]; }
+const uint8_t *orc_forest_mark(const orc_forest *fo, int l) { return fo->emark[l]; }
+const uint8_t *orc_forest_cell_flag(const orc_forest *fo, int l) { return fo->ecf[l]; }
+int64_t orc_forest_tests(const orc_forest *fo, int l) { return fo->tests[l]; }
+
+/* ------------------------------------------------------------------ */
+/* Link fractions (FP64).                                               */
+/* ------------------------------------------------------------------ */
+/* Segment o + t*D, t in [0,1], against the closed triangle (a,b,c), two-sided
+ * (Moller-Trumbore).  Returns 1 and t, u, v on a hit; det == 0 is no hit. */
+static int ray_tri(const double *o, const double *Dv, const double *a, const double *b, const double *c,
+                   double *t_out, double *u_out, double *v_out) {
+    double E1[3], E2[3], P[3], T[3], Qv[3];
+    for (int k = 0; k < 3; ++k) { E1[k] = b[k] - a[k]; E2[k] = c[k] - a[k]; }
+    cross3(Dv, E2, P);
+    double det = dot3(E1, P);
+    if (det == 0.0) return 0;
+    for (int k = 0; k < 3; ++k) T[k] = o[k] - a[k];
+    double u = dot3(T, P) / det;
+    if (u < 0.0 || u > 1.0) return 0;
+    cross3(T, E1, Qv);
+    double v = dot3(Dv, Qv) / det;
+    if (v < 0.0 || u + v > 1.0) return 0;
+    double t = dot3(E2, Qv) / det;
+    if (t < 0.0 || t > 1.0) return 0;
+    *t_out = t; *u_out = u; *v_out = v;
+    return 1;
+}
+
+/* Segment o + t*D against segment a + s*(b-a), both parameters in [0,1]. */
+static int ray_seg(const double *o, const double *Dv, const double *a, const double *b,
+                   double *t_out, double *s_out) {
+    double e[2] = {b[0] - a[0], b[1] - a[1]};
+    double den = Dv[0] * e[1] - Dv[1] * e[0];
+    if (den == 0.0) return 0;
+    double w[2] = {a[0] - o[0], a[1] - o[1]};
+    double t = (w[0] * e[1] - w[1] * e[0]) / den;
+    double s = (w[0] * Dv[1] - w[1] * Dv[0]) / den;
+    if (t < 0.0 || t > 1.0 || s < 0.0 || s > 1.0) return 0;
+    *t_out = t; *s_out = s;
+    return 1;
+}
+
+/* Hit of the segment with face f: returns 1 and t, plus barycentrics lam[0..dim-1]. */
+static int seg_face(int dim, const float *coords, int64_t f, const double *o, const double *Dv,
+                    double *t, double *lam) {
+    double p[9];
+    for (int k = 0; k < dim * dim; ++k) p[k] = (double)coords[f * dim * dim + k];
+    if (dim == 3) {
+        double u, v;
+        if (!ray_tri(o, Dv, p, p + 3, p + 6, t, &u, &v)) return 0;
+        lam[0] = 1.0 - u - v; lam[1] = u; lam[2] = v;
+        return 1;
+    } else {
+        double s;
+        if (!ray_seg(o, Dv, p, p + 2, t, &s)) return 0;
+        lam[0] = 1.0 - s; lam[1] = s;
+        return 1;
+    }
+}
+
+typedef struct {
+    int dim, Q;
+    int64_t n;
+    uint64_t *key;
+    double *q;
+    int32_t *face;
+    int64_t tests;
+} orc_links;
+
+static int bin_index_d(double x, double lo, double s, int B) {
+    double f = floor((x - lo) * s);
+    if (f < 0.0) return 0;
+    if (f > (double)(B - 1)) return B - 1;
+    return (int)f;
+}
+
+/* Candidate faces of a box [blo, bhi] from the bins (FP64 index, conservative). */
+typedef struct { int32_t *f; int64_t n, cap; } idlist;
+static void idlist_push(idlist *L, int32_t f) {
+    if (L->n == L->cap) { L->cap = L->cap ? 2 * L->cap : 256; L->f = (int32_t *)xrealloc(L->f, (size_t)L->cap * 4); }
+    L->f[L->n++] = f;
+}
+static void box_candidates(const orc_bins *bn, int dim, int64_t F, const double *blo, const double *bhi, idlist *out) {
+    out->n = 0;
+    if (!bn) { for (int64_t f = 0; f < F; ++f) idlist_push(out, (int32_t)f); return; }
+    int l[3] = {0, 0, 0}, u[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) {
+        double s = (double)bn->B / ((double)bn->hi[a] - (double)bn->lo[a]);
+        l[a] = bin_index_d(blo[a], bn->lo[a], s, bn->B);
+        u[a] = bin_index_d(bhi[a], bn->lo[a], s, bn->B);
+    }
+    int B = bn->B;
+    for (int z = l[2]; z <= u[2]; ++z)
+        for (int y = l[1]; y <= u[1]; ++y)
+            for (int x = l[0]; x <= u[0]; ++x) {
+                int64_t b = ((int64_t)z * B + y) * B + x;
+                for (uint32_t j = bn->off[b]; j < bn->off[b + 1]; ++j) idlist_push(out, bn->ids[j]);
+            }
+}
+
+/* q for one cell: fills q[Q], face[Q]; returns the number of links. */
+static int cell_links(int dim, int Q, const int *cv, const float *coords, int64_t F, const orc_bins *bn,
+                      const double *o, const double *dxL, idlist *cand, double *q, int32_t *face, int64_t *ntests) {
+    double blo[3] = {0, 0, 0}, bhi[3] = {0, 0, 0};
+    const double eps = 9.5367431640625e-07;
+    for (int a = 0; a < dim; ++a) { blo[a] = o[a] - dxL[a] - eps; bhi[a] = o[a] + dxL[a] + eps; }
+    box_candidates(bn, dim, F, blo, bhi, cand);
+    *ntests += cand->n;
+    int nl = 0;
+    q[0] = -1.0; face[0] = -1;
+    for (int i = 1; i < Q; ++i) {
+        double Dv[3] = {0, 0, 0};
+        for (int a = 0; a < dim; ++a) Dv[a] = (double)cv[3 * i + a] * dxL[a];
+        double best = INFINITY;
+        int32_t bf = -1;
+        for (int64_t j = 0; j < cand->n; ++j) {
+            int32_t f = cand->f[j];
+            double t, lam[3];
+            if (!seg_face(dim, coords, f, o, Dv, &t, lam)) continue;
+            if (t < best || (t == best && f < bf)) { best = t; bf = f; }
+        }
+        if (bf >= 0) { q[i] = best; face[i] = bf; ++nl; }
+        else { q[i] = -1.0; face[i] = -1; }
+    }
+    return nl;
+}
+
+/*
+ * Link fractions at the finest level L of the forest: for every cell of
+ * every level-L block (all of them, or the block indices in `subset`) and
+ * every non-rest direction c_i, q_i is the smallest t in [0,1] at which
+ * x + t c_i dx_L meets a face, face_i the lowest face id attaining it
+ * (-1/-1 when none).  Cells with at least one link are emitted in
+ * canonical order (block key, then cell x-fastest) with node key
+ * block_key * 4^D + cell.  bins == NULL selects every face as a candidate.
+ */
+orc_links *orc_link_fractions(int dim, const float *coords, int64_t F, const orc_bins *bn,
+                              const orc_forest *fo, int Q, const int64_t *subset, int64_t n_subset) {
+    int cv[27 * 3];
+    if (orc_lattice(Q, cv) != dim) return NULL;
+    int L = fo->L;
+    int cells = dim == 3 ? 64 : 16;
+    const orc_level *lv = &fo->lev[L];
+    int64_t nblk = subset ? n_subset : lv->n;
+    orc_links *lk = (orc_links *)xcalloc(1, sizeof(orc_links));
+    lk->dim = dim; lk->Q = Q;
+    int64_t cap = 1024;
+    lk->key = (uint64_t *)xmalloc((size_t)cap * 8);
+    lk->q = (double *)xmalloc((size_t)cap * Q * 8);
+    lk->face = (int32_t *)xmalloc((size_t)cap * Q * 4);
+    double dxL[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) dxL[a] = (double)fo->dx[L][a];
+    idlist cand = {0, 0, 0};
+    double q[27];
+    int32_t fc[27];
+    for (int64_t bi = 0; bi < nblk; ++bi) {
+        int64_t i = subset ? subset[bi] : bi;
+        const orc_block *b = &lv->b[i];
+        for (int c = 0; c < cells; ++c) {
+            float m[3] = {0, 0, 0};
+            cell_center(fo, L, b->c, c, m);
+            double o[3] = {m[0], m[1], m[2]};
+            if (!cell_links(dim, Q, cv, coords, F, bn, o, dxL, &cand, q, fc, &lk->tests)) continue;
+            if (lk->n == cap) {
+                cap *= 2;
+                lk->key = (uint64_t *)xrealloc(lk->key, (size_t)cap * 8);
+                lk->q = (double *)xrealloc(lk->q, (size_t)cap * Q * 8);
+                lk->face = (int32_t *)xrealloc(lk->face, (size_t)cap * Q * 4);
+            }
+            lk->key[lk->n] = (uint64_t)b->key * (uint64_t)cells + (uint64_t)c;
+            memcpy(lk->q + lk->n * Q, q, (size_t)Q * 8);
+            memcpy(lk->face + lk->n * Q, fc, (size_t)Q * 4);
+            lk->n++;
+        }
+    }
+    free(cand.f);
+    return lk;
+}
+
+void orc_links_free(orc_links *lk) {
+    if (!lk) return;
+    free(lk->key); free(lk->q); free(lk->face); free(lk);
+}
+int64_t orc_links_n(const orc_links *lk) { return lk->n; }
+const uint64_t *orc_links_key(const orc_links *lk) { return lk->key; }
+const double *orc_links_q(const orc_links *lk) { return lk->q; }
+const int32_t *orc_links_face(const orc_links *lk) { return lk->face; }
+int64_t orc_links_tests(const orc_links *lk) { return lk->tests; }
+
+/* Node key -> cell centre (FP32 rule, promoted) for a node of level L. */
+static void node_origin(const orc_forest *fo, uint64_t nkey, double *o) {
+    int dim = fo->dim, L = fo->L;
+    int cells = dim == 3 ? 64 : 16, nch = dim == 3 ? 8 : 4;
+    uint32_t key = (uint32_t)(nkey / (uint64_t)cells);
+    int cell = (int)(nkey % (uint64_t)cells);
+    /* decode block coordinates from the hierarchical key */
+    uint32_t k = key;
+    int32_t path[3] = {0, 0, 0};
+    for (int j = 0; j < L; ++j) {
+        uint32_t ci = k % (uint32_t)nch;
+        k /= (uint32_t)nch;
+        path[0] |= (int32_t)(ci & 1) << j;
+        path[1] |= (int32_t)((ci >> 1) & 1) << j;
+        if (dim == 3) path[2] |= (int32_t)((ci >> 2) & 1) << j;
+    }
+    int32_t r0 = (int32_t)(k % (uint32_t)fo->roots[0]);
+    int32_t r1 = (int32_t)((k / (uint32_t)fo->roots[0]) % (uint32_t)fo->roots[1]);
+    int32_t r2 = (int32_t)(k / ((uint32_t)fo->roots[0] * (uint32_t)fo->roots[1]));
+    int32_t bc[3] = {(r0 << L) | path[0], (r1 << L) | path[1], dim == 3 ? ((r2 << L) | path[2]) : 0};
+    float m[3] = {0, 0, 0};
+    cell_center(fo, L, bc, cell, m);
+    o[0] = m[0]; o[1] = m[1]; o[2] = m[2];
+}
+
+/* ------------------------------------------------------------------ */
+/* Adjoint (FP64): for L = sum_i w_i q_i over link slots,               */
+/*   dL/dv_k += w_i * lambda_k * n / (Dv . n)                           */
+/* for the hit face's vertex k (n a face normal, lambda the barycentric */
+/* weights of the hit), accumulated onto unique vertices.               */
+/* ------------------------------------------------------------------ */
+static void face_normal(int dim, const double *p, double *n) {
+    if (dim == 3) {
+        double e1[3], e2[3];
+        for (int a = 0; a < 3; ++a) { e1[a] = p[3 + a] - p[a]; e2[a] = p[6 + a] - p[a]; }
+        cross3(e1, e2, n);
+    } else {
+        n[0] = -(p[3] - p[1]);
+        n[1] = p[2] - p[0];
+        n[2] = 0.0;
+    }
+}
+
+void orc_link_grad(const orc_forest *fo, const orc_links *lk, const float *coords, const int32_t *fidx,
+                   const double *w, double *grad) {
+    int dim = lk->dim, Q = lk->Q;
+    int cv[27 * 3];
+    orc_lattice(Q, cv);
+    double dxL[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) dxL[a] = (double)fo->dx[fo->L][a];
+    for (int64_t n = 0; n < lk->n; ++n) {
+        double o[3];
+        node_origin(fo, lk->key[n], o);
+        for (int i = 1; i < Q; ++i) {
+            double wi = w[n * Q + i];
+            int32_t f = lk->face[n * Q + i];
+            if (f < 0 || wi == 0.0) continue;
+            double Dv[3] = {0, 0, 0};
+            for (int a = 0; a < dim; ++a) Dv[a] = (double)cv[3 * i + a] * dxL[a];
+            double t, lam[3];
+            if (!seg_face(dim, coords, f, o, Dv, &t, lam)) continue;
+            double p[9] = {0}, nrm[3];
+            for (int k = 0; k < dim * dim; ++k) p[k] = (double)coords[(int64_t)f * dim * dim + k];
+            face_normal(dim, p, nrm);
+            double den = 0.0;
+            for (int a = 0; a < dim; ++a) den += Dv[a] * nrm[a];
+            for (int k = 0; k < dim; ++k) {
+                int64_t vk = fidx[(int64_t)f * dim + k];
+                for (int a = 0; a < dim; ++a) grad[vk * dim + a] += wi * lam[k] * nrm[a] / den;
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Stability screen for finite differences: a link slot is kept when   */
+/*  eta = h / (alt_min * |cos theta|) <= eta_max, every barycentric of  */
+/*  the hit >= bary_min, t in [t_lo, 1 - t_lo], and no other candidate  */
+/*  face hits within gap in t.                                          */
+/* ------------------------------------------------------------------ */
+void orc_link_stable(const orc_forest *fo, const orc_links *lk, const float *coords, int64_t F,
+                     const orc_bins *bn, double h, double eta_max, double bary_min, double t_lo,
+                     double gap, uint8_t *stable) {
+    int dim = lk->dim, Q = lk->Q;
+    int cv[27 * 3];
+    orc_lattice(Q, cv);
+    double dxL[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) dxL[a] = (double)fo->dx[fo->L][a];
+    idlist cand = {0, 0, 0};
+    const double eps = 9.5367431640625e-07;
+    for (int64_t n = 0; n < lk->n; ++n) {
+        double o[3];
+        node_origin(fo, lk->key[n], o);
+        double blo[3] = {0, 0, 0}, bhi[3] = {0, 0, 0};
+        for (int a = 0; a < dim; ++a) { blo[a] = o[a] - dxL[a] - eps - h; bhi[a] = o[a] + dxL[a] + eps + h; }
+        box_candidates(bn, dim, F, blo, bhi, &cand);
+        for (int i = 0; i < Q; ++i) {
+            uint8_t ok = 0;
+            int32_t f = lk->face[n * Q + i];
+            if (i > 0 && f >= 0) {
+                double Dv[3] = {0, 0, 0};
+                for (int a = 0; a < dim; ++a) Dv[a] = (double)cv[3 * i + a] * dxL[a];
+                double t, lam[3];
+                if (seg_face(dim, coords, f, o, Dv, &t, lam)) {
+                    double p[9] = {0}, nrm[3];
+                    for (int k = 0; k < dim * dim; ++k) p[k] = (double)coords[(int64_t)f * dim * dim + k];
+                    face_normal(dim, p, nrm);
+                    double nn = 0.0, dd = 0.0, dn = 0.0;
+                    for (int a = 0; a < dim; ++a) { nn += nrm[a] * nrm[a]; dd += Dv[a] * Dv[a]; dn += Dv[a] * nrm[a]; }
+                    double emax = 0.0;
+                    for (int k = 0; k < dim; ++k) {
+                        int k2 = (k + 1) % dim;
+                        double e2 = 0.0;
+                        for (int a = 0; a < dim; ++a) { double d = p[k2 * dim + a] - p[k * dim + a]; e2 += d * d; }
+                        if (e2 > emax) emax = e2;
+                    }
+                    /* minimum altitude: 2*area / longest edge (3D); segment length (2D) */
+                    double alt = dim == 3 ? sqrt(nn) / sqrt(emax) : sqrt(emax);
+                    double cosv = fabs(dn) / sqrt(nn * dd);
+                    double eta = (cosv > 0.0 && alt > 0.0) ? h / (alt * cosv) : INFINITY;
+                    double lmin = lam[0];
+                    for (int k = 1; k < dim; ++k) if (lam[k] < lmin) lmin = lam[k];
+                    ok = eta <= eta_max && lmin >= bary_min && t >= t_lo && t <= 1.0 - t_lo;
+                    if (ok) {
+                        for (int64_t j = 0; j < cand.n && ok; ++j) {
+                            int32_t g = cand.f[j];
+                            if (g == f) continue;
+                            double t2, lam2[3];
+                            if (seg_face(dim, coords, g, o, Dv, &t2, lam2) && fabs(t2 - t) < gap) ok = 0;
+                        }
+                    }
+                }
+            }
+            stable[n * Q + i] = ok;
+        }
+    }
+    free(cand.f);
+}
+
+/* ------------------------------------------------------------------ */
+/* Central finite differences of L = sum w_i q_i with respect to each   */
+/* coordinate of the listed vertices (FP64), step h.  Only link slots   */
+/* whose candidate set (bins over the link box widened by h) holds a    */
+/* face incident to the vertex are recomputed, each by a full minimum   */
+/* over its candidates with the perturbed coordinates.  Slots whose     */
+/* arg-min face changes at +h or -h are counted in *n_changed.          */
+/* ------------------------------------------------------------------ */
+void orc_fd_grad(const orc_forest *fo, const orc_links *lk, const float *verts, int64_t Nv,
+                 const int32_t *fidx, int64_t F, const orc_bins *bn, const double *w, double h,
+                 const int64_t *vsub, int64_t n_vsub, double *grad_fd, int64_t *n_changed) {
+    int dim = lk->dim, Q = lk->Q;
+    int cv[27 * 3];
+    orc_lattice(Q, cv);
+    double dxL[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) dxL[a] = (double)fo->dx[fo->L][a];
+    const double eps = 9.5367431640625e-07;
+    /* FP64 working copy of the vertices */
+    double *V = (double *)xmalloc((size_t)Nv * dim * 8);
+    for (int64_t i = 0; i < Nv * dim; ++i) V[i] = (double)verts[i];
+    /* FP32 coordinate list for the bin lookup (unperturbed) */
+    /* incidence: vertex -> link nodes whose candidate set contains an incident face */
+    int64_t *cnt = (int64_t *)xcalloc((size_t)Nv + 1, 8);
+    idlist cand = {0, 0, 0};
+    float *coords = (float *)xmalloc((size_t)F * dim * dim * 4);
+    orc_gather(dim, verts, fidx, F, coords);
+    /* node -> candidate list cache */
+    int64_t *coff = (int64_t *)xcalloc((size_t)lk->n + 1, 8);
+    idlist all = {0, 0, 0};
+    for (int64_t n = 0; n < lk->n; ++n) {
+        int any = 0;
+        for (int i = 1; i < Q; ++i) if (w[n * Q + i] != 0.0 && lk->face[n * Q + i] >= 0) any = 1;
+        coff[n] = all.n;
+        if (!any) continue;
+        double o[3];
+        node_origin(fo, lk->key[n], o);
+        double blo[3] = {0, 0, 0}, bhi[3] = {0, 0, 0};
+        for (int a = 0; a < dim; ++a) { blo[a] = o[a] - dxL[a] - eps - h; bhi[a] = o[a] + dxL[a] + eps + h; }
+        box_candidates(bn, dim, F, blo, bhi, &cand);
+        for (int64_t j = 0; j < cand.n; ++j) idlist_push(&all, cand.f[j]);
+    }
+    coff[lk->n] = all.n;
+    /* vertex -> nodes (with duplicates removed per vertex via a stamp) */
+    int64_t *stamp = (int64_t *)xmalloc((size_t)Nv * 8);
+    for (int64_t i = 0; i < Nv; ++i) stamp[i] = -1;
+    for (int64_t n = 0; n < lk->n; ++n)
+        for (int64_t j = coff[n]; j < coff[n + 1]; ++j)
+            for (int k = 0; k < dim; ++k) {
+                int64_t vk = fidx[(int64_t)all.f[j] * dim + k];
+                if (stamp[vk] != n) { stamp[vk] = n; cnt[vk + 1]++; }
+            }
+    for (int64_t i = 0; i < Nv; ++i) cnt[i + 1] += cnt[i];
+    int64_t *vn = (int64_t *)xmalloc((size_t)cnt[Nv] * 8 + 8);
+    int64_t *fill = (int64_t *)xcalloc((size_t)Nv, 8);
+    for (int64_t i = 0; i < Nv; ++i) stamp[i] = -1;
+    for (int64_t n = 0; n < lk->n; ++n)
+        for (int64_t j = coff[n]; j < coff[n + 1]; ++j)
+            for (int k = 0; k < dim; ++k) {
+                int64_t vk = fidx[(int64_t)all.f[j] * dim + k];
+                if (stamp[vk] != n) { stamp[vk] = n; vn[cnt[vk] + fill[vk]++] = n; }
+            }
+    *n_changed = 0;
+    for (int64_t si = 0; si < n_vsub; ++si) {
+        int64_t vk = vsub[si];
+        for (int a = 0; a < dim; ++a) {
+            double Lpm[2] = {0.0, 0.0};
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                double save = V[vk * dim + a];
+                V[vk * dim + a] = save + (sgn == 0 ? h : -h);
+                for (int64_t r = cnt[vk]; r < cnt[vk + 1]; ++r) {
+                    int64_t n = vn[r];
+                    double o[3];
+                    node_origin(fo, lk->key[n], o);
+                    for (int i = 1; i < Q; ++i) {
+                        double wi = w[n * Q + i];
+                        if (wi == 0.0 || lk->face[n * Q + i] < 0) continue;
+                        double Dv[3] = {0, 0, 0};
+                        for (int b = 0; b < dim; ++b) Dv[b] = (double)cv[3 * i + b] * dxL[b];
+                        double best = INFINITY;
+                        int32_t bf = -1;
+                        for (int64_t j = coff[n]; j < coff[n + 1]; ++j) {
+                            int32_t f = all.f[j];
+                            double p[9];
+                            for (int k = 0; k < dim; ++k)
+                                for (int b = 0; b < dim; ++b) p[k * dim + b] = V[(int64_t)fidx[(int64_t)f * dim + k] * dim + b];
+                            double t, u, v, s;
+                            int hit = dim == 3 ? ray_tri(o, Dv, p, p + 3, p + 6, &t, &u, &v)
+                                               : ray_seg(o, Dv, p, p + 2, &t, &s);
+                            if (hit && (t < best || (t == best && f < bf))) { best = t; bf = f; }
+                        }
+                        if (bf != lk->face[n * Q + i]) { (*n_changed)++; continue; }
+                        Lpm[sgn] += wi * (best - lk->q[n * Q + i]);
+                    }
+                }
+                V[vk * dim + a] = save;
+            }
+            grad_fd[vk * dim + a] = (Lpm[0] - Lpm[1]) / (2.0 * h);
+        }
+    }
+    free(V); free(cnt); free(cand.f); free(coords); free(coff); free(all.f); free(stamp); free(vn); free(fill);
+}

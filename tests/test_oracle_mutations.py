@@ -1,0 +1,79 @@
+"""The oracle's pins must catch plausible mistakes: each case below plants one
+mistake in a copy of the oracle source (on the CPU), rebuilds it, and requires
+the named pin tests to fail against it."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(ROOT, "oracle", "agal_oracle.c")
+
+MUTANTS = [
+    ("sat drops the face-normal axis",
+     "if (s > r || s < -r) return 0;", "(void)s; (void)r;",
+     "test_sat_3d_vs_exact_clipping"),
+    ("sat edge axis with a flipped component",
+     "else { iu = 0; iv = 1; au = -e[1]; av = e[0]; }", "else { iu = 0; iv = 1; au = e[1]; av = e[0]; }",
+     "test_sat_3d_vs_exact_clipping"),
+    ("2D sat with a transposed normal",
+     "float Nx = -(Bv[1] - A[1]);\n    float Ny = Bv[0] - A[0];",
+     "float Nx = Bv[0] - A[0];\n    float Ny = -(Bv[1] - A[1]);",
+     "test_sat_2d_vs_exact_clipping"),
+    ("bins linearised y-fastest",
+     "bn->count[((int64_t)z * B + y) * B + x] += 1;", "bn->count[((int64_t)z * B + x) * B + y] += 1;",
+     "test_bins_exact_circle or test_bins_exact_sphere_nondyadic_domain"),
+    ("bin range upper end from the minimum",
+     "hi_i[a] = bin_index(mx,", "hi_i[a] = bin_index(mn,",
+     "test_bins_exact_circle or test_bins_exact_sphere_nondyadic_domain"),
+    ("segment-triangle accepts v < 0",
+     "if (v < 0.0 || u + v > 1.0) return 0;", "if (u + v > 1.0) return 0;",
+     "test_links_exact_random_triangles"),
+    ("segment-triangle t with the wrong sign",
+     "double t = dot3(E2, Qv) / det;", "double t = -dot3(E2, Qv) / det;",
+     "test_links_exact_random_triangles"),
+    ("segment-segment with a transposed cross product",
+     "double s = (w[0] * Dv[1] - w[1] * Dv[0]) / den;", "double s = (w[1] * Dv[0] - w[0] * Dv[1]) / den;",
+     "test_links_exact_random_segments"),
+    ("ties resolved to the highest face id",
+     "if (t < best || (t == best && f < bf)) { best = t; bf = f; }",
+     "if (t < best || (t == best && f > bf)) { best = t; bf = f; }",
+     "test_links_closed_form_box"),
+    ("ripple ignores diagonal neighbours",
+     "if (!dx && !dy && !dz) continue;", "if (!dx && !dy && !dz) continue;\n                            if (dx && dy) continue;",
+     "test_balance_and_structure or test_balance_is_minimal_closure"),
+    ("cell centre shifted by half a cell",
+     "(float)(2 * g + 1) * (0.5f * fo->dx[level][a])", "(float)(2 * g) * (0.5f * fo->dx[level][a])",
+     "test_flags_closed_form_box_body"),
+    ("every pass tested with the first level's distance",
+     "cell_flag(fo, coords, F, bn, m, fo->d[l], &fo->tests[l])", "cell_flag(fo, coords, F, bn, m, fo->d[0], &fo->tests[l])",
+     "test_flags_closed_form_box_body"),
+    ("child coordinates with swapped bits",
+     "ch.c[0] = 2 * b->c[0] + (ci & 1);", "ch.c[0] = 2 * b->c[0] + ((ci >> 1) & 1);",
+     "test_flags_closed_form_box_body or test_links_closed_form_box"),
+    ("adjoint barycentric weights permuted",
+     "lam[0] = 1.0 - u - v; lam[1] = u; lam[2] = v;", "lam[0] = u; lam[1] = 1.0 - u - v; lam[2] = v;",
+     "test_adjoint_horizontal_plane_closed_form or test_adjoint_matches_finite_differences"),
+    ("adjoint with the normal of the wrong orientation in the numerator only",
+     "grad[vk * dim + a] += wi * lam[k] * nrm[a] / den;", "grad[vk * dim + a] -= wi * lam[k] * nrm[a] / den;",
+     "test_adjoint_horizontal_plane_closed_form or test_adjoint_matches_finite_differences"),
+]
+
+
+@pytest.mark.parametrize("name,old,new,tests", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_mutant(tmp_path, name, old, new, tests):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor not found: {old!r}"
+    mutated = src.replace(old, new)
+    cpath = tmp_path / "mut.c"
+    cpath.write_text(mutated)
+    lib = tmp_path / "libmut.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                           "-shared", str(cpath), "-o", str(lib), "-lm"])
+    env = dict(os.environ, AGAL_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        os.path.join(HERE, "test_oracle_pins.py"), "-k", tests],
+                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1, f"pins did not catch: {name}\n{r.stdout[-2000:]}"
