@@ -1,0 +1,322 @@
+"""Benchmark of the near-wall mesh-adaptation hot path on one MI355X.
+
+One step = import the faces (device-resident inputs), bin them, refine the
+forest level by level near the wall, compute the link fractions q and run
+the adjoint for a weighted sum of q -- every row of the hot path, on
+synthetic seeded geometry (see geomgen).  Prints ONE JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--config C1] [--no-cpu-baseline]
+
+`value` is cell-face tests per second: the number of (cell, face) pairs the
+bins put in front of the cells (tested cells of every pass against the faces
+of the bins under their query box, plus finest-level cells against the faces
+under their link box; a fixed property of the workload) divided by the step
+time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0              # MI355X HBM3E
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # non-packed FP32 lane ops/s: 39.3 T
+EPS = 2.0 ** -20
+METRIC = "cell-face tests/s and near-wall pass ms (bin+flag+q) at 1 GPU; % HBM peak; grad ms"
+
+
+# ---------------------------------------------------------------------------
+# workload size: cell-face tests (host-side count from the bins and the forest)
+# ---------------------------------------------------------------------------
+def _bin_index_f32(x, lo, s, B):
+    t = (x.astype(np.float32) - np.float32(lo)) * np.float32(s)
+    f = np.floor(t)
+    return np.clip(f, 0, B - 1).astype(np.int64)
+
+
+def _bin_index_f64(x, lo, s, B):
+    f = np.floor((x - lo) * s)
+    return np.clip(f, 0, B - 1).astype(np.int64)
+
+
+def _decode(keys, level, roots, dim):
+    k = keys.astype(np.int64)
+    path = np.zeros((len(k), 3), dtype=np.int64)
+    for j in range(level):
+        ci = k & ((1 << dim) - 1)
+        k = k >> dim
+        for a in range(dim):
+            path[:, a] |= ((ci >> a) & 1) << j
+    r = np.stack([k % roots[0], (k // roots[0]) % roots[1], k // (roots[0] * roots[1])], 1)
+    return (r << level) | path
+
+
+def cell_face_tests(offsets, B, dim, levels, roots, L, d_spec, lo, hi):
+    """(T_flag per pass, T_q): sum over cells of the face counts of the bins under each
+    cell's query box [m - h - eps, m + h + eps] (FP32 bin index) for the cells tested in
+    each pass, and [x - dx - eps, x + dx + eps] (FP64) for every finest-level cell."""
+    counts = np.diff(offsets.astype(np.int64))
+    shape = (B,) * dim
+    S = np.zeros(tuple(n + 1 for n in shape), dtype=np.int64)
+    if dim == 3:
+        S[1:, 1:, 1:] = counts.reshape(shape).cumsum(0).cumsum(1).cumsum(2)
+    else:
+        S[1:, 1:] = counts.reshape(shape).cumsum(0).cumsum(1)
+    lo32 = np.asarray(lo, np.float32)[:dim]
+    hi32 = np.asarray(hi, np.float32)[:dim]
+    s32 = np.float32(B) / (hi32 - lo32)
+    cells = 4 ** dim
+    ci = np.arange(cells)
+    off = np.stack([ci & 3, (ci >> 2) & 3, (ci >> 4) & 3], 1)[:, :dim]
+
+    def box_sum(il, ih):
+        if dim == 3:
+            z0, y0, x0 = il[:, 2], il[:, 1], il[:, 0]
+            z1, y1, x1 = ih[:, 2] + 1, ih[:, 1] + 1, ih[:, 0] + 1
+            return (S[z1, y1, x1] - S[z0, y1, x1] - S[z1, y0, x1] - S[z1, y1, x0]
+                    + S[z0, y0, x1] + S[z0, y1, x0] + S[z1, y0, x0] - S[z0, y0, x0])
+        y0, x0 = il[:, 1], il[:, 0]
+        y1, x1 = ih[:, 1] + 1, ih[:, 0] + 1
+        return S[y1, x1] - S[y0, x1] - S[y1, x0] + S[y0, x0]
+
+    def centres(keys, level, f64):
+        c = _decode(keys, level, roots, dim)[:, :dim]
+        g = (4 * c[:, None, :] + off[None]).reshape(-1, dim)
+        dx = np.array([np.float32((hi32[a] - lo32[a]) / np.float32(4 * roots[a] * (1 << level))) for a in range(dim)])
+        m = lo32 + (2 * g + 1).astype(np.float32) * (np.float32(0.5) * dx)
+        return m.astype(np.float32), dx
+
+    t_flag = []
+    for l in range(L):
+        lv = levels[l]
+        if l == 0:
+            tested = np.ones(len(lv["keys"]), bool)
+        else:
+            par = levels[l - 1]
+            pk = par["keys"][par["mark"] == 1].astype(np.int64)
+            tested = np.isin(lv["keys"].astype(np.int64) >> dim, pk)
+        keys = lv["keys"][tested]
+        if len(keys) == 0:
+            t_flag.append(0)
+            continue
+        m, _ = centres(keys, l, False)
+        h = np.float32(d_spec[l])
+        ql = (m - h) - np.float32(EPS)
+        qh = (m + h) + np.float32(EPS)
+        il = np.stack([_bin_index_f32(ql[:, a], lo32[a], s32[a], B) for a in range(dim)], 1)
+        ih = np.stack([_bin_index_f32(qh[:, a], lo32[a], s32[a], B) for a in range(dim)], 1)
+        t_flag.append(int(box_sum(il, ih).sum()))
+    keys = levels[L]["keys"]
+    if len(keys) == 0:
+        return t_flag, 0
+    m, dx = centres(keys, L, True)
+    m64, dx64 = m.astype(np.float64), dx.astype(np.float64)
+    s64 = B / (hi32.astype(np.float64) - lo32.astype(np.float64))
+    il = np.stack([_bin_index_f64(m64[:, a] - dx64[a] - EPS, float(lo32[a]), s64[a], B) for a in range(dim)], 1)
+    ih = np.stack([_bin_index_f64(m64[:, a] + dx64[a] + EPS, float(lo32[a]), s64[a], B) for a in range(dim)], 1)
+    return t_flag, int(box_sum(il, ih).sum())
+
+
+# ---------------------------------------------------------------------------
+def host_info():
+    model, cores = platform.processor() or "unknown", os.cpu_count()
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return model, cores
+
+
+def cpu_baseline(wl, w_slots, T_total):
+    """The CPU oracle as it stands, serial, on the same workload (full pass + adjoint)."""
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    r = oracle.run_plain(wl)
+    lk = r["links"]
+    w = np.zeros((lk.n, wl.lattice))
+    n = min(lk.n * wl.lattice, len(w_slots))
+    w.reshape(-1)[:n] = w_slots[:n]
+    w[lk.face < 0] = 0.0
+    oracle.link_grad(r["forest"], lk, r["coords"], wl.faces, w, len(wl.vertices))
+    dt = time.perf_counter() - t0
+    T_orc = sum(r["forest"].tests) + lk.tests
+    model, _ = host_info()
+    return {"value": T_orc / dt, "unit": "cell-face tests/s", "cores": 1, "kind": "oracle",
+            "sample": f"full {wl.name} pass on one host core ({model}): bins, {wl.levels} refinement passes "
+                      f"(FP32 flags), FP64 q for every finest-level cell, FP64 adjoint; {dt:.1f} s",
+            "seconds": dt, "tests": int(T_orc)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="C1")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import torch
+    import geomgen
+    import paper_2502_16310_amd as agal
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    wl = geomgen.workload(args.config)
+    dim, Q = wl.dim, wl.lattice
+    print(f"bench: {wl.name} faces={len(wl.faces)} roots={wl.roots[:dim]} levels={wl.levels} bins={wl.bins} "
+          f"Q={Q}", file=sys.stderr, flush=True)
+    v = torch.from_numpy(wl.vertices).to(dev)
+    f = torch.from_numpy(wl.faces).to(dev)
+    d_spec = [float(x) for x in wl.d_spec()]
+    ctx = agal.agal_context_create()
+    stream = torch.cuda.current_stream().cuda_stream
+    desc = agal.forest_desc(dim, wl.roots[:dim], wl.levels, d_spec, wl.lo[:dim], wl.hi[:dim])
+    grad = torch.zeros((len(wl.vertices), dim), dtype=torch.float32, device=dev)
+    w_host = geomgen.weights(4 ** dim * 4 * 10 ** 6, 2)  # enough slots; first n*Q used
+    w_dev = None
+
+    def step(keep=False):
+        nonlocal w_dev
+        g = agal.agal_import_faces(ctx, dim, v.data_ptr(), v.shape[0], f.data_ptr(), f.shape[0], stream)
+        b = agal.agal_bin_faces(g, wl.lo[:dim], wl.hi[:dim], wl.bins, stream)
+        fo = agal.agal_near_wall_refine(g, b, desc, stream)
+        lk = agal.agal_link_fractions(g, b, fo, Q, stream)
+        n_nodes = agal.agal_links_view(lk)[3]
+        if w_dev is None or w_dev.numel() < n_nodes * Q:
+            w_dev = torch.from_numpy(w_host[: max(1, n_nodes * Q)].copy()).to(dev)
+        grad.zero_()
+        agal.agal_link_fractions_backward(g, lk, w_dev.data_ptr(), grad.data_ptr(), stream)
+        if keep:
+            return g, b, fo, lk
+        for h, fn in ((lk, agal.agal_destroy_links), (fo, agal.agal_destroy_forest), (b, agal.agal_destroy_bins),
+                      (g, agal.agal_destroy_geom)):
+            fn(h)
+        return None
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # workload size, from this GPU run's own bins and forest (outside the timed region)
+    g, b, fo, lk = step(keep=True)
+    torch.cuda.synchronize()
+    off_p, _, nb, P = agal.agal_bins_view(b)
+    off = agal.device_copy(off_p, nb + 1, torch.int32).cpu().numpy().view(np.uint32)
+    levels = []
+    for l in range(wl.levels + 1):
+        kp, _, mp, _, n = agal.agal_forest_level_view(fo, l)
+        levels.append({"keys": agal.device_copy(kp, n, torch.int32).cpu().numpy().view(np.uint32),
+                       "mark": agal.device_copy(mp, n, torch.uint8).cpu().numpy()})
+    n_nodes = agal.agal_links_view(lk)[3]
+    t_flag, t_q = cell_face_tests(off, wl.bins, dim, levels, wl.roots, wl.levels, d_spec, wl.lo, wl.hi)
+    T = sum(t_flag) + t_q
+    n_links = int((agal.device_copy(agal.agal_links_view(lk)[2], n_nodes * Q, torch.int32) >= 0).sum().item())
+    n_blocks = [len(l["keys"]) for l in levels]
+    for h, fn in ((lk, agal.agal_destroy_links), (fo, agal.agal_destroy_forest), (b, agal.agal_destroy_bins),
+                  (g, agal.agal_destroy_geom)):
+        fn(h)
+
+    # timed region: K whole steps, per-kernel HIP events recorded on the launch stream
+    agal.agal_profile_read(ctx)
+    agal.agal_profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    agal.agal_profile_enable(ctx, False)
+    prof = agal.agal_profile_read(ctx)
+    ms = (t1 - t0) * 1e3 / args.steps
+    kern = {k: {"launches_per_step": n / args.steps, "ms_per_step": t / args.steps, "avg_us": 1e3 * t / n}
+            for k, (n, t) in prof.items()}
+    pass_kernels = ("bin_count", "bin_scatter", "bin_canon", "bin_canon_big", "scan_exclusive", "flag_sat",
+                    "balance_ripple", "child_gen", "q_links")
+    pass_ms = sum(kern[k]["ms_per_step"] for k in pass_kernels if k in kern)
+    grad_ms = kern.get("q_adjoint", {}).get("ms_per_step", 0.0)
+    dominant = max(kern, key=lambda k: kern[k]["ms_per_step"])
+
+    # roofline of the dominant kernel
+    F = len(wl.faces)
+    roof = roofline(dominant, kern[dominant], dim=dim, Q=Q, F=F, nb=nb, P=P, n_blocks=n_blocks, n_nodes=n_nodes,
+                    t_flag=t_flag, t_q=t_q, L=wl.levels)
+
+    out = {
+        "metric": METRIC, "value": T / (ms * 1e-3), "unit": "cell-face tests/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{wl.name}: " + describe(wl), "faces": F, "roots": list(wl.roots[:dim]),
+                   "levels": wl.levels, "bins": wl.bins, "lattice": f"D{dim}Q{Q}", "global_batch": 1,
+                   "seq_len": 0, "parallelism": "none"},
+        "near_wall_pass_ms": pass_ms, "grad_ms": grad_ms,
+        "cell_face_tests": {"flag_per_pass": t_flag, "q": t_q, "total": T},
+        "forest_blocks_per_level": n_blocks, "boundary_nodes": n_nodes, "links": n_links,
+        "kernels": kern, "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on the same workload", file=sys.stderr, flush=True)
+        cb = cpu_baseline(wl, w_host.astype(np.float64), T)
+        out["cpu_baseline"] = cb
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+def describe(wl):
+    if wl.name == "C0":
+        return "2D circle r=0.25, 256 segments"
+    if wl.name == "C1":
+        return "icosphere subdivision 5 (20480 triangles) r=0.2"
+    if wl.name == "C2":
+        return "star body on icosphere subdivision 7 (327680 triangles), seed 0"
+    if wl.name == "C3":
+        return "C1 sphere jittered N(0,1e-3), seed 1"
+    return wl.name
+
+
+def roofline(name, k, dim, Q, F, nb, P, n_blocks, n_nodes, t_flag, t_q, L):
+    """Algorithmic bytes (compulsory HBM traffic) per launch of kernel `name`."""
+    us = k["avg_us"]
+    launches = k["launches_per_step"]
+    cells = 4 ** dim
+    face_bytes = F * (4 * dim * dim + 8 * dim)           # SoA coordinates + bounding boxes
+    csr_bytes = 4 * (nb + 1) + 4 * P
+    if name == "q_links":
+        nL = n_blocks[L]
+        byts = 4 * nL + face_bytes + csr_bytes + n_nodes * (8 + 8 * Q)
+    elif name == "flag_sat":
+        tested = sum(n_blocks[:L])
+        byts = (4 * tested + (cells + 1) * tested + L * (face_bytes + csr_bytes)) / max(1, launches)
+    elif name == "q_adjoint":
+        byts = n_nodes * (8 + 8 * Q) + face_bytes + 4 * F * dim + 8 * dim * 4 * F
+    else:
+        byts = None
+    if byts is None:
+        return {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+                "traffic": None, "kernel": name}
+    gbs = byts / (us * 1e-6) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": None, "kernel": name, "bytes_per_launch": byts, "avg_launch_us": us}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * agal.h -- C ABI of the MI355X near-wall mesh-adaptation library.
+ *
+ * Method: "Towards a GPU-native adaptive mesh refinement scheme for the
+ * Lattice Boltzmann Method in complex geometries" (Jaber, Essel, Sullivan,
+ * 2025).  A triangle (3D) or edge (2D) mesh is embedded in a forest of
+ * octrees (quadtrees) whose nodes are blocks of 4^D cells, in three steps
+ * (Abstract; Sec. II): import the faces, distribute them to a uniform grid of
+ * bins of user-set density, then refine the grid level by level near the wall
+ * and link boundary nodes to the faces along the lattice directions.
+ *
+ * Conventions shared by every call
+ *  - Every call returns agal_status; no exception crosses the ABI.  On
+ *    failure out-handles are left untouched and agal_last_error() (per host
+ *    thread) describes the cause.
+ *  - Pointers named d_* are device pointers (HIP device memory of the
+ *    current device); everything else is host memory.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  All
+ *    device work is enqueued on it.  Calls that must size an output read a
+ *    device count back and synchronise that stream (stated per call).
+ *  - Handles own their device memory until destroyed; device pointers
+ *    returned by *_view stay valid until the owning handle is destroyed and
+ *    hold final values once `stream` has been synchronised.
+ *  - Handles are not thread-safe; distinct handles may be used from distinct
+ *    host threads on distinct streams.
+ *  - Inputs are never retained: a call has consumed its input buffers once
+ *    the work it enqueued on `stream` has completed.
+ */
+#ifndef AGAL_H
+#define AGAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AGAL_API __attribute__((visibility("default")))
+
+typedef enum agal_status {
+    AGAL_OK = 0,
+    AGAL_EINVAL = 1,    /* an argument is out of its documented range */
+    AGAL_ENOMEM = 2,    /* a device or host allocation failed */
+    AGAL_EHIP = 3,      /* the HIP runtime reported an error */
+    AGAL_ECAPACITY = 4, /* a preallocated capacity was exceeded (batched plans) */
+    AGAL_ESTATE = 5     /* handles do not belong together or a result is inconsistent */
+} agal_status;
+
+typedef struct agal_context_t *agal_context;
+typedef struct agal_geom_t *agal_geom;
+typedef struct agal_bins_t *agal_bins;
+typedef struct agal_forest_t *agal_forest;
+typedef struct agal_links_t *agal_links;
+
+/* Optional device allocator.  alloc returns device memory usable on `stream`
+ * (or NULL on failure); free releases it in stream order.  A NULL allocator
+ * selects the HIP stream-ordered pool (hipMallocAsync / hipFreeAsync). */
+typedef struct agal_allocator {
+    void *ctx;
+    void *(*alloc)(void *ctx, size_t bytes, void *stream);
+    void (*free)(void *ctx, void *ptr, void *stream);
+} agal_allocator;
+
+/* Lattice velocity sets (Sec. II-C-1: links follow the directions of the
+ * discrete velocity set).  Direction order: rest; the axis directions in
+ * +/- pairs (x, y, z); for D3Q19/D3Q27 the 12 edge directions in +/- pairs
+ * ((1,1,0),(-1,-1,0),(1,-1,0),(-1,1,0), then the xz and yz analogues); for
+ * D3Q27 the 8 corner directions in +/- pairs ((1,1,1),(1,1,-1),(1,-1,1),
+ * (-1,1,1) and negatives).  D2Q9: rest, (+-1,0), (0,+-1), (1,1),(-1,-1),
+ * (1,-1),(-1,1).  Direction i and its opposite are i and i+1 for odd i. */
+enum { AGAL_D2Q9 = 9, AGAL_D3Q19 = 19, AGAL_D3Q27 = 27 };
+
+#define AGAL_MAX_LEVELS 8
+
+/* Forest of root trees (Sec. II-A): roots[a] root blocks along axis a tile
+ * [lo, hi]; each block holds 4^D cells; n_levels refinement passes make
+ * levels 0..n_levels.  d_spec[l] (host, one per pass, >= 0) is the near-wall
+ * distance for the cells tested in pass l (Sec. II-C-2). */
+typedef struct agal_forest_desc {
+    int dim;
+    int roots[3];
+    int n_levels;
+    const float *d_spec;
+    float lo[3];
+    float hi[3];
+} agal_forest_desc;
+
+/* ---- context ---------------------------------------------------------- */
+AGAL_API agal_status agal_context_create(const agal_allocator *alloc, agal_context *out);
+AGAL_API void agal_context_destroy(agal_context ctx);
+
+/* ---- import (Sec. II-B) -------------------------------------------------
+ * Copies the geometry into library-owned device memory as a structure-of-
+ * arrays coordinate list (vertex k, axis a of face f) plus per-face bounding
+ * boxes, and keeps the index list for the adjoint.
+ *   dim         2 (edges) or 3 (triangles).
+ *   d_vertices  n_vertices x dim FP32, row-major.
+ *   d_faces     n_faces x dim int32 vertex indices, row-major; NULL means
+ *               d_vertices is already a coordinate list of n_faces x dim
+ *               corners (then n_vertices must equal n_faces * dim).
+ * Errors: AGAL_EINVAL for dim not in {2,3}, n_faces < 1, n_vertices < 1, an
+ * index outside [0, n_vertices), or a NaN/Inf coordinate (checked on the
+ * device; this call synchronises `stream`). */
+AGAL_API agal_status agal_import_faces(agal_context ctx, int dim, const float *d_vertices, int64_t n_vertices,
+                                       const int32_t *d_faces, int64_t n_faces, void *stream, agal_geom *out);
+/* d_coords: (dim*dim) x n_faces FP32, row (k*dim + a) = axis a of vertex k.
+ * d_aabb: (2*dim) x n_faces FP32, rows 0..dim-1 minima, dim..2dim-1 maxima. */
+AGAL_API agal_status agal_geom_view(agal_geom g, int *dim, int64_t *n_faces, int64_t *n_vertices,
+                                    const float **d_coords, const float **d_aabb);
+
+/* ---- spatial binning (Sec. II-C-3) ---------------------------------------
+ * B bins per axis tile [lo, hi] (B^D bins; bin (ix,iy,iz) has linear index
+ * (iz*B + iy)*B + ix).  Face f belongs to every bin its bounding box touches:
+ * per axis the index range is [idx(min), idx(max)] with
+ * idx(x) = clamp(floor((x - lo) * s), 0, B-1), s = (float)B / (hi - lo), all
+ * FP32, so faces partly outside [lo, hi] go to the edge bins.  Output is a
+ * CSR: offsets (B^D + 1 uint32) and face ids ascending inside each bin.
+ * Errors: AGAL_EINVAL for B < 1, B^D > 2^31, hi <= lo.  Synchronises
+ * `stream` once to size the id array. */
+AGAL_API agal_status agal_bin_faces(agal_geom g, const float lo[3], const float hi[3], int32_t B, void *stream,
+                                    agal_bins *out);
+AGAL_API agal_status agal_bins_view(agal_bins b, const uint32_t **d_offsets, const int32_t **d_face_ids,
+                                    int64_t *n_bins, int64_t *n_entries);
+
+/* ---- near-wall refinement (Sec. II-C-1, II-C-2, II-A) --------------------
+ * For pass l = 0..n_levels-1, every cell of every block present at level l
+ * when the pass starts is tested: it is flagged when a face meets the closed
+ * cube of half-width d_spec[l] centred on the cell centre (13-axis
+ * separating-axis test in FP32; the cell centre is
+ * lo + (float)(2g+1) * (0.5f * dx_l), dx_l = (hi - lo) / (4 * roots * 2^l)).
+ * A block with a flagged cell is marked and refined into 2^D children; 2:1
+ * balance across faces, edges and corners is restored by refining the
+ * coarser neighbours that need it.  Blocks created in pass l are not tested
+ * in pass l.  Results are identical to testing every face (binning only
+ * prunes candidates).
+ * Block keys: a root's key is its x-fastest linear index; a child's key is
+ * parent_key * 2^D + (cx + 2 cy + 4 cz).  Requires
+ * roots_x*roots_y*roots_z * 2^(D*n_levels) <= 2^32.
+ * Errors: AGAL_EINVAL for dim mismatch with the geometry, roots < 1,
+ * n_levels outside [0, AGAL_MAX_LEVELS], key overflow, a negative or
+ * non-finite d_spec, hi <= lo; AGAL_ESTATE when `bins` belongs to another
+ * geometry.  Synchronises `stream` once per pass to size the next level. */
+AGAL_API agal_status agal_near_wall_refine(agal_geom g, agal_bins b, const agal_forest_desc *desc, void *stream,
+                                           agal_forest *out);
+/* Level arrays in ascending key order:
+ *   d_keys[n]          block keys;
+ *   d_leaf[n]          1 when the block has no children;
+ *   d_mark[n]          1 = refined because one of its cells was flagged,
+ *                      2 = refined only to keep 2:1 balance, 0 = not refined;
+ *   d_cell_flag[n*4^D] per-cell test results, cells x-fastest (0 for blocks
+ *                      that were never tested); NULL at the finest level. */
+AGAL_API agal_status agal_forest_level_view(agal_forest f, int level, const uint32_t **d_keys,
+                                            const uint8_t **d_leaf, const uint8_t **d_mark,
+                                            const uint8_t **d_cell_flag, int64_t *n_blocks);
+AGAL_API agal_status agal_forest_info(agal_forest f, int *dim, int *n_levels);
+
+/* ---- link fractions (Sec. II-C-1) ----------------------------------------
+ * For every cell of every block of the finest level and every non-rest
+ * direction c_i of `lattice`, q_i is the smallest t in [0, 1] at which the
+ * segment x + t c_i dx_L (x the cell centre) meets a face (closed faces, both
+ * orientations), and face_i the lowest face id attaining it; -1 / -1 when
+ * there is none (and always for the rest direction).  Cells with at least one
+ * link are emitted in ascending node key = block_key * 4^D + cell.
+ * Outputs: d_node_key[n_nodes] uint64, d_q[n_nodes * Q] FP32,
+ * d_face[n_nodes * Q] int32, row-major by node.
+ * Errors: AGAL_EINVAL when the lattice does not match the dimension;
+ * AGAL_ESTATE when the handles come from different geometries.
+ * Synchronises `stream` once to read the node count. */
+AGAL_API agal_status agal_link_fractions(agal_geom g, agal_bins b, agal_forest f, int lattice, void *stream,
+                                         agal_links *out);
+AGAL_API agal_status agal_links_view(agal_links l, const uint64_t **d_node_key, const float **d_q,
+                                     const int32_t **d_face, int64_t *n_nodes, int *Q);
+
+/* ---- adjoint ---------------------------------------------------------------
+ * Accumulates dL/d(vertex) for L = sum over link slots of grad_q * q:
+ * each slot with face >= 0 adds grad_q * lambda_k * n / (D . n) to vertex k
+ * of its face (lambda the barycentric weights of the hit, n a face normal,
+ * D = c_i dx_L), through the index list given at import.
+ *   d_grad_q        n_nodes x Q FP32 (slots with face < 0 are ignored);
+ *   d_grad_vertices n_vertices x dim FP32, ACCUMULATED into (the caller
+ *                   zeroes it); for a coordinate-list import the "vertices"
+ *                   are the n_faces*dim corners.
+ * The hit is recomputed in FP32 with the denominator D . n in FP64 when the
+ * ray grazes the face.  Float atomics make the summation order vary between
+ * runs (results agree to rounding).
+ * Errors: AGAL_ESTATE when `l` was not computed from `g`. */
+AGAL_API agal_status agal_link_fractions_backward(agal_geom g, agal_links l, const float *d_grad_q,
+                                                  float *d_grad_vertices, void *stream);
+
+/* ---- kernel timing -------------------------------------------------------
+ * With profiling enabled, every kernel the library launches with `ctx` is
+ * bracketed by HIP events recorded on its launch stream.  agal_profile_read
+ * waits for the recorded events, aggregates them per kernel name (launch
+ * count and total milliseconds, in order of first appearance, at most
+ * max_entries names), stores the count in *n_entries and clears the record.
+ * Names are static strings owned by the library. */
+AGAL_API agal_status agal_profile_enable(agal_context ctx, int enable);
+AGAL_API agal_status agal_profile_read(agal_context ctx, int max_entries, const char **names, int64_t *launches,
+                                       double *total_ms, int *n_entries);
+
+/* ---- misc -------------------------------------------------------------- */
+AGAL_API agal_status agal_lattice_vectors(int lattice, int32_t *c /* host, lattice x 3 */);
+AGAL_API void agal_destroy_geom(agal_geom g);
+AGAL_API void agal_destroy_bins(agal_bins b);
+AGAL_API void agal_destroy_forest(agal_forest f);
+AGAL_API void agal_destroy_links(agal_links l);
+AGAL_API const char *agal_status_string(agal_status s);
+AGAL_API const char *agal_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AGAL_H */

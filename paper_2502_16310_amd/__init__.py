@@ -1,0 +1,257 @@
+"""Python binding of ``libagal.so`` -- the MI355X near-wall mesh-adaptation path
+(bin faces -> refine near the wall -> link fractions -> adjoint).
+
+The module-level ``agal_*`` functions have the names and arguments of the C
+ABI in ``include/agal.h`` and only marshal arguments (device pointers are
+plain integers, handles are opaque ``ctypes.c_void_p``).  ``Context``,
+``Geometry`` ... wrap them for torch tensors, and ``LinkFractions`` is the
+``torch.autograd.Function`` around the forward and adjoint.  Every step of
+the path runs in the HIP library; there is no fallback: importing this
+package without a built library raises ``ImportError``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libagal.so")
+
+AGAL_OK, AGAL_EINVAL, AGAL_ENOMEM, AGAL_EHIP, AGAL_ECAPACITY, AGAL_ESTATE = range(6)
+AGAL_D2Q9, AGAL_D3Q19, AGAL_D3Q27 = 9, 19, 27
+AGAL_MAX_LEVELS = 8
+
+
+class AgalError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(message)
+        self.status = status
+
+
+class _ForestDesc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("roots", C.c_int * 3), ("n_levels", C.c_int),
+                ("d_spec", C.POINTER(C.c_float)), ("lo", C.c_float * 3), ("hi", C.c_float * 3)]
+
+
+class _Allocator(C.Structure):
+    _fields_ = [("ctx", C.c_void_p),
+                ("alloc", C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)),
+                ("free", C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p))]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
+                          "or `python paper_2502_16310_amd/build.py`")
+    lib = C.CDLL(LIB_PATH)
+    P, vp = C.c_void_p, C.c_void_p
+    i64, i32 = C.c_int64, C.c_int32
+    PP = C.POINTER(C.c_void_p)
+    sig = {
+        "agal_context_create": [C.POINTER(_Allocator), PP],
+        "agal_context_destroy": [P],
+        "agal_import_faces": [P, C.c_int, vp, i64, vp, i64, vp, PP],
+        "agal_geom_view": [P, C.POINTER(C.c_int), C.POINTER(i64), C.POINTER(i64), PP, PP],
+        "agal_bin_faces": [P, C.POINTER(C.c_float), C.POINTER(C.c_float), i32, vp, PP],
+        "agal_bins_view": [P, PP, PP, C.POINTER(i64), C.POINTER(i64)],
+        "agal_near_wall_refine": [P, P, C.POINTER(_ForestDesc), vp, PP],
+        "agal_forest_level_view": [P, C.c_int, PP, PP, PP, PP, C.POINTER(i64)],
+        "agal_forest_info": [P, C.POINTER(C.c_int), C.POINTER(C.c_int)],
+        "agal_link_fractions": [P, P, P, C.c_int, vp, PP],
+        "agal_links_view": [P, PP, PP, PP, C.POINTER(i64), C.POINTER(C.c_int)],
+        "agal_link_fractions_backward": [P, P, vp, vp, vp],
+        "agal_lattice_vectors": [C.c_int, C.POINTER(i32)],
+        "agal_profile_enable": [P, C.c_int],
+        "agal_profile_read": [P, C.c_int, C.POINTER(C.c_char_p), C.POINTER(i64), C.POINTER(C.c_double),
+                              C.POINTER(C.c_int)],
+        "agal_destroy_geom": [P],
+        "agal_destroy_bins": [P],
+        "agal_destroy_forest": [P],
+        "agal_destroy_links": [P],
+        "agal_status_string": [C.c_int],
+        "agal_last_error": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    for name in ("agal_context_destroy", "agal_destroy_geom", "agal_destroy_bins", "agal_destroy_forest",
+                 "agal_destroy_links"):
+        getattr(lib, name).restype = None
+    lib.agal_status_string.restype = C.c_char_p
+    lib.agal_last_error.restype = C.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status: int, what: str):
+    if status != AGAL_OK:
+        msg = _lib.agal_last_error().decode(errors="replace")
+        raise AgalError(status, f"{what}: {_lib.agal_status_string(status).decode()}: {msg}")
+
+
+def _h(x):
+    return x.value if isinstance(x, C.c_void_p) else x
+
+
+# ---------------------------------------------------------------------------
+# C ABI, same names (raw device pointers as ints, handles as c_void_p)
+# ---------------------------------------------------------------------------
+def agal_context_create(allocator: Optional[_Allocator] = None) -> C.c_void_p:
+    out = C.c_void_p()
+    _check(_lib.agal_context_create(C.byref(allocator) if allocator is not None else None, C.byref(out)),
+           "agal_context_create")
+    return out
+
+
+def agal_context_destroy(ctx):
+    _lib.agal_context_destroy(_h(ctx))
+
+
+def agal_import_faces(ctx, dim: int, d_vertices: int, n_vertices: int, d_faces: Optional[int], n_faces: int,
+                      stream: int = 0) -> C.c_void_p:
+    out = C.c_void_p()
+    _check(_lib.agal_import_faces(_h(ctx), dim, d_vertices, n_vertices, d_faces or None, n_faces, stream or None,
+                                  C.byref(out)), "agal_import_faces")
+    return out
+
+
+def agal_geom_view(geom):
+    dim, F, Nv = C.c_int(), C.c_int64(), C.c_int64()
+    co, bb = C.c_void_p(), C.c_void_p()
+    _check(_lib.agal_geom_view(_h(geom), C.byref(dim), C.byref(F), C.byref(Nv), C.byref(co), C.byref(bb)),
+           "agal_geom_view")
+    return dim.value, F.value, Nv.value, co.value, bb.value
+
+
+def _f3(v, fill):
+    a = (C.c_float * 3)(fill, fill, fill)
+    for i, x in enumerate(list(v)[:3]):
+        a[i] = float(x)
+    return a
+
+
+def agal_bin_faces(geom, lo: Sequence[float], hi: Sequence[float], B: int, stream: int = 0) -> C.c_void_p:
+    out = C.c_void_p()
+    _check(_lib.agal_bin_faces(_h(geom), _f3(lo, 0.0), _f3(hi, 1.0), int(B), stream or None, C.byref(out)),
+           "agal_bin_faces")
+    return out
+
+
+def agal_bins_view(bins):
+    off, ids = C.c_void_p(), C.c_void_p()
+    nb, P = C.c_int64(), C.c_int64()
+    _check(_lib.agal_bins_view(_h(bins), C.byref(off), C.byref(ids), C.byref(nb), C.byref(P)), "agal_bins_view")
+    return off.value, ids.value, nb.value, P.value
+
+
+def forest_desc(dim: int, roots: Sequence[int], n_levels: int, d_spec: Sequence[float], lo: Sequence[float],
+                hi: Sequence[float]):
+    d = (C.c_float * max(1, n_levels))(*[float(x) for x in list(d_spec)[:n_levels]])
+    desc = _ForestDesc()
+    desc.dim = dim
+    r = list(roots) + [1] * (3 - len(roots))
+    desc.roots = (C.c_int * 3)(*[int(x) for x in r[:3]])
+    desc.n_levels = n_levels
+    desc.d_spec = C.cast(d, C.POINTER(C.c_float))
+    desc.lo = _f3(lo, 0.0)
+    desc.hi = _f3(hi, 1.0)
+    desc._keep = d
+    return desc
+
+
+def agal_near_wall_refine(geom, bins, desc: _ForestDesc, stream: int = 0) -> C.c_void_p:
+    out = C.c_void_p()
+    _check(_lib.agal_near_wall_refine(_h(geom), _h(bins), C.byref(desc), stream or None, C.byref(out)),
+           "agal_near_wall_refine")
+    return out
+
+
+def agal_forest_level_view(forest, level: int):
+    k, lf, mk, cf = C.c_void_p(), C.c_void_p(), C.c_void_p(), C.c_void_p()
+    n = C.c_int64()
+    _check(_lib.agal_forest_level_view(_h(forest), level, C.byref(k), C.byref(lf), C.byref(mk), C.byref(cf),
+                                       C.byref(n)), "agal_forest_level_view")
+    return k.value, lf.value, mk.value, cf.value, n.value
+
+
+def agal_forest_info(forest):
+    dim, L = C.c_int(), C.c_int()
+    _check(_lib.agal_forest_info(_h(forest), C.byref(dim), C.byref(L)), "agal_forest_info")
+    return dim.value, L.value
+
+
+def agal_link_fractions(geom, bins, forest, lattice: int, stream: int = 0) -> C.c_void_p:
+    out = C.c_void_p()
+    _check(_lib.agal_link_fractions(_h(geom), _h(bins), _h(forest), int(lattice), stream or None, C.byref(out)),
+           "agal_link_fractions")
+    return out
+
+
+def agal_links_view(links):
+    k, q, f = C.c_void_p(), C.c_void_p(), C.c_void_p()
+    n, Q = C.c_int64(), C.c_int()
+    _check(_lib.agal_links_view(_h(links), C.byref(k), C.byref(q), C.byref(f), C.byref(n), C.byref(Q)),
+           "agal_links_view")
+    return k.value, q.value, f.value, n.value, Q.value
+
+
+def agal_link_fractions_backward(geom, links, d_grad_q: int, d_grad_vertices: int, stream: int = 0):
+    _check(_lib.agal_link_fractions_backward(_h(geom), _h(links), d_grad_q, d_grad_vertices, stream or None),
+           "agal_link_fractions_backward")
+
+
+def agal_lattice_vectors(lattice: int):
+    buf = (C.c_int32 * (3 * lattice))()
+    _check(_lib.agal_lattice_vectors(int(lattice), buf), "agal_lattice_vectors")
+    return [tuple(buf[3 * i:3 * i + 3]) for i in range(lattice)]
+
+
+def agal_profile_enable(ctx, enable: bool = True):
+    _check(_lib.agal_profile_enable(_h(ctx), 1 if enable else 0), "agal_profile_enable")
+
+
+def agal_profile_read(ctx, max_entries: int = 64):
+    """{kernel name: (launches, total ms)} recorded since the last read."""
+    names = (C.c_char_p * max_entries)()
+    launches = (C.c_int64 * max_entries)()
+    ms = (C.c_double * max_entries)()
+    n = C.c_int()
+    _check(_lib.agal_profile_read(_h(ctx), max_entries, names, launches, ms, C.byref(n)), "agal_profile_read")
+    return {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(n.value)}
+
+
+def agal_destroy_geom(h):
+    _lib.agal_destroy_geom(_h(h))
+
+
+def agal_destroy_bins(h):
+    _lib.agal_destroy_bins(_h(h))
+
+
+def agal_destroy_forest(h):
+    _lib.agal_destroy_forest(_h(h))
+
+
+def agal_destroy_links(h):
+    _lib.agal_destroy_links(_h(h))
+
+
+def agal_status_string(s: int) -> str:
+    return _lib.agal_status_string(int(s)).decode()
+
+
+def agal_last_error() -> str:
+    return _lib.agal_last_error().decode(errors="replace")
+
+
+from .torch_api import (Bins, Context, Forest, Geometry, LinkFractions, Links, NearWallConfig,  # noqa: E402
+                        device_copy, near_wall)
+
+__all__ = [n for n in dir() if n.startswith("agal_")] + [
+    "AgalError", "Context", "Geometry", "Bins", "Forest", "Links", "LinkFractions", "NearWallConfig", "near_wall",
+    "forest_desc", "device_copy", "LIB_PATH"]

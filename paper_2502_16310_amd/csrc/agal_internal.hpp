@@ -1,0 +1,185 @@
+// Private declarations of the HIP library: handle layouts, allocation and
+// error plumbing, and the launchers each translation unit exports to the
+// others.  Device arithmetic lives in device.hpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "agal.h"
+
+namespace agal {
+
+constexpr int kMaxLevels = AGAL_MAX_LEVELS;
+
+// Records a message for agal_last_error() and returns `s`.
+agal_status fail(agal_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define AGAL_TRY_HIP(expr)                                                                   \
+    do {                                                                                     \
+        hipError_t e__ = (expr);                                                             \
+        if (e__ != hipSuccess)                                                               \
+            return ::agal::fail(AGAL_EHIP, "%s failed: %s", #expr, hipGetErrorString(e__));  \
+    } while (0)
+
+#define AGAL_TRY(expr)                              \
+    do {                                            \
+        agal_status s__ = (expr);                   \
+        if (s__ != AGAL_OK) return s__;             \
+    } while (0)
+
+// Device memory through the context's allocator (user callback or the HIP
+// stream-ordered pool).  Every allocation is stream ordered.
+struct Allocator {
+    agal_allocator user{};
+    bool has_user = false;
+    void *alloc(size_t bytes, hipStream_t s) const;
+    void release(void *p, hipStream_t s) const;
+};
+
+template <class T>
+inline agal_status dev_alloc(const Allocator &a, T **p, size_t count, hipStream_t s) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    void *q = a.alloc(count * sizeof(T), s);
+    if (!q) return fail(AGAL_ENOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
+    *p = static_cast<T *>(q);
+    return AGAL_OK;
+}
+
+template <class T>
+inline void dev_free(const Allocator &a, T *&p, hipStream_t s) {
+    if (p) a.release(p, s);
+    p = nullptr;
+}
+
+uint64_t next_handle_id();
+
+}  // namespace agal
+
+namespace agal {
+struct ProfRecord {
+    const char *name;
+    hipEvent_t start, stop;
+};
+}  // namespace agal
+
+struct agal_context_t {
+    agal::Allocator mem;
+    int device = 0;
+    // small pinned host buffer for count read-backs
+    uint32_t *h_counts = nullptr;
+    size_t h_counts_cap = 0;
+    // kernel timing (HIP events around each launch) when enabled
+    bool profiling = false;
+    std::vector<agal::ProfRecord> records;
+    std::vector<hipEvent_t> event_pool;
+};
+
+struct agal_geom_t {
+    agal_context ctx = nullptr;
+    uint64_t id = 0;
+    hipStream_t stream = nullptr;
+    int dim = 0;
+    int64_t F = 0, Nv = 0;
+    float *coords = nullptr;   // (dim*dim) x F
+    float *aabb = nullptr;     // (2*dim) x F
+    int32_t *fidx = nullptr;   // F x dim
+};
+
+struct agal_bins_t {
+    agal_context ctx = nullptr;
+    uint64_t geom_id = 0;
+    hipStream_t stream = nullptr;
+    int dim = 0, B = 0;
+    float lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1}, s[3] = {0, 0, 0};
+    int64_t nb = 0, P = 0;
+    uint32_t *off = nullptr;   // nb + 1
+    int32_t *ids = nullptr;    // P
+};
+
+namespace agal {
+struct Level {
+    int64_t n = 0;
+    uint32_t *keys = nullptr;
+    uint8_t *leaf = nullptr;
+    uint8_t *mark = nullptr;   // export mark: 1 flagged, 2 balance
+    uint8_t *cf = nullptr;     // per-cell flags (levels that were tested)
+};
+}  // namespace agal
+
+struct agal_forest_t {
+    agal_context ctx = nullptr;
+    uint64_t geom_id = 0;
+    hipStream_t stream = nullptr;
+    int dim = 0, L = 0;
+    int roots[3] = {1, 1, 1};
+    float lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+    float dx[agal::kMaxLevels + 1][3] = {};
+    float d[agal::kMaxLevels] = {};
+    agal::Level lev[agal::kMaxLevels + 1];
+};
+
+struct agal_links_t {
+    agal_context ctx = nullptr;
+    uint64_t geom_id = 0;
+    hipStream_t stream = nullptr;
+    int dim = 0, Q = 0, L = 0;
+    int roots[3] = {1, 1, 1};
+    float lo[3] = {0, 0, 0};
+    float dx[3] = {0, 0, 0};
+    int64_t n = 0;
+    uint64_t *key = nullptr;
+    float *q = nullptr;
+    int32_t *face = nullptr;
+};
+
+namespace agal {
+
+// Lattice table shared by the link and adjoint kernels (host copy; kernels
+// receive it by value).
+struct Lattice {
+    int Q = 0;
+    int dim = 0;
+    int8_t c[27][3] = {};
+};
+bool lattice_table(int Q, Lattice *out);
+
+// Device-wide exclusive scan of `n` 0/1-or-count values into out[0..n]
+// (out[n] = total).  The input is either uint32 counts or uint8 flags
+// (nonzero = 1).  Scratch is allocated from the context.
+agal_status scan_u32(agal_context ctx, const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s);
+agal_status scan_flags_u8(agal_context ctx, const uint8_t *in, uint32_t *out, int64_t n, hipStream_t s);
+
+// Look-back scratch: status words + ticket for `tiles` tiles, cleared.
+agal_status lookback_alloc(agal_context ctx, int64_t tiles, uint64_t **status, uint32_t **ticket, hipStream_t s);
+
+// Fill kernels (used instead of hipMemsetAsync so the calls stay capturable).
+void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
+void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+void fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
+
+// Records HIP events around the launches in its scope when the context's
+// profiling is on; results are aggregated by agal_profile_read.
+class ProfScope {
+  public:
+    ProfScope(agal_context ctx, const char *name, hipStream_t s);
+    ~ProfScope();
+    ProfScope(const ProfScope &) = delete;
+    ProfScope &operator=(const ProfScope &) = delete;
+
+  private:
+    agal_context ctx_;
+    const char *name_;
+    hipStream_t s_;
+    hipEvent_t start_ = nullptr;
+};
+
+// Read a few uint32 device values back (synchronises the stream).
+agal_status read_back_u32(agal_context ctx, const uint32_t *const *srcs, int n, uint32_t *dst, hipStream_t s);
+
+}  // namespace agal

@@ -1,0 +1,463 @@
+// Near-wall refinement (paper Sec. II-C-1, II-C-2; forest layout Sec. II-A).
+//
+// Level by level: every cell of every block of the tested level checks the
+// faces of the bins its query box overlaps (the paper's "primary mode of
+// access": one level at a time, the block's cells processed together); a
+// block with a flagged cell is marked, 2:1 balance marks the coarser
+// neighbours that must follow, and marked blocks are replaced by 2^D children
+// merged into the next level's sorted key list.
+//
+// Mapping on CDNA: one wave64 per 4x4x4 block (one lane per cell; four 4x4
+// blocks per wave in 2D).  The wave walks the bins under the block's query
+// box, culls each face against the box by its bounding box (lane-parallel,
+// one face per lane), compacts the survivors with a ballot into LDS, then
+// every lane runs the separating-axis test of its cell against the staged
+// faces (LDS broadcast reads) and stops once flagged.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "agal_internal.hpp"
+#include "device.hpp"
+
+namespace agal {
+namespace {
+
+constexpr int kFlagCap = 256;  // staged candidate faces per wave
+
+template <int D>
+struct FlagArgs {
+    dev::Faces faces;
+    dev::BinGrid bins;
+    const uint32_t *keys;
+    int64_t n;
+    int level;
+    int R[3];
+    float lo[3];
+    float dx[3];
+    float eps[3];
+    float h;
+    uint8_t *cf;     // n * 4^D
+    uint8_t *pmark;  // n
+};
+
+template <int D>
+__global__ __launch_bounds__(64) void k_flag(FlagArgs<D> A) {
+    constexpr int CELLS = D == 3 ? 64 : 16;
+    constexpr int BPW = 64 / CELLS;
+    __shared__ float s_f[D * D][kFlagCap];
+    const int lane = threadIdx.x;
+    const int64_t first = (int64_t)blockIdx.x * BPW;
+    const int64_t blk = first + lane / CELLS;
+    const bool valid = blk < A.n;
+    const int cell = lane % CELLS;
+
+    int bc[3] = {0, 0, 0};
+    if (valid) dev::decode_key<D>(A.keys[blk], A.level, A.R[0], A.R[1], bc);
+    const int g0 = 4 * bc[0] + (cell & 3), g1 = 4 * bc[1] + ((cell >> 2) & 3), g2 = 4 * bc[2] + (cell >> 4);
+    float m[3];
+    m[0] = dev::cell_centre(A.lo[0], g0, A.dx[0]);
+    m[1] = dev::cell_centre(A.lo[1], g1, A.dx[1]);
+    m[2] = D == 3 ? dev::cell_centre(A.lo[2], g2, A.dx[2]) : 0.0f;
+    const float h = A.h;
+    bool flagged = !valid;
+    const int64_t F = A.faces.F;
+
+    int count = 0;  // staged faces (wave-uniform)
+    auto test_staged = [&](int n) {
+        __syncthreads();
+        for (int j = 0; j < n; ++j) {
+            if (!flagged) {
+                float v[D * D];
+#pragma unroll
+                for (int k = 0; k < D * D; ++k) v[k] = s_f[k][j];
+                if (D == 3) flagged = dev::sat_triangle(v, m, h);
+                else flagged = dev::sat_segment(v, m, h);
+            }
+            if ((j & 7) == 7 && __ballot(!flagged) == 0) break;
+        }
+        __syncthreads();
+    };
+
+    bool done = __ballot(!flagged) == 0;
+    for (int sb = 0; sb < BPW && !done; ++sb) {
+        if (first + sb >= A.n) break;
+        // block coordinates of sub-block sb (from its first lane)
+        int sc[3];
+        sc[0] = __shfl(bc[0], sb * CELLS, 64);
+        sc[1] = __shfl(bc[1], sb * CELLS, 64);
+        sc[2] = __shfl(bc[2], sb * CELLS, 64);
+        float qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
+        int ilo[3] = {0, 0, 0}, ihi[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            qlo[a] = (dev::cell_centre(A.lo[a], 4 * sc[a], A.dx[a]) - h) - A.eps[a];
+            qhi[a] = (dev::cell_centre(A.lo[a], 4 * sc[a] + 3, A.dx[a]) + h) + A.eps[a];
+            ilo[a] = dev::bin_of(qlo[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
+            ihi[a] = dev::bin_of(qhi[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
+        }
+        for (int z = ilo[2]; z <= ihi[2] && !done; ++z)
+            for (int y = ilo[1]; y <= ihi[1] && !done; ++y)
+                for (int x = ilo[0]; x <= ihi[0] && !done; ++x) {
+                    const int64_t b = ((int64_t)z * A.bins.B + y) * A.bins.B + x;
+                    const uint32_t s0 = A.bins.off[b], s1 = A.bins.off[b + 1];
+                    for (uint32_t base = s0; base < s1 && !done; base += 64) {
+                        const uint32_t j = base + lane;
+                        bool keep = false;
+                        int32_t f = -1;
+                        if (j < s1) {
+                            f = A.bins.ids[j];
+                            keep = true;
+                            const int cur[3] = {x, y, z};
+#pragma unroll
+                            for (int a = 0; a < D; ++a) {
+                                const float mn = A.faces.aabb[(int64_t)a * F + f];
+                                const float mx = A.faces.aabb[(int64_t)(D + a) * F + f];
+                                // visit each face once: in the first bin of (its bins) x (query bins)
+                                const int fb = max(dev::bin_of(mn, A.bins.lo[a], A.bins.s[a], A.bins.B), ilo[a]);
+                                keep = keep && fb == cur[a] && mn <= qhi[a] && mx >= qlo[a];
+                            }
+                        }
+                        const uint64_t mask = __ballot(keep);
+                        const int nk = __popcll(mask);
+                        if (nk == 0) continue;
+                        if (count + nk > kFlagCap) {
+                            test_staged(count);
+                            count = 0;
+                            done = __ballot(!flagged) == 0;
+                            if (done) break;
+                        }
+                        if (keep) {
+                            const int pos = count + dev::lanes_below(mask);
+#pragma unroll
+                            for (int k = 0; k < D * D; ++k) s_f[k][pos] = A.faces.coords[(int64_t)k * F + f];
+                        }
+                        count += nk;
+                    }
+                }
+    }
+    if (!done && count > 0) test_staged(count);
+
+    if (valid) A.cf[blk * CELLS + cell] = flagged ? 1 : 0;
+    // block mark: OR over the block's cells
+    const uint64_t fm = __ballot(valid && flagged);
+    if (valid && cell == 0) {
+        uint64_t bm = fm;
+        if constexpr (CELLS < 64) bm = (fm >> (lane & ~(CELLS - 1))) & ((1ull << CELLS) - 1);
+        A.pmark[blk] = bm ? 1 : 0;
+    }
+}
+
+// 2:1 balance: a block of level m marked in this pass needs every neighbour
+// position (faces, edges, corners) inside the domain to exist at level m;
+// where it does not, the covering level-(m-1) leaf is marked.
+template <int D>
+__global__ void k_ripple(const uint32_t *keys_m, int64_t n_m, const uint8_t *pm_m, int m, const uint32_t *keys_p,
+                         int64_t n_p, const uint8_t *leaf_p, uint8_t *pm_p, int R0, int R1, int R2, uint32_t *err) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_m; i += (int64_t)gridDim.x * blockDim.x) {
+        if (!pm_m[i]) continue;
+        int c[3];
+        dev::decode_key<D>(keys_m[i], m, R0, R1, c);
+        const int ext[3] = {R0 << m, R1 << m, R2 << m};
+        for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (!dx && !dy && !dz) continue;
+                    int nc[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+                    if (nc[0] < 0 || nc[0] >= ext[0] || nc[1] < 0 || nc[1] >= ext[1]) continue;
+                    if (D == 3 && (nc[2] < 0 || nc[2] >= ext[2])) continue;
+                    const uint32_t kn = dev::encode_key<D>(nc, m, R0, R1);
+                    const int64_t jn = dev::lower_bound_u32(keys_m, n_m, kn);
+                    if (jn < n_m && keys_m[jn] == kn) continue;
+                    int pc[3] = {nc[0] >> 1, nc[1] >> 1, D == 3 ? nc[2] >> 1 : 0};
+                    const uint32_t kp = dev::encode_key<D>(pc, m - 1, R0, R1);
+                    const int64_t jp = dev::lower_bound_u32(keys_p, n_p, kp);
+                    if (jp < n_p && keys_p[jp] == kp && leaf_p[jp]) pm_p[jp] = 2;
+                    else atomicOr(err, 1u);
+                }
+    }
+}
+
+// Marked blocks of level m: become parents (leaf 0, export mark = pass mark)
+// and their keys are compacted in order into mk.
+__global__ void k_mark_parents(const uint32_t *keys, const uint8_t *pm, const uint32_t *pos, int64_t n, uint8_t *leaf,
+                               uint8_t *mark, uint32_t *mk) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t p = pm[i];
+        if (!p) continue;
+        leaf[i] = 0;
+        mark[i] = p;
+        mk[pos[i]] = keys[i];
+    }
+}
+
+// Existing blocks of level m+1 move to their place in the merged list.
+template <int CELLS>
+__global__ void k_merge_old(const uint32_t *keys, const uint8_t *leaf, const uint8_t *mark, const uint8_t *cf,
+                            int64_t n_old, const uint32_t *mk, int64_t n_mk, int D, uint32_t *nkeys, uint8_t *nleaf,
+                            uint8_t *nmark, uint8_t *ncf) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_old; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = keys[i];
+        const int64_t r = dev::lower_bound_u32(mk, n_mk, k >> D);
+        const int64_t p = i + (r << D);
+        nkeys[p] = k;
+        nleaf[p] = leaf[i];
+        nmark[p] = mark[i];
+        if (ncf)
+            for (int c = 0; c < CELLS; ++c) ncf[p * CELLS + c] = cf[i * CELLS + c];
+    }
+}
+
+// Children of the marked parents, placed after the existing keys below them.
+template <int CELLS>
+__global__ void k_children(const uint32_t *mk, int64_t n_mk, const uint32_t *keys_old, int64_t n_old, int D,
+                           uint32_t *nkeys, uint8_t *nleaf, uint8_t *nmark, uint8_t *ncf) {
+    const int64_t total = n_mk << D;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pi = t >> D;
+        const uint32_t ci = (uint32_t)(t & ((1 << D) - 1));
+        const uint32_t parent = mk[pi];
+        const int64_t below = dev::lower_bound_u32(keys_old, n_old, parent << D);
+        const int64_t p = below + t;
+        nkeys[p] = (parent << D) | ci;
+        nleaf[p] = 1;
+        nmark[p] = 0;
+        if (ncf)
+            for (int c = 0; c < CELLS; ++c) ncf[p * CELLS + c] = 0;
+    }
+}
+
+__global__ void k_iota_u32(uint32_t *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (uint32_t)i;
+}
+
+unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 16384) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+struct Scratch {
+    agal_context ctx;
+    hipStream_t s;
+    std::vector<void *> ptrs;
+    template <class T>
+    agal_status get(T **p, size_t n) {
+        AGAL_TRY(dev_alloc(ctx->mem, p, n, s));
+        ptrs.push_back(*p);
+        return AGAL_OK;
+    }
+    ~Scratch() {
+        for (void *p : ptrs) ctx->mem.release(p, s);
+    }
+};
+
+template <int D>
+agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s) {
+    constexpr int CELLS = D == 3 ? 64 : 16;
+    constexpr int BPW = 64 / CELLS;
+    agal_context ctx = g->ctx;
+    const auto &mem = ctx->mem;
+    uint32_t *err = nullptr;
+    Scratch keep{ctx, s, {}};
+    AGAL_TRY(keep.get(&err, 1));
+    fill_u32(err, 0u, 1, s);
+
+    // level 0: every root, key = x-fastest linear index
+    agal::Level &L0 = fo->lev[0];
+    L0.n = (int64_t)fo->roots[0] * fo->roots[1] * fo->roots[2];
+    AGAL_TRY(dev_alloc(mem, &L0.keys, (size_t)L0.n, s));
+    AGAL_TRY(dev_alloc(mem, &L0.leaf, (size_t)L0.n, s));
+    AGAL_TRY(dev_alloc(mem, &L0.mark, (size_t)L0.n, s));
+    hipLaunchKernelGGL(k_iota_u32, dim3(grid_for(L0.n)), dim3(256), 0, s, L0.keys, L0.n);
+    fill_u8(L0.leaf, 1, L0.n, s);
+    fill_u8(L0.mark, 0, L0.n, s);
+
+    dev::BinGrid bins{};
+    bins.off = bn->off;
+    bins.ids = bn->ids;
+    bins.B = bn->B;
+    for (int a = 0; a < 3; ++a) {
+        bins.lo[a] = bn->lo[a];
+        bins.s[a] = bn->s[a];
+    }
+    dev::Faces faces{g->coords, g->aabb, g->F};
+
+    for (int l = 0; l < fo->L; ++l) {
+        Scratch pass{ctx, s, {}};
+        uint8_t *pm[kMaxLevels + 1] = {};
+        for (int m = 0; m <= l; ++m) {
+            AGAL_TRY(pass.get(&pm[m], (size_t)fo->lev[m].n));
+            fill_u8(pm[m], 0, fo->lev[m].n, s);
+        }
+        // (i) flag every cell of every level-l block
+        agal::Level &Ll = fo->lev[l];
+        AGAL_TRY(dev_alloc(mem, &Ll.cf, (size_t)Ll.n * CELLS, s));
+        if (Ll.n > 0) {
+            FlagArgs<D> A{};
+            A.faces = faces;
+            A.bins = bins;
+            A.keys = Ll.keys;
+            A.n = Ll.n;
+            A.level = l;
+            for (int a = 0; a < 3; ++a) {
+                A.R[a] = fo->roots[a];
+                A.lo[a] = fo->lo[a];
+                A.dx[a] = fo->dx[l][a];
+                float sc = std::max(1.0f, std::max(std::fabs(fo->lo[a]), std::fabs(fo->hi[a])));
+                A.eps[a] = dev::kEps * sc;
+            }
+            A.h = fo->d[l];
+            A.cf = Ll.cf;
+            A.pmark = pm[l];
+            const int64_t waves = (Ll.n + BPW - 1) / BPW;
+            ProfScope prof(ctx, "flag_sat", s);
+            hipLaunchKernelGGL(k_flag<D>, dim3((unsigned)waves), dim3(64), 0, s, A);
+        }
+        // (ii) balance ripple, level l down to 1
+        for (int m = l; m >= 1; --m) {
+            if (fo->lev[m].n == 0) continue;
+            ProfScope prof(ctx, "balance_ripple", s);
+            hipLaunchKernelGGL(k_ripple<D>, dim3(grid_for(fo->lev[m].n)), dim3(256), 0, s, fo->lev[m].keys,
+                               fo->lev[m].n, pm[m], m, fo->lev[m - 1].keys, fo->lev[m - 1].n, fo->lev[m - 1].leaf,
+                               pm[m - 1], fo->roots[0], fo->roots[1], fo->roots[2], err);
+        }
+        // (iii) children: count marks per level, then merge level by level
+        uint32_t *pos[kMaxLevels + 1] = {};
+        const uint32_t *totals[kMaxLevels + 2] = {};
+        for (int m = 0; m <= l; ++m) {
+            AGAL_TRY(pass.get(&pos[m], (size_t)fo->lev[m].n + 1));
+            AGAL_TRY(scan_flags_u8(ctx, pm[m], pos[m], fo->lev[m].n, s));
+            totals[m] = pos[m] + fo->lev[m].n;
+        }
+        totals[l + 1] = err;
+        uint32_t nmark[kMaxLevels + 2] = {};
+        AGAL_TRY(read_back_u32(ctx, totals, l + 2, nmark, s));
+        if (nmark[l + 1] != 0) return fail(AGAL_ESTATE, "agal_near_wall_refine: forest lost 2:1 balance");
+        for (int m = l; m >= 0; --m) {
+            const int64_t c = nmark[m];
+            agal::Level &P = fo->lev[m];
+            agal::Level &C = fo->lev[m + 1];
+            if (c == 0) {
+                if (m + 1 == l + 1 && C.keys == nullptr) {
+                    // no child level yet: an empty one keeps views valid
+                    AGAL_TRY(dev_alloc(mem, &C.keys, 1, s));
+                    AGAL_TRY(dev_alloc(mem, &C.leaf, 1, s));
+                    AGAL_TRY(dev_alloc(mem, &C.mark, 1, s));
+                    C.n = 0;
+                }
+                continue;
+            }
+            uint32_t *mk = nullptr;
+            AGAL_TRY(pass.get(&mk, (size_t)c));
+            ProfScope prof(ctx, "child_gen", s);
+            hipLaunchKernelGGL(k_mark_parents, dim3(grid_for(P.n)), dim3(256), 0, s, P.keys, pm[m], pos[m], P.n,
+                               P.leaf, P.mark, mk);
+            agal::Level N;
+            N.n = C.n + (c << D);
+            AGAL_TRY(dev_alloc(mem, &N.keys, (size_t)N.n, s));
+            AGAL_TRY(dev_alloc(mem, &N.leaf, (size_t)N.n, s));
+            AGAL_TRY(dev_alloc(mem, &N.mark, (size_t)N.n, s));
+            if (C.cf) AGAL_TRY(dev_alloc(mem, &N.cf, (size_t)N.n * CELLS, s));
+            if (C.n > 0)
+                hipLaunchKernelGGL(k_merge_old<CELLS>, dim3(grid_for(C.n)), dim3(256), 0, s, C.keys, C.leaf, C.mark,
+                                   C.cf, C.n, mk, c, D, N.keys, N.leaf, N.mark, N.cf);
+            hipLaunchKernelGGL(k_children<CELLS>, dim3(grid_for(c << D)), dim3(256), 0, s, mk, c, C.keys, C.n, D,
+                               N.keys, N.leaf, N.mark, N.cf);
+            dev_free(mem, C.keys, s);
+            dev_free(mem, C.leaf, s);
+            dev_free(mem, C.mark, s);
+            dev_free(mem, C.cf, s);
+            C = N;
+        }
+        AGAL_TRY_HIP(hipGetLastError());
+    }
+    return AGAL_OK;
+}
+
+}  // namespace
+}  // namespace agal
+
+using namespace agal;
+
+extern "C" {
+
+agal_status agal_near_wall_refine(agal_geom g, agal_bins b, const agal_forest_desc *desc, void *stream,
+                                  agal_forest *out) {
+    if (!g || !b || !desc || !out) return fail(AGAL_EINVAL, "agal_near_wall_refine: NULL argument");
+    if (b->geom_id != g->id) return fail(AGAL_ESTATE, "agal_near_wall_refine: bins were built from another geometry");
+    const int D = desc->dim;
+    if (D != g->dim) return fail(AGAL_EINVAL, "agal_near_wall_refine: desc->dim %d != geometry dim %d", D, g->dim);
+    if (desc->n_levels < 0 || desc->n_levels > kMaxLevels)
+        return fail(AGAL_EINVAL, "agal_near_wall_refine: n_levels must be in [0, %d]", kMaxLevels);
+    if (desc->n_levels > 0 && !desc->d_spec) return fail(AGAL_EINVAL, "agal_near_wall_refine: d_spec is NULL");
+    uint64_t nroots = 1;
+    for (int a = 0; a < D; ++a) {
+        if (desc->roots[a] < 1) return fail(AGAL_EINVAL, "agal_near_wall_refine: roots must be >= 1");
+        if (!(desc->hi[a] > desc->lo[a])) return fail(AGAL_EINVAL, "agal_near_wall_refine: hi must exceed lo");
+        nroots *= (uint64_t)desc->roots[a];
+    }
+    if ((nroots << (D * desc->n_levels)) > ((uint64_t)1 << 32) || nroots > ((uint64_t)1 << 32))
+        return fail(AGAL_EINVAL, "agal_near_wall_refine: roots * 2^(D*n_levels) exceeds the 32-bit key space");
+    for (int l = 0; l < desc->n_levels; ++l)
+        if (!(desc->d_spec[l] >= 0.0f) || !std::isfinite(desc->d_spec[l]))
+            return fail(AGAL_EINVAL, "agal_near_wall_refine: d_spec[%d] must be finite and >= 0", l);
+
+    auto *fo = new (std::nothrow) agal_forest_t();
+    if (!fo) return fail(AGAL_ENOMEM, "agal_near_wall_refine: host allocation failed");
+    fo->ctx = g->ctx;
+    fo->geom_id = g->id;
+    fo->stream = (hipStream_t)stream;
+    fo->dim = D;
+    fo->L = desc->n_levels;
+    for (int a = 0; a < 3; ++a) {
+        fo->roots[a] = a < D ? desc->roots[a] : 1;
+        fo->lo[a] = a < D ? desc->lo[a] : 0.0f;
+        fo->hi[a] = a < D ? desc->hi[a] : 1.0f;
+    }
+    for (int l = 0; l <= fo->L; ++l)
+        for (int a = 0; a < 3; ++a) fo->dx[l][a] = (fo->hi[a] - fo->lo[a]) / (float)(4 * fo->roots[a] * (1 << l));
+    for (int l = 0; l < fo->L; ++l) fo->d[l] = desc->d_spec[l];
+    agal_status st = D == 3 ? refine_impl<3>(g, b, fo, (hipStream_t)stream) : refine_impl<2>(g, b, fo, (hipStream_t)stream);
+    if (st != AGAL_OK) {
+        agal_destroy_forest(fo);
+        return st;
+    }
+    *out = fo;
+    return AGAL_OK;
+}
+
+agal_status agal_forest_level_view(agal_forest f, int level, const uint32_t **d_keys, const uint8_t **d_leaf,
+                                   const uint8_t **d_mark, const uint8_t **d_cell_flag, int64_t *n_blocks) {
+    if (!f) return fail(AGAL_EINVAL, "agal_forest_level_view: NULL forest");
+    if (level < 0 || level > f->L) return fail(AGAL_EINVAL, "agal_forest_level_view: level %d outside [0, %d]", level, f->L);
+    const agal::Level &L = f->lev[level];
+    if (d_keys) *d_keys = L.keys;
+    if (d_leaf) *d_leaf = L.leaf;
+    if (d_mark) *d_mark = L.mark;
+    if (d_cell_flag) *d_cell_flag = level < f->L ? L.cf : nullptr;
+    if (n_blocks) *n_blocks = L.n;
+    return AGAL_OK;
+}
+
+agal_status agal_forest_info(agal_forest f, int *dim, int *n_levels) {
+    if (!f) return fail(AGAL_EINVAL, "agal_forest_info: NULL forest");
+    if (dim) *dim = f->dim;
+    if (n_levels) *n_levels = f->L;
+    return AGAL_OK;
+}
+
+void agal_destroy_forest(agal_forest f) {
+    if (!f) return;
+    for (int l = 0; l <= kMaxLevels; ++l) {
+        dev_free(f->ctx->mem, f->lev[l].keys, f->stream);
+        dev_free(f->ctx->mem, f->lev[l].leaf, f->stream);
+        dev_free(f->ctx->mem, f->lev[l].mark, f->stream);
+        dev_free(f->ctx->mem, f->lev[l].cf, f->stream);
+    }
+    delete f;
+}
+
+}  // extern "C"

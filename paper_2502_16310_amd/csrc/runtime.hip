@@ -1,0 +1,354 @@
+// Runtime pieces of the library: error reporting, the device allocator,
+// fill kernels, the single-pass exclusive scan and small read-backs.
+#include <atomic>
+#include <cstdio>
+#include <cstring>
+
+#include "agal_internal.hpp"
+#include "device.hpp"
+
+namespace agal {
+
+static thread_local char g_err[512] = "";
+
+agal_status fail(agal_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+uint64_t next_handle_id() {
+    static std::atomic<uint64_t> next{1};
+    return next.fetch_add(1);
+}
+
+void *Allocator::alloc(size_t bytes, hipStream_t s) const {
+    if (has_user) return user.alloc(user.ctx, bytes, (void *)s);
+    void *p = nullptr;
+    if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void Allocator::release(void *p, hipStream_t s) const {
+    if (!p) return;
+    if (has_user) {
+        user.free(user.ctx, p, (void *)s);
+        return;
+    }
+    (void)hipFreeAsync(p, s);
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+static hipEvent_t take_event(agal_context ctx) {
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+ProfScope::ProfScope(agal_context ctx, const char *name, hipStream_t s) : ctx_(ctx), name_(name), s_(s) {
+    if (!ctx_ || !ctx_->profiling) return;
+    start_ = take_event(ctx_);
+    if (start_ && hipEventRecord(start_, s_) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx_->event_pool.push_back(start_);
+        start_ = nullptr;
+    }
+}
+
+ProfScope::~ProfScope() {
+    if (!start_) return;
+    hipEvent_t stop = take_event(ctx_);
+    if (stop && hipEventRecord(stop, s_) == hipSuccess) {
+        ctx_->records.push_back({name_, start_, stop});
+        return;
+    }
+    (void)hipGetLastError();
+    ctx_->event_pool.push_back(start_);
+    if (stop) ctx_->event_pool.push_back(stop);
+}
+
+// ---------------------------------------------------------------------------
+// fills
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_fill(T *p, T v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <class T>
+static void fill(T *p, T v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
+}
+
+void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) { fill(p, v, n, s); }
+void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) { fill(p, v, n, s); }
+void fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s) { fill(p, v, n, s); }
+
+// ---------------------------------------------------------------------------
+// exclusive scan (decoupled look-back)
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+struct LoadU32 {
+    const uint32_t *p;
+    __device__ uint32_t operator()(int64_t i) const { return p[i]; }
+};
+struct LoadFlagU8 {
+    const uint8_t *p;
+    __device__ uint32_t operator()(int64_t i) const { return p[i] != 0 ? 1u : 0u; }
+};
+
+template <class In>
+__global__ __launch_bounds__(kScanThreads) void k_scan(In in, uint32_t *out, int64_t n, uint64_t *status,
+                                                       uint32_t *ticket) {
+    __shared__ uint32_t s_tile, s_prefix;
+    __shared__ uint32_t s_wsum[kScanThreads / dev::kWave];
+    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const int64_t base = (int64_t)tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t idx = base + i;
+        v[i] = idx < n ? in(idx) : 0u;
+        sum += v[i];
+    }
+    const int w = threadIdx.x / dev::kWave, lane = threadIdx.x % dev::kWave;
+    uint32_t incl = dev::wave_inclusive_sum(sum);
+    if (lane == dev::kWave - 1) s_wsum[w] = incl;
+    __syncthreads();
+    uint32_t wpre = 0, total = 0;
+#pragma unroll
+    for (int j = 0; j < kScanThreads / dev::kWave; ++j) {
+        if (j < w) wpre += s_wsum[j];
+        total += s_wsum[j];
+    }
+    if (w == 0) {
+        uint32_t p = dev::lookback_wave(status, tile, total);
+        if (lane == 0) s_prefix = p;
+    }
+    __syncthreads();
+    uint32_t run = s_prefix + wpre + incl - sum;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t idx = base + i;
+        if (idx < n) out[idx] = run;
+        run += v[i];
+        if (idx == n - 1) out[n] = run;
+    }
+}
+
+agal_status lookback_alloc(agal_context ctx, int64_t tiles, uint64_t **status, uint32_t **ticket, hipStream_t s) {
+    // one buffer: status words then the ticket
+    uint64_t *buf = nullptr;
+    AGAL_TRY(dev_alloc(ctx->mem, &buf, (size_t)tiles + 1, s));
+    fill_u64(buf, 0ull, tiles + 1, s);
+    *status = buf;
+    *ticket = reinterpret_cast<uint32_t *>(buf + tiles);
+    return AGAL_OK;
+}
+
+template <class In>
+static agal_status scan_impl(agal_context ctx, In in, uint32_t *out, int64_t n, hipStream_t s) {
+    if (n <= 0) {
+        fill_u32(out, 0u, 1, s);
+        return AGAL_OK;
+    }
+    int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    uint64_t *status = nullptr;
+    uint32_t *ticket = nullptr;
+    AGAL_TRY(lookback_alloc(ctx, tiles, &status, &ticket, s));
+    {
+        ProfScope prof(ctx, "scan_exclusive", s);
+        hipLaunchKernelGGL(k_scan<In>, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, out, n, status, ticket);
+    }
+    dev_free(ctx->mem, status, s);
+    AGAL_TRY_HIP(hipGetLastError());
+    return AGAL_OK;
+}
+
+agal_status scan_u32(agal_context ctx, const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s) {
+    return scan_impl(ctx, LoadU32{in}, out, n, s);
+}
+agal_status scan_flags_u8(agal_context ctx, const uint8_t *in, uint32_t *out, int64_t n, hipStream_t s) {
+    return scan_impl(ctx, LoadFlagU8{in}, out, n, s);
+}
+
+// ---------------------------------------------------------------------------
+// read-back of a few device words
+// ---------------------------------------------------------------------------
+agal_status read_back_u32(agal_context ctx, const uint32_t *const *srcs, int n, uint32_t *dst, hipStream_t s) {
+    if (n <= 0) return AGAL_OK;
+    if (n > 64) return fail(AGAL_EINVAL, "read_back_u32: too many values");
+    for (int i = 0; i < n; ++i) {
+        AGAL_TRY_HIP(hipMemcpyAsync(ctx->h_counts + i, srcs[i], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    }
+    AGAL_TRY_HIP(hipStreamSynchronize(s));
+    memcpy(dst, ctx->h_counts, (size_t)n * sizeof(uint32_t));
+    return AGAL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// lattices
+// ---------------------------------------------------------------------------
+bool lattice_table(int Q, Lattice *out) {
+    // rest, axes (+/- pairs), edges (+/- pairs), corners (+/- pairs)
+    static const int8_t axes3[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+    static const int8_t edges3[12][3] = {{1, 1, 0},  {-1, -1, 0}, {1, -1, 0},  {-1, 1, 0},
+                                         {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},  {-1, 0, 1},
+                                         {0, 1, 1},  {0, -1, -1}, {0, 1, -1},  {0, -1, 1}};
+    static const int8_t corners3[8][3] = {{1, 1, 1},  {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+                                          {1, -1, 1}, {-1, 1, -1},  {-1, 1, 1}, {1, -1, -1}};
+    static const int8_t d2q9[9][3] = {{0, 0, 0}, {1, 0, 0},   {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+                                      {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+    Lattice L;
+    L.Q = Q;
+    if (Q == AGAL_D2Q9) {
+        L.dim = 2;
+        memcpy(L.c, d2q9, sizeof d2q9);
+    } else if (Q == AGAL_D3Q19 || Q == AGAL_D3Q27) {
+        L.dim = 3;
+        int i = 1;
+        for (auto &v : axes3) memcpy(L.c[i++], v, 3);
+        for (auto &v : edges3) memcpy(L.c[i++], v, 3);
+        if (Q == AGAL_D3Q27)
+            for (auto &v : corners3) memcpy(L.c[i++], v, 3);
+    } else {
+        return false;
+    }
+    *out = L;
+    return true;
+}
+
+}  // namespace agal
+
+// ---------------------------------------------------------------------------
+// C ABI: context, status strings, lattice vectors
+// ---------------------------------------------------------------------------
+extern "C" {
+
+agal_status agal_context_create(const agal_allocator *alloc, agal_context *out) {
+    if (!out) return agal::fail(AGAL_EINVAL, "agal_context_create: out is NULL");
+    if (alloc && (!alloc->alloc || !alloc->free))
+        return agal::fail(AGAL_EINVAL, "agal_context_create: allocator needs alloc and free");
+    int dev = 0;
+    AGAL_TRY_HIP(hipGetDevice(&dev));
+    auto *c = new (std::nothrow) agal_context_t();
+    if (!c) return agal::fail(AGAL_ENOMEM, "agal_context_create: host allocation failed");
+    c->device = dev;
+    if (alloc) {
+        c->mem.user = *alloc;
+        c->mem.has_user = true;
+    } else {
+        // keep freed blocks in the stream-ordered pool instead of returning them to the driver
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t thr = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+        (void)hipGetLastError();
+    }
+    c->h_counts_cap = 64;
+    if (hipHostMalloc((void **)&c->h_counts, c->h_counts_cap * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return agal::fail(AGAL_ENOMEM, "agal_context_create: pinned host allocation failed");
+    }
+    *out = c;
+    return AGAL_OK;
+}
+
+void agal_context_destroy(agal_context ctx) {
+    if (!ctx) return;
+    for (auto &r : ctx->records) {
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+    if (ctx->h_counts) (void)hipHostFree(ctx->h_counts);
+    delete ctx;
+}
+
+agal_status agal_profile_enable(agal_context ctx, int enable) {
+    if (!ctx) return agal::fail(AGAL_EINVAL, "agal_profile_enable: NULL context");
+    ctx->profiling = enable != 0;
+    return AGAL_OK;
+}
+
+agal_status agal_profile_read(agal_context ctx, int max_entries, const char **names, int64_t *launches,
+                              double *total_ms, int *n_entries) {
+    if (!ctx || !n_entries) return agal::fail(AGAL_EINVAL, "agal_profile_read: NULL argument");
+    if (max_entries > 0 && (!names || !launches || !total_ms))
+        return agal::fail(AGAL_EINVAL, "agal_profile_read: NULL output array");
+    int n = 0;
+    for (auto &r : ctx->records) {
+        AGAL_TRY_HIP(hipEventSynchronize(r.stop));
+        float ms = 0.0f;
+        AGAL_TRY_HIP(hipEventElapsedTime(&ms, r.start, r.stop));
+        int k = 0;
+        while (k < n && strcmp(names[k], r.name) != 0) ++k;
+        if (k == n) {
+            if (n == max_entries) continue;
+            names[n] = r.name;
+            launches[n] = 0;
+            total_ms[n] = 0.0;
+            ++n;
+        }
+        launches[k] += 1;
+        total_ms[k] += ms;
+    }
+    for (auto &r : ctx->records) {
+        ctx->event_pool.push_back(r.start);
+        ctx->event_pool.push_back(r.stop);
+    }
+    ctx->records.clear();
+    *n_entries = n;
+    return AGAL_OK;
+}
+
+const char *agal_status_string(agal_status s) {
+    switch (s) {
+        case AGAL_OK: return "AGAL_OK";
+        case AGAL_EINVAL: return "AGAL_EINVAL: invalid argument";
+        case AGAL_ENOMEM: return "AGAL_ENOMEM: out of memory";
+        case AGAL_EHIP: return "AGAL_EHIP: HIP runtime error";
+        case AGAL_ECAPACITY: return "AGAL_ECAPACITY: capacity exceeded";
+        case AGAL_ESTATE: return "AGAL_ESTATE: inconsistent handles or state";
+    }
+    return "unknown agal_status";
+}
+
+const char *agal_last_error(void) { return agal::g_err; }
+
+agal_status agal_lattice_vectors(int lattice, int32_t *c) {
+    agal::Lattice L;
+    if (!agal::lattice_table(lattice, &L)) return agal::fail(AGAL_EINVAL, "unknown lattice %d", lattice);
+    if (!c) return agal::fail(AGAL_EINVAL, "agal_lattice_vectors: c is NULL");
+    for (int i = 0; i < lattice; ++i)
+        for (int a = 0; a < 3; ++a) c[3 * i + a] = L.c[i][a];
+    return AGAL_OK;
+}
+
+}  // extern "C"
