@@ -77,6 +77,7 @@ def lib():
             "orc_link_grad": (None, [P, P, fp, i32p, dp, dp]),
             "orc_link_stable": (None, [P, P, fp, C.c_int64, P, C.c_double, C.c_double, C.c_double,
                                        C.c_double, C.c_double, u8p]),
+            "orc_link_t": (C.c_int, [P, C.c_uint64, C.c_int, C.c_int, fp, C.c_int32, dp]),
             "orc_fd_grad": (None, [P, P, fp, C.c_int64, i32p, C.c_int64, P, dp, C.c_double, i64p,
                                    C.c_int64, dp, i64p]),
         }
@@ -254,6 +255,14 @@ def link_stable(forest, links, coords, bins, h=1e-4, eta_max=0.025, bary_min=0.1
                           bins.h if bins is not None else None, h, eta_max, bary_min, t_lo, gap,
                           _ptr(out, C.c_uint8))
     return out.astype(bool)
+
+
+def link_t(forest: Forest, node_key: int, Q: int, i: int, coords, face: int):
+    """FP64 fraction at which link (node, direction i) meets `face`, or None."""
+    coords = np.ascontiguousarray(coords, dtype=np.float32)
+    t = C.c_double()
+    hit = lib().orc_link_t(forest.h, int(node_key), Q, i, _ptr(coords, C.c_float), int(face), C.byref(t))
+    return t.value if hit else None
 
 
 def fd_grad(forest, links, verts, fidx, bins, w, h=1e-4, vertex_subset=None):

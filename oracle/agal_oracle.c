@@ -1019,3 +1019,16 @@ void orc_fd_grad(const orc_forest *fo, const orc_links *lk, const float *verts, 
     }
     free(V); free(cnt); free(cand.f); free(coords); free(coff); free(all.f); free(stamp); free(vn); free(fill);
 }
+
+/* t of the link (node, direction i) against one given face f, FP64; returns 1
+ * on a hit.  Used to check that a face reported for a link is a hit at the
+ * reported fraction (ties between faces sharing an edge or vertex). */
+int orc_link_t(const orc_forest *fo, uint64_t node_key, int Q, int i, const float *coords, int32_t f, double *t) {
+    int cv[27 * 3];
+    int dim = fo->dim;
+    if (orc_lattice(Q, cv) != dim || i <= 0 || i >= Q) return 0;
+    double o[3], Dv[3] = {0, 0, 0}, lam[3];
+    node_origin(fo, node_key, o);
+    for (int a = 0; a < dim; ++a) Dv[a] = (double)cv[3 * i + a] * (double)fo->dx[fo->L][a];
+    return seg_face(dim, coords, f, o, Dv, t, lam);
+}

@@ -72,7 +72,8 @@ struct agal_context_t {
     agal::Allocator mem;
     int device = 0;
     // small pinned host buffer for count read-backs
-    uint32_t *h_counts = nullptr;
+    uint32_t *h_counts = nullptr;   // mapped pinned host memory
+    uint32_t *d_counts = nullptr;   // its device address
     size_t h_counts_cap = 0;
     // kernel timing (HIP events around each launch) when enabled
     bool profiling = false;

@@ -14,6 +14,26 @@
 #include <cstdint>
 
 namespace agal {
+
+// Lattice directions (Sec. II-C-1 links follow the discrete velocity set).
+// Rest; the axis directions in +/- pairs; the 12 edge directions in +/- pairs;
+// the 8 corner directions in +/- pairs.  D3Q19 is the first 19 rows, D3Q27 all
+// 27; D2Q9 has its own table.  Direction 2k+1 and 2k+2 are opposite.
+constexpr int8_t kDir3[27][3] = {
+    {0, 0, 0},
+    {1, 0, 0},  {-1, 0, 0},  {0, 1, 0},  {0, -1, 0}, {0, 0, 1},   {0, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},   {-1, 0, -1},
+    {1, 0, -1}, {-1, 0, 1},  {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+    {1, 1, 1},  {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, -1},
+    {-1, 1, 1}, {1, -1, -1}};
+constexpr int8_t kDir2[9][3] = {{0, 0, 0}, {1, 0, 0},   {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+                                {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+
+template <int D>
+__host__ __device__ constexpr int8_t dir_c(int i, int a) {
+    return D == 3 ? kDir3[i][a] : kDir2[i][a];
+}
+
 namespace dev {
 
 constexpr int kWave = 64;

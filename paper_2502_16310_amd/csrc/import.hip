@@ -9,31 +9,32 @@
 
 namespace agal {
 
-// bit 0: non-finite coordinate, bit 1: index out of range
-__global__ void k_import_check(const float *verts, int64_t nvc, const int32_t *faces, int64_t nfi, int64_t Nv,
-                               uint32_t *err) {
-    uint32_t bad = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvc; i += (int64_t)gridDim.x * blockDim.x)
-        if (!isfinite(verts[i])) bad |= 1u;
-    if (faces)
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nfi; i += (int64_t)gridDim.x * blockDim.x) {
-            int32_t v = faces[i];
-            if (v < 0 || (int64_t)v >= Nv) bad |= 2u;
-        }
-    if (bad) atomicOr(err, bad);
-}
-
+// Validate and gather in one pass.  err bit 0: a non-finite vertex
+// coordinate; bit 1: a face index outside [0, Nv) (such a face is written as
+// zeros and the call fails).
 template <int D>
-__global__ void k_import_gather(const float *verts, const int32_t *faces, int64_t F, float *coords, float *aabb,
-                                int32_t *fidx) {
-    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < F; f += (int64_t)gridDim.x * blockDim.x) {
+__global__ void k_import(const float *verts, int64_t Nv, const int32_t *faces, int64_t F, float *coords, float *aabb,
+                         int32_t *fidx, uint32_t *err) {
+    uint32_t bad = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = t0; i < Nv * D; i += stride)
+        if (!isfinite(verts[i])) bad |= 1u;
+    for (int64_t f = t0; f < F; f += stride) {
         float v[D][D];
+        bool ok = true;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            int64_t vi = faces ? (int64_t)faces[f * D + k] : f * D + k;
-            fidx[f * D + k] = (int32_t)vi;
+            const int64_t vi = faces ? (int64_t)faces[f * D + k] : f * D + k;
+            ok = ok && vi >= 0 && vi < Nv;
+            fidx[f * D + k] = (vi >= 0 && vi < Nv) ? (int32_t)vi : 0;
+        }
+        if (!ok) bad |= 2u;
 #pragma unroll
-            for (int a = 0; a < D; ++a) v[k][a] = verts[vi * D + a];
+        for (int k = 0; k < D; ++k) {
+            const int64_t vi = faces ? (int64_t)faces[f * D + k] : f * D + k;
+#pragma unroll
+            for (int a = 0; a < D; ++a) v[k][a] = ok ? verts[vi * D + a] : 0.0f;
         }
 #pragma unroll
         for (int k = 0; k < D; ++k)
@@ -51,6 +52,7 @@ __global__ void k_import_gather(const float *verts, const int32_t *faces, int64_
             aabb[(int64_t)(D + a) * F + f] = mx;
         }
     }
+    if (bad) atomicOr(err, bad);
 }
 
 static unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 8192) {
@@ -77,21 +79,6 @@ agal_status agal_import_faces(agal_context ctx, int dim, const float *d_vertices
         return fail(AGAL_EINVAL, "agal_import_faces: a coordinate list needs n_vertices == n_faces * dim");
     hipStream_t s = (hipStream_t)stream;
 
-    // validate on the device before any gather touches the indices
-    uint32_t *err = nullptr;
-    AGAL_TRY(dev_alloc(ctx->mem, &err, 1, s));
-    fill_u32(err, 0u, 1, s);
-    ProfScope prof_check(ctx, "import_check", s);
-    hipLaunchKernelGGL(k_import_check, dim3(grid_for(std::max(n_vertices * dim, n_faces * dim))), dim3(256), 0, s,
-                       d_vertices, n_vertices * dim, d_faces, n_faces * dim, n_vertices, err);
-    uint32_t herr = 0;
-    const uint32_t *srcs[1] = {err};
-    agal_status st = read_back_u32(ctx, srcs, 1, &herr, s);
-    dev_free(ctx->mem, err, s);
-    AGAL_TRY(st);
-    if (herr & 1u) return fail(AGAL_EINVAL, "agal_import_faces: NaN or Inf vertex coordinate");
-    if (herr & 2u) return fail(AGAL_EINVAL, "agal_import_faces: face index outside [0, n_vertices)");
-
     auto *g = new (std::nothrow) agal_geom_t();
     if (!g) return fail(AGAL_ENOMEM, "agal_import_faces: host allocation failed");
     g->ctx = ctx;
@@ -100,24 +87,38 @@ agal_status agal_import_faces(agal_context ctx, int dim, const float *d_vertices
     g->dim = dim;
     g->F = n_faces;
     g->Nv = n_vertices;
-    agal_status a1 = dev_alloc(ctx->mem, &g->coords, (size_t)dim * dim * n_faces, s);
-    agal_status a2 = a1 == AGAL_OK ? dev_alloc(ctx->mem, &g->aabb, (size_t)2 * dim * n_faces, s) : a1;
-    agal_status a3 = a2 == AGAL_OK ? dev_alloc(ctx->mem, &g->fidx, (size_t)dim * n_faces, s) : a2;
-    if (a3 != AGAL_OK) {
+    uint32_t *err = nullptr;
+    agal_status st = dev_alloc(ctx->mem, &g->coords, (size_t)dim * dim * n_faces, s);
+    if (st == AGAL_OK) st = dev_alloc(ctx->mem, &g->aabb, (size_t)2 * dim * n_faces, s);
+    if (st == AGAL_OK) st = dev_alloc(ctx->mem, &g->fidx, (size_t)dim * n_faces, s);
+    if (st == AGAL_OK) st = dev_alloc(ctx->mem, &err, 1, s);
+    if (st != AGAL_OK) {
+        dev_free(ctx->mem, err, s);
         agal_destroy_geom(g);
-        return a3;
+        return st;
     }
-    ProfScope prof_gather(ctx, "import_gather", s);
-    if (dim == 3)
-        hipLaunchKernelGGL(k_import_gather<3>, dim3(grid_for(n_faces)), dim3(256), 0, s, d_vertices, d_faces, n_faces,
-                           g->coords, g->aabb, g->fidx);
-    else
-        hipLaunchKernelGGL(k_import_gather<2>, dim3(grid_for(n_faces)), dim3(256), 0, s, d_vertices, d_faces, n_faces,
-                           g->coords, g->aabb, g->fidx);
+    fill_u32(err, 0u, 1, s);
+    {
+        ProfScope prof(ctx, "import", s);
+        const unsigned grid = grid_for(std::max(n_vertices * dim, n_faces));
+        if (dim == 3)
+            hipLaunchKernelGGL(k_import<3>, dim3(grid), dim3(256), 0, s, d_vertices, n_vertices, d_faces, n_faces,
+                               g->coords, g->aabb, g->fidx, err);
+        else
+            hipLaunchKernelGGL(k_import<2>, dim3(grid), dim3(256), 0, s, d_vertices, n_vertices, d_faces, n_faces,
+                               g->coords, g->aabb, g->fidx, err);
+    }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
+    uint32_t herr = 0;
+    const uint32_t *srcs[1] = {err};
+    st = e != hipSuccess ? fail(AGAL_EHIP, "agal_import_faces: launch failed: %s", hipGetErrorString(e))
+                         : read_back_u32(ctx, srcs, 1, &herr, s);
+    dev_free(ctx->mem, err, s);
+    if (st == AGAL_OK && (herr & 1u)) st = fail(AGAL_EINVAL, "agal_import_faces: NaN or Inf vertex coordinate");
+    if (st == AGAL_OK && (herr & 2u)) st = fail(AGAL_EINVAL, "agal_import_faces: face index outside [0, n_vertices)");
+    if (st != AGAL_OK) {
         agal_destroy_geom(g);
-        return fail(AGAL_EHIP, "agal_import_faces: launch failed: %s", hipGetErrorString(e));
+        return st;
     }
     *out = g;
     return AGAL_OK;

@@ -23,7 +23,7 @@
 namespace agal {
 namespace {
 
-constexpr int kFlagCap = 256;  // staged candidate faces per wave
+constexpr int kFlagCap = 128;  // staged candidate faces per wave
 
 template <int D>
 struct FlagArgs {
@@ -45,7 +45,8 @@ template <int D>
 __global__ __launch_bounds__(64) void k_flag(FlagArgs<D> A) {
     constexpr int CELLS = D == 3 ? 64 : 16;
     constexpr int BPW = 64 / CELLS;
-    __shared__ float s_f[D * D][kFlagCap];
+    constexpr int NF = D * D + 2 * D;   // coordinates, then the bounding box
+    __shared__ float s_f[NF][kFlagCap];
     const int lane = threadIdx.x;
     const int64_t first = (int64_t)blockIdx.x * BPW;
     const int64_t blk = first + lane / CELLS;
@@ -64,17 +65,36 @@ __global__ __launch_bounds__(64) void k_flag(FlagArgs<D> A) {
     const int64_t F = A.faces.F;
 
     int count = 0;  // staged faces (wave-uniform)
+    // Batches of 64 staged faces: each lane marks the faces its cube's box axes do
+    // not separate from it -- the separating-axis test's own three box-axis tests,
+    // since min_k fl(v_k - m) = fl(min_k v_k - m) -- then runs the full test on
+    // those faces only, until flagged.
     auto test_staged = [&](int n) {
         __syncthreads();
-        for (int j = 0; j < n; ++j) {
-            if (!flagged) {
+        for (int j0 = 0; j0 < n; j0 += 64) {
+            if (__ballot(!flagged) == 0) break;
+            const int jn = min(64, n - j0);
+            uint64_t nm = 0;
+            if (!flagged)
+                for (int jj = 0; jj < jn; ++jj) {
+                    bool near = true;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        const float lo_a = s_f[D * D + a][j0 + jj] - m[a];
+                        const float hi_a = s_f[D * D + D + a][j0 + jj] - m[a];
+                        near = near && !(lo_a > h) && !(hi_a < -h);
+                    }
+                    nm |= near ? (1ull << jj) : 0ull;
+                }
+            while (nm && !flagged) {
+                const int j = j0 + __builtin_ctzll(nm);
+                nm &= nm - 1ull;
                 float v[D * D];
 #pragma unroll
                 for (int k = 0; k < D * D; ++k) v[k] = s_f[k][j];
-                if (D == 3) flagged = dev::sat_triangle(v, m, h);
+                if constexpr (D == 3) flagged = dev::sat_triangle(v, m, h);
                 else flagged = dev::sat_segment(v, m, h);
             }
-            if ((j & 7) == 7 && __ballot(!flagged) == 0) break;
         }
         __syncthreads();
     };
@@ -131,6 +151,8 @@ __global__ __launch_bounds__(64) void k_flag(FlagArgs<D> A) {
                             const int pos = count + dev::lanes_below(mask);
 #pragma unroll
                             for (int k = 0; k < D * D; ++k) s_f[k][pos] = A.faces.coords[(int64_t)k * F + f];
+#pragma unroll
+                            for (int k = 0; k < 2 * D; ++k) s_f[D * D + k][pos] = A.faces.aabb[(int64_t)k * F + f];
                         }
                         count += nk;
                     }
@@ -150,31 +172,33 @@ __global__ __launch_bounds__(64) void k_flag(FlagArgs<D> A) {
 
 // 2:1 balance: a block of level m marked in this pass needs every neighbour
 // position (faces, edges, corners) inside the domain to exist at level m;
-// where it does not, the covering level-(m-1) leaf is marked.
+// where it does not, the covering level-(m-1) leaf is marked.  One thread per
+// (block, neighbour position), so each thread does two binary searches.
 template <int D>
 __global__ void k_ripple(const uint32_t *keys_m, int64_t n_m, const uint8_t *pm_m, int m, const uint32_t *keys_p,
                          int64_t n_p, const uint8_t *leaf_p, uint8_t *pm_p, int R0, int R1, int R2, uint32_t *err) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_m; i += (int64_t)gridDim.x * blockDim.x) {
+    constexpr int NNB = D == 3 ? 26 : 8;
+    const int64_t total = n_m * NNB;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / NNB;
         if (!pm_m[i]) continue;
+        int k = (int)(t % NNB);
+        k += k >= NNB / 2 ? 1 : 0;   // skip the centre of the 3^D stencil
+        const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = D == 3 ? k / 9 - 1 : 0;
         int c[3];
         dev::decode_key<D>(keys_m[i], m, R0, R1, c);
         const int ext[3] = {R0 << m, R1 << m, R2 << m};
-        for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    if (!dx && !dy && !dz) continue;
-                    int nc[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
-                    if (nc[0] < 0 || nc[0] >= ext[0] || nc[1] < 0 || nc[1] >= ext[1]) continue;
-                    if (D == 3 && (nc[2] < 0 || nc[2] >= ext[2])) continue;
-                    const uint32_t kn = dev::encode_key<D>(nc, m, R0, R1);
-                    const int64_t jn = dev::lower_bound_u32(keys_m, n_m, kn);
-                    if (jn < n_m && keys_m[jn] == kn) continue;
-                    int pc[3] = {nc[0] >> 1, nc[1] >> 1, D == 3 ? nc[2] >> 1 : 0};
-                    const uint32_t kp = dev::encode_key<D>(pc, m - 1, R0, R1);
-                    const int64_t jp = dev::lower_bound_u32(keys_p, n_p, kp);
-                    if (jp < n_p && keys_p[jp] == kp && leaf_p[jp]) pm_p[jp] = 2;
-                    else atomicOr(err, 1u);
-                }
+        int nc[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+        if (nc[0] < 0 || nc[0] >= ext[0] || nc[1] < 0 || nc[1] >= ext[1]) continue;
+        if (D == 3 && (nc[2] < 0 || nc[2] >= ext[2])) continue;
+        const uint32_t kn = dev::encode_key<D>(nc, m, R0, R1);
+        const int64_t jn = dev::lower_bound_u32(keys_m, n_m, kn);
+        if (jn < n_m && keys_m[jn] == kn) continue;
+        int pc[3] = {nc[0] >> 1, nc[1] >> 1, D == 3 ? nc[2] >> 1 : 0};
+        const uint32_t kp = dev::encode_key<D>(pc, m - 1, R0, R1);
+        const int64_t jp = dev::lower_bound_u32(keys_p, n_p, kp);
+        if (jp < n_p && keys_p[jp] == kp && leaf_p[jp]) pm_p[jp] = 2;
+        else atomicOr(err, 1u);
     }
 }
 
@@ -320,7 +344,8 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
         for (int m = l; m >= 1; --m) {
             if (fo->lev[m].n == 0) continue;
             ProfScope prof(ctx, "balance_ripple", s);
-            hipLaunchKernelGGL(k_ripple<D>, dim3(grid_for(fo->lev[m].n)), dim3(256), 0, s, fo->lev[m].keys,
+            hipLaunchKernelGGL(k_ripple<D>, dim3(grid_for(fo->lev[m].n * (D == 3 ? 26 : 8))), dim3(256), 0, s,
+                               fo->lev[m].keys,
                                fo->lev[m].n, pm[m], m, fo->lev[m - 1].keys, fo->lev[m - 1].n, fo->lev[m - 1].leaf,
                                pm[m - 1], fo->roots[0], fo->roots[1], fo->roots[2], err);
         }

@@ -200,14 +200,32 @@ agal_status scan_flags_u8(agal_context ctx, const uint8_t *in, uint32_t *out, in
 // ---------------------------------------------------------------------------
 // read-back of a few device words
 // ---------------------------------------------------------------------------
+// A one-wave kernel copies the words into mapped pinned host memory; this
+// avoids a DMA transfer per value, whose setup latency dominates such tiny
+// copies.
+constexpr int kReadBackMax = 16;
+struct ReadBackArgs {
+    const uint32_t *src[kReadBackMax];
+    int n;
+    uint32_t *dst;
+};
+
+__global__ void k_read_back(ReadBackArgs a) {
+    const int i = threadIdx.x;
+    if (i < a.n) a.dst[i] = *a.src[i];
+}
+
 agal_status read_back_u32(agal_context ctx, const uint32_t *const *srcs, int n, uint32_t *dst, hipStream_t s) {
     if (n <= 0) return AGAL_OK;
-    if (n > 64) return fail(AGAL_EINVAL, "read_back_u32: too many values");
-    for (int i = 0; i < n; ++i) {
-        AGAL_TRY_HIP(hipMemcpyAsync(ctx->h_counts + i, srcs[i], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    }
+    if (n > kReadBackMax) return fail(AGAL_EINVAL, "read_back_u32: at most %d values", kReadBackMax);
+    ReadBackArgs a{};
+    for (int i = 0; i < n; ++i) a.src[i] = srcs[i];
+    a.n = n;
+    a.dst = ctx->d_counts;
+    hipLaunchKernelGGL(k_read_back, dim3(1), dim3(64), 0, s, a);
+    AGAL_TRY_HIP(hipGetLastError());
     AGAL_TRY_HIP(hipStreamSynchronize(s));
-    memcpy(dst, ctx->h_counts, (size_t)n * sizeof(uint32_t));
+    memcpy(dst, (const void *)ctx->h_counts, (size_t)n * sizeof(uint32_t));
     return AGAL_OK;
 }
 
@@ -215,30 +233,13 @@ agal_status read_back_u32(agal_context ctx, const uint32_t *const *srcs, int n, 
 // lattices
 // ---------------------------------------------------------------------------
 bool lattice_table(int Q, Lattice *out) {
-    // rest, axes (+/- pairs), edges (+/- pairs), corners (+/- pairs)
-    static const int8_t axes3[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
-    static const int8_t edges3[12][3] = {{1, 1, 0},  {-1, -1, 0}, {1, -1, 0},  {-1, 1, 0},
-                                         {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},  {-1, 0, 1},
-                                         {0, 1, 1},  {0, -1, -1}, {0, 1, -1},  {0, -1, 1}};
-    static const int8_t corners3[8][3] = {{1, 1, 1},  {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
-                                          {1, -1, 1}, {-1, 1, -1},  {-1, 1, 1}, {1, -1, -1}};
-    static const int8_t d2q9[9][3] = {{0, 0, 0}, {1, 0, 0},   {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
-                                      {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
     Lattice L;
     L.Q = Q;
-    if (Q == AGAL_D2Q9) {
-        L.dim = 2;
-        memcpy(L.c, d2q9, sizeof d2q9);
-    } else if (Q == AGAL_D3Q19 || Q == AGAL_D3Q27) {
-        L.dim = 3;
-        int i = 1;
-        for (auto &v : axes3) memcpy(L.c[i++], v, 3);
-        for (auto &v : edges3) memcpy(L.c[i++], v, 3);
-        if (Q == AGAL_D3Q27)
-            for (auto &v : corners3) memcpy(L.c[i++], v, 3);
-    } else {
-        return false;
-    }
+    if (Q == AGAL_D2Q9) L.dim = 2;
+    else if (Q == AGAL_D3Q19 || Q == AGAL_D3Q27) L.dim = 3;
+    else return false;
+    for (int i = 0; i < Q; ++i)
+        for (int a = 0; a < 3; ++a) L.c[i][a] = L.dim == 3 ? kDir3[i][a] : kDir2[i][a];
     *out = L;
     return true;
 }
@@ -272,9 +273,13 @@ agal_status agal_context_create(const agal_allocator *alloc, agal_context *out) 
         (void)hipGetLastError();
     }
     c->h_counts_cap = 64;
-    if (hipHostMalloc((void **)&c->h_counts, c->h_counts_cap * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&c->h_counts, c->h_counts_cap * sizeof(uint32_t),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->d_counts, c->h_counts, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->h_counts) (void)hipHostFree(c->h_counts);
         delete c;
-        return agal::fail(AGAL_ENOMEM, "agal_context_create: pinned host allocation failed");
+        return agal::fail(AGAL_ENOMEM, "agal_context_create: mapped pinned host allocation failed");
     }
     *out = c;
     return AGAL_OK;

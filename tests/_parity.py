@@ -74,6 +74,19 @@ class LinkReport:
     face_diff: int
 
 
+def check_face_ties(orc, forest, coords, Q, GQ, GF, OQ, OF, allk, tol=2.4e-7):
+    """Where both sides link but name different faces, the GPU's face must also be hit
+    (FP64) at the oracle's fraction to within two FP32 steps: ties between faces sharing an edge
+    or vertex are broken on the FP32-rounded fraction, then by the lower face id."""
+    bad = 0
+    rows, cols = np.nonzero((GF >= 0) & (OF >= 0) & (GF != OF))
+    for r, c in zip(rows, cols):
+        t = orc.link_t(forest, int(allk[r]), Q, int(c), coords, int(GF[r, c]))
+        if t is None or abs(t - OQ[r, c]) > tol:
+            bad += 1
+    return len(rows), bad
+
+
 def compare_links(g, lk, restrict_blocks=None, cells=64):
     """Join GPU and oracle nodes by key; q within Q_TOL where both sides have a link;
     a link on one side only must sit within END_TOL of a segment end (else counted)."""
@@ -99,4 +112,4 @@ def compare_links(g, lk, restrict_blocks=None, cells=64):
     qq = np.where(GF >= 0, GQ, OQ)[one]
     at_end = (qq <= END_TOL) | (qq >= 1 - END_TOL)
     return LinkReport(len(gk), len(ok_), int(both.sum()), max_err, int(one.sum()), int((~at_end).sum()),
-                      int((GF != OF)[both].sum())), (GQ, GF, OQ, OF)
+                      int((GF != OF)[both].sum())), (GQ, GF, OQ, OF, allk)

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import geomgen
-from _parity import END_TOL, Q_TOL, compare_bins, compare_forest, compare_links, gpu_run, log
+from _parity import END_TOL, Q_TOL, check_face_ties, compare_bins, compare_forest, compare_links, gpu_run, log
 
 pytestmark = pytest.mark.gpu
 
@@ -34,8 +34,11 @@ def _full(orc, wl, B=None, allow_one_sided=0):
     of = orc.refine(wl.dim, coords, ob, wl.roots[:wl.dim], wl.levels, wl.d_spec(), wl.lo[:wl.dim], wl.hi[:wl.dim])
     compare_forest(g, of, wl.levels)
     lk = orc.link_fractions(wl.dim, coords, ob, of, wl.lattice)
-    rep, _ = compare_links(g, lk, cells=4 ** wl.dim)
+    rep, arrs = compare_links(g, lk, cells=4 ** wl.dim)
     _check_links(rep, allow_one_sided)
+    nd, bad = check_face_ties(orc, of, coords, wl.lattice, *arrs)
+    log(f"  face ids differing at ties: {nd}, not a tie: {bad}")
+    assert bad == 0
     return g, of, lk
 
 
@@ -111,8 +114,11 @@ def test_sphere_c1_bins_flags_exact_and_sampled_q(orc):
     rng = np.random.default_rng(7)
     sub = np.sort(rng.choice(nL, size=min(nL, 2500), replace=False))
     lk = orc.link_fractions(3, coords, ob, of, wl.lattice, subset=sub)
-    rep, _ = compare_links(g, lk, restrict_blocks=of.levels[wl.levels]["keys"][sub])
+    rep, arrs = compare_links(g, lk, restrict_blocks=of.levels[wl.levels]["keys"][sub])
     _check_links(rep)
+    nd, bad = check_face_ties(orc, of, coords, wl.lattice, *arrs)
+    log(f"  face ids differing at ties: {nd}, not a tie: {bad}")
+    assert bad == 0
 
 
 def test_run_twice_bitwise_equal(orc):
