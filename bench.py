@@ -250,10 +250,11 @@ def main():
     kern = {k: {"launches_per_step": n / args.steps, "ms_per_step": t / args.steps, "avg_us": 1e3 * t / n}
             for k, (n, t) in prof.items()}
     pass_kernels = ("bin_count", "bin_scatter", "bin_canon", "bin_canon_big", "scan_exclusive", "flag_sat",
-                    "balance_ripple", "child_gen", "q_links")
+                    "balance_ripple", "child_gen", "q_links", "q_compact")
     pass_ms = sum(kern[k]["ms_per_step"] for k in pass_kernels if k in kern)
     grad_ms = kern.get("q_adjoint", {}).get("ms_per_step", 0.0)
     dominant = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    hbm_pass = pass_hbm_bytes(dim, Q, len(wl.faces), nb, P, n_blocks, n_nodes, wl.levels)
 
     # roofline of the dominant kernel
     F = len(wl.faces)
@@ -268,6 +269,8 @@ def main():
                    "levels": wl.levels, "bins": wl.bins, "lattice": f"D{dim}Q{Q}", "global_batch": 1,
                    "seq_len": 0, "parallelism": "none"},
         "near_wall_pass_ms": pass_ms, "grad_ms": grad_ms,
+        "near_wall_pass_hbm": {"algorithmic_bytes": hbm_pass, "GBps": hbm_pass / (pass_ms * 1e-3) / 1e9,
+                               "frac_of_peak": hbm_pass / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "cell_face_tests": {"flag_per_pass": t_flag, "q": t_q, "total": T},
         "forest_blocks_per_level": n_blocks, "boundary_nodes": n_nodes, "links": n_links,
         "kernels": kern, "roofline": roof,
@@ -293,21 +296,35 @@ def describe(wl):
     return wl.name
 
 
+CULL_OPS = 12   # FP32 ops of one bounding-box rejection: 6 subtractions, 6 comparisons
+
+
 def roofline(name, k, dim, Q, F, nb, P, n_blocks, n_nodes, t_flag, t_q, L):
-    """Algorithmic bytes (compulsory HBM traffic) per launch of kernel `name`."""
+    """Roofline entry of kernel `name` from its average launch time.
+
+    flag_sat / q_links are arithmetic kernels: algorithmic work = the (cell,
+    candidate face) pairs the bins present (t_flag per pass / t_q) times the
+    CULL_OPS every candidate costs at least, against the FP32 VALU peak without
+    packed math or FMA (256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T op/s).
+    Streaming kernels are charged their compulsory HBM bytes."""
     us = k["avg_us"]
     launches = k["launches_per_step"]
     cells = 4 ** dim
     face_bytes = F * (4 * dim * dim + 8 * dim)           # SoA coordinates + bounding boxes
     csr_bytes = 4 * (nb + 1) + 4 * P
-    if name == "q_links":
-        nL = n_blocks[L]
-        byts = 4 * nL + face_bytes + csr_bytes + n_nodes * (8 + 8 * Q)
-    elif name == "flag_sat":
-        tested = sum(n_blocks[:L])
-        byts = (4 * tested + (cells + 1) * tested + L * (face_bytes + csr_bytes)) / max(1, launches)
-    elif name == "q_adjoint":
-        byts = n_nodes * (8 + 8 * Q) + face_bytes + 4 * F * dim + 8 * dim * 4 * F
+    if name in ("flag_sat", "q_links"):
+        pairs = (sum(t_flag) / max(1, launches)) if name == "flag_sat" else t_q
+        ops = CULL_OPS * pairs
+        tops = ops / (us * 1e-6) / 1e12
+        return {"bound": "alu", "achieved": tops, "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
+                "frac": tops / VALU_PEAK_TOPS, "traffic": None, "kernel": name, "ops_per_launch": ops,
+                "cell_face_pairs_per_launch": pairs, "avg_launch_us": us}
+    if name == "q_adjoint":
+        byts = n_nodes * (8 + 8 * Q) + face_bytes + 4 * F * dim + 4 * dim * 4 * F
+    elif name == "q_compact":
+        byts = 2 * n_nodes * (8 + 8 * Q)
+    elif name == "bin_canon":
+        byts = 2 * 4 * P + 4 * (nb + 1)
     else:
         byts = None
     if byts is None:
@@ -316,6 +333,17 @@ def roofline(name, k, dim, Q, F, nb, P, n_blocks, n_nodes, t_flag, t_q, L):
     gbs = byts / (us * 1e-6) / 1e9
     return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
             "traffic": None, "kernel": name, "bytes_per_launch": byts, "avg_launch_us": us}
+
+
+def pass_hbm_bytes(dim, Q, F, nb, P, n_blocks, n_nodes, L):
+    """Compulsory HBM bytes of one near-wall pass (bins + all levels + q write-back)."""
+    cells = 4 ** dim
+    face_bytes = F * (4 * dim * dim + 8 * dim)
+    bins = face_bytes + 8 * (nb + 1) + 8 * P
+    flags = sum(n_blocks[:L]) * (4 + cells + 1) + L * (face_bytes + 4 * (nb + 1) + 4 * P)
+    refine = sum(n_blocks) * 8
+    q = 4 * n_blocks[L] + face_bytes + 4 * (nb + 1) + 4 * P + n_nodes * (8 + 8 * Q)
+    return bins + flags + refine + q
 
 
 if __name__ == "__main__":

@@ -11,149 +11,39 @@
 
 #include "agal_internal.hpp"
 #include "device.hpp"
+#include "kernels.hpp"
 
 namespace agal {
 
 namespace {
 
-constexpr int kCanonCap = 2048;      // ids per LDS segment in the rank sort
-constexpr int kBigThreads = 1024;
+using namespace kern;
 
-template <int D>
-__device__ __forceinline__ void face_bin_range(const float *aabb, int64_t F, int64_t f, const dev::BinGrid &g,
-                                               int lo[3], int hi[3]) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) { lo[a] = 0; hi[a] = 0; }
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        lo[a] = dev::bin_of(aabb[(int64_t)a * F + f], g.lo[a], g.s[a], g.B);
-        hi[a] = dev::bin_of(aabb[(int64_t)(D + a) * F + f], g.lo[a], g.s[a], g.B);
-    }
-}
+#define AGAL_GRID_STRIDE(i, n) \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
 template <int D>
 __global__ void k_bin_count(const float *aabb, int64_t F, dev::BinGrid g, uint32_t *count) {
-    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < F; f += (int64_t)gridDim.x * blockDim.x) {
-        int lo[3], hi[3];
-        face_bin_range<D>(aabb, F, f, g, lo, hi);
-        for (int z = lo[2]; z <= hi[2]; ++z)
-            for (int y = lo[1]; y <= hi[1]; ++y)
-                for (int x = lo[0]; x <= hi[0]; ++x)
-                    atomicAdd(&count[((int64_t)z * g.B + y) * g.B + x], 1u);
-    }
+    AGAL_GRID_STRIDE(f, F) bin_count_item<D>(aabb, F, g, count, f);
 }
 
 template <int D>
 __global__ void k_bin_scatter(const float *aabb, int64_t F, dev::BinGrid g, const uint32_t *off, uint32_t *cursor,
                               int32_t *ids) {
-    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < F; f += (int64_t)gridDim.x * blockDim.x) {
-        int lo[3], hi[3];
-        face_bin_range<D>(aabb, F, f, g, lo, hi);
-        for (int z = lo[2]; z <= hi[2]; ++z)
-            for (int y = lo[1]; y <= hi[1]; ++y)
-                for (int x = lo[0]; x <= hi[0]; ++x) {
-                    int64_t b = ((int64_t)z * g.B + y) * g.B + x;
-                    uint32_t pos = off[b] + atomicAdd(&cursor[b], 1u);
-                    ids[pos] = (int32_t)f;
-                }
-    }
+    AGAL_GRID_STRIDE(f, F) bin_scatter_item<D>(aabb, F, g, off, cursor, ids, f);
 }
 
-// Sort ids[s0, s1) (bins b_first..b_last whose offsets are in s_off) by rank:
-// each entry's position inside its bin is the number of smaller ids there.
-__device__ void rank_sort_segment(int32_t *ids, const uint32_t *s_off, int nbins, uint32_t s0, uint32_t s1,
-                                  int32_t *s_val) {
-    const int lane = threadIdx.x;
-    const int n = (int)(s1 - s0);
-    for (int e = lane; e < n; e += dev::kWave) s_val[e] = ids[s0 + e];
-    __syncthreads();
-    for (int e = lane; e < n; e += dev::kWave) {
-        uint32_t pos = s0 + (uint32_t)e;
-        // bin of entry e: last bin whose start <= pos
-        int lo = 0, hi = nbins - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= pos) lo = mid; else hi = mid - 1;
-        }
-        // the last bin starting at or before pos is the non-empty one holding it
-        int b = lo;
-        const int bs = (int)(s_off[b] - s0), be = (int)(s_off[b + 1] - s0);
-        const int32_t v = s_val[e];
-        int rank = 0;
-        for (int j = bs; j < be; ++j) rank += s_val[j] < v ? 1 : 0;
-        ids[s0 + bs + rank] = v;
-    }
-    __syncthreads();
-}
-
-// One wave per group of 64 consecutive bins.
 __global__ __launch_bounds__(64) void k_bin_canon_small(int32_t *ids, const uint32_t *off, int64_t nb,
                                                         uint32_t *big_list, uint32_t *big_count) {
-    __shared__ uint32_t s_off[dev::kWave + 1];
-    __shared__ int32_t s_val[kCanonCap];
-    const int64_t b0 = (int64_t)blockIdx.x * dev::kWave;
-    const int nbins = (int)std::min<int64_t>(dev::kWave, nb - b0);
-    const int lane = threadIdx.x;
-    for (int i = lane; i <= nbins; i += dev::kWave) s_off[i] = off[b0 + i];
-    __syncthreads();
-    const uint32_t g0 = s_off[0], g1 = s_off[nbins];
-    if (g1 - g0 <= 1) return;
-    if (g1 - g0 <= (uint32_t)kCanonCap) {
-        rank_sort_segment(ids, s_off, nbins, g0, g1, s_val);
-        return;
-    }
-    // group too large: bin by bin
-    for (int b = 0; b < nbins; ++b) {
-        const uint32_t a0 = s_off[b], a1 = s_off[b + 1];
-        if (a1 - a0 <= 1) continue;
-        if (a1 - a0 <= (uint32_t)kCanonCap) {
-            __shared__ uint32_t s_one[2];
-            if (lane == 0) { s_one[0] = a0; s_one[1] = a1; }
-            __syncthreads();
-            rank_sort_segment(ids, s_one, 1, a0, a1, s_val);
-        } else if (lane == 0) {
-            uint32_t k = atomicAdd(big_count, 1u);
-            big_list[k] = (uint32_t)(b0 + b);
-        }
-    }
+    bin_canon_group(ids, off, nb, (int64_t)blockIdx.x * dev::kWave, big_list, big_count, 0u);
 }
 
-// Bins with more than kCanonCap ids: rewrite the segment by an ordered sweep
-// over all faces (membership recomputed from the bounding boxes).
 template <int D>
 __global__ __launch_bounds__(kBigThreads) void k_bin_canon_big(const float *aabb, int64_t F, dev::BinGrid g,
                                                                const uint32_t *off, int32_t *ids,
                                                                const uint32_t *big_list, const uint32_t *big_count) {
-    __shared__ uint32_t s_wsum[kBigThreads / dev::kWave];
     const uint32_t nbig = *big_count;
-    const int w = threadIdx.x / dev::kWave, lane = threadIdx.x % dev::kWave;
-    for (uint32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
-        const int64_t b = big_list[bi];
-        const int bx = (int)(b % g.B);
-        const int by = (int)((b / g.B) % g.B);
-        const int bz = D == 3 ? (int)(b / ((int64_t)g.B * g.B)) : 0;
-        uint32_t run = off[b];
-        for (int64_t f0 = 0; f0 < F; f0 += kBigThreads) {
-            const int64_t f = f0 + threadIdx.x;
-            uint32_t mem = 0;
-            if (f < F) {
-                int lo[3], hi[3];
-                face_bin_range<D>(aabb, F, f, g, lo, hi);
-                mem = (bx >= lo[0] && bx <= hi[0] && by >= lo[1] && by <= hi[1] && bz >= lo[2] && bz <= hi[2]) ? 1u : 0u;
-            }
-            uint32_t incl = dev::wave_inclusive_sum(mem);
-            if (lane == dev::kWave - 1) s_wsum[w] = incl;
-            __syncthreads();
-            uint32_t pre = 0, tot = 0;
-            for (int j = 0; j < kBigThreads / dev::kWave; ++j) {
-                if (j < w) pre += s_wsum[j];
-                tot += s_wsum[j];
-            }
-            if (mem) ids[run + pre + incl - 1] = (int32_t)f;
-            run += tot;
-            __syncthreads();
-        }
-    }
+    for (uint32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) bin_canon_big_bin<D>(aabb, F, g, off, ids, big_list[bi]);
 }
 
 unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 8192) {

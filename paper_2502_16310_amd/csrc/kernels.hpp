@@ -1,0 +1,954 @@
+// Per-item device code of every kernel of the path: one wave's blocks for the
+// flag and link kernels, one thread's item for the balance and merge steps,
+// one workgroup's node tile for the adjoint, one face / bin group for the
+// binning.  The single-body kernels (refine.hip, links.hip, bins.hip) and the
+// batched persistent kernels (batch.hip) are thin loops around these, so both
+// forms compute bit-identical flags and link fractions.
+#pragma once
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device.hpp"
+
+namespace agal {
+namespace kern {
+
+// ===========================================================================
+// Spatial binning (paper Sec. II-C-3)
+// ===========================================================================
+constexpr int kCanonCap = 2048;      // ids per LDS segment in the rank sort
+constexpr int kBigThreads = 1024;
+
+template <int D>
+__device__ __forceinline__ void face_bin_range(const float *aabb, int64_t F, int64_t f, const dev::BinGrid &g,
+                                               int lo[3], int hi[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { lo[a] = 0; hi[a] = 0; }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        lo[a] = dev::bin_of(aabb[(int64_t)a * F + f], g.lo[a], g.s[a], g.B);
+        hi[a] = dev::bin_of(aabb[(int64_t)(D + a) * F + f], g.lo[a], g.s[a], g.B);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void bin_count_item(const float *aabb, int64_t F, const dev::BinGrid &g, uint32_t *count,
+                                               int64_t f) {
+    {
+        int lo[3], hi[3];
+        face_bin_range<D>(aabb, F, f, g, lo, hi);
+        for (int z = lo[2]; z <= hi[2]; ++z)
+            for (int y = lo[1]; y <= hi[1]; ++y)
+                for (int x = lo[0]; x <= hi[0]; ++x)
+                    atomicAdd(&count[((int64_t)z * g.B + y) * g.B + x], 1u);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void bin_scatter_item(const float *aabb, int64_t F, const dev::BinGrid &g,
+                                                 const uint32_t *off, uint32_t *cursor, int32_t *ids, int64_t f) {
+    {
+        int lo[3], hi[3];
+        face_bin_range<D>(aabb, F, f, g, lo, hi);
+        for (int z = lo[2]; z <= hi[2]; ++z)
+            for (int y = lo[1]; y <= hi[1]; ++y)
+                for (int x = lo[0]; x <= hi[0]; ++x) {
+                    int64_t b = ((int64_t)z * g.B + y) * g.B + x;
+                    uint32_t pos = off[b] + atomicAdd(&cursor[b], 1u);
+                    ids[pos] = (int32_t)f;
+                }
+    }
+}
+
+// Sort ids[s0, s1) (bins b_first..b_last whose offsets are in s_off) by rank:
+// each entry's position inside its bin is the number of smaller ids there.
+__device__ void rank_sort_segment(int32_t *ids, const uint32_t *s_off, int nbins, uint32_t s0, uint32_t s1,
+                                  int32_t *s_val) {
+    const int lane = threadIdx.x;
+    const int n = (int)(s1 - s0);
+    for (int e = lane; e < n; e += dev::kWave) s_val[e] = ids[s0 + e];
+    __syncthreads();
+    for (int e = lane; e < n; e += dev::kWave) {
+        uint32_t pos = s0 + (uint32_t)e;
+        // bin of entry e: last bin whose start <= pos
+        int lo = 0, hi = nbins - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= pos) lo = mid; else hi = mid - 1;
+        }
+        // the last bin starting at or before pos is the non-empty one holding it
+        int b = lo;
+        const int bs = (int)(s_off[b] - s0), be = (int)(s_off[b + 1] - s0);
+        const int32_t v = s_val[e];
+        int rank = 0;
+        for (int j = bs; j < be; ++j) rank += s_val[j] < v ? 1 : 0;
+        ids[s0 + bs + rank] = v;
+    }
+    __syncthreads();
+}
+
+// One wave: the group of 64 consecutive bins starting at b0.  Oversized bins
+// are appended to big_list as big_tag + bin.
+__device__ __forceinline__ void bin_canon_group(int32_t *ids, const uint32_t *off, int64_t nb, int64_t b0,
+                                                uint32_t *big_list, uint32_t *big_count, uint32_t big_tag) {
+    __shared__ uint32_t s_off[dev::kWave + 1];
+    __shared__ int32_t s_val[kCanonCap];
+    const int nbins = (int)std::min<int64_t>(dev::kWave, nb - b0);
+    const int lane = threadIdx.x;
+    for (int i = lane; i <= nbins; i += dev::kWave) s_off[i] = off[b0 + i];
+    __syncthreads();
+    const uint32_t g0 = s_off[0], g1 = s_off[nbins];
+    if (g1 - g0 <= 1) {
+        __syncthreads();
+        return;
+    }
+    if (g1 - g0 <= (uint32_t)kCanonCap) {
+        rank_sort_segment(ids, s_off, nbins, g0, g1, s_val);
+        return;
+    }
+    // group too large: bin by bin
+    for (int b = 0; b < nbins; ++b) {
+        const uint32_t a0 = s_off[b], a1 = s_off[b + 1];
+        if (a1 - a0 <= 1) continue;
+        if (a1 - a0 <= (uint32_t)kCanonCap) {
+            __shared__ uint32_t s_one[2];
+            if (lane == 0) { s_one[0] = a0; s_one[1] = a1; }
+            __syncthreads();
+            rank_sort_segment(ids, s_one, 1, a0, a1, s_val);
+        } else if (lane == 0) {
+            uint32_t k = atomicAdd(big_count, 1u);
+            big_list[k] = big_tag + (uint32_t)(b0 + b);
+        }
+    }
+    __syncthreads();
+}
+
+// Bins with more than kCanonCap ids: rewrite the segment by an ordered sweep
+// over all faces (membership recomputed from the bounding boxes).
+// One workgroup of kBigThreads threads rebuilds bin b's segment.
+template <int D>
+__device__ __forceinline__ void bin_canon_big_bin(const float *aabb, int64_t F, const dev::BinGrid &g,
+                                                  const uint32_t *off, int32_t *ids, int64_t b) {
+    __shared__ uint32_t s_wsum[kBigThreads / dev::kWave];
+    const int w = threadIdx.x / dev::kWave, lane = threadIdx.x % dev::kWave;
+    {
+        const int bx = (int)(b % g.B);
+        const int by = (int)((b / g.B) % g.B);
+        const int bz = D == 3 ? (int)(b / ((int64_t)g.B * g.B)) : 0;
+        uint32_t run = off[b];
+        for (int64_t f0 = 0; f0 < F; f0 += kBigThreads) {
+            const int64_t f = f0 + threadIdx.x;
+            uint32_t mem = 0;
+            if (f < F) {
+                int lo[3], hi[3];
+                face_bin_range<D>(aabb, F, f, g, lo, hi);
+                mem = (bx >= lo[0] && bx <= hi[0] && by >= lo[1] && by <= hi[1] && bz >= lo[2] && bz <= hi[2]) ? 1u : 0u;
+            }
+            uint32_t incl = dev::wave_inclusive_sum(mem);
+            if (lane == dev::kWave - 1) s_wsum[w] = incl;
+            __syncthreads();
+            uint32_t pre = 0, tot = 0;
+            for (int j = 0; j < kBigThreads / dev::kWave; ++j) {
+                if (j < w) pre += s_wsum[j];
+                tot += s_wsum[j];
+            }
+            if (mem) ids[run + pre + incl - 1] = (int32_t)f;
+            run += tot;
+            __syncthreads();
+        }
+    }
+}
+
+
+// ===========================================================================
+// Near-wall refinement (paper Sec. II-C-1, II-C-2)
+// ===========================================================================
+constexpr int kFlagCap = 128;  // staged candidate faces per wave
+
+template <int D>
+struct FlagArgs {
+    dev::Faces faces;
+    dev::BinGrid bins;
+    const uint32_t *keys;
+    int64_t n;
+    int level;
+    int R[3];
+    float lo[3];
+    float dx[3];
+    float eps[3];
+    float h;
+    uint8_t *cf;     // n * 4^D
+    uint8_t *pmark;  // n
+};
+
+// One wave: blocks first .. first + 64/4^D - 1 of A (one lane per cell).
+template <int D>
+__device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
+    constexpr int CELLS = D == 3 ? 64 : 16;
+    constexpr int BPW = 64 / CELLS;
+    constexpr int NF = D * D + 2 * D;   // coordinates, then the bounding box
+    __shared__ float s_f[NF][kFlagCap];
+    const int lane = threadIdx.x;
+    const int64_t blk = first + lane / CELLS;
+    const bool valid = blk < A.n;
+    const int cell = lane % CELLS;
+
+    int bc[3] = {0, 0, 0};
+    if (valid) dev::decode_key<D>(A.keys[blk], A.level, A.R[0], A.R[1], bc);
+    const int g0 = 4 * bc[0] + (cell & 3), g1 = 4 * bc[1] + ((cell >> 2) & 3), g2 = 4 * bc[2] + (cell >> 4);
+    float m[3];
+    m[0] = dev::cell_centre(A.lo[0], g0, A.dx[0]);
+    m[1] = dev::cell_centre(A.lo[1], g1, A.dx[1]);
+    m[2] = D == 3 ? dev::cell_centre(A.lo[2], g2, A.dx[2]) : 0.0f;
+    const float h = A.h;
+    bool flagged = !valid;
+    const int64_t F = A.faces.F;
+
+    int count = 0;  // staged faces (wave-uniform)
+    // Batches of 64 staged faces: each lane marks the faces its cube's box axes do
+    // not separate from it -- the separating-axis test's own three box-axis tests,
+    // since min_k fl(v_k - m) = fl(min_k v_k - m) -- then runs the full test on
+    // those faces only, until flagged.
+    auto test_staged = [&](int n) {
+        __syncthreads();
+        for (int j0 = 0; j0 < n; j0 += 64) {
+            if (__ballot(!flagged) == 0) break;
+            const int jn = min(64, n - j0);
+            uint64_t nm = 0;
+            if (!flagged)
+                for (int jj = 0; jj < jn; ++jj) {
+                    bool near = true;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        const float lo_a = s_f[D * D + a][j0 + jj] - m[a];
+                        const float hi_a = s_f[D * D + D + a][j0 + jj] - m[a];
+                        near = near && !(lo_a > h) && !(hi_a < -h);
+                    }
+                    nm |= near ? (1ull << jj) : 0ull;
+                }
+            while (nm && !flagged) {
+                const int j = j0 + __builtin_ctzll(nm);
+                nm &= nm - 1ull;
+                float v[D * D];
+#pragma unroll
+                for (int k = 0; k < D * D; ++k) v[k] = s_f[k][j];
+                if constexpr (D == 3) flagged = dev::sat_triangle(v, m, h);
+                else flagged = dev::sat_segment(v, m, h);
+            }
+        }
+        __syncthreads();
+    };
+
+    bool done = __ballot(!flagged) == 0;
+    for (int sb = 0; sb < BPW && !done; ++sb) {
+        if (first + sb >= A.n) break;
+        // block coordinates of sub-block sb (from its first lane)
+        int sc[3];
+        sc[0] = __shfl(bc[0], sb * CELLS, 64);
+        sc[1] = __shfl(bc[1], sb * CELLS, 64);
+        sc[2] = __shfl(bc[2], sb * CELLS, 64);
+        float qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
+        int ilo[3] = {0, 0, 0}, ihi[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            qlo[a] = (dev::cell_centre(A.lo[a], 4 * sc[a], A.dx[a]) - h) - A.eps[a];
+            qhi[a] = (dev::cell_centre(A.lo[a], 4 * sc[a] + 3, A.dx[a]) + h) + A.eps[a];
+            ilo[a] = dev::bin_of(qlo[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
+            ihi[a] = dev::bin_of(qhi[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
+        }
+        for (int z = ilo[2]; z <= ihi[2] && !done; ++z)
+            for (int y = ilo[1]; y <= ihi[1] && !done; ++y)
+                for (int x = ilo[0]; x <= ihi[0] && !done; ++x) {
+                    const int64_t b = ((int64_t)z * A.bins.B + y) * A.bins.B + x;
+                    const uint32_t s0 = A.bins.off[b], s1 = A.bins.off[b + 1];
+                    for (uint32_t base = s0; base < s1 && !done; base += 64) {
+                        const uint32_t j = base + lane;
+                        bool keep = false;
+                        int32_t f = -1;
+                        if (j < s1) {
+                            f = A.bins.ids[j];
+                            keep = true;
+                            const int cur[3] = {x, y, z};
+#pragma unroll
+                            for (int a = 0; a < D; ++a) {
+                                const float mn = A.faces.aabb[(int64_t)a * F + f];
+                                const float mx = A.faces.aabb[(int64_t)(D + a) * F + f];
+                                // visit each face once: in the first bin of (its bins) x (query bins)
+                                const int fb = max(dev::bin_of(mn, A.bins.lo[a], A.bins.s[a], A.bins.B), ilo[a]);
+                                keep = keep && fb == cur[a] && mn <= qhi[a] && mx >= qlo[a];
+                            }
+                        }
+                        const uint64_t mask = __ballot(keep);
+                        const int nk = __popcll(mask);
+                        if (nk == 0) continue;
+                        if (count + nk > kFlagCap) {
+                            test_staged(count);
+                            count = 0;
+                            done = __ballot(!flagged) == 0;
+                            if (done) break;
+                        }
+                        if (keep) {
+                            const int pos = count + dev::lanes_below(mask);
+#pragma unroll
+                            for (int k = 0; k < D * D; ++k) s_f[k][pos] = A.faces.coords[(int64_t)k * F + f];
+#pragma unroll
+                            for (int k = 0; k < 2 * D; ++k) s_f[D * D + k][pos] = A.faces.aabb[(int64_t)k * F + f];
+                        }
+                        count += nk;
+                    }
+                }
+    }
+    if (!done && count > 0) test_staged(count);
+
+    if (valid) A.cf[blk * CELLS + cell] = flagged ? 1 : 0;
+    // block mark: OR over the block's cells
+    const uint64_t fm = __ballot(valid && flagged);
+    if (valid && cell == 0) {
+        uint64_t bm = fm;
+        if constexpr (CELLS < 64) bm = (fm >> (lane & ~(CELLS - 1))) & ((1ull << CELLS) - 1);
+        A.pmark[blk] = bm ? 1 : 0;
+    }
+}
+
+// 2:1 balance: a block of level m marked in this pass needs every neighbour
+// position (faces, edges, corners) inside the domain to exist at level m;
+// where it does not, the covering level-(m-1) leaf is marked.  One thread per
+// (block, neighbour position), so each thread does two binary searches.
+template <int D>
+__device__ __forceinline__ void ripple_item(const uint32_t *keys_m, int64_t n_m, const uint8_t *pm_m, int m,
+                                            const uint32_t *keys_p, int64_t n_p, const uint8_t *leaf_p, uint8_t *pm_p,
+                                            int R0, int R1, int R2, uint32_t *err, int64_t t) {
+    constexpr int NNB = D == 3 ? 26 : 8;
+    {
+        const int64_t i = t / NNB;
+        if (!pm_m[i]) return;
+        int k = (int)(t % NNB);
+        k += k >= NNB / 2 ? 1 : 0;   // skip the centre of the 3^D stencil
+        const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = D == 3 ? k / 9 - 1 : 0;
+        int c[3];
+        dev::decode_key<D>(keys_m[i], m, R0, R1, c);
+        const int ext[3] = {R0 << m, R1 << m, R2 << m};
+        int nc[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+        if (nc[0] < 0 || nc[0] >= ext[0] || nc[1] < 0 || nc[1] >= ext[1]) return;
+        if (D == 3 && (nc[2] < 0 || nc[2] >= ext[2])) return;
+        const uint32_t kn = dev::encode_key<D>(nc, m, R0, R1);
+        const int64_t jn = dev::lower_bound_u32(keys_m, n_m, kn);
+        if (jn < n_m && keys_m[jn] == kn) return;
+        int pc[3] = {nc[0] >> 1, nc[1] >> 1, D == 3 ? nc[2] >> 1 : 0};
+        const uint32_t kp = dev::encode_key<D>(pc, m - 1, R0, R1);
+        const int64_t jp = dev::lower_bound_u32(keys_p, n_p, kp);
+        if (jp < n_p && keys_p[jp] == kp && leaf_p[jp]) pm_p[jp] = 2;
+        else atomicOr(err, 1u);
+    }
+}
+
+// Marked blocks of level m: become parents (leaf 0, export mark = pass mark)
+// and their keys are compacted in order into mk.
+__device__ __forceinline__ void mark_parents_item(const uint32_t *keys, const uint8_t *pm, const uint32_t *pos,
+                                                  uint8_t *leaf, uint8_t *mark, uint32_t *mk, int64_t i) {
+    {
+        const uint8_t p = pm[i];
+        if (!p) return;
+        leaf[i] = 0;
+        mark[i] = p;
+        mk[pos[i]] = keys[i];
+    }
+}
+
+// Existing blocks of level m+1 move to their place in the merged list.
+template <int CELLS>
+__device__ __forceinline__ void merge_old_item(const uint32_t *keys, const uint8_t *leaf, const uint8_t *mark,
+                                               const uint8_t *cf, const uint32_t *mk, int64_t n_mk, int D,
+                                               uint32_t *nkeys, uint8_t *nleaf, uint8_t *nmark, uint8_t *ncf,
+                                               int64_t i) {
+    {
+        const uint32_t k = keys[i];
+        const int64_t r = dev::lower_bound_u32(mk, n_mk, k >> D);
+        const int64_t p = i + (r << D);
+        nkeys[p] = k;
+        nleaf[p] = leaf[i];
+        nmark[p] = mark[i];
+        if (ncf)
+            for (int c = 0; c < CELLS; ++c) ncf[p * CELLS + c] = cf[i * CELLS + c];
+    }
+}
+
+// Children of the marked parents, placed after the existing keys below them.
+template <int CELLS>
+__device__ __forceinline__ void children_item(const uint32_t *mk, const uint32_t *keys_old, int64_t n_old, int D,
+                                              uint32_t *nkeys, uint8_t *nleaf, uint8_t *nmark, uint8_t *ncf,
+                                              int64_t t) {
+    {
+        const int64_t pi = t >> D;
+        const uint32_t ci = (uint32_t)(t & ((1 << D) - 1));
+        const uint32_t parent = mk[pi];
+        const int64_t below = dev::lower_bound_u32(keys_old, n_old, parent << D);
+        const int64_t p = below + t;
+        nkeys[p] = (parent << D) | ci;
+        nleaf[p] = 1;
+        nmark[p] = 0;
+        if (ncf)
+            for (int c = 0; c < CELLS; ++c) ncf[p * CELLS + c] = 0;
+    }
+}
+
+
+
+// ===========================================================================
+// Link fractions and their adjoint (paper Sec. II-C-1)
+// ===========================================================================
+constexpr int kLinkCap = 128;  // staged faces per wave
+
+template <int D, int Q>
+struct LinkArgs {
+    dev::Faces faces;
+    dev::BinGrid bins;
+    const uint32_t *keys;
+    int64_t n;
+    int level;
+    int R[3];
+    float lo[3];
+    float dx[3];
+    float eps[3];
+    uint64_t *node_key;    // staging rows
+    float *q;
+    int32_t *face;
+};
+
+// One wave: finest-level blocks first .. first + 64/4^D - 1 of A.  `out` places
+// each block's nodes: out.rows(blk, count) returns the first staging row of the
+// block (and records the count); rows are written in cell order.
+template <int D, int Q, class Out>
+__device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t first, Out &out) {
+    constexpr int CELLS = D == 3 ? 64 : 16;
+    constexpr int BPW = 64 / CELLS;
+    constexpr int NP = (Q - 1) / 2;            // direction pairs
+    constexpr int NF = D == 3 ? 18 : 8;        // floats staged per face
+    __shared__ float s_f[NF][kLinkCap];
+    __shared__ int32_t s_id[kLinkCap];
+    __shared__ float s_dir[NP][3];   // D = c * dx of each direction pair's first direction
+    const int lane = threadIdx.x;
+    if (lane < NP)
+        for (int a = 0; a < 3; ++a) s_dir[lane][a] = (float)dir_c<D>(1 + 2 * lane, a) * A.dx[a];
+    const int64_t blk = first + lane / CELLS;
+    const bool valid = blk < A.n;
+    const int cell = lane % CELLS;
+    const int64_t F = A.faces.F;
+
+    int bc[3] = {0, 0, 0};
+    uint32_t key = 0;
+    if (valid) {
+        key = A.keys[blk];
+        dev::decode_key<D>(key, A.level, A.R[0], A.R[1], bc);
+    }
+    float o[3];
+    o[0] = dev::cell_centre(A.lo[0], 4 * bc[0] + (cell & 3), A.dx[0]);
+    o[1] = dev::cell_centre(A.lo[1], 4 * bc[1] + ((cell >> 2) & 3), A.dx[1]);
+    o[2] = D == 3 ? dev::cell_centre(A.lo[2], 4 * bc[2] + (cell >> 4), A.dx[2]) : 0.0f;
+    float clo[3], chi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        clo[a] = (o[a] - A.dx[a]) - A.eps[a];
+        chi[a] = (o[a] + A.dx[a]) + A.eps[a];
+    }
+
+    float best_t[Q - 1];
+    int32_t best_f[Q - 1];
+#pragma unroll
+    for (int i = 0; i < Q - 1; ++i) {
+        best_t[i] = 2.0f;
+        best_f[i] = -1;
+    }
+
+    // t is decided in FP64 and kept rounded to FP32; equal FP32 values go to the
+    // lower face id (both faces are then hits at the same q).
+    auto consider = [&](int i, double t64, int32_t f) {
+        if (!(t64 >= 0.0 && t64 <= 1.0)) return;
+        const float t = (float)t64;
+        if (t < best_t[i] || (t == best_t[i] && f < best_f[i])) {
+            best_t[i] = t;
+            best_f[i] = f;
+        }
+    };
+
+    // FP64 decision for one (face, direction pair) that passed the FP32 filter:
+    // the segment-triangle test in the same expression order as the definition
+    // (Moller-Trumbore), so both directions of the pair come out exactly as
+    // separate evaluations would (negating D negates P, det and t exactly).
+    auto decide64_tri = [&](int p, int j, double &tout) -> bool {
+        const double a0 = s_f[0][j], a1 = s_f[1][j], a2 = s_f[2][j];
+        const double E1[3] = {(double)s_f[3][j] - a0, (double)s_f[4][j] - a1, (double)s_f[5][j] - a2};
+        const double E2[3] = {(double)s_f[6][j] - a0, (double)s_f[7][j] - a1, (double)s_f[8][j] - a2};
+        const double T[3] = {(double)o[0] - a0, (double)o[1] - a1, (double)o[2] - a2};
+        const double Dv[3] = {(double)s_dir[p][0], (double)s_dir[p][1], (double)s_dir[p][2]};
+        const double P[3] = {Dv[1] * E2[2] - Dv[2] * E2[1], Dv[2] * E2[0] - Dv[0] * E2[2], Dv[0] * E2[1] - Dv[1] * E2[0]};
+        const double det = E1[0] * P[0] + E1[1] * P[1] + E1[2] * P[2];
+        if (det == 0.0) return false;
+        const double u = (T[0] * P[0] + T[1] * P[1] + T[2] * P[2]) / det;
+        if (u < 0.0 || u > 1.0) return false;
+        const double Qv[3] = {T[1] * E1[2] - T[2] * E1[1], T[2] * E1[0] - T[0] * E1[2], T[0] * E1[1] - T[1] * E1[0]};
+        const double v = (Dv[0] * Qv[0] + Dv[1] * Qv[1] + Dv[2] * Qv[2]) / det;
+        if (v < 0.0 || u + v > 1.0) return false;
+        tout = (E2[0] * Qv[0] + E2[1] * Qv[1] + E2[2] * Qv[2]) / det;
+        return true;
+    };
+    auto decide64_seg = [&](int p, int j, double &tout) -> bool {
+        const double a0 = s_f[0][j], a1 = s_f[1][j];
+        const double e0 = (double)s_f[2][j] - a0, e1 = (double)s_f[3][j] - a1;
+        const double D0 = (double)s_dir[p][0], D1 = (double)s_dir[p][1];
+        const double den = D0 * e1 - D1 * e0;
+        if (den == 0.0) return false;
+        const double w0 = a0 - (double)o[0], w1 = a1 - (double)o[1];
+        tout = (w0 * e1 - w1 * e0) / den;
+        const double sp = (w0 * D1 - w1 * D0) / den;
+        return sp >= 0.0 && sp <= 1.0;
+    };
+    // Runtime pair index p: one copy of the FP64 code; the result reaches the
+    // register-resident best arrays through an unrolled predicated update.
+    auto decide_mask = [&](uint32_t cm, int j, int32_t f) {
+        while (cm) {
+            const int p = __builtin_ctz(cm);
+            cm &= cm - 1u;
+            double t;
+            bool hit;
+            if constexpr (D == 3) hit = decide64_tri(p, j, t);
+            else hit = decide64_seg(p, j, t);
+            if (!hit) continue;
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+                if (q == p) {
+                    consider(2 * q, t, f);       // direction 1 + 2q
+                    consider(2 * q + 1, -t, f);  // its opposite
+                }
+        }
+    };
+
+    // Staged faces are visited in batches of 64: each lane first marks the faces
+    // whose box meets its link box (broadcast LDS reads), then walks only its
+    // own marked faces, so lanes stay busy whatever the spatial mix.
+    auto test_staged = [&](int n) {
+        __syncthreads();
+        if (valid)
+        for (int j0 = 0; j0 < n; j0 += 64) {
+            const int jn = min(64, n - j0);
+            uint64_t nm = 0;
+            for (int jj = 0; jj < jn; ++jj) {
+                bool near = true;
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    const float mn = s_f[NF - 2 * D + a][j0 + jj], mx = s_f[NF - D + a][j0 + jj];
+                    near = near && mn <= chi[a] && mx >= clo[a];
+                }
+                nm |= near ? (1ull << jj) : 0ull;
+            }
+            while (nm) {
+                const int j = j0 + __builtin_ctzll(nm);
+                nm &= nm - 1ull;
+                const int32_t f = s_id[j];
+                if constexpr (D == 3) {
+                    // FP32 filter.  Each quantity below carries an absolute rounding error
+                    // bounded by 2^-21 times the product of the L1 norms of its factors;
+                    // margins of 2^-20 times those products keep every true hit.
+                    const float T0 = o[0] - s_f[0][j], T1 = o[1] - s_f[1][j], T2 = o[2] - s_f[2][j];
+                    const float e10 = s_f[3][j] - s_f[0][j], e11 = s_f[4][j] - s_f[1][j], e12 = s_f[5][j] - s_f[2][j];
+                    const float e20 = s_f[6][j] - s_f[0][j], e21 = s_f[7][j] - s_f[1][j], e22 = s_f[8][j] - s_f[2][j];
+                    const float n0 = s_f[9][j], n1 = s_f[10][j], n2 = s_f[11][j];
+                    const float nT = fabsf(T0) + fabsf(T1) + fabsf(T2);
+                    const float n1n = fabsf(e10) + fabsf(e11) + fabsf(e12);
+                    const float n2n = fabsf(e20) + fabsf(e21) + fabsf(e22);
+                    const float mx_ = fmaxf(fmaxf(A.dx[0], A.dx[1]), A.dx[2]) * 9.5367431640625e-07f;  // dx * 2^-20
+                    const float MU = mx_ * nT * n2n;
+                    const float MV = mx_ * n1n * nT;
+                    const float MD = mx_ * n1n * n2n;
+                    const float MT = 9.5367431640625e-07f * nT * n1n * n2n;
+                    const float p10 = (T1 * e22 - T2 * e21) * A.dx[0];
+                    const float p11 = (T2 * e20 - T0 * e22) * A.dx[1];
+                    const float p12 = (T0 * e21 - T1 * e20) * A.dx[2];
+                    const float p20 = (e11 * T2 - e12 * T1) * A.dx[0];
+                    const float p21 = (e12 * T0 - e10 * T2) * A.dx[1];
+                    const float p22 = (e10 * T1 - e11 * T0) * A.dx[2];
+                    const float d0 = n0 * A.dx[0], d1 = n1 * A.dx[1], d2 = n2 * A.dx[2];
+                    const float tn = (T0 * n0 + T1 * n1) + T2 * n2;
+                    uint32_t cm = 0;   // direction pairs that pass the FP32 filter
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        const int i = 1 + 2 * p;
+                        const int c0 = dir_c<D>(i, 0), c1 = dir_c<D>(i, 1), c2 = dir_c<D>(i, 2);
+                        float den = 0.0f, nu = 0.0f, nv = 0.0f;
+                        if (c0) { den += c0 > 0 ? d0 : -d0; nu += c0 > 0 ? p10 : -p10; nv += c0 > 0 ? p20 : -p20; }
+                        if (c1) { den += c1 > 0 ? d1 : -d1; nu += c1 > 0 ? p11 : -p11; nv += c1 > 0 ? p21 : -p21; }
+                        if (c2) { den += c2 > 0 ? d2 : -d2; nu += c2 > 0 ? p12 : -p12; nv += c2 > 0 ? p22 : -p22; }
+                        bool cand;
+                        if (fabsf(den) <= MD) {
+                            cand = true;   // grazing: the sign of the denominator is not known in FP32
+                        } else {
+                            const float ad = fabsf(den);
+                            const float su = den < 0.0f ? -nu : nu;
+                            const float sv = den < 0.0f ? -nv : nv;
+                            const float st = den < 0.0f ? tn : -tn;   // sign(den) * (-tn) = t * |den|
+                            const float lim = ad + MD + MT;
+                            cand = su >= -MU && sv >= -MV && su + sv <= ad + MU + MV + MD &&
+                                   ((st >= -MT && st <= lim) || (-st >= -MT && -st <= lim));
+                        }
+                        cm |= cand ? (1u << p) : 0u;
+                    }
+                    if (cm) decide_mask(cm, j, f);
+                } else {
+                    const float w0 = s_f[0][j] - o[0], w1 = s_f[1][j] - o[1];
+                    const float e0 = s_f[2][j] - s_f[0][j], e1 = s_f[3][j] - s_f[1][j];
+                    const float nw = fabsf(w0) + fabsf(w1), ne = fabsf(e0) + fabsf(e1);
+                    const float mx_ = fmaxf(A.dx[0], A.dx[1]) * 9.5367431640625e-07f;
+                    const float MD = mx_ * ne, MS = mx_ * nw, MW = 9.5367431640625e-07f * nw * ne;
+                    const float wxe = w0 * e1 - w1 * e0;
+                    uint32_t cm = 0;
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        const int i = 1 + 2 * p;
+                        const float D0 = (float)dir_c<D>(i, 0) * A.dx[0], D1 = (float)dir_c<D>(i, 1) * A.dx[1];
+                        const float den = D0 * e1 - D1 * e0;
+                        bool cand;
+                        if (fabsf(den) <= MD) {
+                            cand = true;
+                        } else {
+                            const float ad = fabsf(den);
+                            const float sn = w0 * D1 - w1 * D0;
+                            const float ss = den < 0.0f ? -sn : sn;
+                            const float st = den < 0.0f ? -wxe : wxe;
+                            const float lim = ad + MD + MW;
+                            cand = ss >= -MS && ss <= ad + MS + MD &&
+                                   ((st >= -MW && st <= lim) || (-st >= -MW && -st <= lim));
+                        }
+                        cm |= cand ? (1u << p) : 0u;
+                    }
+                    if (cm) decide_mask(cm, j, f);
+                }
+            }
+        }
+        __syncthreads();
+    };
+
+    int count = 0;
+    for (int sb = 0; sb < BPW; ++sb) {
+        if (first + sb >= A.n) break;
+        int sc[3];
+        sc[0] = __shfl(bc[0], sb * CELLS, 64);
+        sc[1] = __shfl(bc[1], sb * CELLS, 64);
+        sc[2] = __shfl(bc[2], sb * CELLS, 64);
+        float qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
+        int ilo[3] = {0, 0, 0}, ihi[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            qlo[a] = (dev::cell_centre(A.lo[a], 4 * sc[a], A.dx[a]) - A.dx[a]) - A.eps[a];
+            qhi[a] = (dev::cell_centre(A.lo[a], 4 * sc[a] + 3, A.dx[a]) + A.dx[a]) + A.eps[a];
+            ilo[a] = dev::bin_of(qlo[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
+            ihi[a] = dev::bin_of(qhi[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
+        }
+        for (int z = ilo[2]; z <= ihi[2]; ++z)
+            for (int y = ilo[1]; y <= ihi[1]; ++y)
+                for (int x = ilo[0]; x <= ihi[0]; ++x) {
+                    const int64_t b = ((int64_t)z * A.bins.B + y) * A.bins.B + x;
+                    const uint32_t s0 = A.bins.off[b], s1 = A.bins.off[b + 1];
+                    for (uint32_t base = s0; base < s1; base += 64) {
+                        const uint32_t j = base + lane;
+                        bool keep = false;
+                        int32_t f = -1;
+                        float bb[6] = {0, 0, 0, 0, 0, 0};
+                        if (j < s1) {
+                            f = A.bins.ids[j];
+                            keep = true;
+                            const int cur[3] = {x, y, z};
+#pragma unroll
+                            for (int a = 0; a < D; ++a) {
+                                bb[a] = A.faces.aabb[(int64_t)a * F + f];
+                                bb[D + a] = A.faces.aabb[(int64_t)(D + a) * F + f];
+                                const int fb = max(dev::bin_of(bb[a], A.bins.lo[a], A.bins.s[a], A.bins.B), ilo[a]);
+                                keep = keep && fb == cur[a] && bb[a] <= qhi[a] && bb[D + a] >= qlo[a];
+                            }
+                        }
+                        const uint64_t mask = __ballot(keep);
+                        const int nk = __popcll(mask);
+                        if (nk == 0) continue;
+                        if (count + nk > kLinkCap) {
+                            test_staged(count);
+                            count = 0;
+                        }
+                        if (keep) {
+                            const int pos = count + dev::lanes_below(mask);
+                            s_id[pos] = f;
+                            if constexpr (D == 3) {
+                                float v[9];
+#pragma unroll
+                                for (int k = 0; k < 9; ++k) v[k] = A.faces.coords[(int64_t)k * F + f];
+                                const float e10 = v[3] - v[0], e11 = v[4] - v[1], e12 = v[5] - v[2];
+                                const float e20 = v[6] - v[0], e21 = v[7] - v[1], e22 = v[8] - v[2];
+#pragma unroll
+                                for (int k = 0; k < 9; ++k) s_f[k][pos] = v[k];
+                                s_f[9][pos] = e11 * e22 - e12 * e21;
+                                s_f[10][pos] = e12 * e20 - e10 * e22;
+                                s_f[11][pos] = e10 * e21 - e11 * e20;
+                            } else {
+#pragma unroll
+                                for (int k = 0; k < 4; ++k) s_f[k][pos] = A.faces.coords[(int64_t)k * F + f];
+                            }
+#pragma unroll
+                            for (int a = 0; a < 2 * D; ++a) s_f[NF - 2 * D + a][pos] = bb[a];
+                        }
+                        count += nk;
+                    }
+                }
+    }
+    if (count > 0) test_staged(count);
+
+    // ordered compaction of the cells that have a link
+    bool has = false;
+#pragma unroll
+    for (int i = 0; i < Q - 1; ++i) has = has || best_f[i] >= 0;
+    has = has && valid;
+    const uint64_t hm = __ballot(has);
+    // rank inside the block: lanes of this block below this lane that have a link
+    const int sub = lane / CELLS;
+    uint64_t bm = hm;
+    if constexpr (CELLS < 64) bm = (hm >> (sub * CELLS)) & ((1ull << CELLS) - 1);
+    int64_t row0 = 0;
+    if (valid && cell == 0) row0 = out.rows(blk, (uint32_t)__popcll(bm));
+    row0 = __shfl(row0, sub * CELLS, 64);
+    if (has) {
+        const int64_t node = row0 + __popcll(bm & ((1ull << cell) - 1));
+        A.node_key[node] = (uint64_t)key * CELLS + (uint64_t)cell;
+        float *qr = A.q + node * Q;
+        int32_t *fr = A.face + node * Q;
+        qr[0] = -1.0f;
+        fr[0] = -1;
+#pragma unroll
+        for (int i = 0; i < Q - 1; ++i) {
+            qr[i + 1] = best_f[i] >= 0 ? best_t[i] : -1.0f;
+            fr[i + 1] = best_f[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint: one thread per (node, direction) slot.
+// ---------------------------------------------------------------------------
+template <int D, int Q>
+struct AdjArgs {
+    const float *coords;
+    int64_t F;
+    const int32_t *fidx;
+    const uint64_t *node_key;
+    const int32_t *face;
+    const float *gq;
+    int64_t n;
+    int level;
+    int R[3];
+    float lo[3];
+    float dx[3];
+    float *grad;
+};
+
+constexpr int kAdjThreads = 256;   // one node per thread
+constexpr int kAdjHash = 512;      // per-workgroup face accumulators
+
+// Gradient of one link's t with respect to the D vertices of its face,
+// scaled by w: out[k][a] = w * lambda_k * n_a / (D . n).
+template <int D>
+__device__ __forceinline__ void link_grad(const float *coords, int64_t F, int32_t f, const float o[3],
+                                          const float Dv[3], float w, float out[D][D]) {
+    if constexpr (D == 3) {
+        float v[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) v[k] = coords[(int64_t)k * F + f];
+        const float e1[3] = {v[3] - v[0], v[4] - v[1], v[5] - v[2]};
+        const float e2[3] = {v[6] - v[0], v[7] - v[1], v[8] - v[2]};
+        const float T[3] = {o[0] - v[0], o[1] - v[1], o[2] - v[2]};
+        const float n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                            e1[0] * e2[1] - e1[1] * e2[0]};
+        const float den = (Dv[0] * n[0] + Dv[1] * n[1]) + Dv[2] * n[2];
+        const float dd = sqrtf((Dv[0] * Dv[0] + Dv[1] * Dv[1]) + Dv[2] * Dv[2]);
+        const float ee = sqrtf((e1[0] * e1[0] + e1[1] * e1[1]) + e1[2] * e1[2]) *
+                         sqrtf((e2[0] * e2[0] + e2[1] * e2[1]) + e2[2] * e2[2]);
+        float u, vv, inv;
+        if (fabsf(den) < 0.0009765625f * dd * ee) {
+            // grazing ray: barycentrics and denominator in FP64 from the FP32 data
+            double E1[3], E2[3], N[3], TT[3];
+            for (int a = 0; a < 3; ++a) {
+                E1[a] = (double)v[3 + a] - (double)v[a];
+                E2[a] = (double)v[6 + a] - (double)v[a];
+                TT[a] = (double)o[a] - (double)v[a];
+            }
+            N[0] = E1[1] * E2[2] - E1[2] * E2[1];
+            N[1] = E1[2] * E2[0] - E1[0] * E2[2];
+            N[2] = E1[0] * E2[1] - E1[1] * E2[0];
+            const double den64 = (double)Dv[0] * N[0] + (double)Dv[1] * N[1] + (double)Dv[2] * N[2];
+            const double P1[3] = {TT[1] * E2[2] - TT[2] * E2[1], TT[2] * E2[0] - TT[0] * E2[2],
+                                  TT[0] * E2[1] - TT[1] * E2[0]};
+            const double P2[3] = {E1[1] * TT[2] - E1[2] * TT[1], E1[2] * TT[0] - E1[0] * TT[2],
+                                  E1[0] * TT[1] - E1[1] * TT[0]};
+            u = (float)(((double)Dv[0] * P1[0] + (double)Dv[1] * P1[1] + (double)Dv[2] * P1[2]) / den64);
+            vv = (float)(((double)Dv[0] * P2[0] + (double)Dv[1] * P2[1] + (double)Dv[2] * P2[2]) / den64);
+            inv = (float)(1.0 / den64);
+        } else {
+            const float p1[3] = {T[1] * e2[2] - T[2] * e2[1], T[2] * e2[0] - T[0] * e2[2],
+                                 T[0] * e2[1] - T[1] * e2[0]};
+            const float p2[3] = {e1[1] * T[2] - e1[2] * T[1], e1[2] * T[0] - e1[0] * T[2],
+                                 e1[0] * T[1] - e1[1] * T[0]};
+            inv = 1.0f / den;
+            u = ((Dv[0] * p1[0] + Dv[1] * p1[1]) + Dv[2] * p1[2]) * inv;
+            vv = ((Dv[0] * p2[0] + Dv[1] * p2[1]) + Dv[2] * p2[2]) * inv;
+        }
+        const float lam[3] = {1.0f - u - vv, u, vv};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float sc = w * lam[k] * inv;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) out[k][a] = sc * n[a];
+        }
+    } else {
+        const float a0 = coords[(int64_t)0 * F + f], a1 = coords[(int64_t)1 * F + f];
+        const float b0 = coords[(int64_t)2 * F + f], b1 = coords[(int64_t)3 * F + f];
+        const float e0 = b0 - a0, e1 = b1 - a1;
+        const float n[2] = {-e1, e0};
+        const float w0 = a0 - o[0], w1 = a1 - o[1];
+        const float den = Dv[0] * n[0] + Dv[1] * n[1];
+        const float dd = sqrtf(Dv[0] * Dv[0] + Dv[1] * Dv[1]);
+        const float ee = sqrtf(e0 * e0 + e1 * e1);
+        float sp, inv;
+        if (fabsf(den) < 0.0009765625f * dd * ee) {
+            const double E0 = (double)b0 - (double)a0, E1 = (double)b1 - (double)a1;
+            const double W0 = (double)a0 - (double)o[0], W1 = (double)a1 - (double)o[1];
+            const double dxe = (double)Dv[0] * E1 - (double)Dv[1] * E0;   // D x e
+            sp = (float)((W0 * (double)Dv[1] - W1 * (double)Dv[0]) / dxe);
+            inv = (float)(1.0 / ((double)Dv[0] * -E1 + (double)Dv[1] * E0));
+        } else {
+            const float dxe = Dv[0] * e1 - Dv[1] * e0;
+            sp = (w0 * Dv[1] - w1 * Dv[0]) / dxe;
+            inv = 1.0f / den;
+        }
+        const float lam[2] = {1.0f - sp, sp};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const float sc = w * lam[k] * inv;
+            out[k][0] = sc * n[0];
+            out[k][1] = sc * n[1];
+        }
+    }
+}
+
+// One thread per node.  A thread walks only its live directions (bitmask);
+// consecutive contributions to the same face are summed in registers, then
+// per face in an LDS hash table (neighbouring nodes in key order hit few
+// distinct faces), and each face's sums go to its vertices with one float
+// atomic per coordinate.
+// One workgroup of kAdjThreads threads: nodes node0 .. node0 + kAdjThreads - 1 of A.
+template <int D, int Q>
+__device__ __forceinline__ void adjoint_tile(const AdjArgs<D, Q> &A, int64_t node0) {
+    constexpr int CELLS = D == 3 ? 64 : 16;
+    __shared__ int32_t s_key[kAdjHash];
+    __shared__ float s_acc[kAdjHash][D * D];
+    __shared__ float s_D[Q][3];
+    for (int i = threadIdx.x; i < kAdjHash; i += kAdjThreads) {
+        s_key[i] = -1;
+#pragma unroll
+        for (int c = 0; c < D * D; ++c) s_acc[i][c] = 0.0f;
+    }
+    if (threadIdx.x < Q)
+        for (int a = 0; a < 3; ++a) s_D[threadIdx.x][a] = (float)dir_c<D>(threadIdx.x, a) * A.dx[a];
+    __syncthreads();
+
+    auto to_lds = [&](int32_t f, const float (&g)[D][D]) {
+        uint32_t h = ((uint32_t)f * 2654435761u) >> 23;   // 9 bits: kAdjHash slots
+        for (int probe = 0; probe < kAdjHash; ++probe) {
+            const int32_t prev = atomicCAS(&s_key[h], -1, f);
+            if (prev == -1 || prev == f) {
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+#pragma unroll
+                    for (int a = 0; a < D; ++a) atomicAdd(&s_acc[h][k * D + a], g[k][a]);
+                return;
+            }
+            h = (h + 1) & (kAdjHash - 1);
+        }
+        // table full: straight to the vertices
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int64_t vk = A.fidx[(int64_t)f * D + k];
+#pragma unroll
+            for (int a = 0; a < D; ++a) unsafeAtomicAdd(&A.grad[vk * D + a], g[k][a]);
+        }
+    };
+
+    const int64_t node = node0 + threadIdx.x;
+    if (node < A.n) {
+        uint32_t live = 0;
+        for (int i = 1; i < Q; ++i)
+            live |= (A.face[node * Q + i] >= 0 && A.gq[node * Q + i] != 0.0f) ? (1u << i) : 0u;
+        if (live) {
+            const uint64_t nk = A.node_key[node];
+            const uint32_t key = (uint32_t)(nk / CELLS);
+            const int cell = (int)(nk % CELLS);
+            int bc[3];
+            dev::decode_key<D>(key, A.level, A.R[0], A.R[1], bc);
+            float o[3];
+            o[0] = dev::cell_centre(A.lo[0], 4 * bc[0] + (cell & 3), A.dx[0]);
+            o[1] = dev::cell_centre(A.lo[1], 4 * bc[1] + ((cell >> 2) & 3), A.dx[1]);
+            o[2] = D == 3 ? dev::cell_centre(A.lo[2], 4 * bc[2] + (cell >> 4), A.dx[2]) : 0.0f;
+            int32_t cur = -1;
+            float acc[D][D];
+            while (live) {
+                const int i = __builtin_ctz(live);
+                live &= live - 1u;
+                const int32_t f = A.face[node * Q + i];
+                const float w = A.gq[node * Q + i];
+                const float Dv[3] = {s_D[i][0], s_D[i][1], s_D[i][2]};
+                float g[D][D];
+                link_grad<D>(A.coords, A.F, f, o, Dv, w, g);
+                if (f == cur) {
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+#pragma unroll
+                        for (int a = 0; a < D; ++a) acc[k][a] += g[k][a];
+                } else {
+                    if (cur >= 0) to_lds(cur, acc);
+                    cur = f;
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+#pragma unroll
+                        for (int a = 0; a < D; ++a) acc[k][a] = g[k][a];
+                }
+            }
+            if (cur >= 0) to_lds(cur, acc);
+        }
+    }
+    __syncthreads();
+    for (int sl = threadIdx.x; sl < kAdjHash; sl += kAdjThreads) {
+        const int32_t f = s_key[sl];
+        if (f < 0) continue;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int64_t vk = A.fidx[(int64_t)f * D + k];
+#pragma unroll
+            for (int a = 0; a < D; ++a) unsafeAtomicAdd(&A.grad[vk * D + a], s_acc[sl][k * D + a]);
+        }
+    }
+    __syncthreads();
+}
+
+// Copy c staged node rows (key, q row, face row) from row src to row dst, as
+// flat coalesced runs over one wave.
+template <int Q>
+__device__ __forceinline__ void compact_block(int c, int64_t src, int64_t dst, const uint64_t *skey, const float *sq,
+                                              const int32_t *sface, uint64_t *key, float *q, int32_t *face) {
+    if (c == 0) return;
+    for (int r = threadIdx.x; r < c; r += 64) key[dst + r] = skey[src + r];
+    for (int e = threadIdx.x; e < c * Q; e += 64) {
+        q[dst * Q + e] = sq[src * Q + e];
+        face[dst * Q + e] = sface[src * Q + e];
+    }
+}
+
+
+}  // namespace kern
+}  // namespace agal

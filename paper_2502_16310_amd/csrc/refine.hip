@@ -19,241 +19,48 @@
 
 #include "agal_internal.hpp"
 #include "device.hpp"
+#include "kernels.hpp"
 
 namespace agal {
 namespace {
 
-constexpr int kFlagCap = 128;  // staged candidate faces per wave
+using namespace kern;
 
-template <int D>
-struct FlagArgs {
-    dev::Faces faces;
-    dev::BinGrid bins;
-    const uint32_t *keys;
-    int64_t n;
-    int level;
-    int R[3];
-    float lo[3];
-    float dx[3];
-    float eps[3];
-    float h;
-    uint8_t *cf;     // n * 4^D
-    uint8_t *pmark;  // n
-};
+#define AGAL_GRID_STRIDE(i, n) \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
 template <int D>
 __global__ __launch_bounds__(64) void k_flag(FlagArgs<D> A) {
-    constexpr int CELLS = D == 3 ? 64 : 16;
-    constexpr int BPW = 64 / CELLS;
-    constexpr int NF = D * D + 2 * D;   // coordinates, then the bounding box
-    __shared__ float s_f[NF][kFlagCap];
-    const int lane = threadIdx.x;
-    const int64_t first = (int64_t)blockIdx.x * BPW;
-    const int64_t blk = first + lane / CELLS;
-    const bool valid = blk < A.n;
-    const int cell = lane % CELLS;
-
-    int bc[3] = {0, 0, 0};
-    if (valid) dev::decode_key<D>(A.keys[blk], A.level, A.R[0], A.R[1], bc);
-    const int g0 = 4 * bc[0] + (cell & 3), g1 = 4 * bc[1] + ((cell >> 2) & 3), g2 = 4 * bc[2] + (cell >> 4);
-    float m[3];
-    m[0] = dev::cell_centre(A.lo[0], g0, A.dx[0]);
-    m[1] = dev::cell_centre(A.lo[1], g1, A.dx[1]);
-    m[2] = D == 3 ? dev::cell_centre(A.lo[2], g2, A.dx[2]) : 0.0f;
-    const float h = A.h;
-    bool flagged = !valid;
-    const int64_t F = A.faces.F;
-
-    int count = 0;  // staged faces (wave-uniform)
-    // Batches of 64 staged faces: each lane marks the faces its cube's box axes do
-    // not separate from it -- the separating-axis test's own three box-axis tests,
-    // since min_k fl(v_k - m) = fl(min_k v_k - m) -- then runs the full test on
-    // those faces only, until flagged.
-    auto test_staged = [&](int n) {
-        __syncthreads();
-        for (int j0 = 0; j0 < n; j0 += 64) {
-            if (__ballot(!flagged) == 0) break;
-            const int jn = min(64, n - j0);
-            uint64_t nm = 0;
-            if (!flagged)
-                for (int jj = 0; jj < jn; ++jj) {
-                    bool near = true;
-#pragma unroll
-                    for (int a = 0; a < D; ++a) {
-                        const float lo_a = s_f[D * D + a][j0 + jj] - m[a];
-                        const float hi_a = s_f[D * D + D + a][j0 + jj] - m[a];
-                        near = near && !(lo_a > h) && !(hi_a < -h);
-                    }
-                    nm |= near ? (1ull << jj) : 0ull;
-                }
-            while (nm && !flagged) {
-                const int j = j0 + __builtin_ctzll(nm);
-                nm &= nm - 1ull;
-                float v[D * D];
-#pragma unroll
-                for (int k = 0; k < D * D; ++k) v[k] = s_f[k][j];
-                if constexpr (D == 3) flagged = dev::sat_triangle(v, m, h);
-                else flagged = dev::sat_segment(v, m, h);
-            }
-        }
-        __syncthreads();
-    };
-
-    bool done = __ballot(!flagged) == 0;
-    for (int sb = 0; sb < BPW && !done; ++sb) {
-        if (first + sb >= A.n) break;
-        // block coordinates of sub-block sb (from its first lane)
-        int sc[3];
-        sc[0] = __shfl(bc[0], sb * CELLS, 64);
-        sc[1] = __shfl(bc[1], sb * CELLS, 64);
-        sc[2] = __shfl(bc[2], sb * CELLS, 64);
-        float qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
-        int ilo[3] = {0, 0, 0}, ihi[3] = {0, 0, 0};
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            qlo[a] = (dev::cell_centre(A.lo[a], 4 * sc[a], A.dx[a]) - h) - A.eps[a];
-            qhi[a] = (dev::cell_centre(A.lo[a], 4 * sc[a] + 3, A.dx[a]) + h) + A.eps[a];
-            ilo[a] = dev::bin_of(qlo[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
-            ihi[a] = dev::bin_of(qhi[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
-        }
-        for (int z = ilo[2]; z <= ihi[2] && !done; ++z)
-            for (int y = ilo[1]; y <= ihi[1] && !done; ++y)
-                for (int x = ilo[0]; x <= ihi[0] && !done; ++x) {
-                    const int64_t b = ((int64_t)z * A.bins.B + y) * A.bins.B + x;
-                    const uint32_t s0 = A.bins.off[b], s1 = A.bins.off[b + 1];
-                    for (uint32_t base = s0; base < s1 && !done; base += 64) {
-                        const uint32_t j = base + lane;
-                        bool keep = false;
-                        int32_t f = -1;
-                        if (j < s1) {
-                            f = A.bins.ids[j];
-                            keep = true;
-                            const int cur[3] = {x, y, z};
-#pragma unroll
-                            for (int a = 0; a < D; ++a) {
-                                const float mn = A.faces.aabb[(int64_t)a * F + f];
-                                const float mx = A.faces.aabb[(int64_t)(D + a) * F + f];
-                                // visit each face once: in the first bin of (its bins) x (query bins)
-                                const int fb = max(dev::bin_of(mn, A.bins.lo[a], A.bins.s[a], A.bins.B), ilo[a]);
-                                keep = keep && fb == cur[a] && mn <= qhi[a] && mx >= qlo[a];
-                            }
-                        }
-                        const uint64_t mask = __ballot(keep);
-                        const int nk = __popcll(mask);
-                        if (nk == 0) continue;
-                        if (count + nk > kFlagCap) {
-                            test_staged(count);
-                            count = 0;
-                            done = __ballot(!flagged) == 0;
-                            if (done) break;
-                        }
-                        if (keep) {
-                            const int pos = count + dev::lanes_below(mask);
-#pragma unroll
-                            for (int k = 0; k < D * D; ++k) s_f[k][pos] = A.faces.coords[(int64_t)k * F + f];
-#pragma unroll
-                            for (int k = 0; k < 2 * D; ++k) s_f[D * D + k][pos] = A.faces.aabb[(int64_t)k * F + f];
-                        }
-                        count += nk;
-                    }
-                }
-    }
-    if (!done && count > 0) test_staged(count);
-
-    if (valid) A.cf[blk * CELLS + cell] = flagged ? 1 : 0;
-    // block mark: OR over the block's cells
-    const uint64_t fm = __ballot(valid && flagged);
-    if (valid && cell == 0) {
-        uint64_t bm = fm;
-        if constexpr (CELLS < 64) bm = (fm >> (lane & ~(CELLS - 1))) & ((1ull << CELLS) - 1);
-        A.pmark[blk] = bm ? 1 : 0;
-    }
+    flag_wave<D>(A, (int64_t)blockIdx.x * (D == 3 ? 1 : 4));
 }
 
-// 2:1 balance: a block of level m marked in this pass needs every neighbour
-// position (faces, edges, corners) inside the domain to exist at level m;
-// where it does not, the covering level-(m-1) leaf is marked.  One thread per
-// (block, neighbour position), so each thread does two binary searches.
 template <int D>
 __global__ void k_ripple(const uint32_t *keys_m, int64_t n_m, const uint8_t *pm_m, int m, const uint32_t *keys_p,
                          int64_t n_p, const uint8_t *leaf_p, uint8_t *pm_p, int R0, int R1, int R2, uint32_t *err) {
-    constexpr int NNB = D == 3 ? 26 : 8;
-    const int64_t total = n_m * NNB;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = t / NNB;
-        if (!pm_m[i]) continue;
-        int k = (int)(t % NNB);
-        k += k >= NNB / 2 ? 1 : 0;   // skip the centre of the 3^D stencil
-        const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = D == 3 ? k / 9 - 1 : 0;
-        int c[3];
-        dev::decode_key<D>(keys_m[i], m, R0, R1, c);
-        const int ext[3] = {R0 << m, R1 << m, R2 << m};
-        int nc[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
-        if (nc[0] < 0 || nc[0] >= ext[0] || nc[1] < 0 || nc[1] >= ext[1]) continue;
-        if (D == 3 && (nc[2] < 0 || nc[2] >= ext[2])) continue;
-        const uint32_t kn = dev::encode_key<D>(nc, m, R0, R1);
-        const int64_t jn = dev::lower_bound_u32(keys_m, n_m, kn);
-        if (jn < n_m && keys_m[jn] == kn) continue;
-        int pc[3] = {nc[0] >> 1, nc[1] >> 1, D == 3 ? nc[2] >> 1 : 0};
-        const uint32_t kp = dev::encode_key<D>(pc, m - 1, R0, R1);
-        const int64_t jp = dev::lower_bound_u32(keys_p, n_p, kp);
-        if (jp < n_p && keys_p[jp] == kp && leaf_p[jp]) pm_p[jp] = 2;
-        else atomicOr(err, 1u);
-    }
+    AGAL_GRID_STRIDE(t, n_m * (D == 3 ? 26 : 8))
+    ripple_item<D>(keys_m, n_m, pm_m, m, keys_p, n_p, leaf_p, pm_p, R0, R1, R2, err, t);
 }
 
-// Marked blocks of level m: become parents (leaf 0, export mark = pass mark)
-// and their keys are compacted in order into mk.
 __global__ void k_mark_parents(const uint32_t *keys, const uint8_t *pm, const uint32_t *pos, int64_t n, uint8_t *leaf,
                                uint8_t *mark, uint32_t *mk) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint8_t p = pm[i];
-        if (!p) continue;
-        leaf[i] = 0;
-        mark[i] = p;
-        mk[pos[i]] = keys[i];
-    }
+    AGAL_GRID_STRIDE(i, n) mark_parents_item(keys, pm, pos, leaf, mark, mk, i);
 }
 
-// Existing blocks of level m+1 move to their place in the merged list.
 template <int CELLS>
 __global__ void k_merge_old(const uint32_t *keys, const uint8_t *leaf, const uint8_t *mark, const uint8_t *cf,
                             int64_t n_old, const uint32_t *mk, int64_t n_mk, int D, uint32_t *nkeys, uint8_t *nleaf,
                             uint8_t *nmark, uint8_t *ncf) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_old; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t k = keys[i];
-        const int64_t r = dev::lower_bound_u32(mk, n_mk, k >> D);
-        const int64_t p = i + (r << D);
-        nkeys[p] = k;
-        nleaf[p] = leaf[i];
-        nmark[p] = mark[i];
-        if (ncf)
-            for (int c = 0; c < CELLS; ++c) ncf[p * CELLS + c] = cf[i * CELLS + c];
-    }
+    AGAL_GRID_STRIDE(i, n_old) merge_old_item<CELLS>(keys, leaf, mark, cf, mk, n_mk, D, nkeys, nleaf, nmark, ncf, i);
 }
 
-// Children of the marked parents, placed after the existing keys below them.
 template <int CELLS>
 __global__ void k_children(const uint32_t *mk, int64_t n_mk, const uint32_t *keys_old, int64_t n_old, int D,
                            uint32_t *nkeys, uint8_t *nleaf, uint8_t *nmark, uint8_t *ncf) {
-    const int64_t total = n_mk << D;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t pi = t >> D;
-        const uint32_t ci = (uint32_t)(t & ((1 << D) - 1));
-        const uint32_t parent = mk[pi];
-        const int64_t below = dev::lower_bound_u32(keys_old, n_old, parent << D);
-        const int64_t p = below + t;
-        nkeys[p] = (parent << D) | ci;
-        nleaf[p] = 1;
-        nmark[p] = 0;
-        if (ncf)
-            for (int c = 0; c < CELLS; ++c) ncf[p * CELLS + c] = 0;
-    }
+    AGAL_GRID_STRIDE(t, n_mk << D) children_item<CELLS>(mk, keys_old, n_old, D, nkeys, nleaf, nmark, ncf, t);
 }
 
 __global__ void k_iota_u32(uint32_t *p, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = (uint32_t)i;
+    AGAL_GRID_STRIDE(i, n) p[i] = (uint32_t)i;
 }
 
 unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 16384) {
