@@ -5,7 +5,10 @@ forest level by level near the wall, compute the link fractions q and run
 the adjoint for a weighted sum of q -- every row of the hot path, on
 synthetic seeded geometry (see geomgen).  Prints ONE JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--config C1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--config C1|C2|C4] [--no-cpu-baseline]
+
+--config C4 times the batched form (64 bodies, one graph launch, forward and
+adjoint) against the same bodies through the single-body calls.
 
 `value` is cell-face tests per second: the number of (cell, face) pairs the
 bins put in front of the cells (tested cells of every pass against the faces
@@ -168,6 +171,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="C1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (3 times) and exit: the reference kernel that "
+                         "scales the FETCH_SIZE / WRITE_SIZE counters into bytes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -180,6 +186,17 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}), flush=True)
+        return
+    if args.config.upper() == "C4":
+        return bench_batch(args)
     wl = geomgen.workload(args.config)
     dim, Q = wl.dim, wl.lattice
     print(f"bench: {wl.name} faces={len(wl.faces)} roots={wl.roots[:dim]} levels={wl.levels} bins={wl.bins} "
@@ -281,6 +298,122 @@ def main():
         out["cpu_baseline"] = cb
     else:
         out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """64 star bodies (subdivision 3..7, D3Q27) as one graph launch (forward q + adjoint), against the
+    same bodies run one after another through the single-body calls at the plan's bin densities."""
+    import torch
+    import geomgen
+    import paper_2502_16310_amd as agal
+
+    dev = torch.device("cuda", 0)
+    draws = geomgen.batch_draws(64)
+    wls = [geomgen.batch_body(d) for d in draws]
+    ts = [(torch.from_numpy(w.vertices).to(dev), torch.from_numpy(w.faces).to(dev)) for w in wls]
+    F_total = sum(len(w.faces) for w in wls)
+    print(f"bench: C4 batch of {len(wls)} star bodies, {F_total} faces", file=sys.stderr, flush=True)
+    cfgs = [agal.NearWallConfig(dim=3, roots=w.roots, n_levels=w.levels, bins=0, lattice=w.lattice,
+                                d_spec=list(w.d_spec()[:w.levels])) for w in wls]
+    t0 = time.perf_counter()
+    bt = agal.Batch([(v, f, c) for (v, f), c in zip(ts, cfgs)], tune_bins=True, tune_grid=True, with_adjoint=True)
+    plan_s = time.perf_counter() - t0
+    bins = [bt.bins(i) for i in range(len(wls))]
+    print(f"bench: plan {plan_s:.1f} s, grid {bt.workgroups_per_cu} workgroups/CU, bins {sorted(set(bins))}",
+          file=sys.stderr, flush=True)
+    bt.run()
+    bt.status()
+    weights = []
+    for i, w in enumerate(wls):
+        n = bt.links(i)[0].numel()
+        wt = torch.from_numpy(geomgen.weights(max(1, n * w.lattice), 2 + i)[: n * w.lattice].reshape(n, w.lattice))
+        weights.append(wt.to(dev))
+        bt.set_grad_q(i, weights[-1])
+
+    # single-body path, body after body, same bins and adjoint weights
+    ctx = agal.agal_context_create()
+    stream = torch.cuda.current_stream().cuda_stream
+    grads = [torch.zeros_like(v) for v, _ in ts]
+    descs = [agal.forest_desc(3, w.roots, w.levels, [float(x) for x in w.d_spec()], w.lo, w.hi) for w in wls]
+
+    def plain_all(keep=False):
+        kept = []
+        for i, w in enumerate(wls):
+            v, f = ts[i]
+            g = agal.agal_import_faces(ctx, 3, v.data_ptr(), v.shape[0], f.data_ptr(), f.shape[0], stream)
+            b = agal.agal_bin_faces(g, w.lo, w.hi, bins[i], stream)
+            fo = agal.agal_near_wall_refine(g, b, descs[i], stream)
+            lk = agal.agal_link_fractions(g, b, fo, w.lattice, stream)
+            grads[i].zero_()
+            agal.agal_link_fractions_backward(g, lk, weights[i].data_ptr(), grads[i].data_ptr(), stream)
+            hs = ((lk, agal.agal_destroy_links), (fo, agal.agal_destroy_forest), (b, agal.agal_destroy_bins),
+                  (g, agal.agal_destroy_geom))
+            if keep:
+                kept.append((g, b, fo, lk))
+            else:
+                for h, fn in hs:
+                    fn(h)
+        return kept
+
+    for _ in range(args.warmup):
+        plain_all()
+        bt.run()
+    torch.cuda.synchronize()
+    # workload size per body from the single-body results (identical to the batch's)
+    T = 0
+    kept = plain_all(keep=True)
+    torch.cuda.synchronize()
+    n_nodes = 0
+    for i, (w, (g, b, fo, lk)) in enumerate(zip(wls, kept)):
+        off_p, _, nb, P = agal.agal_bins_view(b)
+        off = agal.device_copy(off_p, nb + 1, torch.int32).cpu().numpy().view(np.uint32)
+        levels = []
+        for l in range(w.levels + 1):
+            kp, _, mp, _, n = agal.agal_forest_level_view(fo, l)
+            levels.append({"keys": agal.device_copy(kp, n, torch.int32).cpu().numpy().view(np.uint32),
+                           "mark": agal.device_copy(mp, n, torch.uint8).cpu().numpy()})
+        tf, tq = cell_face_tests(off, bins[i], 3, levels, w.roots, w.levels, [float(x) for x in w.d_spec()],
+                                 w.lo, w.hi)
+        T += sum(tf) + tq
+        n_nodes += agal.agal_links_view(lk)[3]
+        for h, fn in ((lk, agal.agal_destroy_links), (fo, agal.agal_destroy_forest), (b, agal.agal_destroy_bins),
+                      (g, agal.agal_destroy_geom)):
+            fn(h)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plain_all()
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+
+    agal.agal_profile_read(bt.ctx.h)
+    agal.agal_profile_enable(bt.ctx.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bt.run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    agal.agal_profile_enable(bt.ctx.h, False)
+    prof = agal.agal_profile_read(bt.ctx.h)
+    bt.status()
+    graph_us = 1e3 * prof["batch_graph"][1] / prof["batch_graph"][0] if "batch_graph" in prof else None
+
+    out = {
+        "metric": METRIC, "value": T / (ms * 1e-3), "unit": "cell-face tests/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "C4: 64 star bodies, icosphere subdivisions 3-7, roots 16^3 (3 levels) or 32^3 "
+                               "(4 levels), D3Q27, forward q + adjoint, one graph launch",
+                   "faces": F_total, "bodies": len(wls), "global_batch": len(wls), "seq_len": 0,
+                   "parallelism": "none"},
+        "batch_graph_ms": ms, "batch_graph_event_us": graph_us, "plain_sum_ms": plain_ms,
+        "speedup_vs_plain": plain_ms / ms, "plan_s": plan_s, "workgroups_per_cu": bt.workgroups_per_cu,
+        "bins_per_body": bins, "cell_face_tests": T, "boundary_nodes": n_nodes,
+        "roofline": None, "cpu_baseline": None,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -52,6 +52,7 @@ typedef struct agal_geom_t *agal_geom;
 typedef struct agal_bins_t *agal_bins;
 typedef struct agal_forest_t *agal_forest;
 typedef struct agal_links_t *agal_links;
+typedef struct agal_batch_t *agal_batch;
 
 /* Optional device allocator.  alloc returns device memory usable on `stream`
  * (or NULL on failure); free releases it in stream order.  A NULL allocator
@@ -187,6 +188,71 @@ AGAL_API agal_status agal_links_view(agal_links l, const uint64_t **d_node_key, 
  * Errors: AGAL_ESTATE when `l` was not computed from `g`. */
 AGAL_API agal_status agal_link_fractions_backward(agal_geom g, agal_links l, const float *d_grad_q,
                                                   float *d_grad_vertices, void *stream);
+
+/* ---- batched form: many bodies, one graph launch --------------------------
+ * Each body is a complete near-wall problem (import, bins, refinement, link
+ * fractions and optionally the adjoint) with its own geometry, forest, bins
+ * and lattice.  A plan sizes every body once with the calls above, reserves
+ * device capacity for all intermediate arrays (measured sizes times
+ * 1 + capacity_margin), and captures one hipGraph of persistent kernels that
+ * process all bodies together; every size stays on the device.  Each run is a
+ * single hipGraphLaunch with no host synchronisation.  Flags and link
+ * fractions are bit-identical to the single-body calls on the same input.
+ *
+ * Body inputs are device pointers that must stay valid and keep their shapes
+ * while the plan lives; their values may change between runs (the plan
+ * re-reads them).  If a run outgrows a capacity, the arrays concerned stop
+ * growing, the results of that run are incomplete and agal_batch_status
+ * returns AGAL_ECAPACITY: create a new plan.
+ */
+typedef struct agal_body_desc {
+    int dim;
+    const float *d_vertices;       /* n_vertices x dim FP32 */
+    int64_t n_vertices;
+    const int32_t *d_faces;        /* n_faces x dim int32; NULL: coordinate list */
+    int64_t n_faces;
+    agal_forest_desc forest;       /* forest.d_spec is read during plan creation */
+    int lattice;
+    int32_t bins;                  /* bins per axis; <= 0: chosen by the tuner */
+} agal_body_desc;
+
+typedef struct agal_tune_opts {
+    int tune_bins;                 /* 1: time candidate bin densities per face-count bucket */
+    int tune_grid;                 /* 1: time persistent grids of 1, 2, 4, 8 workgroups per CU */
+    int with_adjoint;              /* 1: the graph ends with the adjoint of every body */
+    float capacity_margin;         /* extra fraction of each measured size (0: 0.25) */
+    const char *cache_path;        /* text file of tuned bin densities, read and extended; NULL: none */
+} agal_tune_opts;
+
+/* Plans and captures the batch (synchronises `stream`; runs every body once
+ * on it).  n_bodies in [1, 256]; bodies of one plan share the dimension.
+ * Errors: as the single-body calls for each body; AGAL_EINVAL for an empty or
+ * oversized batch. */
+AGAL_API agal_status agal_batch_plan_create(agal_context ctx, int n_bodies, const agal_body_desc *bodies,
+                                            const agal_tune_opts *opts, void *stream, agal_batch *out);
+/* Enqueues one run (one graph launch) on `stream`. */
+AGAL_API agal_status agal_batch_run(agal_batch b, void *stream);
+/* Synchronises `stream`, reads the per-body sizes of the last run, and
+ * returns AGAL_ECAPACITY if a capacity overflowed, AGAL_EINVAL if an input was
+ * invalid (non-finite coordinate or index out of range), AGAL_ESTATE if a
+ * forest lost 2:1 balance. */
+AGAL_API agal_status agal_batch_status(agal_batch b, void *stream);
+/* Results of body `body` after agal_batch_status: node keys, q and faces as
+ * agal_links_view; *d_grad_q is where the caller writes the n_nodes x Q
+ * adjoint input before a run (plans with the adjoint; capacity
+ * *node_capacity rows), *d_grad_vertices the n_vertices x dim result (zeroed
+ * by every run). */
+AGAL_API agal_status agal_batch_body_view(agal_batch b, int body, const uint64_t **d_node_key, const float **d_q,
+                                          const int32_t **d_face, int64_t *n_nodes, int *Q, float **d_grad_q,
+                                          const float **d_grad_vertices, int64_t *node_capacity, int32_t *bins);
+/* Forest level of body `body` after agal_batch_status (layout as
+ * agal_forest_level_view). */
+AGAL_API agal_status agal_batch_level_view(agal_batch b, int body, int level, const uint32_t **d_keys,
+                                           const uint8_t **d_leaf, const uint8_t **d_mark,
+                                           const uint8_t **d_cell_flag, int64_t *n_blocks);
+/* Persistent grid chosen by the plan (workgroups per CU). */
+AGAL_API agal_status agal_batch_info(agal_batch b, int *n_bodies, int *workgroups_per_cu);
+AGAL_API void agal_destroy_batch(agal_batch b);
 
 /* ---- kernel timing -------------------------------------------------------
  * With profiling enabled, every kernel the library launches with `ctx` is

@@ -41,10 +41,24 @@ class _Allocator(C.Structure):
                 ("free", C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p))]
 
 
+class _BodyDesc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("d_vertices", C.c_void_p), ("n_vertices", C.c_int64), ("d_faces", C.c_void_p),
+                ("n_faces", C.c_int64), ("forest", _ForestDesc), ("lattice", C.c_int), ("bins", C.c_int32)]
+
+
+class _TuneOpts(C.Structure):
+    _fields_ = [("tune_bins", C.c_int), ("tune_grid", C.c_int), ("with_adjoint", C.c_int),
+                ("capacity_margin", C.c_float), ("cache_path", C.c_char_p)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
                           "or `python paper_2502_16310_amd/build.py`")
+    # torch ships its own HIP runtime under the same soname; loading torch first
+    # makes this library bind to that copy instead of starting a second runtime
+    # in the process (which then finds no device)
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P, vp = C.c_void_p, C.c_void_p
     i64, i32 = C.c_int64, C.c_int32
@@ -66,6 +80,14 @@ def _load():
         "agal_profile_enable": [P, C.c_int],
         "agal_profile_read": [P, C.c_int, C.POINTER(C.c_char_p), C.POINTER(i64), C.POINTER(C.c_double),
                               C.POINTER(C.c_int)],
+        "agal_batch_plan_create": [P, C.c_int, C.POINTER(_BodyDesc), C.POINTER(_TuneOpts), vp, PP],
+        "agal_batch_run": [P, vp],
+        "agal_batch_status": [P, vp],
+        "agal_batch_body_view": [P, C.c_int, PP, PP, PP, C.POINTER(i64), C.POINTER(C.c_int), PP, PP,
+                                 C.POINTER(i64), C.POINTER(i32)],
+        "agal_batch_level_view": [P, C.c_int, C.c_int, PP, PP, PP, PP, C.POINTER(i64)],
+        "agal_batch_info": [P, C.POINTER(C.c_int), C.POINTER(C.c_int)],
+        "agal_destroy_batch": [P],
         "agal_destroy_geom": [P],
         "agal_destroy_bins": [P],
         "agal_destroy_forest": [P],
@@ -78,7 +100,7 @@ def _load():
         fn.argtypes = args
         fn.restype = C.c_int
     for name in ("agal_context_destroy", "agal_destroy_geom", "agal_destroy_bins", "agal_destroy_forest",
-                 "agal_destroy_links"):
+                 "agal_destroy_links", "agal_destroy_batch"):
         getattr(lib, name).restype = None
     lib.agal_status_string.restype = C.c_char_p
     lib.agal_last_error.restype = C.c_char_p
@@ -225,6 +247,71 @@ def agal_profile_read(ctx, max_entries: int = 64):
     return {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(n.value)}
 
 
+def body_desc(dim: int, d_vertices: int, n_vertices: int, d_faces: Optional[int], n_faces: int,
+              forest: _ForestDesc, lattice: int, bins: int = 0) -> _BodyDesc:
+    b = _BodyDesc()
+    b.dim, b.d_vertices, b.n_vertices = dim, d_vertices, n_vertices
+    b.d_faces, b.n_faces = d_faces or None, n_faces
+    b.forest, b.lattice, b.bins = forest, int(lattice), int(bins)
+    b._keep = forest._keep
+    return b
+
+
+def tune_opts(tune_bins: bool = True, tune_grid: bool = True, with_adjoint: bool = False,
+              capacity_margin: float = 0.0, cache_path: Optional[str] = None) -> _TuneOpts:
+    o = _TuneOpts()
+    o.tune_bins, o.tune_grid, o.with_adjoint = int(tune_bins), int(tune_grid), int(with_adjoint)
+    o.capacity_margin = float(capacity_margin)
+    o.cache_path = cache_path.encode() if cache_path else None
+    return o
+
+
+def agal_batch_plan_create(ctx, bodies: Sequence[_BodyDesc], opts: Optional[_TuneOpts] = None,
+                           stream: int = 0) -> C.c_void_p:
+    arr = (_BodyDesc * len(bodies))(*bodies)
+    out = C.c_void_p()
+    _check(_lib.agal_batch_plan_create(_h(ctx), len(bodies), arr, C.byref(opts) if opts is not None else None,
+                                       stream or None, C.byref(out)), "agal_batch_plan_create")
+    return out
+
+
+def agal_batch_run(batch, stream: int = 0):
+    _check(_lib.agal_batch_run(_h(batch), stream or None), "agal_batch_run")
+
+
+def agal_batch_status(batch, stream: int = 0):
+    _check(_lib.agal_batch_status(_h(batch), stream or None), "agal_batch_status")
+
+
+def agal_batch_body_view(batch, body: int):
+    """(node_key, q, face, n_nodes, Q, grad_q, grad_vertices, node_capacity, bins)"""
+    k, q, f, gq, gv = (C.c_void_p() for _ in range(5))
+    n, cap = C.c_int64(), C.c_int64()
+    Q, B = C.c_int(), C.c_int32()
+    _check(_lib.agal_batch_body_view(_h(batch), int(body), C.byref(k), C.byref(q), C.byref(f), C.byref(n),
+                                     C.byref(Q), C.byref(gq), C.byref(gv), C.byref(cap), C.byref(B)),
+           "agal_batch_body_view")
+    return k.value, q.value, f.value, n.value, Q.value, gq.value, gv.value, cap.value, B.value
+
+
+def agal_batch_level_view(batch, body: int, level: int):
+    k, lf, mk, cf = C.c_void_p(), C.c_void_p(), C.c_void_p(), C.c_void_p()
+    n = C.c_int64()
+    _check(_lib.agal_batch_level_view(_h(batch), int(body), int(level), C.byref(k), C.byref(lf), C.byref(mk),
+                                      C.byref(cf), C.byref(n)), "agal_batch_level_view")
+    return k.value, lf.value, mk.value, cf.value, n.value
+
+
+def agal_batch_info(batch):
+    nb, w = C.c_int(), C.c_int()
+    _check(_lib.agal_batch_info(_h(batch), C.byref(nb), C.byref(w)), "agal_batch_info")
+    return nb.value, w.value
+
+
+def agal_destroy_batch(h):
+    _lib.agal_destroy_batch(_h(h))
+
+
 def agal_destroy_geom(h):
     _lib.agal_destroy_geom(_h(h))
 
@@ -249,9 +336,9 @@ def agal_last_error() -> str:
     return _lib.agal_last_error().decode(errors="replace")
 
 
-from .torch_api import (Bins, Context, Forest, Geometry, LinkFractions, Links, NearWallConfig,  # noqa: E402
-                        device_copy, near_wall)
+from .torch_api import (Batch, Bins, Context, Forest, Geometry, LinkFractions, Links, NearWallConfig,  # noqa: E402
+                        device_copy, device_write, near_wall)
 
 __all__ = [n for n in dir() if n.startswith("agal_")] + [
-    "AgalError", "Context", "Geometry", "Bins", "Forest", "Links", "LinkFractions", "NearWallConfig", "near_wall",
-    "forest_desc", "device_copy", "LIB_PATH"]
+    "AgalError", "Batch", "device_write", "Context", "Geometry", "Bins", "Forest", "Links", "LinkFractions", "NearWallConfig", "near_wall",
+    "forest_desc", "body_desc", "tune_opts", "device_copy", "LIB_PATH"]

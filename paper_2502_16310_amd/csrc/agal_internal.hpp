@@ -8,6 +8,9 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <map>
+#include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "agal.h"
@@ -32,13 +35,28 @@ agal_status fail(agal_status s, const char *fmt, ...) __attribute__((format(prin
         if (s__ != AGAL_OK) return s__;             \
     } while (0)
 
-// Device memory through the context's allocator (user callback or the HIP
-// stream-ordered pool).  Every allocation is stream ordered.
+// Device memory through the context's allocator: the user's callbacks, or a
+// caching layer over the HIP stream-ordered pool.  Every allocation is stream
+// ordered.  The cache keeps released blocks by size class and hands a block
+// out again only to an allocation on the stream it was released on (work on
+// one stream runs in order, so no event is needed); blocks beyond kCacheCap
+// bytes go back to the pool.
 struct Allocator {
     agal_allocator user{};
     bool has_user = false;
+    static constexpr size_t kCacheCap = size_t(16) << 30;
+    struct Block {
+        void *p;
+        hipStream_t s;
+    };
+    mutable std::mutex mu;
+    mutable std::multimap<size_t, Block> cached;                    // size class -> released block
+    mutable std::unordered_map<void *, size_t> live;                // block -> its size class
+    mutable size_t cached_bytes = 0;
+    static size_t size_class(size_t bytes);
     void *alloc(size_t bytes, hipStream_t s) const;
     void release(void *p, hipStream_t s) const;
+    void drain() const;   // returns every cached block (device synchronised first)
 };
 
 template <class T>

@@ -48,7 +48,7 @@ __device__ __forceinline__ float fabsf_(float a) { return a < 0.0f ? -a : a; }
 __device__ __forceinline__ int bin_of(float x, float lo, float s, int B) {
     float t = (x - lo) * s;
     float f = floorf(t);
-    if (f < 0.0f) return 0;
+    if (!(f >= 0.0f)) return 0;   // also a NaN coordinate: stays inside the grid
     if (f > (float)(B - 1)) return B - 1;
     return (int)f;
 }

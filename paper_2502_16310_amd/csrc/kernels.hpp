@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <climits>
 
 #include "device.hpp"
 
@@ -363,11 +364,12 @@ template <int CELLS>
 __device__ __forceinline__ void merge_old_item(const uint32_t *keys, const uint8_t *leaf, const uint8_t *mark,
                                                const uint8_t *cf, const uint32_t *mk, int64_t n_mk, int D,
                                                uint32_t *nkeys, uint8_t *nleaf, uint8_t *nmark, uint8_t *ncf,
-                                               int64_t i) {
+                                               int64_t i, int64_t cap = INT64_MAX) {
     {
         const uint32_t k = keys[i];
         const int64_t r = dev::lower_bound_u32(mk, n_mk, k >> D);
         const int64_t p = i + (r << D);
+        if (p >= cap) return;   // batched plans: out of planned capacity (reported by the count step)
         nkeys[p] = k;
         nleaf[p] = leaf[i];
         nmark[p] = mark[i];
@@ -380,13 +382,14 @@ __device__ __forceinline__ void merge_old_item(const uint32_t *keys, const uint8
 template <int CELLS>
 __device__ __forceinline__ void children_item(const uint32_t *mk, const uint32_t *keys_old, int64_t n_old, int D,
                                               uint32_t *nkeys, uint8_t *nleaf, uint8_t *nmark, uint8_t *ncf,
-                                              int64_t t) {
+                                              int64_t t, int64_t cap = INT64_MAX) {
     {
         const int64_t pi = t >> D;
         const uint32_t ci = (uint32_t)(t & ((1 << D) - 1));
         const uint32_t parent = mk[pi];
         const int64_t below = dev::lower_bound_u32(keys_old, n_old, parent << D);
         const int64_t p = below + t;
+        if (p >= cap) return;
         nkeys[p] = (parent << D) | ci;
         nleaf[p] = 1;
         nmark[p] = 0;
@@ -420,7 +423,8 @@ struct LinkArgs {
 
 // One wave: finest-level blocks first .. first + 64/4^D - 1 of A.  `out` places
 // each block's nodes: out.rows(blk, count) returns the first staging row of the
-// block (and records the count); rows are written in cell order.
+// block (and records the count), or -1 when it has no room; rows are written in
+// cell order.
 template <int D, int Q, class Out>
 __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t first, Out &out) {
     constexpr int CELLS = D == 3 ? 64 : 16;
@@ -715,7 +719,7 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
     int64_t row0 = 0;
     if (valid && cell == 0) row0 = out.rows(blk, (uint32_t)__popcll(bm));
     row0 = __shfl(row0, sub * CELLS, 64);
-    if (has) {
+    if (has && row0 >= 0) {   // a negative first row: the output policy ran out of capacity
         const int64_t node = row0 + __popcll(bm & ((1ull << cell) - 1));
         A.node_key[node] = (uint64_t)key * CELLS + (uint64_t)cell;
         float *qr = A.q + node * Q;

@@ -24,13 +24,41 @@ uint64_t next_handle_id() {
     return next.fetch_add(1);
 }
 
+// 256-byte granules up to 4 KiB, then eight classes per octave (at most 12.5 %
+// slack).
+size_t Allocator::size_class(size_t bytes) {
+    if (bytes <= 4096) return (bytes + 255) & ~size_t(255);
+    int e = 63 - __builtin_clzll((unsigned long long)bytes);
+    const size_t step = size_t(1) << (e - 3);
+    return (bytes + step - 1) & ~(step - 1);
+}
+
 void *Allocator::alloc(size_t bytes, hipStream_t s) const {
     if (has_user) return user.alloc(user.ctx, bytes, (void *)s);
-    void *p = nullptr;
-    if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
+    const size_t cls = size_class(bytes);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto range = cached.equal_range(cls);
+        for (auto it = range.first; it != range.second; ++it)
+            if (it->second.s == s) {
+                void *p = it->second.p;
+                cached.erase(it);
+                cached_bytes -= cls;
+                live[p] = cls;
+                return p;
+            }
     }
+    void *p = nullptr;
+    if (hipMallocAsync(&p, cls, s) != hipSuccess) {
+        (void)hipGetLastError();
+        drain();   // give cached blocks back to the pool and try once more
+        if (hipMallocAsync(&p, cls, s) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    live[p] = cls;
     return p;
 }
 
@@ -40,7 +68,31 @@ void Allocator::release(void *p, hipStream_t s) const {
         user.free(user.ctx, p, (void *)s);
         return;
     }
-    (void)hipFreeAsync(p, s);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = live.find(p);
+    if (it == live.end()) {
+        (void)hipFreeAsync(p, s);
+        return;
+    }
+    const size_t cls = it->second;
+    live.erase(it);
+    if (cached_bytes + cls > kCacheCap) {
+        (void)hipFreeAsync(p, s);
+        return;
+    }
+    cached.emplace(cls, Block{p, s});
+    cached_bytes += cls;
+}
+
+void Allocator::drain() const {
+    if (has_user) return;
+    std::lock_guard<std::mutex> lk(mu);
+    if (cached.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (auto &kv : cached) (void)hipFree(kv.second.p);
+    (void)hipGetLastError();
+    cached.clear();
+    cached_bytes = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -287,6 +339,7 @@ agal_status agal_context_create(const agal_allocator *alloc, agal_context *out) 
 
 void agal_context_destroy(agal_context ctx) {
     if (!ctx) return;
+    ctx->mem.drain();
     for (auto &r : ctx->records) {
         (void)hipEventDestroy(r.start);
         (void)hipEventDestroy(r.stop);

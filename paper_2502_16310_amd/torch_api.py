@@ -13,10 +13,12 @@ from typing import List, Optional, Sequence, Tuple
 
 import torch
 
-from . import (AgalError, agal_bin_faces, agal_bins_view, agal_context_create, agal_context_destroy,
-               agal_destroy_bins, agal_destroy_forest, agal_destroy_geom, agal_destroy_links, agal_forest_info,
-               agal_forest_level_view, agal_geom_view, agal_import_faces, agal_link_fractions,
-               agal_link_fractions_backward, agal_links_view, agal_near_wall_refine, forest_desc)
+from . import (AgalError, agal_batch_body_view, agal_batch_info, agal_batch_level_view, agal_batch_plan_create,
+               agal_batch_run, agal_batch_status, agal_bin_faces, agal_bins_view, agal_context_create,
+               agal_context_destroy, agal_destroy_batch, agal_destroy_bins, agal_destroy_forest, agal_destroy_geom,
+               agal_destroy_links, agal_forest_info, agal_forest_level_view, agal_geom_view, agal_import_faces,
+               agal_link_fractions, agal_link_fractions_backward, agal_links_view, agal_near_wall_refine, body_desc,
+               forest_desc, tune_opts)
 
 _hip = None
 
@@ -42,6 +44,16 @@ def device_copy(ptr: int, numel: int, dtype: torch.dtype, device=None) -> torch.
         if rc != 0:
             raise AgalError(3, f"hipMemcpyAsync failed with code {rc}")
     return t
+
+
+def device_write(ptr: int, src: torch.Tensor):
+    """Copy a contiguous device tensor to device address `ptr` (stream ordered)."""
+    src = src.contiguous()
+    if src.numel():
+        rc = _hiprt().hipMemcpyAsync(ptr, src.data_ptr(), src.numel() * src.element_size(), 3,
+                                     current_stream() or None)
+        if rc != 0:
+            raise AgalError(3, f"hipMemcpyAsync failed with code {rc}")
 
 
 class Context:
@@ -225,3 +237,71 @@ class LinkFractions(torch.autograd.Function):
         if g_q is not None:
             links.backward(g_q.contiguous(), grad_v)
         return grad_v, None, None, None
+
+
+class Batch:
+    """Many bodies, one graph launch per run.
+
+    bodies: sequence of (vertices, faces or None, NearWallConfig); a config with
+    bins <= 0 lets the plan's tuner choose the bin density.  The tensors must
+    stay alive (and keep their shapes) while the batch lives; their values may
+    change between runs."""
+
+    def __init__(self, bodies, tune_bins: bool = True, tune_grid: bool = True, with_adjoint: bool = False,
+                 capacity_margin: float = 0.0, cache_path: Optional[str] = None, ctx: Optional[Context] = None):
+        self.ctx = ctx or default_context()
+        self._inputs = []
+        descs = []
+        for v, f, cfg in bodies:
+            v = v.contiguous()
+            f = None if f is None else f.to(torch.int32).contiguous()
+            self._inputs.append((v, f))
+            fd = forest_desc(cfg.dim, cfg.roots, cfg.n_levels, cfg.distances(), cfg.lo, cfg.hi)
+            descs.append(body_desc(cfg.dim, v.data_ptr(), v.shape[0], None if f is None else f.data_ptr(),
+                                   f.shape[0] if f is not None else v.shape[0] // cfg.dim, fd, cfg.lattice,
+                                   cfg.bins))
+        self.cfgs = [b[2] for b in bodies]
+        opts = tune_opts(tune_bins, tune_grid, with_adjoint, capacity_margin, cache_path)
+        self.h = agal_batch_plan_create(self.ctx.h, descs, opts, current_stream())
+        self.n_bodies, self.workgroups_per_cu = agal_batch_info(self.h)
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None:
+            agal_destroy_batch(self.h)
+            self.h = None
+
+    def run(self):
+        agal_batch_run(self.h, current_stream())
+
+    def status(self):
+        agal_batch_status(self.h, current_stream())
+
+    def bins(self, body: int) -> int:
+        return agal_batch_body_view(self.h, body)[8]
+
+    def links(self, body: int):
+        """(node_key int64, q (n, Q) float32, face (n, Q) int32) of the last run (after status())."""
+        k, q, f, n, Q, _, _, _, _ = agal_batch_body_view(self.h, body)
+        return (device_copy(k, n, torch.int64), device_copy(q, n * Q, torch.float32).view(n, Q),
+                device_copy(f, n * Q, torch.int32).view(n, Q))
+
+    def level(self, body: int, level: int):
+        k, lf, mk, cf, n = agal_batch_level_view(self.h, body, level)
+        cells = 4 ** self.cfgs[body].dim
+        return {"keys": device_copy(k, n, torch.int32), "leaf": device_copy(lf, n, torch.uint8),
+                "mark": device_copy(mk, n, torch.uint8),
+                "cell_flag": None if not cf else device_copy(cf, n * cells, torch.uint8).view(n, cells)}
+
+    def set_grad_q(self, body: int, grad_q: torch.Tensor):
+        """Adjoint input of `body` for the next run: (n_nodes, Q) float32, rows in node order."""
+        _, _, _, n, Q, gq, _, cap, _ = agal_batch_body_view(self.h, body)
+        if grad_q.shape[0] > cap or (grad_q.numel() and grad_q.shape[1] != Q):
+            raise AgalError(1, f"grad_q of shape {tuple(grad_q.shape)} does not fit ({cap}, {Q})")
+        if not gq:
+            raise AgalError(1, "the batch was planned without the adjoint")
+        device_write(gq, grad_q.to(torch.float32))
+
+    def grad_vertices(self, body: int) -> torch.Tensor:
+        _, _, _, _, _, _, gv, _, _ = agal_batch_body_view(self.h, body)
+        v, _ = self._inputs[body]
+        return device_copy(gv, v.numel(), torch.float32).view_as(v)
