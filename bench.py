@@ -211,17 +211,23 @@ def main():
     w_host = geomgen.weights(4 ** dim * 4 * 10 ** 6, 2)  # enough slots; first n*Q used
     w_dev = None
 
-    def step(keep=False):
+    def step(keep=False, ev=None):
         nonlocal w_dev
         g = agal.agal_import_faces(ctx, dim, v.data_ptr(), v.shape[0], f.data_ptr(), f.shape[0], stream)
+        if ev:
+            ev[0].record()
         b = agal.agal_bin_faces(g, wl.lo[:dim], wl.hi[:dim], wl.bins, stream)
         fo = agal.agal_near_wall_refine(g, b, desc, stream)
         lk = agal.agal_link_fractions(g, b, fo, Q, stream)
+        if ev:
+            ev[1].record()
         n_nodes = agal.agal_links_view(lk)[3]
         if w_dev is None or w_dev.numel() < n_nodes * Q:
             w_dev = torch.from_numpy(w_host[: max(1, n_nodes * Q)].copy()).to(dev)
         grad.zero_()
         agal.agal_link_fractions_backward(g, lk, w_dev.data_ptr(), grad.data_ptr(), stream)
+        if ev:
+            ev[2].record()
         if keep:
             return g, b, fo, lk
         for h, fn in ((lk, agal.agal_destroy_links), (fo, agal.agal_destroy_forest), (b, agal.agal_destroy_bins),
@@ -252,23 +258,32 @@ def main():
                   (g, agal.agal_destroy_geom)):
         fn(h)
 
-    # timed region: K whole steps, per-kernel HIP events recorded on the launch stream
+    # timed region: K whole steps.  HIP events on the launch stream (torch's
+    # current stream) bracket the near-wall pass (bins -> refinement -> q,
+    # in-pass host synchronisations included) and the adjoint of every step;
+    # the library records events around each of its kernels.
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     agal.agal_profile_read(ctx)
     agal.agal_profile_enable(ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    for k in range(args.steps):
+        step(ev=evs[k])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     agal.agal_profile_enable(ctx, False)
     prof = agal.agal_profile_read(ctx)
     ms = (t1 - t0) * 1e3 / args.steps
+    pass_ev = sorted(e[0].elapsed_time(e[1]) for e in evs)
+    grad_ev = sorted(e[1].elapsed_time(e[2]) for e in evs)
+    pass_ms_median = pass_ev[len(pass_ev) // 2]
+    grad_step_median = grad_ev[len(grad_ev) // 2]
+    copy_gbs = copy_bandwidth(torch, dev)
     kern = {k: {"launches_per_step": n / args.steps, "ms_per_step": t / args.steps, "avg_us": 1e3 * t / n}
             for k, (n, t) in prof.items()}
     pass_kernels = ("bin_count", "bin_scatter", "bin_canon", "bin_canon_big", "scan_exclusive", "flag_sat",
                     "balance_ripple", "child_gen", "q_links", "q_compact")
-    pass_ms = sum(kern[k]["ms_per_step"] for k in pass_kernels if k in kern)
+    pass_kernel_ms = sum(kern[k]["ms_per_step"] for k in pass_kernels if k in kern)
     grad_ms = kern.get("q_adjoint", {}).get("ms_per_step", 0.0)
     dominant = max(kern, key=lambda k: kern[k]["ms_per_step"])
     hbm_pass = pass_hbm_bytes(dim, Q, len(wl.faces), nb, P, n_blocks, n_nodes, wl.levels)
@@ -276,7 +291,7 @@ def main():
     # roofline of the dominant kernel
     F = len(wl.faces)
     roof = roofline(dominant, kern[dominant], dim=dim, Q=Q, F=F, nb=nb, P=P, n_blocks=n_blocks, n_nodes=n_nodes,
-                    t_flag=t_flag, t_q=t_q, L=wl.levels)
+                    t_flag=t_flag, t_q=t_q, L=wl.levels, workload=wl.name)
 
     out = {
         "metric": METRIC, "value": T / (ms * 1e-3), "unit": "cell-face tests/s", "n_gpus": 1,
@@ -285,10 +300,18 @@ def main():
         "config": {"workload": f"{wl.name}: " + describe(wl), "faces": F, "roots": list(wl.roots[:dim]),
                    "levels": wl.levels, "bins": wl.bins, "lattice": f"D{dim}Q{Q}", "global_batch": 1,
                    "seq_len": 0, "parallelism": "none"},
-        "near_wall_pass_ms": pass_ms, "grad_ms": grad_ms,
-        "near_wall_pass_hbm": {"algorithmic_bytes": hbm_pass, "GBps": hbm_pass / (pass_ms * 1e-3) / 1e9,
-                               "frac_of_peak": hbm_pass / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
-        "cell_face_tests": {"flag_per_pass": t_flag, "q": t_q, "total": T},
+        "near_wall_pass_ms": pass_ms_median, "near_wall_pass_kernel_ms": pass_kernel_ms,
+        "grad_ms": grad_ms, "grad_step_ms": grad_step_median,
+        "near_wall_pass_hbm": {"algorithmic_bytes": hbm_pass,
+                               "GBps": hbm_pass / (pass_ms_median * 1e-3) / 1e9,
+                               "frac_of_peak": hbm_pass / (pass_ms_median * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                               "frac_of_copy": hbm_pass / (pass_ms_median * 1e-3) / 1e9 / copy_gbs,
+                               "copy_GBps": copy_gbs},
+        "cell_face_tests": {"flag_per_pass": t_flag, "q": t_q, "total": T,
+                            "per_s_pass": T / (pass_ms_median * 1e-3),
+                            "flag_per_s": sum(t_flag) / (kern["flag_sat"]["ms_per_step"] * 1e-3)
+                            if "flag_sat" in kern else None,
+                            "q_per_s": t_q / (kern["q_links"]["ms_per_step"] * 1e-3) if "q_links" in kern else None},
         "forest_blocks_per_level": n_blocks, "boundary_nodes": n_nodes, "links": n_links,
         "kernels": kern, "roofline": roof,
     }
@@ -417,6 +440,23 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_bandwidth(torch, dev, mib=1024, reps=5):
+    """Device-to-device copy rate (read + write bytes / s): the measured second denominator for % HBM."""
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * 4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    return gbs
+
+
 def describe(wl):
     if wl.name == "C0":
         return "2D circle r=0.25, 256 segments"
@@ -431,8 +471,41 @@ def describe(wl):
 
 CULL_OPS = 12   # FP32 ops of one bounding-box rejection: 6 subtractions, 6 comparisons
 
+# Library timing names -> kernel symbols as profilers list them, and the sources each kernel is built from.
+KERNEL_SYMBOL = {"flag_sat": ("k_flag", "refine.hip"), "q_links": ("k_links", "links.hip"),
+                 "q_adjoint": ("k_adjoint", "links.hip"), "q_compact": ("k_compact_nodes", "links.hip"),
+                 "bin_canon": ("k_bin_canon_small", "bins.hip")}
 
-def roofline(name, k, dim, Q, F, nb, P, n_blocks, n_nodes, t_flag, t_q, L):
+
+def kernel_source_hash(name):
+    """sha256 of the sources a kernel is compiled from (its .hip file and the shared device headers)."""
+    import hashlib
+    if name not in KERNEL_SYMBOL:
+        return None
+    csrc = os.path.join(ROOT, "paper_2502_16310_amd", "csrc")
+    h = hashlib.sha256()
+    for fn in (KERNEL_SYMBOL[name][1], "kernels.hpp", "device.hpp"):
+        with open(os.path.join(csrc, fn), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(name, workload):
+    """HBM bytes per launch of kernel `name` on `workload` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (profiles/traffic.json, counters scaled by a plain copy of known size); None when there is none or
+    the kernel's sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        table = json.load(fh)
+    e = table.get(workload, {}).get(name)
+    if not e or e.get("source_sha256") != kernel_source_hash(name):
+        return None
+    return e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+
+
+def roofline(name, k, dim, Q, F, nb, P, n_blocks, n_nodes, t_flag, t_q, L, workload=None):
     """Roofline entry of kernel `name` from its average launch time.
 
     flag_sat / q_links are arithmetic kernels: algorithmic work = the (cell,
@@ -450,7 +523,8 @@ def roofline(name, k, dim, Q, F, nb, P, n_blocks, n_nodes, t_flag, t_q, L):
         ops = CULL_OPS * pairs
         tops = ops / (us * 1e-6) / 1e12
         return {"bound": "alu", "achieved": tops, "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
-                "frac": tops / VALU_PEAK_TOPS, "traffic": None, "kernel": name, "ops_per_launch": ops,
+                "frac": tops / VALU_PEAK_TOPS, "traffic": measured_traffic(name, workload), "kernel": name,
+                "ops_per_launch": ops,
                 "cell_face_pairs_per_launch": pairs, "avg_launch_us": us}
     if name == "q_adjoint":
         byts = n_nodes * (8 + 8 * Q) + face_bytes + 4 * F * dim + 4 * dim * 4 * F
@@ -465,7 +539,8 @@ def roofline(name, k, dim, Q, F, nb, P, n_blocks, n_nodes, t_flag, t_q, L):
                 "traffic": None, "kernel": name}
     gbs = byts / (us * 1e-6) / 1e9
     return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-            "traffic": None, "kernel": name, "bytes_per_launch": byts, "avg_launch_us": us}
+            "traffic": measured_traffic(name, workload), "kernel": name, "bytes_per_launch": byts,
+            "avg_launch_us": us}
 
 
 def pass_hbm_bytes(dim, Q, F, nb, P, n_blocks, n_nodes, L):

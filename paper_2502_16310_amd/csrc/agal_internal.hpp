@@ -107,6 +107,7 @@ struct agal_geom_t {
     int64_t F = 0, Nv = 0;
     float *coords = nullptr;   // (dim*dim) x F
     float *aabb = nullptr;     // (2*dim) x F
+    float *rec = nullptr;      // F x (16 in 3D, 8 in 2D): corners, min, max
     int32_t *fidx = nullptr;   // F x dim
 };
 

@@ -47,7 +47,7 @@ struct BodyDev {
     const float *verts;
     const int32_t *faces;
     int64_t Nv, F;
-    float *coords, *aabb;
+    float *coords, *aabb, *rec;
     int32_t *fidx;
     dev::BinGrid bins;     // off = global offsets + bin_base, ids = global ids
     int64_t nb, bin_base;
@@ -184,37 +184,7 @@ __global__ void k_b_import(const BodyDev *bodies, int nb, Ctl *ctl) {
     AGAL_THREAD_ITEMS(it, nf) {
         const int b = find_seg(s_pre, nb, it);
         const BodyDev &B = bodies[b];
-        const int64_t f = it - s_pre[b];
-        float v[D][D];
-        bool ok = true;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const int64_t vi = B.faces ? (int64_t)B.faces[f * D + k] : f * D + k;
-            ok = ok && vi >= 0 && vi < B.Nv;
-            B.fidx[f * D + k] = (vi >= 0 && vi < B.Nv) ? (int32_t)vi : 0;
-        }
-        if (!ok) bad |= 2u;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const int64_t vi = B.faces ? (int64_t)B.faces[f * D + k] : f * D + k;
-#pragma unroll
-            for (int a = 0; a < D; ++a) v[k][a] = ok ? B.verts[vi * D + a] : 0.0f;
-        }
-#pragma unroll
-        for (int k = 0; k < D; ++k)
-#pragma unroll
-            for (int a = 0; a < D; ++a) B.coords[(int64_t)(k * D + a) * B.F + f] = v[k][a];
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            float mn = v[0][a], mx = v[0][a];
-#pragma unroll
-            for (int k = 1; k < D; ++k) {
-                mn = dev::fminf_(mn, v[k][a]);
-                mx = dev::fmaxf_(mx, v[k][a]);
-            }
-            B.aabb[(int64_t)a * B.F + f] = mn;
-            B.aabb[(int64_t)(D + a) * B.F + f] = mx;
-        }
+        bad |= import_face<D>(B.verts, B.Nv, B.faces, B.F, B.coords, B.aabb, B.rec, B.fidx, it - s_pre[b]);
     }
     if (bad) atomicOr(&ctl->err, bad);
 }
@@ -353,7 +323,7 @@ __global__ __launch_bounds__(64) void k_b_flag(const BodyDev *bodies, int nb, in
         const int b = find_seg(s_pre, nb, it);
         const BodyDev &B = bodies[b];
         FlagArgs<D> A{};
-        A.faces = dev::Faces{B.coords, B.aabb, B.F};
+        A.faces = dev::Faces{B.coords, B.aabb, B.rec, B.F};
         A.bins = B.bins;
         A.keys = B.keys[p][0];
         A.n = cnt[b * kLv + p];
@@ -503,7 +473,7 @@ __global__ __launch_bounds__(64) void k_b_links(const BodyDev *bodies, int nb, c
         const BodyDev &B = bodies[b];
         const int L = B.L;
         LinkArgs<D, Q> A{};
-        A.faces = dev::Faces{B.coords, B.aabb, B.F};
+        A.faces = dev::Faces{B.coords, B.aabb, B.rec, B.F};
         A.bins = B.bins;
         A.keys = B.keys[L][final_buf(L, L)];
         A.n = cnt[b * kLv + L];
@@ -548,7 +518,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_b_adjoint(const BodyDev *bodies
         const int b = find_seg(s_pre, nb, it);
         const BodyDev &B = bodies[b];
         AdjArgs<D, Q> A{};
-        A.coords = B.coords;
+        A.rec = B.rec;
         A.F = B.F;
         A.fidx = B.fidx;
         A.node_key = B.key;
@@ -899,6 +869,7 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
         X.F = d.n_faces;
         AGAL_TRY(own(bt, &X.coords, (size_t)D * D * X.F));
         AGAL_TRY(own(bt, &X.aabb, (size_t)2 * D * X.F));
+        AGAL_TRY(own(bt, &X.rec, (size_t)dev::kRecFloats<D> * X.F));
         AGAL_TRY(own(bt, &X.fidx, (size_t)D * X.F));
         X.bins.B = h.B;
         X.nb = h.nb;

@@ -61,11 +61,38 @@ struct BinGrid {
     int B;
 };
 
+// A value known to be equal on every lane, moved to a scalar register.
+__device__ __forceinline__ float uniform(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+// Per-face record, one 64-byte (3D) or 32-byte (2D) row per face so that a
+// gather of one face touches one cache line:
+//   3D: v0 v1 v2 (9 floats), min (3), max (3), 0
+//   2D: a b (4 floats), min (2), max (2)
+template <int D>
+constexpr int kRecFloats = D == 3 ? 16 : 8;
+
 struct Faces {
     const float *coords;  // (D*D) x F
     const float *aabb;    // (2*D) x F
+    const float *rec;     // F x kRecFloats<D>
     int64_t F;
 };
+
+// The record of face f as kRecFloats<D> / 4 aligned 16-byte loads.
+template <int D>
+__device__ __forceinline__ void load_rec(const float *rec, int64_t f, float out[kRecFloats<D>]) {
+    const float4 *r = reinterpret_cast<const float4 *>(rec) + f * (kRecFloats<D> / 4);
+#pragma unroll
+    for (int i = 0; i < kRecFloats<D> / 4; ++i) {
+        const float4 x = r[i];
+        out[4 * i] = x.x;
+        out[4 * i + 1] = x.y;
+        out[4 * i + 2] = x.z;
+        out[4 * i + 3] = x.w;
+    }
+}
 
 // Block coordinates at `level` from a hierarchical key.
 template <int D>

@@ -1,11 +1,13 @@
 // Import (paper Sec. II-B): index lists or a coordinate list -> the
 // library-owned structure-of-arrays coordinate list, per-face bounding
-// boxes and a copy of the index list (needed by the adjoint).
+// boxes, one 16/8-float record per face (corners and box, for single-line
+// gathers) and a copy of the index list (needed by the adjoint).
 #include <algorithm>
 #include <cmath>
 
 #include "agal_internal.hpp"
 #include "device.hpp"
+#include "kernels.hpp"
 
 namespace agal {
 
@@ -14,44 +16,13 @@ namespace agal {
 // zeros and the call fails).
 template <int D>
 __global__ void k_import(const float *verts, int64_t Nv, const int32_t *faces, int64_t F, float *coords, float *aabb,
-                         int32_t *fidx, uint32_t *err) {
+                         float *rec, int32_t *fidx, uint32_t *err) {
     uint32_t bad = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t i = t0; i < Nv * D; i += stride)
         if (!isfinite(verts[i])) bad |= 1u;
-    for (int64_t f = t0; f < F; f += stride) {
-        float v[D][D];
-        bool ok = true;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const int64_t vi = faces ? (int64_t)faces[f * D + k] : f * D + k;
-            ok = ok && vi >= 0 && vi < Nv;
-            fidx[f * D + k] = (vi >= 0 && vi < Nv) ? (int32_t)vi : 0;
-        }
-        if (!ok) bad |= 2u;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const int64_t vi = faces ? (int64_t)faces[f * D + k] : f * D + k;
-#pragma unroll
-            for (int a = 0; a < D; ++a) v[k][a] = ok ? verts[vi * D + a] : 0.0f;
-        }
-#pragma unroll
-        for (int k = 0; k < D; ++k)
-#pragma unroll
-            for (int a = 0; a < D; ++a) coords[(int64_t)(k * D + a) * F + f] = v[k][a];
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            float mn = v[0][a], mx = v[0][a];
-#pragma unroll
-            for (int k = 1; k < D; ++k) {
-                mn = dev::fminf_(mn, v[k][a]);
-                mx = dev::fmaxf_(mx, v[k][a]);
-            }
-            aabb[(int64_t)a * F + f] = mn;
-            aabb[(int64_t)(D + a) * F + f] = mx;
-        }
-    }
+    for (int64_t f = t0; f < F; f += stride) bad |= kern::import_face<D>(verts, Nv, faces, F, coords, aabb, rec, fidx, f);
     if (bad) atomicOr(err, bad);
 }
 
@@ -90,6 +61,7 @@ agal_status agal_import_faces(agal_context ctx, int dim, const float *d_vertices
     uint32_t *err = nullptr;
     agal_status st = dev_alloc(ctx->mem, &g->coords, (size_t)dim * dim * n_faces, s);
     if (st == AGAL_OK) st = dev_alloc(ctx->mem, &g->aabb, (size_t)2 * dim * n_faces, s);
+    if (st == AGAL_OK) st = dev_alloc(ctx->mem, &g->rec, (size_t)(dim == 3 ? 16 : 8) * n_faces, s);
     if (st == AGAL_OK) st = dev_alloc(ctx->mem, &g->fidx, (size_t)dim * n_faces, s);
     if (st == AGAL_OK) st = dev_alloc(ctx->mem, &err, 1, s);
     if (st != AGAL_OK) {
@@ -103,10 +75,10 @@ agal_status agal_import_faces(agal_context ctx, int dim, const float *d_vertices
         const unsigned grid = grid_for(std::max(n_vertices * dim, n_faces));
         if (dim == 3)
             hipLaunchKernelGGL(k_import<3>, dim3(grid), dim3(256), 0, s, d_vertices, n_vertices, d_faces, n_faces,
-                               g->coords, g->aabb, g->fidx, err);
+                               g->coords, g->aabb, g->rec, g->fidx, err);
         else
             hipLaunchKernelGGL(k_import<2>, dim3(grid), dim3(256), 0, s, d_vertices, n_vertices, d_faces, n_faces,
-                               g->coords, g->aabb, g->fidx, err);
+                               g->coords, g->aabb, g->rec, g->fidx, err);
     }
     hipError_t e = hipGetLastError();
     uint32_t herr = 0;
@@ -139,6 +111,7 @@ void agal_destroy_geom(agal_geom g) {
     if (!g) return;
     dev_free(g->ctx->mem, g->coords, g->stream);
     dev_free(g->ctx->mem, g->aabb, g->stream);
+    dev_free(g->ctx->mem, g->rec, g->stream);
     dev_free(g->ctx->mem, g->fidx, g->stream);
     delete g;
 }

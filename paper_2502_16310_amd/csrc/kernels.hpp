@@ -18,6 +18,59 @@ namespace agal {
 namespace kern {
 
 // ===========================================================================
+// Import (paper Sec. II-B)
+// ===========================================================================
+// Face f: validate its indices, gather its corners into the structure-of-arrays
+// coordinate list, the bounding-box rows and the per-face record, and copy
+// its indices.  Returns error bits: 2 for an index outside [0, Nv) (the face
+// is then written as zeros).
+template <int D>
+__device__ __forceinline__ uint32_t import_face(const float *verts, int64_t Nv, const int32_t *faces, int64_t F,
+                                                float *coords, float *aabb, float *rec, int32_t *fidx, int64_t f) {
+    float v[D][D];
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const int64_t vi = faces ? (int64_t)faces[f * D + k] : f * D + k;
+        ok = ok && vi >= 0 && vi < Nv;
+        fidx[f * D + k] = (vi >= 0 && vi < Nv) ? (int32_t)vi : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const int64_t vi = faces ? (int64_t)faces[f * D + k] : f * D + k;
+#pragma unroll
+        for (int a = 0; a < D; ++a) v[k][a] = ok ? verts[vi * D + a] : 0.0f;
+    }
+    float r[dev::kRecFloats<D>];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            coords[(int64_t)(k * D + a) * F + f] = v[k][a];
+            r[k * D + a] = v[k][a];
+        }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        float mn = v[0][a], mx = v[0][a];
+#pragma unroll
+        for (int k = 1; k < D; ++k) {
+            mn = dev::fminf_(mn, v[k][a]);
+            mx = dev::fmaxf_(mx, v[k][a]);
+        }
+        aabb[(int64_t)a * F + f] = mn;
+        aabb[(int64_t)(D + a) * F + f] = mx;
+        r[D * D + a] = mn;
+        r[D * D + D + a] = mx;
+    }
+    if constexpr (D == 3) r[15] = 0.0f;
+    float4 *out = reinterpret_cast<float4 *>(rec) + f * (dev::kRecFloats<D> / 4);
+#pragma unroll
+    for (int i = 0; i < dev::kRecFloats<D> / 4; ++i)
+        out[i] = make_float4(r[4 * i], r[4 * i + 1], r[4 * i + 2], r[4 * i + 3]);
+    return ok ? 0u : 2u;
+}
+
+// ===========================================================================
 // Spatial binning (paper Sec. II-C-3)
 // ===========================================================================
 constexpr int kCanonCap = 2048;      // ids per LDS segment in the rank sort
@@ -165,6 +218,64 @@ __device__ __forceinline__ void bin_canon_big_bin(const float *aabb, int64_t F, 
 
 
 // ===========================================================================
+// Candidate faces of a box (shared by the flag and q kernels)
+// ===========================================================================
+// Walks the face ids of bins [ilo, ihi] (inclusive, per axis) in rounds of 64,
+// one candidate per lane: round(has, f, cur) is called by the whole wave, with
+// `cur` the bin coordinates of the lane's candidate, and returns false to stop.
+// Up to 64 bins are opened at once (one lane per bin, offsets loaded together;
+// a wave prefix of their sizes makes one list), so small bins share rounds,
+// and the ids of the next round are loaded while the current round runs:
+// about one memory latency per 64 candidates instead of two per bin.
+template <class Round>
+__device__ __forceinline__ void for_candidates(const dev::BinGrid &g, const int ilo[3], const int ihi[3],
+                                               Round &&round) {
+    const int lane = dev::lane_id();
+    const int nx = ihi[0] - ilo[0] + 1, ny = ihi[1] - ilo[1] + 1, nz = ihi[2] - ilo[2] + 1;
+    const int nbins = nx * ny * nz;
+    for (int bg = 0; bg < nbins; bg += dev::kWave) {
+        const int bi = bg + lane;
+        uint32_t s0 = 0, cnt = 0;
+        if (bi < nbins) {
+            const int bx = ilo[0] + bi % nx, by = ilo[1] + (bi / nx) % ny, bz = ilo[2] + bi / (nx * ny);
+            const int64_t b = ((int64_t)bz * g.B + by) * g.B + bx;
+            s0 = g.off[b];
+            cnt = g.off[b + 1] - s0;
+        }
+        const uint32_t incl = dev::wave_inclusive_sum(cnt);
+        const uint32_t pre = incl - cnt;
+        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, dev::kWave - 1);   // scalar
+        const uint64_t nonempty = __ballot(cnt > 0);
+        // id of list entry c0 + lane (or -1) and the lane holding its bin.  The
+        // cross-lane reads run with every lane active: a lane reading from an
+        // inactive lane gets 0, not that lane's value.
+        auto fetch = [&](uint32_t c0, int &k) -> int32_t {
+            const uint32_t v = c0 + lane;
+            k = 0;
+            for (uint64_t m = nonempty; m; m &= m - 1ull) {
+                const int kk = __builtin_ctzll(m);
+                k = __builtin_amdgcn_readlane(pre, kk) <= v ? kk : k;
+            }
+            const uint32_t s0k = __shfl(s0, k, dev::kWave);
+            const uint32_t prek = __shfl(pre, k, dev::kWave);
+            if (v >= total) return -1;
+            return g.ids[s0k + (v - prek)];
+        };
+        int k = 0;
+        int32_t f = fetch(0, k);
+        for (uint32_t c0 = 0; c0 < total; c0 += dev::kWave) {
+            int kn = 0;
+            const int32_t fn = c0 + dev::kWave < total ? fetch(c0 + dev::kWave, kn) : -1;   // next round, in flight
+            const int bk = bg + k;
+            const int cur[3] = {ilo[0] + bk % nx, ilo[1] + (bk / nx) % ny, ilo[2] + bk / (nx * ny)};
+            if (!round(f >= 0, f, cur)) return;
+            f = fn;
+            k = kn;
+        }
+    }
+}
+
+// ===========================================================================
 // Near-wall refinement (paper Sec. II-C-1, II-C-2)
 // ===========================================================================
 constexpr int kFlagCap = 128;  // staged candidate faces per wave
@@ -190,29 +301,53 @@ template <int D>
 __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
     constexpr int CELLS = D == 3 ? 64 : 16;
     constexpr int BPW = 64 / CELLS;
-    constexpr int NF = D * D + 2 * D;   // coordinates, then the bounding box
+    constexpr int NF = D * D;   // staged corner coordinates
     __shared__ float s_f[NF][kFlagCap];
+    __shared__ __align__(16) uint32_t s_code[kFlagCap];
     const int lane = threadIdx.x;
     const int64_t blk = first + lane / CELLS;
     const bool valid = blk < A.n;
     const int cell = lane % CELLS;
+    const int sub = lane / CELLS;
 
     int bc[3] = {0, 0, 0};
     if (valid) dev::decode_key<D>(A.keys[blk], A.level, A.R[0], A.R[1], bc);
-    const int g0 = 4 * bc[0] + (cell & 3), g1 = 4 * bc[1] + ((cell >> 2) & 3), g2 = 4 * bc[2] + (cell >> 4);
+    const int pos3[3] = {cell & 3, (cell >> 2) & 3, cell >> 4};
     float m[3];
-    m[0] = dev::cell_centre(A.lo[0], g0, A.dx[0]);
-    m[1] = dev::cell_centre(A.lo[1], g1, A.dx[1]);
-    m[2] = D == 3 ? dev::cell_centre(A.lo[2], g2, A.dx[2]) : 0.0f;
+    m[0] = dev::cell_centre(A.lo[0], 4 * bc[0] + pos3[0], A.dx[0]);
+    m[1] = dev::cell_centre(A.lo[1], 4 * bc[1] + pos3[1], A.dx[1]);
+    m[2] = D == 3 ? dev::cell_centre(A.lo[2], 4 * bc[2] + pos3[2], A.dx[2]) : 0.0f;
     const float h = A.h;
     bool flagged = !valid;
-    const int64_t F = A.faces.F;
+
+    // The box-axis part of the separating-axis test is separable: cell (i0,i1,i2)
+    // of a block is not separated from a face along axis a exactly when position
+    // i_a passes the axis-a test, so a staged face carries one bit per (axis,
+    // position) of the block it was staged for, computed with the same FP32
+    // expressions every lane would use (min_k fl(v_k - m) = fl(min_k v_k - m)),
+    // and a lane tests a face with one AND against its own D bits.  (In 2D the
+    // four blocks of a wave take bits 8t..8t+7; a face near a cell of block t
+    // lies in block t's query box, so it is staged, and coded, for block t.)
+    uint32_t lbits = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) lbits |= 1u << (sub * 4 * D + 4 * a + pos3[a]);
+    float mc[D][4];   // cell centres along each axis of the block being staged
+    auto face_code = [&](int t, const float *bb) -> uint32_t {   // bb: min[D], max[D]
+        uint32_t c = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float lo_a = bb[a] - mc[a][i], hi_a = bb[D + a] - mc[a][i];
+                c |= (!(lo_a > h) && !(hi_a < -h)) ? (1u << (4 * a + i)) : 0u;
+            }
+        return c << (t * 4 * D);
+    };
 
     int count = 0;  // staged faces (wave-uniform)
     // Batches of 64 staged faces: each lane marks the faces its cube's box axes do
-    // not separate from it -- the separating-axis test's own three box-axis tests,
-    // since min_k fl(v_k - m) = fl(min_k v_k - m) -- then runs the full test on
-    // those faces only, until flagged.
+    // not separate from it, then runs the full test on those faces only, until
+    // flagged.
     auto test_staged = [&](int n) {
         __syncthreads();
         for (int j0 = 0; j0 < n; j0 += 64) {
@@ -220,15 +355,13 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
             const int jn = min(64, n - j0);
             uint64_t nm = 0;
             if (!flagged)
-                for (int jj = 0; jj < jn; ++jj) {
-                    bool near = true;
+                for (int jj = 0; jj < jn; jj += 4) {
+                    // four codes per step, read as the uint32_t objects they are
+                    const uint32_t cs[4] = {s_code[j0 + jj], s_code[j0 + jj + 1], s_code[j0 + jj + 2],
+                                            s_code[j0 + jj + 3]};
 #pragma unroll
-                    for (int a = 0; a < D; ++a) {
-                        const float lo_a = s_f[D * D + a][j0 + jj] - m[a];
-                        const float hi_a = s_f[D * D + D + a][j0 + jj] - m[a];
-                        near = near && !(lo_a > h) && !(hi_a < -h);
-                    }
-                    nm |= near ? (1ull << jj) : 0ull;
+                    for (int u = 0; u < 4; ++u)
+                        nm |= ((cs[u] & lbits) == lbits && jj + u < jn) ? (1ull << (jj + u)) : 0ull;
                 }
             while (nm && !flagged) {
                 const int j = j0 + __builtin_ctzll(nm);
@@ -254,53 +387,49 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
         float qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
         int ilo[3] = {0, 0, 0}, ihi[3] = {0, 0, 0};
 #pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) mc[a][i] = dev::uniform(dev::cell_centre(A.lo[a], 4 * sc[a] + i, A.dx[a]));
+#pragma unroll
         for (int a = 0; a < D; ++a) {
             qlo[a] = (dev::cell_centre(A.lo[a], 4 * sc[a], A.dx[a]) - h) - A.eps[a];
             qhi[a] = (dev::cell_centre(A.lo[a], 4 * sc[a] + 3, A.dx[a]) + h) + A.eps[a];
             ilo[a] = dev::bin_of(qlo[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
             ihi[a] = dev::bin_of(qhi[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
         }
-        for (int z = ilo[2]; z <= ihi[2] && !done; ++z)
-            for (int y = ilo[1]; y <= ihi[1] && !done; ++y)
-                for (int x = ilo[0]; x <= ihi[0] && !done; ++x) {
-                    const int64_t b = ((int64_t)z * A.bins.B + y) * A.bins.B + x;
-                    const uint32_t s0 = A.bins.off[b], s1 = A.bins.off[b + 1];
-                    for (uint32_t base = s0; base < s1 && !done; base += 64) {
-                        const uint32_t j = base + lane;
-                        bool keep = false;
-                        int32_t f = -1;
-                        if (j < s1) {
-                            f = A.bins.ids[j];
-                            keep = true;
-                            const int cur[3] = {x, y, z};
+        for_candidates(A.bins, ilo, ihi, [&](bool has, int32_t f, const int cur[3]) -> bool {
+            bool keep = false;
+            float r[dev::kRecFloats<D>];
+            if (has) {
+                dev::load_rec<D>(A.faces.rec, f, r);
+                keep = true;
 #pragma unroll
-                            for (int a = 0; a < D; ++a) {
-                                const float mn = A.faces.aabb[(int64_t)a * F + f];
-                                const float mx = A.faces.aabb[(int64_t)(D + a) * F + f];
-                                // visit each face once: in the first bin of (its bins) x (query bins)
-                                const int fb = max(dev::bin_of(mn, A.bins.lo[a], A.bins.s[a], A.bins.B), ilo[a]);
-                                keep = keep && fb == cur[a] && mn <= qhi[a] && mx >= qlo[a];
-                            }
-                        }
-                        const uint64_t mask = __ballot(keep);
-                        const int nk = __popcll(mask);
-                        if (nk == 0) continue;
-                        if (count + nk > kFlagCap) {
-                            test_staged(count);
-                            count = 0;
-                            done = __ballot(!flagged) == 0;
-                            if (done) break;
-                        }
-                        if (keep) {
-                            const int pos = count + dev::lanes_below(mask);
-#pragma unroll
-                            for (int k = 0; k < D * D; ++k) s_f[k][pos] = A.faces.coords[(int64_t)k * F + f];
-#pragma unroll
-                            for (int k = 0; k < 2 * D; ++k) s_f[D * D + k][pos] = A.faces.aabb[(int64_t)k * F + f];
-                        }
-                        count += nk;
-                    }
+                for (int a = 0; a < D; ++a) {
+                    const float mn = r[D * D + a];
+                    const float mx = r[D * D + D + a];
+                    // visit each face once: in the first bin of (its bins) x (query bins)
+                    const int fb = max(dev::bin_of(mn, A.bins.lo[a], A.bins.s[a], A.bins.B), ilo[a]);
+                    keep = keep && fb == cur[a] && mn <= qhi[a] && mx >= qlo[a];
                 }
+            }
+            const uint64_t mask = __ballot(keep);
+            const int nk = __popcll(mask);
+            if (nk == 0) return true;
+            if (count + nk > kFlagCap) {
+                test_staged(count);
+                count = 0;
+                done = __ballot(!flagged) == 0;
+                if (done) return false;
+            }
+            if (keep) {
+                const int pos = count + dev::lanes_below(mask);
+#pragma unroll
+                for (int k = 0; k < NF; ++k) s_f[k][pos] = r[k];
+                s_code[pos] = face_code(sb, r + D * D);
+            }
+            count += nk;
+            return true;
+        });
     }
     if (!done && count > 0) test_staged(count);
 
@@ -373,8 +502,14 @@ __device__ __forceinline__ void merge_old_item(const uint32_t *keys, const uint8
         nkeys[p] = k;
         nleaf[p] = leaf[i];
         nmark[p] = mark[i];
-        if (ncf)
-            for (int c = 0; c < CELLS; ++c) ncf[p * CELLS + c] = cf[i * CELLS + c];
+        if (ncf) {   // one 16- or 64-byte row: 16-byte moves
+#pragma unroll
+            for (int c = 0; c < CELLS / 16; ++c) {
+                uint4 x;
+                __builtin_memcpy(&x, cf + i * CELLS + 16 * c, 16);
+                __builtin_memcpy(ncf + p * CELLS + 16 * c, &x, 16);
+            }
+        }
     }
 }
 
@@ -393,8 +528,11 @@ __device__ __forceinline__ void children_item(const uint32_t *mk, const uint32_t
         nkeys[p] = (parent << D) | ci;
         nleaf[p] = 1;
         nmark[p] = 0;
-        if (ncf)
-            for (int c = 0; c < CELLS; ++c) ncf[p * CELLS + c] = 0;
+        if (ncf) {
+            const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+            for (int c = 0; c < CELLS / 16; ++c) __builtin_memcpy(ncf + p * CELLS + 16 * c, &z, 16);
+        }
     }
 }
 
@@ -430,9 +568,10 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
     constexpr int CELLS = D == 3 ? 64 : 16;
     constexpr int BPW = 64 / CELLS;
     constexpr int NP = (Q - 1) / 2;            // direction pairs
-    constexpr int NF = D == 3 ? 18 : 8;        // floats staged per face
+    constexpr int NF = D == 3 ? 12 : 4;        // floats staged per face: corners (+ normal in 3D)
     __shared__ float s_f[NF][kLinkCap];
     __shared__ int32_t s_id[kLinkCap];
+    __shared__ __align__(16) uint32_t s_code[kLinkCap];
     __shared__ float s_dir[NP][3];   // D = c * dx of each direction pair's first direction
     const int lane = threadIdx.x;
     if (lane < NP)
@@ -440,7 +579,7 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
     const int64_t blk = first + lane / CELLS;
     const bool valid = blk < A.n;
     const int cell = lane % CELLS;
-    const int64_t F = A.faces.F;
+    const int sub = lane / CELLS;
 
     int bc[3] = {0, 0, 0};
     uint32_t key = 0;
@@ -452,12 +591,26 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
     o[0] = dev::cell_centre(A.lo[0], 4 * bc[0] + (cell & 3), A.dx[0]);
     o[1] = dev::cell_centre(A.lo[1], 4 * bc[1] + ((cell >> 2) & 3), A.dx[1]);
     o[2] = D == 3 ? dev::cell_centre(A.lo[2], 4 * bc[2] + (cell >> 4), A.dx[2]) : 0.0f;
-    float clo[3], chi[3];
+    // Near test of a staged face against the lane's link box (cell +- one cell
+    // per axis), separable by axis: a staged face carries one bit per (axis,
+    // position) of the block it was staged for, from the same FP32 expressions
+    // every lane would use, and a lane tests it with one AND against its own D
+    // bits.  (2D: block t of the wave uses bits 8t..8t+7; a face near a cell of
+    // block t lies in block t's link box, so it is staged, and coded, for t.)
+    const int pos3[3] = {cell & 3, (cell >> 2) & 3, cell >> 4};
+    uint32_t lbits = 0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        clo[a] = (o[a] - A.dx[a]) - A.eps[a];
-        chi[a] = (o[a] + A.dx[a]) + A.eps[a];
-    }
+    for (int a = 0; a < D; ++a) lbits |= 1u << (sub * 4 * D + 4 * a + pos3[a]);
+    float mlo[D][4], mhi[D][4];   // link-box bounds along each axis of the block being staged
+    auto face_code = [&](int t, const float *bb) -> uint32_t {   // bb: min[D], max[D]
+        uint32_t c = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                c |= (bb[a] <= mhi[a][i] && bb[D + a] >= mlo[a][i]) ? (1u << (4 * a + i)) : 0u;
+        return c << (t * 4 * D);
+    };
 
     float best_t[Q - 1];
     int32_t best_f[Q - 1];
@@ -539,14 +692,12 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
         for (int j0 = 0; j0 < n; j0 += 64) {
             const int jn = min(64, n - j0);
             uint64_t nm = 0;
-            for (int jj = 0; jj < jn; ++jj) {
-                bool near = true;
+            for (int jj = 0; jj < jn; jj += 4) {
+                const uint32_t cs[4] = {s_code[j0 + jj], s_code[j0 + jj + 1], s_code[j0 + jj + 2],
+                                        s_code[j0 + jj + 3]};
 #pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    const float mn = s_f[NF - 2 * D + a][j0 + jj], mx = s_f[NF - D + a][j0 + jj];
-                    near = near && mn <= chi[a] && mx >= clo[a];
-                }
-                nm |= near ? (1ull << jj) : 0ull;
+                for (int u = 0; u < 4; ++u)
+                    nm |= ((cs[u] & lbits) == lbits && jj + u < jn) ? (1ull << (jj + u)) : 0ull;
             }
             while (nm) {
                 const int j = j0 + __builtin_ctzll(nm);
@@ -644,65 +795,62 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
         float qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
         int ilo[3] = {0, 0, 0}, ihi[3] = {0, 0, 0};
 #pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {   // wave-uniform: kept in scalar registers
+                const float c = dev::cell_centre(A.lo[a], 4 * sc[a] + i, A.dx[a]);
+                mlo[a][i] = dev::uniform((c - A.dx[a]) - A.eps[a]);
+                mhi[a][i] = dev::uniform((c + A.dx[a]) + A.eps[a]);
+            }
+#pragma unroll
         for (int a = 0; a < D; ++a) {
             qlo[a] = (dev::cell_centre(A.lo[a], 4 * sc[a], A.dx[a]) - A.dx[a]) - A.eps[a];
             qhi[a] = (dev::cell_centre(A.lo[a], 4 * sc[a] + 3, A.dx[a]) + A.dx[a]) + A.eps[a];
             ilo[a] = dev::bin_of(qlo[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
             ihi[a] = dev::bin_of(qhi[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
         }
-        for (int z = ilo[2]; z <= ihi[2]; ++z)
-            for (int y = ilo[1]; y <= ihi[1]; ++y)
-                for (int x = ilo[0]; x <= ihi[0]; ++x) {
-                    const int64_t b = ((int64_t)z * A.bins.B + y) * A.bins.B + x;
-                    const uint32_t s0 = A.bins.off[b], s1 = A.bins.off[b + 1];
-                    for (uint32_t base = s0; base < s1; base += 64) {
-                        const uint32_t j = base + lane;
-                        bool keep = false;
-                        int32_t f = -1;
-                        float bb[6] = {0, 0, 0, 0, 0, 0};
-                        if (j < s1) {
-                            f = A.bins.ids[j];
-                            keep = true;
-                            const int cur[3] = {x, y, z};
+        for_candidates(A.bins, ilo, ihi, [&](bool has, int32_t f, const int cur[3]) -> bool {
+            bool keep = false;
+            float r[dev::kRecFloats<D>];
+            const float *bb = r + D * D;   // min then max
+            if (has) {
+                dev::load_rec<D>(A.faces.rec, f, r);
+                keep = true;
 #pragma unroll
-                            for (int a = 0; a < D; ++a) {
-                                bb[a] = A.faces.aabb[(int64_t)a * F + f];
-                                bb[D + a] = A.faces.aabb[(int64_t)(D + a) * F + f];
-                                const int fb = max(dev::bin_of(bb[a], A.bins.lo[a], A.bins.s[a], A.bins.B), ilo[a]);
-                                keep = keep && fb == cur[a] && bb[a] <= qhi[a] && bb[D + a] >= qlo[a];
-                            }
-                        }
-                        const uint64_t mask = __ballot(keep);
-                        const int nk = __popcll(mask);
-                        if (nk == 0) continue;
-                        if (count + nk > kLinkCap) {
-                            test_staged(count);
-                            count = 0;
-                        }
-                        if (keep) {
-                            const int pos = count + dev::lanes_below(mask);
-                            s_id[pos] = f;
-                            if constexpr (D == 3) {
-                                float v[9];
-#pragma unroll
-                                for (int k = 0; k < 9; ++k) v[k] = A.faces.coords[(int64_t)k * F + f];
-                                const float e10 = v[3] - v[0], e11 = v[4] - v[1], e12 = v[5] - v[2];
-                                const float e20 = v[6] - v[0], e21 = v[7] - v[1], e22 = v[8] - v[2];
-#pragma unroll
-                                for (int k = 0; k < 9; ++k) s_f[k][pos] = v[k];
-                                s_f[9][pos] = e11 * e22 - e12 * e21;
-                                s_f[10][pos] = e12 * e20 - e10 * e22;
-                                s_f[11][pos] = e10 * e21 - e11 * e20;
-                            } else {
-#pragma unroll
-                                for (int k = 0; k < 4; ++k) s_f[k][pos] = A.faces.coords[(int64_t)k * F + f];
-                            }
-#pragma unroll
-                            for (int a = 0; a < 2 * D; ++a) s_f[NF - 2 * D + a][pos] = bb[a];
-                        }
-                        count += nk;
-                    }
+                for (int a = 0; a < D; ++a) {
+                    // visit each face once: in the first bin of (its bins) x (query bins)
+                    const int fb = max(dev::bin_of(bb[a], A.bins.lo[a], A.bins.s[a], A.bins.B), ilo[a]);
+                    keep = keep && fb == cur[a] && bb[a] <= qhi[a] && bb[D + a] >= qlo[a];
                 }
+            }
+            const uint64_t mask = __ballot(keep);
+            const int nk = __popcll(mask);
+            if (nk == 0) return true;
+            if (count + nk > kLinkCap) {
+                test_staged(count);
+                count = 0;
+            }
+            if (keep) {
+                const int pos = count + dev::lanes_below(mask);
+                s_id[pos] = f;
+                if constexpr (D == 3) {
+                    const float *v = r;
+                    const float e10 = v[3] - v[0], e11 = v[4] - v[1], e12 = v[5] - v[2];
+                    const float e20 = v[6] - v[0], e21 = v[7] - v[1], e22 = v[8] - v[2];
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) s_f[k][pos] = v[k];
+                    s_f[9][pos] = e11 * e22 - e12 * e21;
+                    s_f[10][pos] = e12 * e20 - e10 * e22;
+                    s_f[11][pos] = e10 * e21 - e11 * e20;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) s_f[k][pos] = r[k];
+                }
+                s_code[pos] = face_code(sb, bb);
+            }
+            count += nk;
+            return true;
+        });
     }
     if (count > 0) test_staged(count);
 
@@ -713,7 +861,6 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
     has = has && valid;
     const uint64_t hm = __ballot(has);
     // rank inside the block: lanes of this block below this lane that have a link
-    const int sub = lane / CELLS;
     uint64_t bm = hm;
     if constexpr (CELLS < 64) bm = (hm >> (sub * CELLS)) & ((1ull << CELLS) - 1);
     int64_t row0 = 0;
@@ -739,7 +886,7 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
 // ---------------------------------------------------------------------------
 template <int D, int Q>
 struct AdjArgs {
-    const float *coords;
+    const float *rec;      // face records (F x kRecFloats<D>)
     int64_t F;
     const int32_t *fidx;
     const uint64_t *node_key;
@@ -759,12 +906,11 @@ constexpr int kAdjHash = 512;      // per-workgroup face accumulators
 // Gradient of one link's t with respect to the D vertices of its face,
 // scaled by w: out[k][a] = w * lambda_k * n_a / (D . n).
 template <int D>
-__device__ __forceinline__ void link_grad(const float *coords, int64_t F, int32_t f, const float o[3],
-                                          const float Dv[3], float w, float out[D][D]) {
+__device__ __forceinline__ void link_grad(const float *rec, int32_t f, const float o[3], const float Dv[3], float w,
+                                          float out[D][D]) {
+    float v[dev::kRecFloats<D>];
+    dev::load_rec<D>(rec, f, v);
     if constexpr (D == 3) {
-        float v[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) v[k] = coords[(int64_t)k * F + f];
         const float e1[3] = {v[3] - v[0], v[4] - v[1], v[5] - v[2]};
         const float e2[3] = {v[6] - v[0], v[7] - v[1], v[8] - v[2]};
         const float T[3] = {o[0] - v[0], o[1] - v[1], o[2] - v[2]};
@@ -811,8 +957,8 @@ __device__ __forceinline__ void link_grad(const float *coords, int64_t F, int32_
             for (int a = 0; a < 3; ++a) out[k][a] = sc * n[a];
         }
     } else {
-        const float a0 = coords[(int64_t)0 * F + f], a1 = coords[(int64_t)1 * F + f];
-        const float b0 = coords[(int64_t)2 * F + f], b1 = coords[(int64_t)3 * F + f];
+        const float a0 = v[0], a1 = v[1];
+        const float b0 = v[2], b1 = v[3];
         const float e0 = b0 - a0, e1 = b1 - a1;
         const float n[2] = {-e1, e0};
         const float w0 = a0 - o[0], w1 = a1 - o[1];
@@ -908,7 +1054,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs<D, Q> &A, int64_t nod
                 const float w = A.gq[node * Q + i];
                 const float Dv[3] = {s_D[i][0], s_D[i][1], s_D[i][2]};
                 float g[D][D];
-                link_grad<D>(A.coords, A.F, f, o, Dv, w, g);
+                link_grad<D>(A.rec, f, o, Dv, w, g);
                 if (f == cur) {
 #pragma unroll
                     for (int k = 0; k < D; ++k)
@@ -943,13 +1089,36 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs<D, Q> &A, int64_t nod
 // Copy c staged node rows (key, q row, face row) from row src to row dst, as
 // flat coalesced runs over one wave.
 template <int Q>
-__device__ __forceinline__ void compact_block(int c, int64_t src, int64_t dst, const uint64_t *skey, const float *sq,
-                                              const int32_t *sface, uint64_t *key, float *q, int32_t *face) {
+__device__ __forceinline__ void compact_block(int c, int64_t src, int64_t dst, const uint64_t *__restrict__ skey,
+                                              const float *__restrict__ sq, const int32_t *__restrict__ sface,
+                                              uint64_t *__restrict__ key, float *__restrict__ q,
+                                              int32_t *__restrict__ face) {
     if (c == 0) return;
     for (int r = threadIdx.x; r < c; r += 64) key[dst + r] = skey[src + r];
-    for (int e = threadIdx.x; e < c * Q; e += 64) {
-        q[dst * Q + e] = sq[src * Q + e];
-        face[dst * Q + e] = sface[src * Q + e];
+    const float *__restrict__ qs = sq + src * Q;
+    const int32_t *__restrict__ fs = sface + src * Q;
+    float *__restrict__ qd = q + dst * Q;
+    int32_t *__restrict__ fd = face + dst * Q;
+    const int n = c * Q;
+    // four loads per array in flight before the stores
+    int e = threadIdx.x;
+    for (; e + 3 * 64 < n; e += 4 * 64) {
+        float a[4];
+        int32_t b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = qs[e + u * 64];
+            b[u] = fs[e + u * 64];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            qd[e + u * 64] = a[u];
+            fd[e + u * 64] = b[u];
+        }
+    }
+    for (; e < n; e += 64) {
+        qd[e] = qs[e];
+        fd[e] = fs[e];
     }
 }
 

@@ -46,7 +46,7 @@ struct BlockSlots {
 };
 
 template <int D, int Q>
-__global__ __launch_bounds__(64) void k_links(LinkArgs<D, Q> A, uint32_t *count) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_links(LinkArgs<D, Q> A, uint32_t *count) {
     BlockSlots<D == 3 ? 64 : 16> out{count};
     links_wave<D, Q>(A, (int64_t)blockIdx.x * (D == 3 ? 1 : 4), out);
 }
@@ -102,7 +102,7 @@ agal_status links_forward(agal_geom g, agal_bins bn, agal_forest fo, const Latti
     AGAL_TRY(dev_alloc(ctx->mem, &st.q, (size_t)cap * Q, s));
     AGAL_TRY(dev_alloc(ctx->mem, &st.face, (size_t)cap * Q, s));
     LinkArgs<D, Q> A{};
-    A.faces = dev::Faces{g->coords, g->aabb, g->F};
+    A.faces = dev::Faces{g->coords, g->aabb, g->rec, g->F};
     A.bins.off = bn->off;
     A.bins.ids = bn->ids;
     A.bins.B = bn->B;
@@ -148,7 +148,7 @@ template <int D, int Q>
 agal_status links_backward(agal_geom g, agal_links lk, const Lattice &lat, const float *gq, float *grad, hipStream_t s) {
     if (lk->n == 0) return AGAL_OK;
     AdjArgs<D, Q> A{};
-    A.coords = g->coords;
+    A.rec = g->rec;
     A.F = g->F;
     A.fidx = g->fidx;
     A.node_key = lk->key;

@@ -114,7 +114,7 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
         bins.lo[a] = bn->lo[a];
         bins.s[a] = bn->s[a];
     }
-    dev::Faces faces{g->coords, g->aabb, g->F};
+    dev::Faces faces{g->coords, g->aabb, g->rec, g->F};
 
     for (int l = 0; l < fo->L; ++l) {
         Scratch pass{ctx, s, {}};
