@@ -319,8 +319,11 @@ __global__ __launch_bounds__(64) void k_b_flag(const BodyDev *bodies, int nb, in
     __shared__ uint32_t s_pre[kMaxBodies + 1];
     const uint32_t total = lds_prefix(nb, [&](int b) {
         return bodies[b].L > p ? (uint32_t)((cnt[b * kLv + p] + BPW - 1) / BPW) : 0u; }, s_pre);
-    for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
-        const int b = find_seg(s_pre, nb, it);
+    {
+        // one block (2D: four) per workgroup; the grid covers the planned capacity
+        const uint32_t it = blockIdx.x;
+        if (it >= total) return;
+        const int b = __builtin_amdgcn_readfirstlane(find_seg(s_pre, nb, it));   // workgroup-uniform
         const BodyDev &B = bodies[b];
         FlagArgs<D> A{};
         A.faces = dev::Faces{B.coords, B.aabb, B.rec, B.F};
@@ -462,14 +465,16 @@ struct ChunkRows {
 };
 
 template <int D, int Q>
-__global__ __launch_bounds__(64) void k_b_links(const BodyDev *bodies, int nb, const uint32_t *cnt,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_b_links(const BodyDev *bodies, int nb, const uint32_t *cnt,
                                                 uint32_t *cursor, Ctl *ctl) {
     constexpr int BPW = D == 3 ? 1 : 4;
     __shared__ uint32_t s_pre[kMaxBodies + 1];
     const uint32_t total = lds_prefix(nb, [&](int b) {
         return bodies[b].Q == Q ? (uint32_t)((cnt[b * kLv + bodies[b].L] + BPW - 1) / BPW) : 0u; }, s_pre);
-    for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
-        const int b = find_seg(s_pre, nb, it);
+    {
+        const uint32_t it = blockIdx.x;
+        if (it >= total) return;
+        const int b = __builtin_amdgcn_readfirstlane(find_seg(s_pre, nb, it));   // workgroup-uniform
         const BodyDev &B = bodies[b];
         const int L = B.L;
         LinkArgs<D, Q> A{};
@@ -583,6 +588,8 @@ struct agal_batch_t {
     int fill_pass_base = 0;
     int wg_per_cu = 4, n_cu = 256;
     bool with_adjoint = false;
+    unsigned flag_grid[agal::kMaxLevels] = {};   // workgroups of the flag kernel per pass (from capacities)
+    unsigned links_grid[28] = {};                // workgroups of the q kernel per lattice
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<uint32_t> h_cnt, h_nodes;
@@ -724,7 +731,7 @@ static agal_status capture(agal_batch bt) {
     for (int p = 0; p < bt->Lmax; ++p) {
         hipLaunchKernelGGL(k_fill_table, dim3(G), dim3(256), 0, s, bt->d_fills + bt->pass_fill_off[p],
                            bt->pass_fill_n[p]);
-        hipLaunchKernelGGL(k_b_flag<D>, dim3(G64), dim3(64), 0, s, B, nb, p, bt->d_cnt);
+        hipLaunchKernelGGL(k_b_flag<D>, dim3(bt->flag_grid[p]), dim3(64), 0, s, B, nb, p, bt->d_cnt);
         for (int m = p; m >= 1; --m)
             hipLaunchKernelGGL(k_b_ripple<D>, dim3(G), dim3(256), 0, s, B, nb, p, m, bt->d_cnt, bt->d_ctl);
         scan(bt->pass_seg_off[p], bt->pass_seg_n[p], true);
@@ -734,10 +741,16 @@ static agal_status capture(agal_batch bt) {
         hipLaunchKernelGGL(k_b_counts<D>, dim3(1), dim3(256), 0, s, B, nb, p, bt->d_cnt, bt->d_ctl);
     }
     if (D == 3) {
-        hipLaunchKernelGGL((k_b_links<3, 19>), dim3(G64), dim3(64), 0, s, B, nb, bt->d_cnt, bt->d_cursor, bt->d_ctl);
-        hipLaunchKernelGGL((k_b_links<3, 27>), dim3(G64), dim3(64), 0, s, B, nb, bt->d_cnt, bt->d_cursor, bt->d_ctl);
+        if (bt->links_grid[19])
+            hipLaunchKernelGGL((k_b_links<3, 19>), dim3(bt->links_grid[19]), dim3(64), 0, s, B, nb, bt->d_cnt,
+                               bt->d_cursor, bt->d_ctl);
+        if (bt->links_grid[27])
+            hipLaunchKernelGGL((k_b_links<3, 27>), dim3(bt->links_grid[27]), dim3(64), 0, s, B, nb, bt->d_cnt,
+                               bt->d_cursor, bt->d_ctl);
     } else {
-        hipLaunchKernelGGL((k_b_links<2, 9>), dim3(G64), dim3(64), 0, s, B, nb, bt->d_cnt, bt->d_cursor, bt->d_ctl);
+        if (bt->links_grid[9])
+            hipLaunchKernelGGL((k_b_links<2, 9>), dim3(bt->links_grid[9]), dim3(64), 0, s, B, nb, bt->d_cnt,
+                               bt->d_cursor, bt->d_ctl);
     }
     scan(bt->links_seg_off, nb, false);
     hipLaunchKernelGGL(k_b_nodes, dim3(1), dim3(256), 0, s, B, nb, bt->d_cnt, bt->d_nodes);
@@ -915,6 +928,11 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
     }
     bt->nb_total = bin_base;
     bt->cap_ids = cap_ids;
+    for (int b = 0; b < bt->nb; ++b) {
+        const BodyDev &X = bt->bodies[b];
+        for (int p = 0; p < X.L; ++p) bt->flag_grid[p] += (unsigned)((X.cap[p] + (64 / CELLS) - 1) / (64 / CELLS));
+        bt->links_grid[X.Q] += (unsigned)((X.cap[X.L] + (64 / CELLS) - 1) / (64 / CELLS));
+    }
     AGAL_TRY(own(bt, &bt->d_bin_count, (size_t)bt->nb_total));
     AGAL_TRY(own(bt, &bt->d_bin_off, (size_t)bt->nb_total + 1));
     AGAL_TRY(own(bt, &bt->d_bin_cursor, (size_t)bt->nb_total));

@@ -612,86 +612,178 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
         return c << (t * 4 * D);
     };
 
-    float best_t[Q - 1];
-    int32_t best_f[Q - 1];
+    // Best hit per (lane, direction) as one 64-bit key: the FP32 bits of t
+    // (t >= 0, so they order like t) above the face id, so the smaller key is
+    // the smaller t and, between equal t, the lower face id.
+    __shared__ unsigned long long s_best[Q - 1][64];
+    __shared__ float s_o[64][3];
+    // FP64 decisions wait in a queue of (lane, staged face, direction pairs)
+    // and are taken 64 at a time, one per lane, whichever lanes queued them.
+    constexpr int TCAP = 128;   // below 64 after a drain, at most 64 added per step
+    __shared__ uint32_t s_task[TCAP];
 #pragma unroll
-    for (int i = 0; i < Q - 1; ++i) {
-        best_t[i] = 2.0f;
-        best_f[i] = -1;
-    }
+    for (int i = 0; i < Q - 1; ++i) s_best[i][lane] = ~0ull;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) s_o[lane][a] = o[a];
+    int ntask = 0;   // wave-uniform
 
-    // t is decided in FP64 and kept rounded to FP32; equal FP32 values go to the
-    // lower face id (both faces are then hits at the same q).
-    auto consider = [&](int i, double t64, int32_t f) {
+    // A hit at t64 for direction i of lane l.  t is decided in FP64 and kept
+    // rounded to FP32 (a negative zero as zero).
+    auto consider = [&](int i, int l, double t64, int32_t f) {
         if (!(t64 >= 0.0 && t64 <= 1.0)) return;
-        const float t = (float)t64;
-        if (t < best_t[i] || (t == best_t[i] && f < best_f[i])) {
-            best_t[i] = t;
-            best_f[i] = f;
-        }
+        const float t = (float)t64 + 0.0f;
+        const unsigned long long k = ((unsigned long long)__float_as_uint(t) << 32) | (uint32_t)f;
+        atomicMin(&s_best[i][l], k);
     };
 
-    // FP64 decision for one (face, direction pair) that passed the FP32 filter:
-    // the segment-triangle test in the same expression order as the definition
-    // (Moller-Trumbore), so both directions of the pair come out exactly as
-    // separate evaluations would (negating D negates P, det and t exactly).
-    auto decide64_tri = [&](int p, int j, double &tout) -> bool {
-        const double a0 = s_f[0][j], a1 = s_f[1][j], a2 = s_f[2][j];
-        const double E1[3] = {(double)s_f[3][j] - a0, (double)s_f[4][j] - a1, (double)s_f[5][j] - a2};
-        const double E2[3] = {(double)s_f[6][j] - a0, (double)s_f[7][j] - a1, (double)s_f[8][j] - a2};
-        const double T[3] = {(double)o[0] - a0, (double)o[1] - a1, (double)o[2] - a2};
-        const double Dv[3] = {(double)s_dir[p][0], (double)s_dir[p][1], (double)s_dir[p][2]};
-        const double P[3] = {Dv[1] * E2[2] - Dv[2] * E2[1], Dv[2] * E2[0] - Dv[0] * E2[2], Dv[0] * E2[1] - Dv[1] * E2[0]};
-        const double det = E1[0] * P[0] + E1[1] * P[1] + E1[2] * P[2];
-        if (det == 0.0) return false;
-        const double u = (T[0] * P[0] + T[1] * P[1] + T[2] * P[2]) / det;
-        if (u < 0.0 || u > 1.0) return false;
-        const double Qv[3] = {T[1] * E1[2] - T[2] * E1[1], T[2] * E1[0] - T[0] * E1[2], T[0] * E1[1] - T[1] * E1[0]};
-        const double v = (Dv[0] * Qv[0] + Dv[1] * Qv[1] + Dv[2] * Qv[2]) / det;
-        if (v < 0.0 || u + v > 1.0) return false;
-        tout = (E2[0] * Qv[0] + E2[1] * Qv[1] + E2[2] * Qv[2]) / det;
-        return true;
-    };
-    auto decide64_seg = [&](int p, int j, double &tout) -> bool {
-        const double a0 = s_f[0][j], a1 = s_f[1][j];
-        const double e0 = (double)s_f[2][j] - a0, e1 = (double)s_f[3][j] - a1;
-        const double D0 = (double)s_dir[p][0], D1 = (double)s_dir[p][1];
-        const double den = D0 * e1 - D1 * e0;
-        if (den == 0.0) return false;
-        const double w0 = a0 - (double)o[0], w1 = a1 - (double)o[1];
-        tout = (w0 * e1 - w1 * e0) / den;
-        const double sp = (w0 * D1 - w1 * D0) / den;
-        return sp >= 0.0 && sp <= 1.0;
-    };
-    // Runtime pair index p: one copy of the FP64 code; the result reaches the
-    // register-resident best arrays through an unrolled predicated update.
-    auto decide_mask = [&](uint32_t cm, int j, int32_t f) {
-        while (cm) {
-            const int p = __builtin_ctz(cm);
-            cm &= cm - 1u;
-            double t;
-            bool hit;
-            if constexpr (D == 3) hit = decide64_tri(p, j, t);
-            else hit = decide64_seg(p, j, t);
-            if (!hit) continue;
-#pragma unroll
-            for (int q = 0; q < NP; ++q)
-                if (q == p) {
-                    consider(2 * q, t, f);       // direction 1 + 2q
-                    consider(2 * q + 1, -t, f);  // its opposite
-                }
+    // FP64 decisions for staged face j and the direction pairs in cm, against
+    // the link origin of lane l: the segment-triangle test in the same
+    // expression order as the definition (Moller-Trumbore), so both directions
+    // of a pair come out exactly as separate evaluations would (negating D
+    // negates P, det and t exactly).  What depends on the face and the origin
+    // only (edges, T, Q = T x E1 and E2 . Q) is formed once for all pairs.
+    auto decide_task = [&](uint32_t task) {
+        const int l = (int)(task >> 20);
+        const int j = (int)((task >> 13) & 127u);
+        uint32_t cm = task & 0x1FFFu;
+        const int32_t f = s_id[j];
+        const double o0 = s_o[l][0], o1 = s_o[l][1];
+        if constexpr (D == 3) {
+            const double o2 = s_o[l][2];
+            const double a0 = s_f[0][j], a1 = s_f[1][j], a2 = s_f[2][j];
+            const double E1[3] = {(double)s_f[3][j] - a0, (double)s_f[4][j] - a1, (double)s_f[5][j] - a2};
+            const double E2[3] = {(double)s_f[6][j] - a0, (double)s_f[7][j] - a1, (double)s_f[8][j] - a2};
+            const double T[3] = {o0 - a0, o1 - a1, o2 - a2};
+            const double Qv[3] = {T[1] * E1[2] - T[2] * E1[1], T[2] * E1[0] - T[0] * E1[2], T[0] * E1[1] - T[1] * E1[0]};
+            const double tn = E2[0] * Qv[0] + E2[1] * Qv[1] + E2[2] * Qv[2];
+            while (cm) {
+                const int p = __builtin_ctz(cm);
+                cm &= cm - 1u;
+                const double Dv[3] = {(double)s_dir[p][0], (double)s_dir[p][1], (double)s_dir[p][2]};
+                const double P[3] = {Dv[1] * E2[2] - Dv[2] * E2[1], Dv[2] * E2[0] - Dv[0] * E2[2],
+                                     Dv[0] * E2[1] - Dv[1] * E2[0]};
+                const double det = E1[0] * P[0] + E1[1] * P[1] + E1[2] * P[2];
+                if (det == 0.0) continue;
+                const double u = (T[0] * P[0] + T[1] * P[1] + T[2] * P[2]) / det;
+                if (u < 0.0 || u > 1.0) continue;
+                const double v = (Dv[0] * Qv[0] + Dv[1] * Qv[1] + Dv[2] * Qv[2]) / det;
+                if (v < 0.0 || u + v > 1.0) continue;
+                const double t = tn / det;
+                consider(2 * p, l, t, f);        // direction 1 + 2p
+                consider(2 * p + 1, l, -t, f);   // its opposite
+            }
+        } else {
+            const double a0 = s_f[0][j], a1 = s_f[1][j];
+            const double e0 = (double)s_f[2][j] - a0, e1 = (double)s_f[3][j] - a1;
+            const double w0 = a0 - o0, w1 = a1 - o1;
+            const double tn = w0 * e1 - w1 * e0;
+            while (cm) {
+                const int p = __builtin_ctz(cm);
+                cm &= cm - 1u;
+                const double D0 = (double)s_dir[p][0], D1 = (double)s_dir[p][1];
+                const double den = D0 * e1 - D1 * e0;
+                if (den == 0.0) continue;
+                const double t = tn / den;
+                const double sp = (w0 * D1 - w1 * D0) / den;
+                if (!(sp >= 0.0 && sp <= 1.0)) continue;
+                consider(2 * p, l, t, f);
+                consider(2 * p + 1, l, -t, f);
+            }
         }
+    };
+    // Takes queued decisions 0 .. take-1, one per lane, and moves the rest to
+    // the front.  Wave-uniform.
+    auto drain = [&](int take) {
+        __syncthreads();
+        const uint32_t task = lane < take ? s_task[lane] : 0u;
+        __syncthreads();
+        if (lane < ntask - take) s_task[lane] = s_task[take + lane];
+        ntask -= take;
+        if (lane < take) decide_task(task);
+    };
+
+    // FP32 filter of one (lane, staged face) over all direction pairs: the
+    // pairs whose segment may meet the face.  Each quantity carries an absolute
+    // rounding error bounded by 2^-21 times the product of the L1 norms of its
+    // factors; margins of 2^-20 times those products keep every true hit.
+    auto filter = [&](int j) -> uint32_t {
+        uint32_t cm = 0;
+        if constexpr (D == 3) {
+            const float T0 = o[0] - s_f[0][j], T1 = o[1] - s_f[1][j], T2 = o[2] - s_f[2][j];
+            const float e10 = s_f[3][j] - s_f[0][j], e11 = s_f[4][j] - s_f[1][j], e12 = s_f[5][j] - s_f[2][j];
+            const float e20 = s_f[6][j] - s_f[0][j], e21 = s_f[7][j] - s_f[1][j], e22 = s_f[8][j] - s_f[2][j];
+            const float n0 = s_f[9][j], n1 = s_f[10][j], n2 = s_f[11][j];
+            const float nT = fabsf(T0) + fabsf(T1) + fabsf(T2);
+            const float n1n = fabsf(e10) + fabsf(e11) + fabsf(e12);
+            const float n2n = fabsf(e20) + fabsf(e21) + fabsf(e22);
+            const float mx_ = fmaxf(fmaxf(A.dx[0], A.dx[1]), A.dx[2]) * 9.5367431640625e-07f;  // dx * 2^-20
+            const float MU = mx_ * nT * n2n;
+            const float MV = mx_ * n1n * nT;
+            const float MD = mx_ * n1n * n2n;
+            const float MT = 9.5367431640625e-07f * nT * n1n * n2n;
+            const float p10 = (T1 * e22 - T2 * e21) * A.dx[0];
+            const float p11 = (T2 * e20 - T0 * e22) * A.dx[1];
+            const float p12 = (T0 * e21 - T1 * e20) * A.dx[2];
+            const float p20 = (e11 * T2 - e12 * T1) * A.dx[0];
+            const float p21 = (e12 * T0 - e10 * T2) * A.dx[1];
+            const float p22 = (e10 * T1 - e11 * T0) * A.dx[2];
+            const float d0 = n0 * A.dx[0], d1 = n1 * A.dx[1], d2 = n2 * A.dx[2];
+            const float tn = (T0 * n0 + T1 * n1) + T2 * n2;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int i = 1 + 2 * p;
+                const int c0 = dir_c<D>(i, 0), c1 = dir_c<D>(i, 1), c2 = dir_c<D>(i, 2);
+                float den = 0.0f, nu = 0.0f, nv = 0.0f;
+                if (c0) { den += c0 > 0 ? d0 : -d0; nu += c0 > 0 ? p10 : -p10; nv += c0 > 0 ? p20 : -p20; }
+                if (c1) { den += c1 > 0 ? d1 : -d1; nu += c1 > 0 ? p11 : -p11; nv += c1 > 0 ? p21 : -p21; }
+                if (c2) { den += c2 > 0 ? d2 : -d2; nu += c2 > 0 ? p12 : -p12; nv += c2 > 0 ? p22 : -p22; }
+                // |den| <= MD: grazing, the sign of the denominator is not known in FP32
+                const float ad = fabsf(den);
+                const bool neg = den < 0.0f;
+                const float su = neg ? -nu : nu;
+                const float sv = neg ? -nv : nv;
+                const float st = neg ? tn : -tn;   // sign(den) * (-tn) = t * |den|
+                const float lim = ad + MD + MT;
+                const bool in = (su >= -MU) & (sv >= -MV) & (su + sv <= ad + MU + MV + MD) &
+                                (((st >= -MT) & (st <= lim)) | ((-st >= -MT) & (-st <= lim)));
+                cm |= ((ad <= MD) | in) ? (1u << p) : 0u;
+            }
+        } else {
+            const float w0 = s_f[0][j] - o[0], w1 = s_f[1][j] - o[1];
+            const float e0 = s_f[2][j] - s_f[0][j], e1 = s_f[3][j] - s_f[1][j];
+            const float nw = fabsf(w0) + fabsf(w1), ne = fabsf(e0) + fabsf(e1);
+            const float mx_ = fmaxf(A.dx[0], A.dx[1]) * 9.5367431640625e-07f;
+            const float MD = mx_ * ne, MS = mx_ * nw, MW = 9.5367431640625e-07f * nw * ne;
+            const float wxe = w0 * e1 - w1 * e0;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int i = 1 + 2 * p;
+                const float D0 = (float)dir_c<D>(i, 0) * A.dx[0], D1 = (float)dir_c<D>(i, 1) * A.dx[1];
+                const float den = D0 * e1 - D1 * e0;
+                const float ad = fabsf(den);
+                const float sn = w0 * D1 - w1 * D0;
+                const bool neg = den < 0.0f;
+                const float ss = neg ? -sn : sn;
+                const float st = neg ? -wxe : wxe;
+                const float lim = ad + MD + MW;
+                const bool in = (ss >= -MS) & (ss <= ad + MS + MD) &
+                                (((st >= -MW) & (st <= lim)) | ((-st >= -MW) & (-st <= lim)));
+                cm |= ((ad <= MD) | in) ? (1u << p) : 0u;
+            }
+        }
+        return cm;
     };
 
     // Staged faces are visited in batches of 64: each lane first marks the faces
-    // whose box meets its link box (broadcast LDS reads), then walks only its
-    // own marked faces, so lanes stay busy whatever the spatial mix.
+    // whose box meets its link box (broadcast LDS reads), then filters its own
+    // marked faces one per step; the (face, pairs) that pass are queued, and
+    // whenever 64 are queued the whole wave takes them.
     auto test_staged = [&](int n) {
         __syncthreads();
-        if (valid)
         for (int j0 = 0; j0 < n; j0 += 64) {
             const int jn = min(64, n - j0);
             uint64_t nm = 0;
+            if (valid)
             for (int jj = 0; jj < jn; jj += 4) {
                 const uint32_t cs[4] = {s_code[j0 + jj], s_code[j0 + jj + 1], s_code[j0 + jj + 2],
                                         s_code[j0 + jj + 3]};
@@ -699,89 +791,21 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
                 for (int u = 0; u < 4; ++u)
                     nm |= ((cs[u] & lbits) == lbits && jj + u < jn) ? (1ull << (jj + u)) : 0ull;
             }
-            while (nm) {
-                const int j = j0 + __builtin_ctzll(nm);
-                nm &= nm - 1ull;
-                const int32_t f = s_id[j];
-                if constexpr (D == 3) {
-                    // FP32 filter.  Each quantity below carries an absolute rounding error
-                    // bounded by 2^-21 times the product of the L1 norms of its factors;
-                    // margins of 2^-20 times those products keep every true hit.
-                    const float T0 = o[0] - s_f[0][j], T1 = o[1] - s_f[1][j], T2 = o[2] - s_f[2][j];
-                    const float e10 = s_f[3][j] - s_f[0][j], e11 = s_f[4][j] - s_f[1][j], e12 = s_f[5][j] - s_f[2][j];
-                    const float e20 = s_f[6][j] - s_f[0][j], e21 = s_f[7][j] - s_f[1][j], e22 = s_f[8][j] - s_f[2][j];
-                    const float n0 = s_f[9][j], n1 = s_f[10][j], n2 = s_f[11][j];
-                    const float nT = fabsf(T0) + fabsf(T1) + fabsf(T2);
-                    const float n1n = fabsf(e10) + fabsf(e11) + fabsf(e12);
-                    const float n2n = fabsf(e20) + fabsf(e21) + fabsf(e22);
-                    const float mx_ = fmaxf(fmaxf(A.dx[0], A.dx[1]), A.dx[2]) * 9.5367431640625e-07f;  // dx * 2^-20
-                    const float MU = mx_ * nT * n2n;
-                    const float MV = mx_ * n1n * nT;
-                    const float MD = mx_ * n1n * n2n;
-                    const float MT = 9.5367431640625e-07f * nT * n1n * n2n;
-                    const float p10 = (T1 * e22 - T2 * e21) * A.dx[0];
-                    const float p11 = (T2 * e20 - T0 * e22) * A.dx[1];
-                    const float p12 = (T0 * e21 - T1 * e20) * A.dx[2];
-                    const float p20 = (e11 * T2 - e12 * T1) * A.dx[0];
-                    const float p21 = (e12 * T0 - e10 * T2) * A.dx[1];
-                    const float p22 = (e10 * T1 - e11 * T0) * A.dx[2];
-                    const float d0 = n0 * A.dx[0], d1 = n1 * A.dx[1], d2 = n2 * A.dx[2];
-                    const float tn = (T0 * n0 + T1 * n1) + T2 * n2;
-                    uint32_t cm = 0;   // direction pairs that pass the FP32 filter
-#pragma unroll
-                    for (int p = 0; p < NP; ++p) {
-                        const int i = 1 + 2 * p;
-                        const int c0 = dir_c<D>(i, 0), c1 = dir_c<D>(i, 1), c2 = dir_c<D>(i, 2);
-                        float den = 0.0f, nu = 0.0f, nv = 0.0f;
-                        if (c0) { den += c0 > 0 ? d0 : -d0; nu += c0 > 0 ? p10 : -p10; nv += c0 > 0 ? p20 : -p20; }
-                        if (c1) { den += c1 > 0 ? d1 : -d1; nu += c1 > 0 ? p11 : -p11; nv += c1 > 0 ? p21 : -p21; }
-                        if (c2) { den += c2 > 0 ? d2 : -d2; nu += c2 > 0 ? p12 : -p12; nv += c2 > 0 ? p22 : -p22; }
-                        bool cand;
-                        if (fabsf(den) <= MD) {
-                            cand = true;   // grazing: the sign of the denominator is not known in FP32
-                        } else {
-                            const float ad = fabsf(den);
-                            const float su = den < 0.0f ? -nu : nu;
-                            const float sv = den < 0.0f ? -nv : nv;
-                            const float st = den < 0.0f ? tn : -tn;   // sign(den) * (-tn) = t * |den|
-                            const float lim = ad + MD + MT;
-                            cand = su >= -MU && sv >= -MV && su + sv <= ad + MU + MV + MD &&
-                                   ((st >= -MT && st <= lim) || (-st >= -MT && -st <= lim));
-                        }
-                        cm |= cand ? (1u << p) : 0u;
-                    }
-                    if (cm) decide_mask(cm, j, f);
-                } else {
-                    const float w0 = s_f[0][j] - o[0], w1 = s_f[1][j] - o[1];
-                    const float e0 = s_f[2][j] - s_f[0][j], e1 = s_f[3][j] - s_f[1][j];
-                    const float nw = fabsf(w0) + fabsf(w1), ne = fabsf(e0) + fabsf(e1);
-                    const float mx_ = fmaxf(A.dx[0], A.dx[1]) * 9.5367431640625e-07f;
-                    const float MD = mx_ * ne, MS = mx_ * nw, MW = 9.5367431640625e-07f * nw * ne;
-                    const float wxe = w0 * e1 - w1 * e0;
-                    uint32_t cm = 0;
-#pragma unroll
-                    for (int p = 0; p < NP; ++p) {
-                        const int i = 1 + 2 * p;
-                        const float D0 = (float)dir_c<D>(i, 0) * A.dx[0], D1 = (float)dir_c<D>(i, 1) * A.dx[1];
-                        const float den = D0 * e1 - D1 * e0;
-                        bool cand;
-                        if (fabsf(den) <= MD) {
-                            cand = true;
-                        } else {
-                            const float ad = fabsf(den);
-                            const float sn = w0 * D1 - w1 * D0;
-                            const float ss = den < 0.0f ? -sn : sn;
-                            const float st = den < 0.0f ? -wxe : wxe;
-                            const float lim = ad + MD + MW;
-                            cand = ss >= -MS && ss <= ad + MS + MD &&
-                                   ((st >= -MW && st <= lim) || (-st >= -MW && -st <= lim));
-                        }
-                        cm |= cand ? (1u << p) : 0u;
-                    }
-                    if (cm) decide_mask(cm, j, f);
+            while (__ballot(nm != 0)) {
+                uint32_t cm = 0;
+                int j = 0;
+                if (nm) {
+                    j = j0 + __builtin_ctzll(nm);
+                    nm &= nm - 1ull;
+                    cm = filter(j);
                 }
+                const uint64_t want = __ballot(cm != 0);
+                if (cm) s_task[ntask + dev::lanes_below(want)] = ((uint32_t)lane << 20) | ((uint32_t)j << 13) | cm;
+                ntask += __popcll(want);
+                if (ntask >= 64) drain(64);
             }
         }
+        if (ntask > 0) drain(ntask);
         __syncthreads();
     };
 
@@ -855,9 +879,13 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
     if (count > 0) test_staged(count);
 
     // ordered compaction of the cells that have a link
+    uint64_t best[Q - 1];
     bool has = false;
 #pragma unroll
-    for (int i = 0; i < Q - 1; ++i) has = has || best_f[i] >= 0;
+    for (int i = 0; i < Q - 1; ++i) {
+        best[i] = s_best[i][lane];
+        has = has || best[i] != ~0ull;
+    }
     has = has && valid;
     const uint64_t hm = __ballot(has);
     // rank inside the block: lanes of this block below this lane that have a link
@@ -875,14 +903,15 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
         fr[0] = -1;
 #pragma unroll
         for (int i = 0; i < Q - 1; ++i) {
-            qr[i + 1] = best_f[i] >= 0 ? best_t[i] : -1.0f;
-            fr[i + 1] = best_f[i];
+            const bool hit = best[i] != ~0ull;
+            qr[i + 1] = hit ? __uint_as_float((uint32_t)(best[i] >> 32)) : -1.0f;
+            fr[i + 1] = hit ? (int32_t)(uint32_t)best[i] : -1;
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint: one thread per (node, direction) slot.
+// Adjoint: a queue of live links per tile of nodes, one link per thread.
 // ---------------------------------------------------------------------------
 template <int D, int Q>
 struct AdjArgs {
@@ -900,29 +929,73 @@ struct AdjArgs {
     float *grad;
 };
 
-constexpr int kAdjThreads = 256;   // one node per thread
-constexpr int kAdjHash = 512;      // per-workgroup face accumulators
+constexpr int kAdjThreads = 256;   // nodes per tile = threads per workgroup
+constexpr int kAdjWaves = kAdjThreads / 64;
+constexpr int kAdjHashBits = 8;
+constexpr int kAdjHash = 1 << kAdjHashBits;   // per-workgroup face accumulators
 
-// Gradient of one link's t with respect to the D vertices of its face,
-// scaled by w: out[k][a] = w * lambda_k * n_a / (D . n).
+// Gradient of one link's t with respect to the D vertices of its face, scaled
+// by the link's weight w: out[k][a] = w * lambda_k * n_a / (D . n), lambda the
+// barycentric coordinates of the hit and n = E1 x E2 (2D: the edge normal).
+//
+// face_run sets up what depends on the face and the node only (edges, normal,
+// cross products with T = o - v0); link_grad adds the direction.  A grazing
+// link (|D . n| below 2^-10 of |D| |E1| |E2|) takes its barycentrics and
+// denominator in FP64 from the FP32 data.
 template <int D>
-__device__ __forceinline__ void link_grad(const float *rec, int32_t f, const float o[3], const float Dv[3], float w,
-                                          float out[D][D]) {
+struct FaceRun {
+    float e1[3], e2[3], n[3], p1[3], p2[3];   // 3D: edges, normal, T x E2, E1 x T   (T = o - v0)
+    float ee;                                  // |E1| |E2| (2D: |E|)
+};
+
+template <int D>
+__device__ __forceinline__ void face_run(const float *rec, int32_t f, const float o[3], FaceRun<D> &R) {
     float v[dev::kRecFloats<D>];
     dev::load_rec<D>(rec, f, v);
     if constexpr (D == 3) {
         const float e1[3] = {v[3] - v[0], v[4] - v[1], v[5] - v[2]};
         const float e2[3] = {v[6] - v[0], v[7] - v[1], v[8] - v[2]};
         const float T[3] = {o[0] - v[0], o[1] - v[1], o[2] - v[2]};
-        const float n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
-                            e1[0] * e2[1] - e1[1] * e2[0]};
-        const float den = (Dv[0] * n[0] + Dv[1] * n[1]) + Dv[2] * n[2];
-        const float dd = sqrtf((Dv[0] * Dv[0] + Dv[1] * Dv[1]) + Dv[2] * Dv[2]);
-        const float ee = sqrtf((e1[0] * e1[0] + e1[1] * e1[1]) + e1[2] * e1[2]) *
-                         sqrtf((e2[0] * e2[0] + e2[1] * e2[1]) + e2[2] * e2[2]);
-        float u, vv, inv;
-        if (fabsf(den) < 0.0009765625f * dd * ee) {
-            // grazing ray: barycentrics and denominator in FP64 from the FP32 data
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            R.e1[a] = e1[a];
+            R.e2[a] = e2[a];
+        }
+        R.n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        R.n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        R.n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        R.p1[0] = T[1] * e2[2] - T[2] * e2[1];
+        R.p1[1] = T[2] * e2[0] - T[0] * e2[2];
+        R.p1[2] = T[0] * e2[1] - T[1] * e2[0];
+        R.p2[0] = e1[1] * T[2] - e1[2] * T[1];
+        R.p2[1] = e1[2] * T[0] - e1[0] * T[2];
+        R.p2[2] = e1[0] * T[1] - e1[1] * T[0];
+        R.ee = sqrtf((e1[0] * e1[0] + e1[1] * e1[1]) + e1[2] * e1[2]) *
+               sqrtf((e2[0] * e2[0] + e2[1] * e2[1]) + e2[2] * e2[2]);
+    } else {
+        const float e0 = v[2] - v[0], e1 = v[3] - v[1];
+        R.e1[0] = e0;
+        R.e1[1] = e1;
+        R.n[0] = -e1;
+        R.n[1] = e0;
+        R.p1[0] = v[0] - o[0];   // w = a - o
+        R.p1[1] = v[1] - o[1];
+        R.ee = sqrtf(e0 * e0 + e1 * e1);
+    }
+}
+
+// Link of direction Dv (length dd) with weight w against the current run:
+// accumulates w * lambda_k * n / (D . n) into acc[k].
+template <int D>
+__device__ __forceinline__ void link_grad(const float *rec, int32_t f, const float o[3], const FaceRun<D> &R,
+                                          const float Dv[3], float dd, float w, float acc[D][D], bool first) {
+    float lam[D], inv;
+    if constexpr (D == 3) {
+        const float den = (Dv[0] * R.n[0] + Dv[1] * R.n[1]) + Dv[2] * R.n[2];
+        float u, vv;
+        if (fabsf(den) < 0.0009765625f * dd * R.ee) {
+            float v[dev::kRecFloats<D>];
+            dev::load_rec<D>(rec, f, v);
             double E1[3], E2[3], N[3], TT[3];
             for (int a = 0; a < 3; ++a) {
                 E1[a] = (double)v[3 + a] - (double)v[a];
@@ -941,34 +1014,23 @@ __device__ __forceinline__ void link_grad(const float *rec, int32_t f, const flo
             vv = (float)(((double)Dv[0] * P2[0] + (double)Dv[1] * P2[1] + (double)Dv[2] * P2[2]) / den64);
             inv = (float)(1.0 / den64);
         } else {
-            const float p1[3] = {T[1] * e2[2] - T[2] * e2[1], T[2] * e2[0] - T[0] * e2[2],
-                                 T[0] * e2[1] - T[1] * e2[0]};
-            const float p2[3] = {e1[1] * T[2] - e1[2] * T[1], e1[2] * T[0] - e1[0] * T[2],
-                                 e1[0] * T[1] - e1[1] * T[0]};
             inv = 1.0f / den;
-            u = ((Dv[0] * p1[0] + Dv[1] * p1[1]) + Dv[2] * p1[2]) * inv;
-            vv = ((Dv[0] * p2[0] + Dv[1] * p2[1]) + Dv[2] * p2[2]) * inv;
+            u = ((Dv[0] * R.p1[0] + Dv[1] * R.p1[1]) + Dv[2] * R.p1[2]) * inv;
+            vv = ((Dv[0] * R.p2[0] + Dv[1] * R.p2[1]) + Dv[2] * R.p2[2]) * inv;
         }
-        const float lam[3] = {1.0f - u - vv, u, vv};
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const float sc = w * lam[k] * inv;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) out[k][a] = sc * n[a];
-        }
+        lam[0] = 1.0f - u - vv;
+        lam[1] = u;
+        lam[2] = vv;
     } else {
-        const float a0 = v[0], a1 = v[1];
-        const float b0 = v[2], b1 = v[3];
-        const float e0 = b0 - a0, e1 = b1 - a1;
-        const float n[2] = {-e1, e0};
-        const float w0 = a0 - o[0], w1 = a1 - o[1];
-        const float den = Dv[0] * n[0] + Dv[1] * n[1];
-        const float dd = sqrtf(Dv[0] * Dv[0] + Dv[1] * Dv[1]);
-        const float ee = sqrtf(e0 * e0 + e1 * e1);
-        float sp, inv;
-        if (fabsf(den) < 0.0009765625f * dd * ee) {
-            const double E0 = (double)b0 - (double)a0, E1 = (double)b1 - (double)a1;
-            const double W0 = (double)a0 - (double)o[0], W1 = (double)a1 - (double)o[1];
+        const float e0 = R.e1[0], e1 = R.e1[1];
+        const float w0 = R.p1[0], w1 = R.p1[1];
+        const float den = Dv[0] * R.n[0] + Dv[1] * R.n[1];
+        float sp;
+        if (fabsf(den) < 0.0009765625f * dd * R.ee) {
+            float v[dev::kRecFloats<D>];
+            dev::load_rec<D>(rec, f, v);
+            const double E0 = (double)v[2] - (double)v[0], E1 = (double)v[3] - (double)v[1];
+            const double W0 = (double)v[0] - (double)o[0], W1 = (double)v[1] - (double)o[1];
             const double dxe = (double)Dv[0] * E1 - (double)Dv[1] * E0;   // D x e
             sp = (float)((W0 * (double)Dv[1] - W1 * (double)Dv[0]) / dxe);
             inv = (float)(1.0 / ((double)Dv[0] * -E1 + (double)Dv[1] * E0));
@@ -977,39 +1039,68 @@ __device__ __forceinline__ void link_grad(const float *rec, int32_t f, const flo
             sp = (w0 * Dv[1] - w1 * Dv[0]) / dxe;
             inv = 1.0f / den;
         }
-        const float lam[2] = {1.0f - sp, sp};
+        lam[0] = 1.0f - sp;
+        lam[1] = sp;
+    }
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const float sc = w * lam[k] * inv;
-            out[k][0] = sc * n[0];
-            out[k][1] = sc * n[1];
-        }
+    for (int k = 0; k < D; ++k) {
+        const float sc = w * lam[k] * inv;
+#pragma unroll
+        for (int a = 0; a < D; ++a) acc[k][a] = first ? sc * R.n[a] : acc[k][a] + sc * R.n[a];
     }
 }
 
-// One thread per node.  A thread walks only its live directions (bitmask);
-// consecutive contributions to the same face are summed in registers, then
-// per face in an LDS hash table (neighbouring nodes in key order hit few
-// distinct faces), and each face's sums go to its vertices with one float
-// atomic per coordinate.
-// One workgroup of kAdjThreads threads: nodes node0 .. node0 + kAdjThreads - 1 of A.
+// The links of a tile of kAdjThreads nodes: the tile's face and weight rows
+// are one contiguous span, read in 64-slot chunks with coalesced loads (the
+// next chunk in flight while the current one is handled), the waves taking
+// every kAdjWaves-th chunk.  Each wave appends the live slots it reads (a
+// face and a non-zero weight) to a queue of its own and takes 64 at a time,
+// one link per lane, whatever the per-node link counts.  A link's gradient
+// goes to its face in the workgroup's LDS hash table (neighbouring nodes in
+// key order hit few distinct faces), and each face's sums go to its vertices
+// with one float atomic per coordinate at the end.  One workgroup of
+// kAdjThreads threads: nodes node0 .. node0 + kAdjThreads - 1 of A.
 template <int D, int Q>
 __device__ __forceinline__ void adjoint_tile(const AdjArgs<D, Q> &A, int64_t node0) {
     constexpr int CELLS = D == 3 ? 64 : 16;
+    constexpr int QCAP = 2 * dev::kWave;   // below 64 after a take, at most 64 added per chunk
+    static_assert(Q <= 32, "direction index packed in 5 bits");
     __shared__ int32_t s_key[kAdjHash];
     __shared__ float s_acc[kAdjHash][D * D];
-    __shared__ float s_D[Q][3];
-    for (int i = threadIdx.x; i < kAdjHash; i += kAdjThreads) {
+    __shared__ float s_D[Q][4];   // c_i * dx per axis, then its length
+    __shared__ float s_o[kAdjThreads][3];
+    __shared__ uint32_t s_meta[kAdjWaves][QCAP];   // tile-local node * 32 + direction
+    __shared__ int32_t s_qf[kAdjWaves][QCAP];
+    __shared__ float s_qw[kAdjWaves][QCAP];
+    const int tid = threadIdx.x;
+    const int lane = dev::lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane(tid / dev::kWave);
+    for (int i = tid; i < kAdjHash; i += kAdjThreads) {
         s_key[i] = -1;
 #pragma unroll
         for (int c = 0; c < D * D; ++c) s_acc[i][c] = 0.0f;
     }
-    if (threadIdx.x < Q)
-        for (int a = 0; a < 3; ++a) s_D[threadIdx.x][a] = (float)dir_c<D>(threadIdx.x, a) * A.dx[a];
+    if (tid < Q) {
+        float d[3];
+        for (int a = 0; a < 3; ++a) d[a] = (float)dir_c<D>(tid, a) * A.dx[a];
+        for (int a = 0; a < 3; ++a) s_D[tid][a] = d[a];
+        s_D[tid][3] = D == 3 ? sqrtf((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]) : sqrtf(d[0] * d[0] + d[1] * d[1]);
+    }
+    const int nn = (int)min((int64_t)kAdjThreads, A.n - node0);
+    if (tid < nn) {
+        const uint64_t nk = A.node_key[node0 + tid];
+        const uint32_t key = (uint32_t)(nk / CELLS);
+        const int cell = (int)(nk % CELLS);
+        int bc[3];
+        dev::decode_key<D>(key, A.level, A.R[0], A.R[1], bc);
+        s_o[tid][0] = dev::cell_centre(A.lo[0], 4 * bc[0] + (cell & 3), A.dx[0]);
+        s_o[tid][1] = dev::cell_centre(A.lo[1], 4 * bc[1] + ((cell >> 2) & 3), A.dx[1]);
+        s_o[tid][2] = D == 3 ? dev::cell_centre(A.lo[2], 4 * bc[2] + (cell >> 4), A.dx[2]) : 0.0f;
+    }
     __syncthreads();
 
     auto to_lds = [&](int32_t f, const float (&g)[D][D]) {
-        uint32_t h = ((uint32_t)f * 2654435761u) >> 23;   // 9 bits: kAdjHash slots
+        uint32_t h = ((uint32_t)f * 2654435761u) >> (32 - kAdjHashBits);
         for (int probe = 0; probe < kAdjHash; ++probe) {
             const int32_t prev = atomicCAS(&s_key[h], -1, f);
             if (prev == -1 || prev == f) {
@@ -1029,51 +1120,78 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs<D, Q> &A, int64_t nod
             for (int a = 0; a < D; ++a) unsafeAtomicAdd(&A.grad[vk * D + a], g[k][a]);
         }
     };
-
-    const int64_t node = node0 + threadIdx.x;
-    if (node < A.n) {
-        uint32_t live = 0;
-        for (int i = 1; i < Q; ++i)
-            live |= (A.face[node * Q + i] >= 0 && A.gq[node * Q + i] != 0.0f) ? (1u << i) : 0u;
-        if (live) {
-            const uint64_t nk = A.node_key[node];
-            const uint32_t key = (uint32_t)(nk / CELLS);
-            const int cell = (int)(nk % CELLS);
-            int bc[3];
-            dev::decode_key<D>(key, A.level, A.R[0], A.R[1], bc);
-            float o[3];
-            o[0] = dev::cell_centre(A.lo[0], 4 * bc[0] + (cell & 3), A.dx[0]);
-            o[1] = dev::cell_centre(A.lo[1], 4 * bc[1] + ((cell >> 2) & 3), A.dx[1]);
-            o[2] = D == 3 ? dev::cell_centre(A.lo[2], 4 * bc[2] + (cell >> 4), A.dx[2]) : 0.0f;
-            int32_t cur = -1;
-            float acc[D][D];
-            while (live) {
-                const int i = __builtin_ctz(live);
-                live &= live - 1u;
-                const int32_t f = A.face[node * Q + i];
-                const float w = A.gq[node * Q + i];
-                const float Dv[3] = {s_D[i][0], s_D[i][1], s_D[i][2]};
-                float g[D][D];
-                link_grad<D>(A.rec, f, o, Dv, w, g);
-                if (f == cur) {
-#pragma unroll
-                    for (int k = 0; k < D; ++k)
-#pragma unroll
-                        for (int a = 0; a < D; ++a) acc[k][a] += g[k][a];
-                } else {
-                    if (cur >= 0) to_lds(cur, acc);
-                    cur = f;
-#pragma unroll
-                    for (int k = 0; k < D; ++k)
-#pragma unroll
-                        for (int a = 0; a < D; ++a) acc[k][a] = g[k][a];
-                }
-            }
-            if (cur >= 0) to_lds(cur, acc);
+    uint32_t *qm = s_meta[wv];
+    int32_t *qf = s_qf[wv];
+    float *qw = s_qw[wv];
+    int qn = 0;   // wave-uniform queue length
+    // Takes queue entries 0 .. take-1 (one per lane), moves the rest to the
+    // front, then computes the taken links.
+    auto take = [&](int cnt) {
+        dev::wave_sync();
+        const int t = min(cnt, dev::kWave);
+        uint32_t meta = 0;
+        int32_t f = -1;
+        float w = 0.0f;
+        if (lane < t) {
+            meta = qm[lane];
+            f = qf[lane];
+            w = qw[lane];
         }
+        dev::wave_sync();
+        if (lane < cnt - t) {
+            qm[lane] = qm[t + lane];
+            qf[lane] = qf[t + lane];
+            qw[lane] = qw[t + lane];
+        }
+        qn = cnt - t;
+        if (lane < t) {
+            const int nl = (int)(meta >> 5), i = (int)(meta & 31u);
+            const float o[3] = {s_o[nl][0], s_o[nl][1], s_o[nl][2]};
+            const float Dv[3] = {s_D[i][0], s_D[i][1], s_D[i][2]};
+            FaceRun<D> R;
+            face_run<D>(A.rec, f, o, R);
+            float g[D][D];
+            link_grad<D>(A.rec, f, o, R, Dv, s_D[i][3], w, g, true);
+            to_lds(f, g);
+        }
+    };
+
+    const int64_t base = node0 * Q;
+    const int span = nn * Q;
+    const int nch = (span + dev::kWave - 1) / dev::kWave;
+    auto load = [&](int c, int32_t &f, float &w) {
+        const int s = c * dev::kWave + lane;
+        f = -1;
+        w = 0.0f;
+        if (c < nch && s < span) {
+            f = A.face[base + s];
+            w = A.gq[base + s];
+        }
+    };
+    int32_t nf;
+    float nw;
+    load(wv, nf, nw);
+    for (int c = wv; c < nch; c += kAdjWaves) {
+        const int32_t f = nf;
+        const float w = nw;
+        load(c + kAdjWaves, nf, nw);
+        const int s = c * dev::kWave + lane;
+        const int nl = s / Q, i = s - nl * Q;
+        const bool live = i != 0 && f >= 0 && w != 0.0f;
+        const uint64_t m = __ballot(live);
+        if (live) {
+            const int at = qn + dev::lanes_below(m);
+            qm[at] = ((uint32_t)nl << 5) | (uint32_t)i;
+            qf[at] = f;
+            qw[at] = w;
+        }
+        qn += __popcll(m);
+        if (qn >= dev::kWave) take(qn);
     }
+    if (qn > 0) take(qn);
     __syncthreads();
-    for (int sl = threadIdx.x; sl < kAdjHash; sl += kAdjThreads) {
+
+    for (int sl = tid; sl < kAdjHash; sl += kAdjThreads) {
         const int32_t f = s_key[sl];
         if (f < 0) continue;
 #pragma unroll
