@@ -568,7 +568,7 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
     constexpr int CELLS = D == 3 ? 64 : 16;
     constexpr int BPW = 64 / CELLS;
     constexpr int NP = (Q - 1) / 2;            // direction pairs
-    constexpr int NF = D == 3 ? 12 : 4;        // floats staged per face: corners (+ normal in 3D)
+    constexpr int NF = D == 3 ? 15 : 4;   // floats staged per face: corners (3D: + normal, |E1|_1, |E2|_1, S)
     __shared__ float s_f[NF][kLinkCap];
     __shared__ int32_t s_id[kLinkCap];
     __shared__ __align__(16) uint32_t s_code[kLinkCap];
@@ -617,15 +617,17 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
     // the smaller t and, between equal t, the lower face id.
     __shared__ unsigned long long s_best[Q - 1][64];
     __shared__ float s_o[64][3];
-    // FP64 decisions wait in a queue of (lane, staged face, direction pairs)
-    // and are taken 64 at a time, one per lane, whichever lanes queued them.
-    constexpr int TCAP = 128;   // below 64 after a drain, at most 64 added per step
-    __shared__ uint32_t s_task[TCAP];
+    // Work waits in two queues and is taken 64 at a time, one item per lane,
+    // whichever lanes queued it: (lane, staged face) pairs for the FP32
+    // filter, then (lane, staged face, direction pair) for the FP64 decision.
+    constexpr int TCAP = 128;   // below 64 after a take, at most 64 added per step
+    __shared__ uint32_t s_qa[TCAP];
+    __shared__ uint32_t s_qb[TCAP];
 #pragma unroll
     for (int i = 0; i < Q - 1; ++i) s_best[i][lane] = ~0ull;
 #pragma unroll
     for (int a = 0; a < 3; ++a) s_o[lane][a] = o[a];
-    int ntask = 0;   // wave-uniform
+    int na = 0, nb = 0;   // wave-uniform queue lengths
 
     // A hit at t64 for direction i of lane l.  t is decided in FP64 and kept
     // rounded to FP32 (a negative zero as zero).
@@ -636,16 +638,15 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
         atomicMin(&s_best[i][l], k);
     };
 
-    // FP64 decisions for staged face j and the direction pairs in cm, against
-    // the link origin of lane l: the segment-triangle test in the same
-    // expression order as the definition (Moller-Trumbore), so both directions
-    // of a pair come out exactly as separate evaluations would (negating D
-    // negates P, det and t exactly).  What depends on the face and the origin
-    // only (edges, T, Q = T x E1 and E2 . Q) is formed once for all pairs.
-    auto decide_task = [&](uint32_t task) {
-        const int l = (int)(task >> 20);
-        const int j = (int)((task >> 13) & 127u);
-        uint32_t cm = task & 0x1FFFu;
+    // FP64 decision for staged face j, direction pair p and the link origin
+    // of lane l: the segment-triangle test in the same expression order as
+    // the definition (Moller-Trumbore), so both directions of the pair come
+    // out exactly as separate evaluations would (negating D negates P, det
+    // and t exactly).
+    auto decide = [&](uint32_t item) {
+        const int l = (int)(item >> 20);
+        const int j = (int)((item >> 13) & 127u);
+        const int p = (int)(item & 31u);
         const int32_t f = s_id[j];
         const double o0 = s_o[l][0], o1 = s_o[l][1];
         if constexpr (D == 3) {
@@ -654,68 +655,58 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
             const double E1[3] = {(double)s_f[3][j] - a0, (double)s_f[4][j] - a1, (double)s_f[5][j] - a2};
             const double E2[3] = {(double)s_f[6][j] - a0, (double)s_f[7][j] - a1, (double)s_f[8][j] - a2};
             const double T[3] = {o0 - a0, o1 - a1, o2 - a2};
+            const double Dv[3] = {(double)s_dir[p][0], (double)s_dir[p][1], (double)s_dir[p][2]};
+            const double P[3] = {Dv[1] * E2[2] - Dv[2] * E2[1], Dv[2] * E2[0] - Dv[0] * E2[2],
+                                 Dv[0] * E2[1] - Dv[1] * E2[0]};
+            const double det = E1[0] * P[0] + E1[1] * P[1] + E1[2] * P[2];
+            if (det == 0.0) return;
+            const double u = (T[0] * P[0] + T[1] * P[1] + T[2] * P[2]) / det;
+            if (u < 0.0 || u > 1.0) return;
             const double Qv[3] = {T[1] * E1[2] - T[2] * E1[1], T[2] * E1[0] - T[0] * E1[2], T[0] * E1[1] - T[1] * E1[0]};
-            const double tn = E2[0] * Qv[0] + E2[1] * Qv[1] + E2[2] * Qv[2];
-            while (cm) {
-                const int p = __builtin_ctz(cm);
-                cm &= cm - 1u;
-                const double Dv[3] = {(double)s_dir[p][0], (double)s_dir[p][1], (double)s_dir[p][2]};
-                const double P[3] = {Dv[1] * E2[2] - Dv[2] * E2[1], Dv[2] * E2[0] - Dv[0] * E2[2],
-                                     Dv[0] * E2[1] - Dv[1] * E2[0]};
-                const double det = E1[0] * P[0] + E1[1] * P[1] + E1[2] * P[2];
-                if (det == 0.0) continue;
-                const double u = (T[0] * P[0] + T[1] * P[1] + T[2] * P[2]) / det;
-                if (u < 0.0 || u > 1.0) continue;
-                const double v = (Dv[0] * Qv[0] + Dv[1] * Qv[1] + Dv[2] * Qv[2]) / det;
-                if (v < 0.0 || u + v > 1.0) continue;
-                const double t = tn / det;
-                consider(2 * p, l, t, f);        // direction 1 + 2p
-                consider(2 * p + 1, l, -t, f);   // its opposite
-            }
+            const double v = (Dv[0] * Qv[0] + Dv[1] * Qv[1] + Dv[2] * Qv[2]) / det;
+            if (v < 0.0 || u + v > 1.0) return;
+            const double t = (E2[0] * Qv[0] + E2[1] * Qv[1] + E2[2] * Qv[2]) / det;
+            consider(2 * p, l, t, f);        // direction 1 + 2p
+            consider(2 * p + 1, l, -t, f);   // its opposite
         } else {
             const double a0 = s_f[0][j], a1 = s_f[1][j];
             const double e0 = (double)s_f[2][j] - a0, e1 = (double)s_f[3][j] - a1;
+            const double D0 = (double)s_dir[p][0], D1 = (double)s_dir[p][1];
+            const double den = D0 * e1 - D1 * e0;
+            if (den == 0.0) return;
             const double w0 = a0 - o0, w1 = a1 - o1;
-            const double tn = w0 * e1 - w1 * e0;
-            while (cm) {
-                const int p = __builtin_ctz(cm);
-                cm &= cm - 1u;
-                const double D0 = (double)s_dir[p][0], D1 = (double)s_dir[p][1];
-                const double den = D0 * e1 - D1 * e0;
-                if (den == 0.0) continue;
-                const double t = tn / den;
-                const double sp = (w0 * D1 - w1 * D0) / den;
-                if (!(sp >= 0.0 && sp <= 1.0)) continue;
-                consider(2 * p, l, t, f);
-                consider(2 * p + 1, l, -t, f);
-            }
+            const double t = (w0 * e1 - w1 * e0) / den;
+            const double sp = (w0 * D1 - w1 * D0) / den;
+            if (!(sp >= 0.0 && sp <= 1.0)) return;
+            consider(2 * p, l, t, f);
+            consider(2 * p + 1, l, -t, f);
         }
     };
-    // Takes queued decisions 0 .. take-1, one per lane, and moves the rest to
-    // the front.  Wave-uniform.
-    auto drain = [&](int take) {
+    auto take_b = [&](int take) {   // wave-uniform
         __syncthreads();
-        const uint32_t task = lane < take ? s_task[lane] : 0u;
+        const uint32_t item = lane < take ? s_qb[lane] : 0u;
         __syncthreads();
-        if (lane < ntask - take) s_task[lane] = s_task[take + lane];
-        ntask -= take;
-        if (lane < take) decide_task(task);
+        if (lane < nb - take) s_qb[lane] = s_qb[take + lane];
+        nb -= take;
+        if (lane < take) decide(item);
     };
 
-    // FP32 filter of one (lane, staged face) over all direction pairs: the
-    // pairs whose segment may meet the face.  Each quantity carries an absolute
-    // rounding error bounded by 2^-21 times the product of the L1 norms of its
-    // factors; margins of 2^-20 times those products keep every true hit.
-    auto filter = [&](int j) -> uint32_t {
+    // FP32 filter of staged face j for a link origin o over all direction
+    // pairs: the pairs whose segment may meet the face.  Each quantity carries
+    // an absolute rounding error bounded by 2^-21 times the product of the L1
+    // norms of its factors; margins of 2^-20 times those products keep every
+    // true hit.  A pair needs |t| <= 1 on the face's plane, |T . n| <= |D . n|
+    // (within margins), and, unless D . n is too small to have a known sign,
+    // barycentrics inside the face.
+    auto filter = [&](int j, const float (&o)[3]) -> uint32_t {
         uint32_t cm = 0;
         if constexpr (D == 3) {
             const float T0 = o[0] - s_f[0][j], T1 = o[1] - s_f[1][j], T2 = o[2] - s_f[2][j];
             const float e10 = s_f[3][j] - s_f[0][j], e11 = s_f[4][j] - s_f[1][j], e12 = s_f[5][j] - s_f[2][j];
             const float e20 = s_f[6][j] - s_f[0][j], e21 = s_f[7][j] - s_f[1][j], e22 = s_f[8][j] - s_f[2][j];
             const float n0 = s_f[9][j], n1 = s_f[10][j], n2 = s_f[11][j];
+            const float n1n = s_f[12][j], n2n = s_f[13][j];
             const float nT = fabsf(T0) + fabsf(T1) + fabsf(T2);
-            const float n1n = fabsf(e10) + fabsf(e11) + fabsf(e12);
-            const float n2n = fabsf(e20) + fabsf(e21) + fabsf(e22);
             const float mx_ = fmaxf(fmaxf(A.dx[0], A.dx[1]), A.dx[2]) * 9.5367431640625e-07f;  // dx * 2^-20
             const float MU = mx_ * nT * n2n;
             const float MV = mx_ * n1n * nT;
@@ -728,7 +719,7 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
             const float p21 = (e12 * T0 - e10 * T2) * A.dx[1];
             const float p22 = (e10 * T1 - e11 * T0) * A.dx[2];
             const float d0 = n0 * A.dx[0], d1 = n1 * A.dx[1], d2 = n2 * A.dx[2];
-            const float tn = (T0 * n0 + T1 * n1) + T2 * n2;
+            const float atn = fabsf((T0 * n0 + T1 * n1) + T2 * n2);
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const int i = 1 + 2 * p;
@@ -737,16 +728,13 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
                 if (c0) { den += c0 > 0 ? d0 : -d0; nu += c0 > 0 ? p10 : -p10; nv += c0 > 0 ? p20 : -p20; }
                 if (c1) { den += c1 > 0 ? d1 : -d1; nu += c1 > 0 ? p11 : -p11; nv += c1 > 0 ? p21 : -p21; }
                 if (c2) { den += c2 > 0 ? d2 : -d2; nu += c2 > 0 ? p12 : -p12; nv += c2 > 0 ? p22 : -p22; }
-                // |den| <= MD: grazing, the sign of the denominator is not known in FP32
                 const float ad = fabsf(den);
                 const bool neg = den < 0.0f;
                 const float su = neg ? -nu : nu;
                 const float sv = neg ? -nv : nv;
-                const float st = neg ? tn : -tn;   // sign(den) * (-tn) = t * |den|
-                const float lim = ad + MD + MT;
-                const bool in = (su >= -MU) & (sv >= -MV) & (su + sv <= ad + MU + MV + MD) &
-                                (((st >= -MT) & (st <= lim)) | ((-st >= -MT) & (-st <= lim)));
-                cm |= ((ad <= MD) | in) ? (1u << p) : 0u;
+                const bool t_ok = atn <= ad + MD + MT;
+                const bool bary = (su >= -MU) & (sv >= -MV) & (su + sv <= ad + MU + MV + MD);
+                cm |= (t_ok & ((ad <= MD) | bary)) ? (1u << p) : 0u;
             }
         } else {
             const float w0 = s_f[0][j] - o[0], w1 = s_f[1][j] - o[1];
@@ -754,7 +742,7 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
             const float nw = fabsf(w0) + fabsf(w1), ne = fabsf(e0) + fabsf(e1);
             const float mx_ = fmaxf(A.dx[0], A.dx[1]) * 9.5367431640625e-07f;
             const float MD = mx_ * ne, MS = mx_ * nw, MW = 9.5367431640625e-07f * nw * ne;
-            const float wxe = w0 * e1 - w1 * e0;
+            const float awxe = fabsf(w0 * e1 - w1 * e0);
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const int i = 1 + 2 * p;
@@ -762,22 +750,61 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
                 const float den = D0 * e1 - D1 * e0;
                 const float ad = fabsf(den);
                 const float sn = w0 * D1 - w1 * D0;
-                const bool neg = den < 0.0f;
-                const float ss = neg ? -sn : sn;
-                const float st = neg ? -wxe : wxe;
-                const float lim = ad + MD + MW;
-                const bool in = (ss >= -MS) & (ss <= ad + MS + MD) &
-                                (((st >= -MW) & (st <= lim)) | ((-st >= -MW) & (-st <= lim)));
-                cm |= ((ad <= MD) | in) ? (1u << p) : 0u;
+                const float ss = den < 0.0f ? -sn : sn;
+                const bool t_ok = awxe <= ad + MD + MW;
+                const bool seg = (ss >= -MS) & (ss <= ad + MS + MD);
+                cm |= (t_ok & ((ad <= MD) | seg)) ? (1u << p) : 0u;
             }
         }
         return cm;
     };
+    // Whether any direction pair can pass the filter for staged face j and
+    // this lane's origin: the filter's |t| test with the largest |D . n| of any
+    // direction, S = sum |n_a dx_a| (3D; always in 2D).
+    auto reach = [&](int j) -> bool {
+        if constexpr (D == 3) {
+            const float T0 = o[0] - s_f[0][j], T1 = o[1] - s_f[1][j], T2 = o[2] - s_f[2][j];
+            const float n0 = s_f[9][j], n1 = s_f[10][j], n2 = s_f[11][j];
+            const float n1n = s_f[12][j], n2n = s_f[13][j], S = s_f[14][j];
+            const float nT = fabsf(T0) + fabsf(T1) + fabsf(T2);
+            const float mx_ = fmaxf(fmaxf(A.dx[0], A.dx[1]), A.dx[2]) * 9.5367431640625e-07f;
+            const float MD = mx_ * n1n * n2n;
+            const float MT = 9.5367431640625e-07f * nT * n1n * n2n;
+            return fabsf((T0 * n0 + T1 * n1) + T2 * n2) <= S + MD + MT;
+        } else {
+            return true;
+        }
+    };
+    auto take_a = [&](int take) {   // wave-uniform
+        __syncthreads();
+        const uint32_t item = lane < take ? s_qa[lane] : 0u;
+        __syncthreads();
+        if (lane < na - take) s_qa[lane] = s_qa[take + lane];
+        na -= take;
+        const int l = (int)(item >> 7), j = (int)(item & 127u);
+        uint32_t cm = 0;
+        if (lane < take) {
+            const float ol[3] = {s_o[l][0], s_o[l][1], s_o[l][2]};
+            cm = filter(j, ol);
+        }
+        while (__ballot(cm != 0)) {
+            const bool has = cm != 0;
+            int p = 0;
+            if (has) {
+                p = __builtin_ctz(cm);
+                cm &= cm - 1u;
+            }
+            const uint64_t m = __ballot(has);
+            if (has) s_qb[nb + dev::lanes_below(m)] = ((uint32_t)l << 20) | ((uint32_t)j << 13) | (uint32_t)p;
+            nb += __popcll(m);
+            if (nb >= 64) take_b(64);
+        }
+    };
 
-    // Staged faces are visited in batches of 64: each lane first marks the faces
-    // whose box meets its link box (broadcast LDS reads), then filters its own
-    // marked faces one per step; the (face, pairs) that pass are queued, and
-    // whenever 64 are queued the whole wave takes them.
+    // Staged faces are visited in batches of 64: each lane marks the faces
+    // whose box meets its link box (broadcast LDS reads), then queues its own
+    // marked faces that its links can reach.  Both queues are emptied before
+    // the staging area is refilled.
     auto test_staged = [&](int n) {
         __syncthreads();
         for (int j0 = 0; j0 < n; j0 += 64) {
@@ -792,20 +819,21 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
                     nm |= ((cs[u] & lbits) == lbits && jj + u < jn) ? (1ull << (jj + u)) : 0ull;
             }
             while (__ballot(nm != 0)) {
-                uint32_t cm = 0;
+                bool pass = false;
                 int j = 0;
                 if (nm) {
                     j = j0 + __builtin_ctzll(nm);
                     nm &= nm - 1ull;
-                    cm = filter(j);
+                    pass = reach(j);
                 }
-                const uint64_t want = __ballot(cm != 0);
-                if (cm) s_task[ntask + dev::lanes_below(want)] = ((uint32_t)lane << 20) | ((uint32_t)j << 13) | cm;
-                ntask += __popcll(want);
-                if (ntask >= 64) drain(64);
+                const uint64_t m = __ballot(pass);
+                if (pass) s_qa[na + dev::lanes_below(m)] = ((uint32_t)lane << 7) | (uint32_t)j;
+                na += __popcll(m);
+                if (na >= 64) take_a(64);
             }
         }
-        if (ntask > 0) drain(ntask);
+        if (na > 0) take_a(na);
+        if (nb > 0) take_b(nb);
         __syncthreads();
     };
 
@@ -863,9 +891,15 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
                     const float e20 = v[6] - v[0], e21 = v[7] - v[1], e22 = v[8] - v[2];
 #pragma unroll
                     for (int k = 0; k < 9; ++k) s_f[k][pos] = v[k];
-                    s_f[9][pos] = e11 * e22 - e12 * e21;
-                    s_f[10][pos] = e12 * e20 - e10 * e22;
-                    s_f[11][pos] = e10 * e21 - e11 * e20;
+                    const float n0 = e11 * e22 - e12 * e21;
+                    const float n1 = e12 * e20 - e10 * e22;
+                    const float n2 = e10 * e21 - e11 * e20;
+                    s_f[9][pos] = n0;
+                    s_f[10][pos] = n1;
+                    s_f[11][pos] = n2;
+                    s_f[12][pos] = fabsf(e10) + fabsf(e11) + fabsf(e12);
+                    s_f[13][pos] = fabsf(e20) + fabsf(e21) + fabsf(e22);
+                    s_f[14][pos] = fabsf(n0 * A.dx[0]) + fabsf(n1 * A.dx[1]) + fabsf(n2 * A.dx[2]);
                 } else {
 #pragma unroll
                     for (int k = 0; k < 4; ++k) s_f[k][pos] = r[k];
@@ -931,27 +965,48 @@ struct AdjArgs {
 
 constexpr int kAdjThreads = 256;   // nodes per tile = threads per workgroup
 constexpr int kAdjWaves = kAdjThreads / 64;
-constexpr int kAdjHashBits = 8;
+constexpr int kAdjGroup = 4;      // chunks of 64 slots per wave per step
+constexpr int kAdjHashBits = 9;
 constexpr int kAdjHash = 1 << kAdjHashBits;   // per-workgroup face accumulators
 
 // Gradient of one link's t with respect to the D vertices of its face, scaled
-// by the link's weight w: out[k][a] = w * lambda_k * n_a / (D . n), lambda the
-// barycentric coordinates of the hit and n = E1 x E2 (2D: the edge normal).
+// by the link's weight w: out[k][a] = s_k n_a with s_k = w lambda_k / (D . n),
+// lambda the barycentric coordinates of the hit and n = E1 x E2 (2D: the edge
+// normal).  n belongs to the face, so the links of one face are summed as the
+// D scalars s_k and multiplied by n once.
 //
-// face_run sets up what depends on the face and the node only (edges, normal,
-// cross products with T = o - v0); link_grad adds the direction.  A grazing
-// link (|D . n| below 2^-10 of |D| |E1| |E2|) takes its barycentrics and
-// denominator in FP64 from the FP32 data.
+// face_normal is the one expression of n (per link and at the final scatter).
+// link_setup sets up what depends on the face and the node only (edges,
+// normal, cross products with T = o - v0); link_scalars adds the direction.
+// A grazing link (|D . n| below 2^-10 of |D| |E1| |E2|) takes its barycentrics
+// and denominator in FP64 from the FP32 data.
 template <int D>
-struct FaceRun {
+__device__ __forceinline__ void face_normal(const float *v, float n[3]) {
+    if constexpr (D == 3) {
+        const float e1[3] = {v[3] - v[0], v[4] - v[1], v[5] - v[2]};
+        const float e2[3] = {v[6] - v[0], v[7] - v[1], v[8] - v[2]};
+        n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    } else {
+        n[0] = -(v[3] - v[1]);
+        n[1] = v[2] - v[0];
+        n[2] = 0.0f;
+    }
+}
+
+template <int D>
+struct LinkFace {
+    float v[dev::kRecFloats<D>];               // the face record
     float e1[3], e2[3], n[3], p1[3], p2[3];   // 3D: edges, normal, T x E2, E1 x T   (T = o - v0)
     float ee;                                  // |E1| |E2| (2D: |E|)
 };
 
 template <int D>
-__device__ __forceinline__ void face_run(const float *rec, int32_t f, const float o[3], FaceRun<D> &R) {
-    float v[dev::kRecFloats<D>];
-    dev::load_rec<D>(rec, f, v);
+__device__ __forceinline__ void link_setup(const float *rec, int32_t f, const float o[3], LinkFace<D> &R) {
+    dev::load_rec<D>(rec, f, R.v);
+    const float *v = R.v;
+    face_normal<D>(v, R.n);
     if constexpr (D == 3) {
         const float e1[3] = {v[3] - v[0], v[4] - v[1], v[5] - v[2]};
         const float e2[3] = {v[6] - v[0], v[7] - v[1], v[8] - v[2]};
@@ -961,9 +1016,6 @@ __device__ __forceinline__ void face_run(const float *rec, int32_t f, const floa
             R.e1[a] = e1[a];
             R.e2[a] = e2[a];
         }
-        R.n[0] = e1[1] * e2[2] - e1[2] * e2[1];
-        R.n[1] = e1[2] * e2[0] - e1[0] * e2[2];
-        R.n[2] = e1[0] * e2[1] - e1[1] * e2[0];
         R.p1[0] = T[1] * e2[2] - T[2] * e2[1];
         R.p1[1] = T[2] * e2[0] - T[0] * e2[2];
         R.p1[2] = T[0] * e2[1] - T[1] * e2[0];
@@ -976,26 +1028,22 @@ __device__ __forceinline__ void face_run(const float *rec, int32_t f, const floa
         const float e0 = v[2] - v[0], e1 = v[3] - v[1];
         R.e1[0] = e0;
         R.e1[1] = e1;
-        R.n[0] = -e1;
-        R.n[1] = e0;
         R.p1[0] = v[0] - o[0];   // w = a - o
         R.p1[1] = v[1] - o[1];
         R.ee = sqrtf(e0 * e0 + e1 * e1);
     }
 }
 
-// Link of direction Dv (length dd) with weight w against the current run:
-// accumulates w * lambda_k * n / (D . n) into acc[k].
+// Link of direction Dv (length dd) with weight w: s[k] = w * lambda_k / (D . n).
 template <int D>
-__device__ __forceinline__ void link_grad(const float *rec, int32_t f, const float o[3], const FaceRun<D> &R,
-                                          const float Dv[3], float dd, float w, float acc[D][D], bool first) {
+__device__ __forceinline__ void link_scalars(const float o[3], const LinkFace<D> &R, const float Dv[3], float dd,
+                                             float w, float s[D]) {
     float lam[D], inv;
+    const float *v = R.v;
     if constexpr (D == 3) {
         const float den = (Dv[0] * R.n[0] + Dv[1] * R.n[1]) + Dv[2] * R.n[2];
         float u, vv;
         if (fabsf(den) < 0.0009765625f * dd * R.ee) {
-            float v[dev::kRecFloats<D>];
-            dev::load_rec<D>(rec, f, v);
             double E1[3], E2[3], N[3], TT[3];
             for (int a = 0; a < 3; ++a) {
                 E1[a] = (double)v[3 + a] - (double)v[a];
@@ -1027,8 +1075,6 @@ __device__ __forceinline__ void link_grad(const float *rec, int32_t f, const flo
         const float den = Dv[0] * R.n[0] + Dv[1] * R.n[1];
         float sp;
         if (fabsf(den) < 0.0009765625f * dd * R.ee) {
-            float v[dev::kRecFloats<D>];
-            dev::load_rec<D>(rec, f, v);
             const double E0 = (double)v[2] - (double)v[0], E1 = (double)v[3] - (double)v[1];
             const double W0 = (double)v[0] - (double)o[0], W1 = (double)v[1] - (double)o[1];
             const double dxe = (double)Dv[0] * E1 - (double)Dv[1] * E0;   // D x e
@@ -1043,42 +1089,40 @@ __device__ __forceinline__ void link_grad(const float *rec, int32_t f, const flo
         lam[1] = sp;
     }
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        const float sc = w * lam[k] * inv;
-#pragma unroll
-        for (int a = 0; a < D; ++a) acc[k][a] = first ? sc * R.n[a] : acc[k][a] + sc * R.n[a];
-    }
+    for (int k = 0; k < D; ++k) s[k] = w * lam[k] * inv;
 }
 
 // The links of a tile of kAdjThreads nodes: the tile's face and weight rows
-// are one contiguous span, read in 64-slot chunks with coalesced loads (the
-// next chunk in flight while the current one is handled), the waves taking
-// every kAdjWaves-th chunk.  Each wave appends the live slots it reads (a
+// are one contiguous span, read in 64-slot chunks with coalesced loads, the
+// waves taking every kAdjWaves-th chunk, kAdjGroup chunks at a time with the
+// next group's loads in flight.  Each wave appends the live slots it reads (a
 // face and a non-zero weight) to a queue of its own and takes 64 at a time,
-// one link per lane, whatever the per-node link counts.  A link's gradient
-// goes to its face in the workgroup's LDS hash table (neighbouring nodes in
-// key order hit few distinct faces), and each face's sums go to its vertices
-// with one float atomic per coordinate at the end.  One workgroup of
-// kAdjThreads threads: nodes node0 .. node0 + kAdjThreads - 1 of A.
+// one link per lane, whatever the per-node link counts.  Queue order is slot
+// order, so the links of one face tend to sit in neighbouring lanes: a
+// segmented sum over runs of equal face ids leaves one lane per run, which
+// adds the run's D scalars to the face's entry of the workgroup's LDS hash
+// table (neighbouring nodes in key order hit few distinct faces).  At the end
+// each face's sums, times its normal, go to its vertices with one float atomic
+// per coordinate.  One workgroup of kAdjThreads threads: nodes node0 ..
+// node0 + kAdjThreads - 1 of A.
 template <int D, int Q>
 __device__ __forceinline__ void adjoint_tile(const AdjArgs<D, Q> &A, int64_t node0) {
     constexpr int CELLS = D == 3 ? 64 : 16;
-    constexpr int QCAP = 2 * dev::kWave;   // below 64 after a take, at most 64 added per chunk
+    constexpr int QCAP = (kAdjGroup + 1) * dev::kWave;   // below 64 after the takes, 64 per chunk added
     static_assert(Q <= 32, "direction index packed in 5 bits");
     __shared__ int32_t s_key[kAdjHash];
-    __shared__ float s_acc[kAdjHash][D * D];
+    __shared__ float s_acc[kAdjHash][D];
     __shared__ float s_D[Q][4];   // c_i * dx per axis, then its length
     __shared__ float s_o[kAdjThreads][3];
     __shared__ uint32_t s_meta[kAdjWaves][QCAP];   // tile-local node * 32 + direction
     __shared__ int32_t s_qf[kAdjWaves][QCAP];
-    __shared__ float s_qw[kAdjWaves][QCAP];
     const int tid = threadIdx.x;
     const int lane = dev::lane_id();
     const int wv = __builtin_amdgcn_readfirstlane(tid / dev::kWave);
     for (int i = tid; i < kAdjHash; i += kAdjThreads) {
         s_key[i] = -1;
 #pragma unroll
-        for (int c = 0; c < D * D; ++c) s_acc[i][c] = 0.0f;
+        for (int k = 0; k < D; ++k) s_acc[i][k] = 0.0f;
     }
     if (tid < Q) {
         float d[3];
@@ -1099,94 +1143,121 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs<D, Q> &A, int64_t nod
     }
     __syncthreads();
 
-    auto to_lds = [&](int32_t f, const float (&g)[D][D]) {
+    // Scalars s of face f (normal n) into the hash table; a full table sends
+    // s_k n straight to the vertices.
+    auto to_lds = [&](int32_t f, const float (&s)[D], const float (&n)[3]) {
         uint32_t h = ((uint32_t)f * 2654435761u) >> (32 - kAdjHashBits);
         for (int probe = 0; probe < kAdjHash; ++probe) {
             const int32_t prev = atomicCAS(&s_key[h], -1, f);
             if (prev == -1 || prev == f) {
 #pragma unroll
-                for (int k = 0; k < D; ++k)
-#pragma unroll
-                    for (int a = 0; a < D; ++a) atomicAdd(&s_acc[h][k * D + a], g[k][a]);
+                for (int k = 0; k < D; ++k) atomicAdd(&s_acc[h][k], s[k]);
                 return;
             }
             h = (h + 1) & (kAdjHash - 1);
         }
-        // table full: straight to the vertices
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const int64_t vk = A.fidx[(int64_t)f * D + k];
 #pragma unroll
-            for (int a = 0; a < D; ++a) unsafeAtomicAdd(&A.grad[vk * D + a], g[k][a]);
+            for (int a = 0; a < D; ++a) unsafeAtomicAdd(&A.grad[vk * D + a], s[k] * n[a]);
         }
     };
     uint32_t *qm = s_meta[wv];
     int32_t *qf = s_qf[wv];
-    float *qw = s_qw[wv];
+    const int64_t base = node0 * Q;
     int qn = 0;   // wave-uniform queue length
     // Takes queue entries 0 .. take-1 (one per lane), moves the rest to the
-    // front, then computes the taken links.
+    // front, computes the taken links and sums them per run of equal faces.
     auto take = [&](int cnt) {
         dev::wave_sync();
         const int t = min(cnt, dev::kWave);
         uint32_t meta = 0;
         int32_t f = -1;
-        float w = 0.0f;
         if (lane < t) {
             meta = qm[lane];
             f = qf[lane];
-            w = qw[lane];
         }
         dev::wave_sync();
         if (lane < cnt - t) {
             qm[lane] = qm[t + lane];
             qf[lane] = qf[t + lane];
-            qw[lane] = qw[t + lane];
         }
         qn = cnt - t;
+        float s[D], n[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int k = 0; k < D; ++k) s[k] = 0.0f;
         if (lane < t) {
             const int nl = (int)(meta >> 5), i = (int)(meta & 31u);
+            const float w = A.gq[base + nl * Q + i];   // read again (just fetched): keeps queue entries at 8 B
             const float o[3] = {s_o[nl][0], s_o[nl][1], s_o[nl][2]};
             const float Dv[3] = {s_D[i][0], s_D[i][1], s_D[i][2]};
-            FaceRun<D> R;
-            face_run<D>(A.rec, f, o, R);
-            float g[D][D];
-            link_grad<D>(A.rec, f, o, R, Dv, s_D[i][3], w, g, true);
-            to_lds(f, g);
+            LinkFace<D> R;
+            link_setup<D>(A.rec, f, o, R);
+            link_scalars<D>(o, R, Dv, s_D[i][3], w, s);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) n[a] = R.n[a];
         }
+        // segmented inclusive sum over runs of equal f (every lane active here)
+        const int32_t fp = __shfl_up(f, 1, dev::kWave);
+        const uint64_t heads = __ballot(lane == 0 || fp != f);
+        const uint64_t upto = (2ull << lane) - 1ull;   // lanes 0 .. lane (all 64 at lane 63)
+        const int start = 63 - __clzll(heads & upto);
+        for (int d = 1; d < dev::kWave; d <<= 1) {
+            const bool use = lane - d >= start;
+            if (!__ballot(use)) break;
+            float up[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) up[k] = __shfl_up(s[k], d, dev::kWave);
+            if (use)
+#pragma unroll
+                for (int k = 0; k < D; ++k) s[k] += up[k];
+        }
+        const bool tail = lane == dev::kWave - 1 || (((heads >> lane) >> 1) & 1ull);
+        if (tail && f >= 0) to_lds(f, s, n);
     };
 
-    const int64_t base = node0 * Q;
     const int span = nn * Q;
     const int nch = (span + dev::kWave - 1) / dev::kWave;
-    auto load = [&](int c, int32_t &f, float &w) {
-        const int s = c * dev::kWave + lane;
-        f = -1;
-        w = 0.0f;
-        if (c < nch && s < span) {
-            f = A.face[base + s];
-            w = A.gq[base + s];
+    constexpr int STEP = kAdjWaves * kAdjGroup;   // chunks per group over the workgroup
+    int32_t nf[kAdjGroup];
+    float nw[kAdjGroup];
+    auto load = [&](int c0) {   // chunks c0, c0 + kAdjWaves, ... of this wave
+#pragma unroll
+        for (int g = 0; g < kAdjGroup; ++g) {
+            const int s = (c0 + g * kAdjWaves) * dev::kWave + lane;
+            nf[g] = -1;
+            nw[g] = 0.0f;
+            if (s < span) {
+                nf[g] = A.face[base + s];
+                nw[g] = A.gq[base + s];
+            }
         }
     };
-    int32_t nf;
-    float nw;
-    load(wv, nf, nw);
-    for (int c = wv; c < nch; c += kAdjWaves) {
-        const int32_t f = nf;
-        const float w = nw;
-        load(c + kAdjWaves, nf, nw);
-        const int s = c * dev::kWave + lane;
-        const int nl = s / Q, i = s - nl * Q;
-        const bool live = i != 0 && f >= 0 && w != 0.0f;
-        const uint64_t m = __ballot(live);
-        if (live) {
-            const int at = qn + dev::lanes_below(m);
-            qm[at] = ((uint32_t)nl << 5) | (uint32_t)i;
-            qf[at] = f;
-            qw[at] = w;
+    load(wv);
+    for (int c0 = wv; c0 < nch; c0 += STEP) {
+        int32_t f[kAdjGroup];
+        float w[kAdjGroup];
+#pragma unroll
+        for (int g = 0; g < kAdjGroup; ++g) {
+            f[g] = nf[g];
+            w[g] = nw[g];
         }
-        qn += __popcll(m);
-        if (qn >= dev::kWave) take(qn);
+        if (c0 + STEP < nch) load(c0 + STEP);
+#pragma unroll
+        for (int g = 0; g < kAdjGroup; ++g) {
+            const int s = (c0 + g * kAdjWaves) * dev::kWave + lane;
+            const int nl = s / Q, i = s - nl * Q;
+            const bool live = i != 0 && f[g] >= 0 && w[g] != 0.0f;   // false past the span (f = -1)
+            const uint64_t m = __ballot(live);
+            if (live) {
+                const int at = qn + dev::lanes_below(m);
+                qm[at] = ((uint32_t)nl << 5) | (uint32_t)i;
+                qf[at] = f[g];
+            }
+            qn += __popcll(m);
+        }
+        while (qn >= dev::kWave) take(qn);
     }
     if (qn > 0) take(qn);
     __syncthreads();
@@ -1194,11 +1265,15 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs<D, Q> &A, int64_t nod
     for (int sl = tid; sl < kAdjHash; sl += kAdjThreads) {
         const int32_t f = s_key[sl];
         if (f < 0) continue;
+        float v[dev::kRecFloats<D>], n[3];
+        dev::load_rec<D>(A.rec, f, v);
+        face_normal<D>(v, n);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const int64_t vk = A.fidx[(int64_t)f * D + k];
+            const float sk = s_acc[sl][k];
 #pragma unroll
-            for (int a = 0; a < D; ++a) unsafeAtomicAdd(&A.grad[vk * D + a], s_acc[sl][k * D + a]);
+            for (int a = 0; a < D; ++a) unsafeAtomicAdd(&A.grad[vk * D + a], sk * n[a]);
         }
     }
     __syncthreads();
