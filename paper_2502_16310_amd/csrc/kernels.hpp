@@ -541,7 +541,7 @@ __device__ __forceinline__ void children_item(const uint32_t *mk, const uint32_t
 // ===========================================================================
 // Link fractions and their adjoint (paper Sec. II-C-1)
 // ===========================================================================
-constexpr int kLinkCap = 128;  // staged faces per wave
+constexpr int kLinkCap = 32;   // staged faces per wave (LDS per wave bounds occupancy)
 
 template <int D, int Q>
 struct LinkArgs {
