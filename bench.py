@@ -171,6 +171,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="C1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the one-body graph timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the reference kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters into bytes")
@@ -286,6 +287,7 @@ def main():
     agal.agal_profile_enable(ctx, False)
     prof = agal.agal_profile_read(ctx)
     ms_profiled = (tp1 - tp0) * 1e3 / args.steps
+    graph = None if args.no_graph else graph_step(args, agal, torch, wl, v, f, w_host, n_nodes, T)
     pass_ms_median = pass_ev[len(pass_ev) // 2]
     grad_step_median = grad_ev[len(grad_ev) // 2]
     copy_gbs = copy_bandwidth(torch, dev)
@@ -310,7 +312,7 @@ def main():
         "config": {"workload": f"{wl.name}: " + describe(wl), "faces": F, "roots": list(wl.roots[:dim]),
                    "levels": wl.levels, "bins": wl.bins, "lattice": f"D{dim}Q{Q}", "global_batch": 1,
                    "seq_len": 0, "parallelism": "none"},
-        "ms_per_step_with_kernel_events": ms_profiled,
+        "ms_per_step_with_kernel_events": ms_profiled, "graph": graph,
         "near_wall_pass_ms": pass_ms_median, "near_wall_pass_kernel_ms": pass_kernel_ms,
         "grad_ms": grad_ms, "grad_step_ms": grad_step_median,
         "near_wall_pass_hbm": {"algorithmic_bytes": hbm_pass,
@@ -333,6 +335,33 @@ def main():
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+def graph_step(args, agal, torch, wl, v, f, w_host, n_nodes, T):
+    """The same step as the batched form with one body: planned once (untimed, the plan runs the single-body
+    calls to size every array), then K replays of one captured graph (import, bins, refinement, q, adjoint;
+    no host synchronisation inside).  Results are identical to the single-body calls (tests/test_gpu_batch.py)."""
+    dim, Q = wl.dim, wl.lattice
+    cfg = agal.NearWallConfig(dim=dim, roots=wl.roots[:dim], n_levels=wl.levels, bins=wl.bins, lattice=Q,
+                              lo=wl.lo[:dim], hi=wl.hi[:dim], d_spec=list(wl.d_spec()[:wl.levels]))
+    t0 = time.perf_counter()
+    bt = agal.Batch([(v, f, cfg)], tune_bins=False, tune_grid=True, with_adjoint=True)
+    plan_s = time.perf_counter() - t0
+    bt.run()
+    bt.status()
+    n = bt.links(0)[0].numel()
+    assert n == n_nodes, (n, n_nodes)
+    bt.set_grad_q(0, torch.from_numpy(w_host[: max(1, n * Q)][: n * Q].reshape(n, Q)).to(v.device))
+    for _ in range(args.warmup):
+        bt.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bt.run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    bt.status()
+    return {"ms_per_step": ms, "value": T / (ms * 1e-3), "plan_s": plan_s, "workgroups_per_cu": bt.workgroups_per_cu}
 
 
 def bench_batch(args):

@@ -345,12 +345,42 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
     };
 
     int count = 0;  // staged faces (wave-uniform)
+    // The full tests wait in a queue of (lane, staged face) pairs and are taken
+    // 64 at a time, one per lane, whichever lane queued them: a cell near many
+    // faces does not hold the wave while the other lanes idle.  A pair whose
+    // cell is flagged meanwhile is dropped.
+    constexpr int TCAP = 128;   // below 64 after a take, at most 64 added per step
+    __shared__ uint32_t s_q[TCAP];
+    __shared__ float s_m[64][3];
+    __shared__ int s_fl[64];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) s_m[lane][a] = m[a];
+    s_fl[lane] = flagged ? 1 : 0;
+    int nq = 0;   // wave-uniform
+    auto take = [&](int t) {
+        __syncthreads();
+        const uint32_t item = lane < t ? s_q[lane] : 0u;
+        __syncthreads();
+        if (lane < nq - t) s_q[lane] = s_q[t + lane];
+        nq -= t;
+        const int l = (int)(item >> 7), j = (int)(item & 127u);
+        if (lane < t && !s_fl[l]) {
+            float v[D * D];
+#pragma unroll
+            for (int k = 0; k < D * D; ++k) v[k] = s_f[k][j];
+            const float ml[3] = {s_m[l][0], s_m[l][1], s_m[l][2]};
+            bool hit;
+            if constexpr (D == 3) hit = dev::sat_triangle(v, ml, h);
+            else hit = dev::sat_segment(v, ml, h);
+            if (hit) s_fl[l] = 1;
+        }
+    };
     // Batches of 64 staged faces: each lane marks the faces its cube's box axes do
-    // not separate from it, then runs the full test on those faces only, until
-    // flagged.
+    // not separate from it and queues them for the full test, until flagged.
     auto test_staged = [&](int n) {
         __syncthreads();
         for (int j0 = 0; j0 < n; j0 += 64) {
+            flagged = s_fl[lane] != 0;
             if (__ballot(!flagged) == 0) break;
             const int jn = min(64, n - j0);
             uint64_t nm = 0;
@@ -363,17 +393,26 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
                     for (int u = 0; u < 4; ++u)
                         nm |= ((cs[u] & lbits) == lbits && jj + u < jn) ? (1ull << (jj + u)) : 0ull;
                 }
-            while (nm && !flagged) {
-                const int j = j0 + __builtin_ctzll(nm);
-                nm &= nm - 1ull;
-                float v[D * D];
-#pragma unroll
-                for (int k = 0; k < D * D; ++k) v[k] = s_f[k][j];
-                if constexpr (D == 3) flagged = dev::sat_triangle(v, m, h);
-                else flagged = dev::sat_segment(v, m, h);
+            while (__ballot(nm != 0)) {
+                int j = 0;
+                const bool has = nm != 0;
+                if (has) {
+                    j = j0 + __builtin_ctzll(nm);
+                    nm &= nm - 1ull;
+                }
+                const uint64_t want = __ballot(has);
+                if (has) s_q[nq + dev::lanes_below(want)] = ((uint32_t)lane << 7) | (uint32_t)j;
+                nq += __popcll(want);
+                if (nq >= 64) {
+                    take(64);
+                    __syncthreads();
+                    if (s_fl[lane]) nm = 0;   // flagged meanwhile: nothing more to queue
+                }
             }
         }
+        if (nq > 0) take(nq);
         __syncthreads();
+        flagged = s_fl[lane] != 0;
     };
 
     bool done = __ballot(!flagged) == 0;
