@@ -89,6 +89,7 @@ struct ProfRecord {
 struct agal_context_t {
     agal::Allocator mem;
     int device = 0;
+    int n_cu = 256;                 // compute units of the device
     // small pinned host buffer for count read-backs
     uint32_t *h_counts = nullptr;   // mapped pinned host memory
     uint32_t *d_counts = nullptr;   // its device address
@@ -174,6 +175,17 @@ bool lattice_table(int Q, Lattice *out);
 // (nonzero = 1).  Scratch is allocated from the context.
 agal_status scan_u32(agal_context ctx, const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s);
 agal_status scan_flags_u8(agal_context ctx, const uint8_t *in, uint32_t *out, int64_t n, hipStream_t s);
+// k exclusive scans of 0/1 flags (out[i] of length n[i] + 1) in one launch; k <= kMultiScanMax.
+constexpr int kMultiScanMax = kMaxLevels + 1;
+struct MultiScanArgs {
+    const uint8_t *in[kMultiScanMax];
+    uint32_t *out[kMultiScanMax];
+    int64_t n[kMultiScanMax];
+    uint32_t tile0[kMultiScanMax];
+    int nseg;
+};
+agal_status scan_flags_u8_multi(agal_context ctx, const uint8_t *const *in, uint32_t *const *out, const int64_t *n,
+                                int k, hipStream_t s);
 
 // Look-back scratch: status words + ticket for `tiles` tiles, cleared.
 agal_status lookback_alloc(agal_context ctx, int64_t tiles, uint64_t **status, uint32_t **ticket, hipStream_t s);

@@ -275,6 +275,105 @@ __device__ __forceinline__ void for_candidates(const dev::BinGrid &g, const int 
     }
 }
 
+// Each face of bins [ilo, ihi] once, for boxes that span many bins (the flag
+// pass): ids are read four rounds of 64 at a time (one memory latency per 256
+// list entries), an LDS hash set of face ids drops the repeats of a face that
+// lies in several bins, and the records of the faces that remain are loaded
+// 64 at a time.  stage(has, f, r) is called by the whole wave with up to 64
+// such faces (r the lane's face record) and returns false to stop.  A face
+// that finds no free slot within kSeenProbes tries is passed on as new, so a
+// crowded set can let a repeat through; stage() must tolerate that.
+constexpr int kSeen = 1024;             // hash-set slots (power of two)
+constexpr int kSeenProbes = 16;         // slots tried before a face is let through as new
+constexpr int kUniqCap = 5 * 64;        // faces waiting for their records
+
+template <int D, class Stage>
+__device__ __forceinline__ void for_unique_candidates(const dev::BinGrid &g, const float *rec, const int ilo[3],
+                                                      const int ihi[3], int32_t *s_seen, int32_t *s_list,
+                                                      uint32_t *s_bpre, uint32_t *s_bs0, Stage &&stage) {
+    constexpr int RF = dev::kRecFloats<D>;
+    const int lane = dev::lane_id();
+    const int nx = ihi[0] - ilo[0] + 1, ny = ihi[1] - ilo[1] + 1, nz = ihi[2] - ilo[2] + 1;
+    const int nbins = nx * ny * nz;
+    __syncthreads();
+    for (int i = lane; i < kSeen; i += dev::kWave) s_seen[i] = -1;
+    int nl = 0;   // wave-uniform list length
+    // records of list entries 0 .. t-1, one per lane, to stage(); the rest moves to the front
+    auto flush = [&](int t) -> bool {
+        __syncthreads();
+        const int32_t f = lane < t ? s_list[lane] : -1;
+        __syncthreads();
+        for (int i = lane; i < nl - t; i += dev::kWave) s_list[i] = s_list[t + i];   // up to 4 x 64 remain
+        nl -= t;
+        float r[RF];
+        if (f >= 0) dev::load_rec<D>(rec, f, r);
+        return stage(f >= 0, f, (const float *)r);
+    };
+    for (int bg = 0; bg < nbins; bg += dev::kWave) {
+        const int bi = bg + lane;
+        uint32_t s0 = 0, cnt = 0;
+        if (bi < nbins) {
+            const int bx = ilo[0] + bi % nx, by = ilo[1] + (bi / nx) % ny, bz = ilo[2] + bi / (nx * ny);
+            const int64_t b = ((int64_t)bz * g.B + by) * g.B + bx;
+            s0 = g.off[b];
+            cnt = g.off[b + 1] - s0;
+        }
+        const uint32_t incl = dev::wave_inclusive_sum(cnt);
+        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, dev::kWave - 1);   // scalar
+        if (total == 0) continue;
+        // the non-empty bins in list order, for a binary search per list entry
+        const uint64_t ne = __ballot(cnt > 0);
+        const int nne = __popcll(ne);
+        __syncthreads();
+        if (cnt > 0) {
+            const int k = dev::lanes_below(ne);
+            s_bpre[k] = incl - cnt;
+            s_bs0[k] = s0;
+        }
+        __syncthreads();
+        for (uint32_t c0 = 0; c0 < total; c0 += 4 * dev::kWave) {
+            int32_t id[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t v = c0 + q * dev::kWave + lane;
+                id[q] = -1;
+                if (v < total) {
+                    int lo = 0, hi = nne - 1;   // last non-empty bin starting at or before v
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_bpre[mid] <= v) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    id[q] = g.ids[s_bs0[lo] + (v - s_bpre[lo])];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                bool fresh = false;
+                if (id[q] >= 0) {
+                    uint32_t h = ((uint32_t)id[q] * 2654435761u) >> 22;   // 10 bits: kSeen slots
+                    fresh = true;   // a crowded set lets the face through
+                    for (int probe = 0; probe < kSeenProbes; ++probe) {
+                        const int32_t prev = atomicCAS(&s_seen[h], -1, id[q]);
+                        if (prev == -1) break;
+                        if (prev == id[q]) {
+                            fresh = false;
+                            break;
+                        }
+                        h = (h + 1) & (kSeen - 1);
+                    }
+                }
+                const uint64_t m = __ballot(fresh);
+                if (fresh) s_list[nl + dev::lanes_below(m)] = id[q];
+                nl += __popcll(m);
+            }
+            while (nl >= dev::kWave)
+                if (!flush(dev::kWave)) return;
+        }
+    }
+    if (nl > 0) (void)flush(nl);
+}
+
 // ===========================================================================
 // Near-wall refinement (paper Sec. II-C-1, II-C-2)
 // ===========================================================================
@@ -297,7 +396,7 @@ struct FlagArgs {
 };
 
 // One wave: blocks first .. first + 64/4^D - 1 of A (one lane per cell).
-template <int D>
+template <int D, bool kDedup = false>
 __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
     constexpr int CELLS = D == 3 ? 64 : 16;
     constexpr int BPW = 64 / CELLS;
@@ -415,6 +514,9 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
         flagged = s_fl[lane] != 0;
     };
 
+    __shared__ int32_t s_seen[kDedup ? kSeen : 1];
+    __shared__ int32_t s_list[kDedup ? kUniqCap : 1];
+    __shared__ uint32_t s_bpre[kDedup ? 64 : 1], s_bs0[kDedup ? 64 : 1];
     bool done = __ballot(!flagged) == 0;
     for (int sb = 0; sb < BPW && !done; ++sb) {
         if (first + sb >= A.n) break;
@@ -436,21 +538,11 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
             ilo[a] = dev::bin_of(qlo[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
             ihi[a] = dev::bin_of(qhi[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
         }
-        for_candidates(A.bins, ilo, ihi, [&](bool has, int32_t f, const int cur[3]) -> bool {
-            bool keep = false;
-            float r[dev::kRecFloats<D>];
-            if (has) {
-                dev::load_rec<D>(A.faces.rec, f, r);
-                keep = true;
+        // stage the faces whose box meets the query box (r: the lane's face record)
+        auto stage = [&](bool has, int32_t f, const float *r) -> bool {
+            bool keep = has;
 #pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    const float mn = r[D * D + a];
-                    const float mx = r[D * D + D + a];
-                    // visit each face once: in the first bin of (its bins) x (query bins)
-                    const int fb = max(dev::bin_of(mn, A.bins.lo[a], A.bins.s[a], A.bins.B), ilo[a]);
-                    keep = keep && fb == cur[a] && mn <= qhi[a] && mx >= qlo[a];
-                }
-            }
+            for (int a = 0; a < D; ++a) keep = keep && r[D * D + a] <= qhi[a] && r[D * D + D + a] >= qlo[a];
             const uint64_t mask = __ballot(keep);
             const int nk = __popcll(mask);
             if (nk == 0) return true;
@@ -468,7 +560,24 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
             }
             count += nk;
             return true;
-        });
+        };
+        if constexpr (kDedup) {
+            for_unique_candidates<D>(A.bins, A.faces.rec, ilo, ihi, s_seen, s_list, s_bpre, s_bs0, stage);
+        } else {
+            for_candidates(A.bins, ilo, ihi, [&](bool has, int32_t f, const int cur[3]) -> bool {
+                // visit each face once: in the first bin of (its bins) x (query bins)
+                float r[dev::kRecFloats<D>];
+                bool first_bin = has;
+                if (has) {
+                    dev::load_rec<D>(A.faces.rec, f, r);
+#pragma unroll
+                    for (int a = 0; a < D; ++a)
+                        first_bin = first_bin &&
+                                    max(dev::bin_of(r[D * D + a], A.bins.lo[a], A.bins.s[a], A.bins.B), ilo[a]) == cur[a];
+                }
+                return stage(first_bin, f, (const float *)r);
+            });
+        }
     }
     if (!done && count > 0) test_staged(count);
 
@@ -1218,9 +1327,11 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs<D, Q> &A, int64_t nod
             f = qf[lane];
         }
         dev::wave_sync();
-        if (lane < cnt - t) {
-            qm[lane] = qm[t + lane];
-            qf[lane] = qf[t + lane];
+        // up to 4 x 64 entries remain: every lane moves several, in order (a
+        // read of entry t + i precedes the write of entry i + 64 over it)
+        for (int i = lane; i < cnt - t; i += dev::kWave) {
+            qm[i] = qm[t + i];
+            qf[i] = qf[t + i];
         }
         qn = cnt - t;
         float s[D], n[3] = {0.0f, 0.0f, 0.0f};

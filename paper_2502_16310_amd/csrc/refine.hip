@@ -29,9 +29,9 @@ using namespace kern;
 #define AGAL_GRID_STRIDE(i, n) \
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
-template <int D>
+template <int D, bool kDedup>
 __global__ __launch_bounds__(64) void k_flag(FlagArgs<D> A) {
-    flag_wave<D>(A, (int64_t)blockIdx.x * (D == 3 ? 1 : 4));
+    flag_wave<D, kDedup>(A, (int64_t)blockIdx.x * (D == 3 ? 1 : 4));
 }
 
 template <int D>
@@ -41,26 +41,69 @@ __global__ void k_ripple(const uint32_t *keys_m, int64_t n_m, const uint8_t *pm_
     ripple_item<D>(keys_m, n_m, pm_m, m, keys_p, n_p, leaf_p, pm_p, R0, R1, R2, err, t);
 }
 
-__global__ void k_mark_parents(const uint32_t *keys, const uint8_t *pm, const uint32_t *pos, int64_t n, uint8_t *leaf,
-                               uint8_t *mark, uint32_t *mk) {
-    AGAL_GRID_STRIDE(i, n) mark_parents_item(keys, pm, pos, leaf, mark, mk, i);
+// Level 0 (every root, key = x-fastest linear index, all leaves, no marks) and
+// the error word, in one launch.
+__global__ void k_init_roots(uint32_t *keys, uint8_t *leaf, uint8_t *mark, int64_t n, uint32_t *err) {
+    AGAL_GRID_STRIDE(i, n) {
+        keys[i] = (uint32_t)i;
+        leaf[i] = 1;
+        mark[i] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *err = 0u;
+}
+
+// Child generation of one pass for every parent level m with marks, in two
+// launches: first the parents (k_mark_parents_all), then the new child levels
+// (existing children moved and new children written, k_grow_all).  Segment i
+// is parent level seg[i].m; items of the launches are numbered across the
+// segments by the host-made prefixes.
+struct GrowSeg {
+    const uint32_t *pkeys;   // parent level m
+    const uint8_t *pm;
+    const uint32_t *pos;
+    uint8_t *pleaf, *pmark;
+    int64_t pn;
+    uint32_t *mk;            // marked parent keys (c of them)
+    int64_t c;
+    const uint32_t *ckeys;   // child level m + 1 before the pass
+    const uint8_t *cleaf, *cmark, *ccf;
+    int64_t cn;
+    uint32_t *nkeys;         // child level m + 1 after the pass
+    uint8_t *nleaf, *nmark, *ncf;
+};
+struct GrowArgs {
+    GrowSeg seg[kMaxLevels + 1];
+    int64_t pre_p[kMaxLevels + 2];   // prefix of pn
+    int64_t pre_g[kMaxLevels + 2];   // prefix of cn + (c << D)
+    int nseg;
+    int D;
+};
+
+__device__ __forceinline__ int seg_of(const int64_t *pre, int nseg, int64_t i) {
+    int k = 0;
+    while (k + 1 < nseg && pre[k + 1] <= i) ++k;
+    return k;
+}
+
+__global__ void k_mark_parents_all(GrowArgs a) {
+    AGAL_GRID_STRIDE(i, a.pre_p[a.nseg]) {
+        const int k = seg_of(a.pre_p, a.nseg, i);
+        const GrowSeg &g = a.seg[k];
+        mark_parents_item(g.pkeys, g.pm, g.pos, g.pleaf, g.pmark, g.mk, i - a.pre_p[k]);
+    }
 }
 
 template <int CELLS>
-__global__ void k_merge_old(const uint32_t *keys, const uint8_t *leaf, const uint8_t *mark, const uint8_t *cf,
-                            int64_t n_old, const uint32_t *mk, int64_t n_mk, int D, uint32_t *nkeys, uint8_t *nleaf,
-                            uint8_t *nmark, uint8_t *ncf) {
-    AGAL_GRID_STRIDE(i, n_old) merge_old_item<CELLS>(keys, leaf, mark, cf, mk, n_mk, D, nkeys, nleaf, nmark, ncf, i);
-}
-
-template <int CELLS>
-__global__ void k_children(const uint32_t *mk, int64_t n_mk, const uint32_t *keys_old, int64_t n_old, int D,
-                           uint32_t *nkeys, uint8_t *nleaf, uint8_t *nmark, uint8_t *ncf) {
-    AGAL_GRID_STRIDE(t, n_mk << D) children_item<CELLS>(mk, keys_old, n_old, D, nkeys, nleaf, nmark, ncf, t);
-}
-
-__global__ void k_iota_u32(uint32_t *p, int64_t n) {
-    AGAL_GRID_STRIDE(i, n) p[i] = (uint32_t)i;
+__global__ void k_grow_all(GrowArgs a) {
+    AGAL_GRID_STRIDE(i, a.pre_g[a.nseg]) {
+        const int k = seg_of(a.pre_g, a.nseg, i);
+        const GrowSeg &g = a.seg[k];
+        const int64_t j = i - a.pre_g[k];
+        if (j < g.cn)
+            merge_old_item<CELLS>(g.ckeys, g.cleaf, g.cmark, g.ccf, g.mk, g.c, a.D, g.nkeys, g.nleaf, g.nmark, g.ncf, j);
+        else
+            children_item<CELLS>(g.mk, g.ckeys, g.cn, a.D, g.nkeys, g.nleaf, g.nmark, g.ncf, j - g.cn);
+    }
 }
 
 unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 16384) {
@@ -85,6 +128,21 @@ struct Scratch {
     }
 };
 
+// Which candidate walker the flag pass of n blocks takes at cell size dx and
+// distance h.  The deduplicating one (many list entries per memory latency,
+// repeats dropped by a hash set before any record is read) shortens the waves
+// of blocks whose query box (4 dx + 2 h per axis) spans many bins; it pays for
+// clearing the set and for more LDS per wave.  Measured on MI355X: it wins
+// when the pass is bound by its longest waves (few blocks: C1 levels 0 and 1,
+// 80 -> 60 and 40 -> 27 us) and loses when the pass has blocks enough to fill
+// the GPU many times (C2 level 0, 32768 blocks: 285 -> 375 us).
+template <int D>
+bool flag_dedup(const agal_bins_t *bn, const float dx[3], float h, int64_t n_blocks, int n_cu) {
+    double nbins = 1.0;
+    for (int a = 0; a < D; ++a) nbins *= std::min((double)bn->B, std::floor((4.0 * dx[a] + 2.0 * h) * bn->s[a]) + 2.0);
+    return nbins > 64.0 && n_blocks < 32 * (int64_t)n_cu;
+}
+
 template <int D>
 agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s) {
     constexpr int CELLS = D == 3 ? 64 : 16;
@@ -94,7 +152,6 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
     uint32_t *err = nullptr;
     Scratch keep{ctx, s, {}};
     AGAL_TRY(keep.get(&err, 1));
-    fill_u32(err, 0u, 1, s);
 
     // level 0: every root, key = x-fastest linear index
     agal::Level &L0 = fo->lev[0];
@@ -102,9 +159,7 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
     AGAL_TRY(dev_alloc(mem, &L0.keys, (size_t)L0.n, s));
     AGAL_TRY(dev_alloc(mem, &L0.leaf, (size_t)L0.n, s));
     AGAL_TRY(dev_alloc(mem, &L0.mark, (size_t)L0.n, s));
-    hipLaunchKernelGGL(k_iota_u32, dim3(grid_for(L0.n)), dim3(256), 0, s, L0.keys, L0.n);
-    fill_u8(L0.leaf, 1, L0.n, s);
-    fill_u8(L0.mark, 0, L0.n, s);
+    hipLaunchKernelGGL(k_init_roots, dim3(grid_for(L0.n)), dim3(256), 0, s, L0.keys, L0.leaf, L0.mark, L0.n, err);
 
     dev::BinGrid bins{};
     bins.off = bn->off;
@@ -118,10 +173,19 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
 
     for (int l = 0; l < fo->L; ++l) {
         Scratch pass{ctx, s, {}};
+        // pass marks of every level l' <= l, one zeroed buffer
         uint8_t *pm[kMaxLevels + 1] = {};
-        for (int m = 0; m <= l; ++m) {
-            AGAL_TRY(pass.get(&pm[m], (size_t)fo->lev[m].n));
-            fill_u8(pm[m], 0, fo->lev[m].n, s);
+        {
+            int64_t tot = 0;
+            for (int m = 0; m <= l; ++m) tot += fo->lev[m].n;
+            uint8_t *pmb = nullptr;
+            AGAL_TRY(pass.get(&pmb, (size_t)std::max<int64_t>(tot, 1)));
+            fill_u8(pmb, 0, tot, s);
+            int64_t at = 0;
+            for (int m = 0; m <= l; ++m) {
+                pm[m] = pmb + at;
+                at += fo->lev[m].n;
+            }
         }
         // (i) flag every cell of every level-l block
         agal::Level &Ll = fo->lev[l];
@@ -145,7 +209,10 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
             A.pmark = pm[l];
             const int64_t waves = (Ll.n + BPW - 1) / BPW;
             ProfScope prof(ctx, "flag_sat", s);
-            hipLaunchKernelGGL(k_flag<D>, dim3((unsigned)waves), dim3(64), 0, s, A);
+            if (flag_dedup<D>(bn, fo->dx[l], A.h, Ll.n, ctx->n_cu))
+                hipLaunchKernelGGL((k_flag<D, true>), dim3((unsigned)waves), dim3(64), 0, s, A);
+            else
+                hipLaunchKernelGGL((k_flag<D, false>), dim3((unsigned)waves), dim3(64), 0, s, A);
         }
         // (ii) balance ripple, level l down to 1
         for (int m = l; m >= 1; --m) {
@@ -159,15 +226,29 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
         // (iii) children: count marks per level, then merge level by level
         uint32_t *pos[kMaxLevels + 1] = {};
         const uint32_t *totals[kMaxLevels + 2] = {};
-        for (int m = 0; m <= l; ++m) {
-            AGAL_TRY(pass.get(&pos[m], (size_t)fo->lev[m].n + 1));
-            AGAL_TRY(scan_flags_u8(ctx, pm[m], pos[m], fo->lev[m].n, s));
-            totals[m] = pos[m] + fo->lev[m].n;
+        {
+            const uint8_t *ins[kMaxLevels + 1];
+            int64_t ns[kMaxLevels + 1];
+            for (int m = 0; m <= l; ++m) {
+                AGAL_TRY(pass.get(&pos[m], (size_t)fo->lev[m].n + 1));
+                ins[m] = pm[m];
+                ns[m] = fo->lev[m].n;
+                totals[m] = pos[m] + fo->lev[m].n;
+            }
+            AGAL_TRY(scan_flags_u8_multi(ctx, ins, pos, ns, l + 1, s));
         }
         totals[l + 1] = err;
         uint32_t nmark[kMaxLevels + 2] = {};
         AGAL_TRY(read_back_u32(ctx, totals, l + 2, nmark, s));
         if (nmark[l + 1] != 0) return fail(AGAL_ESTATE, "agal_near_wall_refine: forest lost 2:1 balance");
+        // every parent level with marks at once: the new child levels are fresh
+        // arrays, and a level that is both a parent (m) and a child (of m - 1)
+        // has its leaf and mark bytes set by the first launch before the second
+        // copies them
+        GrowArgs ga{};
+        ga.D = D;
+        agal::Level Nl[kMaxLevels + 1];
+        int segm[kMaxLevels + 1];
         for (int m = l; m >= 0; --m) {
             const int64_t c = nmark[m];
             agal::Level &P = fo->lev[m];
@@ -182,27 +263,49 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
                 }
                 continue;
             }
-            uint32_t *mk = nullptr;
-            AGAL_TRY(pass.get(&mk, (size_t)c));
-            ProfScope prof(ctx, "child_gen", s);
-            hipLaunchKernelGGL(k_mark_parents, dim3(grid_for(P.n)), dim3(256), 0, s, P.keys, pm[m], pos[m], P.n,
-                               P.leaf, P.mark, mk);
-            agal::Level N;
+            GrowSeg &gs = ga.seg[ga.nseg];
+            segm[ga.nseg] = m;
+            agal::Level &N = Nl[ga.nseg];
+            ++ga.nseg;
+            AGAL_TRY(pass.get(&gs.mk, (size_t)c));
             N.n = C.n + (c << D);
             AGAL_TRY(dev_alloc(mem, &N.keys, (size_t)N.n, s));
             AGAL_TRY(dev_alloc(mem, &N.leaf, (size_t)N.n, s));
             AGAL_TRY(dev_alloc(mem, &N.mark, (size_t)N.n, s));
             if (C.cf) AGAL_TRY(dev_alloc(mem, &N.cf, (size_t)N.n * CELLS, s));
-            if (C.n > 0)
-                hipLaunchKernelGGL(k_merge_old<CELLS>, dim3(grid_for(C.n)), dim3(256), 0, s, C.keys, C.leaf, C.mark,
-                                   C.cf, C.n, mk, c, D, N.keys, N.leaf, N.mark, N.cf);
-            hipLaunchKernelGGL(k_children<CELLS>, dim3(grid_for(c << D)), dim3(256), 0, s, mk, c, C.keys, C.n, D,
-                               N.keys, N.leaf, N.mark, N.cf);
+            gs.pkeys = P.keys;
+            gs.pm = pm[m];
+            gs.pos = pos[m];
+            gs.pleaf = P.leaf;
+            gs.pmark = P.mark;
+            gs.pn = P.n;
+            gs.c = c;
+            gs.ckeys = C.keys;
+            gs.cleaf = C.leaf;
+            gs.cmark = C.mark;
+            gs.ccf = C.cf;
+            gs.cn = C.n;
+            gs.nkeys = N.keys;
+            gs.nleaf = N.leaf;
+            gs.nmark = N.mark;
+            gs.ncf = N.cf;
+        }
+        if (ga.nseg > 0) {
+            for (int k = 0; k < ga.nseg; ++k) {
+                ga.pre_p[k + 1] = ga.pre_p[k] + ga.seg[k].pn;
+                ga.pre_g[k + 1] = ga.pre_g[k] + ga.seg[k].cn + (ga.seg[k].c << D);
+            }
+            ProfScope prof(ctx, "child_gen", s);
+            hipLaunchKernelGGL(k_mark_parents_all, dim3(grid_for(ga.pre_p[ga.nseg])), dim3(256), 0, s, ga);
+            hipLaunchKernelGGL(k_grow_all<CELLS>, dim3(grid_for(ga.pre_g[ga.nseg])), dim3(256), 0, s, ga);
+        }
+        for (int k = 0; k < ga.nseg; ++k) {
+            agal::Level &C = fo->lev[segm[k] + 1];
             dev_free(mem, C.keys, s);
             dev_free(mem, C.leaf, s);
             dev_free(mem, C.mark, s);
             dev_free(mem, C.cf, s);
-            C = N;
+            C = Nl[k];
         }
         AGAL_TRY_HIP(hipGetLastError());
     }

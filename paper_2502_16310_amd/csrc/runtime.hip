@@ -1,5 +1,6 @@
 // Runtime pieces of the library: error reporting, the device allocator,
 // fill kernels, the single-pass exclusive scan and small read-backs.
+#include <algorithm>
 #include <atomic>
 #include <cstdio>
 #include <cstring>
@@ -249,6 +250,83 @@ agal_status scan_flags_u8(agal_context ctx, const uint8_t *in, uint32_t *out, in
     return scan_impl(ctx, LoadFlagU8{in}, out, n, s);
 }
 
+// Several flag scans in one launch: the tiles of all arrays share one ticket
+// counter, so every array's tiles are taken in order and each looks back only
+// over its own array's status words.
+__global__ __launch_bounds__(kScanThreads) void k_scan_flags_multi(MultiScanArgs a, uint64_t *status,
+                                                                    uint32_t *ticket) {
+    __shared__ uint32_t s_tile, s_prefix;
+    __shared__ uint32_t s_wsum[kScanThreads / dev::kWave];
+    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t gtile = s_tile;
+    int seg = 0;
+    while (seg + 1 < a.nseg && a.tile0[seg + 1] <= gtile) ++seg;
+    const uint32_t tile = gtile - a.tile0[seg];
+    const uint8_t *in = a.in[seg];
+    uint32_t *out = a.out[seg];
+    const int64_t n = a.n[seg];
+    const int64_t base = (int64_t)tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = base + i;
+        v[i] = idx < n ? (in[idx] != 0 ? 1u : 0u) : 0u;
+        sum += v[i];
+    }
+    const int w = threadIdx.x / dev::kWave, lane = threadIdx.x % dev::kWave;
+    const uint32_t incl = dev::wave_inclusive_sum(sum);
+    if (lane == dev::kWave - 1) s_wsum[w] = incl;
+    __syncthreads();
+    uint32_t wpre = 0, total = 0;
+#pragma unroll
+    for (int j = 0; j < kScanThreads / dev::kWave; ++j) {
+        if (j < w) wpre += s_wsum[j];
+        total += s_wsum[j];
+    }
+    if (w == 0) {
+        const uint32_t p = dev::lookback_wave(status + a.tile0[seg], tile, total);
+        if (lane == 0) s_prefix = p;
+    }
+    __syncthreads();
+    uint32_t run = s_prefix + wpre + incl - sum;
+    if (n == 0 && threadIdx.x == 0) out[0] = 0u;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = base + i;
+        if (idx < n) out[idx] = run;
+        run += v[i];
+        if (idx == n - 1) out[n] = run;
+    }
+}
+
+agal_status scan_flags_u8_multi(agal_context ctx, const uint8_t *const *in, uint32_t *const *out, const int64_t *n,
+                                int k, hipStream_t s) {
+    if (k <= 0) return AGAL_OK;
+    if (k > kMultiScanMax) return fail(AGAL_EINVAL, "scan_flags_u8_multi: at most %d arrays", kMultiScanMax);
+    MultiScanArgs a{};
+    a.nseg = k;
+    uint32_t tiles = 0;
+    for (int i = 0; i < k; ++i) {
+        a.in[i] = in[i];
+        a.out[i] = out[i];
+        a.n[i] = n[i];
+        a.tile0[i] = tiles;
+        tiles += (uint32_t)std::max<int64_t>(1, (n[i] + kScanTile - 1) / kScanTile);   // an empty array still writes out[0]
+    }
+    uint64_t *status = nullptr;
+    uint32_t *ticket = nullptr;
+    AGAL_TRY(lookback_alloc(ctx, tiles, &status, &ticket, s));
+    {
+        ProfScope prof(ctx, "scan_exclusive", s);
+        hipLaunchKernelGGL(k_scan_flags_multi, dim3(tiles), dim3(kScanThreads), 0, s, a, status, ticket);
+    }
+    dev_free(ctx->mem, status, s);
+    AGAL_TRY_HIP(hipGetLastError());
+    return AGAL_OK;
+}
+
 // ---------------------------------------------------------------------------
 // read-back of a few device words
 // ---------------------------------------------------------------------------
@@ -312,6 +390,10 @@ agal_status agal_context_create(const agal_allocator *alloc, agal_context *out) 
     auto *c = new (std::nothrow) agal_context_t();
     if (!c) return agal::fail(AGAL_ENOMEM, "agal_context_create: host allocation failed");
     c->device = dev;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+        c->n_cu = ncu;
+    (void)hipGetLastError();
     if (alloc) {
         c->mem.user = *alloc;
         c->mem.has_user = true;

@@ -64,6 +64,16 @@ def test_c3_adjoint_against_fp64_adjoint_and_finite_differences(orc):
     comp, norm, ok = _rel_checks(grad, g_ref, 1e-3, 1e-4)
     log(f"  GPU vs FP64 adjoint: max component rel {comp:.2e}, norm rel {norm:.2e}")
     assert ok
+    # every link weighted (dense link queues in the adjoint's waves: up to 4 x 64 + 63 entries wait between
+    # takes; a take that moved only 64 of them lost some links and repeated others)
+    w_all = geomgen.weights(lk.n * wl.lattice, 3).astype(np.float64).reshape(lk.n, wl.lattice)
+    w_all[(lk.face < 0) | (g["face"] != lk.face)] = 0.0
+    grad_all = links_h.backward(torch.from_numpy(w_all.astype(np.float32)).cuda()).cpu().numpy().astype(np.float64)
+    g_all = orc.link_grad(fo, lk, coords, wl.faces, w_all, len(wl.vertices))
+    comp, norm, ok = _rel_checks(grad_all, g_all, 1e-3, 1e-4)
+    log(f"  all {int((w_all != 0).sum())} links weighted: GPU vs FP64 adjoint max component rel {comp:.2e}, "
+        f"norm rel {norm:.2e}")
+    assert ok
     sub = np.sort(np.random.default_rng(4).choice(len(wl.vertices), 1024, replace=False))
     fd4, ch4 = orc.fd_grad(fo, lk, wl.vertices, wl.faces, bins, w, h=1e-4, vertex_subset=sub)
     fd5, ch5 = orc.fd_grad(fo, lk, wl.vertices, wl.faces, bins, w, h=1e-5, vertex_subset=sub)

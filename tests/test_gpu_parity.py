@@ -62,12 +62,64 @@ def test_bin_density_invariance(orc, B):
     _full(orc, _small_sphere(3, 4, 2, 16), B=B)
 
 
+def _max_adjoint_queue(face, w, tile=256, waves=4, group=4, lanes=64):
+    """Longest per-wave link queue of the adjoint kernel's schedule: a tile of `tile` nodes is one span of
+    node * Q slots read in chunks of `lanes`, chunk c by wave c % waves, `group` chunks per step; the live
+    slots (direction > 0, face >= 0, weight != 0) are appended and taken `lanes` at a time."""
+    n, Q = face.shape
+    live = ((face >= 0) & (w != 0)).copy()
+    live[:, 0] = False
+    worst = 0
+    for t0 in range(0, n, tile):
+        span = live[t0:t0 + tile].reshape(-1)
+        chunks = [span[c:c + lanes].sum() for c in range(0, span.size, lanes)]
+        for wv in range(waves):
+            mine = chunks[wv::waves]
+            q = 0
+            for g0 in range(0, len(mine), group):
+                q += sum(mine[g0:g0 + group])
+                worst = max(worst, q)
+                q %= lanes
+    return worst
+
+
+def _adjoint_all_links(orc, wl, g, of, lk, coords):
+    """GPU adjoint against the FP64 one with every link weighted (where both sides name the same face)."""
+    import torch
+    geom, bins_h, forest_h, links_h = g["handles"]
+    assert np.array_equal(g["key"], lk.key)
+    w = geomgen.weights(lk.n * wl.lattice, 5).astype(np.float64).reshape(lk.n, wl.lattice)
+    w[(lk.face < 0) | (g["face"] != lk.face)] = 0.0
+    grad = links_h.backward(torch.from_numpy(w.astype(np.float32)).cuda()).cpu().numpy().astype(np.float64)
+    ref = orc.link_grad(of, lk, coords, wl.faces, w, len(wl.vertices))
+    err = np.abs(grad - ref)
+    comp = float((err / np.maximum(np.abs(ref), 1e-2 * np.abs(ref).max())).max())
+    norm = float(np.linalg.norm(grad - ref) / np.linalg.norm(ref))
+    return comp, norm, w
+
+
 def test_random_triangles_and_outside_faces(orc):
     v, f = geomgen.random_triangles(300, 9, 0.05, 0.95, 0.08)
     v = v.copy()
     v[:30] += np.float32(0.9)  # some faces stick out of the domain
     wl = geomgen.Workload("rand", 3, v, f, (3, 3, 3), 2, 10, 27)
     _full(orc, wl)
+
+
+def test_adjoint_dense_link_queues(orc):
+    """A soup of large triangles cuts many directions per node, so the adjoint's per-wave link queues hold up
+    to 4 x 64 + 63 links between takes (regression: a take moved only 64 of the waiting links, losing some
+    and repeating others).  Every link is weighted; the GPU gradient must match the FP64 adjoint."""
+    v, f = geomgen.random_triangles(600, 9, 0.05, 0.95, 0.15)
+    wl = geomgen.Workload("soup", 3, v, f, (3, 3, 3), 2, 10, 27)
+    g, of, lk = _full(orc, wl)
+    coords = orc.gather(wl.dim, wl.vertices, wl.faces)
+    comp, norm, w = _adjoint_all_links(orc, wl, g, of, lk, coords)
+    qmax = _max_adjoint_queue(g["face"], w)
+    log(f"  adjoint, all {int((w != 0).sum())} links weighted: max component rel {comp:.2e}, norm rel {norm:.2e}; "
+        f"longest link queue {qmax}")
+    assert qmax > 128   # the workload does exercise long queues
+    assert comp <= 1e-3 and norm <= 1e-4
 
 
 def test_random_segments_2d(orc):
