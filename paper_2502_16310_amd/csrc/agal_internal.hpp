@@ -183,9 +183,18 @@ struct MultiScanArgs {
     int64_t n[kMultiScanMax];
     uint32_t tile0[kMultiScanMax];
     int nseg;
+    const uint32_t *extra;   // one more device word to report (or null: 0)
+    uint32_t *host_total;    // mapped host memory: k totals, then *extra
 };
+// totals[0..k-1] = sum of each array, totals[k] = *extra; synchronises the stream.
 agal_status scan_flags_u8_multi(agal_context ctx, const uint8_t *const *in, uint32_t *const *out, const int64_t *n,
-                                int k, hipStream_t s);
+                                int k, const uint32_t *extra, uint32_t *totals, hipStream_t s);
+// Tiles of a scan of n elements; a caller-provided status buffer holds tiles + 1 zeroed 64-bit words.
+int64_t scan_tiles(int64_t n);
+// Exclusive scan whose sum comes back through mapped host memory (synchronises the stream); status is a
+// zeroed buffer of scan_tiles(n) + 1 words, or null.
+agal_status scan_u32_total(agal_context ctx, const uint32_t *in, uint32_t *out, int64_t n, uint64_t *status,
+                           uint32_t *total, hipStream_t s);
 
 // Look-back scratch: status words + ticket for `tiles` tiles, cleared.
 agal_status lookback_alloc(agal_context ctx, int64_t tiles, uint64_t **status, uint32_t **ticket, hipStream_t s);
@@ -211,7 +220,5 @@ class ProfScope {
     hipEvent_t start_ = nullptr;
 };
 
-// Read a few uint32 device values back (synchronises the stream).
-agal_status read_back_u32(agal_context ctx, const uint32_t *const *srcs, int n, uint32_t *dst, hipStream_t s);
 
 }  // namespace agal

@@ -91,15 +91,23 @@ agal_status agal_bin_faces(agal_geom g, const float lo[3], const float hi[3], in
         grid.lo[a] = bn->lo[a];
         grid.s[a] = bn->s[a];
     }
-    uint32_t *count = nullptr;
-    agal_status st = dev_alloc(ctx->mem, &count, (size_t)nb, s);
+    // one zeroed work buffer: per-bin counts, per-bin scatter cursors, the
+    // oversized-bin counter, and the scan's look-back status words
+    const int64_t tiles = scan_tiles(nb);
+    const int64_t work_words = 2 * nb + 2 + 2 * (tiles + 1);
+    uint32_t *work = nullptr;
+    agal_status st = dev_alloc(ctx->mem, &work, (size_t)work_words, s);
     if (st == AGAL_OK) st = dev_alloc(ctx->mem, &bn->off, (size_t)nb + 1, s);
     if (st != AGAL_OK) {
-        dev_free(ctx->mem, count, s);
+        dev_free(ctx->mem, work, s);
         agal_destroy_bins(bn);
         return st;
     }
-    fill_u32(count, 0u, nb, s);
+    fill_u32(work, 0u, work_words, s);
+    uint32_t *count = work;
+    uint32_t *cursor = work + nb;
+    uint32_t *big_count = work + 2 * nb;
+    uint64_t *scan_status = reinterpret_cast<uint64_t *>(work + ((2 * nb + 3) & ~int64_t(1)));
     {
     ProfScope prof(ctx, "bin_count", s);
     if (D == 3)
@@ -107,51 +115,45 @@ agal_status agal_bin_faces(agal_geom g, const float lo[3], const float hi[3], in
     else
         hipLaunchKernelGGL(k_bin_count<2>, dim3(grid_for(g->F)), dim3(256), 0, s, g->aabb, g->F, grid, count);
     }
-    st = scan_u32(ctx, count, bn->off, nb, s);
     uint32_t P = 0;
-    if (st == AGAL_OK) {
-        const uint32_t *src[1] = {bn->off + nb};
-        st = read_back_u32(ctx, src, 1, &P, s);
-    }
+    st = scan_u32_total(ctx, count, bn->off, nb, scan_status, &P, s);
     bn->P = P;
-    uint32_t *big = nullptr;
-    const int64_t big_cap = (int64_t)P / kCanonCap + 2;
+    uint32_t *big = nullptr;   // the oversized bins (big_count[0] of them)
+    const int64_t big_cap = (int64_t)P / kCanonCap + 1;
     if (st == AGAL_OK) st = dev_alloc(ctx->mem, &bn->ids, (size_t)std::max<uint32_t>(P, 1u), s);
     if (st == AGAL_OK) st = dev_alloc(ctx->mem, &big, (size_t)big_cap, s);
     if (st != AGAL_OK) {
-        dev_free(ctx->mem, count, s);
+        dev_free(ctx->mem, work, s);
         dev_free(ctx->mem, big, s);
         agal_destroy_bins(bn);
         return st;
     }
-    fill_u32(count, 0u, nb, s);   // reused as scatter cursors
-    fill_u32(big, 0u, 1, s);      // big[0] = number of oversized bins; list follows
     {
     ProfScope prof(ctx, "bin_scatter", s);
     if (D == 3)
         hipLaunchKernelGGL(k_bin_scatter<3>, dim3(grid_for(g->F)), dim3(256), 0, s, g->aabb, g->F, grid, bn->off,
-                           count, bn->ids);
+                           cursor, bn->ids);
     else
         hipLaunchKernelGGL(k_bin_scatter<2>, dim3(grid_for(g->F)), dim3(256), 0, s, g->aabb, g->F, grid, bn->off,
-                           count, bn->ids);
+                           cursor, bn->ids);
     }
     const int64_t groups = (nb + dev::kWave - 1) / dev::kWave;
     {
     ProfScope prof(ctx, "bin_canon", s);
     hipLaunchKernelGGL(k_bin_canon_small, dim3((unsigned)groups), dim3(dev::kWave), 0, s, bn->ids, bn->off, nb,
-                       big + 1, big);
+                       big, big_count);
     }
     const unsigned big_grid = (unsigned)std::min<int64_t>(big_cap, 256);
     {
     ProfScope prof(ctx, "bin_canon_big", s);
     if (D == 3)
         hipLaunchKernelGGL(k_bin_canon_big<3>, dim3(big_grid), dim3(kBigThreads), 0, s, g->aabb, g->F, grid, bn->off,
-                           bn->ids, big + 1, big);
+                           bn->ids, big, big_count);
     else
         hipLaunchKernelGGL(k_bin_canon_big<2>, dim3(big_grid), dim3(kBigThreads), 0, s, g->aabb, g->F, grid, bn->off,
-                           bn->ids, big + 1, big);
+                           bn->ids, big, big_count);
     }
-    dev_free(ctx->mem, count, s);
+    dev_free(ctx->mem, work, s);
     dev_free(ctx->mem, big, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {

@@ -23,7 +23,10 @@ __global__ void k_import(const float *verts, int64_t Nv, const int32_t *faces, i
     for (int64_t i = t0; i < Nv * D; i += stride)
         if (!isfinite(verts[i])) bad |= 1u;
     for (int64_t f = t0; f < F; f += stride) bad |= kern::import_face<D>(verts, Nv, faces, F, coords, aabb, rec, fidx, f);
-    if (bad) atomicOr(err, bad);
+    // err: two words of mapped host memory, zeroed by the host; plain stores of
+    // the same value need no atomics
+    if (bad & 1u) err[0] = 1u;
+    if (bad & 2u) err[1] = 1u;
 }
 
 static unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 8192) {
@@ -58,18 +61,19 @@ agal_status agal_import_faces(agal_context ctx, int dim, const float *d_vertices
     g->dim = dim;
     g->F = n_faces;
     g->Nv = n_vertices;
-    uint32_t *err = nullptr;
     agal_status st = dev_alloc(ctx->mem, &g->coords, (size_t)dim * dim * n_faces, s);
     if (st == AGAL_OK) st = dev_alloc(ctx->mem, &g->aabb, (size_t)2 * dim * n_faces, s);
     if (st == AGAL_OK) st = dev_alloc(ctx->mem, &g->rec, (size_t)(dim == 3 ? 16 : 8) * n_faces, s);
     if (st == AGAL_OK) st = dev_alloc(ctx->mem, &g->fidx, (size_t)dim * n_faces, s);
-    if (st == AGAL_OK) st = dev_alloc(ctx->mem, &err, 1, s);
     if (st != AGAL_OK) {
-        dev_free(ctx->mem, err, s);
         agal_destroy_geom(g);
         return st;
     }
-    fill_u32(err, 0u, 1, s);
+    // error words in the context's mapped host memory (no kernel of an earlier
+    // call still writes them: every call that uses them synchronises)
+    uint32_t *err = ctx->d_counts;
+    ctx->h_counts[0] = 0u;
+    ctx->h_counts[1] = 0u;
     {
         ProfScope prof(ctx, "import", s);
         const unsigned grid = grid_for(std::max(n_vertices * dim, n_faces));
@@ -81,11 +85,9 @@ agal_status agal_import_faces(agal_context ctx, int dim, const float *d_vertices
                                g->coords, g->aabb, g->rec, g->fidx, err);
     }
     hipError_t e = hipGetLastError();
-    uint32_t herr = 0;
-    const uint32_t *srcs[1] = {err};
-    st = e != hipSuccess ? fail(AGAL_EHIP, "agal_import_faces: launch failed: %s", hipGetErrorString(e))
-                         : read_back_u32(ctx, srcs, 1, &herr, s);
-    dev_free(ctx->mem, err, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    st = e != hipSuccess ? fail(AGAL_EHIP, "agal_import_faces: %s", hipGetErrorString(e)) : AGAL_OK;
+    const uint32_t herr = (ctx->h_counts[0] ? 1u : 0u) | (ctx->h_counts[1] ? 2u : 0u);
     if (st == AGAL_OK && (herr & 1u)) st = fail(AGAL_EINVAL, "agal_import_faces: NaN or Inf vertex coordinate");
     if (st == AGAL_OK && (herr & 2u)) st = fail(AGAL_EINVAL, "agal_import_faces: face index outside [0, n_vertices)");
     if (st != AGAL_OK) {

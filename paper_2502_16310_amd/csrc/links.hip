@@ -127,10 +127,8 @@ agal_status links_forward(agal_geom g, agal_bins bn, agal_forest fo, const Latti
         hipLaunchKernelGGL((k_links<D, Q>), dim3((unsigned)waves), dim3(64), 0, s, A, st.count);
     }
     AGAL_TRY_HIP(hipGetLastError());
-    AGAL_TRY(scan_u32(ctx, st.count, st.off, LL.n, s));
     uint32_t nn = 0;
-    const uint32_t *src[1] = {st.off + LL.n};
-    AGAL_TRY(read_back_u32(ctx, src, 1, &nn, s));
+    AGAL_TRY(scan_u32_total(ctx, st.count, st.off, LL.n, nullptr, &nn, s));
     lk->n = nn;
     AGAL_TRY(dev_alloc(ctx->mem, &lk->key, (size_t)std::max<uint32_t>(nn, 1u), s));
     AGAL_TRY(dev_alloc(ctx->mem, &lk->q, (size_t)std::max<uint32_t>(nn, 1u) * Q, s));

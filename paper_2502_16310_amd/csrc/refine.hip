@@ -225,7 +225,7 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
         }
         // (iii) children: count marks per level, then merge level by level
         uint32_t *pos[kMaxLevels + 1] = {};
-        const uint32_t *totals[kMaxLevels + 2] = {};
+        uint32_t nmark[kMaxLevels + 2] = {};
         {
             const uint8_t *ins[kMaxLevels + 1];
             int64_t ns[kMaxLevels + 1];
@@ -233,13 +233,10 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
                 AGAL_TRY(pass.get(&pos[m], (size_t)fo->lev[m].n + 1));
                 ins[m] = pm[m];
                 ns[m] = fo->lev[m].n;
-                totals[m] = pos[m] + fo->lev[m].n;
             }
-            AGAL_TRY(scan_flags_u8_multi(ctx, ins, pos, ns, l + 1, s));
+            // marks per level and the balance error word, back through mapped host memory
+            AGAL_TRY(scan_flags_u8_multi(ctx, ins, pos, ns, l + 1, err, nmark, s));
         }
-        totals[l + 1] = err;
-        uint32_t nmark[kMaxLevels + 2] = {};
-        AGAL_TRY(read_back_u32(ctx, totals, l + 2, nmark, s));
         if (nmark[l + 1] != 0) return fail(AGAL_ESTATE, "agal_near_wall_refine: forest lost 2:1 balance");
         // every parent level with marks at once: the new child levels are fresh
         // arrays, and a level that is both a parent (m) and a child (of m - 1)

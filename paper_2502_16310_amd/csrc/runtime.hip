@@ -174,7 +174,7 @@ struct LoadFlagU8 {
 
 template <class In>
 __global__ __launch_bounds__(kScanThreads) void k_scan(In in, uint32_t *out, int64_t n, uint64_t *status,
-                                                       uint32_t *ticket) {
+                                                       uint32_t *ticket, uint32_t *host_total) {
     __shared__ uint32_t s_tile, s_prefix;
     __shared__ uint32_t s_wsum[kScanThreads / dev::kWave];
     if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
@@ -210,7 +210,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(In in, uint32_t *out, int
         int64_t idx = base + i;
         if (idx < n) out[idx] = run;
         run += v[i];
-        if (idx == n - 1) out[n] = run;
+        if (idx == n - 1) {
+            out[n] = run;
+            if (host_total) *host_total = run;
+        }
     }
 }
 
@@ -224,27 +227,45 @@ agal_status lookback_alloc(agal_context ctx, int64_t tiles, uint64_t **status, u
     return AGAL_OK;
 }
 
+// status: tiles + 1 zeroed words (look-back status, then the ticket), or null
+// to have one allocated and zeroed here.  total: when non-null, the sum is
+// written to mapped host memory by the kernel and returned after a stream
+// synchronisation (no separate read-back).
 template <class In>
-static agal_status scan_impl(agal_context ctx, In in, uint32_t *out, int64_t n, hipStream_t s) {
+static agal_status scan_impl(agal_context ctx, In in, uint32_t *out, int64_t n, hipStream_t s,
+                             uint64_t *status = nullptr, uint32_t *total = nullptr) {
     if (n <= 0) {
         fill_u32(out, 0u, 1, s);
+        if (total) *total = 0;
         return AGAL_OK;
     }
-    int64_t tiles = (n + kScanTile - 1) / kScanTile;
-    uint64_t *status = nullptr;
+    const int64_t tiles = scan_tiles(n);
+    const bool own = status == nullptr;
     uint32_t *ticket = nullptr;
-    AGAL_TRY(lookback_alloc(ctx, tiles, &status, &ticket, s));
+    if (own) AGAL_TRY(lookback_alloc(ctx, tiles, &status, &ticket, s));
+    else ticket = reinterpret_cast<uint32_t *>(status + tiles);
     {
         ProfScope prof(ctx, "scan_exclusive", s);
-        hipLaunchKernelGGL(k_scan<In>, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, out, n, status, ticket);
+        hipLaunchKernelGGL(k_scan<In>, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, out, n, status, ticket,
+                           total ? ctx->d_counts : nullptr);
     }
-    dev_free(ctx->mem, status, s);
+    if (own) dev_free(ctx->mem, status, s);
     AGAL_TRY_HIP(hipGetLastError());
+    if (total) {
+        AGAL_TRY_HIP(hipStreamSynchronize(s));
+        *total = ctx->h_counts[0];
+    }
     return AGAL_OK;
 }
 
+int64_t scan_tiles(int64_t n) { return n <= 0 ? 0 : (n + kScanTile - 1) / kScanTile; }
+
 agal_status scan_u32(agal_context ctx, const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s) {
     return scan_impl(ctx, LoadU32{in}, out, n, s);
+}
+agal_status scan_u32_total(agal_context ctx, const uint32_t *in, uint32_t *out, int64_t n, uint64_t *status,
+                           uint32_t *total, hipStream_t s) {
+    return scan_impl(ctx, LoadU32{in}, out, n, s, status, total);
 }
 agal_status scan_flags_u8(agal_context ctx, const uint8_t *in, uint32_t *out, int64_t n, hipStream_t s) {
     return scan_impl(ctx, LoadFlagU8{in}, out, n, s);
@@ -291,22 +312,31 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_flags_multi(MultiScanArgs
     }
     __syncthreads();
     uint32_t run = s_prefix + wpre + incl - sum;
-    if (n == 0 && threadIdx.x == 0) out[0] = 0u;
+    if (n == 0 && threadIdx.x == 0) {
+        out[0] = 0u;
+        a.host_total[seg] = 0u;
+    }
+    if (gtile == 0 && threadIdx.x == 0) a.host_total[a.nseg] = a.extra ? *a.extra : 0u;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const int64_t idx = base + i;
         if (idx < n) out[idx] = run;
         run += v[i];
-        if (idx == n - 1) out[n] = run;
+        if (idx == n - 1) {
+            out[n] = run;
+            a.host_total[seg] = run;
+        }
     }
 }
 
 agal_status scan_flags_u8_multi(agal_context ctx, const uint8_t *const *in, uint32_t *const *out, const int64_t *n,
-                                int k, hipStream_t s) {
+                                int k, const uint32_t *extra, uint32_t *totals, hipStream_t s) {
     if (k <= 0) return AGAL_OK;
     if (k > kMultiScanMax) return fail(AGAL_EINVAL, "scan_flags_u8_multi: at most %d arrays", kMultiScanMax);
     MultiScanArgs a{};
     a.nseg = k;
+    a.extra = extra;
+    a.host_total = ctx->d_counts;
     uint32_t tiles = 0;
     for (int i = 0; i < k; ++i) {
         a.in[i] = in[i];
@@ -324,40 +354,11 @@ agal_status scan_flags_u8_multi(agal_context ctx, const uint8_t *const *in, uint
     }
     dev_free(ctx->mem, status, s);
     AGAL_TRY_HIP(hipGetLastError());
-    return AGAL_OK;
-}
-
-// ---------------------------------------------------------------------------
-// read-back of a few device words
-// ---------------------------------------------------------------------------
-// A one-wave kernel copies the words into mapped pinned host memory; this
-// avoids a DMA transfer per value, whose setup latency dominates such tiny
-// copies.
-constexpr int kReadBackMax = 16;
-struct ReadBackArgs {
-    const uint32_t *src[kReadBackMax];
-    int n;
-    uint32_t *dst;
-};
-
-__global__ void k_read_back(ReadBackArgs a) {
-    const int i = threadIdx.x;
-    if (i < a.n) a.dst[i] = *a.src[i];
-}
-
-agal_status read_back_u32(agal_context ctx, const uint32_t *const *srcs, int n, uint32_t *dst, hipStream_t s) {
-    if (n <= 0) return AGAL_OK;
-    if (n > kReadBackMax) return fail(AGAL_EINVAL, "read_back_u32: at most %d values", kReadBackMax);
-    ReadBackArgs a{};
-    for (int i = 0; i < n; ++i) a.src[i] = srcs[i];
-    a.n = n;
-    a.dst = ctx->d_counts;
-    hipLaunchKernelGGL(k_read_back, dim3(1), dim3(64), 0, s, a);
-    AGAL_TRY_HIP(hipGetLastError());
     AGAL_TRY_HIP(hipStreamSynchronize(s));
-    memcpy(dst, (const void *)ctx->h_counts, (size_t)n * sizeof(uint32_t));
+    for (int i = 0; i <= k; ++i) totals[i] = ctx->h_counts[i];
     return AGAL_OK;
 }
+
 
 // ---------------------------------------------------------------------------
 // lattices
