@@ -117,6 +117,20 @@ __device__ uint32_t lds_prefix(int n, Units units, uint32_t *s_pre) {
     return s_pre[n];
 }
 
+// Body of workgroup `it` in a grid laid out at plan time: pre[b] .. pre[b+1]
+// are body b's workgroups (its planned capacity), so no per-launch prefix is
+// needed; it is workgroup-uniform, so the search reads pre through the scalar
+// cache.
+__device__ __forceinline__ int body_of_wg(const uint32_t *pre, int nb, uint32_t it) {
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= it) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // last i with s_pre[i] <= item (the non-empty range holding item)
 __device__ __forceinline__ int find_seg(const uint32_t *s_pre, int n, uint32_t item) {
     int lo = 0, hi = n - 1;
@@ -314,16 +328,15 @@ __global__ __launch_bounds__(kScanThreads) void k_b_scan(const Seg *segs, int ns
 // refinement, pass p
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ __launch_bounds__(64) void k_b_flag(const BodyDev *bodies, int nb, int p, const uint32_t *cnt) {
+__global__ __launch_bounds__(64) void k_b_flag(const BodyDev *bodies, int nb, int p, const uint32_t *cnt,
+                                               const uint32_t *wg_pre) {
     constexpr int BPW = D == 3 ? 1 : 4;
-    __shared__ uint32_t s_pre[kMaxBodies + 1];
-    const uint32_t total = lds_prefix(nb, [&](int b) {
-        return bodies[b].L > p ? (uint32_t)((cnt[b * kLv + p] + BPW - 1) / BPW) : 0u; }, s_pre);
     {
         // one block (2D: four) per workgroup; the grid covers the planned capacity
         const uint32_t it = blockIdx.x;
-        if (it >= total) return;
-        const int b = __builtin_amdgcn_readfirstlane(find_seg(s_pre, nb, it));   // workgroup-uniform
+        const int b = body_of_wg(wg_pre, nb, it);
+        const uint32_t local = it - wg_pre[b];
+        if (bodies[b].L <= p || local >= (cnt[b * kLv + p] + BPW - 1) / BPW) return;
         const BodyDev &B = bodies[b];
         FlagArgs<D> A{};
         A.faces = dev::Faces{B.coords, B.aabb, B.rec, B.F};
@@ -340,7 +353,7 @@ __global__ __launch_bounds__(64) void k_b_flag(const BodyDev *bodies, int nb, in
         A.h = B.d[p];
         A.cf = B.cf[p][0];
         A.pmark = B.pm[p];
-        flag_wave<D>(A, (int64_t)(it - s_pre[b]) * BPW);
+        flag_wave<D>(A, (int64_t)local * BPW);
     }
 }
 
@@ -466,17 +479,15 @@ struct ChunkRows {
 
 template <int D, int Q>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_b_links(const BodyDev *bodies, int nb, const uint32_t *cnt,
-                                                uint32_t *cursor, Ctl *ctl) {
+                                                uint32_t *cursor, Ctl *ctl, const uint32_t *wg_pre) {
     constexpr int BPW = D == 3 ? 1 : 4;
-    __shared__ uint32_t s_pre[kMaxBodies + 1];
-    const uint32_t total = lds_prefix(nb, [&](int b) {
-        return bodies[b].Q == Q ? (uint32_t)((cnt[b * kLv + bodies[b].L] + BPW - 1) / BPW) : 0u; }, s_pre);
     {
         const uint32_t it = blockIdx.x;
-        if (it >= total) return;
-        const int b = __builtin_amdgcn_readfirstlane(find_seg(s_pre, nb, it));   // workgroup-uniform
+        const int b = body_of_wg(wg_pre, nb, it);
         const BodyDev &B = bodies[b];
         const int L = B.L;
+        const uint32_t local = it - wg_pre[b];
+        if (B.Q != Q || local >= (cnt[b * kLv + L] + BPW - 1) / BPW) return;
         LinkArgs<D, Q> A{};
         A.faces = dev::Faces{B.coords, B.aabb, B.rec, B.F};
         A.bins = B.bins;
@@ -493,7 +504,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         A.q = B.sq;
         A.face = B.sface;
         ChunkRows out{B.blk_start, B.blk_count, cursor + b, B.cap_nodes, ctl};
-        links_wave<D, Q>(A, (int64_t)(it - s_pre[b]) * BPW, out);
+        links_wave<D, Q>(A, (int64_t)local * BPW, out);
     }
 }
 
@@ -590,6 +601,7 @@ struct agal_batch_t {
     bool with_adjoint = false;
     unsigned flag_grid[agal::kMaxLevels] = {};   // workgroups of the flag kernel per pass (from capacities)
     unsigned links_grid[28] = {};                // workgroups of the q kernel per lattice
+    uint32_t *d_wg_pre = nullptr;   // per flag pass, then per lattice (9, 19, 27): nb + 1 workgroup offsets
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<uint32_t> h_cnt, h_nodes;
@@ -731,7 +743,8 @@ static agal_status capture(agal_batch bt) {
     for (int p = 0; p < bt->Lmax; ++p) {
         hipLaunchKernelGGL(k_fill_table, dim3(G), dim3(256), 0, s, bt->d_fills + bt->pass_fill_off[p],
                            bt->pass_fill_n[p]);
-        hipLaunchKernelGGL(k_b_flag<D>, dim3(bt->flag_grid[p]), dim3(64), 0, s, B, nb, p, bt->d_cnt);
+        hipLaunchKernelGGL(k_b_flag<D>, dim3(bt->flag_grid[p]), dim3(64), 0, s, B, nb, p, bt->d_cnt,
+                           bt->d_wg_pre + (size_t)p * (nb + 1));
         for (int m = p; m >= 1; --m)
             hipLaunchKernelGGL(k_b_ripple<D>, dim3(G), dim3(256), 0, s, B, nb, p, m, bt->d_cnt, bt->d_ctl);
         scan(bt->pass_seg_off[p], bt->pass_seg_n[p], true);
@@ -743,14 +756,14 @@ static agal_status capture(agal_batch bt) {
     if (D == 3) {
         if (bt->links_grid[19])
             hipLaunchKernelGGL((k_b_links<3, 19>), dim3(bt->links_grid[19]), dim3(64), 0, s, B, nb, bt->d_cnt,
-                               bt->d_cursor, bt->d_ctl);
+                               bt->d_cursor, bt->d_ctl, bt->d_wg_pre + (size_t)(kLv + 1) * (nb + 1));
         if (bt->links_grid[27])
             hipLaunchKernelGGL((k_b_links<3, 27>), dim3(bt->links_grid[27]), dim3(64), 0, s, B, nb, bt->d_cnt,
-                               bt->d_cursor, bt->d_ctl);
+                               bt->d_cursor, bt->d_ctl, bt->d_wg_pre + (size_t)(kLv + 2) * (nb + 1));
     } else {
         if (bt->links_grid[9])
             hipLaunchKernelGGL((k_b_links<2, 9>), dim3(bt->links_grid[9]), dim3(64), 0, s, B, nb, bt->d_cnt,
-                               bt->d_cursor, bt->d_ctl);
+                               bt->d_cursor, bt->d_ctl, bt->d_wg_pre + (size_t)(kLv + 0) * (nb + 1));
     }
     scan(bt->links_seg_off, nb, false);
     hipLaunchKernelGGL(k_b_nodes, dim3(1), dim3(256), 0, s, B, nb, bt->d_cnt, bt->d_nodes);
@@ -928,11 +941,26 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
     }
     bt->nb_total = bin_base;
     bt->cap_ids = cap_ids;
+    // workgroup offsets per body of the one-block-per-workgroup kernels (flag per pass, q per lattice)
+    std::vector<uint32_t> wg_pre((size_t)(kLv + 3) * (bt->nb + 1), 0u);
     for (int b = 0; b < bt->nb; ++b) {
         const BodyDev &X = bt->bodies[b];
-        for (int p = 0; p < X.L; ++p) bt->flag_grid[p] += (unsigned)((X.cap[p] + (64 / CELLS) - 1) / (64 / CELLS));
-        bt->links_grid[X.Q] += (unsigned)((X.cap[X.L] + (64 / CELLS) - 1) / (64 / CELLS));
+        for (int p = 0; p < kLv; ++p) {
+            wg_pre[(size_t)p * (bt->nb + 1) + b] = bt->flag_grid[p < agal::kMaxLevels ? p : 0];
+            if (p < X.L) bt->flag_grid[p] += (unsigned)((X.cap[p] + (64 / CELLS) - 1) / (64 / CELLS));
+        }
+        for (int k = 0; k < 3; ++k) {
+            const int q = k == 0 ? 9 : (k == 1 ? 19 : 27);
+            wg_pre[(size_t)(kLv + k) * (bt->nb + 1) + b] = bt->links_grid[q];
+            if (X.Q == q) bt->links_grid[X.Q] += (unsigned)((X.cap[X.L] + (64 / CELLS) - 1) / (64 / CELLS));
+        }
     }
+    for (int p = 0; p < kLv; ++p) wg_pre[(size_t)p * (bt->nb + 1) + bt->nb] = bt->flag_grid[p < agal::kMaxLevels ? p : 0];
+    for (int k = 0; k < 3; ++k)
+        wg_pre[(size_t)(kLv + k) * (bt->nb + 1) + bt->nb] = bt->links_grid[k == 0 ? 9 : (k == 1 ? 19 : 27)];
+    AGAL_TRY(own(bt, &bt->d_wg_pre, wg_pre.size()));
+    AGAL_TRY_HIP(hipMemcpyAsync(bt->d_wg_pre, wg_pre.data(), wg_pre.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                bt->cap_stream));
     AGAL_TRY(own(bt, &bt->d_bin_count, (size_t)bt->nb_total));
     AGAL_TRY(own(bt, &bt->d_bin_off, (size_t)bt->nb_total + 1));
     AGAL_TRY(own(bt, &bt->d_bin_cursor, (size_t)bt->nb_total));
