@@ -69,6 +69,16 @@ struct BodyDev {
 };
 
 // Device scalars of a run.
+// Staging rows of a body of node capacity cap: kRowCursors ranges (see
+// ChunkRows) of this many rows each.  A range serves every kRowCursors-th
+// block, so its share is about cap / kRowCursors, give or take a few standard
+// deviations of a sum of block counts (each at most 64); the slack covers that.
+constexpr int kRowCursors = 32;
+constexpr int kCursorStride = 64;   // words: one 256-byte line per cursor
+__host__ __device__ inline int64_t row_range(int64_t cap) {
+    return cap / kRowCursors + cap / 20 / kRowCursors + 8 * (int64_t)sqrt((double)cap) + 128;
+}
+
 struct Ctl {
     uint32_t overflow;   // bit 0 bins, bit 1 forest level, bit 2 nodes
     uint32_t err;        // bit 0 non-finite coordinate, bit 1 face index
@@ -172,7 +182,8 @@ __global__ void k_b_init(const BodyDev *bodies, int nb, uint32_t *cnt, uint32_t 
         for (int i = threadIdx.x; i < nb * kLv; i += blockDim.x) {
             const int b = i / kLv, l = i % kLv;
             cnt[i] = l == 0 ? (uint32_t)(bodies[b].R[0] * bodies[b].R[1] * bodies[b].R[2]) : 0u;
-            if (l == 0) cursor[b] = 0;
+            if (l == 0)
+                for (int r = 0; r < kRowCursors; ++r) cursor[((int64_t)b * kRowCursors + r) * kCursorStride] = 0;
         }
     const uint32_t total = lds_prefix(nb, [&](int b) { return (uint32_t)(bodies[b].R[0] * bodies[b].R[1] * bodies[b].R[2]); }, s_pre);
     AGAL_THREAD_ITEMS(it, total) {
@@ -458,22 +469,29 @@ __global__ void k_b_counts(const BodyDev *bodies, int nb, int p, uint32_t *cnt, 
 // ---------------------------------------------------------------------------
 // link fractions, compaction, adjoint
 // ---------------------------------------------------------------------------
-// Staging rows handed out in block-sized chunks from a per-body cursor.
+// Staging rows handed out in block-sized chunks.  A body's staging area is
+// kRowCursors ranges of row_range(cap) rows, each with its own cursor in its
+// own 256-byte line, and block blk draws from range blk mod kRowCursors.
+// (One counter per body took every block's atomic at one address; those
+// serialise: 86 us of a 206 us pass on C1.)
 struct ChunkRows {
-    uint32_t *blk_start, *blk_count, *cursor;
-    int64_t cap;
+    uint32_t *blk_start, *blk_count, *cursor;   // cursor: this body's kRowCursors counters
+    int64_t cap;                                // node capacity of the body
     Ctl *ctl;
     __device__ int64_t rows(int64_t blk, uint32_t c) {
-        const uint32_t start = c ? atomicAdd(cursor, c) : 0u;
-        if ((int64_t)start + c > cap) {
+        const int r = (int)(blk % kRowCursors);
+        const int64_t range = row_range(cap);
+        const uint32_t start = c ? atomicAdd(&cursor[r * kCursorStride], c) : 0u;
+        if ((int64_t)start + c > range) {
             atomicOr(&ctl->overflow, 4u);
             blk_count[blk] = 0;
             blk_start[blk] = 0;
             return -1;
         }
-        blk_start[blk] = start;
+        const int64_t row = r * range + start;
+        blk_start[blk] = (uint32_t)row;
         blk_count[blk] = c;
-        return start;
+        return row;
     }
 };
 
@@ -503,14 +521,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         A.node_key = B.skey;
         A.q = B.sq;
         A.face = B.sface;
-        ChunkRows out{B.blk_start, B.blk_count, cursor + b, B.cap_nodes, ctl};
+        ChunkRows out{B.blk_start, B.blk_count, cursor + (int64_t)b * kRowCursors * kCursorStride, B.cap_nodes, ctl};
         links_wave<D, Q>(A, (int64_t)local * BPW, out);
     }
 }
 
-__global__ void k_b_nodes(const BodyDev *bodies, int nb, const uint32_t *cnt, uint32_t *nodes) {
-    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x)
-        nodes[b] = bodies[b].blk_off[cnt[b * kLv + bodies[b].L]];
+// Nodes of each body; more than its capacity is reported and clamped (the
+// compaction then leaves out the blocks that would not fit).
+__global__ void k_b_nodes(const BodyDev *bodies, int nb, const uint32_t *cnt, uint32_t *nodes, Ctl *ctl) {
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
+        const uint32_t n = bodies[b].blk_off[cnt[b * kLv + bodies[b].L]];
+        if ((int64_t)n > bodies[b].cap_nodes) atomicOr(&ctl->overflow, 4u);
+        nodes[b] = (uint32_t)std::min<int64_t>(n, bodies[b].cap_nodes);
+    }
 }
 
 template <int D, int Q>
@@ -521,7 +544,9 @@ __global__ __launch_bounds__(64) void k_b_compact(const BodyDev *bodies, int nb,
         const int b = find_seg(s_pre, nb, it);
         const BodyDev &B = bodies[b];
         const uint32_t i = it - s_pre[b];
-        compact_block<Q>((int)B.blk_count[i], B.blk_start[i], B.blk_off[i], B.skey, B.sq, B.sface, B.key, B.q, B.face);
+        const uint32_t c = B.blk_count[i], dst = B.blk_off[i];
+        if ((int64_t)dst + c > B.cap_nodes) continue;   // over capacity (reported by k_b_nodes)
+        compact_block<Q>((int)c, B.blk_start[i], dst, B.skey, B.sq, B.sface, B.key, B.q, B.face);
     }
 }
 
@@ -766,7 +791,7 @@ static agal_status capture(agal_batch bt) {
                                bt->d_cursor, bt->d_ctl, bt->d_wg_pre + (size_t)(kLv + 0) * (nb + 1));
     }
     scan(bt->links_seg_off, nb, false);
-    hipLaunchKernelGGL(k_b_nodes, dim3(1), dim3(256), 0, s, B, nb, bt->d_cnt, bt->d_nodes);
+    hipLaunchKernelGGL(k_b_nodes, dim3(1), dim3(256), 0, s, B, nb, bt->d_cnt, bt->d_nodes, bt->d_ctl);
     if (D == 3) {
         hipLaunchKernelGGL((k_b_compact<3, 19>), dim3(G64), dim3(64), 0, s, B, nb, bt->d_cnt);
         hipLaunchKernelGGL((k_b_compact<3, 27>), dim3(G64), dim3(64), 0, s, B, nb, bt->d_cnt);
@@ -924,9 +949,10 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
         }
         X.cap_nodes = margin(h.nodes, mg);
         const int64_t nL = X.cap[X.L];
-        AGAL_TRY(own(bt, &X.skey, (size_t)X.cap_nodes));
-        AGAL_TRY(own(bt, &X.sq, (size_t)X.cap_nodes * X.Q));
-        AGAL_TRY(own(bt, &X.sface, (size_t)X.cap_nodes * X.Q));
+        const int64_t stage_rows = kRowCursors * row_range(X.cap_nodes);
+        AGAL_TRY(own(bt, &X.skey, (size_t)stage_rows));
+        AGAL_TRY(own(bt, &X.sq, (size_t)stage_rows * X.Q));
+        AGAL_TRY(own(bt, &X.sface, (size_t)stage_rows * X.Q));
         AGAL_TRY(own(bt, &X.blk_start, (size_t)nL));
         AGAL_TRY(own(bt, &X.blk_count, (size_t)nL));
         AGAL_TRY(own(bt, &X.blk_off, (size_t)nL + 1));
@@ -972,7 +998,7 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
     }
     AGAL_TRY(own(bt, &bt->d_cnt, (size_t)bt->nb * kLv));
     AGAL_TRY(own(bt, &bt->d_nodes, (size_t)bt->nb));
-    AGAL_TRY(own(bt, &bt->d_cursor, (size_t)bt->nb));
+    AGAL_TRY(own(bt, &bt->d_cursor, (size_t)bt->nb * kRowCursors * kCursorStride));
     AGAL_TRY(own(bt, &bt->d_ctl, 1));
     AGAL_TRY(own(bt, &bt->d_bodies, (size_t)bt->nb));
 
