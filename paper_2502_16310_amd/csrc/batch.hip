@@ -84,7 +84,6 @@ struct Ctl {
     uint32_t err;        // bit 0 non-finite coordinate, bit 1 face index
     uint32_t balance;    // nonzero: a forest lost 2:1 balance
     uint32_t big_count;
-    uint32_t scan_ticket;
 };
 
 // Scan segment: out[0..n] = exclusive prefix of in[0..n) (n = *n_dev or n_const).
@@ -176,7 +175,6 @@ __global__ void k_b_init(const BodyDev *bodies, int nb, uint32_t *cnt, uint32_t 
         ctl->err = 0;
         ctl->balance = 0;
         ctl->big_count = 0;
-        ctl->scan_ticket = 0;
     }
     if (blockIdx.x == 0)
         for (int i = threadIdx.x; i < nb * kLv; i += blockDim.x) {
@@ -280,14 +278,15 @@ __global__ __launch_bounds__(1024) void k_b_canon_big(const BodyDev *bodies, int
 // segmented exclusive scan (decoupled look-back inside each segment)
 // ---------------------------------------------------------------------------
 template <bool FLAGS>
-__global__ __launch_bounds__(kScanThreads) void k_b_scan(const Seg *segs, int nseg, uint64_t *status, Ctl *ctl) {
+__global__ __launch_bounds__(kScanThreads) void k_b_scan(const Seg *segs, int nseg, uint64_t *status,
+                                                         uint32_t *ticket) {
     __shared__ uint32_t s_pre[kMaxSeg + 1];
     __shared__ uint32_t s_tile, s_prefix;
     __shared__ uint32_t s_wsum[kScanThreads / dev::kWave];
     auto seg_n = [&](int s) -> int64_t { return segs[s].n_dev ? (int64_t)*segs[s].n_dev : segs[s].n_const; };
     const uint32_t total = lds_prefix(nseg, [&](int s) { return (uint32_t)((seg_n(s) + kScanTile) / kScanTile); }, s_pre);
     // every segment has at least one tile (it writes out[n] even when n = 0)
-    if (threadIdx.x == 0) s_tile = atomicAdd(&ctl->scan_ticket, 1u);
+    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
     const uint32_t t = s_tile;
     if (t >= total) return;
@@ -424,6 +423,18 @@ __global__ void k_b_merge(const BodyDev *bodies, int nb, int p, const uint32_t *
         merge_old_item<CELLS>(B.keys[m + 1][c], B.leaf[m + 1][c], B.mark[m + 1][c], has_cf ? B.cf[m + 1][c] : nullptr,
                               B.mk[m], nmk, D, B.keys[m + 1][w], B.leaf[m + 1][w], B.mark[m + 1][w],
                               has_cf ? B.cf[m + 1][w] : nullptr, it - s_pre[s], B.cap[m + 1]);
+    }
+    // the pass marks are consumed (the parents are marked, the scans are done):
+    // clear them for the next pass, which finds them zero as the first pass
+    // finds them from the plan's initial clearing
+    __syncthreads();
+    const uint32_t words = lds_prefix(nseg, [&](int s) {
+        int b, m;
+        return seg_live(bodies, p, s, b, m) ? (uint32_t)((bodies[b].cap[m] + 3) / 4) : 0u; }, s_pre);
+    AGAL_THREAD_ITEMS(it, words) {
+        const int s = find_seg(s_pre, nseg, it);
+        const int b = s / (p + 1), m = s % (p + 1);
+        reinterpret_cast<uint32_t *>(bodies[b].pm[m])[it - s_pre[s]] = 0u;
     }
 }
 
@@ -618,8 +629,9 @@ struct agal_batch_t {
     std::vector<agal::batch::Seg> seg_store;
     agal::batch::Seg *d_segs = nullptr;
     agal::batch::Fill *d_fills = nullptr;
-    int n_fill_init = 0, fill_scan = 0, fill_adj = 0, n_fill_adj = 0;
-    std::vector<int> pass_seg_off, pass_seg_n, pass_fill_off, pass_fill_n;
+    int n_fill_init = 0;
+    std::vector<int> pass_seg_off, pass_seg_n;
+    uint32_t *d_tickets = nullptr;   // one look-back ticket per scan of a run
     int links_seg_off = 0, bins_seg_off = 0;
     int fill_pass_base = 0;
     int wg_per_cu = 4, n_cu = 256;
@@ -747,17 +759,19 @@ static agal_status capture(agal_batch bt) {
     // scans use ticket order; each scan resets the ticket afterwards via the next fill
     // every scan starts from cleared status words and ticket (two fill entries);
     // its grid is the largest tile count any scan of the plan can need
-    auto scan = [&](int seg_off, int nseg, bool flags) {
-        hipLaunchKernelGGL(k_fill_table, dim3(G), dim3(256), 0, s, bt->d_fills + bt->fill_scan, 2);
+    // scan i has its own status words and ticket, all cleared by the first fill
+    auto scan = [&](int idx, int seg_off, int nseg, bool flags) {
         const unsigned grid = (unsigned)bt->status_words;
+        uint64_t *st = bt->d_status + (size_t)idx * bt->status_words;
+        uint32_t *tk = bt->d_tickets + idx;
         if (flags)
-            hipLaunchKernelGGL(k_b_scan<true>, dim3(grid), dim3(kScanThreads), 0, s, bt->d_segs + seg_off, nseg,
-                               bt->d_status, bt->d_ctl);
+            hipLaunchKernelGGL(k_b_scan<true>, dim3(grid), dim3(kScanThreads), 0, s, bt->d_segs + seg_off, nseg, st,
+                               tk);
         else
-            hipLaunchKernelGGL(k_b_scan<false>, dim3(grid), dim3(kScanThreads), 0, s, bt->d_segs + seg_off, nseg,
-                               bt->d_status, bt->d_ctl);
+            hipLaunchKernelGGL(k_b_scan<false>, dim3(grid), dim3(kScanThreads), 0, s, bt->d_segs + seg_off, nseg, st,
+                               tk);
     };
-    scan(bt->bins_seg_off, 1, false);
+    scan(0, bt->bins_seg_off, 1, false);
     hipLaunchKernelGGL(k_b_bin_scatter<D>, dim3(G), dim3(256), 0, s, B, nb, bt->d_bin_off, bt->d_bin_cursor, bt->d_ids,
                        bt->cap_ids, bt->d_ctl);
     hipLaunchKernelGGL(k_b_bin_clear, dim3(G), dim3(256), 0, s, bt->d_bin_off, bt->nb_total, bt->d_ctl);
@@ -766,13 +780,11 @@ static agal_status capture(agal_batch bt) {
     hipLaunchKernelGGL(k_b_canon_big<D>, dim3(std::min<unsigned>(G, 256)), dim3(1024), 0, s, B, nb, bt->d_bin_off,
                        bt->d_ids, bt->d_big, bt->d_ctl);
     for (int p = 0; p < bt->Lmax; ++p) {
-        hipLaunchKernelGGL(k_fill_table, dim3(G), dim3(256), 0, s, bt->d_fills + bt->pass_fill_off[p],
-                           bt->pass_fill_n[p]);
         hipLaunchKernelGGL(k_b_flag<D>, dim3(bt->flag_grid[p]), dim3(64), 0, s, B, nb, p, bt->d_cnt,
                            bt->d_wg_pre + (size_t)p * (nb + 1));
         for (int m = p; m >= 1; --m)
             hipLaunchKernelGGL(k_b_ripple<D>, dim3(G), dim3(256), 0, s, B, nb, p, m, bt->d_cnt, bt->d_ctl);
-        scan(bt->pass_seg_off[p], bt->pass_seg_n[p], true);
+        scan(1 + p, bt->pass_seg_off[p], bt->pass_seg_n[p], true);
         hipLaunchKernelGGL(k_b_mark_parents, dim3(G), dim3(256), 0, s, B, nb, p, bt->d_cnt);
         hipLaunchKernelGGL(k_b_merge<D>, dim3(G), dim3(256), 0, s, B, nb, p, bt->d_cnt);
         hipLaunchKernelGGL(k_b_children<D>, dim3(G), dim3(256), 0, s, B, nb, p, bt->d_cnt);
@@ -790,7 +802,7 @@ static agal_status capture(agal_batch bt) {
             hipLaunchKernelGGL((k_b_links<2, 9>), dim3(bt->links_grid[9]), dim3(64), 0, s, B, nb, bt->d_cnt,
                                bt->d_cursor, bt->d_ctl, bt->d_wg_pre + (size_t)(kLv + 0) * (nb + 1));
     }
-    scan(bt->links_seg_off, nb, false);
+    scan(1 + bt->Lmax, bt->links_seg_off, nb, false);
     hipLaunchKernelGGL(k_b_nodes, dim3(1), dim3(256), 0, s, B, nb, bt->d_cnt, bt->d_nodes, bt->d_ctl);
     if (D == 3) {
         hipLaunchKernelGGL((k_b_compact<3, 19>), dim3(G64), dim3(64), 0, s, B, nb, bt->d_cnt);
@@ -799,7 +811,6 @@ static agal_status capture(agal_batch bt) {
         hipLaunchKernelGGL((k_b_compact<2, 9>), dim3(G64), dim3(64), 0, s, B, nb, bt->d_cnt);
     }
     if (bt->with_adjoint) {
-        hipLaunchKernelGGL(k_fill_table, dim3(G), dim3(256), 0, s, bt->d_fills + bt->fill_adj, bt->n_fill_adj);
         if (D == 3) {
             hipLaunchKernelGGL((k_b_adjoint<3, 19>), dim3(G), dim3(kAdjThreads), 0, s, B, nb, bt->d_nodes);
             hipLaunchKernelGGL((k_b_adjoint<3, 27>), dim3(G), dim3(kAdjThreads), 0, s, B, nb, bt->d_nodes);
@@ -1045,38 +1056,25 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
             sg.n_dev = nullptr;
         }
     bt->status_words = max_sw + 1;
-    AGAL_TRY(own(bt, &bt->d_status, (size_t)bt->status_words + 1));
+    const int n_scans = bt->Lmax + 2;   // bins, one per pass, links
+    AGAL_TRY(own(bt, &bt->d_status, (size_t)bt->status_words * n_scans));
+    AGAL_TRY(own(bt, &bt->d_tickets, (size_t)n_scans));
     AGAL_TRY(own(bt, &bt->d_segs, bt->seg_store.size()));
 
-    // ---- fill table ------------------------------------------------------------
+    // ---- fill table: everything a run needs cleared, in the run's first launch --
     std::vector<Fill> fills;
     auto words = [](size_t bytes) { return (int64_t)((bytes + 3) / 4); };
     fills.push_back({bt->d_bin_count, words(bt->nb_total * 4), 0u});
     fills.push_back({bt->d_bin_cursor, words(bt->nb_total * 4), 0u});
-    bt->n_fill_init = (int)fills.size();
-    bt->fill_scan = (int)fills.size();
-    fills.push_back({reinterpret_cast<uint32_t *>(bt->d_status), words(bt->status_words * 8), 0u});
-    fills.push_back({&bt->d_ctl->scan_ticket, 1, 0u});
-    bt->fill_adj = (int)fills.size();
-    bt->n_fill_adj = 0;
-    if (bt->with_adjoint)
-        for (int b = 0; b < bt->nb; ++b) {
-            fills.push_back({reinterpret_cast<uint32_t *>(bt->bodies[b].grad_v), words(bt->bodies[b].Nv * D * 4), 0u});
-            bt->n_fill_adj++;
-        }
-    for (int p = 0; p < bt->Lmax; ++p) {
-        bt->pass_fill_off.push_back((int)fills.size());
-        int n = 0;
-        for (int b = 0; b < bt->nb; ++b) {
-            const BodyDev &X = bt->bodies[b];
-            if (X.L <= p) continue;
-            for (int m = 0; m <= p; ++m) {
-                fills.push_back({reinterpret_cast<uint32_t *>(X.pm[m]), words(X.cap[m]), 0u});
-                ++n;
-            }
-        }
-        bt->pass_fill_n.push_back(n);
+    fills.push_back({reinterpret_cast<uint32_t *>(bt->d_status), words((size_t)bt->status_words * n_scans * 8), 0u});
+    fills.push_back({bt->d_tickets, n_scans, 0u});
+    for (int b = 0; b < bt->nb; ++b) {
+        const BodyDev &X = bt->bodies[b];
+        for (int m = 0; m < X.L; ++m) fills.push_back({reinterpret_cast<uint32_t *>(X.pm[m]), words(X.cap[m]), 0u});
+        if (bt->with_adjoint)
+            fills.push_back({reinterpret_cast<uint32_t *>(X.grad_v), words(X.Nv * D * 4), 0u});
     }
+    bt->n_fill_init = (int)fills.size();
     AGAL_TRY(own(bt, &bt->d_fills, fills.size()));
     AGAL_TRY_HIP(hipMemcpyAsync(bt->d_fills, fills.data(), fills.size() * sizeof(Fill), hipMemcpyHostToDevice,
                                 bt->cap_stream));
