@@ -337,7 +337,7 @@ __global__ __launch_bounds__(kScanThreads) void k_b_scan(const Seg *segs, int ns
 // ---------------------------------------------------------------------------
 // refinement, pass p
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, bool kDedup>
 __global__ __launch_bounds__(64) void k_b_flag(const BodyDev *bodies, int nb, int p, const uint32_t *cnt,
                                                const uint32_t *wg_pre) {
     constexpr int BPW = D == 3 ? 1 : 4;
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(64) void k_b_flag(const BodyDev *bodies, int nb, in
         A.h = B.d[p];
         A.cf = B.cf[p][0];
         A.pmark = B.pm[p];
-        flag_wave<D>(A, (int64_t)local * BPW);
+        flag_wave<D, kDedup>(A, (int64_t)local * BPW);
     }
 }
 
@@ -637,6 +637,7 @@ struct agal_batch_t {
     int wg_per_cu = 4, n_cu = 256;
     bool with_adjoint = false;
     unsigned flag_grid[agal::kMaxLevels] = {};   // workgroups of the flag kernel per pass (from capacities)
+    bool flag_dedup[agal::kMaxLevels] = {};      // the flag pass takes the deduplicating walker
     unsigned links_grid[28] = {};                // workgroups of the q kernel per lattice
     uint32_t *d_wg_pre = nullptr;   // per flag pass, then per lattice (9, 19, 27): nb + 1 workgroup offsets
     hipGraph_t graph = nullptr;
@@ -780,8 +781,12 @@ static agal_status capture(agal_batch bt) {
     hipLaunchKernelGGL(k_b_canon_big<D>, dim3(std::min<unsigned>(G, 256)), dim3(1024), 0, s, B, nb, bt->d_bin_off,
                        bt->d_ids, bt->d_big, bt->d_ctl);
     for (int p = 0; p < bt->Lmax; ++p) {
-        hipLaunchKernelGGL(k_b_flag<D>, dim3(bt->flag_grid[p]), dim3(64), 0, s, B, nb, p, bt->d_cnt,
-                           bt->d_wg_pre + (size_t)p * (nb + 1));
+        if (bt->flag_dedup[p])
+            hipLaunchKernelGGL((k_b_flag<D, true>), dim3(bt->flag_grid[p]), dim3(64), 0, s, B, nb, p, bt->d_cnt,
+                               bt->d_wg_pre + (size_t)p * (nb + 1));
+        else
+            hipLaunchKernelGGL((k_b_flag<D, false>), dim3(bt->flag_grid[p]), dim3(64), 0, s, B, nb, p, bt->d_cnt,
+                               bt->d_wg_pre + (size_t)p * (nb + 1));
         for (int m = p; m >= 1; --m)
             hipLaunchKernelGGL(k_b_ripple<D>, dim3(G), dim3(256), 0, s, B, nb, p, m, bt->d_cnt, bt->d_ctl);
         scan(1 + p, bt->pass_seg_off[p], bt->pass_seg_n[p], true);
@@ -993,6 +998,27 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
         }
     }
     for (int p = 0; p < kLv; ++p) wg_pre[(size_t)p * (bt->nb + 1) + bt->nb] = bt->flag_grid[p < agal::kMaxLevels ? p : 0];
+    // as in the single-body pass: the deduplicating walker when some body's query boxes span more than 64 bins
+    // and the pass has fewer than 32 workgroups per CU (bound by its longest waves)
+    {
+        int ncu = 0, cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, cur) != hipSuccess || ncu < 1)
+            ncu = 256;
+        (void)hipGetLastError();
+        for (int p = 0; p < agal::kMaxLevels; ++p) {
+            double most = 0.0;
+            for (int b = 0; b < bt->nb; ++b) {
+                const BodyDev &X = bt->bodies[b];
+                if (X.L <= p) continue;
+                double nbins = 1.0;
+                for (int a = 0; a < D; ++a)
+                    nbins *= std::min((double)X.bins.B, std::floor((4.0 * X.dx[p][a] + 2.0 * X.d[p]) * X.bins.s[a]) + 2.0);
+                most = std::max(most, nbins);
+            }
+            bt->flag_dedup[p] = most > 64.0 && bt->flag_grid[p] < 32u * (unsigned)ncu;
+        }
+    }
     for (int k = 0; k < 3; ++k)
         wg_pre[(size_t)(kLv + k) * (bt->nb + 1) + bt->nb] = bt->links_grid[k == 0 ? 9 : (k == 1 ? 19 : 27)];
     AGAL_TRY(own(bt, &bt->d_wg_pre, wg_pre.size()));
