@@ -186,9 +186,12 @@ struct MultiScanArgs {
     const uint32_t *extra;   // one more device word to report (or null: 0)
     uint32_t *host_total;    // mapped host memory: k totals, then *extra
 };
-// totals[0..k-1] = sum of each array, totals[k] = *extra; synchronises the stream.
+// totals[0..k-1] = sum of each array, totals[k] = *extra; synchronises the stream.  status_zeroed: null, or
+// scan_flags_u8_multi_tiles(n, k) + 1 zeroed 64-bit words the caller provides.
 agal_status scan_flags_u8_multi(agal_context ctx, const uint8_t *const *in, uint32_t *const *out, const int64_t *n,
-                                int k, const uint32_t *extra, uint32_t *totals, hipStream_t s);
+                                int k, const uint32_t *extra, uint32_t *totals, hipStream_t s,
+                                uint64_t *status_zeroed = nullptr);
+int64_t scan_flags_u8_multi_tiles(const int64_t *n, int k);
 // Tiles of a scan of n elements; a caller-provided status buffer holds tiles + 1 zeroed 64-bit words.
 int64_t scan_tiles(int64_t n);
 // Exclusive scan whose sum comes back through mapped host memory (synchronises the stream); status is a

@@ -46,7 +46,11 @@ struct BlockSlots {
 };
 
 template <int D, int Q>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_links(LinkArgs<D, Q> A, uint32_t *count) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_links(LinkArgs<D, Q> A, uint32_t *count, uint64_t *zero,
+                                                                                           int64_t nzero) {
+    // the look-back status words of the scan that follows, cleared here
+    // rather than by a launch of their own
+    for (int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x; i < nzero; i += (int64_t)gridDim.x * 64) zero[i] = 0;
     BlockSlots<D == 3 ? 64 : 16> out{count};
     links_wave<D, Q>(A, (int64_t)blockIdx.x * (D == 3 ? 1 : 4), out);
 }
@@ -85,10 +89,11 @@ agal_status links_forward(agal_geom g, agal_bins bn, agal_forest fo, const Latti
         agal_context ctx;
         hipStream_t s;
         uint32_t *count = nullptr, *off = nullptr;
-        uint64_t *key = nullptr;
+        uint64_t *key = nullptr, *status = nullptr;
         float *q = nullptr;
         int32_t *face = nullptr;
         ~Staging() {
+            dev_free(ctx->mem, status, s);
             dev_free(ctx->mem, count, s);
             dev_free(ctx->mem, off, s);
             dev_free(ctx->mem, key, s);
@@ -98,6 +103,7 @@ agal_status links_forward(agal_geom g, agal_bins bn, agal_forest fo, const Latti
     } st{ctx, s};
     AGAL_TRY(dev_alloc(ctx->mem, &st.count, (size_t)LL.n, s));
     AGAL_TRY(dev_alloc(ctx->mem, &st.off, (size_t)LL.n + 1, s));
+    AGAL_TRY(dev_alloc(ctx->mem, &st.status, (size_t)scan_tiles(LL.n) + 1, s));
     AGAL_TRY(dev_alloc(ctx->mem, &st.key, (size_t)cap, s));
     AGAL_TRY(dev_alloc(ctx->mem, &st.q, (size_t)cap * Q, s));
     AGAL_TRY(dev_alloc(ctx->mem, &st.face, (size_t)cap * Q, s));
@@ -124,11 +130,12 @@ agal_status links_forward(agal_geom g, agal_bins bn, agal_forest fo, const Latti
     const int64_t waves = (LL.n + BPW - 1) / BPW;
     {
         ProfScope prof(ctx, "q_links", s);
-        hipLaunchKernelGGL((k_links<D, Q>), dim3((unsigned)waves), dim3(64), 0, s, A, st.count);
+        hipLaunchKernelGGL((k_links<D, Q>), dim3((unsigned)waves), dim3(64), 0, s, A, st.count, st.status,
+                           scan_tiles(LL.n) + 1);
     }
     AGAL_TRY_HIP(hipGetLastError());
     uint32_t nn = 0;
-    AGAL_TRY(scan_u32_total(ctx, st.count, st.off, LL.n, nullptr, &nn, s));
+    AGAL_TRY(scan_u32_total(ctx, st.count, st.off, LL.n, st.status, &nn, s));
     lk->n = nn;
     AGAL_TRY(dev_alloc(ctx->mem, &lk->key, (size_t)std::max<uint32_t>(nn, 1u), s));
     AGAL_TRY(dev_alloc(ctx->mem, &lk->q, (size_t)std::max<uint32_t>(nn, 1u) * Q, s));

@@ -173,17 +173,25 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
 
     for (int l = 0; l < fo->L; ++l) {
         Scratch pass{ctx, s, {}};
-        // pass marks of every level l' <= l, one zeroed buffer
+        // one zeroed buffer: the look-back status words of this pass's scan of
+        // the marks, then the pass marks of every level l' <= l
         uint8_t *pm[kMaxLevels + 1] = {};
+        uint64_t *scan_status = nullptr;
         {
-            int64_t tot = 0;
-            for (int m = 0; m <= l; ++m) tot += fo->lev[m].n;
-            uint8_t *pmb = nullptr;
-            AGAL_TRY(pass.get(&pmb, (size_t)std::max<int64_t>(tot, 1)));
-            fill_u8(pmb, 0, tot, s);
-            int64_t at = 0;
+            int64_t ns[kMaxLevels + 1], tot = 0;
             for (int m = 0; m <= l; ++m) {
-                pm[m] = pmb + at;
+                ns[m] = fo->lev[m].n;
+                tot += ns[m];
+            }
+            const int64_t status_bytes = 8 * (scan_flags_u8_multi_tiles(ns, l + 1) + 1);
+            uint8_t *buf = nullptr;
+            const int64_t words = (status_bytes + tot + 3) / 4;
+            AGAL_TRY(pass.get(&buf, (size_t)(4 * words)));
+            fill_u32(reinterpret_cast<uint32_t *>(buf), 0u, words, s);
+            scan_status = reinterpret_cast<uint64_t *>(buf);
+            int64_t at = status_bytes;
+            for (int m = 0; m <= l; ++m) {
+                pm[m] = buf + at;
                 at += fo->lev[m].n;
             }
         }
@@ -235,7 +243,7 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
                 ns[m] = fo->lev[m].n;
             }
             // marks per level and the balance error word, back through mapped host memory
-            AGAL_TRY(scan_flags_u8_multi(ctx, ins, pos, ns, l + 1, err, nmark, s));
+            AGAL_TRY(scan_flags_u8_multi(ctx, ins, pos, ns, l + 1, err, nmark, s, scan_status));
         }
         if (nmark[l + 1] != 0) return fail(AGAL_ESTATE, "agal_near_wall_refine: forest lost 2:1 balance");
         // every parent level with marks at once: the new child levels are fresh

@@ -329,8 +329,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_flags_multi(MultiScanArgs
     }
 }
 
+int64_t scan_flags_u8_multi_tiles(const int64_t *n, int k) {
+    int64_t tiles = 0;
+    for (int i = 0; i < k; ++i) tiles += std::max<int64_t>(1, (n[i] + kScanTile - 1) / kScanTile);
+    return tiles;
+}
+
 agal_status scan_flags_u8_multi(agal_context ctx, const uint8_t *const *in, uint32_t *const *out, const int64_t *n,
-                                int k, const uint32_t *extra, uint32_t *totals, hipStream_t s) {
+                                int k, const uint32_t *extra, uint32_t *totals, hipStream_t s, uint64_t *status_zeroed) {
     if (k <= 0) return AGAL_OK;
     if (k > kMultiScanMax) return fail(AGAL_EINVAL, "scan_flags_u8_multi: at most %d arrays", kMultiScanMax);
     MultiScanArgs a{};
@@ -345,14 +351,15 @@ agal_status scan_flags_u8_multi(agal_context ctx, const uint8_t *const *in, uint
         a.tile0[i] = tiles;
         tiles += (uint32_t)std::max<int64_t>(1, (n[i] + kScanTile - 1) / kScanTile);   // an empty array still writes out[0]
     }
-    uint64_t *status = nullptr;
+    uint64_t *status = status_zeroed;
     uint32_t *ticket = nullptr;
-    AGAL_TRY(lookback_alloc(ctx, tiles, &status, &ticket, s));
+    if (status) ticket = reinterpret_cast<uint32_t *>(status + tiles);
+    else AGAL_TRY(lookback_alloc(ctx, tiles, &status, &ticket, s));
     {
         ProfScope prof(ctx, "scan_exclusive", s);
         hipLaunchKernelGGL(k_scan_flags_multi, dim3(tiles), dim3(kScanThreads), 0, s, a, status, ticket);
     }
-    dev_free(ctx->mem, status, s);
+    if (!status_zeroed) dev_free(ctx->mem, status, s);
     AGAL_TRY_HIP(hipGetLastError());
     AGAL_TRY_HIP(hipStreamSynchronize(s));
     for (int i = 0; i <= k; ++i) totals[i] = ctx->h_counts[i];
