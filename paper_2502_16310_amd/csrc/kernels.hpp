@@ -282,27 +282,33 @@ __device__ __forceinline__ void for_candidates(const dev::BinGrid &g, const int 
 // 64 at a time.  stage(has, f, r) is called by the whole wave with up to 64
 // such faces (r the lane's face record) and returns false to stop.  A face
 // that finds no free slot within kSeenProbes tries is passed on as new, so a
-// crowded set can let a repeat through; stage() must tolerate that.
+// crowded set can let a repeat through; stage() must tolerate that.  With W > 1
+// waves walking the same box, wave w keeps only the ids with id % W == w, and
+// the waves synchronise only within themselves.
 constexpr int kSeen = 1024;             // hash-set slots (power of two)
 constexpr int kSeenProbes = 16;         // slots tried before a face is let through as new
 constexpr int kUniqCap = 5 * 64;        // faces waiting for their records
 
-template <int D, class Stage>
+template <int D, int W = 1, class Stage>
 __device__ __forceinline__ void for_unique_candidates(const dev::BinGrid &g, const float *rec, const int ilo[3],
                                                       const int ihi[3], int32_t *s_seen, int32_t *s_list,
-                                                      uint32_t *s_bpre, uint32_t *s_bs0, Stage &&stage) {
+                                                      uint32_t *s_bpre, uint32_t *s_bs0, Stage &&stage, int w = 0) {
     constexpr int RF = dev::kRecFloats<D>;
+    auto sync = [] {
+        if constexpr (W == 1) __syncthreads();
+        else dev::wave_sync();
+    };
     const int lane = dev::lane_id();
     const int nx = ihi[0] - ilo[0] + 1, ny = ihi[1] - ilo[1] + 1, nz = ihi[2] - ilo[2] + 1;
     const int nbins = nx * ny * nz;
-    __syncthreads();
+    sync();
     for (int i = lane; i < kSeen; i += dev::kWave) s_seen[i] = -1;
     int nl = 0;   // wave-uniform list length
     // records of list entries 0 .. t-1, one per lane, to stage(); the rest moves to the front
     auto flush = [&](int t) -> bool {
-        __syncthreads();
+        sync();
         const int32_t f = lane < t ? s_list[lane] : -1;
-        __syncthreads();
+        sync();
         for (int i = lane; i < nl - t; i += dev::kWave) s_list[i] = s_list[t + i];   // up to 4 x 64 remain
         nl -= t;
         float r[RF];
@@ -324,13 +330,13 @@ __device__ __forceinline__ void for_unique_candidates(const dev::BinGrid &g, con
         // the non-empty bins in list order, for a binary search per list entry
         const uint64_t ne = __ballot(cnt > 0);
         const int nne = __popcll(ne);
-        __syncthreads();
+        sync();
         if (cnt > 0) {
             const int k = dev::lanes_below(ne);
             s_bpre[k] = incl - cnt;
             s_bs0[k] = s0;
         }
-        __syncthreads();
+        sync();
         for (uint32_t c0 = 0; c0 < total; c0 += 4 * dev::kWave) {
             int32_t id[4];
 #pragma unroll
@@ -345,6 +351,7 @@ __device__ __forceinline__ void for_unique_candidates(const dev::BinGrid &g, con
                         else hi = mid - 1;
                     }
                     id[q] = g.ids[s_bs0[lo] + (v - s_bpre[lo])];
+                    if (W > 1 && id[q] % W != w) id[q] = -1;
                 }
             }
 #pragma unroll
@@ -395,15 +402,28 @@ struct FlagArgs {
     uint8_t *pmark;  // n
 };
 
-// One wave: blocks first .. first + 64/4^D - 1 of A (one lane per cell).
-template <int D, bool kDedup = false>
+// One wave: blocks first .. first + 64/4^D - 1 of A (one lane per cell).  With
+// W > 1 the W waves of a workgroup take the same blocks and split their
+// candidate faces by id (face f to wave f % W), each with its own staging and
+// queue; the cell flags are one LDS array that every wave sets and reads, so a
+// cell flagged by one wave drops out of the others' tests too.  That puts W
+// SIMDs on a block for passes with fewer blocks than the chip has room for,
+// where the time is that of the longest wave.
+template <int D, bool kDedup = false, int W = 1>
 __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
     constexpr int CELLS = D == 3 ? 64 : 16;
     constexpr int BPW = 64 / CELLS;
     constexpr int NF = D * D;   // staged corner coordinates
-    __shared__ float s_f[NF][kFlagCap];
-    __shared__ __align__(16) uint32_t s_code[kFlagCap];
-    const int lane = threadIdx.x;
+    auto sync = [] {
+        if constexpr (W == 1) __syncthreads();
+        else dev::wave_sync();
+    };
+    __shared__ float s_f_all[W][NF][kFlagCap];
+    __shared__ __align__(16) uint32_t s_code_all[W][kFlagCap];
+    const int lane = threadIdx.x % dev::kWave;
+    const int w = W == 1 ? 0 : (int)threadIdx.x / dev::kWave;
+    float(*s_f)[kFlagCap] = s_f_all[w];
+    uint32_t *s_code = s_code_all[w];
     const int64_t blk = first + lane / CELLS;
     const bool valid = blk < A.n;
     const int cell = lane % CELLS;
@@ -449,17 +469,20 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
     // faces does not hold the wave while the other lanes idle.  A pair whose
     // cell is flagged meanwhile is dropped.
     constexpr int TCAP = 128;   // below 64 after a take, at most 64 added per step
-    __shared__ uint32_t s_q[TCAP];
-    __shared__ float s_m[64][3];
+    __shared__ uint32_t s_q_all[W][TCAP];
+    __shared__ float s_m_all[W][64][3];
     __shared__ int s_fl[64];
+    uint32_t *s_q = s_q_all[w];
+    float(*s_m)[3] = s_m_all[w];
 #pragma unroll
     for (int a = 0; a < 3; ++a) s_m[lane][a] = m[a];
-    s_fl[lane] = flagged ? 1 : 0;
+    if (w == 0) s_fl[lane] = flagged ? 1 : 0;
+    if constexpr (W > 1) __syncthreads();   // every wave sees the initial flags
     int nq = 0;   // wave-uniform
     auto take = [&](int t) {
-        __syncthreads();
+        sync();
         const uint32_t item = lane < t ? s_q[lane] : 0u;
-        __syncthreads();
+        sync();
         if (lane < nq - t) s_q[lane] = s_q[t + lane];
         nq -= t;
         const int l = (int)(item >> 7), j = (int)(item & 127u);
@@ -477,7 +500,7 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
     // Batches of 64 staged faces: each lane marks the faces its cube's box axes do
     // not separate from it and queues them for the full test, until flagged.
     auto test_staged = [&](int n) {
-        __syncthreads();
+        sync();
         for (int j0 = 0; j0 < n; j0 += 64) {
             flagged = s_fl[lane] != 0;
             if (__ballot(!flagged) == 0) break;
@@ -504,19 +527,21 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
                 nq += __popcll(want);
                 if (nq >= 64) {
                     take(64);
-                    __syncthreads();
+                    sync();
                     if (s_fl[lane]) nm = 0;   // flagged meanwhile: nothing more to queue
                 }
             }
         }
         if (nq > 0) take(nq);
-        __syncthreads();
+        sync();
         flagged = s_fl[lane] != 0;
     };
 
-    __shared__ int32_t s_seen[kDedup ? kSeen : 1];
-    __shared__ int32_t s_list[kDedup ? kUniqCap : 1];
-    __shared__ uint32_t s_bpre[kDedup ? 64 : 1], s_bs0[kDedup ? 64 : 1];
+    __shared__ int32_t s_seen_all[W][kDedup ? kSeen : 1];
+    __shared__ int32_t s_list_all[W][kDedup ? kUniqCap : 1];
+    __shared__ uint32_t s_bpre_all[W][kDedup ? 64 : 1], s_bs0_all[W][kDedup ? 64 : 1];
+    int32_t *s_seen = s_seen_all[w], *s_list = s_list_all[w];
+    uint32_t *s_bpre = s_bpre_all[w], *s_bs0 = s_bs0_all[w];
     bool done = __ballot(!flagged) == 0;
     for (int sb = 0; sb < BPW && !done; ++sb) {
         if (first + sb >= A.n) break;
@@ -562,13 +587,13 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
             return true;
         };
         if constexpr (kDedup) {
-            for_unique_candidates<D>(A.bins, A.faces.rec, ilo, ihi, s_seen, s_list, s_bpre, s_bs0, stage);
+            for_unique_candidates<D, W>(A.bins, A.faces.rec, ilo, ihi, s_seen, s_list, s_bpre, s_bs0, stage, w);
         } else {
             for_candidates(A.bins, ilo, ihi, [&](bool has, int32_t f, const int cur[3]) -> bool {
                 // visit each face once: in the first bin of (its bins) x (query bins)
                 float r[dev::kRecFloats<D>];
-                bool first_bin = has;
-                if (has) {
+                bool first_bin = has && (W == 1 || f % W == w);
+                if (first_bin) {
                     dev::load_rec<D>(A.faces.rec, f, r);
 #pragma unroll
                     for (int a = 0; a < D; ++a)
@@ -580,6 +605,11 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
         }
     }
     if (!done && count > 0) test_staged(count);
+    if constexpr (W > 1) {
+        __syncthreads();   // every wave's flags are in
+        flagged = s_fl[lane] != 0;
+        if (w != 0) return;
+    }
 
     if (valid) A.cf[blk * CELLS + cell] = flagged ? 1 : 0;
     // block mark: OR over the block's cells
@@ -588,6 +618,126 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
         uint64_t bm = fm;
         if constexpr (CELLS < 64) bm = (fm >> (lane & ~(CELLS - 1))) & ((1ull << CELLS) - 1);
         A.pmark[blk] = bm ? 1 : 0;
+    }
+}
+
+// Face-centric flag pass.  A cell's flag is an OR over faces of one FP32 test
+// (sat_triangle / sat_segment at the cell centre, half-width h), so it can be
+// gathered from the faces' side as well: each face visits the cells whose
+// centre lies within h + eps of its box on every axis (a superset of the cells
+// whose box-axis tests it passes) and sets the flag of each cell it is not
+// separated from.  The work is a few cells per face, spread over every lane of
+// the chip, where the cell-centric pass is as long as its busiest block's wave
+// (a coarse block's query box spans hundreds of bins).  Cells of blocks that
+// do not exist at the level are skipped: a dense table over the level's block
+// grid holds each block's index + 1 (0: absent); at level 0 every block exists
+// and the index is the linear one.  Cell flags and block marks must start at
+// zero; only ones are stored, so faces that meet the same cell race harmlessly.
+constexpr int kFaceFlagG = 16;   // faces per wave
+
+template <int D>
+struct FaceFlagArgs {
+    const float *rec;         // F x kRecFloats<D>
+    int64_t F;
+    int NB[3];                // blocks per axis at this level (roots << level)
+    const uint32_t *table;    // NB0 NB1 NB2 entries, x fastest; null at level 0
+    float lo[3];
+    float dx[3];              // cell size at this level
+    float eps[3];
+    float h;
+    uint8_t *cf;              // n x 4^D, zeroed
+    uint8_t *pmark;           // n, zeroed
+};
+
+// One wave: faces face0 .. face0 + kFaceFlagG - 1.  The (face, cell) pairs of
+// its faces are listed in face order and taken 64 at a time, one per lane.
+template <int D>
+__device__ __forceinline__ void flag_faces_wave(const FaceFlagArgs<D> &A, int64_t face0,
+                                                float (*s_rec)[dev::kRecFloats<D>], int (*s_i)[8]) {
+    constexpr int RF = dev::kRecFloats<D>;
+    constexpr int CELLS = D == 3 ? 64 : 16;
+    constexpr int G = kFaceFlagG;
+    static_assert(G == 16, "face search below takes 4 steps");
+    const int lane = dev::lane_id();
+    uint32_t cnt = 0;
+    if (lane < G) {
+        const int64_t f = face0 + lane;
+        int ilo[3] = {0, 0, 0}, n[3] = {0, 1, 1};
+        if (f < A.F) {
+            float r[RF];
+            dev::load_rec<D>(A.rec, f, r);
+#pragma unroll
+            for (int k = 0; k < RF; ++k) s_rec[lane][k] = r[k];
+            cnt = 1;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                // cells i with centre lo + (i + 1/2) dx in [min - h - eps, max + h + eps]
+                const int nc = 4 * A.NB[a];
+                const double lo = A.lo[a], dx = A.dx[a], reach = (double)A.h + (double)A.eps[a];
+                const double xl = fmax(((double)r[D * D + a] - reach - lo) / dx - 0.5, -1.0);
+                const double xh = fmin(((double)r[D * D + D + a] + reach - lo) / dx - 0.5, (double)nc);
+                const int i0 = max(0, (int)ceil(xl));
+                const int i1 = min(nc - 1, (int)floor(xh));
+                ilo[a] = i0;
+                n[a] = max(0, i1 - i0 + 1);
+                cnt *= (uint32_t)n[a];
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            s_i[lane][a] = ilo[a];
+            s_i[lane][3 + a] = n[a];
+        }
+    }
+    const uint32_t incl = dev::wave_inclusive_sum(cnt);
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, dev::kWave - 1);
+    if (lane < G) s_i[lane][6] = (int)(incl - cnt);
+    dev::wave_sync();
+    for (uint32_t c0 = 0; c0 < total; c0 += dev::kWave) {
+        const uint32_t v = c0 + lane;
+        if (v >= total) continue;
+        int k = 0;   // the last face whose pairs start at or before v
+#pragma unroll
+        for (int step = G / 2; step >= 1; step >>= 1)
+            if ((uint32_t)s_i[k + step][6] <= v) k += step;
+        uint32_t u = v - (uint32_t)s_i[k][6];
+        int g[3] = {0, 0, 0};
+        const uint32_t n0 = (uint32_t)s_i[k][3];
+        g[0] = s_i[k][0] + (int)(u % n0);
+        u /= n0;
+        if constexpr (D == 3) {
+            const uint32_t n1 = (uint32_t)s_i[k][4];
+            g[1] = s_i[k][1] + (int)(u % n1);
+            g[2] = s_i[k][2] + (int)(u / n1);
+        } else {
+            g[1] = s_i[k][1] + (int)u;
+        }
+        float m[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int a = 0; a < D; ++a) m[a] = dev::cell_centre(A.lo[a], g[a], A.dx[a]);
+        int64_t blk = (int64_t)(g[1] >> 2) * A.NB[0] + (g[0] >> 2);
+        int cell = (g[0] & 3) | ((g[1] & 3) << 2);
+        if constexpr (D == 3) {
+            blk += (int64_t)(g[2] >> 2) * A.NB[0] * A.NB[1];
+            cell |= (g[2] & 3) << 4;
+        }
+        if (A.table) {
+            const uint32_t t = A.table[blk];
+            if (t == 0) continue;   // no such block at this level
+            blk = (int64_t)t - 1;
+        }
+        uint8_t *cp = A.cf + blk * CELLS + cell;
+        if (*cp) continue;   // flagged already
+        float vv[D * D];
+#pragma unroll
+        for (int j = 0; j < D * D; ++j) vv[j] = s_rec[k][j];
+        bool hit;
+        if constexpr (D == 3) hit = dev::sat_triangle(vv, m, A.h);
+        else hit = dev::sat_segment(vv, m, A.h);
+        if (hit) {
+            *cp = 1;
+            A.pmark[blk] = 1;
+        }
     }
 }
 

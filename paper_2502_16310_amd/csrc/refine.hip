@@ -29,9 +29,28 @@ using namespace kern;
 #define AGAL_GRID_STRIDE(i, n) \
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
-template <int D, bool kDedup>
-__global__ __launch_bounds__(64) void k_flag(FlagArgs<D> A) {
-    flag_wave<D, kDedup>(A, (int64_t)blockIdx.x * (D == 3 ? 1 : 4));
+template <int D, bool kDedup, int W>
+__global__ __launch_bounds__(64 * W) void k_flag(FlagArgs<D> A) {
+    flag_wave<D, kDedup, W>(A, (int64_t)blockIdx.x * (D == 3 ? 1 : 4));
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_flag_faces(FaceFlagArgs<D> A) {
+    __shared__ float s_rec[4][kFaceFlagG][dev::kRecFloats<D>];
+    __shared__ int s_i[4][kFaceFlagG][8];
+    const int w = (int)threadIdx.x / dev::kWave;
+    flag_faces_wave<D>(A, ((int64_t)blockIdx.x * 4 + w) * kFaceFlagG, s_rec[w], s_i[w]);
+}
+
+// table[block grid position] = block index + 1 for every block of a level.
+template <int D>
+__global__ void k_block_table(const uint32_t *keys, int64_t n, int level, int R0, int R1, int NB0, int NB1,
+                              uint32_t *table) {
+    AGAL_GRID_STRIDE(i, n) {
+        int c[3];
+        dev::decode_key<D>(keys[i], level, R0, R1, c);
+        table[((int64_t)c[2] * NB1 + c[1]) * NB0 + c[0]] = (uint32_t)(i + 1);
+    }
 }
 
 template <int D>
@@ -133,14 +152,42 @@ struct Scratch {
 // repeats dropped by a hash set before any record is read) shortens the waves
 // of blocks whose query box (4 dx + 2 h per axis) spans many bins; it pays for
 // clearing the set and for more LDS per wave.  Measured on MI355X: it wins
-// when the pass is bound by its longest waves (few blocks: C1 levels 0 and 1,
-// 80 -> 60 and 40 -> 27 us) and loses when the pass has blocks enough to fill
-// the GPU many times (C2 level 0, 32768 blocks: 285 -> 375 us).
+// when the pass is bound by its longest waves (few blocks: the two coarsest
+// levels over a 20,480-face sphere, 4096 and 3776 blocks, 80 -> 60 and
+// 40 -> 27 us) and loses when the pass has blocks enough to fill the GPU many
+// times (32768 blocks over a 327,680-face body: 285 -> 375 us).
 template <int D>
 bool flag_dedup(const agal_bins_t *bn, const float dx[3], float h, int64_t n_blocks, int n_cu) {
     double nbins = 1.0;
     for (int a = 0; a < D; ++a) nbins *= std::min((double)bn->B, std::floor((4.0 * dx[a] + 2.0 * h) * bn->s[a]) + 2.0);
     return nbins > 64.0 && n_blocks < 32 * (int64_t)n_cu;
+}
+
+// Waves per block of a 3D flag pass (the faces of a block split between them
+// by id).  A pass with few blocks per CU is as long as its busiest block's
+// wave, while most SIMDs idle; more waves per block shorten that wave.
+constexpr int kFlagSplitPerCu = 24;
+template <int D>
+int flag_waves_per_block(int64_t n_blocks, int n_cu) {
+    return D == 3 && n_blocks < kFlagSplitPerCu * (int64_t)n_cu ? 4 : 1;
+}
+
+// The flag pass of level l runs face-centric (one lane per (face, cell) pair
+// near the face) at level 0, and at finer levels while the dense table of the
+// level's block grid stays within kFaceFlagTableMax entries; beyond that the
+// cell-centric pass (one wave per block) runs.
+constexpr int64_t kFaceFlagTableMax = int64_t(1) << 24;
+template <int D>
+int64_t block_grid_size(const agal_forest_t *fo, int l) {
+    int64_t e = 1;
+    for (int a = 0; a < D; ++a) e *= (int64_t)fo->roots[a] << l;
+    return e;
+}
+
+template <int D, int W>
+void launch_flag(bool dedup, int64_t waves, const FlagArgs<D> &A, hipStream_t s) {
+    if (dedup) hipLaunchKernelGGL((k_flag<D, true, W>), dim3((unsigned)waves), dim3(64 * W), 0, s, A);
+    else hipLaunchKernelGGL((k_flag<D, false, W>), dim3((unsigned)waves), dim3(64 * W), 0, s, A);
 }
 
 template <int D>
@@ -173,10 +220,14 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
 
     for (int l = 0; l < fo->L; ++l) {
         Scratch pass{ctx, s, {}};
+        const bool by_face = l == 0 || block_grid_size<D>(fo, l) <= kFaceFlagTableMax;
+        const int64_t table_words = l > 0 && by_face ? block_grid_size<D>(fo, l) : 0;
         // one zeroed buffer: the look-back status words of this pass's scan of
-        // the marks, then the pass marks of every level l' <= l
+        // the marks, the pass marks of every level l' <= l, then the block
+        // table of level l (face-centric flags above level 0)
         uint8_t *pm[kMaxLevels + 1] = {};
         uint64_t *scan_status = nullptr;
+        uint32_t *table = nullptr;
         {
             int64_t ns[kMaxLevels + 1], tot = 0;
             for (int m = 0; m <= l; ++m) {
@@ -186,9 +237,10 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
             const int64_t status_bytes = 8 * (scan_flags_u8_multi_tiles(ns, l + 1) + 1);
             uint8_t *buf = nullptr;
             const int64_t words = (status_bytes + tot + 3) / 4;
-            AGAL_TRY(pass.get(&buf, (size_t)(4 * words)));
-            fill_u32(reinterpret_cast<uint32_t *>(buf), 0u, words, s);
+            AGAL_TRY(pass.get(&buf, (size_t)(4 * (words + table_words))));
+            fill_u32(reinterpret_cast<uint32_t *>(buf), 0u, words + table_words, s);
             scan_status = reinterpret_cast<uint64_t *>(buf);
+            if (table_words) table = reinterpret_cast<uint32_t *>(buf) + words;
             int64_t at = status_bytes;
             for (int m = 0; m <= l; ++m) {
                 pm[m] = buf + at;
@@ -217,10 +269,35 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
             A.pmark = pm[l];
             const int64_t waves = (Ll.n + BPW - 1) / BPW;
             ProfScope prof(ctx, "flag_sat", s);
-            if (flag_dedup<D>(bn, fo->dx[l], A.h, Ll.n, ctx->n_cu))
-                hipLaunchKernelGGL((k_flag<D, true>), dim3((unsigned)waves), dim3(64), 0, s, A);
-            else
-                hipLaunchKernelGGL((k_flag<D, false>), dim3((unsigned)waves), dim3(64), 0, s, A);
+            const bool dedup = flag_dedup<D>(bn, fo->dx[l], A.h, Ll.n, ctx->n_cu);
+            if (by_face) {
+                FaceFlagArgs<D> B{};
+                B.rec = g->rec;
+                B.F = g->F;
+                for (int a = 0; a < 3; ++a) {
+                    B.NB[a] = a < D ? fo->roots[a] << l : 1;
+                    B.lo[a] = A.lo[a];
+                    B.dx[a] = A.dx[a];
+                    B.eps[a] = A.eps[a];
+                }
+                B.table = table;
+                B.h = A.h;
+                B.cf = Ll.cf;
+                B.pmark = pm[l];
+                if (table)
+                    hipLaunchKernelGGL(k_block_table<D>, dim3(grid_for(Ll.n)), dim3(256), 0, s, Ll.keys, Ll.n, l,
+                                       fo->roots[0], fo->roots[1], B.NB[0], B.NB[1], table);
+                fill_u32(reinterpret_cast<uint32_t *>(Ll.cf), 0u, Ll.n * CELLS / 4, s);
+                const int64_t per_wg = 4 * kFaceFlagG;
+                if (g->F > 0)
+                    hipLaunchKernelGGL(k_flag_faces<D>, dim3((unsigned)((g->F + per_wg - 1) / per_wg)), dim3(256), 0,
+                                       s, B);
+            } else if constexpr (D == 3) {
+                if (flag_waves_per_block<D>(Ll.n, ctx->n_cu) == 4) launch_flag<D, 4>(dedup, waves, A, s);
+                else launch_flag<D, 1>(dedup, waves, A, s);
+            } else {
+                launch_flag<D, 1>(dedup, waves, A, s);
+            }
         }
         // (ii) balance ripple, level l down to 1
         for (int m = l; m >= 1; --m) {
