@@ -144,6 +144,16 @@ AGAL_API agal_status agal_bins_view(agal_bins b, const uint32_t **d_offsets, con
  * geometry.  Synchronises `stream` once per pass to size the next level. */
 AGAL_API agal_status agal_near_wall_refine(agal_geom g, agal_bins b, const agal_forest_desc *desc, void *stream,
                                            agal_forest *out);
+/* How the flag step of each pass runs (the flags are identical either way).
+ * Face-centric: one lane per (face, cell near the face) pair; above level 0
+ * it finds blocks through a dense scratch table over the level's block grid
+ * (roots * 2^l positions per axis, 4 bytes each).  Cell-centric: one wave per
+ * block over the bins under the block, no table.  A level whose block grid
+ * has at most max_entries positions takes the face-centric step.  Default
+ * 2^24 (a 64 MiB table at most); 0 makes every level cell-centric.  Applies
+ * to agal_near_wall_refine calls made with ctx afterwards.
+ * Errors: AGAL_EINVAL for a NULL context or a negative limit. */
+AGAL_API agal_status agal_context_set_flag_table_limit(agal_context ctx, int64_t max_entries);
 /* Level arrays in ascending key order:
  *   d_keys[n]          block keys;
  *   d_leaf[n]          1 when the block has no children;

@@ -78,6 +78,7 @@ def _load():
         "agal_link_fractions_backward": [P, P, vp, vp, vp],
         "agal_lattice_vectors": [C.c_int, C.POINTER(i32)],
         "agal_profile_enable": [P, C.c_int],
+        "agal_context_set_flag_table_limit": [P, C.c_int64],
         "agal_profile_read": [P, C.c_int, C.POINTER(C.c_char_p), C.POINTER(i64), C.POINTER(C.c_double),
                               C.POINTER(C.c_int)],
         "agal_batch_plan_create": [P, C.c_int, C.POINTER(_BodyDesc), C.POINTER(_TuneOpts), vp, PP],
@@ -231,6 +232,10 @@ def agal_lattice_vectors(lattice: int):
     buf = (C.c_int32 * (3 * lattice))()
     _check(_lib.agal_lattice_vectors(int(lattice), buf), "agal_lattice_vectors")
     return [tuple(buf[3 * i:3 * i + 3]) for i in range(lattice)]
+
+
+def agal_context_set_flag_table_limit(ctx, max_entries: int):
+    _check(_lib.agal_context_set_flag_table_limit(_h(ctx), int(max_entries)), "agal_context_set_flag_table_limit")
 
 
 def agal_profile_enable(ctx, enable: bool = True):

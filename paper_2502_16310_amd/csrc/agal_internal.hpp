@@ -96,6 +96,7 @@ struct agal_context_t {
     size_t h_counts_cap = 0;
     // kernel timing (HIP events around each launch) when enabled
     bool profiling = false;
+    int64_t flag_table_max = int64_t(1) << 24;   // agal_context_set_flag_table_limit
     std::vector<agal::ProfRecord> records;
     std::vector<hipEvent_t> event_pool;
 };

@@ -282,33 +282,27 @@ __device__ __forceinline__ void for_candidates(const dev::BinGrid &g, const int 
 // 64 at a time.  stage(has, f, r) is called by the whole wave with up to 64
 // such faces (r the lane's face record) and returns false to stop.  A face
 // that finds no free slot within kSeenProbes tries is passed on as new, so a
-// crowded set can let a repeat through; stage() must tolerate that.  With W > 1
-// waves walking the same box, wave w keeps only the ids with id % W == w, and
-// the waves synchronise only within themselves.
+// crowded set can let a repeat through; stage() must tolerate that.
 constexpr int kSeen = 1024;             // hash-set slots (power of two)
 constexpr int kSeenProbes = 16;         // slots tried before a face is let through as new
 constexpr int kUniqCap = 5 * 64;        // faces waiting for their records
 
-template <int D, int W = 1, class Stage>
+template <int D, class Stage>
 __device__ __forceinline__ void for_unique_candidates(const dev::BinGrid &g, const float *rec, const int ilo[3],
                                                       const int ihi[3], int32_t *s_seen, int32_t *s_list,
-                                                      uint32_t *s_bpre, uint32_t *s_bs0, Stage &&stage, int w = 0) {
+                                                      uint32_t *s_bpre, uint32_t *s_bs0, Stage &&stage) {
     constexpr int RF = dev::kRecFloats<D>;
-    auto sync = [] {
-        if constexpr (W == 1) __syncthreads();
-        else dev::wave_sync();
-    };
     const int lane = dev::lane_id();
     const int nx = ihi[0] - ilo[0] + 1, ny = ihi[1] - ilo[1] + 1, nz = ihi[2] - ilo[2] + 1;
     const int nbins = nx * ny * nz;
-    sync();
+    __syncthreads();
     for (int i = lane; i < kSeen; i += dev::kWave) s_seen[i] = -1;
     int nl = 0;   // wave-uniform list length
     // records of list entries 0 .. t-1, one per lane, to stage(); the rest moves to the front
     auto flush = [&](int t) -> bool {
-        sync();
+        __syncthreads();
         const int32_t f = lane < t ? s_list[lane] : -1;
-        sync();
+        __syncthreads();
         for (int i = lane; i < nl - t; i += dev::kWave) s_list[i] = s_list[t + i];   // up to 4 x 64 remain
         nl -= t;
         float r[RF];
@@ -330,13 +324,13 @@ __device__ __forceinline__ void for_unique_candidates(const dev::BinGrid &g, con
         // the non-empty bins in list order, for a binary search per list entry
         const uint64_t ne = __ballot(cnt > 0);
         const int nne = __popcll(ne);
-        sync();
+        __syncthreads();
         if (cnt > 0) {
             const int k = dev::lanes_below(ne);
             s_bpre[k] = incl - cnt;
             s_bs0[k] = s0;
         }
-        sync();
+        __syncthreads();
         for (uint32_t c0 = 0; c0 < total; c0 += 4 * dev::kWave) {
             int32_t id[4];
 #pragma unroll
@@ -351,7 +345,6 @@ __device__ __forceinline__ void for_unique_candidates(const dev::BinGrid &g, con
                         else hi = mid - 1;
                     }
                     id[q] = g.ids[s_bs0[lo] + (v - s_bpre[lo])];
-                    if (W > 1 && id[q] % W != w) id[q] = -1;
                 }
             }
 #pragma unroll
@@ -402,28 +395,15 @@ struct FlagArgs {
     uint8_t *pmark;  // n
 };
 
-// One wave: blocks first .. first + 64/4^D - 1 of A (one lane per cell).  With
-// W > 1 the W waves of a workgroup take the same blocks and split their
-// candidate faces by id (face f to wave f % W), each with its own staging and
-// queue; the cell flags are one LDS array that every wave sets and reads, so a
-// cell flagged by one wave drops out of the others' tests too.  That puts W
-// SIMDs on a block for passes with fewer blocks than the chip has room for,
-// where the time is that of the longest wave.
-template <int D, bool kDedup = false, int W = 1>
+// One wave: blocks first .. first + 64/4^D - 1 of A (one lane per cell).
+template <int D, bool kDedup = false>
 __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
     constexpr int CELLS = D == 3 ? 64 : 16;
     constexpr int BPW = 64 / CELLS;
     constexpr int NF = D * D;   // staged corner coordinates
-    auto sync = [] {
-        if constexpr (W == 1) __syncthreads();
-        else dev::wave_sync();
-    };
-    __shared__ float s_f_all[W][NF][kFlagCap];
-    __shared__ __align__(16) uint32_t s_code_all[W][kFlagCap];
-    const int lane = threadIdx.x % dev::kWave;
-    const int w = W == 1 ? 0 : (int)threadIdx.x / dev::kWave;
-    float(*s_f)[kFlagCap] = s_f_all[w];
-    uint32_t *s_code = s_code_all[w];
+    __shared__ float s_f[NF][kFlagCap];
+    __shared__ __align__(16) uint32_t s_code[kFlagCap];
+    const int lane = threadIdx.x;
     const int64_t blk = first + lane / CELLS;
     const bool valid = blk < A.n;
     const int cell = lane % CELLS;
@@ -469,20 +449,17 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
     // faces does not hold the wave while the other lanes idle.  A pair whose
     // cell is flagged meanwhile is dropped.
     constexpr int TCAP = 128;   // below 64 after a take, at most 64 added per step
-    __shared__ uint32_t s_q_all[W][TCAP];
-    __shared__ float s_m_all[W][64][3];
+    __shared__ uint32_t s_q[TCAP];
+    __shared__ float s_m[64][3];
     __shared__ int s_fl[64];
-    uint32_t *s_q = s_q_all[w];
-    float(*s_m)[3] = s_m_all[w];
 #pragma unroll
     for (int a = 0; a < 3; ++a) s_m[lane][a] = m[a];
-    if (w == 0) s_fl[lane] = flagged ? 1 : 0;
-    if constexpr (W > 1) __syncthreads();   // every wave sees the initial flags
+    s_fl[lane] = flagged ? 1 : 0;
     int nq = 0;   // wave-uniform
     auto take = [&](int t) {
-        sync();
+        __syncthreads();
         const uint32_t item = lane < t ? s_q[lane] : 0u;
-        sync();
+        __syncthreads();
         if (lane < nq - t) s_q[lane] = s_q[t + lane];
         nq -= t;
         const int l = (int)(item >> 7), j = (int)(item & 127u);
@@ -500,7 +477,7 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
     // Batches of 64 staged faces: each lane marks the faces its cube's box axes do
     // not separate from it and queues them for the full test, until flagged.
     auto test_staged = [&](int n) {
-        sync();
+        __syncthreads();
         for (int j0 = 0; j0 < n; j0 += 64) {
             flagged = s_fl[lane] != 0;
             if (__ballot(!flagged) == 0) break;
@@ -527,21 +504,19 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
                 nq += __popcll(want);
                 if (nq >= 64) {
                     take(64);
-                    sync();
+                    __syncthreads();
                     if (s_fl[lane]) nm = 0;   // flagged meanwhile: nothing more to queue
                 }
             }
         }
         if (nq > 0) take(nq);
-        sync();
+        __syncthreads();
         flagged = s_fl[lane] != 0;
     };
 
-    __shared__ int32_t s_seen_all[W][kDedup ? kSeen : 1];
-    __shared__ int32_t s_list_all[W][kDedup ? kUniqCap : 1];
-    __shared__ uint32_t s_bpre_all[W][kDedup ? 64 : 1], s_bs0_all[W][kDedup ? 64 : 1];
-    int32_t *s_seen = s_seen_all[w], *s_list = s_list_all[w];
-    uint32_t *s_bpre = s_bpre_all[w], *s_bs0 = s_bs0_all[w];
+    __shared__ int32_t s_seen[kDedup ? kSeen : 1];
+    __shared__ int32_t s_list[kDedup ? kUniqCap : 1];
+    __shared__ uint32_t s_bpre[kDedup ? 64 : 1], s_bs0[kDedup ? 64 : 1];
     bool done = __ballot(!flagged) == 0;
     for (int sb = 0; sb < BPW && !done; ++sb) {
         if (first + sb >= A.n) break;
@@ -587,13 +562,13 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
             return true;
         };
         if constexpr (kDedup) {
-            for_unique_candidates<D, W>(A.bins, A.faces.rec, ilo, ihi, s_seen, s_list, s_bpre, s_bs0, stage, w);
+            for_unique_candidates<D>(A.bins, A.faces.rec, ilo, ihi, s_seen, s_list, s_bpre, s_bs0, stage);
         } else {
             for_candidates(A.bins, ilo, ihi, [&](bool has, int32_t f, const int cur[3]) -> bool {
                 // visit each face once: in the first bin of (its bins) x (query bins)
                 float r[dev::kRecFloats<D>];
-                bool first_bin = has && (W == 1 || f % W == w);
-                if (first_bin) {
+                bool first_bin = has;
+                if (has) {
                     dev::load_rec<D>(A.faces.rec, f, r);
 #pragma unroll
                     for (int a = 0; a < D; ++a)
@@ -605,11 +580,6 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
         }
     }
     if (!done && count > 0) test_staged(count);
-    if constexpr (W > 1) {
-        __syncthreads();   // every wave's flags are in
-        flagged = s_fl[lane] != 0;
-        if (w != 0) return;
-    }
 
     if (valid) A.cf[blk * CELLS + cell] = flagged ? 1 : 0;
     // block mark: OR over the block's cells

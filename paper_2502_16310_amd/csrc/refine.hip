@@ -29,9 +29,9 @@ using namespace kern;
 #define AGAL_GRID_STRIDE(i, n) \
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
-template <int D, bool kDedup, int W>
-__global__ __launch_bounds__(64 * W) void k_flag(FlagArgs<D> A) {
-    flag_wave<D, kDedup, W>(A, (int64_t)blockIdx.x * (D == 3 ? 1 : 4));
+template <int D, bool kDedup>
+__global__ __launch_bounds__(64) void k_flag(FlagArgs<D> A) {
+    flag_wave<D, kDedup>(A, (int64_t)blockIdx.x * (D == 3 ? 1 : 4));
 }
 
 template <int D>
@@ -163,31 +163,18 @@ bool flag_dedup(const agal_bins_t *bn, const float dx[3], float h, int64_t n_blo
     return nbins > 64.0 && n_blocks < 32 * (int64_t)n_cu;
 }
 
-// Waves per block of a 3D flag pass (the faces of a block split between them
-// by id).  A pass with few blocks per CU is as long as its busiest block's
-// wave, while most SIMDs idle; more waves per block shorten that wave.
-constexpr int kFlagSplitPerCu = 24;
-template <int D>
-int flag_waves_per_block(int64_t n_blocks, int n_cu) {
-    return D == 3 && n_blocks < kFlagSplitPerCu * (int64_t)n_cu ? 4 : 1;
-}
-
 // The flag pass of level l runs face-centric (one lane per (face, cell) pair
-// near the face) at level 0, and at finer levels while the dense table of the
-// level's block grid stays within kFaceFlagTableMax entries; beyond that the
-// cell-centric pass (one wave per block) runs.
-constexpr int64_t kFaceFlagTableMax = int64_t(1) << 24;
+// near the face) while the level's block grid has at most the context's
+// flag_table_max positions (the table is needed above level 0 only), else
+// cell-centric (one wave per block).  Measured on MI355X, face-centric wins at
+// every level tried: flags 127 -> 74 us over a 20,480-face sphere (3 levels)
+// and 875 -> 272 us over a 327,680-face body (4 levels), most at the coarse
+// levels, whose few blocks each span hundreds of bins.
 template <int D>
 int64_t block_grid_size(const agal_forest_t *fo, int l) {
     int64_t e = 1;
     for (int a = 0; a < D; ++a) e *= (int64_t)fo->roots[a] << l;
     return e;
-}
-
-template <int D, int W>
-void launch_flag(bool dedup, int64_t waves, const FlagArgs<D> &A, hipStream_t s) {
-    if (dedup) hipLaunchKernelGGL((k_flag<D, true, W>), dim3((unsigned)waves), dim3(64 * W), 0, s, A);
-    else hipLaunchKernelGGL((k_flag<D, false, W>), dim3((unsigned)waves), dim3(64 * W), 0, s, A);
 }
 
 template <int D>
@@ -220,7 +207,7 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
 
     for (int l = 0; l < fo->L; ++l) {
         Scratch pass{ctx, s, {}};
-        const bool by_face = l == 0 || block_grid_size<D>(fo, l) <= kFaceFlagTableMax;
+        const bool by_face = block_grid_size<D>(fo, l) <= ctx->flag_table_max;
         const int64_t table_words = l > 0 && by_face ? block_grid_size<D>(fo, l) : 0;
         // one zeroed buffer: the look-back status words of this pass's scan of
         // the marks, the pass marks of every level l' <= l, then the block
@@ -292,11 +279,10 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
                 if (g->F > 0)
                     hipLaunchKernelGGL(k_flag_faces<D>, dim3((unsigned)((g->F + per_wg - 1) / per_wg)), dim3(256), 0,
                                        s, B);
-            } else if constexpr (D == 3) {
-                if (flag_waves_per_block<D>(Ll.n, ctx->n_cu) == 4) launch_flag<D, 4>(dedup, waves, A, s);
-                else launch_flag<D, 1>(dedup, waves, A, s);
+            } else if (dedup) {
+                hipLaunchKernelGGL((k_flag<D, true>), dim3((unsigned)waves), dim3(64), 0, s, A);
             } else {
-                launch_flag<D, 1>(dedup, waves, A, s);
+                hipLaunchKernelGGL((k_flag<D, false>), dim3((unsigned)waves), dim3(64), 0, s, A);
             }
         }
         // (ii) balance ripple, level l down to 1

@@ -439,6 +439,13 @@ void agal_context_destroy(agal_context ctx) {
     delete ctx;
 }
 
+agal_status agal_context_set_flag_table_limit(agal_context ctx, int64_t max_entries) {
+    if (!ctx) return agal::fail(AGAL_EINVAL, "agal_context_set_flag_table_limit: NULL context");
+    if (max_entries < 0) return agal::fail(AGAL_EINVAL, "agal_context_set_flag_table_limit: negative limit");
+    ctx->flag_table_max = max_entries;
+    return AGAL_OK;
+}
+
 agal_status agal_profile_enable(agal_context ctx, int enable) {
     if (!ctx) return agal::fail(AGAL_EINVAL, "agal_profile_enable: NULL context");
     ctx->profiling = enable != 0;

@@ -173,6 +173,24 @@ def test_sphere_c1_bins_flags_exact_and_sampled_q(orc):
     assert bad == 0
 
 
+@pytest.mark.parametrize("limit", [0, 4096])
+def test_cell_centric_and_mixed_flag_steps(orc, limit):
+    """The flag step one wave per block (limit 0: every level) or mixed (levels
+    whose block grid exceeds 4096 positions cell-centric, the rest face-centric):
+    the same bit-exact forest as the oracle."""
+    import paper_2502_16310_amd as agal
+    ctx = agal.Context()
+    ctx.set_flag_table_limit(limit)
+    for wl in (_small_sphere(3, 8, 3, 16, 19), geomgen.workload("C0")):
+        log(f"case {wl.name} flag table limit {limit}: roots {wl.roots[:wl.dim]} L {wl.levels}")
+        g = gpu_run(wl, with_links=False, ctx=ctx)
+        coords = orc.gather(wl.dim, wl.vertices, wl.faces)
+        ob = orc.bin_faces(wl.dim, coords, wl.lo[:wl.dim], wl.hi[:wl.dim], wl.bins)
+        of = orc.refine(wl.dim, coords, ob, wl.roots[:wl.dim], wl.levels, wl.d_spec(), wl.lo[:wl.dim],
+                        wl.hi[:wl.dim])
+        compare_forest(g, of, wl.levels)
+
+
 def test_run_twice_bitwise_equal(orc):
     wl = _small_sphere(3, 4, 2, 16, 27)
     a = gpu_run(wl)
