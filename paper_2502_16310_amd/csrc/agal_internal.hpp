@@ -97,6 +97,10 @@ struct agal_context_t {
     // kernel timing (HIP events around each launch) when enabled
     bool profiling = false;
     int64_t flag_table_max = int64_t(1) << 24;   // agal_context_set_flag_table_limit
+    // completion signals: a device arrival counter (zero between kernels) and
+    // the sequence number last handed out; the signal word is h_counts[kSyncWord]
+    uint32_t *d_done = nullptr;
+    uint32_t sync_seq = 0;
     std::vector<agal::ProfRecord> records;
     std::vector<hipEvent_t> event_pool;
 };
@@ -178,6 +182,20 @@ agal_status scan_u32(agal_context ctx, const uint32_t *in, uint32_t *out, int64_
 agal_status scan_flags_u8(agal_context ctx, const uint8_t *in, uint32_t *out, int64_t n, hipStream_t s);
 // k exclusive scans of 0/1 flags (out[i] of length n[i] + 1) in one launch; k <= kMultiScanMax.
 constexpr int kMultiScanMax = kMaxLevels + 1;
+// A kernel's completion signal (see dev::signal_host): arrival counter, the
+// device address of the mapped signal word (null: none) and the value stored.
+struct HostSignal {
+    uint32_t *done;
+    uint32_t *word;
+    uint32_t seq;
+};
+constexpr int kSyncWord = 63;   // index in the context's mapped words
+HostSignal host_signal(agal_context ctx);
+// Waits until the kernel that carries `sig` has signalled (spinning on the
+// mapped word, with the stream's status checked every so often), in place of
+// a stream synchronisation: the host learns of the totals a few microseconds
+// after they are written instead of after a runtime wake-up.
+agal_status wait_signal(agal_context ctx, hipStream_t s, const HostSignal &sig, const char *what);
 struct MultiScanArgs {
     const uint8_t *in[kMultiScanMax];
     uint32_t *out[kMultiScanMax];
@@ -186,6 +204,7 @@ struct MultiScanArgs {
     int nseg;
     const uint32_t *extra;   // one more device word to report (or null: 0)
     uint32_t *host_total;    // mapped host memory: k totals, then *extra
+    HostSignal sig;
 };
 // totals[0..k-1] = sum of each array, totals[k] = *extra; synchronises the stream.  status_zeroed: null, or
 // scan_flags_u8_multi_tiles(n, k) + 1 zeroed 64-bit words the caller provides.

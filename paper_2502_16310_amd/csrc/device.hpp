@@ -214,6 +214,27 @@ __device__ __forceinline__ bool sat_segment(const float v[4], const float m[2], 
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// Completion signal to the host through mapped host memory, called by every
+// thread of every block at the end of a kernel: the last block to arrive
+// (counted in *done, a device word that is zero before the kernel and is left
+// zero after it) stores seq into *word.  Each block's earlier writes, mapped
+// host memory included, are ordered before its arrival by a system-scope
+// fence, so a host that reads seq from *word sees all of them.  word == null:
+// no signal.
+__device__ __forceinline__ void signal_host(uint32_t *done, uint32_t *word, uint32_t seq) {
+    if (!word) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence_system();
+        const uint32_t blocks = gridDim.x * gridDim.y * gridDim.z;
+        if (__hip_atomic_fetch_add(done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_SYSTEM) == blocks - 1u) {
+            __threadfence_system();
+            __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(word, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+}
+
 // Orders the LDS accesses of the lanes of one wave before and after it (data
 // passed between lanes of a wave through LDS).
 __device__ __forceinline__ void wave_sync() {

@@ -16,7 +16,7 @@ namespace agal {
 // zeros and the call fails).
 template <int D>
 __global__ void k_import(const float *verts, int64_t Nv, const int32_t *faces, int64_t F, float *coords, float *aabb,
-                         float *rec, int32_t *fidx, uint32_t *err) {
+                         float *rec, int32_t *fidx, uint32_t *err, HostSignal sig) {
     uint32_t bad = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -27,6 +27,7 @@ __global__ void k_import(const float *verts, int64_t Nv, const int32_t *faces, i
     // the same value need no atomics
     if (bad & 1u) err[0] = 1u;
     if (bad & 2u) err[1] = 1u;
+    dev::signal_host(sig.done, sig.word, sig.seq);
 }
 
 static unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 8192) {
@@ -74,19 +75,20 @@ agal_status agal_import_faces(agal_context ctx, int dim, const float *d_vertices
     uint32_t *err = ctx->d_counts;
     ctx->h_counts[0] = 0u;
     ctx->h_counts[1] = 0u;
+    const HostSignal sig = host_signal(ctx);
     {
         ProfScope prof(ctx, "import", s);
         const unsigned grid = grid_for(std::max(n_vertices * dim, n_faces));
         if (dim == 3)
             hipLaunchKernelGGL(k_import<3>, dim3(grid), dim3(256), 0, s, d_vertices, n_vertices, d_faces, n_faces,
-                               g->coords, g->aabb, g->rec, g->fidx, err);
+                               g->coords, g->aabb, g->rec, g->fidx, err, sig);
         else
             hipLaunchKernelGGL(k_import<2>, dim3(grid), dim3(256), 0, s, d_vertices, n_vertices, d_faces, n_faces,
-                               g->coords, g->aabb, g->rec, g->fidx, err);
+                               g->coords, g->aabb, g->rec, g->fidx, err, sig);
     }
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    st = e != hipSuccess ? fail(AGAL_EHIP, "agal_import_faces: %s", hipGetErrorString(e)) : AGAL_OK;
+    st = e != hipSuccess ? fail(AGAL_EHIP, "agal_import_faces: %s", hipGetErrorString(e))
+                         : wait_signal(ctx, s, sig, "agal_import_faces");
     const uint32_t herr = (ctx->h_counts[0] ? 1u : 0u) | (ctx->h_counts[1] ? 2u : 0u);
     if (st == AGAL_OK && (herr & 1u)) st = fail(AGAL_EINVAL, "agal_import_faces: NaN or Inf vertex coordinate");
     if (st == AGAL_OK && (herr & 2u)) st = fail(AGAL_EINVAL, "agal_import_faces: face index outside [0, n_vertices)");

@@ -42,14 +42,18 @@ __global__ __launch_bounds__(256) void k_flag_faces(FaceFlagArgs<D> A) {
     flag_faces_wave<D>(A, ((int64_t)blockIdx.x * 4 + w) * kFaceFlagG, s_rec[w], s_i[w]);
 }
 
-// table[block grid position] = block index + 1 for every block of a level.
+// table[block grid position] = block index + 1 for every block of a level,
+// and the block's cell flags zeroed (4^D bytes, 16-byte stores).
 template <int D>
 __global__ void k_block_table(const uint32_t *keys, int64_t n, int level, int R0, int R1, int NB0, int NB1,
-                              uint32_t *table) {
+                              uint32_t *table, uint4 *cf) {
+    constexpr int V = (D == 3 ? 64 : 16) / 16;
     AGAL_GRID_STRIDE(i, n) {
         int c[3];
         dev::decode_key<D>(keys[i], level, R0, R1, c);
         table[((int64_t)c[2] * NB1 + c[1]) * NB0 + c[0]] = (uint32_t)(i + 1);
+#pragma unroll
+        for (int j = 0; j < V; ++j) cf[i * V + j] = make_uint4(0u, 0u, 0u, 0u);
     }
 }
 
@@ -62,11 +66,15 @@ __global__ void k_ripple(const uint32_t *keys_m, int64_t n_m, const uint8_t *pm_
 
 // Level 0 (every root, key = x-fastest linear index, all leaves, no marks) and
 // the error word, in one launch.
-__global__ void k_init_roots(uint32_t *keys, uint8_t *leaf, uint8_t *mark, int64_t n, uint32_t *err) {
+// (cf: the roots' cell flags to zero, cf_vec 16-byte words per root, or null)
+__global__ void k_init_roots(uint32_t *keys, uint8_t *leaf, uint8_t *mark, int64_t n, uint32_t *err, uint4 *cf,
+                             int cf_vec) {
     AGAL_GRID_STRIDE(i, n) {
         keys[i] = (uint32_t)i;
         leaf[i] = 1;
         mark[i] = 0;
+        if (cf)
+            for (int j = 0; j < cf_vec; ++j) cf[i * cf_vec + j] = make_uint4(0u, 0u, 0u, 0u);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *err = 0u;
 }
@@ -193,7 +201,10 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
     AGAL_TRY(dev_alloc(mem, &L0.keys, (size_t)L0.n, s));
     AGAL_TRY(dev_alloc(mem, &L0.leaf, (size_t)L0.n, s));
     AGAL_TRY(dev_alloc(mem, &L0.mark, (size_t)L0.n, s));
-    hipLaunchKernelGGL(k_init_roots, dim3(grid_for(L0.n)), dim3(256), 0, s, L0.keys, L0.leaf, L0.mark, L0.n, err);
+    // the level-0 cell flags exist when a pass runs; zeroed here for the face-centric step
+    if (fo->L > 0) AGAL_TRY(dev_alloc(mem, &L0.cf, (size_t)L0.n * CELLS, s));
+    hipLaunchKernelGGL(k_init_roots, dim3(grid_for(L0.n)), dim3(256), 0, s, L0.keys, L0.leaf, L0.mark, L0.n, err,
+                       reinterpret_cast<uint4 *>(L0.cf), CELLS / 16);
 
     dev::BinGrid bins{};
     bins.off = bn->off;
@@ -236,7 +247,7 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
         }
         // (i) flag every cell of every level-l block
         agal::Level &Ll = fo->lev[l];
-        AGAL_TRY(dev_alloc(mem, &Ll.cf, (size_t)Ll.n * CELLS, s));
+        if (l > 0) AGAL_TRY(dev_alloc(mem, &Ll.cf, (size_t)Ll.n * CELLS, s));
         if (Ll.n > 0) {
             FlagArgs<D> A{};
             A.faces = faces;
@@ -271,10 +282,11 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
                 B.h = A.h;
                 B.cf = Ll.cf;
                 B.pmark = pm[l];
+                // the cell flags start at zero: level 0's from k_init_roots, the others' here
                 if (table)
                     hipLaunchKernelGGL(k_block_table<D>, dim3(grid_for(Ll.n)), dim3(256), 0, s, Ll.keys, Ll.n, l,
-                                       fo->roots[0], fo->roots[1], B.NB[0], B.NB[1], table);
-                fill_u32(reinterpret_cast<uint32_t *>(Ll.cf), 0u, Ll.n * CELLS / 4, s);
+                                       fo->roots[0], fo->roots[1], B.NB[0], B.NB[1], table,
+                                       reinterpret_cast<uint4 *>(Ll.cf));
                 const int64_t per_wg = 4 * kFaceFlagG;
                 if (g->F > 0)
                     hipLaunchKernelGGL(k_flag_faces<D>, dim3((unsigned)((g->F + per_wg - 1) / per_wg)), dim3(256), 0,
