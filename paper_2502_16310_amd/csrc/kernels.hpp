@@ -600,9 +600,12 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
 // the chip, where the cell-centric pass is as long as its busiest block's wave
 // (a coarse block's query box spans hundreds of bins).  Cells of blocks that
 // do not exist at the level are skipped: a dense table over the level's block
-// grid holds each block's index + 1 (0: absent); at level 0 every block exists
-// and the index is the linear one.  Cell flags and block marks must start at
-// zero; only ones are stored, so faces that meet the same cell race harmlessly.
+// grid holds each block's index; an entry counts only when it is below n and
+// the level's key at that index is the key of the grid position, so the table
+// is never cleared and stale entries read as absent.  At level 0 every block
+// exists and the index is the linear one.  Cell flags and block marks must
+// start at zero; only ones are stored, so faces that meet the same cell race
+// harmlessly.
 constexpr int kFaceFlagG = 16;   // faces per wave
 
 template <int D>
@@ -611,6 +614,10 @@ struct FaceFlagArgs {
     int64_t F;
     int NB[3];                // blocks per axis at this level (roots << level)
     const uint32_t *table;    // NB0 NB1 NB2 entries, x fastest; null at level 0
+    const uint32_t *keys;     // the level's keys (n), to validate table entries
+    int64_t n;
+    int level;
+    int R[2];                 // roots along x and y (key encoding)
     float lo[3];
     float dx[3];              // cell size at this level
     float eps[3];
@@ -693,8 +700,10 @@ __device__ __forceinline__ void flag_faces_wave(const FaceFlagArgs<D> &A, int64_
         }
         if (A.table) {
             const uint32_t t = A.table[blk];
-            if (t == 0) continue;   // no such block at this level
-            blk = (int64_t)t - 1;
+            const int bc[3] = {g[0] >> 2, g[1] >> 2, D == 3 ? g[2] >> 2 : 0};
+            if ((int64_t)t >= A.n || A.keys[t] != dev::encode_key<D>(bc, A.level, A.R[0], A.R[1]))
+                continue;   // no such block at this level
+            blk = t;
         }
         uint8_t *cp = A.cf + blk * CELLS + cell;
         if (*cp) continue;   // flagged already

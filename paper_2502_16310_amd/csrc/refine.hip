@@ -42,19 +42,21 @@ __global__ __launch_bounds__(256) void k_flag_faces(FaceFlagArgs<D> A) {
     flag_faces_wave<D>(A, ((int64_t)blockIdx.x * 4 + w) * kFaceFlagG, s_rec[w], s_i[w]);
 }
 
-// table[block grid position] = block index + 1 for every block of a level,
-// and the block's cell flags zeroed (4^D bytes, 16-byte stores).
+// table[block grid position] = block index for every block of a level, the
+// block's cell flags zeroed (4^D bytes, 16-byte stores), and the pass's zeroed
+// scratch (zero[0 .. nzero)) cleared, in one launch.
 template <int D>
 __global__ void k_block_table(const uint32_t *keys, int64_t n, int level, int R0, int R1, int NB0, int NB1,
-                              uint32_t *table, uint4 *cf) {
+                              uint32_t *table, uint4 *cf, uint32_t *zero, int64_t nzero) {
     constexpr int V = (D == 3 ? 64 : 16) / 16;
     AGAL_GRID_STRIDE(i, n) {
         int c[3];
         dev::decode_key<D>(keys[i], level, R0, R1, c);
-        table[((int64_t)c[2] * NB1 + c[1]) * NB0 + c[0]] = (uint32_t)(i + 1);
+        table[((int64_t)c[2] * NB1 + c[1]) * NB0 + c[0]] = (uint32_t)i;
 #pragma unroll
         for (int j = 0; j < V; ++j) cf[i * V + j] = make_uint4(0u, 0u, 0u, 0u);
     }
+    AGAL_GRID_STRIDE(i, nzero) zero[i] = 0u;
 }
 
 template <int D>
@@ -66,9 +68,10 @@ __global__ void k_ripple(const uint32_t *keys_m, int64_t n_m, const uint8_t *pm_
 
 // Level 0 (every root, key = x-fastest linear index, all leaves, no marks) and
 // the error word, in one launch.
-// (cf: the roots' cell flags to zero, cf_vec 16-byte words per root, or null)
+// (cf: the roots' cell flags to zero, cf_vec 16-byte words per root, or null;
+// zero[0 .. nzero): the first pass's zeroed scratch)
 __global__ void k_init_roots(uint32_t *keys, uint8_t *leaf, uint8_t *mark, int64_t n, uint32_t *err, uint4 *cf,
-                             int cf_vec) {
+                             int cf_vec, uint32_t *zero, int64_t nzero) {
     AGAL_GRID_STRIDE(i, n) {
         keys[i] = (uint32_t)i;
         leaf[i] = 1;
@@ -76,6 +79,7 @@ __global__ void k_init_roots(uint32_t *keys, uint8_t *leaf, uint8_t *mark, int64
         if (cf)
             for (int j = 0; j < cf_vec; ++j) cf[i * cf_vec + j] = make_uint4(0u, 0u, 0u, 0u);
     }
+    AGAL_GRID_STRIDE(i, nzero) zero[i] = 0u;
     if (blockIdx.x == 0 && threadIdx.x == 0) *err = 0u;
 }
 
@@ -201,10 +205,32 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
     AGAL_TRY(dev_alloc(mem, &L0.keys, (size_t)L0.n, s));
     AGAL_TRY(dev_alloc(mem, &L0.leaf, (size_t)L0.n, s));
     AGAL_TRY(dev_alloc(mem, &L0.mark, (size_t)L0.n, s));
-    // the level-0 cell flags exist when a pass runs; zeroed here for the face-centric step
-    if (fo->L > 0) AGAL_TRY(dev_alloc(mem, &L0.cf, (size_t)L0.n * CELLS, s));
+    // Zeroed scratch of pass l: the look-back status words of the pass's scan of
+    // the marks, then the pass marks of every level l' <= l.
+    struct PassBuf {
+        uint8_t *buf = nullptr;
+        int64_t words = 0, status_bytes = 0;
+    };
+    auto pass_buf = [&](Scratch &sc, int l, PassBuf &pb) -> agal_status {
+        int64_t ns[kMaxLevels + 1], tot = 0;
+        for (int m = 0; m <= l; ++m) {
+            ns[m] = fo->lev[m].n;
+            tot += ns[m];
+        }
+        pb.status_bytes = 8 * (scan_flags_u8_multi_tiles(ns, l + 1) + 1);
+        pb.words = (pb.status_bytes + tot + 3) / 4;
+        return sc.get(&pb.buf, (size_t)(4 * pb.words));
+    };
+    // the level-0 cell flags (for the face-centric step) and the first pass's
+    // scratch are zeroed by the root-init launch
+    PassBuf pb0;
+    if (fo->L > 0) {
+        AGAL_TRY(dev_alloc(mem, &L0.cf, (size_t)L0.n * CELLS, s));
+        AGAL_TRY(pass_buf(keep, 0, pb0));
+    }
     hipLaunchKernelGGL(k_init_roots, dim3(grid_for(L0.n)), dim3(256), 0, s, L0.keys, L0.leaf, L0.mark, L0.n, err,
-                       reinterpret_cast<uint4 *>(L0.cf), CELLS / 16);
+                       reinterpret_cast<uint4 *>(L0.cf), CELLS / 16, reinterpret_cast<uint32_t *>(pb0.buf),
+                       pb0.words);
 
     dev::BinGrid bins{};
     bins.off = bn->off;
@@ -218,35 +244,28 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
 
     for (int l = 0; l < fo->L; ++l) {
         Scratch pass{ctx, s, {}};
+        agal::Level &Ll = fo->lev[l];
         const bool by_face = block_grid_size<D>(fo, l) <= ctx->flag_table_max;
-        const int64_t table_words = l > 0 && by_face ? block_grid_size<D>(fo, l) : 0;
-        // one zeroed buffer: the look-back status words of this pass's scan of
-        // the marks, the pass marks of every level l' <= l, then the block
-        // table of level l (face-centric flags above level 0)
-        uint8_t *pm[kMaxLevels + 1] = {};
-        uint64_t *scan_status = nullptr;
+        // the block table of level l (face-centric step above level 0): never
+        // cleared, its entries are checked against the level's keys
         uint32_t *table = nullptr;
+        if (l > 0 && by_face && Ll.n > 0) AGAL_TRY(pass.get(&table, (size_t)block_grid_size<D>(fo, l)));
+        PassBuf pb = pb0;
+        if (l > 0) {
+            AGAL_TRY(pass_buf(pass, l, pb));
+            // zeroed by the table launch when there is one
+            if (!table) fill_u32(reinterpret_cast<uint32_t *>(pb.buf), 0u, pb.words, s);
+        }
+        uint8_t *pm[kMaxLevels + 1] = {};
+        uint64_t *scan_status = reinterpret_cast<uint64_t *>(pb.buf);
         {
-            int64_t ns[kMaxLevels + 1], tot = 0;
+            int64_t at = pb.status_bytes;
             for (int m = 0; m <= l; ++m) {
-                ns[m] = fo->lev[m].n;
-                tot += ns[m];
-            }
-            const int64_t status_bytes = 8 * (scan_flags_u8_multi_tiles(ns, l + 1) + 1);
-            uint8_t *buf = nullptr;
-            const int64_t words = (status_bytes + tot + 3) / 4;
-            AGAL_TRY(pass.get(&buf, (size_t)(4 * (words + table_words))));
-            fill_u32(reinterpret_cast<uint32_t *>(buf), 0u, words + table_words, s);
-            scan_status = reinterpret_cast<uint64_t *>(buf);
-            if (table_words) table = reinterpret_cast<uint32_t *>(buf) + words;
-            int64_t at = status_bytes;
-            for (int m = 0; m <= l; ++m) {
-                pm[m] = buf + at;
+                pm[m] = pb.buf + at;
                 at += fo->lev[m].n;
             }
         }
         // (i) flag every cell of every level-l block
-        agal::Level &Ll = fo->lev[l];
         if (l > 0) AGAL_TRY(dev_alloc(mem, &Ll.cf, (size_t)Ll.n * CELLS, s));
         if (Ll.n > 0) {
             FlagArgs<D> A{};
@@ -279,6 +298,11 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
                     B.eps[a] = A.eps[a];
                 }
                 B.table = table;
+                B.keys = Ll.keys;
+                B.n = Ll.n;
+                B.level = l;
+                B.R[0] = fo->roots[0];
+                B.R[1] = fo->roots[1];
                 B.h = A.h;
                 B.cf = Ll.cf;
                 B.pmark = pm[l];
@@ -286,7 +310,8 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
                 if (table)
                     hipLaunchKernelGGL(k_block_table<D>, dim3(grid_for(Ll.n)), dim3(256), 0, s, Ll.keys, Ll.n, l,
                                        fo->roots[0], fo->roots[1], B.NB[0], B.NB[1], table,
-                                       reinterpret_cast<uint4 *>(Ll.cf));
+                                       reinterpret_cast<uint4 *>(Ll.cf), reinterpret_cast<uint32_t *>(pb.buf),
+                                       pb.words);
                 const int64_t per_wg = 4 * kFaceFlagG;
                 if (g->F > 0)
                     hipLaunchKernelGGL(k_flag_faces<D>, dim3((unsigned)((g->F + per_wg - 1) / per_wg)), dim3(256), 0,
