@@ -1379,9 +1379,11 @@ __device__ __forceinline__ void link_scalars(const float o[3], const LinkFace<D>
 // segmented sum over runs of equal face ids leaves one lane per run, which
 // adds the run's D scalars to the face's entry of the workgroup's LDS hash
 // table (neighbouring nodes in key order hit few distinct faces).  At the end
-// each face's sums, times its normal, go to its vertices with one float atomic
-// per coordinate.  One workgroup of kAdjThreads threads: nodes node0 ..
-// node0 + kAdjThreads - 1 of A.
+// each face's sums, times its normal, are added per vertex in a second LDS hash
+// table (a tile's faces share most of their vertices), and each vertex's sum
+// goes out with one float atomic per coordinate: about a sixth of the global
+// atomics of sending every face's share straight to its vertices.  One
+// workgroup of kAdjThreads threads: nodes node0 .. node0 + kAdjThreads - 1 of A.
 template <int D, int Q>
 __device__ __forceinline__ void adjoint_tile(const AdjArgs<D, Q> &A, int64_t node0) {
     constexpr int CELLS = D == 3 ? 64 : 16;
@@ -1391,8 +1393,15 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs<D, Q> &A, int64_t nod
     __shared__ float s_acc[kAdjHash][D];
     __shared__ float s_D[Q][4];   // c_i * dx per axis, then its length
     __shared__ float s_o[kAdjThreads][3];
-    __shared__ uint32_t s_meta[kAdjWaves][QCAP];   // tile-local node * 32 + direction
-    __shared__ int32_t s_qf[kAdjWaves][QCAP];
+    // the link queues (tile-local node * 32 + direction, face), reused at the
+    // end for the vertex table
+    __shared__ uint32_t s_qraw[2 * kAdjWaves * QCAP];
+    uint32_t(*s_meta)[QCAP] = reinterpret_cast<uint32_t(*)[QCAP]>(s_qraw);
+    int32_t(*s_qf)[QCAP] = reinterpret_cast<int32_t(*)[QCAP]>(s_qraw + kAdjWaves * QCAP);
+    constexpr int kVHash = 512;   // vertex accumulators (power of two)
+    static_assert(kVHash * (1 + D) <= 2 * kAdjWaves * QCAP, "vertex table fits in the queues");
+    int32_t *v_key = reinterpret_cast<int32_t *>(s_qraw);
+    float(*v_acc)[D] = reinterpret_cast<float(*)[D]>(s_qraw + kVHash);
     const int tid = threadIdx.x;
     const int lane = dev::lane_id();
     const int wv = __builtin_amdgcn_readfirstlane(tid / dev::kWave);
@@ -1541,6 +1550,13 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs<D, Q> &A, int64_t nod
     if (qn > 0) take(qn);
     __syncthreads();
 
+    // the queues are free: vertex table
+    for (int i = tid; i < kVHash; i += kAdjThreads) {
+        v_key[i] = -1;
+#pragma unroll
+        for (int a = 0; a < D; ++a) v_acc[i][a] = 0.0f;
+    }
+    __syncthreads();
     for (int sl = tid; sl < kAdjHash; sl += kAdjThreads) {
         const int32_t f = s_key[sl];
         if (f < 0) continue;
@@ -1549,11 +1565,31 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs<D, Q> &A, int64_t nod
         face_normal<D>(v, n);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            const int64_t vk = A.fidx[(int64_t)f * D + k];
+            const int32_t vk = A.fidx[(int64_t)f * D + k];
             const float sk = s_acc[sl][k];
+            uint32_t h = ((uint32_t)vk * 2654435761u) >> 23;   // 9 bits: kVHash slots
+            bool placed = false;
+            for (int probe = 0; probe < 32; ++probe) {
+                const int32_t prev = atomicCAS(&v_key[h], -1, vk);
+                if (prev == -1 || prev == vk) {
 #pragma unroll
-            for (int a = 0; a < D; ++a) unsafeAtomicAdd(&A.grad[vk * D + a], sk * n[a]);
+                    for (int a = 0; a < D; ++a) atomicAdd(&v_acc[h][a], sk * n[a]);
+                    placed = true;
+                    break;
+                }
+                h = (h + 1) & (kVHash - 1);
+            }
+            if (!placed)
+#pragma unroll
+                for (int a = 0; a < D; ++a) unsafeAtomicAdd(&A.grad[(int64_t)vk * D + a], sk * n[a]);
         }
+    }
+    __syncthreads();
+    for (int i = tid; i < kVHash; i += kAdjThreads) {
+        const int32_t vk = v_key[i];
+        if (vk < 0) continue;
+#pragma unroll
+        for (int a = 0; a < D; ++a) unsafeAtomicAdd(&A.grad[(int64_t)vk * D + a], v_acc[i][a]);
     }
     __syncthreads();
 }
