@@ -55,6 +55,7 @@ struct BodyDev {
     uint8_t *leaf[kLv][2], *mark[kLv][2], *cf[kLv][2];
     int64_t cap[kLv];
     uint8_t *pm[kLv];
+    uint32_t *ftable[kLv];   // block table of level p for the face-centric flag step (null: none, or level 0)
     uint32_t *pos[kLv];
     uint32_t *mk[kLv];
     uint64_t *skey;
@@ -367,6 +368,60 @@ __global__ __launch_bounds__(64) void k_b_flag(const BodyDev *bodies, int nb, in
     }
 }
 
+// Face-centric flag step of pass p (as in the single-body pass): first every
+// level-p block's cell flags are zeroed and its table entry written (bodies
+// with a table), then each workgroup takes 4 x 16 faces of one body.
+template <int D>
+__global__ void k_b_ftable(const BodyDev *bodies, int nb, int p, const uint32_t *cnt) {
+    constexpr int V = (D == 3 ? 64 : 16) / 16;
+    __shared__ uint32_t s_pre[kMaxBodies + 1];
+    const uint32_t total = lds_prefix(nb, [&](int b) { return bodies[b].L > p ? cnt[b * kLv + p] : 0u; }, s_pre);
+    AGAL_THREAD_ITEMS(it, total) {
+        const int b = find_seg(s_pre, nb, it);
+        const BodyDev &B = bodies[b];
+        const uint32_t i = it - s_pre[b];
+        uint4 *cf = reinterpret_cast<uint4 *>(B.cf[p][0]);
+#pragma unroll
+        for (int j = 0; j < V; ++j) cf[(int64_t)i * V + j] = make_uint4(0u, 0u, 0u, 0u);
+        if (B.ftable[p]) {
+            int c[3];
+            dev::decode_key<D>(B.keys[p][0][i], p, B.R[0], B.R[1], c);
+            B.ftable[p][((int64_t)c[2] * (B.R[1] << p) + c[1]) * (B.R[0] << p) + c[0]] = i;
+        }
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_b_flag_faces(const BodyDev *bodies, int nb, int p, const uint32_t *cnt,
+                                                      const uint32_t *wg_pre) {
+    __shared__ float s_rec[4][kFaceFlagG][dev::kRecFloats<D>];
+    __shared__ int s_i[4][kFaceFlagG][8];
+    const uint32_t it = blockIdx.x;
+    const int b = body_of_wg(wg_pre, nb, it);
+    const BodyDev &B = bodies[b];
+    if (B.L <= p || cnt[b * kLv + p] == 0) return;
+    const int w = (int)threadIdx.x / dev::kWave;
+    FaceFlagArgs<D> A{};
+    A.rec = B.rec;
+    A.F = B.F;
+    for (int a = 0; a < 3; ++a) {
+        A.NB[a] = a < D ? B.R[a] << p : 1;
+        A.lo[a] = B.lo[a];
+        A.dx[a] = B.dx[p][a];
+        A.eps[a] = B.eps[a];
+    }
+    A.table = p > 0 ? B.ftable[p] : nullptr;
+    A.keys = B.keys[p][0];
+    A.n = cnt[b * kLv + p];
+    A.level = p;
+    A.R[0] = B.R[0];
+    A.R[1] = B.R[1];
+    A.h = B.d[p];
+    A.cf = B.cf[p][0];
+    A.pmark = B.pm[p];
+    flag_faces_wave<D>(A, ((int64_t)(it - wg_pre[b]) * 4 + w) * kFaceFlagG, s_rec[w], s_i[w]);
+}
+
 template <int D>
 __global__ void k_b_ripple(const BodyDev *bodies, int nb, int p, int m, const uint32_t *cnt, Ctl *ctl) {
     constexpr int NNB = D == 3 ? 26 : 8;
@@ -638,8 +693,10 @@ struct agal_batch_t {
     bool with_adjoint = false;
     unsigned flag_grid[agal::kMaxLevels] = {};   // workgroups of the flag kernel per pass (from capacities)
     bool flag_dedup[agal::kMaxLevels] = {};      // the flag pass takes the deduplicating walker
+    bool flag_faces[agal::kMaxLevels] = {};      // the flag pass is face-centric (every body's table fits)
+    unsigned fflag_grid = 0;                     // workgroups of the face-centric flag kernel (64 faces each)
     unsigned links_grid[28] = {};                // workgroups of the q kernel per lattice
-    uint32_t *d_wg_pre = nullptr;   // per flag pass, then per lattice (9, 19, 27): nb + 1 workgroup offsets
+    uint32_t *d_wg_pre = nullptr;   // per flag pass, per lattice (9, 19, 27), then per face group: nb + 1 offsets
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<uint32_t> h_cnt, h_nodes;
@@ -781,7 +838,11 @@ static agal_status capture(agal_batch bt) {
     hipLaunchKernelGGL(k_b_canon_big<D>, dim3(std::min<unsigned>(G, 256)), dim3(1024), 0, s, B, nb, bt->d_bin_off,
                        bt->d_ids, bt->d_big, bt->d_ctl);
     for (int p = 0; p < bt->Lmax; ++p) {
-        if (bt->flag_dedup[p])
+        if (bt->flag_faces[p]) {
+            hipLaunchKernelGGL(k_b_ftable<D>, dim3(G), dim3(256), 0, s, B, nb, p, bt->d_cnt);
+            hipLaunchKernelGGL(k_b_flag_faces<D>, dim3(bt->fflag_grid), dim3(256), 0, s, B, nb, p, bt->d_cnt,
+                               bt->d_wg_pre + (size_t)(kLv + 3) * (nb + 1));
+        } else if (bt->flag_dedup[p])
             hipLaunchKernelGGL((k_b_flag<D, true>), dim3(bt->flag_grid[p]), dim3(64), 0, s, B, nb, p, bt->d_cnt,
                                bt->d_wg_pre + (size_t)p * (nb + 1));
         else
@@ -984,7 +1045,7 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
     bt->nb_total = bin_base;
     bt->cap_ids = cap_ids;
     // workgroup offsets per body of the one-block-per-workgroup kernels (flag per pass, q per lattice)
-    std::vector<uint32_t> wg_pre((size_t)(kLv + 3) * (bt->nb + 1), 0u);
+    std::vector<uint32_t> wg_pre((size_t)(kLv + 4) * (bt->nb + 1), 0u);
     for (int b = 0; b < bt->nb; ++b) {
         const BodyDev &X = bt->bodies[b];
         for (int p = 0; p < kLv; ++p) {
@@ -1021,6 +1082,33 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
     }
     for (int k = 0; k < 3; ++k)
         wg_pre[(size_t)(kLv + k) * (bt->nb + 1) + bt->nb] = bt->links_grid[k == 0 ? 9 : (k == 1 ? 19 : 27)];
+    // face-centric flag step: 64 faces per workgroup, body by body; a pass takes it when every body refining
+    // in it has a block grid within the context's table limit (level 0 needs no table); tables are never
+    // cleared (entries are checked against the level's keys)
+    for (int b = 0; b < bt->nb; ++b) {
+        wg_pre[(size_t)(kLv + 3) * (bt->nb + 1) + b] = bt->fflag_grid;
+        bt->fflag_grid += (unsigned)((bt->bodies[b].F + 63) / 64);
+    }
+    wg_pre[(size_t)(kLv + 3) * (bt->nb + 1) + bt->nb] = bt->fflag_grid;
+    for (int p = 0; p < agal::kMaxLevels; ++p) {
+        bool ok = p < bt->Lmax;
+        for (int b = 0; b < bt->nb && ok; ++b) {
+            const BodyDev &X = bt->bodies[b];
+            if (X.L <= p) continue;
+            int64_t e = 1;
+            for (int a = 0; a < D; ++a) e *= (int64_t)X.R[a] << p;
+            ok = e <= bt->ctx->flag_table_max;
+        }
+        bt->flag_faces[p] = ok;
+        if (!ok || p == 0) continue;
+        for (int b = 0; b < bt->nb; ++b) {
+            BodyDev &X = bt->bodies[b];
+            if (X.L <= p) continue;
+            int64_t e = 1;
+            for (int a = 0; a < D; ++a) e *= (int64_t)X.R[a] << p;
+            AGAL_TRY(own(bt, &X.ftable[p], (size_t)e));
+        }
+    }
     AGAL_TRY(own(bt, &bt->d_wg_pre, wg_pre.size()));
     AGAL_TRY_HIP(hipMemcpyAsync(bt->d_wg_pre, wg_pre.data(), wg_pre.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
                                 bt->cap_stream));

@@ -627,7 +627,11 @@ struct FaceFlagArgs {
 };
 
 // One wave: faces face0 .. face0 + kFaceFlagG - 1.  The (face, cell) pairs of
-// its faces are listed in face order and taken 64 at a time, one per lane.
+// its faces are listed in face order and taken 64 at a time, one per lane.  A
+// face with a non-finite coordinate has no pairs (its input is rejected
+// anyway; the batched form reports it after the run).  Pair counts are 64-bit:
+// a face much larger than the level's cells can have more than 2^32 / 16
+// pairs; index arithmetic stays 32-bit while the wave's total fits.
 template <int D>
 __device__ __forceinline__ void flag_faces_wave(const FaceFlagArgs<D> &A, int64_t face0,
                                                 float (*s_rec)[dev::kRecFloats<D>], int (*s_i)[8]) {
@@ -636,7 +640,7 @@ __device__ __forceinline__ void flag_faces_wave(const FaceFlagArgs<D> &A, int64_
     constexpr int G = kFaceFlagG;
     static_assert(G == 16, "face search below takes 4 steps");
     const int lane = dev::lane_id();
-    uint32_t cnt = 0;
+    uint64_t cnt = 0;
     if (lane < G) {
         const int64_t f = face0 + lane;
         int ilo[3] = {0, 0, 0}, n[3] = {0, 1, 1};
@@ -645,19 +649,22 @@ __device__ __forceinline__ void flag_faces_wave(const FaceFlagArgs<D> &A, int64_
             dev::load_rec<D>(A.rec, f, r);
 #pragma unroll
             for (int k = 0; k < RF; ++k) s_rec[lane][k] = r[k];
-            cnt = 1;
+            bool finite = true;
+#pragma unroll
+            for (int k = 0; k < D * D + 2 * D; ++k) finite = finite && isfinite(r[k]);
+            cnt = finite ? 1u : 0u;
 #pragma unroll
             for (int a = 0; a < D; ++a) {
                 // cells i with centre lo + (i + 1/2) dx in [min - h - eps, max + h + eps]
                 const int nc = 4 * A.NB[a];
                 const double lo = A.lo[a], dx = A.dx[a], reach = (double)A.h + (double)A.eps[a];
-                const double xl = fmax(((double)r[D * D + a] - reach - lo) / dx - 0.5, -1.0);
-                const double xh = fmin(((double)r[D * D + D + a] + reach - lo) / dx - 0.5, (double)nc);
+                const double xl = fmin(fmax(((double)r[D * D + a] - reach - lo) / dx - 0.5, -1.0), (double)nc);
+                const double xh = fmax(fmin(((double)r[D * D + D + a] + reach - lo) / dx - 0.5, (double)nc), -1.0);
                 const int i0 = max(0, (int)ceil(xl));
                 const int i1 = min(nc - 1, (int)floor(xh));
                 ilo[a] = i0;
-                n[a] = max(0, i1 - i0 + 1);
-                cnt *= (uint32_t)n[a];
+                n[a] = finite ? max(0, i1 - i0 + 1) : 0;
+                cnt *= (uint64_t)n[a];
             }
         }
 #pragma unroll
@@ -666,24 +673,37 @@ __device__ __forceinline__ void flag_faces_wave(const FaceFlagArgs<D> &A, int64_
             s_i[lane][3 + a] = n[a];
         }
     }
-    const uint32_t incl = dev::wave_inclusive_sum(cnt);
-    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, dev::kWave - 1);
-    if (lane < G) s_i[lane][6] = (int)(incl - cnt);
+    // 64-bit inclusive wave prefix of the pair counts
+    uint64_t incl = cnt;
+#pragma unroll
+    for (int d = 1; d < dev::kWave; d <<= 1) {
+        const uint64_t y = __shfl_up(incl, d, dev::kWave);
+        if (lane >= d) incl += y;
+    }
+    const uint64_t total = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(incl >> 32), dev::kWave - 1) << 32) |
+                           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)incl, dev::kWave - 1);
+    if (lane < G) {
+        const uint64_t pre = incl - cnt;
+        s_i[lane][6] = (int)(uint32_t)pre;
+        s_i[lane][7] = (int)(uint32_t)(pre >> 32);
+    }
     dev::wave_sync();
-    for (uint32_t c0 = 0; c0 < total; c0 += dev::kWave) {
-        const uint32_t v = c0 + lane;
-        if (v >= total) continue;
+    auto pair = [&](auto v) {
+        using T = decltype(v);
+        auto pre_of = [&](int k) -> T {
+            return (T)(((uint64_t)(uint32_t)s_i[k][7] << 32) | (uint32_t)s_i[k][6]);
+        };
         int k = 0;   // the last face whose pairs start at or before v
 #pragma unroll
         for (int step = G / 2; step >= 1; step >>= 1)
-            if ((uint32_t)s_i[k + step][6] <= v) k += step;
-        uint32_t u = v - (uint32_t)s_i[k][6];
+            if (pre_of(k + step) <= v) k += step;
+        T u = v - pre_of(k);
         int g[3] = {0, 0, 0};
-        const uint32_t n0 = (uint32_t)s_i[k][3];
+        const T n0 = (T)s_i[k][3];
         g[0] = s_i[k][0] + (int)(u % n0);
         u /= n0;
         if constexpr (D == 3) {
-            const uint32_t n1 = (uint32_t)s_i[k][4];
+            const T n1 = (T)s_i[k][4];
             g[1] = s_i[k][1] + (int)(u % n1);
             g[2] = s_i[k][2] + (int)(u / n1);
         } else {
@@ -702,11 +722,11 @@ __device__ __forceinline__ void flag_faces_wave(const FaceFlagArgs<D> &A, int64_
             const uint32_t t = A.table[blk];
             const int bc[3] = {g[0] >> 2, g[1] >> 2, D == 3 ? g[2] >> 2 : 0};
             if ((int64_t)t >= A.n || A.keys[t] != dev::encode_key<D>(bc, A.level, A.R[0], A.R[1]))
-                continue;   // no such block at this level
+                return;   // no such block at this level
             blk = t;
         }
         uint8_t *cp = A.cf + blk * CELLS + cell;
-        if (*cp) continue;   // flagged already
+        if (*cp) return;   // flagged already
         float vv[D * D];
 #pragma unroll
         for (int j = 0; j < D * D; ++j) vv[j] = s_rec[k][j];
@@ -717,6 +737,14 @@ __device__ __forceinline__ void flag_faces_wave(const FaceFlagArgs<D> &A, int64_
             *cp = 1;
             A.pmark[blk] = 1;
         }
+    };
+    if (total <= 0xFFFFFFFFull) {
+        const uint32_t tot = (uint32_t)total;
+        for (uint32_t c0 = 0; c0 < tot; c0 += dev::kWave)
+            if (c0 + lane < tot) pair((uint32_t)(c0 + lane));
+    } else {
+        for (uint64_t c0 = 0; c0 < total; c0 += dev::kWave)
+            if (c0 + lane < total) pair((uint64_t)(c0 + lane));
     }
 }
 

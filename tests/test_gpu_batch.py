@@ -95,6 +95,24 @@ def test_batch_mixed_3d_equals_plain():
         _same_as_plain(bt, i, w, plain[i])
 
 
+@pytest.mark.parametrize("limit", [0, 512])
+def test_batch_cell_centric_and_mixed_flag_steps(limit):
+    """The batched flag step cell-centric at every pass (limit 0) or mixed (limit 512: pass 0
+    face-centric, passes 1 and 2 cell-centric): still identical to the plain calls."""
+    import paper_2502_16310_amd as agal
+    ctx = agal.Context()
+    ctx.set_flag_table_limit(limit)
+    wls = _mixed_3d()[:3]
+    ts = [_tensors(w) for w in wls]
+    bt = agal.Batch([(v, f, _cfg(w, w.bins)) for w, (v, f) in zip(wls, ts)], tune_bins=False, tune_grid=False,
+                    ctx=ctx)
+    log(f"case batch flag table limit {limit}: {len(wls)} bodies")
+    bt.run()
+    bt.status()
+    for i, w in enumerate(wls):
+        _same_as_plain(bt, i, w)
+
+
 def test_batch_2d_equals_plain():
     import paper_2502_16310_amd as agal
     wls = [geomgen.workload("C0")]
