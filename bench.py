@@ -512,7 +512,7 @@ def describe(wl):
 CULL_OPS = 12   # FP32 ops of one bounding-box rejection: 6 subtractions, 6 comparisons
 
 # Library timing names -> kernel symbols as profilers list them, and the sources each kernel is built from.
-KERNEL_SYMBOL = {"flag_sat": ("k_flag", "refine.hip"), "q_links": ("k_links", "links.hip"),
+KERNEL_SYMBOL = {"flag_sat": ("k_flag_faces", "refine.hip"), "q_links": ("k_links", "links.hip"),
                  "q_adjoint": ("k_adjoint", "links.hip"), "q_compact": ("k_compact_nodes", "links.hip"),
                  "bin_canon": ("k_bin_canon_small", "bins.hip")}
 
