@@ -149,7 +149,9 @@ AGAL_API agal_status agal_near_wall_refine(agal_geom g, agal_bins b, const agal_
  * it finds blocks through a dense scratch table over the level's block grid
  * (roots * 2^l positions per axis, 4 bytes each).  Cell-centric: one wave per
  * block over the bins under the block, no table.  A level whose block grid
- * has at most max_entries positions takes the face-centric step.  Default
+ * has at most max_entries positions takes the face-centric step, unless the
+ * geometry's largest face has more than 4096 candidate cells there (its box
+ * extent plus the distance on both sides, per axis; measured at import).  Default
  * 2^24 (a 64 MiB table at most); 0 makes every level cell-centric.  Applies
  * to agal_near_wall_refine calls made with ctx afterwards.
  * Errors: AGAL_EINVAL for a NULL context or a negative limit. */

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
@@ -98,7 +99,9 @@ struct agal_context_t {
     bool profiling = false;
     int64_t flag_table_max = int64_t(1) << 24;   // agal_context_set_flag_table_limit
     // completion signals: a device arrival counter (zero between kernels) and
-    // the sequence number last handed out; the signal word is h_counts[kSyncWord]
+    // the sequence number last handed out; the signal word is h_counts[kSyncWord].
+    // d_done[1..3]: device words a signalling kernel accumulates and the last
+    // block moves to mapped memory (zero between kernels)
     uint32_t *d_done = nullptr;
     uint32_t sync_seq = 0;
     std::vector<agal::ProfRecord> records;
@@ -115,6 +118,7 @@ struct agal_geom_t {
     float *aabb = nullptr;     // (2*dim) x F
     float *rec = nullptr;      // F x (16 in 3D, 8 in 2D): corners, min, max
     int32_t *fidx = nullptr;   // F x dim
+    float max_extent[3] = {};  // largest face bounding-box extent per axis
 };
 
 struct agal_bins_t {
@@ -182,6 +186,19 @@ agal_status scan_u32(agal_context ctx, const uint32_t *in, uint32_t *out, int64_
 agal_status scan_flags_u8(agal_context ctx, const uint8_t *in, uint32_t *out, int64_t n, hipStream_t s);
 // k exclusive scans of 0/1 flags (out[i] of length n[i] + 1) in one launch; k <= kMultiScanMax.
 constexpr int kMultiScanMax = kMaxLevels + 1;
+// Candidate cells of the largest face in a face-centric flag step: per axis its
+// box extent plus h + eps on both sides, in cells, plus two for rounding.  A
+// level takes the face-centric step only while this stays within
+// kFaceFlagMaxPairs: one wave takes 16 faces, so a face far larger than the
+// cells would make its wave the whole pass.
+constexpr double kFaceFlagMaxPairs = 4096.0;
+inline double face_flag_pairs(int D, const float ext[3], float h, const float dx[3], const float eps[3]) {
+    double p = 1.0;
+    for (int a = 0; a < D; ++a)
+        p *= std::floor(((double)ext[a] + 2.0 * ((double)h + (double)eps[a])) / (double)dx[a]) + 2.0;
+    return p;
+}
+
 // A kernel's completion signal (see dev::signal_host): arrival counter, the
 // device address of the mapped signal word (null: none) and the value stored.
 struct HostSignal {

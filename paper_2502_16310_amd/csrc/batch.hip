@@ -661,6 +661,7 @@ struct BodyHost {
     int64_t n[kLv] = {};
     int64_t nodes = 0;
     double tune_ms = 0;
+    float max_extent[3] = {};   // largest face box extent per axis (from the sizing run)
 };
 
 }  // namespace batch
@@ -794,6 +795,7 @@ static agal_status size_body(agal_context ctx, const agal_body_desc &d, int B, h
         h.P = bn->P;
         for (int l = 0; l <= fo->L; ++l) h.n[l] = fo->lev[l].n;
         h.nodes = lk->n;
+        for (int a = 0; a < 3; ++a) h.max_extent[a] = g->max_extent[a];
     }
     agal_destroy_links(lk);
     agal_destroy_forest(fo);
@@ -1097,7 +1099,8 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
             if (X.L <= p) continue;
             int64_t e = 1;
             for (int a = 0; a < D; ++a) e *= (int64_t)X.R[a] << p;
-            ok = e <= bt->ctx->flag_table_max;
+            ok = e <= bt->ctx->flag_table_max &&
+                 face_flag_pairs(D, bt->host[b].max_extent, X.d[p], X.dx[p], X.eps) <= kFaceFlagMaxPairs;
         }
         bt->flag_faces[p] = ok;
         if (!ok || p == 0) continue;

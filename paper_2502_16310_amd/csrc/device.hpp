@@ -221,13 +221,21 @@ __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 // host memory included, are ordered before its arrival by a system-scope
 // fence, so a host that reads seq from *word sees all of them.  word == null:
 // no signal.
-__device__ __forceinline__ void signal_host(uint32_t *done, uint32_t *word, uint32_t seq) {
+// The last block also moves n_words device words (accumulated by the blocks
+// with atomics before they arrived) to host_words and clears them.
+__device__ __forceinline__ void signal_host(uint32_t *done, uint32_t *word, uint32_t seq, uint32_t *dev_words = nullptr,
+                                            uint32_t *host_words = nullptr, int n_words = 0) {
     if (!word) return;
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence_system();
         const uint32_t blocks = gridDim.x * gridDim.y * gridDim.z;
         if (__hip_atomic_fetch_add(done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_SYSTEM) == blocks - 1u) {
+            __threadfence_system();
+            for (int i = 0; i < n_words; ++i) {
+                host_words[i] = __hip_atomic_load(dev_words + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(dev_words + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
             __threadfence_system();
             __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             __hip_atomic_store(word, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);

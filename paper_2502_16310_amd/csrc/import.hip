@@ -4,6 +4,7 @@
 // gathers) and a copy of the index list (needed by the adjoint).
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "agal_internal.hpp"
 #include "device.hpp"
@@ -22,12 +23,24 @@ __global__ void k_import(const float *verts, int64_t Nv, const int32_t *faces, i
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t i = t0; i < Nv * D; i += stride)
         if (!isfinite(verts[i])) bad |= 1u;
-    for (int64_t f = t0; f < F; f += stride) bad |= kern::import_face<D>(verts, Nv, faces, F, coords, aabb, rec, fidx, f);
+    float ext[D] = {};
+    for (int64_t f = t0; f < F; f += stride)
+        bad |= kern::import_face<D>(verts, Nv, faces, F, coords, aabb, rec, fidx, f, ext);
     // err: two words of mapped host memory, zeroed by the host; plain stores of
     // the same value need no atomics
     if (bad & 1u) err[0] = 1u;
     if (bad & 2u) err[1] = 1u;
-    dev::signal_host(sig.done, sig.word, sig.seq);
+    // largest face box extent per axis: wave maximum, one atomic per wave on
+    // the (non-negative) float bits in device words, moved to err[2 .. 2 + D)
+    // by the last block
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        float e = ext[a];
+#pragma unroll
+        for (int d = dev::kWave / 2; d >= 1; d >>= 1) e = fmaxf(e, __shfl_xor(e, d, dev::kWave));
+        if (dev::lane_id() == 0) atomicMax(sig.done + 1 + a, __float_as_uint(e));
+    }
+    dev::signal_host(sig.done, sig.word, sig.seq, sig.done + 1, err + 2, D);
 }
 
 static unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 8192) {
@@ -90,6 +103,12 @@ agal_status agal_import_faces(agal_context ctx, int dim, const float *d_vertices
     st = e != hipSuccess ? fail(AGAL_EHIP, "agal_import_faces: %s", hipGetErrorString(e))
                          : wait_signal(ctx, s, sig, "agal_import_faces");
     const uint32_t herr = (ctx->h_counts[0] ? 1u : 0u) | (ctx->h_counts[1] ? 2u : 0u);
+    for (int a = 0; a < 3; ++a) {
+        uint32_t bits = a < dim ? ctx->h_counts[2 + a] : 0u;
+        float e;
+        std::memcpy(&e, &bits, sizeof e);
+        g->max_extent[a] = e;
+    }
     if (st == AGAL_OK && (herr & 1u)) st = fail(AGAL_EINVAL, "agal_import_faces: NaN or Inf vertex coordinate");
     if (st == AGAL_OK && (herr & 2u)) st = fail(AGAL_EINVAL, "agal_import_faces: face index outside [0, n_vertices)");
     if (st != AGAL_OK) {

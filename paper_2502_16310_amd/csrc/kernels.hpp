@@ -26,7 +26,8 @@ namespace kern {
 // is then written as zeros).
 template <int D>
 __device__ __forceinline__ uint32_t import_face(const float *verts, int64_t Nv, const int32_t *faces, int64_t F,
-                                                float *coords, float *aabb, float *rec, int32_t *fidx, int64_t f) {
+                                                float *coords, float *aabb, float *rec, int32_t *fidx, int64_t f,
+                                                float *ext = nullptr) {
     float v[D][D];
     bool ok = true;
 #pragma unroll
@@ -61,6 +62,7 @@ __device__ __forceinline__ uint32_t import_face(const float *verts, int64_t Nv, 
         aabb[(int64_t)(D + a) * F + f] = mx;
         r[D * D + a] = mn;
         r[D * D + D + a] = mx;
+        if (ext) ext[a] = fmaxf(ext[a], mx - mn);   // largest box extent per axis (NaN ignored)
     }
     if constexpr (D == 3) r[15] = 0.0f;
     float4 *out = reinterpret_cast<float4 *>(rec) + f * (dev::kRecFloats<D> / 4);

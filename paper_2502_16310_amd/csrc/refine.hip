@@ -177,7 +177,8 @@ bool flag_dedup(const agal_bins_t *bn, const float dx[3], float h, int64_t n_blo
 
 // The flag pass of level l runs face-centric (one lane per (face, cell) pair
 // near the face) while the level's block grid has at most the context's
-// flag_table_max positions (the table is needed above level 0 only), else
+// flag_table_max positions (the table is needed above level 0 only) and the
+// largest face has at most kFaceFlagMaxPairs candidate cells, else
 // cell-centric (one wave per block).  Measured on MI355X, face-centric wins at
 // every level tried: flags 127 -> 74 us over a 20,480-face sphere (3 levels)
 // and 875 -> 272 us over a 327,680-face body (4 levels), most at the coarse
@@ -245,7 +246,10 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
     for (int l = 0; l < fo->L; ++l) {
         Scratch pass{ctx, s, {}};
         agal::Level &Ll = fo->lev[l];
-        const bool by_face = block_grid_size<D>(fo, l) <= ctx->flag_table_max;
+        float eps_l[3];
+        for (int a = 0; a < 3; ++a) eps_l[a] = dev::kEps * std::max(1.0f, std::max(std::fabs(fo->lo[a]), std::fabs(fo->hi[a])));
+        const bool by_face = block_grid_size<D>(fo, l) <= ctx->flag_table_max &&
+                             face_flag_pairs(D, g->max_extent, fo->d[l], fo->dx[l], eps_l) <= kFaceFlagMaxPairs;
         // the block table of level l (face-centric step above level 0): never
         // cleared, its entries are checked against the level's keys
         uint32_t *table = nullptr;

@@ -455,8 +455,8 @@ agal_status agal_context_create(const agal_allocator *alloc, agal_context *out) 
         return agal::fail(AGAL_ENOMEM, "agal_context_create: mapped pinned host allocation failed");
     }
     c->h_counts[agal::kSyncWord] = 0u;
-    if (hipMalloc((void **)&c->d_done, sizeof(uint32_t)) != hipSuccess ||
-        hipMemset(c->d_done, 0, sizeof(uint32_t)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    if (hipMalloc((void **)&c->d_done, 4 * sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(c->d_done, 0, 4 * sizeof(uint32_t)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         (void)hipGetLastError();
         if (c->d_done) (void)hipFree(c->d_done);
         (void)hipHostFree(c->h_counts);

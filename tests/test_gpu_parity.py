@@ -191,6 +191,21 @@ def test_cell_centric_and_mixed_flag_steps(orc, limit):
         compare_forest(g, of, wl.levels)
 
 
+def test_large_faces_flag_steps(orc):
+    """A 12-triangle box much larger than the cells: level 0 takes the face-centric step,
+    levels 1 and 2 the cell-centric one (a face would have more than 4096 candidate cells);
+    the forest is the oracle's, bit for bit."""
+    v, f = geomgen.box_mesh()
+    wl = geomgen.Workload("box-L3", 3, v, f, (4, 4, 4), 3, 8, 19)
+    log(f"case {wl.name}: faces {len(wl.faces)} roots {wl.roots} L {wl.levels}")
+    g = gpu_run(wl, with_links=False)
+    coords = orc.gather(3, wl.vertices, wl.faces)
+    ob = orc.bin_faces(3, coords, wl.lo, wl.hi, wl.bins)
+    of = orc.refine(3, coords, ob, wl.roots, wl.levels, wl.d_spec(), wl.lo, wl.hi)
+    compare_forest(g, of, wl.levels)
+    assert int(g["levels"][2]["cell_flag"].sum()) > 0
+
+
 def test_run_twice_bitwise_equal(orc):
     wl = _small_sphere(3, 4, 2, 16, 27)
     a = gpu_run(wl)
