@@ -539,7 +539,7 @@ __global__ void k_b_counts(const BodyDev *bodies, int nb, int p, uint32_t *cnt, 
 // kRowCursors ranges of row_range(cap) rows, each with its own cursor in its
 // own 256-byte line, and block blk draws from range blk mod kRowCursors.
 // (One counter per body took every block's atomic at one address; those
-// serialise: 86 us of a 206 us pass on C1.)
+// serialise: 86 us of a 206 us pass over a 20,480-face sphere.)
 struct ChunkRows {
     uint32_t *blk_start, *blk_count, *cursor;   // cursor: this body's kRowCursors counters
     int64_t cap;                                // node capacity of the body
