@@ -391,11 +391,11 @@ __global__ void k_b_ftable(const BodyDev *bodies, int nb, int p, const uint32_t 
     }
 }
 
-template <int D>
-__global__ __launch_bounds__(256) void k_b_flag_faces(const BodyDev *bodies, int nb, int p, const uint32_t *cnt,
-                                                      const uint32_t *wg_pre) {
-    __shared__ float s_rec[4][kFaceFlagG][dev::kRecFloats<D>];
-    __shared__ int s_i[4][kFaceFlagG][8];
+template <int D, int G>
+__global__ __launch_bounds__(64 * kFaceFlagWaves) void k_b_flag_faces(const BodyDev *bodies, int nb, int p,
+                                                                     const uint32_t *cnt, const uint32_t *wg_pre) {
+    __shared__ float s_rec[kFaceFlagWaves][G][dev::kRecFloats<D>];
+    __shared__ int s_i[kFaceFlagWaves][G][8];
     const uint32_t it = blockIdx.x;
     const int b = body_of_wg(wg_pre, nb, it);
     const BodyDev &B = bodies[b];
@@ -419,7 +419,7 @@ __global__ __launch_bounds__(256) void k_b_flag_faces(const BodyDev *bodies, int
     A.h = B.d[p];
     A.cf = B.cf[p][0];
     A.pmark = B.pm[p];
-    flag_faces_wave<D>(A, ((int64_t)(it - wg_pre[b]) * 4 + w) * kFaceFlagG, s_rec[w], s_i[w]);
+    flag_faces_wave<D, G>(A, ((int64_t)(it - wg_pre[b]) * kFaceFlagWaves + w) * G, s_rec[w], s_i[w]);
 }
 
 template <int D>
@@ -695,7 +695,8 @@ struct agal_batch_t {
     unsigned flag_grid[agal::kMaxLevels] = {};   // workgroups of the flag kernel per pass (from capacities)
     bool flag_dedup[agal::kMaxLevels] = {};      // the flag pass takes the deduplicating walker
     bool flag_faces[agal::kMaxLevels] = {};      // the flag pass is face-centric (every body's table fits)
-    unsigned fflag_grid = 0;                     // workgroups of the face-centric flag kernel (64 faces each)
+    unsigned fflag_grid = 0;                     // workgroups of the face-centric flag kernel (4 G faces each)
+    int fflag_g = 16;                            // faces per wave of that kernel (face_flag_g of all faces)
     unsigned links_grid[28] = {};                // workgroups of the q kernel per lattice
     uint32_t *d_wg_pre = nullptr;   // per flag pass, per lattice (9, 19, 27), then per face group: nb + 1 offsets
     hipGraph_t graph = nullptr;
@@ -842,8 +843,16 @@ static agal_status capture(agal_batch bt) {
     for (int p = 0; p < bt->Lmax; ++p) {
         if (bt->flag_faces[p]) {
             hipLaunchKernelGGL(k_b_ftable<D>, dim3(G), dim3(256), 0, s, B, nb, p, bt->d_cnt);
-            hipLaunchKernelGGL(k_b_flag_faces<D>, dim3(bt->fflag_grid), dim3(256), 0, s, B, nb, p, bt->d_cnt,
-                               bt->d_wg_pre + (size_t)(kLv + 3) * (nb + 1));
+            const uint32_t *pre = bt->d_wg_pre + (size_t)(kLv + 3) * (nb + 1);
+            if (bt->fflag_g == 16)
+                hipLaunchKernelGGL((k_b_flag_faces<D, 16>), dim3(bt->fflag_grid), dim3(64 * kFaceFlagWaves), 0, s, B,
+                                   nb, p, bt->d_cnt, pre);
+            else if (bt->fflag_g == 8)
+                hipLaunchKernelGGL((k_b_flag_faces<D, 8>), dim3(bt->fflag_grid), dim3(64 * kFaceFlagWaves), 0, s, B,
+                                   nb, p, bt->d_cnt, pre);
+            else
+                hipLaunchKernelGGL((k_b_flag_faces<D, 4>), dim3(bt->fflag_grid), dim3(64 * kFaceFlagWaves), 0, s, B,
+                                   nb, p, bt->d_cnt, pre);
         } else if (bt->flag_dedup[p])
             hipLaunchKernelGGL((k_b_flag<D, true>), dim3(bt->flag_grid[p]), dim3(64), 0, s, B, nb, p, bt->d_cnt,
                                bt->d_wg_pre + (size_t)p * (nb + 1));
@@ -1084,12 +1093,23 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
     }
     for (int k = 0; k < 3; ++k)
         wg_pre[(size_t)(kLv + k) * (bt->nb + 1) + bt->nb] = bt->links_grid[k == 0 ? 9 : (k == 1 ? 19 : 27)];
-    // face-centric flag step: 64 faces per workgroup, body by body; a pass takes it when every body refining
+    // face-centric flag step: 4 G faces per workgroup, body by body; a pass takes it when every body refining
     // in it has a block grid within the context's table limit (level 0 needs no table); tables are never
     // cleared (entries are checked against the level's keys)
+    {
+        int64_t all_faces = 0;
+        for (int b = 0; b < bt->nb; ++b) all_faces += bt->bodies[b].F;
+        int ncu = 0, cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, cur) != hipSuccess || ncu < 1)
+            ncu = 256;
+        (void)hipGetLastError();
+        bt->fflag_g = face_flag_g(all_faces, ncu);
+    }
+    const int64_t fper_wg = (int64_t)kFaceFlagWaves * bt->fflag_g;
     for (int b = 0; b < bt->nb; ++b) {
         wg_pre[(size_t)(kLv + 3) * (bt->nb + 1) + b] = bt->fflag_grid;
-        bt->fflag_grid += (unsigned)((bt->bodies[b].F + 63) / 64);
+        bt->fflag_grid += (unsigned)((bt->bodies[b].F + fper_wg - 1) / fper_wg);
     }
     wg_pre[(size_t)(kLv + 3) * (bt->nb + 1) + bt->nb] = bt->fflag_grid;
     for (int p = 0; p < agal::kMaxLevels; ++p) {

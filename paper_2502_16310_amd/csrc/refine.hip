@@ -34,12 +34,19 @@ __global__ __launch_bounds__(64) void k_flag(FlagArgs<D> A) {
     flag_wave<D, kDedup>(A, (int64_t)blockIdx.x * (D == 3 ? 1 : 4));
 }
 
-template <int D>
-__global__ __launch_bounds__(256) void k_flag_faces(FaceFlagArgs<D> A) {
-    __shared__ float s_rec[4][kFaceFlagG][dev::kRecFloats<D>];
-    __shared__ int s_i[4][kFaceFlagG][8];
+template <int D, int G>
+__global__ __launch_bounds__(64 * kFaceFlagWaves) void k_flag_faces(FaceFlagArgs<D> A) {
+    __shared__ float s_rec[kFaceFlagWaves][G][dev::kRecFloats<D>];
+    __shared__ int s_i[kFaceFlagWaves][G][8];
     const int w = (int)threadIdx.x / dev::kWave;
-    flag_faces_wave<D>(A, ((int64_t)blockIdx.x * 4 + w) * kFaceFlagG, s_rec[w], s_i[w]);
+    flag_faces_wave<D, G>(A, ((int64_t)blockIdx.x * kFaceFlagWaves + w) * G, s_rec[w], s_i[w]);
+}
+
+template <int D, int G>
+void launch_flag_faces(const FaceFlagArgs<D> &A, hipStream_t s) {
+    const int64_t per_wg = (int64_t)kFaceFlagWaves * G;
+    hipLaunchKernelGGL((k_flag_faces<D, G>), dim3((unsigned)((A.F + per_wg - 1) / per_wg)), dim3(64 * kFaceFlagWaves),
+                       0, s, A);
 }
 
 // table[block grid position] = block index for every block of a level, the
@@ -316,10 +323,12 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
                                        fo->roots[0], fo->roots[1], B.NB[0], B.NB[1], table,
                                        reinterpret_cast<uint4 *>(Ll.cf), reinterpret_cast<uint32_t *>(pb.buf),
                                        pb.words);
-                const int64_t per_wg = 4 * kFaceFlagG;
-                if (g->F > 0)
-                    hipLaunchKernelGGL(k_flag_faces<D>, dim3((unsigned)((g->F + per_wg - 1) / per_wg)), dim3(256), 0,
-                                       s, B);
+                if (g->F > 0) {
+                    const int G = face_flag_g(g->F, ctx->n_cu);
+                    if (G == 16) launch_flag_faces<D, 16>(B, s);
+                    else if (G == 8) launch_flag_faces<D, 8>(B, s);
+                    else launch_flag_faces<D, 4>(B, s);
+                }
             } else if (dedup) {
                 hipLaunchKernelGGL((k_flag<D, true>), dim3((unsigned)waves), dim3(64), 0, s, A);
             } else {
