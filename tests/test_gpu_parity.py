@@ -206,6 +206,20 @@ def test_large_faces_flag_steps(orc):
     assert int(g["levels"][2]["cell_flag"].sum()) > 0
 
 
+def test_sphere_81920_faces_flags_exact(orc):
+    """81,920 faces: the face-centric step runs 8 faces per wave on a 256-CU device (4 on the
+    small cases, 16 on the 327,680-face body); the forest is the oracle's, bit for bit."""
+    v, f = geomgen.icosphere(6, 0.2)
+    wl = geomgen.Workload("ico6", 3, v, f, (8, 8, 8), 2, 32, 19)
+    log(f"case {wl.name}: faces {len(wl.faces)} roots {wl.roots} L {wl.levels}")
+    g = gpu_run(wl, with_links=False)
+    coords = orc.gather(3, wl.vertices, wl.faces)
+    ob = orc.bin_faces(3, coords, wl.lo, wl.hi, wl.bins)
+    compare_bins(g, ob)
+    of = orc.refine(3, coords, ob, wl.roots, wl.levels, wl.d_spec(), wl.lo, wl.hi)
+    compare_forest(g, of, wl.levels)
+
+
 def test_run_twice_bitwise_equal(orc):
     wl = _small_sphere(3, 4, 2, 16, 27)
     a = gpu_run(wl)
