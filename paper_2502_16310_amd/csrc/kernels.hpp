@@ -1189,15 +1189,21 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
                     keep = keep && fb == cur[a] && bb[a] <= qhi[a] && bb[D + a] >= qlo[a];
                 }
             }
-            const uint64_t mask = __ballot(keep);
-            const int nk = __popcll(mask);
-            if (nk == 0) return true;
-            if (count + nk > kLinkCap) {
-                test_staged(count);
-                count = 0;
-            }
-            if (keep) {
-                const int pos = count + dev::lanes_below(mask);
+            // A round can keep up to 64 faces, more than the staging area
+            // holds: they are staged in pieces that fit, the area being
+            // tested and emptied between pieces.
+            uint64_t rest = __ballot(keep);
+            while (rest) {
+                if (count > 0 && count + __popcll(rest) > kLinkCap) {
+                    test_staged(count);
+                    count = 0;
+                }
+                const bool now = ((rest >> lane) & 1ull) && dev::lanes_below(rest) < kLinkCap - count;
+                const uint64_t part = __ballot(now);
+                rest &= ~part;
+                const int pos = count + dev::lanes_below(part);
+                count += __popcll(part);
+                if (now) {
                 s_id[pos] = f;
                 if constexpr (D == 3) {
                     const float *v = r;
@@ -1219,8 +1225,8 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
                     for (int k = 0; k < 4; ++k) s_f[k][pos] = r[k];
                 }
                 s_code[pos] = face_code(sb, bb);
+                }
             }
-            count += nk;
             return true;
         });
     }

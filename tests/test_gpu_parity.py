@@ -220,6 +220,15 @@ def test_sphere_81920_faces_flags_exact(orc):
     compare_forest(g, of, wl.levels)
 
 
+def test_link_staging_round_wider_than_staging_area(orc):
+    """400 small triangles packed near one point and 4 bins per axis: one round of 64
+    candidates keeps every one of them, more than the 32 faces the link kernel stages at a
+    time, so a round is staged in pieces.  Links and q against the oracle."""
+    v, f = geomgen.random_triangles(400, 5, 0.47, 0.53, 0.01)
+    wl = geomgen.Workload("packed400", 3, v, f, (4, 4, 4), 2, 4, 19)
+    _full(orc, wl)
+
+
 def test_run_twice_bitwise_equal(orc):
     wl = _small_sphere(3, 4, 2, 16, 27)
     a = gpu_run(wl)
