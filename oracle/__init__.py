@@ -59,7 +59,10 @@ def lib():
             "orc_bins_ids": (i32p, [P]),
             "orc_sat": (C.c_int, [C.c_int, fp, fp, C.c_float]),
             "orc_near_face_l2": (C.c_int, [C.c_int, dp, dp, C.c_double]),
+            "orc_face_dist2": (C.c_double, [C.c_int, dp, dp]),
+            "orc_near_l2_f32": (C.c_int, [C.c_int, fp, fp, C.c_float]),
             "orc_refine": (P, [C.c_int, fp, C.c_int64, P, i32p, C.c_int, fp, fp, fp]),
+            "orc_refine_own_bin": (P, [C.c_int, fp, C.c_int64, P, i32p, C.c_int, fp, fp, fp, C.c_int]),
             "orc_forest_free": (None, [P]),
             "orc_forest_n": (C.c_int64, [P, C.c_int]),
             "orc_forest_keys": (C.POINTER(C.c_uint32), [P, C.c_int]),
@@ -157,14 +160,34 @@ def sat(dim: int, face: np.ndarray, m: Sequence[float], h: float) -> bool:
 
 
 def near_face_l2(dim: int, face: np.ndarray, p: Sequence[float], R: float) -> bool:
+    """FP64: is p within Euclidean distance R of the closed face?"""
     face = np.ascontiguousarray(face, dtype=np.float64).ravel()
     pp = np.zeros(3, dtype=np.float64)
     pp[:dim] = np.asarray(p, dtype=np.float64)[:dim]
     return bool(lib().orc_near_face_l2(dim, _ptr(face, C.c_double), _ptr(pp, C.c_double), R))
 
 
+def face_dist2(dim: int, face: np.ndarray, p: Sequence[float]) -> float:
+    """FP64 squared Euclidean distance from p to the closed face."""
+    face = np.ascontiguousarray(face, dtype=np.float64).ravel()
+    pp = np.zeros(3, dtype=np.float64)
+    pp[:dim] = np.asarray(p, dtype=np.float64)[:dim]
+    return float(lib().orc_face_dist2(dim, _ptr(face, C.c_double), _ptr(pp, C.c_double)))
+
+
+def near_l2_f32(dim: int, face: np.ndarray, p: Sequence[float], R: float) -> bool:
+    """The FP32 decision of the own-bin flag step (fixed rounded sequence)."""
+    face = np.ascontiguousarray(face, dtype=np.float32).ravel()
+    pp = _vec3(p, 0.0)
+    return bool(lib().orc_near_l2_f32(dim, _ptr(face, C.c_float), _ptr(pp, C.c_float), C.c_float(R)))
+
+
 class Forest:
-    def __init__(self, dim, coords, bins: Optional[Bins], roots, L, d_spec, lo, hi):
+    """Near-wall refinement.  own_bin=False: separating-axis flags over every bin
+    under the query box.  own_bin=True: the paper's own-bin Euclidean flags
+    with mark propagation (n_prop < 0: the paper's step count)."""
+
+    def __init__(self, dim, coords, bins: Optional[Bins], roots, L, d_spec, lo, hi, own_bin=False, n_prop=-1):
         self._coords = np.ascontiguousarray(coords, dtype=np.float32)
         self._bins = bins
         self.dim, self.L = dim, L
@@ -177,9 +200,16 @@ class Forest:
         if len(d) == 0:
             d = np.zeros(1, dtype=np.float32)
         self.lo, self.hi = _vec3(lo, 0.0), _vec3(hi, 1.0)
-        self.h = lib().orc_refine(dim, _ptr(self._coords, C.c_float), self._coords.shape[0],
-                                  bins.h if bins is not None else None, _ptr(r, C.c_int32), L,
-                                  _ptr(d, C.c_float), _ptr(self.lo, C.c_float), _ptr(self.hi, C.c_float))
+        if own_bin:
+            if bins is None:
+                raise ValueError("the own-bin mode needs bins")
+            self.h = lib().orc_refine_own_bin(dim, _ptr(self._coords, C.c_float), self._coords.shape[0], bins.h,
+                                              _ptr(r, C.c_int32), L, _ptr(d, C.c_float), _ptr(self.lo, C.c_float),
+                                              _ptr(self.hi, C.c_float), int(n_prop))
+        else:
+            self.h = lib().orc_refine(dim, _ptr(self._coords, C.c_float), self._coords.shape[0],
+                                      bins.h if bins is not None else None, _ptr(r, C.c_int32), L,
+                                      _ptr(d, C.c_float), _ptr(self.lo, C.c_float), _ptr(self.hi, C.c_float))
         if not self.h:
             raise ValueError("oracle refine rejected its arguments")
         cells = 64 if dim == 3 else 16
@@ -200,8 +230,8 @@ class Forest:
             self.h = None
 
 
-def refine(dim, coords, bins, roots, L, d_spec, lo, hi) -> Forest:
-    return Forest(dim, coords, bins, roots, L, d_spec, lo, hi)
+def refine(dim, coords, bins, roots, L, d_spec, lo, hi, own_bin=False, n_prop=-1) -> Forest:
+    return Forest(dim, coords, bins, roots, L, d_spec, lo, hi, own_bin, n_prop)
 
 
 class Links:

@@ -29,8 +29,12 @@
  *    one of its cells is adjacent.  Adjacency is the closed-box reading: the
  *    face meets the closed cube of half-width d centred on the cell centre,
  *    decided by the 13-axis separating-axis test (the L-infinity form of the
- *    paper's distance criterion; Algorithm 1 is provided separately below as
- *    the L2 cross-check).
+ *    paper's distance criterion).
+ *  - own-bin flagging (orc_refine_own_bin): the paper's own form, Sec.
+ *    II-C-2 with Algorithm 1 and the propagation paragraph of Sec. II-C-3: a
+ *    cell is flagged when its centre lies within Euclidean distance d of a
+ *    face of the one bin holding the centre, then the marks spread over
+ *    1 + floor(d / block length) rings of neighbouring blocks.
  *  - refinement: Sec. II-A (forest of octrees, blocks of 4^D cells, one level
  *    at a time) and Sec. II-C-1 (marked blocks are subdivided); 2:1 balance
  *    across faces, edges and corners is closed by a downward ripple.
@@ -280,10 +284,13 @@ int orc_sat(int dim, const float *face, const float *m, float h) {
 }
 
 /* ------------------------------------------------------------------ */
-/* Algorithm 1 (point within distance R of a triangle: three vertex     */
-/* spheres, three edge cylinders, one prism), FP64, closed.  2D: two    */
-/* discs and one rectangle.  Cross-check only: L2-near(d) implies the   */
-/* closed-box predicate at d, which implies L2-near(sqrt(D) d).         */
+/* Point within distance R of a face (Sec. II-C-2, Algorithm 1).  The   */
+/* paper's region -- three vertex spheres, three edge cylinders and a   */
+/* prism over the face (2D: two discs and a rectangle) -- is the set of */
+/* points whose Euclidean distance to the closed face is at most R, so  */
+/* it is decided here from that distance: the nearest point of a closed */
+/* triangle lies on one of its three closed edges or, when the point    */
+/* projects into the triangle, at that projection.                      */
 /* ------------------------------------------------------------------ */
 static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 static void cross3(const double *a, const double *b, double *c) {
@@ -292,54 +299,122 @@ static void cross3(const double *a, const double *b, double *c) {
     c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-int orc_near_face_l2(int dim, const double *v, const double *p, double R) {
-    if (dim == 3) {
-        for (int k = 0; k < 3; ++k) {
-            const double *vk = v + 3 * k, *vn = v + 3 * ((k + 1) % 3);
-            double dvp[3], e[3], cr[3], dn[3];
-            for (int a = 0; a < 3; ++a) { dvp[a] = vk[a] - p[a]; e[a] = vn[a] - vk[a]; dn[a] = vn[a] - p[a]; }
-            if (dot3(dvp, dvp) <= R * R) return 1;                      /* sphere */
-            double ee = dot3(e, e);
-            if (ee > 0.0) {
-                cross3(e, dvp, cr);
-                double d2 = dot3(cr, cr) / ee;
-                double de1 = -dot3(dvp, e), de2 = dot3(dn, e);
-                if (d2 <= R * R && de1 >= 0.0 && de2 >= 0.0) return 1;  /* cylinder */
-            }
-        }
-        double e0[3], e1[3], n[3];
-        for (int a = 0; a < 3; ++a) { e0[a] = v[3 + a] - v[a]; e1[a] = v[6 + a] - v[a]; }
-        cross3(e0, e1, n);
-        double nn = sqrt(dot3(n, n));
-        if (nn == 0.0) return 0;
-        for (int a = 0; a < 3; ++a) n[a] /= nn;
-        int pos = 1, neg = 1;
-        for (int k = 0; k < 3; ++k) {
-            const double *vk = v + 3 * k, *vn = v + 3 * ((k + 1) % 3);
-            double e[3], en[3], dvp[3];
-            for (int a = 0; a < 3; ++a) { e[a] = vn[a] - vk[a]; dvp[a] = vk[a] - p[a]; }
-            cross3(e, n, en);
-            double sgn = -dot3(dvp, en);
-            if (sgn < 0.0) pos = 0;
-            if (sgn > 0.0) neg = 0;
-        }
-        double dpl[3];
-        for (int a = 0; a < 3; ++a) dpl[a] = p[a] - v[a];
-        double hgt = dot3(dpl, n);
-        return (pos || neg) && (hgt <= R && hgt >= -R);                 /* prism */
-    } else {
-        for (int k = 0; k < 2; ++k) {
-            double dx = v[2 * k] - p[0], dy = v[2 * k + 1] - p[1];
-            if (dx * dx + dy * dy <= R * R) return 1;                   /* discs */
-        }
-        double ex = v[2] - v[0], ey = v[3] - v[1];
-        double ee = ex * ex + ey * ey;
-        if (ee == 0.0) return 0;
-        double wx = p[0] - v[0], wy = p[1] - v[1];
-        double along = (wx * ex + wy * ey) / ee;
-        double cr = ex * wy - ey * wx;
-        return along >= 0.0 && along <= 1.0 && cr * cr <= R * R * ee;  /* rectangle */
+/* Squared distance from p to the closed segment [a, b] (dim 2 or 3), FP64. */
+static double seg_dist2_d(int dim, const double *a, const double *b, const double *p) {
+    double w[3] = {0, 0, 0}, e[3] = {0, 0, 0};
+    for (int k = 0; k < dim; ++k) { w[k] = p[k] - a[k]; e[k] = b[k] - a[k]; }
+    double ee = dot3(e, e), we = dot3(w, e);
+    double s = ee > 0.0 ? we / ee : 0.0;          /* parameter of the nearest point */
+    if (s < 0.0) s = 0.0;
+    if (s > 1.0) s = 1.0;
+    double r[3] = {0, 0, 0};
+    for (int k = 0; k < dim; ++k) r[k] = p[k] - (a[k] + s * e[k]);
+    return dot3(r, r);
+}
+
+/* Squared Euclidean distance from p to the closed face v (2D segment or 3D
+ * triangle), FP64. */
+double orc_face_dist2(int dim, const double *v, const double *p) {
+    if (dim == 2) return seg_dist2_d(2, v, v + 2, p);
+    double best = INFINITY;
+    for (int k = 0; k < 3; ++k) {
+        double d = seg_dist2_d(3, v + 3 * k, v + 3 * ((k + 1) % 3), p);
+        if (d < best) best = d;
     }
+    double e1[3], e2[3], n[3], w[3];
+    for (int a = 0; a < 3; ++a) { e1[a] = v[3 + a] - v[a]; e2[a] = v[6 + a] - v[a]; w[a] = p[a] - v[a]; }
+    cross3(e1, e2, n);
+    double nn = dot3(n, n);
+    if (nn > 0.0) {
+        /* projection of p onto the plane, in the barycentric frame of (e1, e2) */
+        double h = dot3(w, n) / nn;
+        double x[3];
+        for (int a = 0; a < 3; ++a) x[a] = w[a] - h * n[a];
+        double c1[3], c2[3];
+        cross3(x, e2, c1);
+        cross3(e1, x, c2);
+        double u = dot3(c1, n) / nn, t = dot3(c2, n) / nn;
+        if (u >= 0.0 && t >= 0.0 && u + t <= 1.0) {
+            double d = h * h * nn;
+            if (d < best) best = d;
+        }
+    }
+    return best;
+}
+
+int orc_near_face_l2(int dim, const double *v, const double *p, double R) {
+    return orc_face_dist2(dim, v, p) <= R * R;
+}
+
+/* The same decision in FP32 as a fixed sequence of rounded operations (the
+ * flag step of the own-bin refinement mode compares against it bit for bit).
+ * No division: a squared distance d2 = c / m is compared as c <= R^2 m.
+ *   R2 = R * R
+ *   each closed edge [a, b] (2D: the segment; 3D: (v0,v1), (v1,v2), (v2,v0)):
+ *     w = p - a, e = b - a, we = w.e
+ *     we <= 0        -> near when w.w <= R2            (nearest point a)
+ *     we >= e.e      -> near when u.u <= R2, u = p - b (nearest point b)
+ *     otherwise      -> near when |e x w|^2 <= R2 (e.e)  (2D: (e0 w1 - e1 w0)^2)
+ *   3D interior: n = (v1 - v0) x (v2 - v0), nn = n.n; when nn > 0 and
+ *     ((v_{k+1} - v_k) x (p - v_k)) . n >= 0 for k = 0, 1, 2, near when
+ *     ((p - v0) . n)^2 <= R2 nn.
+ * Dot products are (x0 y0 + x1 y1) + x2 y2; cross products c0 = a1 b2 - a2 b1,
+ * c1 = a2 b0 - a0 b2, c2 = a0 b1 - a1 b0. */
+static float dot3f(const float *a, const float *b) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+static void cross3f(const float *a, const float *b, float *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static int edge_near_f(int dim, const float *a, const float *b, const float *p, float R2) {
+    float w[3] = {0, 0, 0}, e[3] = {0, 0, 0};
+    for (int k = 0; k < dim; ++k) { w[k] = p[k] - a[k]; e[k] = b[k] - a[k]; }
+    float we = dim == 3 ? dot3f(w, e) : w[0] * e[0] + w[1] * e[1];
+    if (we <= 0.0f) {
+        float ww = dim == 3 ? dot3f(w, w) : w[0] * w[0] + w[1] * w[1];
+        return ww <= R2;
+    }
+    float ee = dim == 3 ? dot3f(e, e) : e[0] * e[0] + e[1] * e[1];
+    if (we >= ee) {
+        float u[3] = {0, 0, 0};
+        for (int k = 0; k < dim; ++k) u[k] = p[k] - b[k];
+        float uu = dim == 3 ? dot3f(u, u) : u[0] * u[0] + u[1] * u[1];
+        return uu <= R2;
+    }
+    float cc;
+    if (dim == 3) {
+        float c[3];
+        cross3f(e, w, c);
+        cc = dot3f(c, c);
+    } else {
+        float cr = e[0] * w[1] - e[1] * w[0];
+        cc = cr * cr;
+    }
+    return cc <= R2 * ee;
+}
+
+int orc_near_l2_f32(int dim, const float *v, const float *p, float R) {
+    float R2 = R * R;
+    if (dim == 2) return edge_near_f(2, v, v + 2, p, R2);
+    for (int k = 0; k < 3; ++k)
+        if (edge_near_f(3, v + 3 * k, v + 3 * ((k + 1) % 3), p, R2)) return 1;
+    float e1[3], e2[3], n[3];
+    for (int a = 0; a < 3; ++a) { e1[a] = v[3 + a] - v[a]; e2[a] = v[6 + a] - v[a]; }
+    cross3f(e1, e2, n);
+    float nn = dot3f(n, n);
+    if (!(nn > 0.0f)) return 0;
+    for (int k = 0; k < 3; ++k) {
+        float e[3], w[3], c[3];
+        const float *a = v + 3 * k, *b = v + 3 * ((k + 1) % 3);
+        for (int j = 0; j < 3; ++j) { e[j] = b[j] - a[j]; w[j] = p[j] - a[j]; }
+        cross3f(e, w, c);
+        if (!(dot3f(c, n) >= 0.0f)) return 0;
+    }
+    float w0[3];
+    for (int j = 0; j < 3; ++j) w0[j] = p[j] - v[j];
+    float hh = dot3f(w0, n);
+    return hh * hh <= R2 * nn;
 }
 
 /* ------------------------------------------------------------------ */
@@ -450,6 +525,34 @@ static int cell_flag(const orc_forest *fo, const float *coords, int64_t F, const
     return hit;
 }
 
+/* Own-bin form of the flag (Sec. II-C-2, II-C-3): the cell looks only at the
+ * faces of the one bin that holds its centre and is flagged when its centre
+ * lies within distance R of one of them (FP32 decision above).  With B = 1
+ * the bin holds every face (the paper's naive scheme). */
+static int cell_flag_own_bin(const orc_forest *fo, const float *coords, const orc_bins *bn, const float *m, float R,
+                             int64_t *ntests) {
+    int dim = fo->dim;
+    int ix[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) ix[a] = bin_index(m[a], bn->lo[a], bn->s[a], bn->B);
+    int64_t b = ((int64_t)ix[2] * bn->B + ix[1]) * bn->B + ix[0];
+    *ntests += bn->count[b];
+    for (uint32_t j = bn->off[b]; j < bn->off[b + 1]; ++j)
+        if (orc_near_l2_f32(dim, coords + (int64_t)bn->ids[j] * dim * dim, m, R)) return 1;
+    return 0;
+}
+
+/* Number of propagation steps of a pass (Sec. II-C-3): one more than the
+ * whole number of block lengths in the distance, 1 + floor(d / (4 dx)), with
+ * the smallest cell size over the axes; none at B = 1, where every cell sees
+ * every face.  n_prop >= 0 overrides the rule. */
+static int prop_steps(const orc_forest *fo, int l, int B, int n_prop) {
+    if (n_prop >= 0) return n_prop;
+    if (B <= 1) return 0;
+    float dxm = fo->dx[l][0];
+    for (int a = 1; a < fo->dim; ++a) dxm = fmin2(dxm, fo->dx[l][a]);
+    return 1 + (int)floorf(fo->d[l] / (4.0f * dxm));
+}
+
 static void forest_export(orc_forest *fo) {
     int cells = fo->dim == 3 ? 64 : 16;
     for (int l = 0; l <= fo->L; ++l) {
@@ -481,9 +584,11 @@ static void forest_export(orc_forest *fo) {
  * Blocks created in pass l are not tested in pass l.
  * bins == NULL selects the brute-force face loop.
  */
-orc_forest *orc_refine(int dim, const float *coords, int64_t F, const orc_bins *bn, const int *roots,
-                       int L, const float *d_spec, const float *lo, const float *hi) {
+static orc_forest *refine_core(int dim, const float *coords, int64_t F, const orc_bins *bn, const int *roots,
+                               int L, const float *d_spec, const float *lo, const float *hi, int own_bin,
+                               int n_prop) {
     if (L < 0 || L > ORC_MAXL) return NULL;
+    if (own_bin && !bn) return NULL;
     orc_forest *fo = (orc_forest *)xcalloc(1, sizeof(orc_forest));
     fo->dim = dim;
     fo->L = L;
@@ -523,10 +628,37 @@ orc_forest *orc_refine(int dim, const float *coords, int64_t F, const orc_bins *
             for (int c = 0; c < cells; ++c) {
                 float m[3] = {0, 0, 0};
                 cell_center(fo, l, b->c, c, m);
-                b->cf[c] = (uint8_t)cell_flag(fo, coords, F, bn, m, fo->d[l], &fo->tests[l]);
+                b->cf[c] = (uint8_t)(own_bin ? cell_flag_own_bin(fo, coords, bn, m, fo->d[l], &fo->tests[l])
+                                             : cell_flag(fo, coords, F, bn, m, fo->d[l], &fo->tests[l]));
                 any |= b->cf[c];
             }
             if (any) { b->mark = 1; b->pass_mark = 1; }
+        }
+        /* (i') own-bin mode: propagation.  Each step first gives every unmarked
+         * level-l neighbour (faces, edges, corners) of a marked level-l block
+         * an intermediate value, then turns the intermediate values into
+         * marks (3 = marked by propagation), so a step grows the marked set by
+         * exactly one ring of blocks whatever the visiting order. */
+        int nsteps = own_bin ? prop_steps(fo, l, bn->B, n_prop) : 0;
+        for (int st = 0; st < nsteps; ++st) {
+            for (int64_t i = 0; i < lv->n; ++i) {
+                orc_block *b = &lv->b[i];
+                if (b->pass_mark != 1 && b->pass_mark != 3) continue;
+                for (int dz = (dim == 3 ? -1 : 0); dz <= (dim == 3 ? 1 : 0); ++dz)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            if (!dx && !dy && !dz) continue;
+                            int32_t nc[3] = {b->c[0] + dx, b->c[1] + dy, b->c[2] + dz};
+                            int inside = 1;
+                            for (int a = 0; a < dim; ++a)
+                                if (nc[a] < 0 || nc[a] >= fo->roots[a] << l) inside = 0;
+                            if (!inside) continue;
+                            orc_block *nb = level_find(lv, key_of(fo, l, nc));
+                            if (nb && nb->pass_mark == 0) nb->pass_mark = 4;
+                        }
+            }
+            for (int64_t i = 0; i < lv->n; ++i)
+                if (lv->b[i].pass_mark == 4) { lv->b[i].pass_mark = 3; lv->b[i].mark = 3; }
         }
         /* (ii) ripple */
         for (int m = l; m >= 1; --m) {
@@ -578,6 +710,22 @@ orc_forest *orc_refine(int dim, const float *coords, int64_t F, const orc_bins *
     }
     forest_export(fo);
     return fo;
+}
+
+orc_forest *orc_refine(int dim, const float *coords, int64_t F, const orc_bins *bn, const int *roots,
+                       int L, const float *d_spec, const float *lo, const float *hi) {
+    return refine_core(dim, coords, F, bn, roots, L, d_spec, lo, hi, 0, 0);
+}
+
+/*
+ * The paper's own-bin refinement: as orc_refine, but a cell is flagged when
+ * its centre lies within d[l] (Euclidean) of a face of the bin holding the
+ * centre, and after the flags each pass propagates its marks to neighbouring
+ * level-l blocks, prop_steps() rings of them (mark 3).  Requires bins.
+ */
+orc_forest *orc_refine_own_bin(int dim, const float *coords, int64_t F, const orc_bins *bn, const int *roots,
+                               int L, const float *d_spec, const float *lo, const float *hi, int n_prop) {
+    return refine_core(dim, coords, F, bn, roots, L, d_spec, lo, hi, 1, n_prop);
 }
 
 void orc_forest_free(orc_forest *fo) {

@@ -59,6 +59,30 @@ MUTANTS = [
     ("adjoint with the normal of the wrong orientation in the numerator only",
      "grad[vk * dim + a] += wi * lam[k] * nrm[a] / den;", "grad[vk * dim + a] -= wi * lam[k] * nrm[a] / den;",
      "test_adjoint_horizontal_plane_closed_form or test_adjoint_matches_finite_differences"),
+    ("2D adjoint with the segment weights swapped",
+     "lam[0] = 1.0 - s; lam[1] = s;", "lam[0] = s; lam[1] = 1.0 - s;",
+     "test_adjoint_horizontal_segment_closed_form or test_adjoint_2d_matches_finite_differences"),
+    ("2D adjoint with a transposed segment normal",
+     "n[0] = -(p[3] - p[1]);\n        n[1] = p[2] - p[0];", "n[0] = p[2] - p[0];\n        n[1] = -(p[3] - p[1]);",
+     "test_adjoint_horizontal_segment_closed_form or test_adjoint_2d_matches_finite_differences"),
+    ("near decision drops the face interior",
+     "return hh * hh <= R2 * nn;", "return 0 && hh * hh <= R2 * nn;",
+     "test_near_l2_f32_closed_boundary_dyadic or test_near_l2_f32_agrees_with_distance_off_the_boundary"),
+    ("near decision with the edge-interior cross product from the wrong vector",
+     "cross3f(e, w, c);\n        cc = dot3f(c, c);", "cross3f(e, p, c);\n        cc = dot3f(c, c);",
+     "test_near_l2_f32_closed_boundary_dyadic or test_near_l2_f32_agrees_with_distance_off_the_boundary"),
+    ("distance: segment parameter not clamped at the far end",
+     "if (s > 1.0) s = 1.0;", "(void)0;",
+     "test_face_distance_vs_numerical_minimisation"),
+    ("own bin taken from the lower corner of the query box",
+     "ix[a] = bin_index(m[a], bn->lo[a], bn->s[a], bn->B);", "ix[a] = bin_index(m[a] - R, bn->lo[a], bn->s[a], bn->B);",
+     "test_own_bin_flags_and_propagation_brute_force"),
+    ("propagation marks in one sweep (a step can run on through blocks it just marked)",
+     "if (nb && nb->pass_mark == 0) nb->pass_mark = 4;", "if (nb && nb->pass_mark == 0) { nb->pass_mark = 3; nb->mark = 3; }",
+     "test_own_bin_flags_and_propagation_brute_force"),
+    ("one propagation step too few",
+     "return 1 + (int)floorf(fo->d[l] / (4.0f * dxm));", "return (int)floorf(fo->d[l] / (4.0f * dxm));",
+     "test_own_bin_flags_and_propagation_brute_force"),
 ]
 
 
@@ -74,6 +98,7 @@ def test_pins_catch_mutant(tmp_path, name, old, new, tests):
                            "-shared", str(cpath), "-o", str(lib), "-lm"])
     env = dict(os.environ, AGAL_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        os.path.join(HERE, "test_oracle_pins.py"), "-k", tests],
+                        os.path.join(HERE, "test_oracle_pins.py"), os.path.join(HERE, "test_oracle_own_bin.py"),
+                        "-k", tests],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"pins did not catch: {name}\n{r.stdout[-2000:]}"

@@ -740,6 +740,64 @@ def test_adjoint_horizontal_plane_closed_form(orc):
     assert np.allclose(grad[:, :2], 0.0, atol=1e-12)
 
 
+def _golden(name):
+    import os
+    gold = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as fh:
+        for line in fh:
+            line = line.split("#")[0].strip()
+            if line:
+                k, val = line.split("=")
+                gold[k.strip()] = [float(x) for x in val.split()]
+    return gold
+
+
+def test_adjoint_horizontal_segment_closed_form(orc):
+    """2D: an upward and a diagonal link through a horizontal segment, dq/dy_k = lambda_k / dx
+    with lambda = (1 - s, s), zero along x (golden values in tests/golden/adjoint_segment.txt)."""
+    gold = _golden("adjoint_segment.txt")
+    v = np.array(gold["segment"], dtype=np.float32).reshape(2, 2)
+    f = np.array([[0, 1]], dtype=np.int32)
+    wl, coords, bins, fo = _all_level_forest(orc, 2, v, f, (1, 1), 1, 9)
+    lk = orc.link_fractions(2, coords, bins, fo, 9)
+    n = int(np.nonzero(lk.key == int(gold["node_key"][0]))[0][0])
+    c = orc.lattice(9)
+    up = int(np.nonzero((c[:, 0] == 0) & (c[:, 1] == 1))[0][0])
+    diag = int(np.nonzero((c[:, 0] == 1) & (c[:, 1] == 1))[0][0])
+    for i, qk, gk in ((up, "q_up", "grad_y_up"), (diag, "q_diag", "grad_y_diag")):
+        assert lk.face[n, i] == 0
+        assert abs(lk.q[n, i] - gold[qk][0]) < 1e-12
+        w = np.zeros((lk.n, 9))
+        w[n, i] = 1.0
+        grad = orc.link_grad(fo, lk, coords, f, w, 2)
+        assert np.allclose(grad[:, 1], gold[gk], rtol=1e-12, atol=0), (gk, grad)
+        assert np.allclose(grad[:, 0], 0.0, atol=1e-12)
+
+
+def test_adjoint_2d_matches_finite_differences(orc):
+    """2D adjoint against central differences of the oracle's own q on a jittered circle."""
+    n = 96
+    th = 2 * np.pi * np.arange(n) / n
+    v64 = np.stack([0.5 + 0.25 * np.cos(th), 0.5 + 0.25 * np.sin(th)], 1)
+    v64 = geomgen.jitter_fp64(v64, 1e-3, 1)
+    v = v64.astype(np.float32)
+    f = np.stack([np.arange(n), (np.arange(n) + 1) % n], 1).astype(np.int32)
+    wl = geomgen.Workload("j2", 2, v, f, (4, 4, 1), 3, 16, 9)
+    coords, bins, fo = _forest(orc, wl)
+    lk = orc.link_fractions(2, coords, bins, fo, 9)
+    stable = orc.link_stable(fo, lk, coords, bins, h=1e-5)
+    w = geomgen.weights(lk.n * 9, 2).astype(np.float64).reshape(lk.n, 9)
+    w[~stable] = 0.0
+    assert stable.sum() > 200
+    g = orc.link_grad(fo, lk, coords, f, w, n)
+    gfd, nch = orc.fd_grad(fo, lk, v, f, bins, w, h=1e-5)
+    assert nch == 0
+    err = np.abs(g - gfd)
+    scale = np.maximum(np.abs(gfd), 1e-2 * np.abs(gfd).max())
+    assert (err <= 1e-3 * scale).all(), float((err / scale).max())
+    assert np.linalg.norm(g - gfd) <= 1e-4 * np.linalg.norm(gfd)
+
+
 def test_adjoint_matches_finite_differences(orc):
     u, f = geomgen.icosphere_unit(2)
     v64 = geomgen.jitter_fp64(np.array([0.5, 0.5, 0.5]) + 0.2 * u, 1e-3, 1)
