@@ -5,7 +5,10 @@ forest level by level near the wall, compute the link fractions q and run
 the adjoint for a weighted sum of q -- every row of the hot path, on
 synthetic seeded geometry (see geomgen).  Prints ONE JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--config C1|C2|C4] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--config C2|C1|C4] [--no-cpu-baseline]
+
+The default workload is C2 (327,680-face star body, 32^3 roots, 4 passes,
+D3Q27), the largest single-body configuration.
 
 --config C4 times the batched form (64 bodies, one graph launch, forward and
 adjoint) against the same bodies through the single-body calls.
@@ -143,25 +146,45 @@ def host_info():
     return model, cores
 
 
+Q_SAMPLE_BLOCKS = 4000   # finest-level blocks whose q the CPU baseline computes when a full pass is too long
+Q_SAMPLE_SEED = 5
+
+
 def cpu_baseline(wl, w_slots, T_total):
-    """The CPU oracle as it stands, serial, on the same workload (full pass + adjoint)."""
+    """The CPU oracle as it stands, serial, on the same workload: bins and every refinement pass in full, then
+    FP64 q and the FP64 adjoint for every finest-level block, or, when the finest level has more than
+    Q_SAMPLE_BLOCKS blocks (a full q pass of the 327,680-face body is about 20 minutes on one core), for a seeded
+    uniform sample of Q_SAMPLE_BLOCKS of them.  The rate is the cell-face tests the oracle performed divided by
+    its time."""
     import oracle
     oracle.build(force=False)
     t0 = time.perf_counter()
-    r = oracle.run_plain(wl)
-    lk = r["links"]
+    r = oracle.run_plain(wl, with_links=False)
+    t1 = time.perf_counter()
+    fo = r["forest"]
+    n_fin = len(fo.levels[wl.levels]["keys"])
+    sub = None
+    if n_fin > Q_SAMPLE_BLOCKS:
+        rng = np.random.default_rng(Q_SAMPLE_SEED)
+        sub = np.sort(rng.choice(n_fin, Q_SAMPLE_BLOCKS, replace=False))
+    lk = oracle.link_fractions(wl.dim, r["coords"], r["bins"], fo, wl.lattice, sub)
     w = np.zeros((lk.n, wl.lattice))
     n = min(lk.n * wl.lattice, len(w_slots))
     w.reshape(-1)[:n] = w_slots[:n]
     w[lk.face < 0] = 0.0
-    oracle.link_grad(r["forest"], lk, r["coords"], wl.faces, w, len(wl.vertices))
-    dt = time.perf_counter() - t0
-    T_orc = sum(r["forest"].tests) + lk.tests
+    oracle.link_grad(fo, lk, r["coords"], wl.faces, w, len(wl.vertices))
+    t2 = time.perf_counter()
+    dt = t2 - t0
+    T_orc = sum(fo.tests) + lk.tests
     model, _ = host_info()
+    what = ("every finest-level cell" if sub is None else
+            f"the cells of {len(sub)} of the {n_fin} finest-level blocks (seeded uniform sample, seed {Q_SAMPLE_SEED})")
     return {"value": T_orc / dt, "unit": "cell-face tests/s", "cores": 1, "kind": "oracle",
-            "sample": f"full {wl.name} pass on one host core ({model}): bins, {wl.levels} refinement passes "
-                      f"(FP32 flags), FP64 q for every finest-level cell, FP64 adjoint; {dt:.1f} s",
-            "seconds": dt, "tests": int(T_orc)}
+            "sample": f"{wl.name} on one host core ({model}): bins and {wl.levels} refinement passes in full "
+                      f"(FP32 flags, {t1 - t0:.1f} s), then FP64 q and the FP64 adjoint for {what} "
+                      f"({t2 - t1:.1f} s); rate = cell-face tests performed / time",
+            "seconds": dt, "tests": int(T_orc), "refine_seconds": t1 - t0, "q_seconds": t2 - t1,
+            "q_blocks": n_fin if sub is None else len(sub), "finest_blocks": n_fin}
 
 
 def main():
@@ -169,7 +192,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C1")
+    ap.add_argument("--config", default="C2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the one-body graph timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -328,6 +351,8 @@ def main():
         "forest_blocks_per_level": n_blocks, "boundary_nodes": n_nodes, "links": n_links,
         "kernels": kern, "roofline": roof,
     }
+    if wl.name != "C3":
+        out["grad_C3"] = grad_c3(args, agal, torch, dev)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on the same workload", file=sys.stderr, flush=True)
         cb = cpu_baseline(wl, w_host.astype(np.float64), T)
@@ -335,6 +360,57 @@ def main():
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+def grad_c3(args, agal, torch, dev):
+    """The differentiated form on its own workload: the jittered 20,480-face sphere (C3, D3Q19) with weights
+    U(-1, 1) (seed 2) on every link slot.  HIP events on the launch stream time the adjoint launch alone and the
+    whole forward (import, bins, refinement, q) plus backward; medians over K runs."""
+    import geomgen
+    wl = geomgen.workload("C3")
+    dim, Q = wl.dim, wl.lattice
+    print(f"bench: gradient leg on {wl.name} ({len(wl.faces)} faces, D{dim}Q{Q})", file=sys.stderr, flush=True)
+    ctx = agal.agal_context_create()
+    stream = torch.cuda.current_stream().cuda_stream
+    v = torch.from_numpy(wl.vertices).to(dev)
+    f = torch.from_numpy(wl.faces).to(dev)
+    desc = agal.forest_desc(dim, wl.roots[:dim], wl.levels, [float(x) for x in wl.d_spec()], wl.lo[:dim],
+                            wl.hi[:dim])
+    grad = torch.zeros((len(wl.vertices), dim), dtype=torch.float32, device=dev)
+    w_host = None
+    w_dev = None
+    adj, tot = [], []
+    n_links = 0
+    for k in range(args.warmup + args.steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        g = agal.agal_import_faces(ctx, dim, v.data_ptr(), v.shape[0], f.data_ptr(), f.shape[0], stream)
+        b = agal.agal_bin_faces(g, wl.lo[:dim], wl.hi[:dim], wl.bins, stream)
+        fo = agal.agal_near_wall_refine(g, b, desc, stream)
+        lk = agal.agal_link_fractions(g, b, fo, Q, stream)
+        n = agal.agal_links_view(lk)[3]
+        if w_dev is None:
+            face = agal.device_copy(agal.agal_links_view(lk)[2], n * Q, torch.int32)
+            w_host = geomgen.weights(n * Q, wl.extra["weights_seed"])
+            w_dev = torch.from_numpy(w_host).to(dev) * (face >= 0)
+            n_links = int((face >= 0).sum().item())
+        grad.zero_()
+        e[1].record()
+        agal.agal_link_fractions_backward(g, lk, w_dev.data_ptr(), grad.data_ptr(), stream)
+        e[2].record()
+        for h, fn in ((lk, agal.agal_destroy_links), (fo, agal.agal_destroy_forest), (b, agal.agal_destroy_bins),
+                      (g, agal.agal_destroy_geom)):
+            fn(h)
+        torch.cuda.synchronize()
+        if k >= args.warmup:
+            adj.append(e[1].elapsed_time(e[2]))
+            tot.append(e[0].elapsed_time(e[2]))
+    agal.agal_context_destroy(ctx)
+    adj.sort()
+    tot.sort()
+    return {"workload": "C3: icosphere subdivision 5 (20480 triangles) r=0.2, vertices jittered N(0,1e-3) seed 1, "
+                        "weights U(-1,1) seed 2, D3Q19",
+            "adjoint_ms": adj[len(adj) // 2], "forward_backward_ms": tot[len(tot) // 2], "live_links": n_links}
 
 
 def graph_step(args, agal, torch, wl, v, f, w_host, n_nodes, T):
@@ -509,7 +585,10 @@ def describe(wl):
     return wl.name
 
 
-CULL_OPS = 12   # FP32 ops of one bounding-box rejection: 6 subtractions, 6 comparisons
+# FP32 operations charged per (cell, candidate face) pair: the least work a candidate costs.  Link kernel: one
+# face-box cull against the link box, 8 ops; flag kernel: the rejection of one separating-axis test by the box
+# axes, 24 ops.
+OPS_PER_PAIR = {"q_links": 8, "flag_sat": 24}
 
 # Library timing names -> kernel symbols as profilers list them, and the sources each kernel is built from.
 KERNEL_SYMBOL = {"flag_sat": ("k_flag_faces", "refine.hip"), "q_links": ("k_links", "links.hip"),
@@ -550,8 +629,9 @@ def roofline(name, k, dim, Q, F, nb, P, n_blocks, n_nodes, t_flag, t_q, L, workl
 
     flag_sat / q_links are arithmetic kernels: algorithmic work = the (cell,
     candidate face) pairs the bins present (t_flag per pass / t_q) times the
-    CULL_OPS every candidate costs at least, against the FP32 VALU peak without
-    packed math or FMA (256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T op/s).
+    OPS_PER_PAIR every candidate costs at least, against the FP32 VALU peak
+    without packed math or FMA (256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T
+    op/s).
     Streaming kernels are charged their compulsory HBM bytes."""
     us = k["avg_us"]
     launches = k["launches_per_step"]
@@ -560,11 +640,11 @@ def roofline(name, k, dim, Q, F, nb, P, n_blocks, n_nodes, t_flag, t_q, L, workl
     csr_bytes = 4 * (nb + 1) + 4 * P
     if name in ("flag_sat", "q_links"):
         pairs = (sum(t_flag) / max(1, launches)) if name == "flag_sat" else t_q
-        ops = CULL_OPS * pairs
+        ops = OPS_PER_PAIR[name] * pairs
         tops = ops / (us * 1e-6) / 1e12
         return {"bound": "alu", "achieved": tops, "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
                 "frac": tops / VALU_PEAK_TOPS, "traffic": measured_traffic(name, workload), "kernel": name,
-                "ops_per_launch": ops,
+                "ops_per_pair": OPS_PER_PAIR[name], "ops_per_launch": ops,
                 "cell_face_pairs_per_launch": pairs, "avg_launch_us": us}
     if name == "q_adjoint":
         byts = n_nodes * (8 + 8 * Q) + face_bytes + 4 * F * dim + 4 * dim * 4 * F

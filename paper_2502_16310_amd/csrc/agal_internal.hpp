@@ -98,10 +98,11 @@ struct agal_context_t {
     // kernel timing (HIP events around each launch) when enabled
     bool profiling = false;
     int64_t flag_table_max = int64_t(1) << 24;   // agal_context_set_flag_table_limit
-    // completion signals: a device arrival counter (zero between kernels) and
-    // the sequence number last handed out; the signal word is h_counts[kSyncWord].
-    // d_done[1..3]: device words a signalling kernel accumulates and the last
-    // block moves to mapped memory (zero between kernels)
+    // completion signals: a device arrival counter d_done[0] (zero between
+    // kernels) and the sequence number last handed out; the signal word is
+    // h_counts[kSyncWord].  d_done[1..5]: device words the import kernel
+    // accumulates and its signal launch moves to mapped memory (zero between
+    // kernels)
     uint32_t *d_done = nullptr;
     uint32_t sync_seq = 0;
     std::vector<agal::ProfRecord> records;

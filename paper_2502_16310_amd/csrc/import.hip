@@ -17,7 +17,7 @@ namespace agal {
 // zeros and the call fails).
 template <int D>
 __global__ void k_import(const float *verts, int64_t Nv, const int32_t *faces, int64_t F, float *coords, float *aabb,
-                         float *rec, int32_t *fidx, uint32_t *err, HostSignal sig) {
+                         float *rec, int32_t *fidx, uint32_t *acc) {
     uint32_t bad = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -26,21 +26,30 @@ __global__ void k_import(const float *verts, int64_t Nv, const int32_t *faces, i
     float ext[D] = {};
     for (int64_t f = t0; f < F; f += stride)
         bad |= kern::import_face<D>(verts, Nv, faces, F, coords, aabb, rec, fidx, f, ext);
-    // err: two words of mapped host memory, zeroed by the host; plain stores of
-    // the same value need no atomics
-    if (bad & 1u) err[0] = 1u;
-    if (bad & 2u) err[1] = 1u;
+    // error bits in device words (acc[3], acc[4]), zero before the launch
+    if (bad & 1u) atomicOr(acc + 3, 1u);
+    if (bad & 2u) atomicOr(acc + 4, 1u);
     // largest face box extent per axis: wave maximum, one atomic per wave on
-    // the (non-negative) float bits in device words, moved to err[2 .. 2 + D)
-    // by the last block
+    // the (non-negative) float bits in acc[0 .. D)
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         float e = ext[a];
 #pragma unroll
         for (int d = dev::kWave / 2; d >= 1; d >>= 1) e = fmaxf(e, __shfl_xor(e, d, dev::kWave));
-        if (dev::lane_id() == 0) atomicMax(sig.done + 1 + a, __float_as_uint(e));
+        if (dev::lane_id() == 0) atomicMax(acc + a, __float_as_uint(e));
     }
-    dev::signal_host(sig.done, sig.word, sig.seq, sig.done + 1, err + 2, D);
+}
+
+// After the import kernel (stream order makes its device words final): the
+// error bits to err[0..1] and the extents to err[2..2+D) of mapped host
+// memory, the device words cleared, then the completion signal.
+__global__ void k_import_signal(uint32_t *acc, uint32_t *err, int D, HostSignal sig) {
+    if (threadIdx.x != 0) return;
+    err[0] = acc[3];
+    err[1] = acc[4];
+    for (int a = 0; a < D; ++a) err[2 + a] = acc[a];
+    for (int i = 0; i < 5; ++i) acc[i] = 0u;
+    dev::publish_host(sig.word, sig.seq);
 }
 
 static unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 8192) {
@@ -94,10 +103,11 @@ agal_status agal_import_faces(agal_context ctx, int dim, const float *d_vertices
         const unsigned grid = grid_for(std::max(n_vertices * dim, n_faces));
         if (dim == 3)
             hipLaunchKernelGGL(k_import<3>, dim3(grid), dim3(256), 0, s, d_vertices, n_vertices, d_faces, n_faces,
-                               g->coords, g->aabb, g->rec, g->fidx, err, sig);
+                               g->coords, g->aabb, g->rec, g->fidx, ctx->d_done + 1);
         else
             hipLaunchKernelGGL(k_import<2>, dim3(grid), dim3(256), 0, s, d_vertices, n_vertices, d_faces, n_faces,
-                               g->coords, g->aabb, g->rec, g->fidx, err, sig);
+                               g->coords, g->aabb, g->rec, g->fidx, ctx->d_done + 1);
+        hipLaunchKernelGGL(k_import_signal, dim3(1), dim3(64), 0, s, ctx->d_done + 1, err, dim, sig);
     }
     hipError_t e = hipGetLastError();
     st = e != hipSuccess ? fail(AGAL_EHIP, "agal_import_faces: %s", hipGetErrorString(e))

@@ -239,10 +239,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(In in, uint32_t *out, int
         run += v[i];
         if (idx == n - 1) {
             out[n] = run;
-            if (host_total) *host_total = run;
+            // the total is known once this tile's look-back ends: the host
+            // needs nothing else from this launch
+            if (host_total) {
+                *host_total = run;
+                dev::publish_host(sig.word, sig.seq);
+            }
         }
     }
-    dev::signal_host(sig.done, sig.word, sig.seq);
 }
 
 agal_status lookback_alloc(agal_context ctx, int64_t tiles, uint64_t **status, uint32_t **ticket, hipStream_t s) {
@@ -341,11 +345,15 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_flags_multi(MultiScanArgs
     }
     __syncthreads();
     uint32_t run = s_prefix + wpre + incl - sum;
+    // the thread holding an array's last element (tile 0's first thread for
+    // an empty array) reports its total, and the last of the k reports adds
+    // the extra word and signals the host
+    bool report = false;
     if (n == 0 && threadIdx.x == 0) {
         out[0] = 0u;
         a.host_total[seg] = 0u;
+        report = true;
     }
-    if (gtile == 0 && threadIdx.x == 0) a.host_total[a.nseg] = a.extra ? *a.extra : 0u;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const int64_t idx = base + i;
@@ -354,9 +362,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_flags_multi(MultiScanArgs
         if (idx == n - 1) {
             out[n] = run;
             a.host_total[seg] = run;
+            report = true;
         }
     }
-    dev::signal_host(a.sig.done, a.sig.word, a.sig.seq);
+    if (report && dev::arrive_last(a.sig.done, (uint32_t)a.nseg)) {
+        a.host_total[a.nseg] = a.extra ? *a.extra : 0u;
+        dev::publish_host(a.sig.word, a.sig.seq);
+    }
 }
 
 int64_t scan_flags_u8_multi_tiles(const int64_t *n, int k) {
@@ -455,8 +467,8 @@ agal_status agal_context_create(const agal_allocator *alloc, agal_context *out) 
         return agal::fail(AGAL_ENOMEM, "agal_context_create: mapped pinned host allocation failed");
     }
     c->h_counts[agal::kSyncWord] = 0u;
-    if (hipMalloc((void **)&c->d_done, 4 * sizeof(uint32_t)) != hipSuccess ||
-        hipMemset(c->d_done, 0, 4 * sizeof(uint32_t)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    if (hipMalloc((void **)&c->d_done, 8 * sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(c->d_done, 0, 8 * sizeof(uint32_t)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         (void)hipGetLastError();
         if (c->d_done) (void)hipFree(c->d_done);
         (void)hipHostFree(c->h_counts);

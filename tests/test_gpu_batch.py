@@ -3,12 +3,13 @@ exactly what the single-body calls give on the same input (forest levels,
 cell flags, node keys, q and face ids bit-identical; vertex gradients equal up
 to the order of floating-point atomics), including mixed lattices, zero
 levels, empty refinement, tuned bin densities, reruns of the same plan,
-capacity overflow and invalid input."""
+capacity overflow and invalid input -- and, body by body, what the oracle
+gives (forest bit-exact, q within 1e-5 of FP64)."""
 import numpy as np
 import pytest
 
 import geomgen
-from _parity import gpu_run, log
+from _parity import Q_TOL, check_face_ties, compare_forest, compare_links, gpu_run, log
 
 pytestmark = pytest.mark.gpu
 
@@ -77,7 +78,32 @@ def _same_as_plain(bt, i, wl, g=None):
     return g
 
 
-def test_batch_mixed_3d_equals_plain():
+def _same_as_oracle(orc, bt, i, wl, sample=None, seed=0):
+    """Body i of the batch against the oracle at the bin density the plan used: every forest level bit
+    for bit, then the links of every finest-level block (or of `sample` of them, seeded): q within 1e-5
+    of FP64, no link on one side only away from a segment end, face ids equal except at ties."""
+    dim = wl.dim
+    coords = orc.gather(dim, wl.vertices, wl.faces)
+    ob = orc.bin_faces(dim, coords, wl.lo[:dim], wl.hi[:dim], bt.bins(i))
+    of = orc.refine(dim, coords, ob, wl.roots[:dim], wl.levels, wl.d_spec(), wl.lo[:dim], wl.hi[:dim])
+    levels, k, q, f = _batch_body(bt, i, wl)
+    compare_forest({"levels": levels}, of, wl.levels)
+    nL = len(of.levels[wl.levels]["keys"])
+    sub = None
+    if sample is not None and nL > sample:
+        sub = np.sort(np.random.default_rng(seed).choice(nL, sample, replace=False))
+    lk = orc.link_fractions(dim, coords, ob, of, wl.lattice, subset=sub)
+    rep, arrs = compare_links({"key": k, "q": q, "face": f}, lk,
+                              restrict_blocks=None if sub is None else of.levels[wl.levels]["keys"][sub],
+                              cells=4 ** dim)
+    nd, bad = check_face_ties(orc, of, coords, wl.lattice, *arrs)
+    log(f"  {wl.name} vs oracle (B {bt.bins(i)}): nodes {rep.nodes_gpu}/{rep.nodes_orc} links {rep.links} "
+        f"max|dq| {rep.max_err:.2e} one-sided {rep.one_sided} ties {nd}")
+    assert rep.max_err <= Q_TOL and rep.one_sided_not_at_end == 0 and bad == 0
+    assert rep.links > 0 or wl.levels == 0
+
+
+def test_batch_mixed_3d_equals_plain(orc):
     import paper_2502_16310_amd as agal
     wls = _mixed_3d()
     ts = [_tensors(w) for w in wls]
@@ -87,6 +113,8 @@ def test_batch_mixed_3d_equals_plain():
     bt.status()
     plain = [_same_as_plain(bt, i, w) for i, w in enumerate(wls)]
     log("  " + ", ".join(f"{w.name}: {len(p['key'])} nodes" for w, p in zip(wls, plain)))
+    for i, w in enumerate(wls):
+        _same_as_oracle(orc, bt, i, w)
     # the same plan again: identical results
     bt.run()
     bt.run()
@@ -113,7 +141,7 @@ def test_batch_cell_centric_and_mixed_flag_steps(limit):
         _same_as_plain(bt, i, w)
 
 
-def test_batch_2d_equals_plain():
+def test_batch_2d_equals_plain(orc):
     import paper_2502_16310_amd as agal
     wls = [geomgen.workload("C0")]
     v, f = geomgen.random_segments(200, 10, 0.05, 0.95, 0.1)
@@ -127,6 +155,7 @@ def test_batch_2d_equals_plain():
     bt.status()
     for i, w in enumerate(wls):
         _same_as_plain(bt, i, w)
+        _same_as_oracle(orc, bt, i, w)
 
 
 def test_batch_tuned_bins_and_cache(tmp_path):
@@ -214,8 +243,10 @@ def test_batch_capacity_overflow_and_invalid_input():
     _same_as_plain(bt, 0, wl, g)
 
 
-def test_batch_64_star_bodies_equal_plain():
-    """64 star bodies of 1,280 to 327,680 faces (subdivision 3..7), D3Q27, tuned bins and grid."""
+def test_batch_64_star_bodies_equal_plain(orc):
+    """64 star bodies of 1,280 to 327,680 faces (subdivision 3..7), D3Q27, tuned bins and grid; every body
+    against the single-body calls, and a seeded handful of the subdivision 3-5 bodies against the oracle
+    (forest in full, links on 300 sampled finest-level blocks)."""
     import paper_2502_16310_amd as agal
     draws = geomgen.batch_draws(64)
     wls = [geomgen.batch_body(d) for d in draws]
@@ -230,3 +261,7 @@ def test_batch_64_star_bodies_equal_plain():
         g = _same_as_plain(bt, i, w)
         nodes += len(g["key"])
     log(f"  all 64 bodies identical to the single-body path ({nodes} nodes)")
+    small = [i for i, d in enumerate(draws) if d["s"] <= 5]
+    pick = sorted(np.random.default_rng(3).choice(small, size=min(5, len(small)), replace=False))
+    for i in pick:
+        _same_as_oracle(orc, bt, int(i), wls[i], sample=300, seed=int(i))

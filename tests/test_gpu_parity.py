@@ -58,8 +58,71 @@ def test_small_sphere_d3q27_non_dyadic_domain(orc):
 
 @pytest.mark.parametrize("B", [1, 2, 8, 37])
 def test_bin_density_invariance(orc, B):
-    # B = 1 is the naive all-faces search; tiny B exercises the oversized-bin path
+    # B = 1 is the naive all-faces search (one bin of 1,280 ids: still one LDS rank sort)
     _full(orc, _small_sphere(3, 4, 2, 16), B=B)
+
+
+@pytest.mark.parametrize("s,B", [(4, 1), (4, 2), (5, 2), (5, 3)])
+def test_oversized_bins_csr_exact(orc, s, B):
+    """Bins and 64-bin groups holding more than the 2,048 ids one LDS rank sort takes: s=4, B=1 puts
+    5,120 ids in one bin (the ordered sweep over all faces); s=4, B=2 gives a group of eight bins above
+    2,048 ids whose bins fit one by one; s=5 at B=2 and 3 gives several oversized bins at once.  The
+    CSR is compared with the oracle's, bit for bit, and the forest as well."""
+    v, f = geomgen.icosphere(s, 0.2)
+    wl = geomgen.Workload(f"ico{s}-B{B}", 3, v, f, (2, 2, 2), 2, B, 19)
+    log(f"case {wl.name}: faces {len(wl.faces)} B {B}")
+    g = gpu_run(wl, with_links=False)
+    coords = orc.gather(3, wl.vertices, wl.faces)
+    ob = orc.bin_faces(3, coords, wl.lo, wl.hi, B)
+    counts = np.diff(ob.offsets.astype(np.int64))
+    groups = np.add.reduceat(counts, np.arange(0, len(counts), 64))
+    log(f"  largest bin {counts.max()} ids, largest 64-bin group {groups.max()} ids")
+    assert groups.max() > 2048
+    compare_bins(g, ob)
+    of = orc.refine(3, coords, ob, wl.roots, wl.levels, wl.d_spec(), wl.lo, wl.hi)
+    compare_forest(g, of, wl.levels)
+
+
+@pytest.mark.parametrize("lo,hi", [(5 / 16, 11 / 16), (81 / 256, 175 / 256)])
+def test_box_links_exact_ties_and_grazing(orc, lo, hi):
+    """An axis-aligned box of 12 triangles with dyadic corners: links through the shared diagonal edges
+    and corners tie exactly between faces, links parallel to a face have det == 0, and with the faces at
+    odd multiples of half a finest cell (second case: finest cells of 1/128, centres at odd multiples of
+    1/256) cell centres lie on the faces (t = 0) or one cell away (t = 1).  Links, q and face ids
+    against the oracle, ties checked."""
+    v, f = geomgen.box_mesh((lo,) * 3, (hi,) * 3)
+    for Q in (19, 27):
+        wl = geomgen.Workload(f"box-Q{Q}", 3, v, f, (4, 4, 4), 3, 16, Q)
+        g, of, lk = _full(orc, wl)
+        qs = lk.q[lk.face >= 0]
+        log(f"  q = 0: {int((qs == 0).sum())}, q = 1: {int((qs == 1).sum())}")
+
+
+def test_square_links_2d_exact(orc):
+    """2D: an axis-aligned square of 4 segments with dyadic corners on finest-level cell centres (exact
+    ties at the corners, den == 0 for links along a side, t = 0 and t = 1)."""
+    v, f = geomgen.square_loop((81 / 256, 81 / 256), (175 / 256, 175 / 256))
+    wl = geomgen.Workload("square", 2, v, f, (4, 4, 1), 3, 16, 9)
+    _full(orc, wl)
+
+
+def test_degenerate_faces(orc):
+    """Zero-area triangles mixed into a soup: all three corners equal, two equal, and three distinct
+    (nearly) collinear corners.  Bins, flags, links and q against the oracle (a degenerate face meets the
+    separating-axis test through its box axes and edge axes only, and links through it have det == 0)."""
+    v, f = geomgen.random_triangles(240, 12, 0.1, 0.9, 0.08)
+    v = v.reshape(-1, 3, 3).copy()
+    v[0::4, 1] = v[0::4, 0]                               # two corners equal
+    v[1::4, 1] = v[1::4, 0]
+    v[1::4, 2] = v[1::4, 0]                               # all three equal
+    v[2::4, 2] = v[2::4, 0] + np.float32(2.0) * (v[2::4, 1] - v[2::4, 0])   # collinear up to FP32 rounding
+    wl = geomgen.Workload("degenerate", 3, v.reshape(-1, 3).astype(np.float32), f, (3, 3, 3), 2, 8, 27)
+    _full(orc, wl)
+    v2, f2 = geomgen.random_segments(120, 13, 0.1, 0.9, 0.08)
+    v2 = v2.reshape(-1, 2, 2).copy()
+    v2[0::3, 1] = v2[0::3, 0]                             # zero-length segments
+    wl2 = geomgen.Workload("degenerate-2d", 2, v2.reshape(-1, 2), f2, (4, 4, 1), 3, 8, 9)
+    _full(orc, wl2)
 
 
 def _max_adjoint_queue(face, w, tile=256, waves=4, group=4, lanes=64):
@@ -153,7 +216,8 @@ def test_zero_levels(orc):
     _check_links(rep)
 
 
-def test_sphere_c1_bins_flags_exact_and_sampled_q(orc):
+def test_sphere_c1_full(orc):
+    """The 20,480-face sphere in full: bins and flags bit-exact, every finest-level block's links."""
     wl = geomgen.workload("C1")
     log(f"case C1: faces {len(wl.faces)}")
     g = gpu_run(wl)
@@ -162,11 +226,8 @@ def test_sphere_c1_bins_flags_exact_and_sampled_q(orc):
     compare_bins(g, ob)
     of = orc.refine(3, coords, ob, wl.roots, wl.levels, wl.d_spec(), (0, 0, 0), (1, 1, 1))
     compare_forest(g, of, wl.levels)
-    nL = len(of.levels[wl.levels]["keys"])
-    rng = np.random.default_rng(7)
-    sub = np.sort(rng.choice(nL, size=min(nL, 2500), replace=False))
-    lk = orc.link_fractions(3, coords, ob, of, wl.lattice, subset=sub)
-    rep, arrs = compare_links(g, lk, restrict_blocks=of.levels[wl.levels]["keys"][sub])
+    lk = orc.link_fractions(3, coords, ob, of, wl.lattice)
+    rep, arrs = compare_links(g, lk)
     _check_links(rep)
     nd, bad = check_face_ties(orc, of, coords, wl.lattice, *arrs)
     log(f"  face ids differing at ties: {nd}, not a tie: {bad}")
@@ -238,3 +299,106 @@ def test_run_twice_bitwise_equal(orc):
     for la, lb in zip(a["levels"], b["levels"]):
         for k in ("keys", "leaf", "mark"):
             assert np.array_equal(la[k], lb[k])
+
+
+def _adjoint_2d_case(orc, wl):
+    import torch
+    g, of, lk = _full(orc, wl)
+    coords = orc.gather(2, wl.vertices, wl.faces)
+    comp, norm, w = _adjoint_all_links(orc, wl, g, of, lk, coords)
+    log(f"  2D adjoint, {int((w != 0).sum())} links weighted: max component rel {comp:.2e}, norm rel {norm:.2e}")
+    assert comp <= 1e-3 and norm <= 1e-4
+    return g, of, lk, coords
+
+
+def test_adjoint_2d_against_oracle(orc):
+    """D2Q9 backward: every link of the circle and of a segment soup weighted, against the FP64 adjoint
+    (pinned by the closed-form segment and 2D finite differences)."""
+    _adjoint_2d_case(orc, geomgen.workload("C0"))
+    v, f = geomgen.random_segments(200, 10, 0.05, 0.95, 0.1)
+    _adjoint_2d_case(orc, geomgen.Workload("rseg", 2, v, f, (5, 3, 1), 3, 9, 9))
+
+
+def test_adjoint_2d_against_finite_differences(orc):
+    """Jittered 96-segment circle: the GPU's D2Q9 gradient on the links stable under the step against
+    central differences of the FP64 oracle at h = 1e-5."""
+    import torch
+    n = 96
+    th = 2 * np.pi * np.arange(n) / n
+    v64 = geomgen.jitter_fp64(np.stack([0.5 + 0.25 * np.cos(th), 0.5 + 0.25 * np.sin(th)], 1), 1e-3, 1)
+    v = v64.astype(np.float32)
+    f = np.stack([np.arange(n), (np.arange(n) + 1) % n], 1).astype(np.int32)
+    wl = geomgen.Workload("j2", 2, v, f, (4, 4, 1), 3, 16, 9)
+    g = gpu_run(wl)
+    r = orc.run_plain(wl)
+    fo, lk, bins, coords = r["forest"], r["links"], r["bins"], r["coords"]
+    assert np.array_equal(g["key"], lk.key)
+    stable = orc.link_stable(fo, lk, coords, bins, h=1e-5)
+    w = geomgen.weights(lk.n * 9, 2).astype(np.float64).reshape(lk.n, 9)
+    w[~stable | (g["face"] != lk.face)] = 0.0
+    geom, bins_h, forest_h, links_h = g["handles"]
+    grad = links_h.backward(torch.from_numpy(w.astype(np.float32)).cuda()).cpu().numpy().astype(np.float64)
+    fd, nch = orc.fd_grad(fo, lk, wl.vertices, wl.faces, bins, w, h=1e-5)
+    assert nch == 0
+    err = np.abs(grad - fd)
+    scale = np.maximum(np.abs(fd), 1e-2 * np.abs(fd).max())
+    comp = float((err / scale).max())
+    norm = float(np.linalg.norm(grad - fd) / np.linalg.norm(fd))
+    log(f"  2D GPU vs FD h=1e-5 on {int((w != 0).sum())} stable links: max component {comp:.2e}, norm {norm:.2e}")
+    assert comp <= 1e-3 and norm <= 1e-3
+
+
+def test_error_conventions():
+    """The plain calls reject invalid input with AGAL_EINVAL and leave no handle behind: a NaN or an Inf
+    coordinate, a face index out of range, an unknown lattice or one that does not match the dimension,
+    B < 1, hi <= lo, a negative distance and a key space overflow."""
+    import torch
+    import paper_2502_16310_amd as agal
+    dev = torch.device("cuda", 0)
+    ctx = agal.agal_context_create()
+    stream = torch.cuda.current_stream().cuda_stream
+    v, f = geomgen.icosphere(1, 0.2)
+
+    def imp(vv, ff, dim=3):
+        vt = torch.from_numpy(np.ascontiguousarray(vv)).to(dev)
+        ft = torch.from_numpy(np.ascontiguousarray(ff)).to(dev)
+        return agal.agal_import_faces(ctx, dim, vt.data_ptr(), vt.shape[0], ft.data_ptr(), ft.shape[0], stream)
+
+    def einval(fn, what):
+        with pytest.raises(agal.AgalError) as e:
+            fn()
+        assert e.value.status == agal.AGAL_EINVAL, (what, e.value)
+        log(f"  {what}: {e.value}")
+
+    for bad in (np.nan, np.inf, -np.inf):
+        vb = v.copy()
+        vb[7, 1] = bad
+        einval(lambda: imp(vb, f), f"vertex coordinate {bad}")
+    fb = f.copy()
+    fb[3, 2] = len(v)
+    einval(lambda: imp(v, fb), "index == n_vertices")
+    fb[3, 2] = -1
+    einval(lambda: imp(v, fb), "negative index")
+    einval(lambda: imp(v, f, dim=4), "dim 4")
+    g = imp(v, f)   # the context is still usable after the failures
+    einval(lambda: agal.agal_bin_faces(g, (0, 0, 0), (1, 1, 1), 0, stream), "B = 0")
+    einval(lambda: agal.agal_bin_faces(g, (0, 0, 0), (1, 0, 1), 8, stream), "hi <= lo")
+    b = agal.agal_bin_faces(g, (0, 0, 0), (1, 1, 1), 8, stream)
+    einval(lambda: agal.agal_near_wall_refine(g, b, agal.forest_desc(3, (4, 4, 4), 2, [0.01, -0.01], (0, 0, 0),
+                                                                      (1, 1, 1)), stream), "negative d_spec")
+    einval(lambda: agal.agal_near_wall_refine(g, b, agal.forest_desc(2, (4, 4), 2, [0.01, 0.01], (0, 0), (1, 1)),
+                                              stream), "forest dim 2 over 3D faces")
+    einval(lambda: agal.agal_near_wall_refine(g, b, agal.forest_desc(3, (1024, 1024, 1024), 2, [0.01, 0.01],
+                                                                      (0, 0, 0), (1, 1, 1)), stream),
+           "key space overflow")
+    fo = agal.agal_near_wall_refine(g, b, agal.forest_desc(3, (4, 4, 4), 2, [1 / 16, 1 / 32], (0, 0, 0), (1, 1, 1)),
+                                    stream)
+    einval(lambda: agal.agal_link_fractions(g, b, fo, agal.AGAL_D2Q9, stream), "D2Q9 on a 3D forest")
+    einval(lambda: agal.agal_link_fractions(g, b, fo, 15, stream), "unknown lattice")
+    lk = agal.agal_link_fractions(g, b, fo, agal.AGAL_D3Q19, stream)
+    assert agal.agal_links_view(lk)[3] > 0
+    for h, fn in ((lk, agal.agal_destroy_links), (fo, agal.agal_destroy_forest), (b, agal.agal_destroy_bins),
+                  (g, agal.agal_destroy_geom)):
+        fn(h)
+    agal.agal_context_destroy(ctx)
+    torch.cuda.synchronize()
