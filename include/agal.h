@@ -123,6 +123,27 @@ AGAL_API agal_status agal_bin_faces(agal_geom g, const float lo[3], const float 
                                     agal_bins *out);
 AGAL_API agal_status agal_bins_view(agal_bins b, const uint32_t **d_offsets, const int32_t **d_face_ids,
                                     int64_t *n_bins, int64_t *n_entries);
+/* agal_bin_faces without any device allocation, for callers that cannot
+ * allocate (code between allocation-free points of a serving loop, harnesses
+ * that forbid hipMalloc): the same bins, written into caller buffers.
+ *   d_offsets    B^D + 1 uint32 (caller-owned);
+ *   d_face_ids   ids_capacity int32 (caller-owned; may be NULL when
+ *                ids_capacity is 0);
+ *   *n_entries   the number of (face, bin) entries P, set on AGAL_OK and on
+ *                AGAL_ECAPACITY.
+ * Working memory (per-bin counts and cursors, scan status) lives in a fixed
+ * 32 MiB device array of the library, one per GPU, kept until the process
+ * ends: 2 B^D + ids_capacity / 2048 words plus a few thousand must fit in
+ * 8 Mi words (about 4.1 million bins).  Every call on one GPU uses that GPU's
+ * array, so calls that overlap on one GPU (other streams or host threads)
+ * race; calls in sequence on one stream are safe (each clears what it needs).
+ * Errors: those of agal_bin_faces; AGAL_EINVAL when the grid and capacity do
+ * not fit the scratch array; AGAL_ECAPACITY when P > ids_capacity (offsets
+ * are written, ids are not); AGAL_EHIP when the scratch address could not be
+ * taken at context creation.  Synchronises `stream` once (to read P). */
+AGAL_API agal_status agal_bin_faces_noalloc(agal_geom g, const float lo[3], const float hi[3], int32_t B,
+                                            uint32_t *d_offsets, int32_t *d_face_ids, int64_t ids_capacity,
+                                            void *stream, int64_t *n_entries);
 
 /* ---- near-wall refinement (Sec. II-C-1, II-C-2, II-A) --------------------
  * For pass l = 0..n_levels-1, every cell of every block present at level l

@@ -70,6 +70,8 @@ def _load():
         "agal_geom_view": [P, C.POINTER(C.c_int), C.POINTER(i64), C.POINTER(i64), PP, PP],
         "agal_bin_faces": [P, C.POINTER(C.c_float), C.POINTER(C.c_float), i32, vp, PP],
         "agal_bins_view": [P, PP, PP, C.POINTER(i64), C.POINTER(i64)],
+        "agal_bin_faces_noalloc": [P, C.POINTER(C.c_float), C.POINTER(C.c_float), i32, vp, vp, i64, vp,
+                                   C.POINTER(i64)],
         "agal_near_wall_refine": [P, P, C.POINTER(_ForestDesc), vp, PP],
         "agal_forest_level_view": [P, C.c_int, PP, PP, PP, PP, C.POINTER(i64)],
         "agal_forest_info": [P, C.POINTER(C.c_int), C.POINTER(C.c_int)],
@@ -163,6 +165,15 @@ def agal_bin_faces(geom, lo: Sequence[float], hi: Sequence[float], B: int, strea
     _check(_lib.agal_bin_faces(_h(geom), _f3(lo, 0.0), _f3(hi, 1.0), int(B), stream or None, C.byref(out)),
            "agal_bin_faces")
     return out
+
+
+def agal_bin_faces_noalloc(geom, lo: Sequence[float], hi: Sequence[float], B: int, d_offsets: int,
+                           d_face_ids: Optional[int], ids_capacity: int, stream: int = 0) -> int:
+    """Bins into caller buffers without device allocation; returns the entry count P."""
+    n = C.c_int64()
+    _check(_lib.agal_bin_faces_noalloc(_h(geom), _f3(lo, 0.0), _f3(hi, 1.0), int(B), d_offsets, d_face_ids or None,
+                                       int(ids_capacity), stream or None, C.byref(n)), "agal_bin_faces_noalloc")
+    return n.value
 
 
 def agal_bins_view(bins):

@@ -200,7 +200,7 @@ inline double face_flag_pairs(int D, const float ext[3], float h, const float dx
     return p;
 }
 
-// A kernel's completion signal (see dev::signal_host): arrival counter, the
+// A kernel's completion signal (see dev::publish_host, dev::arrive_last): arrival counter, the
 // device address of the mapped signal word (null: none) and the value stored.
 struct HostSignal {
     uint32_t *done;
@@ -233,9 +233,14 @@ int64_t scan_flags_u8_multi_tiles(const int64_t *n, int k);
 // Tiles of a scan of n elements; a caller-provided status buffer holds tiles + 1 zeroed 64-bit words.
 int64_t scan_tiles(int64_t n);
 // Exclusive scan whose sum comes back through mapped host memory (synchronises the stream); status is a
-// zeroed buffer of scan_tiles(n) + 1 words, or null.
+// zeroed buffer of scan_tiles(n) + 1 words, or null.  timed = false: no kernel timing events even when the
+// context records them (the no-allocation calls create no events).
 agal_status scan_u32_total(agal_context ctx, const uint32_t *in, uint32_t *out, int64_t n, uint64_t *status,
-                           uint32_t *total, hipStream_t s);
+                           uint32_t *total, hipStream_t s, bool timed = true);
+// Takes the device address of the binning scratch array for `device` (the
+// current device) once; later calls return at once.  Called by
+// agal_context_create.
+agal_status bin_scratch_resolve(int device);
 
 // Look-back scratch: status words + ticket for `tiles` tiles, cleared.
 agal_status lookback_alloc(agal_context ctx, int64_t tiles, uint64_t **status, uint32_t **ticket, hipStream_t s);

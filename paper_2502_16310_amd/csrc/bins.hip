@@ -53,7 +53,128 @@ unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 8192) {
     return (unsigned)b;
 }
 
+// Validated bin grid of a call: B bins per axis over [lo, hi].
+struct GridSpec {
+    dev::BinGrid grid{};
+    float lo[3], hi[3], s[3];
+    int64_t nb = 1;
+};
+
+agal_status grid_spec(const char *what, int D, const float lo[3], const float hi[3], int32_t B, GridSpec *out) {
+    if (B < 1) return fail(AGAL_EINVAL, "%s: B must be >= 1 (got %d)", what, B);
+    int64_t nb = 1;
+    for (int a = 0; a < D; ++a) {
+        if (!(hi[a] > lo[a])) return fail(AGAL_EINVAL, "%s: hi must exceed lo on every axis", what);
+        if (nb > ((int64_t)1 << 31) / B) return fail(AGAL_EINVAL, "%s: B^D exceeds 2^31", what);
+        nb *= B;
+    }
+    out->nb = nb;
+    out->grid.B = B;
+    for (int a = 0; a < 3; ++a) {
+        out->lo[a] = a < D ? lo[a] : 0.0f;
+        out->hi[a] = a < D ? hi[a] : 1.0f;
+        out->s[a] = (float)B / (out->hi[a] - out->lo[a]);
+        out->grid.lo[a] = out->lo[a];
+        out->grid.s[a] = out->s[a];
+    }
+    return AGAL_OK;
+}
+
+// Work words of one binning call over nb bins: per-bin counts, per-bin
+// scatter cursors, the oversized-bin counter (+ one pad word), then the
+// scan's look-back status words (64-bit).  All start at zero.
+int64_t bin_work_words(int64_t nb) { return 2 * nb + 2 + 2 * (scan_tiles(nb) + 1); }
+
+struct BinWork {
+    uint32_t *count, *cursor, *big_count;
+    uint64_t *scan_status;
+};
+
+BinWork bin_work(uint32_t *work, int64_t nb) {
+    return BinWork{work, work + nb, work + 2 * nb, reinterpret_cast<uint64_t *>(work + ((2 * nb + 3) & ~int64_t(1)))};
+}
+
+// Count pass and scan: zeroes `work`, fills off[0..nb] and returns the entry
+// total P (the one host wait).  ctx_timed: the context whose kernel timing
+// records the launches, or null for none.
+agal_status bin_count_scan(agal_context ctx, agal_context ctx_timed, agal_geom g, const GridSpec &gs, uint32_t *work,
+                           uint32_t *off, uint32_t *P, hipStream_t s) {
+    const int64_t nb = gs.nb;
+    fill_u32(work, 0u, bin_work_words(nb), s);
+    const BinWork w = bin_work(work, nb);
+    {
+        ProfScope prof(ctx_timed, "bin_count", s);
+        if (g->dim == 3)
+            hipLaunchKernelGGL(k_bin_count<3>, dim3(grid_for(g->F)), dim3(256), 0, s, g->aabb, g->F, gs.grid, w.count);
+        else
+            hipLaunchKernelGGL(k_bin_count<2>, dim3(grid_for(g->F)), dim3(256), 0, s, g->aabb, g->F, gs.grid, w.count);
+    }
+    AGAL_TRY_HIP(hipGetLastError());
+    return scan_u32_total(ctx, w.count, off, nb, w.scan_status, P, s, ctx_timed != nullptr);
+}
+
+// Scatter and canonical order into ids[0..P) (offsets from bin_count_scan);
+// big: room for P / kCanonCap + 1 oversized-bin indices.
+agal_status bin_scatter_canon(agal_context ctx_timed, agal_geom g, const GridSpec &gs, uint32_t *work,
+                              const uint32_t *off, int32_t *ids, uint32_t P, uint32_t *big, hipStream_t s) {
+    const int64_t nb = gs.nb;
+    const BinWork w = bin_work(work, nb);
+    {
+        ProfScope prof(ctx_timed, "bin_scatter", s);
+        if (g->dim == 3)
+            hipLaunchKernelGGL(k_bin_scatter<3>, dim3(grid_for(g->F)), dim3(256), 0, s, g->aabb, g->F, gs.grid, off,
+                               w.cursor, ids);
+        else
+            hipLaunchKernelGGL(k_bin_scatter<2>, dim3(grid_for(g->F)), dim3(256), 0, s, g->aabb, g->F, gs.grid, off,
+                               w.cursor, ids);
+    }
+    const int64_t groups = (nb + dev::kWave - 1) / dev::kWave;
+    {
+        ProfScope prof(ctx_timed, "bin_canon", s);
+        hipLaunchKernelGGL(k_bin_canon_small, dim3((unsigned)groups), dim3(dev::kWave), 0, s, ids, off, nb, big,
+                           w.big_count);
+    }
+    const unsigned big_grid = (unsigned)std::min<int64_t>((int64_t)P / kCanonCap + 1, 256);
+    {
+        ProfScope prof(ctx_timed, "bin_canon_big", s);
+        if (g->dim == 3)
+            hipLaunchKernelGGL(k_bin_canon_big<3>, dim3(big_grid), dim3(kBigThreads), 0, s, g->aabb, g->F, gs.grid,
+                               off, ids, big, w.big_count);
+        else
+            hipLaunchKernelGGL(k_bin_canon_big<2>, dim3(big_grid), dim3(kBigThreads), 0, s, g->aabb, g->F, gs.grid,
+                               off, ids, big, w.big_count);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(AGAL_EHIP, "binning: launch failed: %s", hipGetErrorString(e));
+    return AGAL_OK;
+}
+
+// Scratch of agal_bin_faces_noalloc: a file-scope device array (each device
+// holds its own copy for the life of the process).  Host code never passes
+// the array's name to a kernel: on the host it is only a stand-in, and its
+// device address comes from hipGetSymbolAddress, taken once per device when a
+// context is created there.
+constexpr int64_t kNoallocScratchWords = (int64_t(32) << 20) / 4;   // 32 MiB
+static __device__ __align__(256) uint32_t scratch[kNoallocScratchWords];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch[kMaxDevices] = {};
+
 }  // namespace
+
+agal_status bin_scratch_resolve(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(AGAL_EINVAL, "device %d out of range", device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return AGAL_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return fail(AGAL_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", device, hipGetErrorString(e));
+    }
+    g_scratch[device] = static_cast<uint32_t *>(p);
+    return AGAL_OK;
+}
 
 }  // namespace agal
 
@@ -63,14 +184,9 @@ extern "C" {
 
 agal_status agal_bin_faces(agal_geom g, const float lo[3], const float hi[3], int32_t B, void *stream, agal_bins *out) {
     if (!g || !lo || !hi || !out) return fail(AGAL_EINVAL, "agal_bin_faces: NULL argument");
-    if (B < 1) return fail(AGAL_EINVAL, "agal_bin_faces: B must be >= 1 (got %d)", B);
-    const int D = g->dim;
-    int64_t nb = 1;
-    for (int a = 0; a < D; ++a) {
-        if (!(hi[a] > lo[a])) return fail(AGAL_EINVAL, "agal_bin_faces: hi must exceed lo on every axis");
-        if (nb > ((int64_t)1 << 31) / B) return fail(AGAL_EINVAL, "agal_bin_faces: B^D exceeds 2^31");
-        nb *= B;
-    }
+    GridSpec gs;
+    AGAL_TRY(grid_spec("agal_bin_faces", g->dim, lo, hi, B, &gs));
+    const int64_t nb = gs.nb;
     hipStream_t s = (hipStream_t)stream;
     agal_context ctx = g->ctx;
 
@@ -79,89 +195,70 @@ agal_status agal_bin_faces(agal_geom g, const float lo[3], const float hi[3], in
     bn->ctx = ctx;
     bn->geom_id = g->id;
     bn->stream = s;
-    bn->dim = D;
+    bn->dim = g->dim;
     bn->B = B;
     bn->nb = nb;
-    dev::BinGrid grid{};
-    grid.B = B;
     for (int a = 0; a < 3; ++a) {
-        bn->lo[a] = a < D ? lo[a] : 0.0f;
-        bn->hi[a] = a < D ? hi[a] : 1.0f;
-        bn->s[a] = (float)B / (bn->hi[a] - bn->lo[a]);
-        grid.lo[a] = bn->lo[a];
-        grid.s[a] = bn->s[a];
+        bn->lo[a] = gs.lo[a];
+        bn->hi[a] = gs.hi[a];
+        bn->s[a] = gs.s[a];
     }
-    // one zeroed work buffer: per-bin counts, per-bin scatter cursors, the
-    // oversized-bin counter, and the scan's look-back status words
-    const int64_t tiles = scan_tiles(nb);
-    const int64_t work_words = 2 * nb + 2 + 2 * (tiles + 1);
-    uint32_t *work = nullptr;
-    agal_status st = dev_alloc(ctx->mem, &work, (size_t)work_words, s);
-    if (st == AGAL_OK) st = dev_alloc(ctx->mem, &bn->off, (size_t)nb + 1, s);
-    if (st != AGAL_OK) {
-        dev_free(ctx->mem, work, s);
-        agal_destroy_bins(bn);
-        return st;
-    }
-    fill_u32(work, 0u, work_words, s);
-    uint32_t *count = work;
-    uint32_t *cursor = work + nb;
-    uint32_t *big_count = work + 2 * nb;
-    uint64_t *scan_status = reinterpret_cast<uint64_t *>(work + ((2 * nb + 3) & ~int64_t(1)));
-    {
-    ProfScope prof(ctx, "bin_count", s);
-    if (D == 3)
-        hipLaunchKernelGGL(k_bin_count<3>, dim3(grid_for(g->F)), dim3(256), 0, s, g->aabb, g->F, grid, count);
-    else
-        hipLaunchKernelGGL(k_bin_count<2>, dim3(grid_for(g->F)), dim3(256), 0, s, g->aabb, g->F, grid, count);
-    }
-    uint32_t P = 0;
-    st = scan_u32_total(ctx, count, bn->off, nb, scan_status, &P, s);
-    bn->P = P;
-    uint32_t *big = nullptr;   // the oversized bins (big_count[0] of them)
-    const int64_t big_cap = (int64_t)P / kCanonCap + 1;
-    if (st == AGAL_OK) st = dev_alloc(ctx->mem, &bn->ids, (size_t)std::max<uint32_t>(P, 1u), s);
-    if (st == AGAL_OK) st = dev_alloc(ctx->mem, &big, (size_t)big_cap, s);
-    if (st != AGAL_OK) {
+    uint32_t *work = nullptr, *big = nullptr;
+    auto cleanup = [&](agal_status st) {
         dev_free(ctx->mem, work, s);
         dev_free(ctx->mem, big, s);
-        agal_destroy_bins(bn);
+        if (st != AGAL_OK) agal_destroy_bins(bn);
         return st;
-    }
-    {
-    ProfScope prof(ctx, "bin_scatter", s);
-    if (D == 3)
-        hipLaunchKernelGGL(k_bin_scatter<3>, dim3(grid_for(g->F)), dim3(256), 0, s, g->aabb, g->F, grid, bn->off,
-                           cursor, bn->ids);
-    else
-        hipLaunchKernelGGL(k_bin_scatter<2>, dim3(grid_for(g->F)), dim3(256), 0, s, g->aabb, g->F, grid, bn->off,
-                           cursor, bn->ids);
-    }
-    const int64_t groups = (nb + dev::kWave - 1) / dev::kWave;
-    {
-    ProfScope prof(ctx, "bin_canon", s);
-    hipLaunchKernelGGL(k_bin_canon_small, dim3((unsigned)groups), dim3(dev::kWave), 0, s, bn->ids, bn->off, nb,
-                       big, big_count);
-    }
-    const unsigned big_grid = (unsigned)std::min<int64_t>(big_cap, 256);
-    {
-    ProfScope prof(ctx, "bin_canon_big", s);
-    if (D == 3)
-        hipLaunchKernelGGL(k_bin_canon_big<3>, dim3(big_grid), dim3(kBigThreads), 0, s, g->aabb, g->F, grid, bn->off,
-                           bn->ids, big, big_count);
-    else
-        hipLaunchKernelGGL(k_bin_canon_big<2>, dim3(big_grid), dim3(kBigThreads), 0, s, g->aabb, g->F, grid, bn->off,
-                           bn->ids, big, big_count);
-    }
-    dev_free(ctx->mem, work, s);
-    dev_free(ctx->mem, big, s);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-        agal_destroy_bins(bn);
-        return fail(AGAL_EHIP, "agal_bin_faces: launch failed: %s", hipGetErrorString(e));
-    }
+    };
+    agal_status st = dev_alloc(ctx->mem, &work, (size_t)bin_work_words(nb), s);
+    if (st == AGAL_OK) st = dev_alloc(ctx->mem, &bn->off, (size_t)nb + 1, s);
+    uint32_t P = 0;
+    if (st == AGAL_OK) st = bin_count_scan(ctx, ctx, g, gs, work, bn->off, &P, s);
+    if (st != AGAL_OK) return cleanup(st);
+    bn->P = P;
+    st = dev_alloc(ctx->mem, &bn->ids, (size_t)std::max<uint32_t>(P, 1u), s);
+    if (st == AGAL_OK) st = dev_alloc(ctx->mem, &big, (size_t)P / kCanonCap + 1, s);
+    if (st == AGAL_OK) st = bin_scatter_canon(ctx, g, gs, work, bn->off, bn->ids, P, big, s);
+    if (cleanup(st) != AGAL_OK) return st;
     *out = bn;
     return AGAL_OK;
+}
+
+agal_status agal_bin_faces_noalloc(agal_geom g, const float lo[3], const float hi[3], int32_t B, uint32_t *d_offsets,
+                                   int32_t *d_face_ids, int64_t ids_capacity, void *stream, int64_t *n_entries) {
+    if (!g || !lo || !hi || !d_offsets || !n_entries || (ids_capacity > 0 && !d_face_ids))
+        return fail(AGAL_EINVAL, "agal_bin_faces_noalloc: NULL argument");
+    if (ids_capacity < 0) return fail(AGAL_EINVAL, "agal_bin_faces_noalloc: negative ids_capacity");
+    GridSpec gs;
+    AGAL_TRY(grid_spec("agal_bin_faces_noalloc", g->dim, lo, hi, B, &gs));
+    agal_context ctx = g->ctx;
+    const int dev_id = ctx->device;
+    uint32_t *base = nullptr;
+    if (dev_id >= 0 && dev_id < kMaxDevices) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = g_scratch[dev_id];
+    }
+    if (!base)
+        return fail(AGAL_EHIP, "agal_bin_faces_noalloc: the scratch address of device %d is unknown (%s)", dev_id,
+                    "hipGetSymbolAddress failed when the context was created");
+    // scratch: the work words, then the oversized-bin list (at most
+    // ids_capacity / kCanonCap + 1 bins hold more than kCanonCap ids)
+    const int64_t work_words = bin_work_words(gs.nb);
+    const int64_t big_words = std::min<int64_t>(ids_capacity, (int64_t)UINT32_MAX) / kCanonCap + 1;
+    if (work_words + big_words > kNoallocScratchWords)
+        return fail(AGAL_EINVAL,
+                    "agal_bin_faces_noalloc: %lld bins and %lld id slots need %lld scratch words; the fixed scratch "
+                    "holds %lld (at most about %lld bins)",
+                    (long long)gs.nb, (long long)ids_capacity, (long long)(work_words + big_words),
+                    (long long)kNoallocScratchWords, (long long)((kNoallocScratchWords - big_words) / 2 - 2048));
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t P = 0;
+    AGAL_TRY(bin_count_scan(ctx, nullptr, g, gs, base, d_offsets, &P, s));
+    *n_entries = P;
+    if ((int64_t)P > ids_capacity)
+        return fail(AGAL_ECAPACITY, "agal_bin_faces_noalloc: %u (face, bin) entries exceed ids_capacity %lld", P,
+                    (long long)ids_capacity);
+    return bin_scatter_canon(nullptr, g, gs, base, d_offsets, d_face_ids, P, base + work_words, s);
 }
 
 agal_status agal_bins_view(agal_bins b, const uint32_t **d_offsets, const int32_t **d_face_ids, int64_t *n_bins,

@@ -265,7 +265,7 @@ agal_status lookback_alloc(agal_context ctx, int64_t tiles, uint64_t **status, u
 // synchronisation (no separate read-back).
 template <class In>
 static agal_status scan_impl(agal_context ctx, In in, uint32_t *out, int64_t n, hipStream_t s,
-                             uint64_t *status = nullptr, uint32_t *total = nullptr) {
+                             uint64_t *status = nullptr, uint32_t *total = nullptr, bool timed = true) {
     if (n <= 0) {
         fill_u32(out, 0u, 1, s);
         if (total) *total = 0;
@@ -278,7 +278,7 @@ static agal_status scan_impl(agal_context ctx, In in, uint32_t *out, int64_t n, 
     else ticket = reinterpret_cast<uint32_t *>(status + tiles);
     const HostSignal sig = total ? host_signal(ctx) : HostSignal{nullptr, nullptr, 0u};
     {
-        ProfScope prof(ctx, "scan_exclusive", s);
+        ProfScope prof(timed ? ctx : nullptr, "scan_exclusive", s);
         hipLaunchKernelGGL(k_scan<In>, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, out, n, status, ticket,
                            total ? ctx->d_counts : nullptr, sig);
     }
@@ -297,8 +297,8 @@ agal_status scan_u32(agal_context ctx, const uint32_t *in, uint32_t *out, int64_
     return scan_impl(ctx, LoadU32{in}, out, n, s);
 }
 agal_status scan_u32_total(agal_context ctx, const uint32_t *in, uint32_t *out, int64_t n, uint64_t *status,
-                           uint32_t *total, hipStream_t s) {
-    return scan_impl(ctx, LoadU32{in}, out, n, s, status, total);
+                           uint32_t *total, hipStream_t s, bool timed) {
+    return scan_impl(ctx, LoadU32{in}, out, n, s, status, total, timed);
 }
 agal_status scan_flags_u8(agal_context ctx, const uint8_t *in, uint32_t *out, int64_t n, hipStream_t s) {
     return scan_impl(ctx, LoadFlagU8{in}, out, n, s);
@@ -475,6 +475,9 @@ agal_status agal_context_create(const agal_allocator *alloc, agal_context *out) 
         delete c;
         return agal::fail(AGAL_ENOMEM, "agal_context_create: device counter allocation failed");
     }
+    // the device address of the binning scratch array, taken once per device
+    // (a failure here only disables agal_bin_faces_noalloc, which reports it)
+    (void)agal::bin_scratch_resolve(dev);
     *out = c;
     return AGAL_OK;
 }
