@@ -205,6 +205,18 @@ AGAL_API agal_status agal_link_fractions(agal_geom g, agal_bins b, agal_forest f
                                          agal_links *out);
 AGAL_API agal_status agal_links_view(agal_links l, const uint64_t **d_node_key, const float **d_q,
                                      const int32_t **d_face, int64_t *n_nodes, int *Q);
+/* How agal_link_fractions finds each finest-level block's candidate faces
+ * (the results are identical either way).  List mode: every face lists the
+ * blocks whose link box its bounding box meets (face-side, a few blocks per
+ * face), then one pass finds the cells that have a link and a second writes
+ * each node's row at its final place.  Walk mode: each block walks the bins
+ * under it, and nodes are staged per block and compacted.  A call takes list
+ * mode while the geometry's largest face (box extent per axis, measured at
+ * import) has at most max_blocks_per_face candidate blocks at the finest
+ * level; default 512, 0 selects walk mode always.  Applies to calls made with
+ * ctx afterwards.
+ * Errors: AGAL_EINVAL for a NULL context or a negative limit. */
+AGAL_API agal_status agal_context_set_link_list_limit(agal_context ctx, int64_t max_blocks_per_face);
 
 /* ---- adjoint ---------------------------------------------------------------
  * Accumulates dL/d(vertex) for L = sum over link slots of grad_q * q:

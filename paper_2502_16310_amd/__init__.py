@@ -81,6 +81,7 @@ def _load():
         "agal_lattice_vectors": [C.c_int, C.POINTER(i32)],
         "agal_profile_enable": [P, C.c_int],
         "agal_context_set_flag_table_limit": [P, C.c_int64],
+        "agal_context_set_link_list_limit": [P, C.c_int64],
         "agal_profile_read": [P, C.c_int, C.POINTER(C.c_char_p), C.POINTER(i64), C.POINTER(C.c_double),
                               C.POINTER(C.c_int)],
         "agal_batch_plan_create": [P, C.c_int, C.POINTER(_BodyDesc), C.POINTER(_TuneOpts), vp, PP],
@@ -247,6 +248,11 @@ def agal_lattice_vectors(lattice: int):
 
 def agal_context_set_flag_table_limit(ctx, max_entries: int):
     _check(_lib.agal_context_set_flag_table_limit(_h(ctx), int(max_entries)), "agal_context_set_flag_table_limit")
+
+
+def agal_context_set_link_list_limit(ctx, max_blocks_per_face: int):
+    _check(_lib.agal_context_set_link_list_limit(_h(ctx), int(max_blocks_per_face)),
+           "agal_context_set_link_list_limit")
 
 
 def agal_profile_enable(ctx, enable: bool = True):

@@ -98,11 +98,10 @@ struct agal_context_t {
     // kernel timing (HIP events around each launch) when enabled
     bool profiling = false;
     int64_t flag_table_max = int64_t(1) << 24;   // agal_context_set_flag_table_limit
+    int64_t link_list_max = 512;                  // agal_context_set_link_list_limit
     // completion signals: a device arrival counter d_done[0] (zero between
     // kernels) and the sequence number last handed out; the signal word is
-    // h_counts[kSyncWord].  d_done[1..5]: device words the import kernel
-    // accumulates and its signal launch moves to mapped memory (zero between
-    // kernels)
+    // h_counts[kSyncWord]
     uint32_t *d_done = nullptr;
     uint32_t sync_seq = 0;
     std::vector<agal::ProfRecord> records;
@@ -237,6 +236,9 @@ int64_t scan_tiles(int64_t n);
 // context records them (the no-allocation calls create no events).
 agal_status scan_u32_total(agal_context ctx, const uint32_t *in, uint32_t *out, int64_t n, uint64_t *status,
                            uint32_t *total, hipStream_t s, bool timed = true);
+// Exclusive scan of the set-bit counts of n 64-bit masks, with the total (synchronises the stream).
+agal_status scan_popc64_total(agal_context ctx, const unsigned long long *masks, uint32_t *out, int64_t n,
+                              uint32_t *total, hipStream_t s);
 // Takes the device address of the binning scratch array for `device` (the
 // current device) once; later calls return at once.  Called by
 // agal_context_create.

@@ -12,12 +12,17 @@
 
 namespace agal {
 
-// Validate and gather in one pass.  err bit 0: a non-finite vertex
-// coordinate; bit 1: a face index outside [0, Nv) (such a face is written as
-// zeros and the call fails).
+// Validate and gather in one pass.  Each workgroup reduces its error bits
+// (bit 0: a non-finite vertex coordinate; bit 1: a face index outside
+// [0, Nv), such a face is written as zeros and the call fails) and its
+// largest face box extent per axis, and stores them in its own four words
+// part[4 b .. 4 b + 3] (extents as float bits, then the error bits): no
+// atomics, which would serialise thousands of workgroups on three addresses.
 template <int D>
-__global__ void k_import(const float *verts, int64_t Nv, const int32_t *faces, int64_t F, float *coords, float *aabb,
-                         float *rec, int32_t *fidx, uint32_t *acc) {
+__global__ __launch_bounds__(256) void k_import(const float *verts, int64_t Nv, const int32_t *faces, int64_t F,
+                                                float *coords, float *aabb, float *rec, int32_t *fidx,
+                                                uint32_t *part) {
+    __shared__ uint32_t s_red[4][256 / dev::kWave];
     uint32_t bad = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -26,29 +31,44 @@ __global__ void k_import(const float *verts, int64_t Nv, const int32_t *faces, i
     float ext[D] = {};
     for (int64_t f = t0; f < F; f += stride)
         bad |= kern::import_face<D>(verts, Nv, faces, F, coords, aabb, rec, fidx, f, ext);
-    // error bits in device words (acc[3], acc[4]), zero before the launch
-    if (bad & 1u) atomicOr(acc + 3, 1u);
-    if (bad & 2u) atomicOr(acc + 4, 1u);
-    // largest face box extent per axis: wave maximum, one atomic per wave on
-    // the (non-negative) float bits in acc[0 .. D)
+    const int w = threadIdx.x / dev::kWave;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         float e = ext[a];
 #pragma unroll
         for (int d = dev::kWave / 2; d >= 1; d >>= 1) e = fmaxf(e, __shfl_xor(e, d, dev::kWave));
-        if (dev::lane_id() == 0) atomicMax(acc + a, __float_as_uint(e));
+        if (dev::lane_id() == 0) s_red[a][w] = __float_as_uint(e);
+    }
+    const uint64_t b1 = __ballot((bad & 1u) != 0), b2 = __ballot((bad & 2u) != 0);
+    if (dev::lane_id() == 0) s_red[3][w] = (b1 ? 1u : 0u) | (b2 ? 2u : 0u);
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        uint32_t r = 0;
+        for (int j = 0; j < 256 / dev::kWave; ++j)
+            r = threadIdx.x == 3 ? (r | s_red[3][j]) : (threadIdx.x < D ? max(r, s_red[threadIdx.x][j]) : 0u);
+        part[4 * (int64_t)blockIdx.x + threadIdx.x] = r;
     }
 }
 
-// After the import kernel (stream order makes its device words final): the
-// error bits to err[0..1] and the extents to err[2..2+D) of mapped host
-// memory, the device words cleared, then the completion signal.
-__global__ void k_import_signal(uint32_t *acc, uint32_t *err, int D, HostSignal sig) {
+// After the import kernel (stream order makes its partial words final): the
+// error bits to err[0..1] and the extents (non-negative float bits, so they
+// order as unsigned) to err[2..2+D) of mapped host memory, then the
+// completion signal.  One workgroup of 256 threads.
+__global__ __launch_bounds__(256) void k_import_signal(const uint32_t *part, int nblk, uint32_t *err, int D,
+                                                       HostSignal sig) {
+    __shared__ uint32_t s_red[4][256];
+    uint32_t r[4] = {0u, 0u, 0u, 0u};
+    for (int b = threadIdx.x; b < nblk; b += 256)
+        for (int k = 0; k < 4; ++k) r[k] = k == 3 ? (r[k] | part[4 * b + k]) : max(r[k], part[4 * b + k]);
+    for (int k = 0; k < 4; ++k) s_red[k][threadIdx.x] = r[k];
+    __syncthreads();
     if (threadIdx.x != 0) return;
-    err[0] = acc[3];
-    err[1] = acc[4];
-    for (int a = 0; a < D; ++a) err[2 + a] = acc[a];
-    for (int i = 0; i < 5; ++i) acc[i] = 0u;
+    uint32_t t[4] = {0u, 0u, 0u, 0u};
+    for (int j = 0; j < 256; ++j)
+        for (int k = 0; k < 4; ++k) t[k] = k == 3 ? (t[k] | s_red[k][j]) : max(t[k], s_red[k][j]);
+    err[0] = t[3] & 1u;
+    err[1] = (t[3] >> 1) & 1u;
+    for (int a = 0; a < D; ++a) err[2 + a] = t[a];
     dev::publish_host(sig.word, sig.seq);
 }
 
@@ -98,17 +118,24 @@ agal_status agal_import_faces(agal_context ctx, int dim, const float *d_vertices
     ctx->h_counts[0] = 0u;
     ctx->h_counts[1] = 0u;
     const HostSignal sig = host_signal(ctx);
+    const unsigned grid = grid_for(std::max(n_vertices * dim, n_faces));
+    uint32_t *part = nullptr;   // four words per workgroup
+    st = dev_alloc(ctx->mem, &part, (size_t)4 * grid, s);
+    if (st != AGAL_OK) {
+        agal_destroy_geom(g);
+        return st;
+    }
     {
         ProfScope prof(ctx, "import", s);
-        const unsigned grid = grid_for(std::max(n_vertices * dim, n_faces));
         if (dim == 3)
             hipLaunchKernelGGL(k_import<3>, dim3(grid), dim3(256), 0, s, d_vertices, n_vertices, d_faces, n_faces,
-                               g->coords, g->aabb, g->rec, g->fidx, ctx->d_done + 1);
+                               g->coords, g->aabb, g->rec, g->fidx, part);
         else
             hipLaunchKernelGGL(k_import<2>, dim3(grid), dim3(256), 0, s, d_vertices, n_vertices, d_faces, n_faces,
-                               g->coords, g->aabb, g->rec, g->fidx, ctx->d_done + 1);
-        hipLaunchKernelGGL(k_import_signal, dim3(1), dim3(64), 0, s, ctx->d_done + 1, err, dim, sig);
+                               g->coords, g->aabb, g->rec, g->fidx, part);
+        hipLaunchKernelGGL(k_import_signal, dim3(1), dim3(256), 0, s, part, (int)grid, err, dim, sig);
     }
+    dev_free(ctx->mem, part, s);
     hipError_t e = hipGetLastError();
     st = e != hipSuccess ? fail(AGAL_EHIP, "agal_import_faces: %s", hipGetErrorString(e))
                          : wait_signal(ctx, s, sig, "agal_import_faces");

@@ -868,24 +868,312 @@ struct LinkArgs {
     float lo[3];
     float dx[3];
     float eps[3];
-    uint64_t *node_key;    // staging rows
+    // Candidate faces per block (list mode): the faces of block b are
+    // list[loff[b] .. loff[b + 1]).  Null: the wave walks the bins under the
+    // block instead.
+    const uint32_t *loff;
+    const int32_t *list;
+    uint32_t list_cap;     // entries allocated for the lists (reads stay below it)
+    uint64_t *node_key;    // node rows (staging rows in walk mode)
     float *q;
     int32_t *face;
 };
 
-// One wave: finest-level blocks first .. first + 64/4^D - 1 of A.  `out` places
-// each block's nodes: out.rows(blk, count) returns the first staging row of the
-// block (and records the count), or -1 when it has no room; rows are written in
-// cell order.
+// Candidate faces staged in LDS by one link wave: vertices (3D: and the FP32
+// normal n = (b - a) x (c - a), |E1|_1, |E2|_1 and S = sum |n_a dx_a|), the
+// face id and the face's near code (one bit per (axis, cell position) of the
+// block it was staged for).
+template <int D, int CAP = kLinkCap>
+struct LinkStaged {
+    static constexpr int NF = D == 3 ? 15 : 4;
+    float f[NF][CAP];
+    int32_t id[CAP];
+    uint32_t code[CAP];
+};
+
+template <int D, int CAP>
+__device__ __forceinline__ void link_stage(LinkStaged<D, CAP> &S, int pos, int32_t f, const float *r, const float dx[3],
+                                           uint32_t code) {
+    S.id[pos] = f;
+    if constexpr (D == 3) {
+        const float *v = r;
+        const float e10 = v[3] - v[0], e11 = v[4] - v[1], e12 = v[5] - v[2];
+        const float e20 = v[6] - v[0], e21 = v[7] - v[1], e22 = v[8] - v[2];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) S.f[k][pos] = v[k];
+        const float n0 = e11 * e22 - e12 * e21;
+        const float n1 = e12 * e20 - e10 * e22;
+        const float n2 = e10 * e21 - e11 * e20;
+        S.f[9][pos] = n0;
+        S.f[10][pos] = n1;
+        S.f[11][pos] = n2;
+        S.f[12][pos] = fabsf(e10) + fabsf(e11) + fabsf(e12);
+        S.f[13][pos] = fabsf(e20) + fabsf(e21) + fabsf(e22);
+        S.f[14][pos] = fabsf(n0 * dx[0]) + fabsf(n1 * dx[1]) + fabsf(n2 * dx[2]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) S.f[k][pos] = r[k];
+    }
+    S.code[pos] = code;
+}
+
+// FP32 filter of staged face j for a link origin o over all direction pairs.
+// With T = o - a, E1 = b - a, E2 = c - a the solution of o + t D = a + u E1 +
+// v E2 is det = D.n, u = D.(T x E2)/det, v = D.(E1 x T)/det, t = -(T.n)/det;
+// T x E2, E1 x T and T.n do not depend on D, and D = c_i dx has entries in
+// {-dx, 0, dx}, so a direction costs a few additions, and the opposite
+// direction has the same u, v and t of the opposite sign; NP direction pairs
+// (directions 1 + 2p, p < NP).  Each quantity carries an absolute rounding
+// error bounded by 2^-21 times the product of the L1 norms of its factors
+// (the direction counted as its largest cell size); margins of 2^-20 times
+// those products are applied.  Returns the pairs that may meet the face (every true hit passes:
+// |t| <= 1 on the face's plane and, unless D.n is too small to have a known
+// sign, barycentrics inside).  With kSure, *sure gets the pairs that
+// certainly meet it (the same tests narrowed by the margins: the exact u, v,
+// 1 - u - v and 1 - |t| are then positive by at least half a margin, so the
+// FP64 decision finds a hit for one of the pair's two directions).
+template <int D, int NP, bool kSure, int CAP>
+__device__ __forceinline__ uint32_t link_filter(const LinkStaged<D, CAP> &S, int j, const float o[3], const float dx[3],
+                                                uint32_t *sure) {
+    uint32_t cm = 0, cs = 0;
+    if constexpr (D == 3) {
+        const float T0 = o[0] - S.f[0][j], T1 = o[1] - S.f[1][j], T2 = o[2] - S.f[2][j];
+        const float e10 = S.f[3][j] - S.f[0][j], e11 = S.f[4][j] - S.f[1][j], e12 = S.f[5][j] - S.f[2][j];
+        const float e20 = S.f[6][j] - S.f[0][j], e21 = S.f[7][j] - S.f[1][j], e22 = S.f[8][j] - S.f[2][j];
+        const float n0 = S.f[9][j], n1 = S.f[10][j], n2 = S.f[11][j];
+        const float n1n = S.f[12][j], n2n = S.f[13][j];
+        const float nT = fabsf(T0) + fabsf(T1) + fabsf(T2);
+        const float mx_ = fmaxf(fmaxf(dx[0], dx[1]), dx[2]) * 9.5367431640625e-07f;  // dx * 2^-20
+        const float MU = mx_ * nT * n2n;
+        const float MV = mx_ * n1n * nT;
+        const float MD = mx_ * n1n * n2n;
+        const float MT = 9.5367431640625e-07f * nT * n1n * n2n;
+        const float p10 = (T1 * e22 - T2 * e21) * dx[0];
+        const float p11 = (T2 * e20 - T0 * e22) * dx[1];
+        const float p12 = (T0 * e21 - T1 * e20) * dx[2];
+        const float p20 = (e11 * T2 - e12 * T1) * dx[0];
+        const float p21 = (e12 * T0 - e10 * T2) * dx[1];
+        const float p22 = (e10 * T1 - e11 * T0) * dx[2];
+        const float d0 = n0 * dx[0], d1 = n1 * dx[1], d2 = n2 * dx[2];
+        const float atn = fabsf((T0 * n0 + T1 * n1) + T2 * n2);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int i = 1 + 2 * p;
+            const int c0 = dir_c<D>(i, 0), c1 = dir_c<D>(i, 1), c2 = dir_c<D>(i, 2);
+            float den = 0.0f, nu = 0.0f, nv = 0.0f;
+            if (c0) { den += c0 > 0 ? d0 : -d0; nu += c0 > 0 ? p10 : -p10; nv += c0 > 0 ? p20 : -p20; }
+            if (c1) { den += c1 > 0 ? d1 : -d1; nu += c1 > 0 ? p11 : -p11; nv += c1 > 0 ? p21 : -p21; }
+            if (c2) { den += c2 > 0 ? d2 : -d2; nu += c2 > 0 ? p12 : -p12; nv += c2 > 0 ? p22 : -p22; }
+            const float ad = fabsf(den);
+            const bool neg = den < 0.0f;
+            const float su = neg ? -nu : nu;
+            const float sv = neg ? -nv : nv;
+            const bool t_ok = atn <= ad + MD + MT;
+            const bool bary = (su >= -MU) & (sv >= -MV) & (su + sv <= ad + MU + MV + MD);
+            cm |= (t_ok & ((ad <= MD) | bary)) ? (1u << p) : 0u;
+            if constexpr (kSure) {
+                const bool in = (ad > MD) & (atn <= (ad - MD) - MT) & (su >= MU) & (sv >= MV) &
+                                (su + sv <= ((ad - MU) - MV) - MD);
+                cs |= in ? (1u << p) : 0u;
+            }
+        }
+    } else {
+        const float w0 = S.f[0][j] - o[0], w1 = S.f[1][j] - o[1];
+        const float e0 = S.f[2][j] - S.f[0][j], e1 = S.f[3][j] - S.f[1][j];
+        const float nw = fabsf(w0) + fabsf(w1), ne = fabsf(e0) + fabsf(e1);
+        const float mx_ = fmaxf(dx[0], dx[1]) * 9.5367431640625e-07f;
+        const float MD = mx_ * ne, MS = mx_ * nw, MW = 9.5367431640625e-07f * nw * ne;
+        const float awxe = fabsf(w0 * e1 - w1 * e0);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int i = 1 + 2 * p;
+            const float D0 = (float)dir_c<D>(i, 0) * dx[0], D1 = (float)dir_c<D>(i, 1) * dx[1];
+            const float den = D0 * e1 - D1 * e0;
+            const float ad = fabsf(den);
+            const float sn = w0 * D1 - w1 * D0;
+            const float ss = den < 0.0f ? -sn : sn;
+            const bool t_ok = awxe <= ad + MD + MW;
+            const bool seg = (ss >= -MS) & (ss <= ad + MS + MD);
+            cm |= (t_ok & ((ad <= MD) | seg)) ? (1u << p) : 0u;
+            if constexpr (kSure) {
+                const bool in = (ad > MD) & (awxe <= (ad - MD) - MW) & (ss >= MS) & (ss <= (ad - MS) - MD);
+                cs |= in ? (1u << p) : 0u;
+            }
+        }
+    }
+    if constexpr (kSure) *sure = cs;
+    return cm;
+}
+
+// Whether any direction pair can pass the filter for staged face j and origin
+// o: the filter's |t| test with the largest |D . n| of any direction,
+// S = sum |n_a dx_a| (3D; always in 2D).
+template <int D, int CAP>
+__device__ __forceinline__ bool link_reach(const LinkStaged<D, CAP> &S, int j, const float o[3], const float dx[3]) {
+    if constexpr (D == 3) {
+        const float T0 = o[0] - S.f[0][j], T1 = o[1] - S.f[1][j], T2 = o[2] - S.f[2][j];
+        const float n0 = S.f[9][j], n1 = S.f[10][j], n2 = S.f[11][j];
+        const float n1n = S.f[12][j], n2n = S.f[13][j], Sn = S.f[14][j];
+        const float nT = fabsf(T0) + fabsf(T1) + fabsf(T2);
+        const float mx_ = fmaxf(fmaxf(dx[0], dx[1]), dx[2]) * 9.5367431640625e-07f;
+        const float MD = mx_ * n1n * n2n;
+        const float MT = 9.5367431640625e-07f * nT * n1n * n2n;
+        return fabsf((T0 * n0 + T1 * n1) + T2 * n2) <= Sn + MD + MT;
+    } else {
+        return true;
+    }
+}
+
+// FP64 decision for staged face j, direction Dv (the first direction of a
+// pair) and origin o: the segment-triangle test (Moller-Trumbore, two-sided,
+// closed) in the same expression order as the definition; returns t of Dv,
+// or NaN when the line misses the face or det = 0.  The opposite direction
+// hits at -t (negating D negates P, det and t exactly), so the pair has a
+// link in direction Dv when t is in [0, 1] and in -Dv when -t is.
+template <int D, int CAP>
+__device__ __forceinline__ double link_decide(const LinkStaged<D, CAP> &S, int j, const double o[3], const float dir[3]) {
+    const double nan = __builtin_nan("");
+    if constexpr (D == 3) {
+        const double a0 = S.f[0][j], a1 = S.f[1][j], a2 = S.f[2][j];
+        const double E1[3] = {(double)S.f[3][j] - a0, (double)S.f[4][j] - a1, (double)S.f[5][j] - a2};
+        const double E2[3] = {(double)S.f[6][j] - a0, (double)S.f[7][j] - a1, (double)S.f[8][j] - a2};
+        const double T[3] = {o[0] - a0, o[1] - a1, o[2] - a2};
+        const double Dv[3] = {(double)dir[0], (double)dir[1], (double)dir[2]};
+        const double P[3] = {Dv[1] * E2[2] - Dv[2] * E2[1], Dv[2] * E2[0] - Dv[0] * E2[2],
+                             Dv[0] * E2[1] - Dv[1] * E2[0]};
+        const double det = E1[0] * P[0] + E1[1] * P[1] + E1[2] * P[2];
+        if (det == 0.0) return nan;
+        const double u = (T[0] * P[0] + T[1] * P[1] + T[2] * P[2]) / det;
+        if (u < 0.0 || u > 1.0) return nan;
+        const double Qv[3] = {T[1] * E1[2] - T[2] * E1[1], T[2] * E1[0] - T[0] * E1[2], T[0] * E1[1] - T[1] * E1[0]};
+        const double v = (Dv[0] * Qv[0] + Dv[1] * Qv[1] + Dv[2] * Qv[2]) / det;
+        if (v < 0.0 || u + v > 1.0) return nan;
+        return (E2[0] * Qv[0] + E2[1] * Qv[1] + E2[2] * Qv[2]) / det;
+    } else {
+        const double a0 = S.f[0][j], a1 = S.f[1][j];
+        const double e0 = (double)S.f[2][j] - a0, e1 = (double)S.f[3][j] - a1;
+        const double D0 = (double)dir[0], D1 = (double)dir[1];
+        const double den = D0 * e1 - D1 * e0;
+        if (den == 0.0) return nan;
+        const double w0 = a0 - o[0], w1 = a1 - o[1];
+        const double t = (w0 * e1 - w1 * e0) / den;
+        const double sp = (w0 * D1 - w1 * D0) / den;
+        if (!(sp >= 0.0 && sp <= 1.0)) return nan;
+        return t;
+    }
+}
+
+// Link box of sub-block sb of a wave (block coordinates sc): per axis the
+// bounds of each cell position's link box (cell +- one cell, widened by eps;
+// wave-uniform, kept in scalar registers), the block's link box [qlo, qhi]
+// and the bins under it.
+template <int D>
+struct LinkBox {
+    float mlo[D][4], mhi[D][4];
+    float qlo[3], qhi[3];
+    int ilo[3], ihi[3];
+};
+
+template <int D, int Q>
+__device__ __forceinline__ void link_box(const LinkArgs<D, Q> &A, const int sc[3], LinkBox<D> &bx) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        bx.qlo[a] = bx.qhi[a] = 0.0f;
+        bx.ilo[a] = bx.ihi[a] = 0;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float c = dev::cell_centre(A.lo[a], 4 * sc[a] + i, A.dx[a]);
+            bx.mlo[a][i] = dev::uniform((c - A.dx[a]) - A.eps[a]);
+            bx.mhi[a][i] = dev::uniform((c + A.dx[a]) + A.eps[a]);
+        }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        bx.qlo[a] = (dev::cell_centre(A.lo[a], 4 * sc[a], A.dx[a]) - A.dx[a]) - A.eps[a];
+        bx.qhi[a] = (dev::cell_centre(A.lo[a], 4 * sc[a] + 3, A.dx[a]) + A.dx[a]) + A.eps[a];
+        bx.ilo[a] = dev::bin_of(bx.qlo[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
+        bx.ihi[a] = dev::bin_of(bx.qhi[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
+    }
+}
+
+// Offers the candidate faces of block blk (sub-block sb of the wave, link box
+// bx) to the staging area: the faces whose bounding box meets the block's link
+// box, from the block's candidate list (list mode) or from the bins under the
+// box (each face once, in the first bin of (its bins) x (the box's bins)).  A
+// round of 64 candidates can keep more faces than the area holds: they are
+// staged in pieces that fit, flush(count) testing and emptying the area
+// between pieces (whole wave).  Returns the number of faces left staged.
+template <int D, int Q, class Flush>
+__device__ __forceinline__ int link_gather(const LinkArgs<D, Q> &A, int64_t blk, int sb, const LinkBox<D> &bx,
+                                           LinkStaged<D> &S, int count, Flush &&flush) {
+    const int lane = dev::lane_id();
+    auto face_code = [&](const float *bb) -> uint32_t {   // bb: min[D], max[D]
+        uint32_t c = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                c |= (bb[a] <= bx.mhi[a][i] && bb[D + a] >= bx.mlo[a][i]) ? (1u << (4 * a + i)) : 0u;
+        return c << (sb * 4 * D);
+    };
+    auto round = [&](bool has, int32_t f, const int *cur) {
+        bool keep = false;
+        float r[dev::kRecFloats<D>];
+        const float *bb = r + D * D;   // min then max
+        if (has) {
+            dev::load_rec<D>(A.faces.rec, f, r);
+            keep = true;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                if (cur) {
+                    const int fb = max(dev::bin_of(bb[a], A.bins.lo[a], A.bins.s[a], A.bins.B), bx.ilo[a]);
+                    keep = keep && fb == cur[a];
+                }
+                keep = keep && bb[a] <= bx.qhi[a] && bb[D + a] >= bx.qlo[a];
+            }
+        }
+        uint64_t rest = __ballot(keep);
+        while (rest) {
+            if (count > 0 && count + __popcll(rest) > kLinkCap) {
+                flush(count);
+                count = 0;
+            }
+            const bool now = ((rest >> lane) & 1ull) && dev::lanes_below(rest) < kLinkCap - count;
+            const uint64_t part = __ballot(now);
+            rest &= ~part;
+            const int pos = count + dev::lanes_below(part);
+            count += __popcll(part);
+            if (now) link_stage<D>(S, pos, f, r, A.dx, face_code(bb));
+        }
+    };
+    if (A.list) {
+        const uint32_t s0 = A.loff[blk], s1 = min(A.loff[blk + 1], A.list_cap);   // wave-uniform
+        for (uint32_t c0 = s0; c0 < s1; c0 += dev::kWave) {
+            const uint32_t e = c0 + (uint32_t)lane;
+            const int32_t f = e < s1 ? A.list[e] : -1;
+            round(f >= 0 && f < A.faces.F, f, nullptr);
+        }
+    } else {
+        for_candidates(A.bins, bx.ilo, bx.ihi, [&](bool has, int32_t f, const int cur[3]) -> bool {
+            round(has, f, cur);
+            return true;
+        });
+    }
+    return count;
+}
+
+// One wave: finest-level blocks first .. first + 64/4^D - 1 of A; best hit
+// per (cell, direction) and the node rows.  out.rows(blk, count) places each
+// block's nodes: it returns the first row for them (and records the count),
+// or -1 when it has no room; rows are written in cell order.
 template <int D, int Q, class Out>
 __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t first, Out &out) {
     constexpr int CELLS = D == 3 ? 64 : 16;
     constexpr int BPW = 64 / CELLS;
     constexpr int NP = (Q - 1) / 2;            // direction pairs
-    constexpr int NF = D == 3 ? 15 : 4;   // floats staged per face: corners (3D: + normal, |E1|_1, |E2|_1, S)
-    __shared__ float s_f[NF][kLinkCap];
-    __shared__ int32_t s_id[kLinkCap];
-    __shared__ __align__(16) uint32_t s_code[kLinkCap];
+    __shared__ LinkStaged<D> S;
     __shared__ float s_dir[NP][3];   // D = c * dx of each direction pair's first direction
     const int lane = threadIdx.x;
     if (lane < NP)
@@ -894,7 +1182,6 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
     const bool valid = blk < A.n;
     const int cell = lane % CELLS;
     const int sub = lane / CELLS;
-
     int bc[3] = {0, 0, 0};
     uint32_t key = 0;
     if (valid) {
@@ -915,16 +1202,6 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
     uint32_t lbits = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) lbits |= 1u << (sub * 4 * D + 4 * a + pos3[a]);
-    float mlo[D][4], mhi[D][4];   // link-box bounds along each axis of the block being staged
-    auto face_code = [&](int t, const float *bb) -> uint32_t {   // bb: min[D], max[D]
-        uint32_t c = 0;
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                c |= (bb[a] <= mhi[a][i] && bb[D + a] >= mlo[a][i]) ? (1u << (4 * a + i)) : 0u;
-        return c << (t * 4 * D);
-    };
 
     // Best hit per (lane, direction) as one 64-bit key: the FP32 bits of t
     // (t >= 0, so they order like t) above the face id, so the smaller key is
@@ -951,142 +1228,20 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
         const unsigned long long k = ((unsigned long long)__float_as_uint(t) << 32) | (uint32_t)f;
         atomicMin(&s_best[i][l], k);
     };
-
-    // FP64 decision for staged face j, direction pair p and the link origin
-    // of lane l: the segment-triangle test in the same expression order as
-    // the definition (Moller-Trumbore), so both directions of the pair come
-    // out exactly as separate evaluations would (negating D negates P, det
-    // and t exactly).
-    auto decide = [&](uint32_t item) {
-        const int l = (int)(item >> 20);
-        const int j = (int)((item >> 13) & 127u);
-        const int p = (int)(item & 31u);
-        const int32_t f = s_id[j];
-        const double o0 = s_o[l][0], o1 = s_o[l][1];
-        if constexpr (D == 3) {
-            const double o2 = s_o[l][2];
-            const double a0 = s_f[0][j], a1 = s_f[1][j], a2 = s_f[2][j];
-            const double E1[3] = {(double)s_f[3][j] - a0, (double)s_f[4][j] - a1, (double)s_f[5][j] - a2};
-            const double E2[3] = {(double)s_f[6][j] - a0, (double)s_f[7][j] - a1, (double)s_f[8][j] - a2};
-            const double T[3] = {o0 - a0, o1 - a1, o2 - a2};
-            const double Dv[3] = {(double)s_dir[p][0], (double)s_dir[p][1], (double)s_dir[p][2]};
-            const double P[3] = {Dv[1] * E2[2] - Dv[2] * E2[1], Dv[2] * E2[0] - Dv[0] * E2[2],
-                                 Dv[0] * E2[1] - Dv[1] * E2[0]};
-            const double det = E1[0] * P[0] + E1[1] * P[1] + E1[2] * P[2];
-            if (det == 0.0) return;
-            const double u = (T[0] * P[0] + T[1] * P[1] + T[2] * P[2]) / det;
-            if (u < 0.0 || u > 1.0) return;
-            const double Qv[3] = {T[1] * E1[2] - T[2] * E1[1], T[2] * E1[0] - T[0] * E1[2], T[0] * E1[1] - T[1] * E1[0]};
-            const double v = (Dv[0] * Qv[0] + Dv[1] * Qv[1] + Dv[2] * Qv[2]) / det;
-            if (v < 0.0 || u + v > 1.0) return;
-            const double t = (E2[0] * Qv[0] + E2[1] * Qv[1] + E2[2] * Qv[2]) / det;
-            consider(2 * p, l, t, f);        // direction 1 + 2p
-            consider(2 * p + 1, l, -t, f);   // its opposite
-        } else {
-            const double a0 = s_f[0][j], a1 = s_f[1][j];
-            const double e0 = (double)s_f[2][j] - a0, e1 = (double)s_f[3][j] - a1;
-            const double D0 = (double)s_dir[p][0], D1 = (double)s_dir[p][1];
-            const double den = D0 * e1 - D1 * e0;
-            if (den == 0.0) return;
-            const double w0 = a0 - o0, w1 = a1 - o1;
-            const double t = (w0 * e1 - w1 * e0) / den;
-            const double sp = (w0 * D1 - w1 * D0) / den;
-            if (!(sp >= 0.0 && sp <= 1.0)) return;
-            consider(2 * p, l, t, f);
-            consider(2 * p + 1, l, -t, f);
-        }
-    };
     auto take_b = [&](int take) {   // wave-uniform
         __syncthreads();
         const uint32_t item = lane < take ? s_qb[lane] : 0u;
         __syncthreads();
         if (lane < nb - take) s_qb[lane] = s_qb[take + lane];
         nb -= take;
-        if (lane < take) decide(item);
-    };
-
-    // FP32 filter of staged face j for a link origin o over all direction
-    // pairs: the pairs whose segment may meet the face.  Each quantity carries
-    // an absolute rounding error bounded by 2^-21 times the product of the L1
-    // norms of its factors; margins of 2^-20 times those products keep every
-    // true hit.  A pair needs |t| <= 1 on the face's plane, |T . n| <= |D . n|
-    // (within margins), and, unless D . n is too small to have a known sign,
-    // barycentrics inside the face.
-    auto filter = [&](int j, const float (&o)[3]) -> uint32_t {
-        uint32_t cm = 0;
-        if constexpr (D == 3) {
-            const float T0 = o[0] - s_f[0][j], T1 = o[1] - s_f[1][j], T2 = o[2] - s_f[2][j];
-            const float e10 = s_f[3][j] - s_f[0][j], e11 = s_f[4][j] - s_f[1][j], e12 = s_f[5][j] - s_f[2][j];
-            const float e20 = s_f[6][j] - s_f[0][j], e21 = s_f[7][j] - s_f[1][j], e22 = s_f[8][j] - s_f[2][j];
-            const float n0 = s_f[9][j], n1 = s_f[10][j], n2 = s_f[11][j];
-            const float n1n = s_f[12][j], n2n = s_f[13][j];
-            const float nT = fabsf(T0) + fabsf(T1) + fabsf(T2);
-            const float mx_ = fmaxf(fmaxf(A.dx[0], A.dx[1]), A.dx[2]) * 9.5367431640625e-07f;  // dx * 2^-20
-            const float MU = mx_ * nT * n2n;
-            const float MV = mx_ * n1n * nT;
-            const float MD = mx_ * n1n * n2n;
-            const float MT = 9.5367431640625e-07f * nT * n1n * n2n;
-            const float p10 = (T1 * e22 - T2 * e21) * A.dx[0];
-            const float p11 = (T2 * e20 - T0 * e22) * A.dx[1];
-            const float p12 = (T0 * e21 - T1 * e20) * A.dx[2];
-            const float p20 = (e11 * T2 - e12 * T1) * A.dx[0];
-            const float p21 = (e12 * T0 - e10 * T2) * A.dx[1];
-            const float p22 = (e10 * T1 - e11 * T0) * A.dx[2];
-            const float d0 = n0 * A.dx[0], d1 = n1 * A.dx[1], d2 = n2 * A.dx[2];
-            const float atn = fabsf((T0 * n0 + T1 * n1) + T2 * n2);
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                const int i = 1 + 2 * p;
-                const int c0 = dir_c<D>(i, 0), c1 = dir_c<D>(i, 1), c2 = dir_c<D>(i, 2);
-                float den = 0.0f, nu = 0.0f, nv = 0.0f;
-                if (c0) { den += c0 > 0 ? d0 : -d0; nu += c0 > 0 ? p10 : -p10; nv += c0 > 0 ? p20 : -p20; }
-                if (c1) { den += c1 > 0 ? d1 : -d1; nu += c1 > 0 ? p11 : -p11; nv += c1 > 0 ? p21 : -p21; }
-                if (c2) { den += c2 > 0 ? d2 : -d2; nu += c2 > 0 ? p12 : -p12; nv += c2 > 0 ? p22 : -p22; }
-                const float ad = fabsf(den);
-                const bool neg = den < 0.0f;
-                const float su = neg ? -nu : nu;
-                const float sv = neg ? -nv : nv;
-                const bool t_ok = atn <= ad + MD + MT;
-                const bool bary = (su >= -MU) & (sv >= -MV) & (su + sv <= ad + MU + MV + MD);
-                cm |= (t_ok & ((ad <= MD) | bary)) ? (1u << p) : 0u;
-            }
-        } else {
-            const float w0 = s_f[0][j] - o[0], w1 = s_f[1][j] - o[1];
-            const float e0 = s_f[2][j] - s_f[0][j], e1 = s_f[3][j] - s_f[1][j];
-            const float nw = fabsf(w0) + fabsf(w1), ne = fabsf(e0) + fabsf(e1);
-            const float mx_ = fmaxf(A.dx[0], A.dx[1]) * 9.5367431640625e-07f;
-            const float MD = mx_ * ne, MS = mx_ * nw, MW = 9.5367431640625e-07f * nw * ne;
-            const float awxe = fabsf(w0 * e1 - w1 * e0);
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                const int i = 1 + 2 * p;
-                const float D0 = (float)dir_c<D>(i, 0) * A.dx[0], D1 = (float)dir_c<D>(i, 1) * A.dx[1];
-                const float den = D0 * e1 - D1 * e0;
-                const float ad = fabsf(den);
-                const float sn = w0 * D1 - w1 * D0;
-                const float ss = den < 0.0f ? -sn : sn;
-                const bool t_ok = awxe <= ad + MD + MW;
-                const bool seg = (ss >= -MS) & (ss <= ad + MS + MD);
-                cm |= (t_ok & ((ad <= MD) | seg)) ? (1u << p) : 0u;
-            }
-        }
-        return cm;
-    };
-    // Whether any direction pair can pass the filter for staged face j and
-    // this lane's origin: the filter's |t| test with the largest |D . n| of any
-    // direction, S = sum |n_a dx_a| (3D; always in 2D).
-    auto reach = [&](int j) -> bool {
-        if constexpr (D == 3) {
-            const float T0 = o[0] - s_f[0][j], T1 = o[1] - s_f[1][j], T2 = o[2] - s_f[2][j];
-            const float n0 = s_f[9][j], n1 = s_f[10][j], n2 = s_f[11][j];
-            const float n1n = s_f[12][j], n2n = s_f[13][j], S = s_f[14][j];
-            const float nT = fabsf(T0) + fabsf(T1) + fabsf(T2);
-            const float mx_ = fmaxf(fmaxf(A.dx[0], A.dx[1]), A.dx[2]) * 9.5367431640625e-07f;
-            const float MD = mx_ * n1n * n2n;
-            const float MT = 9.5367431640625e-07f * nT * n1n * n2n;
-            return fabsf((T0 * n0 + T1 * n1) + T2 * n2) <= S + MD + MT;
-        } else {
-            return true;
+        if (lane < take) {
+            const int l = (int)(item >> 20);
+            const int j = (int)((item >> 13) & 127u);
+            const int p = (int)(item & 31u);
+            const double ol[3] = {s_o[l][0], s_o[l][1], s_o[l][2]};
+            const double t = link_decide<D>(S, j, ol, s_dir[p]);
+            consider(2 * p, l, t, S.id[j]);        // direction 1 + 2p
+            consider(2 * p + 1, l, -t, S.id[j]);   // its opposite
         }
     };
     auto take_a = [&](int take) {   // wave-uniform
@@ -1099,7 +1254,7 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
         uint32_t cm = 0;
         if (lane < take) {
             const float ol[3] = {s_o[l][0], s_o[l][1], s_o[l][2]};
-            cm = filter(j, ol);
+            cm = link_filter<D, NP, false, kLinkCap>(S, j, ol, A.dx, nullptr);
         }
         while (__ballot(cm != 0)) {
             const bool has = cm != 0;
@@ -1126,8 +1281,8 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
             uint64_t nm = 0;
             if (valid)
             for (int jj = 0; jj < jn; jj += 4) {
-                const uint32_t cs[4] = {s_code[j0 + jj], s_code[j0 + jj + 1], s_code[j0 + jj + 2],
-                                        s_code[j0 + jj + 3]};
+                const uint32_t cs[4] = {S.code[j0 + jj], S.code[j0 + jj + 1], S.code[j0 + jj + 2],
+                                        S.code[j0 + jj + 3]};
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
                     nm |= ((cs[u] & lbits) == lbits && jj + u < jn) ? (1ull << (jj + u)) : 0ull;
@@ -1138,7 +1293,7 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
                 if (nm) {
                     j = j0 + __builtin_ctzll(nm);
                     nm &= nm - 1ull;
-                    pass = reach(j);
+                    pass = link_reach<D>(S, j, o, A.dx);
                 }
                 const uint64_t m = __ballot(pass);
                 if (pass) s_qa[na + dev::lanes_below(m)] = ((uint32_t)lane << 7) | (uint32_t)j;
@@ -1158,81 +1313,12 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
         sc[0] = __shfl(bc[0], sb * CELLS, 64);
         sc[1] = __shfl(bc[1], sb * CELLS, 64);
         sc[2] = __shfl(bc[2], sb * CELLS, 64);
-        float qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
-        int ilo[3] = {0, 0, 0}, ihi[3] = {0, 0, 0};
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {   // wave-uniform: kept in scalar registers
-                const float c = dev::cell_centre(A.lo[a], 4 * sc[a] + i, A.dx[a]);
-                mlo[a][i] = dev::uniform((c - A.dx[a]) - A.eps[a]);
-                mhi[a][i] = dev::uniform((c + A.dx[a]) + A.eps[a]);
-            }
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            qlo[a] = (dev::cell_centre(A.lo[a], 4 * sc[a], A.dx[a]) - A.dx[a]) - A.eps[a];
-            qhi[a] = (dev::cell_centre(A.lo[a], 4 * sc[a] + 3, A.dx[a]) + A.dx[a]) + A.eps[a];
-            ilo[a] = dev::bin_of(qlo[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
-            ihi[a] = dev::bin_of(qhi[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
-        }
-        for_candidates(A.bins, ilo, ihi, [&](bool has, int32_t f, const int cur[3]) -> bool {
-            bool keep = false;
-            float r[dev::kRecFloats<D>];
-            const float *bb = r + D * D;   // min then max
-            if (has) {
-                dev::load_rec<D>(A.faces.rec, f, r);
-                keep = true;
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    // visit each face once: in the first bin of (its bins) x (query bins)
-                    const int fb = max(dev::bin_of(bb[a], A.bins.lo[a], A.bins.s[a], A.bins.B), ilo[a]);
-                    keep = keep && fb == cur[a] && bb[a] <= qhi[a] && bb[D + a] >= qlo[a];
-                }
-            }
-            // A round can keep up to 64 faces, more than the staging area
-            // holds: they are staged in pieces that fit, the area being
-            // tested and emptied between pieces.
-            uint64_t rest = __ballot(keep);
-            while (rest) {
-                if (count > 0 && count + __popcll(rest) > kLinkCap) {
-                    test_staged(count);
-                    count = 0;
-                }
-                const bool now = ((rest >> lane) & 1ull) && dev::lanes_below(rest) < kLinkCap - count;
-                const uint64_t part = __ballot(now);
-                rest &= ~part;
-                const int pos = count + dev::lanes_below(part);
-                count += __popcll(part);
-                if (now) {
-                s_id[pos] = f;
-                if constexpr (D == 3) {
-                    const float *v = r;
-                    const float e10 = v[3] - v[0], e11 = v[4] - v[1], e12 = v[5] - v[2];
-                    const float e20 = v[6] - v[0], e21 = v[7] - v[1], e22 = v[8] - v[2];
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) s_f[k][pos] = v[k];
-                    const float n0 = e11 * e22 - e12 * e21;
-                    const float n1 = e12 * e20 - e10 * e22;
-                    const float n2 = e10 * e21 - e11 * e20;
-                    s_f[9][pos] = n0;
-                    s_f[10][pos] = n1;
-                    s_f[11][pos] = n2;
-                    s_f[12][pos] = fabsf(e10) + fabsf(e11) + fabsf(e12);
-                    s_f[13][pos] = fabsf(e20) + fabsf(e21) + fabsf(e22);
-                    s_f[14][pos] = fabsf(n0 * A.dx[0]) + fabsf(n1 * A.dx[1]) + fabsf(n2 * A.dx[2]);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) s_f[k][pos] = r[k];
-                }
-                s_code[pos] = face_code(sb, bb);
-                }
-            }
-            return true;
-        });
+        LinkBox<D> bx;
+        link_box<D, Q>(A, sc, bx);
+        count = link_gather<D, Q>(A, first + sb, sb, bx, S, count, test_staged);
     }
     if (count > 0) test_staged(count);
 
-    // ordered compaction of the cells that have a link
     uint64_t best[Q - 1];
     bool has = false;
 #pragma unroll
@@ -1240,6 +1326,7 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
         best[i] = s_best[i][lane];
         has = has || best[i] != ~0ull;
     }
+    // ordered compaction of the cells that have a link
     has = has && valid;
     const uint64_t hm = __ballot(has);
     // rank inside the block: lanes of this block below this lane that have a link
@@ -1248,8 +1335,9 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
     int64_t row0 = 0;
     if (valid && cell == 0) row0 = out.rows(blk, (uint32_t)__popcll(bm));
     row0 = __shfl(row0, sub * CELLS, 64);
-    if (has && row0 >= 0) {   // a negative first row: the output policy ran out of capacity
-        const int64_t node = row0 + __popcll(bm & ((1ull << cell) - 1));
+    // a negative first row: the output policy ran out of capacity
+    const int64_t node = has && row0 >= 0 ? row0 + __popcll(bm & ((1ull << cell) - 1)) : -1;
+    if (node >= 0) {
         A.node_key[node] = (uint64_t)key * CELLS + (uint64_t)cell;
         float *qr = A.q + node * Q;
         int32_t *fr = A.face + node * Q;
@@ -1261,6 +1349,351 @@ __device__ __forceinline__ void links_wave(const LinkArgs<D, Q> &A, int64_t firs
             qr[i + 1] = hit ? __uint_as_float((uint32_t)(best[i] >> 32)) : -1.0f;
             fr[i + 1] = hit ? (int32_t)(uint32_t)best[i] : -1;
         }
+    }
+}
+
+// Near code of a face box bb (min[D], max[D]) for the block at block
+// coordinates bc: bit 4a + i is set when the link box of cell position i along
+// axis a (centre +- one cell, widened by eps) meets the box along a -- the
+// same FP32 expressions as link_box.  Per lane (the block need not be
+// wave-uniform).
+template <int D, int Q>
+__device__ __forceinline__ uint32_t link_code_at(const LinkArgs<D, Q> &A, const int bc[3], const float *bb) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float m = dev::cell_centre(A.lo[a], 4 * bc[a] + i, A.dx[a]);
+            const float lo_ = (m - A.dx[a]) - A.eps[a], hi_ = (m + A.dx[a]) + A.eps[a];
+            c |= (bb[a] <= hi_ && bb[D + a] >= lo_) ? (1u << (4 * a + i)) : 0u;
+        }
+    return c;
+}
+
+// Position of the k-th set bit (k < popcount) of a 4-bit mask.
+__device__ __forceinline__ int nth_bit4(uint32_t m, int k) {
+    int i = 0, seen = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const bool set = (m >> b) & 1u;
+        if (set && seen == k) i = b;
+        seen += set ? 1 : 0;
+    }
+    return i;
+}
+
+// Node pass of list mode: which finest-level cells have at least one link.
+// Work is taken from the candidate lists 64 (face, block) entries at a time
+// (persistent loop over the entries): every (entry, cell) pair whose cell
+// link box meets the face box -- exactly the pairs the row pass tests -- is
+// one lane's work.  A pair is dropped when its cell is known to have a link
+// already or when no direction can reach the face's plane; the others go
+// through a queue, 64 at a time, to the FP32 filter narrowed and widened by
+// its margins: a certain hit sets the cell's bit in its block's mask, a
+// possible one is decided in FP64 exactly as the row pass decides it.  So a
+// block's mask is the set of its cells for which the row pass finds a hit.
+// mask: one 64-bit word per block, zeroed; lblk: the block of each entry.
+template <int D, int Q>
+__device__ __forceinline__ void links_nodes_entries(const LinkArgs<D, Q> &A, const uint32_t *lblk,
+                                                    unsigned long long *mask) {
+    constexpr int NP = (Q - 1) / 2;
+    constexpr int RF = dev::kRecFloats<D>;
+    __shared__ LinkStaged<D, 64> S;
+    __shared__ float s_dir[NP][3];
+    __shared__ uint32_t s_pre[64];     // exclusive prefix of the entries' pair counts
+    __shared__ uint32_t s_bits[64];    // code bits of each entry
+    __shared__ uint32_t s_blk[64];     // block of each entry
+    __shared__ int s_bc[64][3];        // its block coordinates
+    constexpr int QCAP = 128;
+    __shared__ uint32_t s_q[QCAP];     // queued pairs: entry << 8 | cell
+    const int lane = dev::lane_id();
+    if (lane < NP)
+        for (int a = 0; a < 3; ++a) s_dir[lane][a] = (float)dir_c<D>(1 + 2 * lane, a) * A.dx[a];
+    const uint32_t total = min(A.loff[A.n], A.list_cap);
+    int nq = 0;   // wave-uniform queue length
+
+    // certain or FP64-decided hit for queued pair `item` (whole wave; lanes
+    // beyond `take` idle)
+    auto take = [&](int ntake) {
+        dev::wave_sync();
+        const uint32_t item = lane < ntake ? s_q[lane] : 0u;
+        dev::wave_sync();
+        if (lane < nq - ntake) s_q[lane] = s_q[ntake + lane];
+        nq -= ntake;
+        if (lane < ntake) {
+            const int j = (int)(item >> 8), cell = (int)(item & 255u);
+            const uint32_t b = s_blk[j];
+            float o[3] = {0.0f, 0.0f, 0.0f};
+            o[0] = dev::cell_centre(A.lo[0], 4 * s_bc[j][0] + (cell & 3), A.dx[0]);
+            o[1] = dev::cell_centre(A.lo[1], 4 * s_bc[j][1] + ((cell >> 2) & 3), A.dx[1]);
+            if constexpr (D == 3) o[2] = dev::cell_centre(A.lo[2], 4 * s_bc[j][2] + (cell >> 4), A.dx[2]);
+            uint32_t sure = 0;
+            uint32_t maybe = link_filter<D, NP, true, 64>(S, j, o, A.dx, &sure);
+            bool hit = sure != 0;
+            if (!hit && maybe) {
+                const double o64[3] = {o[0], o[1], o[2]};
+                while (maybe) {
+                    const int p = __builtin_ctz(maybe);
+                    maybe &= maybe - 1u;
+                    const double t = link_decide<D>(S, j, o64, s_dir[p]);
+                    if (t >= -1.0 && t <= 1.0) {
+                        hit = true;
+                        break;
+                    }
+                }
+            }
+            if (hit) atomicOr(&mask[b], 1ull << cell);
+        }
+    };
+
+    for (int64_t w = blockIdx.x; w * 64 < (int64_t)total; w += gridDim.x) {
+        const uint32_t e = (uint32_t)(w * 64) + (uint32_t)lane;
+        uint32_t bits = 0, cnt = 0, b = 0;
+        int bc[3] = {0, 0, 0};
+        if (e < total) {
+            const int32_t f = A.list[e];
+            b = lblk[e];
+            if (f >= 0 && f < A.faces.F && (int64_t)b < A.n) {
+                float r[RF];
+                dev::load_rec<D>(A.faces.rec, f, r);
+                dev::decode_key<D>(A.keys[b], A.level, A.R[0], A.R[1], bc);
+                bits = link_code_at<D, Q>(A, bc, r + D * D);
+                cnt = 1;
+#pragma unroll
+                for (int a = 0; a < D; ++a) cnt *= (uint32_t)__popc((bits >> (4 * a)) & 15u);
+                link_stage<D>(S, lane, f, r, A.dx, bits);
+            }
+        }
+        const uint32_t incl = dev::wave_inclusive_sum(cnt);
+        const uint32_t npairs = (uint32_t)__builtin_amdgcn_readlane((int)incl, dev::kWave - 1);
+        s_pre[lane] = incl - cnt;
+        s_bits[lane] = bits;
+        s_blk[lane] = b;
+        s_bc[lane][0] = bc[0];
+        s_bc[lane][1] = bc[1];
+        s_bc[lane][2] = bc[2];
+        dev::wave_sync();
+        for (uint32_t c0 = 0; c0 < npairs; c0 += dev::kWave) {
+            const uint32_t v = c0 + (uint32_t)lane;
+            bool want = false;
+            uint32_t item = 0;
+            if (v < npairs) {
+                int k = 0;   // the last entry whose pairs start at or before v
+#pragma unroll
+                for (int step = 32; step >= 1; step >>= 1)
+                    if (s_pre[k + step < 64 ? k + step : 63] <= v && k + step < 64) k += step;
+                uint32_t u = v - s_pre[k];
+                const uint32_t bk = s_bits[k];
+                const uint32_t mx = bk & 15u, my = (bk >> 4) & 15u, mz = (bk >> 8) & 15u;
+                const uint32_t nx = (uint32_t)__popc(mx), ny = (uint32_t)__popc(my);
+                const int ix = nth_bit4(mx, (int)(u % nx));
+                u /= nx;
+                int iy, iz = 0;
+                if constexpr (D == 3) {
+                    iy = nth_bit4(my, (int)(u % ny));
+                    iz = nth_bit4(mz, (int)(u / ny));
+                } else {
+                    iy = nth_bit4(my, (int)u);
+                }
+                const int cell = ix | (iy << 2) | (iz << 4);
+                const uint32_t b = s_blk[k];
+                if (!((mask[b] >> cell) & 1ull)) {
+                    float o[3] = {0.0f, 0.0f, 0.0f};
+                    o[0] = dev::cell_centre(A.lo[0], 4 * s_bc[k][0] + ix, A.dx[0]);
+                    o[1] = dev::cell_centre(A.lo[1], 4 * s_bc[k][1] + iy, A.dx[1]);
+                    if constexpr (D == 3) o[2] = dev::cell_centre(A.lo[2], 4 * s_bc[k][2] + iz, A.dx[2]);
+                    want = link_reach<D>(S, k, o, A.dx);
+                    item = ((uint32_t)k << 8) | (uint32_t)cell;
+                }
+            }
+            const uint64_t m = __ballot(want);
+            if (want) s_q[nq + dev::lanes_below(m)] = item;
+            nq += __popcll(m);
+            if (nq >= 64) take(64);
+        }
+        if (nq > 0) take(nq);
+        dev::wave_sync();
+    }
+}
+
+// Row pass of list mode: one wave per 64 consecutive nodes (node k: block
+// nblk[k], node key written beforehand), one lane per node.  The wave stages
+// the candidate entries of its blocks -- one contiguous range of the lists,
+// blocks being in node order -- and every lane tests the staged faces of its
+// own block near its cell; the best hit per direction is kept as in
+// links_wave, in a node-major table from which the wave writes its rows of q
+// and face ids as flat coalesced runs.
+template <int D, int Q>
+__device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const uint32_t *lblk, const uint32_t *nblk,
+                                                 const uint64_t *node_key, uint32_t nn, int64_t chunk) {
+    constexpr int CELLS = D == 3 ? 64 : 16;
+    constexpr int NP = (Q - 1) / 2;
+    constexpr int RF = dev::kRecFloats<D>;
+    __shared__ LinkStaged<D> S;
+    __shared__ uint32_t s_sblk[kLinkCap];   // block of each staged entry
+    __shared__ float s_dir[NP][3];
+    const int lane = dev::lane_id();
+    if (lane < NP)
+        for (int a = 0; a < 3; ++a) s_dir[lane][a] = (float)dir_c<D>(1 + 2 * lane, a) * A.dx[a];
+    const int64_t k0 = chunk * 64;
+    const int nnodes = (int)min<int64_t>(64, (int64_t)nn - k0);
+    const bool valid = lane < nnodes;
+    const uint32_t myb = valid ? nblk[k0 + lane] : 0xFFFFFFFFu;
+    const uint64_t nkey = valid ? node_key[k0 + lane] : 0ull;
+    const int cell = (int)(nkey % CELLS);
+    int bc[3] = {0, 0, 0};
+    if (valid) dev::decode_key<D>((uint32_t)(nkey / CELLS), A.level, A.R[0], A.R[1], bc);
+    float o[3];
+    o[0] = dev::cell_centre(A.lo[0], 4 * bc[0] + (cell & 3), A.dx[0]);
+    o[1] = dev::cell_centre(A.lo[1], 4 * bc[1] + ((cell >> 2) & 3), A.dx[1]);
+    o[2] = D == 3 ? dev::cell_centre(A.lo[2], 4 * bc[2] + (cell >> 4), A.dx[2]) : 0.0f;
+    uint32_t lbits = 0;
+    {
+        const int pos3[3] = {cell & 3, (cell >> 2) & 3, cell >> 4};
+#pragma unroll
+        for (int a = 0; a < D; ++a) lbits |= 1u << (4 * a + pos3[a]);
+    }
+    // node-major best keys: a row of Q - 1 keys per node, read back in row order
+    __shared__ unsigned long long s_best[64][Q - 1];
+    __shared__ float s_o[64][3];
+    constexpr int TCAP = 128;
+    __shared__ uint32_t s_qa[TCAP];
+    __shared__ uint32_t s_qb[TCAP];
+#pragma unroll
+    for (int i = 0; i < Q - 1; ++i) s_best[lane][i] = ~0ull;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) s_o[lane][a] = o[a];
+    int na = 0, nb = 0;
+
+    auto consider = [&](int i, int l, double t64, int32_t f) {
+        if (!(t64 >= 0.0 && t64 <= 1.0)) return;
+        const float t = (float)t64 + 0.0f;
+        const unsigned long long key = ((unsigned long long)__float_as_uint(t) << 32) | (uint32_t)f;
+        atomicMin(&s_best[l][i], key);
+    };
+    auto take_b = [&](int take) {
+        dev::wave_sync();
+        const uint32_t item = lane < take ? s_qb[lane] : 0u;
+        dev::wave_sync();
+        if (lane < nb - take) s_qb[lane] = s_qb[take + lane];
+        nb -= take;
+        if (lane < take) {
+            const int l = (int)(item >> 20);
+            const int j = (int)((item >> 13) & 127u);
+            const int p = (int)(item & 31u);
+            const double ol[3] = {s_o[l][0], s_o[l][1], s_o[l][2]};
+            const double t = link_decide<D>(S, j, ol, s_dir[p]);
+            consider(2 * p, l, t, S.id[j]);
+            consider(2 * p + 1, l, -t, S.id[j]);
+        }
+    };
+    auto take_a = [&](int take) {
+        dev::wave_sync();
+        const uint32_t item = lane < take ? s_qa[lane] : 0u;
+        dev::wave_sync();
+        if (lane < na - take) s_qa[lane] = s_qa[take + lane];
+        na -= take;
+        const int l = (int)(item >> 7), j = (int)(item & 127u);
+        uint32_t cm = 0;
+        if (lane < take) {
+            const float ol[3] = {s_o[l][0], s_o[l][1], s_o[l][2]};
+            cm = link_filter<D, NP, false, kLinkCap>(S, j, ol, A.dx, nullptr);
+        }
+        while (__ballot(cm != 0)) {
+            const bool has = cm != 0;
+            int p = 0;
+            if (has) {
+                p = __builtin_ctz(cm);
+                cm &= cm - 1u;
+            }
+            const uint64_t m = __ballot(has);
+            if (has) s_qb[nb + dev::lanes_below(m)] = ((uint32_t)l << 20) | ((uint32_t)j << 13) | (uint32_t)p;
+            nb += __popcll(m);
+            if (nb >= 64) take_b(64);
+        }
+    };
+    // staged entries near the lane's cell (same block, all its code bits),
+    // queued while its links can reach them; both queues emptied before the
+    // staging area is refilled
+    auto test_staged = [&](int n) {
+        dev::wave_sync();
+        uint64_t nm = 0;
+        if (valid)
+            for (int j = 0; j < n; ++j)
+                nm |= (s_sblk[j] == myb && (S.code[j] & lbits) == lbits) ? (1ull << j) : 0ull;
+        while (__ballot(nm != 0)) {
+            bool pass = false;
+            int j = 0;
+            if (nm) {
+                j = __builtin_ctzll(nm);
+                nm &= nm - 1ull;
+                pass = link_reach<D>(S, j, o, A.dx);
+            }
+            const uint64_t m = __ballot(pass);
+            if (pass) s_qa[na + dev::lanes_below(m)] = ((uint32_t)lane << 7) | (uint32_t)j;
+            na += __popcll(m);
+            if (na >= 64) take_a(64);
+        }
+        if (na > 0) take_a(na);
+        if (nb > 0) take_b(nb);
+        dev::wave_sync();
+    };
+
+    // the wave's entries: lists of blocks nblk[k0] .. nblk[k0 + nnodes - 1]
+    const uint32_t b_first = (uint32_t)__builtin_amdgcn_readfirstlane((int)nblk[k0]);
+    const uint32_t b_last = (uint32_t)__builtin_amdgcn_readfirstlane((int)nblk[k0 + nnodes - 1]);
+    const uint32_t e0 = A.loff[b_first], e1 = min(A.loff[b_last + 1], A.list_cap);
+    int count = 0;
+    for (uint32_t c0 = e0; c0 < e1; c0 += dev::kWave) {
+        const uint32_t e = c0 + (uint32_t)lane;
+        bool keep = false;
+        int32_t f = -1;
+        uint32_t b = 0, code = 0;
+        float r[RF];
+        if (e < e1) {
+            f = A.list[e];
+            b = lblk[e];
+            if (f >= 0 && f < A.faces.F && (int64_t)b < A.n) {
+                dev::load_rec<D>(A.faces.rec, f, r);
+                int ebc[3] = {0, 0, 0};
+                dev::decode_key<D>(A.keys[b], A.level, A.R[0], A.R[1], ebc);
+                code = link_code_at<D, Q>(A, ebc, r + D * D);
+                keep = true;
+#pragma unroll
+                for (int a = 0; a < D; ++a) keep = keep && ((code >> (4 * a)) & 15u) != 0u;
+            }
+        }
+        uint64_t rest = __ballot(keep);
+        while (rest) {
+            if (count > 0 && count + __popcll(rest) > kLinkCap) {
+                test_staged(count);
+                count = 0;
+            }
+            const bool now = ((rest >> lane) & 1ull) && dev::lanes_below(rest) < kLinkCap - count;
+            const uint64_t part = __ballot(now);
+            rest &= ~part;
+            const int pos = count + dev::lanes_below(part);
+            count += __popcll(part);
+            if (now) {
+                link_stage<D>(S, pos, f, r, A.dx, code);
+                s_sblk[pos] = b;
+            }
+        }
+    }
+    if (count > 0) test_staged(count);
+    dev::wave_sync();
+
+    // rows k0 .. k0 + nnodes - 1 of q and face ids: element e of the span is
+    // node e / Q, direction e % Q
+    float *qd = A.q + k0 * Q;
+    int32_t *fd = A.face + k0 * Q;
+    for (int e = lane; e < nnodes * Q; e += 64) {
+        const int l = e / Q, i = e % Q;
+        const unsigned long long key = i == 0 ? ~0ull : s_best[l][i - 1];
+        const bool hit = key != ~0ull;
+        qd[e] = hit ? __uint_as_float((uint32_t)(key >> 32)) : -1.0f;
+        fd[e] = hit ? (int32_t)(uint32_t)key : -1;
     }
 }
 

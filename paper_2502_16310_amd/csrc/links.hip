@@ -1,30 +1,30 @@
 // Link fractions (paper Sec. II-C-1: cells identify their links with the
 // boundary faces along the directions of the velocity set) and their adjoint.
 //
-// Forward, one wave64 per finest-level block (four blocks per wave in 2D),
-// one lane per cell:
-//  * the wave gathers the faces of the bins under the block's link box
-//    (block +- one cell), culls them by bounding box and stages, per face,
-//    vertices a, b, c, the FP32 normal n = (b - a) x (c - a) and the bounding
-//    box in LDS;
-//  * each lane culls every staged face against its own link box, then
-//    filters all directions at once in FP32.  With T = o - a, E1 = b - a,
-//    E2 = c - a the solution of o + t D = a + u E1 + v E2 is
-//        det = D.n,  u = D.(T x E2)/det,  v = D.(E1 x T)/det,  t = -(T.n)/det;
-//    T x E2, E1 x T and T.n do not depend on D, and D = c_i dx has entries
-//    in {-dx, 0, dx}, so a direction costs a few additions, and the opposite
-//    direction has the same u, v and t of the opposite sign, so directions
-//    are handled in +/- pairs.  The filter widens every test by a bound on
-//    its FP32 rounding error; whatever passes is decided, and its t computed,
+// Forward (list mode, the default):
+//  * candidate lists: every face lists the finest-level blocks whose link box
+//    (block +- one cell) its bounding box meets, found through a hash table of
+//    the blocks' parents (a refined block's 2^D children are consecutive in
+//    the level); count, exclusive scan, scatter;
+//  * node pass: one wave64 per block (four blocks per wave in 2D), one lane
+//    per cell, decides which cells have at least one link, stopping at the
+//    first certain hit; an exclusive scan of the per-block node counts gives
+//    every block its first output row;
+//  * row pass: the same waves compute, for the node cells only, the best hit
+//    per direction and write each node's row once, at its final place.
+//    A wave stages its block's candidate faces in LDS (vertices, FP32 normal,
+//    near code), each lane marks the staged faces near its own cell, and
+//    (lane, face) pairs go through an FP32 filter with rounding margins over
+//    all directions at once; whatever passes is decided, and its t computed,
 //    in FP64 with the textbook segment-triangle expressions (FP64 runs at the
-//    FP32 rate on this chip, and only near actual hits);
-//  * cells with at least one link are written to their block's own slot range
-//    of a staging buffer (block * 4^D rows), with the block's node count; an
-//    exclusive scan of the counts and a copy kernel then lay the nodes out in
-//    canonical order.  (An in-kernel ordered prefix would make every wave wait
-//    for its slowest predecessor before it could publish its count.)
+//    FP32 rate on this chip, and only near actual hits).
+// Walk mode (a face too large for the lists, or lists switched off): one pass
+// walks the bins under each block and writes its nodes into the block's own
+// slot range of a staging buffer (block * 4^D rows); an exclusive scan of the
+// counts and a copy kernel then lay the nodes out in canonical order.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "agal_internal.hpp"
 #include "device.hpp"
@@ -71,42 +71,166 @@ __global__ __launch_bounds__(64) void k_compact_nodes(const uint32_t *count, con
     compact_block<Q>((int)count[b], b * CELLS, off[b], skey, sq, sface, key, q, face);
 }
 
-template <int D, int Q>
-agal_status links_forward(agal_geom g, agal_bins bn, agal_forest fo, const Lattice &lat, agal_links lk, hipStream_t s) {
-    constexpr int CELLS = D == 3 ? 64 : 16;
-    constexpr int BPW = 64 / CELLS;
-    agal_context ctx = g->ctx;
-    const agal::Level &LL = fo->lev[fo->L];
-    if (LL.n == 0) {
-        AGAL_TRY(dev_alloc(ctx->mem, &lk->key, 1, s));
-        AGAL_TRY(dev_alloc(ctx->mem, &lk->q, (size_t)Q, s));
-        AGAL_TRY(dev_alloc(ctx->mem, &lk->face, (size_t)Q, s));
-        lk->n = 0;
-        return AGAL_OK;
+// ---- list mode ------------------------------------------------------------
+// Finest-level block of integer block coordinates c: at level 0 the root's
+// linear index; above, the parent's first child (hash table of parent keys,
+// linear probing; slot = parent key << 32 | index of its first child, ~0
+// empty) plus the child index.  -1: no such block.
+struct BlockFind {
+    const unsigned long long *hash;
+    uint32_t hmask;   // slots - 1
+    int hshift;       // 32 - log2(slots)
+    int level;
+    int R[3];
+    const uint32_t *keys;   // the level's sorted keys (a found index is checked against them)
+    int64_t n;
+};
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t key, int shift) { return (key * 2654435761u) >> shift; }
+
+template <int D>
+__device__ __forceinline__ int64_t find_block(const BlockFind &B, const int c[3]) {
+    if (B.level == 0) {
+        const int64_t i = ((int64_t)c[2] * B.R[1] + c[1]) * B.R[0] + c[0];
+        return i < B.n ? i : -1;
     }
-    const int64_t cap = LL.n * CELLS;   // staging rows: every cell of every block
-    struct Staging {
-        agal_context ctx;
-        hipStream_t s;
-        uint32_t *count = nullptr, *off = nullptr;
-        uint64_t *key = nullptr, *status = nullptr;
-        float *q = nullptr;
-        int32_t *face = nullptr;
-        ~Staging() {
-            dev_free(ctx->mem, status, s);
-            dev_free(ctx->mem, count, s);
-            dev_free(ctx->mem, off, s);
-            dev_free(ctx->mem, key, s);
-            dev_free(ctx->mem, q, s);
-            dev_free(ctx->mem, face, s);
+    const int p[3] = {c[0] >> 1, c[1] >> 1, D == 3 ? c[2] >> 1 : 0};
+    const uint32_t pk = dev::encode_key<D>(p, B.level - 1, B.R[0], B.R[1]);
+    uint32_t ci = (uint32_t)(c[0] & 1) | ((uint32_t)(c[1] & 1) << 1);
+    if (D == 3) ci |= (uint32_t)(c[2] & 1) << 2;
+    uint32_t s = hash_slot(pk, B.hshift);
+    for (uint32_t probe = 0; probe <= B.hmask; ++probe) {
+        const unsigned long long v = B.hash[s];
+        if (v == ~0ull) return -1;
+        if ((uint32_t)(v >> 32) == pk) {
+            const int64_t i = (int64_t)(uint32_t)v + ci;
+            return i < B.n && B.keys[i] == ((pk << D) | ci) ? i : -1;
         }
-    } st{ctx, s};
-    AGAL_TRY(dev_alloc(ctx->mem, &st.count, (size_t)LL.n, s));
-    AGAL_TRY(dev_alloc(ctx->mem, &st.off, (size_t)LL.n + 1, s));
-    AGAL_TRY(dev_alloc(ctx->mem, &st.status, (size_t)scan_tiles(LL.n) + 1, s));
-    AGAL_TRY(dev_alloc(ctx->mem, &st.key, (size_t)cap, s));
-    AGAL_TRY(dev_alloc(ctx->mem, &st.q, (size_t)cap * Q, s));
-    AGAL_TRY(dev_alloc(ctx->mem, &st.face, (size_t)cap * Q, s));
+        s = (s + 1) & B.hmask;
+    }
+    return -1;
+}
+
+// One thread per block of the level: its node mask zeroed and, above level
+// 0, the parent of every first child (child index 0) inserted.
+template <int D>
+__global__ void k_link_blocks(const uint32_t *keys, int64_t n, unsigned long long *hash, uint32_t hmask, int hshift,
+                              unsigned long long *mask) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        mask[i] = 0ull;
+        if (!hash) continue;
+        const uint32_t key = keys[i];
+        if (key & ((1u << D) - 1u)) continue;
+        const uint32_t pk = key >> D;
+        const unsigned long long v = ((unsigned long long)pk << 32) | (uint32_t)i;
+        uint32_t s = hash_slot(pk, hshift);
+        for (uint32_t probe = 0; probe <= hmask; ++probe) {
+            if (atomicCAS(&hash[s], ~0ull, v) == ~0ull) break;
+            s = (s + 1) & hmask;
+        }
+    }
+}
+
+// Block ranges of a face's candidate blocks, per axis in FP64: block b is a
+// candidate when its link box [lo + (4b - 0.5) dx - eps, lo + (4b + 4.5) dx +
+// eps] (FP32 in the link kernels) meets the face box widened by m = 2 eps,
+// a margin above the FP32 rounding of those bounds, so the list holds every
+// face the kernels' own FP32 box test keeps (and a few more, which it drops).
+struct LinkFaceGrid {
+    double lo[3], dx[3], m[3];
+    int NB[3];
+};
+
+// One thread per face: count (kScatter false) or write (true) the face into
+// the list of each existing candidate block.  A face with more than
+// max_coords candidate positions is skipped by both passes (the bound the
+// list was sized with makes that impossible; the test keeps the writes
+// inside the list whatever happens), and so is a write at or past cap.
+template <int D, bool kScatter>
+__global__ void k_link_faces(const float *aabb, int64_t F, LinkFaceGrid G, BlockFind B, int64_t max_coords,
+                             uint32_t *cnt, const uint32_t *loff, uint32_t *cursor, int32_t *list, uint32_t *lblk,
+                             uint32_t cap) {
+    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < F; f += (int64_t)gridDim.x * blockDim.x) {
+        int b0[3] = {0, 0, 0}, b1[3] = {0, 0, 0};
+        bool any = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double mn = aabb[(int64_t)a * F + f], mx = aabb[(int64_t)(D + a) * F + f];
+            double l = ceil((mn - G.lo[a] - G.m[a] - 4.5 * G.dx[a]) / (4.0 * G.dx[a]));
+            double h = floor((mx - G.lo[a] + G.m[a] + 0.5 * G.dx[a]) / (4.0 * G.dx[a]));
+            l = l < 0.0 ? 0.0 : l;
+            h = h > (double)(G.NB[a] - 1) ? (double)(G.NB[a] - 1) : h;
+            if (!(l <= h)) {   // outside the grid, or a non-finite coordinate
+                any = false;
+                continue;
+            }
+            b0[a] = (int)l;
+            b1[a] = (int)h;
+        }
+        if (!any) continue;
+        if ((int64_t)(b1[0] - b0[0] + 1) * (b1[1] - b0[1] + 1) * (b1[2] - b0[2] + 1) > max_coords) continue;
+        for (int z = b0[2]; z <= b1[2]; ++z)
+            for (int y = b0[1]; y <= b1[1]; ++y)
+                for (int x = b0[0]; x <= b1[0]; ++x) {
+                    const int c[3] = {x, y, z};
+                    const int64_t idx = find_block<D>(B, c);
+                    if (idx < 0) continue;
+                    if constexpr (kScatter) {
+                        const uint32_t pos = loff[idx] + atomicAdd(&cursor[idx], 1u);
+                        if (pos < cap) {
+                            list[pos] = (int32_t)f;
+                            lblk[pos] = (uint32_t)idx;
+                        }
+                    } else {
+                        atomicAdd(&cnt[idx], 1u);
+                    }
+                }
+    }
+}
+
+template <int D, int Q>
+__global__ __launch_bounds__(64) void k_links_nodes(LinkArgs<D, Q> A, const uint32_t *lblk,
+                                                    unsigned long long *mask) {
+    links_nodes_entries<D, Q>(A, lblk, mask);
+}
+
+// Node k -> its block (nblk) and node key, from the blocks' masks and first
+// rows: one lane per (block, cell), node rank = set bits of the mask below
+// the cell.
+template <int D>
+__global__ __launch_bounds__(256) void k_node_map(const unsigned long long *mask, const uint32_t *noff,
+                                                  const uint32_t *keys, int64_t n, uint32_t *nblk,
+                                                  uint64_t *node_key) {
+    constexpr int CELLS = D == 3 ? 64 : 16;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t b = t / CELLS;
+    const int cell = (int)(t % CELLS);
+    if (b >= n) return;
+    const unsigned long long m = mask[b];
+    if (!((m >> cell) & 1ull)) return;
+    const int64_t k = (int64_t)noff[b] + __popcll(m & ((1ull << cell) - 1ull));
+    nblk[k] = (uint32_t)b;
+    node_key[k] = (uint64_t)keys[b] * CELLS + (uint64_t)cell;
+}
+
+template <int D, int Q>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_links_rows(
+    LinkArgs<D, Q> A, const uint32_t *lblk, const uint32_t *nblk, uint32_t nn) {
+    links_rows_nodes<D, Q>(A, lblk, nblk, A.node_key, nn, (int64_t)blockIdx.x);
+}
+
+// Candidate blocks per face along each axis at most, from the largest face box
+// extent (bound of the list length); +2 covers the FP64 rounding of the range.
+inline double link_blocks_per_face(int D, const float ext[3], const float dx[3], const float eps[3]) {
+    double p = 1.0;
+    for (int a = 0; a < D; ++a)
+        p *= std::floor(((double)ext[a] * (1.0 + 1e-6) + 5.0 * dx[a] + 4.0 * (double)eps[a]) / (4.0 * dx[a])) + 2.0;
+    return p;
+}
+
+template <int D, int Q>
+LinkArgs<D, Q> link_args(agal_geom g, agal_bins bn, agal_forest fo) {
+    const agal::Level &LL = fo->lev[fo->L];
     LinkArgs<D, Q> A{};
     A.faces = dev::Faces{g->coords, g->aabb, g->rec, g->F};
     A.bins.off = bn->off;
@@ -124,29 +248,190 @@ agal_status links_forward(agal_geom g, agal_bins bn, agal_forest fo, const Latti
     A.keys = LL.keys;
     A.n = LL.n;
     A.level = fo->L;
-    A.node_key = st.key;
-    A.q = st.q;
-    A.face = st.face;
-    const int64_t waves = (LL.n + BPW - 1) / BPW;
-    {
-        ProfScope prof(ctx, "q_links", s);
-        hipLaunchKernelGGL((k_links<D, Q>), dim3((unsigned)waves), dim3(64), 0, s, A, st.count, st.status,
-                           scan_tiles(LL.n) + 1);
+    return A;
+}
+
+// Device memory of one call, released when the call returns (stream ordered).
+struct CallScratch {
+    agal_context ctx;
+    hipStream_t s;
+    std::vector<void *> ptrs;
+    template <class T>
+    agal_status get(T **p, size_t count) {
+        AGAL_TRY(dev_alloc(ctx->mem, p, count, s));
+        ptrs.push_back(*p);
+        return AGAL_OK;
     }
-    AGAL_TRY_HIP(hipGetLastError());
-    uint32_t nn = 0;
-    AGAL_TRY(scan_u32_total(ctx, st.count, st.off, LL.n, st.status, &nn, s));
+    ~CallScratch() {
+        for (void *p : ptrs) dev_free(ctx->mem, p, s);
+    }
+};
+
+template <int D, int Q>
+agal_status alloc_link_outputs(agal_links lk, uint32_t nn, hipStream_t s) {
+    agal_context ctx = lk->ctx;
     lk->n = nn;
     AGAL_TRY(dev_alloc(ctx->mem, &lk->key, (size_t)std::max<uint32_t>(nn, 1u), s));
     AGAL_TRY(dev_alloc(ctx->mem, &lk->q, (size_t)std::max<uint32_t>(nn, 1u) * Q, s));
     AGAL_TRY(dev_alloc(ctx->mem, &lk->face, (size_t)std::max<uint32_t>(nn, 1u) * Q, s));
+    return AGAL_OK;
+}
+
+// Walk mode: bins walked per block, nodes staged per block, then compacted.
+template <int D, int Q>
+agal_status links_forward_walk(agal_geom g, agal_bins bn, agal_forest fo, agal_links lk, hipStream_t s) {
+    constexpr int CELLS = D == 3 ? 64 : 16;
+    constexpr int BPW = 64 / CELLS;
+    agal_context ctx = g->ctx;
+    const agal::Level &LL = fo->lev[fo->L];
+    const int64_t cap = LL.n * CELLS;   // staging rows: every cell of every block
+    CallScratch st{ctx, s};
+    uint32_t *count = nullptr, *off = nullptr;
+    uint64_t *skey = nullptr, *status = nullptr;
+    float *sq = nullptr;
+    int32_t *sface = nullptr;
+    AGAL_TRY(st.get(&count, (size_t)LL.n));
+    AGAL_TRY(st.get(&off, (size_t)LL.n + 1));
+    AGAL_TRY(st.get(&status, (size_t)scan_tiles(LL.n) + 1));
+    AGAL_TRY(st.get(&skey, (size_t)cap));
+    AGAL_TRY(st.get(&sq, (size_t)cap * Q));
+    AGAL_TRY(st.get(&sface, (size_t)cap * Q));
+    LinkArgs<D, Q> A = link_args<D, Q>(g, bn, fo);
+    A.node_key = skey;
+    A.q = sq;
+    A.face = sface;
+    const int64_t waves = (LL.n + BPW - 1) / BPW;
+    {
+        ProfScope prof(ctx, "q_links", s);
+        hipLaunchKernelGGL((k_links<D, Q>), dim3((unsigned)waves), dim3(64), 0, s, A, count, status,
+                           scan_tiles(LL.n) + 1);
+    }
+    AGAL_TRY_HIP(hipGetLastError());
+    uint32_t nn = 0;
+    AGAL_TRY(scan_u32_total(ctx, count, off, LL.n, status, &nn, s));
+    AGAL_TRY((alloc_link_outputs<D, Q>(lk, nn, s)));
     if (nn > 0) {
         ProfScope prof(ctx, "q_compact", s);
-        hipLaunchKernelGGL((k_compact_nodes<Q, CELLS>), dim3((unsigned)LL.n), dim3(64), 0, s, st.count, st.off, LL.n,
-                           st.key, st.q, st.face, lk->key, lk->q, lk->face);
+        hipLaunchKernelGGL((k_compact_nodes<Q, CELLS>), dim3((unsigned)LL.n), dim3(64), 0, s, count, off, LL.n,
+                           skey, sq, sface, lk->key, lk->q, lk->face);
     }
     AGAL_TRY_HIP(hipGetLastError());
     return AGAL_OK;
+}
+
+// List mode: candidate lists, node pass, scan, row pass (rows written once).
+// A list bound above kListNoWait entries is replaced by the exact length (one
+// more host wait) rather than allocated.
+constexpr int64_t kListNoWait = int64_t(1) << 26;
+
+template <int D, int Q>
+agal_status links_forward_lists(agal_geom g, agal_bins bn, agal_forest fo, agal_links lk, int64_t max_coords,
+                                int64_t list_cap, hipStream_t s) {
+    constexpr int CELLS = D == 3 ? 64 : 16;
+    agal_context ctx = g->ctx;
+    const agal::Level &LL = fo->lev[fo->L];
+    const int64_t n = LL.n;
+    const int L = fo->L;
+    LinkArgs<D, Q> A = link_args<D, Q>(g, bn, fo);
+    CallScratch st{ctx, s};
+    BlockFind B{};
+    B.level = L;
+    B.keys = LL.keys;
+    B.n = n;
+    for (int a = 0; a < 3; ++a) B.R[a] = fo->roots[a];
+    unsigned long long *hash = nullptr, *nmask = nullptr;
+    uint32_t *lwork = nullptr, *loff = nullptr, *lblk = nullptr, *noff = nullptr, *nblk = nullptr;
+    int32_t *list = nullptr;
+    const unsigned fgrid = (unsigned)std::min<int64_t>(std::max<int64_t>((g->F + 255) / 256, 1), 8192);
+    const unsigned bgrid = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+    AGAL_TRY(st.get(&nmask, (size_t)n));
+    {
+        ProfScope prof(ctx, "q_lists", s);
+        if (L > 0) {
+            // parents: n / 2^D (complete families); at most half the slots used
+            int bits = 6;
+            while (bits < 31 && (int64_t(1) << bits) < 2 * ((n + (1 << D) - 1) >> D)) ++bits;
+            B.hmask = (uint32_t)((int64_t(1) << bits) - 1);
+            B.hshift = 32 - bits;
+            AGAL_TRY(st.get(&hash, (size_t)B.hmask + 1));
+            fill_u64(reinterpret_cast<uint64_t *>(hash), ~0ull, (int64_t)B.hmask + 1, s);
+        }
+        hipLaunchKernelGGL((k_link_blocks<D>), dim3(bgrid), dim3(256), 0, s, LL.keys, n, hash, B.hmask, B.hshift,
+                           nmask);
+        B.hash = hash;
+        LinkFaceGrid G{};
+        for (int a = 0; a < 3; ++a) {
+            G.lo[a] = fo->lo[a];
+            G.dx[a] = fo->dx[L][a];
+            G.m[a] = 2.0 * (double)A.eps[a];
+            G.NB[a] = a < D ? (fo->roots[a] << L) : 1;
+        }
+        AGAL_TRY(st.get(&lwork, (size_t)2 * n));   // counts, then scatter cursors
+        AGAL_TRY(st.get(&loff, (size_t)n + 1));
+        fill_u32(lwork, 0u, 2 * n, s);
+        hipLaunchKernelGGL((k_link_faces<D, false>), dim3(fgrid), dim3(256), 0, s, g->aabb, g->F, G, B,
+                           max_coords, lwork, nullptr, nullptr, nullptr, nullptr, 0u);
+        if (list_cap <= kListNoWait) {
+            // the bound is small enough to allocate: no host wait
+            AGAL_TRY(scan_u32(ctx, lwork, loff, n, s));
+        } else {
+            uint32_t total = 0;
+            AGAL_TRY(scan_u32_total(ctx, lwork, loff, n, nullptr, &total, s));
+            list_cap = total;
+        }
+        AGAL_TRY(st.get(&list, (size_t)std::max<int64_t>(list_cap, 1)));
+        AGAL_TRY(st.get(&lblk, (size_t)std::max<int64_t>(list_cap, 1)));
+        hipLaunchKernelGGL((k_link_faces<D, true>), dim3(fgrid), dim3(256), 0, s, g->aabb, g->F, G, B,
+                           max_coords, nullptr, loff, lwork + n, list, lblk, (uint32_t)list_cap);
+    }
+    AGAL_TRY_HIP(hipGetLastError());
+    A.loff = loff;
+    A.list = list;
+    A.list_cap = (uint32_t)list_cap;
+    {
+        // persistent waves over the list entries: eight per SIMD at most
+        const int64_t want = (list_cap + 63) / 64;
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)ctx->n_cu * 4 * 8));
+        ProfScope prof(ctx, "q_nodes", s);
+        hipLaunchKernelGGL((k_links_nodes<D, Q>), dim3(grid), dim3(64), 0, s, A, lblk, nmask);
+    }
+    AGAL_TRY_HIP(hipGetLastError());
+    AGAL_TRY(st.get(&noff, (size_t)n + 1));
+    uint32_t nn = 0;
+    AGAL_TRY(scan_popc64_total(ctx, nmask, noff, n, &nn, s));
+    AGAL_TRY((alloc_link_outputs<D, Q>(lk, nn, s)));
+    if (nn > 0) {
+        AGAL_TRY(st.get(&nblk, (size_t)nn));
+        A.node_key = lk->key;
+        A.q = lk->q;
+        A.face = lk->face;
+        ProfScope prof(ctx, "q_links", s);
+        hipLaunchKernelGGL((k_node_map<D>), dim3((unsigned)((n * CELLS + 255) / 256)), dim3(256), 0, s, nmask, noff,
+                           LL.keys, n, nblk, lk->key);
+        hipLaunchKernelGGL((k_links_rows<D, Q>), dim3((unsigned)(((int64_t)nn + 63) / 64)), dim3(64), 0, s, A, lblk,
+                           nblk, nn);
+    }
+    AGAL_TRY_HIP(hipGetLastError());
+    return AGAL_OK;
+}
+
+template <int D, int Q>
+agal_status links_forward(agal_geom g, agal_bins bn, agal_forest fo, const Lattice &, agal_links lk, hipStream_t s) {
+    agal_context ctx = g->ctx;
+    const agal::Level &LL = fo->lev[fo->L];
+    if (LL.n == 0) return alloc_link_outputs<D, Q>(lk, 0u, s);
+    // list mode while every face has few candidate blocks and the list fits
+    // 32-bit offsets
+    float dx[3], eps[3];
+    for (int a = 0; a < 3; ++a) {
+        dx[a] = fo->dx[fo->L][a];
+        eps[a] = dev::kEps * std::max(1.0f, std::max(std::fabs(fo->lo[a]), std::fabs(fo->hi[a])));
+    }
+    const double per_face = link_blocks_per_face(D, g->max_extent, dx, eps);
+    const double cap = per_face * (double)g->F;
+    if (per_face <= (double)ctx->link_list_max && cap <= (double)UINT32_MAX)
+        return links_forward_lists<D, Q>(g, bn, fo, lk, (int64_t)per_face, (int64_t)cap, s);
+    return links_forward_walk<D, Q>(g, bn, fo, lk, s);
 }
 
 template <int D, int Q>

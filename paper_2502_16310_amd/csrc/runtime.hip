@@ -172,6 +172,10 @@ struct LoadFlagU8 {
     const uint8_t *p;
     __device__ uint32_t operator()(int64_t i) const { return p[i] != 0 ? 1u : 0u; }
 };
+struct LoadPopc64 {
+    const unsigned long long *p;
+    __device__ uint32_t operator()(int64_t i) const { return (uint32_t)__popcll(p[i]); }
+};
 
 HostSignal host_signal(agal_context ctx) {
     return HostSignal{ctx->d_done, ctx->d_counts + kSyncWord, ++ctx->sync_seq};
@@ -299,6 +303,10 @@ agal_status scan_u32(agal_context ctx, const uint32_t *in, uint32_t *out, int64_
 agal_status scan_u32_total(agal_context ctx, const uint32_t *in, uint32_t *out, int64_t n, uint64_t *status,
                            uint32_t *total, hipStream_t s, bool timed) {
     return scan_impl(ctx, LoadU32{in}, out, n, s, status, total, timed);
+}
+agal_status scan_popc64_total(agal_context ctx, const unsigned long long *masks, uint32_t *out, int64_t n,
+                              uint32_t *total, hipStream_t s) {
+    return scan_impl(ctx, LoadPopc64{masks}, out, n, s, nullptr, total);
 }
 agal_status scan_flags_u8(agal_context ctx, const uint8_t *in, uint32_t *out, int64_t n, hipStream_t s) {
     return scan_impl(ctx, LoadFlagU8{in}, out, n, s);
@@ -499,6 +507,14 @@ agal_status agal_context_set_flag_table_limit(agal_context ctx, int64_t max_entr
     if (!ctx) return agal::fail(AGAL_EINVAL, "agal_context_set_flag_table_limit: NULL context");
     if (max_entries < 0) return agal::fail(AGAL_EINVAL, "agal_context_set_flag_table_limit: negative limit");
     ctx->flag_table_max = max_entries;
+    return AGAL_OK;
+}
+
+agal_status agal_context_set_link_list_limit(agal_context ctx, int64_t max_blocks_per_face) {
+    if (!ctx) return agal::fail(AGAL_EINVAL, "agal_context_set_link_list_limit: NULL context");
+    if (max_blocks_per_face < 0)
+        return agal::fail(AGAL_EINVAL, "agal_context_set_link_list_limit: negative limit");
+    ctx->link_list_max = max_blocks_per_face;
     return AGAL_OK;
 }
 

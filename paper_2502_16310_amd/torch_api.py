@@ -15,7 +15,7 @@ import torch
 
 from . import (AgalError, agal_batch_body_view, agal_batch_info, agal_batch_level_view, agal_batch_plan_create,
                agal_batch_run, agal_batch_status, agal_bin_faces, agal_bins_view, agal_context_create,
-               agal_context_set_flag_table_limit,
+               agal_context_set_flag_table_limit, agal_context_set_link_list_limit,
                agal_context_destroy, agal_destroy_batch, agal_destroy_bins, agal_destroy_forest, agal_destroy_geom,
                agal_destroy_links, agal_forest_info, agal_forest_level_view, agal_geom_view, agal_import_faces,
                agal_link_fractions, agal_link_fractions_backward, agal_links_view, agal_near_wall_refine, body_desc,
@@ -75,6 +75,12 @@ class Context:
         """Face-centric flag step for levels whose block grid has at most
         max_entries positions, cell-centric above (0: cell-centric everywhere)."""
         agal_context_set_flag_table_limit(self.h, max_entries)
+
+    def set_link_list_limit(self, max_blocks_per_face: int):
+        """Link fractions from per-block candidate lists while the largest face
+        has at most this many candidate blocks, from the bins above (0: always
+        from the bins)."""
+        agal_context_set_link_list_limit(self.h, max_blocks_per_face)
 
 
 _default_ctx: Optional[Context] = None
