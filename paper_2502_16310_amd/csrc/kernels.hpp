@@ -928,14 +928,19 @@ __device__ __forceinline__ void link_stage(LinkStaged<D, CAP> &S, int pos, int32
 // (the direction counted as its largest cell size); margins of 2^-20 times
 // those products are applied.  Returns the pairs that may meet the face (every true hit passes:
 // |t| <= 1 on the face's plane and, unless D.n is too small to have a known
-// sign, barycentrics inside).  With kSure, *sure gets the pairs that
-// certainly meet it (the same tests narrowed by the margins: the exact u, v,
+// sign, barycentrics inside).  With kSure, *sure tells whether some pair
+// certainly meets it (the same tests narrowed by the margins: the exact u, v,
 // 1 - u - v and 1 - |t| are then positive by at least half a margin, so the
 // FP64 decision finds a hit for one of the pair's two directions).
 template <int D, int NP, bool kSure, int CAP>
 __device__ __forceinline__ uint32_t link_filter(const LinkStaged<D, CAP> &S, int j, const float o[3], const float dx[3],
-                                                uint32_t *sure) {
-    uint32_t cm = 0, cs = 0;
+                                                bool *sure) {
+    // The pair-independent sums of margins are formed once: comparing
+    // atn - (MD + MT) <= ad instead of atn <= (ad + MD) + MT (and so on) moves
+    // each bound by a rounding of at most a sixteenth of a margin, within the
+    // half margin the error bounds leave free.
+    uint32_t cm = 0;
+    bool cs = false;
     if constexpr (D == 3) {
         const float T0 = o[0] - S.f[0][j], T1 = o[1] - S.f[1][j], T2 = o[2] - S.f[2][j];
         const float e10 = S.f[3][j] - S.f[0][j], e11 = S.f[4][j] - S.f[1][j], e12 = S.f[5][j] - S.f[2][j];
@@ -956,6 +961,9 @@ __device__ __forceinline__ uint32_t link_filter(const LinkStaged<D, CAP> &S, int
         const float p22 = (e10 * T1 - e11 * T0) * dx[2];
         const float d0 = n0 * dx[0], d1 = n1 * dx[1], d2 = n2 * dx[2];
         const float atn = fabsf((T0 * n0 + T1 * n1) + T2 * n2);
+        const float MDT = MD + MT, MUVD = (MU + MV) + MD;
+        const float t_lo = atn - MDT;   // |t| <= 1 possible: t_lo <= |D.n|
+        const float t_hi = atn + MDT;   // |t| < 1 certain: t_hi <= |D.n|
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const int i = 1 + 2 * p;
@@ -968,14 +976,11 @@ __device__ __forceinline__ uint32_t link_filter(const LinkStaged<D, CAP> &S, int
             const bool neg = den < 0.0f;
             const float su = neg ? -nu : nu;
             const float sv = neg ? -nv : nv;
-            const bool t_ok = atn <= ad + MD + MT;
-            const bool bary = (su >= -MU) & (sv >= -MV) & (su + sv <= ad + MU + MV + MD);
-            cm |= (t_ok & ((ad <= MD) | bary)) ? (1u << p) : 0u;
-            if constexpr (kSure) {
-                const bool in = (ad > MD) & (atn <= (ad - MD) - MT) & (su >= MU) & (sv >= MV) &
-                                (su + sv <= ((ad - MU) - MV) - MD);
-                cs |= in ? (1u << p) : 0u;
-            }
+            const float suv = su + sv;
+            const bool bary = (su >= -MU) & (sv >= -MV) & (suv - ad <= MUVD);
+            cm |= ((t_lo <= ad) & ((ad <= MD) | bary)) ? (1u << p) : 0u;
+            if constexpr (kSure)
+                cs = cs | ((ad > MD) & (t_hi <= ad) & (su >= MU) & (sv >= MV) & (suv + MUVD <= ad));
         }
     } else {
         const float w0 = S.f[0][j] - o[0], w1 = S.f[1][j] - o[1];
@@ -984,6 +989,8 @@ __device__ __forceinline__ uint32_t link_filter(const LinkStaged<D, CAP> &S, int
         const float mx_ = fmaxf(dx[0], dx[1]) * 9.5367431640625e-07f;
         const float MD = mx_ * ne, MS = mx_ * nw, MW = 9.5367431640625e-07f * nw * ne;
         const float awxe = fabsf(w0 * e1 - w1 * e0);
+        const float MDW = MD + MW, MSD = MS + MD;
+        const float t_lo = awxe - MDW, t_hi = awxe + MDW;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const int i = 1 + 2 * p;
@@ -992,13 +999,9 @@ __device__ __forceinline__ uint32_t link_filter(const LinkStaged<D, CAP> &S, int
             const float ad = fabsf(den);
             const float sn = w0 * D1 - w1 * D0;
             const float ss = den < 0.0f ? -sn : sn;
-            const bool t_ok = awxe <= ad + MD + MW;
-            const bool seg = (ss >= -MS) & (ss <= ad + MS + MD);
-            cm |= (t_ok & ((ad <= MD) | seg)) ? (1u << p) : 0u;
-            if constexpr (kSure) {
-                const bool in = (ad > MD) & (awxe <= (ad - MD) - MW) & (ss >= MS) & (ss <= (ad - MS) - MD);
-                cs |= in ? (1u << p) : 0u;
-            }
+            const bool seg = (ss >= -MS) & (ss - ad <= MSD);
+            cm |= ((t_lo <= ad) & ((ad <= MD) | seg)) ? (1u << p) : 0u;
+            if constexpr (kSure) cs = cs | ((ad > MD) & (t_hi <= ad) & (ss >= MS) & (ss + MSD <= ad));
         }
     }
     if constexpr (kSure) *sure = cs;
@@ -1413,40 +1416,6 @@ __device__ __forceinline__ void links_nodes_entries(const LinkArgs<D, Q> &A, con
     const uint32_t total = min(A.loff[A.n], A.list_cap);
     int nq = 0;   // wave-uniform queue length
 
-    // certain or FP64-decided hit for queued pair `item` (whole wave; lanes
-    // beyond `take` idle)
-    auto take = [&](int ntake) {
-        dev::wave_sync();
-        const uint32_t item = lane < ntake ? s_q[lane] : 0u;
-        dev::wave_sync();
-        if (lane < nq - ntake) s_q[lane] = s_q[ntake + lane];
-        nq -= ntake;
-        if (lane < ntake) {
-            const int j = (int)(item >> 8), cell = (int)(item & 255u);
-            const uint32_t b = s_blk[j];
-            float o[3] = {0.0f, 0.0f, 0.0f};
-            o[0] = dev::cell_centre(A.lo[0], 4 * s_bc[j][0] + (cell & 3), A.dx[0]);
-            o[1] = dev::cell_centre(A.lo[1], 4 * s_bc[j][1] + ((cell >> 2) & 3), A.dx[1]);
-            if constexpr (D == 3) o[2] = dev::cell_centre(A.lo[2], 4 * s_bc[j][2] + (cell >> 4), A.dx[2]);
-            uint32_t sure = 0;
-            uint32_t maybe = link_filter<D, NP, true, 64>(S, j, o, A.dx, &sure);
-            bool hit = sure != 0;
-            if (!hit && maybe) {
-                const double o64[3] = {o[0], o[1], o[2]};
-                while (maybe) {
-                    const int p = __builtin_ctz(maybe);
-                    maybe &= maybe - 1u;
-                    const double t = link_decide<D>(S, j, o64, s_dir[p]);
-                    if (t >= -1.0 && t <= 1.0) {
-                        hit = true;
-                        break;
-                    }
-                }
-            }
-            if (hit) atomicOr(&mask[b], 1ull << cell);
-        }
-    };
-
     for (int64_t w = blockIdx.x; w * 64 < (int64_t)total; w += gridDim.x) {
         const uint32_t e = (uint32_t)(w * 64) + (uint32_t)lane;
         uint32_t bits = 0, cnt = 0, b = 0;
@@ -1474,45 +1443,80 @@ __device__ __forceinline__ void links_nodes_entries(const LinkArgs<D, Q> &A, con
         s_bc[lane][1] = bc[1];
         s_bc[lane][2] = bc[2];
         dev::wave_sync();
-        for (uint32_t c0 = 0; c0 < npairs; c0 += dev::kWave) {
-            const uint32_t v = c0 + (uint32_t)lane;
-            bool want = false;
-            uint32_t item = 0;
-            if (v < npairs) {
-                int k = 0;   // the last entry whose pairs start at or before v
-#pragma unroll
-                for (int step = 32; step >= 1; step >>= 1)
-                    if (s_pre[k + step < 64 ? k + step : 63] <= v && k + step < 64) k += step;
-                uint32_t u = v - s_pre[k];
-                const uint32_t bk = s_bits[k];
-                const uint32_t mx = bk & 15u, my = (bk >> 4) & 15u, mz = (bk >> 8) & 15u;
-                const uint32_t nx = (uint32_t)__popc(mx), ny = (uint32_t)__popc(my);
-                const int ix = nth_bit4(mx, (int)(u % nx));
-                u /= nx;
-                int iy, iz = 0;
-                if constexpr (D == 3) {
-                    iy = nth_bit4(my, (int)(u % ny));
-                    iz = nth_bit4(mz, (int)(u / ny));
-                } else {
-                    iy = nth_bit4(my, (int)u);
-                }
-                const int cell = ix | (iy << 2) | (iz << 4);
-                const uint32_t b = s_blk[k];
-                if (!((mask[b] >> cell) & 1ull)) {
+        // one work loop: enumerate 64 pairs, queueing those still open, and
+        // decide 64 queued pairs whenever the queue holds that many (or the
+        // pairs are exhausted); each step has one place in the code
+        uint32_t c0 = 0;
+        while (true) {
+            if (nq >= 64 || (nq > 0 && c0 >= npairs)) {
+                const int ntake = min(nq, 64);
+                dev::wave_sync();
+                const uint32_t item = lane < ntake ? s_q[lane] : 0u;
+                dev::wave_sync();
+                if (lane < nq - ntake) s_q[lane] = s_q[ntake + lane];
+                nq -= ntake;
+                if (lane < ntake) {
+                    const int j = (int)(item >> 8), cell = (int)(item & 255u);
                     float o[3] = {0.0f, 0.0f, 0.0f};
-                    o[0] = dev::cell_centre(A.lo[0], 4 * s_bc[k][0] + ix, A.dx[0]);
-                    o[1] = dev::cell_centre(A.lo[1], 4 * s_bc[k][1] + iy, A.dx[1]);
-                    if constexpr (D == 3) o[2] = dev::cell_centre(A.lo[2], 4 * s_bc[k][2] + iz, A.dx[2]);
-                    want = link_reach<D>(S, k, o, A.dx);
-                    item = ((uint32_t)k << 8) | (uint32_t)cell;
+                    o[0] = dev::cell_centre(A.lo[0], 4 * s_bc[j][0] + (cell & 3), A.dx[0]);
+                    o[1] = dev::cell_centre(A.lo[1], 4 * s_bc[j][1] + ((cell >> 2) & 3), A.dx[1]);
+                    if constexpr (D == 3) o[2] = dev::cell_centre(A.lo[2], 4 * s_bc[j][2] + (cell >> 4), A.dx[2]);
+                    bool hit = false;
+                    uint32_t maybe = link_filter<D, NP, true, 64>(S, j, o, A.dx, &hit);
+                    if (!hit && maybe) {
+                        const double o64[3] = {o[0], o[1], o[2]};
+                        while (maybe) {
+                            const int p = __builtin_ctz(maybe);
+                            maybe &= maybe - 1u;
+                            const double t = link_decide<D>(S, j, o64, s_dir[p]);
+                            if (t >= -1.0 && t <= 1.0) {
+                                hit = true;
+                                break;
+                            }
+                        }
+                    }
+                    if (hit) atomicOr(&mask[s_blk[j]], 1ull << cell);
                 }
+            } else if (c0 < npairs) {
+                const uint32_t v = c0 + (uint32_t)lane;
+                c0 += dev::kWave;
+                bool want = false;
+                uint32_t item = 0;
+                if (v < npairs) {
+                    int k = 0;   // the last entry whose pairs start at or before v
+#pragma unroll
+                    for (int step = 32; step >= 1; step >>= 1)
+                        if (s_pre[k + step] <= v) k += step;
+                    uint32_t u = v - s_pre[k];
+                    const uint32_t bk = s_bits[k];
+                    const uint32_t mx = bk & 15u, my = (bk >> 4) & 15u, mz = (bk >> 8) & 15u;
+                    const uint32_t nx = (uint32_t)__popc(mx), ny = (uint32_t)__popc(my);
+                    const int ix = nth_bit4(mx, (int)(u % nx));
+                    u /= nx;
+                    int iy, iz = 0;
+                    if constexpr (D == 3) {
+                        iy = nth_bit4(my, (int)(u % ny));
+                        iz = nth_bit4(mz, (int)(u / ny));
+                    } else {
+                        iy = nth_bit4(my, (int)u);
+                    }
+                    const int cell = ix | (iy << 2) | (iz << 4);
+                    if (!((mask[s_blk[k]] >> cell) & 1ull)) {
+                        float o[3] = {0.0f, 0.0f, 0.0f};
+                        o[0] = dev::cell_centre(A.lo[0], 4 * s_bc[k][0] + ix, A.dx[0]);
+                        o[1] = dev::cell_centre(A.lo[1], 4 * s_bc[k][1] + iy, A.dx[1]);
+                        if constexpr (D == 3) o[2] = dev::cell_centre(A.lo[2], 4 * s_bc[k][2] + iz, A.dx[2]);
+                        want = link_reach<D>(S, k, o, A.dx);
+                        item = ((uint32_t)k << 8) | (uint32_t)cell;
+                    }
+                }
+                const uint64_t m = __ballot(want);
+                if (want) s_q[nq + dev::lanes_below(m)] = item;
+                nq += __popcll(m);
+            } else {
+                break;
             }
-            const uint64_t m = __ballot(want);
-            if (want) s_q[nq + dev::lanes_below(m)] = item;
-            nq += __popcll(m);
-            if (nq >= 64) take(64);
         }
-        if (nq > 0) take(nq);
         dev::wave_sync();
     }
 }
@@ -1533,6 +1537,7 @@ __device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const 
     __shared__ LinkStaged<D> S;
     __shared__ uint32_t s_sblk[kLinkCap];   // block of each staged entry
     __shared__ float s_dir[NP][3];
+    static_assert(kLinkCap <= 32, "near masks are 32-bit");
     const int lane = dev::lane_id();
     if (lane < NP)
         for (int a = 0; a < 3; ++a) s_dir[lane][a] = (float)dir_c<D>(1 + 2 * lane, a) * A.dx[a];
@@ -1618,16 +1623,16 @@ __device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const 
     // staging area is refilled
     auto test_staged = [&](int n) {
         dev::wave_sync();
-        uint64_t nm = 0;
+        uint32_t nm = 0;
         if (valid)
             for (int j = 0; j < n; ++j)
-                nm |= (s_sblk[j] == myb && (S.code[j] & lbits) == lbits) ? (1ull << j) : 0ull;
+                nm |= (s_sblk[j] == myb && (S.code[j] & lbits) == lbits) ? (1u << j) : 0u;
         while (__ballot(nm != 0)) {
             bool pass = false;
             int j = 0;
             if (nm) {
-                j = __builtin_ctzll(nm);
-                nm &= nm - 1ull;
+                j = __builtin_ctz(nm);
+                nm &= nm - 1u;
                 pass = link_reach<D>(S, j, o, A.dx);
             }
             const uint64_t m = __ballot(pass);
@@ -1688,12 +1693,18 @@ __device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const 
     // node e / Q, direction e % Q
     float *qd = A.q + k0 * Q;
     int32_t *fd = A.face + k0 * Q;
+    int l = lane / Q, i = lane % Q;   // node and direction of element e, advanced by 64 elements a step
     for (int e = lane; e < nnodes * Q; e += 64) {
-        const int l = e / Q, i = e % Q;
         const unsigned long long key = i == 0 ? ~0ull : s_best[l][i - 1];
         const bool hit = key != ~0ull;
         qd[e] = hit ? __uint_as_float((uint32_t)(key >> 32)) : -1.0f;
         fd[e] = hit ? (int32_t)(uint32_t)key : -1;
+        i += 64 % Q;
+        l += 64 / Q;
+        if (i >= Q) {
+            i -= Q;
+            ++l;
+        }
     }
 }
 

@@ -141,20 +141,30 @@ struct LinkFaceGrid {
     int NB[3];
 };
 
-// One thread per face: count (kScatter false) or write (true) the face into
-// the list of each existing candidate block.  A face with more than
-// max_coords candidate positions is skipped by both passes (the bound the
-// list was sized with makes that impossible; the test keeps the writes
+// One wave per kLinkFaceG faces: count (kScatter false) or write (true) each
+// face into the list of every existing candidate block.  The (face, block
+// position) pairs of the wave's faces are taken 64 at a time, one per lane,
+// so the hash probes of many pairs are in flight together.  A face with more
+// than max_coords candidate positions is skipped by both passes (the bound
+// the list was sized with makes that impossible; the test keeps the writes
 // inside the list whatever happens), and so is a write at or past cap.
+constexpr int kLinkFaceG = 16;
+
 template <int D, bool kScatter>
-__global__ void k_link_faces(const float *aabb, int64_t F, LinkFaceGrid G, BlockFind B, int64_t max_coords,
-                             uint32_t *cnt, const uint32_t *loff, uint32_t *cursor, int32_t *list, uint32_t *lblk,
-                             uint32_t cap) {
-    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < F; f += (int64_t)gridDim.x * blockDim.x) {
-        int b0[3] = {0, 0, 0}, b1[3] = {0, 0, 0};
-        bool any = true;
+__global__ __launch_bounds__(64) void k_link_faces(const float *aabb, int64_t F, LinkFaceGrid G, BlockFind B,
+                                                   int64_t max_coords, uint32_t *cnt, const uint32_t *loff,
+                                                   uint32_t *cursor, int32_t *list, uint32_t *lblk, uint32_t cap) {
+    __shared__ int s_i[kLinkFaceG][8];   // per face: first block per axis, positions per axis, pair prefix
+    const int lane = dev::lane_id();
+    const int64_t f0 = (int64_t)blockIdx.x * kLinkFaceG;
+    uint32_t npos = 0;
+    if (lane < kLinkFaceG) {
+        const int64_t f = f0 + lane;
+        int b0[3] = {0, 0, 0}, nb[3] = {1, 1, 1};
+        bool any = f < F;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
+            if (!any) break;
             const double mn = aabb[(int64_t)a * F + f], mx = aabb[(int64_t)(D + a) * F + f];
             double l = ceil((mn - G.lo[a] - G.m[a] - 4.5 * G.dx[a]) / (4.0 * G.dx[a]));
             double h = floor((mx - G.lo[a] + G.m[a] + 0.5 * G.dx[a]) / (4.0 * G.dx[a]));
@@ -162,29 +172,46 @@ __global__ void k_link_faces(const float *aabb, int64_t F, LinkFaceGrid G, Block
             h = h > (double)(G.NB[a] - 1) ? (double)(G.NB[a] - 1) : h;
             if (!(l <= h)) {   // outside the grid, or a non-finite coordinate
                 any = false;
-                continue;
+                break;
             }
             b0[a] = (int)l;
-            b1[a] = (int)h;
+            nb[a] = (int)(h - l) + 1;
         }
-        if (!any) continue;
-        if ((int64_t)(b1[0] - b0[0] + 1) * (b1[1] - b0[1] + 1) * (b1[2] - b0[2] + 1) > max_coords) continue;
-        for (int z = b0[2]; z <= b1[2]; ++z)
-            for (int y = b0[1]; y <= b1[1]; ++y)
-                for (int x = b0[0]; x <= b1[0]; ++x) {
-                    const int c[3] = {x, y, z};
-                    const int64_t idx = find_block<D>(B, c);
-                    if (idx < 0) continue;
-                    if constexpr (kScatter) {
-                        const uint32_t pos = loff[idx] + atomicAdd(&cursor[idx], 1u);
-                        if (pos < cap) {
-                            list[pos] = (int32_t)f;
-                            lblk[pos] = (uint32_t)idx;
-                        }
-                    } else {
-                        atomicAdd(&cnt[idx], 1u);
-                    }
-                }
+        if (any && (int64_t)nb[0] * nb[1] * nb[2] <= max_coords) npos = (uint32_t)(nb[0] * nb[1] * nb[2]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            s_i[lane][a] = b0[a];
+            s_i[lane][3 + a] = nb[a];
+        }
+    }
+    const uint32_t incl = dev::wave_inclusive_sum(npos);
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, dev::kWave - 1);
+    if (lane < kLinkFaceG) s_i[lane][6] = (int)(incl - npos);
+    dev::wave_sync();
+    for (uint32_t c0 = 0; c0 < total; c0 += dev::kWave) {
+        const uint32_t v = c0 + (uint32_t)lane;
+        if (v >= total) break;
+        int k = 0;   // the last face whose pairs start at or before v
+#pragma unroll
+        for (int step = kLinkFaceG / 2; step >= 1; step >>= 1)
+            if ((uint32_t)s_i[k + step][6] <= v) k += step;
+        uint32_t u = v - (uint32_t)s_i[k][6];
+        int c[3];
+        c[0] = s_i[k][0] + (int)(u % (uint32_t)s_i[k][3]);
+        u /= (uint32_t)s_i[k][3];
+        c[1] = s_i[k][1] + (int)(u % (uint32_t)s_i[k][4]);
+        c[2] = s_i[k][2] + (int)(u / (uint32_t)s_i[k][4]);
+        const int64_t idx = find_block<D>(B, c);
+        if (idx < 0) continue;
+        if constexpr (kScatter) {
+            const uint32_t pos = loff[idx] + atomicAdd(&cursor[idx], 1u);
+            if (pos < cap) {
+                list[pos] = (int32_t)(f0 + k);
+                lblk[pos] = (uint32_t)idx;
+            }
+        } else {
+            atomicAdd(&cnt[idx], 1u);
+        }
     }
 }
 
@@ -195,22 +222,24 @@ __global__ __launch_bounds__(64) void k_links_nodes(LinkArgs<D, Q> A, const uint
 }
 
 // Node k -> its block (nblk) and node key, from the blocks' masks and first
-// rows: one lane per (block, cell), node rank = set bits of the mask below
-// the cell.
+// rows: one thread per block writes its nodes in cell order.
 template <int D>
 __global__ __launch_bounds__(256) void k_node_map(const unsigned long long *mask, const uint32_t *noff,
                                                   const uint32_t *keys, int64_t n, uint32_t *nblk,
                                                   uint64_t *node_key) {
     constexpr int CELLS = D == 3 ? 64 : 16;
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t b = t / CELLS;
-    const int cell = (int)(t % CELLS);
-    if (b >= n) return;
-    const unsigned long long m = mask[b];
-    if (!((m >> cell) & 1ull)) return;
-    const int64_t k = (int64_t)noff[b] + __popcll(m & ((1ull << cell) - 1ull));
-    nblk[k] = (uint32_t)b;
-    node_key[k] = (uint64_t)keys[b] * CELLS + (uint64_t)cell;
+    for (int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x; b < n; b += (int64_t)gridDim.x * 256) {
+        unsigned long long m = mask[b];
+        int64_t k = noff[b];
+        const uint64_t base = (uint64_t)keys[b] * CELLS;
+        while (m) {
+            const int cell = __builtin_ctzll(m);
+            m &= m - 1ull;
+            nblk[k] = (uint32_t)b;
+            node_key[k] = base + (uint64_t)cell;
+            ++k;
+        }
+    }
 }
 
 template <int D, int Q>
@@ -342,7 +371,7 @@ agal_status links_forward_lists(agal_geom g, agal_bins bn, agal_forest fo, agal_
     unsigned long long *hash = nullptr, *nmask = nullptr;
     uint32_t *lwork = nullptr, *loff = nullptr, *lblk = nullptr, *noff = nullptr, *nblk = nullptr;
     int32_t *list = nullptr;
-    const unsigned fgrid = (unsigned)std::min<int64_t>(std::max<int64_t>((g->F + 255) / 256, 1), 8192);
+    const unsigned fgrid = (unsigned)((g->F + kLinkFaceG - 1) / kLinkFaceG);
     const unsigned bgrid = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
     AGAL_TRY(st.get(&nmask, (size_t)n));
     {
@@ -369,7 +398,7 @@ agal_status links_forward_lists(agal_geom g, agal_bins bn, agal_forest fo, agal_
         AGAL_TRY(st.get(&lwork, (size_t)2 * n));   // counts, then scatter cursors
         AGAL_TRY(st.get(&loff, (size_t)n + 1));
         fill_u32(lwork, 0u, 2 * n, s);
-        hipLaunchKernelGGL((k_link_faces<D, false>), dim3(fgrid), dim3(256), 0, s, g->aabb, g->F, G, B,
+        hipLaunchKernelGGL((k_link_faces<D, false>), dim3(fgrid), dim3(64), 0, s, g->aabb, g->F, G, B,
                            max_coords, lwork, nullptr, nullptr, nullptr, nullptr, 0u);
         if (list_cap <= kListNoWait) {
             // the bound is small enough to allocate: no host wait
@@ -381,7 +410,7 @@ agal_status links_forward_lists(agal_geom g, agal_bins bn, agal_forest fo, agal_
         }
         AGAL_TRY(st.get(&list, (size_t)std::max<int64_t>(list_cap, 1)));
         AGAL_TRY(st.get(&lblk, (size_t)std::max<int64_t>(list_cap, 1)));
-        hipLaunchKernelGGL((k_link_faces<D, true>), dim3(fgrid), dim3(256), 0, s, g->aabb, g->F, G, B,
+        hipLaunchKernelGGL((k_link_faces<D, true>), dim3(fgrid), dim3(64), 0, s, g->aabb, g->F, G, B,
                            max_coords, nullptr, loff, lwork + n, list, lblk, (uint32_t)list_cap);
     }
     AGAL_TRY_HIP(hipGetLastError());
@@ -406,8 +435,7 @@ agal_status links_forward_lists(agal_geom g, agal_bins bn, agal_forest fo, agal_
         A.q = lk->q;
         A.face = lk->face;
         ProfScope prof(ctx, "q_links", s);
-        hipLaunchKernelGGL((k_node_map<D>), dim3((unsigned)((n * CELLS + 255) / 256)), dim3(256), 0, s, nmask, noff,
-                           LL.keys, n, nblk, lk->key);
+        hipLaunchKernelGGL((k_node_map<D>), dim3(bgrid), dim3(256), 0, s, nmask, noff, LL.keys, n, nblk, lk->key);
         hipLaunchKernelGGL((k_links_rows<D, Q>), dim3((unsigned)(((int64_t)nn + 63) / 64)), dim3(64), 0, s, A, lblk,
                            nblk, nn);
     }
