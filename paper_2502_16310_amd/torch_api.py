@@ -57,11 +57,70 @@ def device_write(ptr: int, src: torch.Tensor):
             raise AgalError(3, f"hipMemcpyAsync failed with code {rc}")
 
 
-class Context:
-    """One agal_context (HIP stream-ordered pool allocator)."""
+class _TorchAllocator:
+    """agal_allocator callbacks over torch's caching allocator: the library's
+    device memory comes from (and returns to) torch's pool, on the stream the
+    library passes."""
 
     def __init__(self):
-        self.h = agal_context_create()
+        from . import _Allocator
+
+        def alloc(_ctx, nbytes, stream):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), stream or 0)
+            except RuntimeError:
+                return None   # out of memory: the library reports AGAL_ENOMEM
+
+        def free(_ctx, ptr, _stream):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        ft = _Allocator._fields_
+        self._alloc = ft[1][1](alloc)   # the callbacks must outlive every context that uses them
+        self._free = ft[2][1](free)
+        self.desc = _Allocator(None, self._alloc, self._free)
+
+
+_torch_allocator: Optional[_TorchAllocator] = None
+
+
+class _DeviceView:
+    """A device array owned by a library handle, exposed to torch without a
+    copy (CUDA array interface); holds its owner so the memory outlives every
+    tensor made from it."""
+
+    _TYPESTR = {torch.int32: "<i4", torch.int64: "<i8", torch.float32: "<f4", torch.uint8: "|u1"}
+
+    def __init__(self, ptr: int, shape: Tuple[int, ...], dtype: torch.dtype, owner):
+        self.owner = owner
+        self.__cuda_array_interface__ = {"shape": tuple(int(x) for x in shape), "typestr": self._TYPESTR[dtype],
+                                         "data": (int(ptr), False), "version": 2}
+
+
+def device_view(ptr: int, shape, dtype: torch.dtype, owner) -> torch.Tensor:
+    """Tensor aliasing `ptr` (no copy), valid while `owner` lives (the tensor keeps it alive)."""
+    shape = tuple(shape)
+    numel = 1
+    for x in shape:
+        numel *= int(x)
+    if numel == 0 or not ptr:
+        return torch.empty(shape, dtype=dtype, device=torch.device("cuda", torch.cuda.current_device()))
+    return torch.as_tensor(_DeviceView(ptr, shape, dtype, owner), device=torch.device("cuda",
+                                                                                       torch.cuda.current_device()))
+
+
+class Context:
+    """One agal_context.  By default the library allocates device memory
+    through torch's caching allocator; torch_allocator=False selects the
+    library's own stream-ordered pool."""
+
+    def __init__(self, torch_allocator: bool = True):
+        global _torch_allocator
+        if torch_allocator:
+            if _torch_allocator is None:
+                _torch_allocator = _TorchAllocator()
+            self.h = agal_context_create(_torch_allocator.desc)
+        else:
+            self.h = agal_context_create()
 
     def __del__(self):
         if getattr(self, "h", None) is not None:
@@ -121,10 +180,10 @@ class Geometry:
             self.h = None
 
     def soa(self) -> Tuple[torch.Tensor, torch.Tensor]:
+        """Views of the coordinate list and bounding boxes (valid while this object lives)."""
         _, F, _, co, bb = agal_geom_view(self.h)
         d = self.dim
-        return (device_copy(co, d * d * F, torch.float32).view(d * d, F),
-                device_copy(bb, 2 * d * F, torch.float32).view(2 * d, F))
+        return device_view(co, (d * d, F), torch.float32, self), device_view(bb, (2 * d, F), torch.float32, self)
 
     def bin_faces(self, lo, hi, B: int) -> "Bins":
         return Bins(self, lo, hi, B)
@@ -143,8 +202,9 @@ class Bins:
             self.h = None
 
     def tensors(self) -> Tuple[torch.Tensor, torch.Tensor]:
+        """Views of the CSR offsets (uint32 bits in int32) and face ids."""
         off, ids, nb, P = agal_bins_view(self.h)
-        return device_copy(off, nb + 1, torch.int32), device_copy(ids, P, torch.int32)
+        return device_view(off, (nb + 1,), torch.int32, self), device_view(ids, (P,), torch.int32, self)
 
 
 class Forest:
@@ -160,11 +220,12 @@ class Forest:
             self.h = None
 
     def level(self, l: int) -> dict:
+        """Views of one level's arrays (keys are uint32 bits in int32)."""
         k, lf, mk, cf, n = agal_forest_level_view(self.h, l)
         cells = 4 ** self.dim
-        out = {"keys": device_copy(k, n, torch.int32), "leaf": device_copy(lf, n, torch.uint8),
-               "mark": device_copy(mk, n, torch.uint8), "n": n}
-        out["cell_flag"] = device_copy(cf, n * cells, torch.uint8).view(n, cells) if cf else None
+        out = {"keys": device_view(k, (n,), torch.int32, self), "leaf": device_view(lf, (n,), torch.uint8, self),
+               "mark": device_view(mk, (n,), torch.uint8, self), "n": n}
+        out["cell_flag"] = device_view(cf, (n, cells), torch.uint8, self) if cf else None
         return out
 
     def link_fractions(self, lattice: int) -> "Links":
@@ -184,9 +245,10 @@ class Links:
             self.h = None
 
     def tensors(self) -> Tuple[torch.Tensor, torch.Tensor, torch.Tensor]:
+        """Views of node keys (uint64 bits in int64), q and face ids."""
         k, q, f, n, Q = agal_links_view(self.h)
-        return (device_copy(k, n, torch.int64), device_copy(q, n * Q, torch.float32).view(n, Q),
-                device_copy(f, n * Q, torch.int32).view(n, Q))
+        return (device_view(k, (n,), torch.int64, self), device_view(q, (n, Q), torch.float32, self),
+                device_view(f, (n, Q), torch.int32, self))
 
     def backward(self, grad_q: torch.Tensor, grad_vertices: Optional[torch.Tensor] = None) -> torch.Tensor:
         g = _require_cuda(grad_q, torch.float32, "grad_q")
@@ -201,7 +263,7 @@ class Links:
 @dataclass
 class NearWallConfig:
     """Forest, bins and lattice of one near-wall pass.  d_spec=None means one cell of the
-    tested level: d_l = (hi - lo) / (4 * roots * 2^l)."""
+    tested level, its largest extent: d_l = max over axes of (hi - lo) / (4 * roots * 2^l)."""
     dim: int
     roots: Sequence[int]
     n_levels: int
@@ -215,8 +277,12 @@ class NearWallConfig:
         if self.d_spec is not None:
             return [float(x) for x in self.d_spec]
         import numpy as np
-        span = np.float32(self.hi[0]) - np.float32(self.lo[0])
-        return [float(np.float32(span / np.float32(4 * self.roots[0] * (1 << l)))) for l in range(self.n_levels)]
+        out = []
+        for l in range(self.n_levels):
+            d = [np.float32(np.float32(self.hi[a]) - np.float32(self.lo[a])) / np.float32(4 * self.roots[a] * (1 << l))
+                 for a in range(self.dim)]
+            out.append(float(max(np.float32(x) for x in d)))
+        return out
 
 
 def near_wall(vertices: torch.Tensor, faces: Optional[torch.Tensor], cfg: NearWallConfig,
@@ -291,6 +357,7 @@ class Batch:
     def bins(self, body: int) -> int:
         return agal_batch_body_view(self.h, body)[8]
 
+    # Results are copies: a run rewrites the plan's buffers in place.
     def links(self, body: int):
         """(node_key int64, q (n, Q) float32, face (n, Q) int32) of the last run (after status())."""
         k, q, f, n, Q, _, _, _, _ = agal_batch_body_view(self.h, body)

@@ -402,3 +402,39 @@ def test_error_conventions():
         fn(h)
     agal.agal_context_destroy(ctx)
     torch.cuda.synchronize()
+
+
+def test_views_alias_library_memory_and_torch_allocator():
+    """Result tensors are views of the library's arrays (no copy) that keep their handle alive, and the
+    default context takes its device memory from torch's caching allocator."""
+    import gc
+    import torch
+    import paper_2502_16310_amd as agal
+    wl = _small_sphere(3, 4, 2, 16, 19)
+    v = torch.from_numpy(wl.vertices).cuda()
+    f = torch.from_numpy(wl.faces).cuda()
+    cfg = agal.NearWallConfig(dim=3, roots=wl.roots, n_levels=wl.levels, bins=wl.bins, lattice=wl.lattice)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    geom, bins, forest, links = agal.near_wall(v, f, cfg, ctx=agal.Context())
+    key, q, face = links.tensors()
+    torch.cuda.synchronize()
+    held = torch.cuda.memory_allocated() - before
+    k_p, q_p, f_p, n, Q = agal.agal_links_view(links.h)
+    assert (key.data_ptr(), q.data_ptr(), face.data_ptr()) == (k_p, q_p, f_p)
+    assert held >= n * (8 + 8 * Q), "library memory is not counted by torch's allocator"
+    ref = (key.cpu().clone(), q.cpu().clone(), face.cpu().clone())
+    del geom, bins, forest, links
+    gc.collect()
+    junk = torch.full((1 << 22,), -3.0, device="cuda")   # reuses freed blocks, if any were freed
+    torch.cuda.synchronize()
+    assert torch.equal(key.cpu(), ref[0]) and torch.equal(q.cpu(), ref[1]) and torch.equal(face.cpu(), ref[2])
+    log(f"  {n} nodes viewed in place; torch's allocator holds {held} bytes for the pass")
+    del junk
+    # the library's own pool: nothing is counted by torch
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    h = agal.near_wall(v, f, cfg, ctx=agal.Context(torch_allocator=False))
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() - before < n * (8 + 8 * Q)
+    del h
