@@ -5,13 +5,15 @@ forest level by level near the wall, compute the link fractions q and run
 the adjoint for a weighted sum of q -- every row of the hot path, on
 synthetic seeded geometry (see geomgen).  Prints ONE JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--config C2|C1|C4] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--config C2|C1|C4|P0|P1] [--no-cpu-baseline]
 
 The default workload is C2 (327,680-face star body, 32^3 roots, 4 passes,
 D3Q27), the largest single-body configuration.
 
 --config C4 times the batched form (64 bodies, one graph launch, forward and
-adjoint) against the same bodies through the single-body calls.
+adjoint) against the same bodies through the single-body calls.  --config P0 /
+P1 runs the paper's bin-density study on its own refinement form (own-bin
+Euclidean flags with mark propagation) for B = 1, 2, 8, 16.
 
 `value` is cell-face tests per second: the number of (cell, face) pairs the
 bins put in front of the cells (tested cells of every pass against the faces
@@ -221,6 +223,8 @@ def main():
         return
     if args.config.upper() == "C4":
         return bench_batch(args)
+    if args.config.upper() in ("P0", "P1"):
+        return bench_bin_density(args)
     wl = geomgen.workload(args.config)
     dim, Q = wl.dim, wl.lattice
     print(f"bench: {wl.name} faces={len(wl.faces)} roots={wl.roots[:dim]} levels={wl.levels} bins={wl.bins} "
@@ -562,6 +566,80 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_bin_density(args):
+    """The paper's bin-density study on its own refinement form: the Euclidean near test against the
+    faces of each cell centre's own bin, then mark propagation (P0: 12,800-segment circle, 256^2 cells,
+    d = 0.1; P1: 81,920-face star, 64^3 cells, d = 0.05; two passes), for B in 1, 2, 8, 16: bin setup and
+    refinement times (HIP events, medians of K runs) and the blocks the refinement inserts, beside the
+    bin-independent closed-box refinement of the same body."""
+    import torch
+    import geomgen
+    import paper_2502_16310_amd as agal
+
+    dev = torch.device("cuda", 0)
+    wl = geomgen.workload(args.config)
+    dim = wl.dim
+    print(f"bench: {wl.name} own-bin refinement, faces={len(wl.faces)} roots={wl.roots[:dim]} "
+          f"levels={wl.levels} d={float(wl.d_spec()[0])}", file=sys.stderr, flush=True)
+    v = torch.from_numpy(wl.vertices).to(dev)
+    f = torch.from_numpy(wl.faces).to(dev)
+    ctx = agal.agal_context_create()
+    stream = torch.cuda.current_stream().cuda_stream
+    desc = agal.forest_desc(dim, wl.roots[:dim], wl.levels, [float(x) for x in wl.d_spec()], wl.lo[:dim],
+                            wl.hi[:dim])
+    g = agal.agal_import_faces(ctx, dim, v.data_ptr(), v.shape[0], f.data_ptr(), f.shape[0], stream)
+
+    def run(B, own_bin):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        b = agal.agal_bin_faces(g, wl.lo[:dim], wl.hi[:dim], B, stream)
+        e[1].record()
+        fo = (agal.agal_near_wall_refine_own_bin(g, b, desc, -1, stream) if own_bin
+              else agal.agal_near_wall_refine(g, b, desc, stream))
+        e[2].record()
+        torch.cuda.synchronize()
+        levels = []
+        for l in range(wl.levels + 1):
+            _, _, mp, _, n = agal.agal_forest_level_view(fo, l)
+            marks = agal.device_copy(mp, n, torch.uint8).cpu().numpy() if n else np.zeros(0, np.uint8)
+            levels.append((n, np.bincount(marks, minlength=4)[:4].tolist()))
+        agal.agal_destroy_forest(fo)
+        agal.agal_destroy_bins(b)
+        return e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), levels
+
+    curve = []
+    for own_bin, Bs in ((True, (1, 2, 8, 16)), (False, (8,))):
+        for B in Bs:
+            for _ in range(args.warmup):
+                run(B, own_bin)
+            t_bin, t_ref = [], []
+            for _ in range(args.steps):
+                tb, tr, levels = run(B, own_bin)
+                t_bin.append(tb)
+                t_ref.append(tr)
+            t_bin.sort()
+            t_ref.sort()
+            blocks = [n for n, _ in levels]
+            curve.append({"form": "own-bin Euclidean + propagation" if own_bin else "closed box (all bins under it)",
+                          "B": B, "bin_ms": t_bin[len(t_bin) // 2], "refine_ms": t_ref[len(t_ref) // 2],
+                          "blocks_per_level": blocks, "inserted_blocks": int(sum(blocks[1:])),
+                          "marks_flag_balance_propagation": [m[1:4] for _, m in levels[:-1]]})
+            print(f"bench: {curve[-1]['form']} B={B}: bins {curve[-1]['bin_ms']:.3f} ms, refinement "
+                  f"{curve[-1]['refine_ms']:.3f} ms, blocks {blocks}", file=sys.stderr, flush=True)
+    agal.agal_destroy_geom(g)
+    agal.agal_context_destroy(ctx)
+    best = min((c for c in curve if c["form"].startswith("own")), key=lambda c: c["bin_ms"] + c["refine_ms"])
+    out = {"metric": "near-wall refinement ms (bins + passes) vs bin density, own-bin form", "value":
+           best["bin_ms"] + best["refine_ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": best["bin_ms"] + best["refine_ms"], "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{wl.name}: " + describe(wl), "faces": len(wl.faces), "roots": list(wl.roots[:dim]),
+                      "levels": wl.levels, "d": float(wl.d_spec()[0]), "global_batch": 1, "seq_len": 0,
+                      "parallelism": "none"},
+           "best_B": best["B"], "curve": curve, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def copy_bandwidth(torch, dev, mib=1024, reps=5):
     """Device-to-device copy rate (read + write bytes / s): the measured second denominator for % HBM."""
     n = mib * (1 << 20) // 4
@@ -588,6 +666,10 @@ def describe(wl):
         return "star body on icosphere subdivision 7 (327680 triangles), seed 0"
     if wl.name == "C3":
         return "C1 sphere jittered N(0,1e-3), seed 1"
+    if wl.name == "P0":
+        return "circle r=0.25, 12800 segments, 256^2 cells, d=0.1, 2 passes"
+    if wl.name == "P1":
+        return "star body on icosphere subdivision 6 (81920 triangles), 64^3 cells, d=0.05, 2 passes"
     return wl.name
 
 

@@ -214,7 +214,10 @@ class Workload:
         return np.float32(span / np.float32(4 * self.roots[axis] * (1 << level)))
 
     def d_spec(self) -> np.ndarray:
-        """Near-wall distance per tested level: one cell of that level (d_l = dx_l)."""
+        """Near-wall distance per tested level: one cell of that level (d_l = dx_l), or the workload's
+        constant distance (extra["d_const"], the paper's setting) on every level."""
+        if "d_const" in self.extra:
+            return np.full(self.levels, np.float32(self.extra["d_const"]), dtype=np.float32)
         return np.array([self.cell_size(l) for l in range(self.levels)], dtype=np.float32)
 
 
@@ -239,6 +242,15 @@ def workload(name: str) -> Workload:
         v = jitter_fp64(v64, 1e-3, SEED_JITTER).astype(np.float32)
         return Workload("C3", 3, v, f, (16, 16, 16), 3, 64, 19,
                         extra={"weights_seed": SEED_WEIGHTS})
+    if name == "P0":
+        # the paper's 2D study shape: a 12,800-segment circle, 256^2 cells, d = 0.1, two passes
+        v, f = circle(12800, 0.25, (0.5, 0.5))
+        return Workload("P0", 2, v, f, (64, 64, 1), 2, 8, 9, extra={"d_const": 0.1})
+    if name == "P1":
+        # the paper's 3D study at the size of its body: a star on an 81,920-face icosphere, 64^3 cells,
+        # d = 0.05, two passes
+        v, f = star(6, SEED_STAR)
+        return Workload("P1", 3, v, f, (16, 16, 16), 2, 8, 19, extra={"d_const": 0.05})
     raise KeyError(name)
 
 

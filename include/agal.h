@@ -133,8 +133,8 @@ AGAL_API agal_status agal_bins_view(agal_bins b, const uint32_t **d_offsets, con
  *                AGAL_ECAPACITY.
  * Working memory (per-bin counts and cursors, scan status) lives in a fixed
  * 32 MiB device array of the library, one per GPU, kept until the process
- * ends: 2 B^D + ids_capacity / 2048 words plus a few thousand must fit in
- * 8 Mi words (about 4.1 million bins).  Every call on one GPU uses that GPU's
+ * ends: 3 B^D + ids_capacity / 2048 words plus a few thousand must fit in
+ * 8 Mi words (about 2.8 million bins).  Every call on one GPU uses that GPU's
  * array, so calls that overlap on one GPU (other streams or host threads)
  * race; calls in sequence on one stream are safe (each clears what it needs).
  * Errors: those of agal_bin_faces; AGAL_EINVAL when the grid and capacity do
@@ -165,6 +165,21 @@ AGAL_API agal_status agal_bin_faces_noalloc(agal_geom g, const float lo[3], cons
  * geometry.  Synchronises `stream` once per pass to size the next level. */
 AGAL_API agal_status agal_near_wall_refine(agal_geom g, agal_bins b, const agal_forest_desc *desc, void *stream,
                                            agal_forest *out);
+/* The paper's own form of the near-wall refinement (Sec. II-C-2 with
+ * Algorithm 1; the propagation paragraph of Sec. II-C-3).  Pass l flags a cell
+ * when its centre lies within Euclidean distance d_spec[l] of a face of the
+ * one bin that holds the centre (FP32 point-to-face distance without
+ * divisions: edges, vertices and the face interior); then the marks spread
+ * to neighbouring blocks of the level (faces, edges, corners), one ring per
+ * step, over n_prop steps (n_prop < 0: 1 + floor(d_spec[l] / (4 dx_l)) with
+ * the smallest cell size over the axes, and none when the bins are a single
+ * bin, where every cell sees every face).  A face beyond the own bin is
+ * missed unless propagation reaches it, so the forest depends on B, as in
+ * the paper.  Exported marks: 1 flagged, 2 balance, 3 propagation; balance
+ * and children as agal_near_wall_refine.  Errors and synchronisation as
+ * agal_near_wall_refine. */
+AGAL_API agal_status agal_near_wall_refine_own_bin(agal_geom g, agal_bins b, const agal_forest_desc *desc,
+                                                   int n_prop, void *stream, agal_forest *out);
 /* How the flag step of each pass runs (the flags are identical either way).
  * Face-centric: one lane per (face, cell near the face) pair; above level 0
  * it finds blocks through a dense scratch table over the level's block grid

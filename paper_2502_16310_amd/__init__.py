@@ -73,6 +73,7 @@ def _load():
         "agal_bin_faces_noalloc": [P, C.POINTER(C.c_float), C.POINTER(C.c_float), i32, vp, vp, i64, vp,
                                    C.POINTER(i64)],
         "agal_near_wall_refine": [P, P, C.POINTER(_ForestDesc), vp, PP],
+        "agal_near_wall_refine_own_bin": [P, P, C.POINTER(_ForestDesc), C.c_int, vp, PP],
         "agal_forest_level_view": [P, C.c_int, PP, PP, PP, PP, C.POINTER(i64)],
         "agal_forest_info": [P, C.POINTER(C.c_int), C.POINTER(C.c_int)],
         "agal_link_fractions": [P, P, P, C.c_int, vp, PP],
@@ -203,6 +204,13 @@ def agal_near_wall_refine(geom, bins, desc: _ForestDesc, stream: int = 0) -> C.c
     out = C.c_void_p()
     _check(_lib.agal_near_wall_refine(_h(geom), _h(bins), C.byref(desc), stream or None, C.byref(out)),
            "agal_near_wall_refine")
+    return out
+
+
+def agal_near_wall_refine_own_bin(geom, bins, desc: _ForestDesc, n_prop: int = -1, stream: int = 0) -> C.c_void_p:
+    out = C.c_void_p()
+    _check(_lib.agal_near_wall_refine_own_bin(_h(geom), _h(bins), C.byref(desc), int(n_prop), stream or None,
+                                              C.byref(out)), "agal_near_wall_refine_own_bin")
     return out
 
 

@@ -84,7 +84,7 @@ struct Ctl {
     uint32_t overflow;   // bit 0 bins, bit 1 forest level, bit 2 nodes
     uint32_t err;        // bit 0 non-finite coordinate, bit 1 face index
     uint32_t balance;    // nonzero: a forest lost 2:1 balance
-    uint32_t big_count;
+    uint32_t lists[2];   // medium- and big-bin list counts of the canonical order
 };
 
 // Scan segment: out[0..n] = exclusive prefix of in[0..n) (n = *n_dev or n_const).
@@ -175,7 +175,8 @@ __global__ void k_b_init(const BodyDev *bodies, int nb, uint32_t *cnt, uint32_t 
         ctl->overflow = 0;
         ctl->err = 0;
         ctl->balance = 0;
-        ctl->big_count = 0;
+        ctl->lists[0] = 0;
+        ctl->lists[1] = 0;
     }
     if (blockIdx.x == 0)
         for (int i = threadIdx.x; i < nb * kLv; i += blockDim.x) {
@@ -252,16 +253,22 @@ __global__ void k_b_bin_clear(uint32_t *off_global, int64_t nb_total, const Ctl 
 }
 
 __global__ __launch_bounds__(64) void k_b_canon_small(int32_t *ids, const uint32_t *off_global, int64_t nb_total,
-                                                      uint32_t *big_list, Ctl *ctl) {
+                                                      uint32_t *med_list, uint32_t *big_list, Ctl *ctl) {
     const int64_t groups = (nb_total + dev::kWave - 1) / dev::kWave;
     for (int64_t g = blockIdx.x; g < groups; g += gridDim.x)
-        bin_canon_group(ids, off_global, nb_total, g * dev::kWave, big_list, &ctl->big_count, 0u);
+        bin_canon_group(ids, off_global, nb_total, g * dev::kWave, med_list, big_list, ctl->lists, 0u);
+}
+
+__global__ __launch_bounds__(kMedThreads) void k_b_canon_medium(int32_t *ids, const uint32_t *off_global,
+                                                                const uint32_t *med_list, const Ctl *ctl) {
+    const uint32_t nmed = ctl->lists[0];
+    for (uint32_t i = blockIdx.x; i < nmed; i += gridDim.x) bin_canon_medium(ids, off_global, med_list[i]);
 }
 
 template <int D>
 __global__ __launch_bounds__(1024) void k_b_canon_big(const BodyDev *bodies, int nb, const uint32_t *off_global,
                                                       int32_t *ids, const uint32_t *big_list, const Ctl *ctl) {
-    const uint32_t nbig = ctl->big_count;
+    const uint32_t nbig = ctl->lists[1];
     for (uint32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
         const int64_t gb = big_list[bi];
         int lo = 0, hi = nb - 1;
@@ -677,7 +684,7 @@ struct agal_batch_t {
     std::vector<void *> owned;
     uint32_t *d_cnt = nullptr, *d_nodes = nullptr, *d_cursor = nullptr;
     agal::batch::Ctl *d_ctl = nullptr;
-    uint32_t *d_bin_count = nullptr, *d_bin_off = nullptr, *d_bin_cursor = nullptr, *d_big = nullptr;
+    uint32_t *d_bin_count = nullptr, *d_bin_off = nullptr, *d_bin_cursor = nullptr, *d_big = nullptr, *d_med = nullptr;
     int32_t *d_ids = nullptr;
     int64_t nb_total = 0, cap_ids = 0;
     uint64_t *d_status = nullptr;
@@ -836,7 +843,9 @@ static agal_status capture(agal_batch bt) {
     hipLaunchKernelGGL(k_b_bin_scatter<D>, dim3(G), dim3(256), 0, s, B, nb, bt->d_bin_off, bt->d_bin_cursor, bt->d_ids,
                        bt->cap_ids, bt->d_ctl);
     hipLaunchKernelGGL(k_b_bin_clear, dim3(G), dim3(256), 0, s, bt->d_bin_off, bt->nb_total, bt->d_ctl);
-    hipLaunchKernelGGL(k_b_canon_small, dim3(G64), dim3(64), 0, s, bt->d_ids, bt->d_bin_off, bt->nb_total, bt->d_big,
+    hipLaunchKernelGGL(k_b_canon_small, dim3(G64), dim3(64), 0, s, bt->d_ids, bt->d_bin_off, bt->nb_total, bt->d_med,
+                       bt->d_big, bt->d_ctl);
+    hipLaunchKernelGGL(k_b_canon_medium, dim3(G), dim3(kMedThreads), 0, s, bt->d_ids, bt->d_bin_off, bt->d_med,
                        bt->d_ctl);
     hipLaunchKernelGGL(k_b_canon_big<D>, dim3(std::min<unsigned>(G, 256)), dim3(1024), 0, s, B, nb, bt->d_bin_off,
                        bt->d_ids, bt->d_big, bt->d_ctl);
@@ -1140,6 +1149,7 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
     AGAL_TRY(own(bt, &bt->d_bin_cursor, (size_t)bt->nb_total));
     AGAL_TRY(own(bt, &bt->d_ids, (size_t)cap_ids));
     AGAL_TRY(own(bt, &bt->d_big, (size_t)(cap_ids / 2048 + 2)));
+    AGAL_TRY(own(bt, &bt->d_med, (size_t)bt->nb_total + 1));
     for (int b = 0; b < bt->nb; ++b) {
         bt->bodies[b].bins.off = bt->d_bin_off + bt->bodies[b].bin_base;
         bt->bodies[b].bins.ids = bt->d_ids;

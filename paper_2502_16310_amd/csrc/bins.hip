@@ -5,8 +5,9 @@
 //
 // Kernels: count (one thread per face, atomics per touched bin) -> exclusive
 // scan -> scatter (atomic cursors) -> canonical order (each bin's segment
-// sorted by rank in LDS; bins too large for LDS are rebuilt by an ordered
-// sweep over all faces, which only happens when B is tiny).
+// sorted by rank in LDS: a group of 64 bins at once when its ids fit, else a
+// workgroup per bin; bins too large for LDS are rebuilt by an ordered sweep
+// over all faces, which only happens when B is tiny).
 #include <algorithm>
 
 #include "agal_internal.hpp"
@@ -34,15 +35,21 @@ __global__ void k_bin_scatter(const float *aabb, int64_t F, dev::BinGrid g, cons
 }
 
 __global__ __launch_bounds__(64) void k_bin_canon_small(int32_t *ids, const uint32_t *off, int64_t nb,
-                                                        uint32_t *big_list, uint32_t *big_count) {
-    bin_canon_group(ids, off, nb, (int64_t)blockIdx.x * dev::kWave, big_list, big_count, 0u);
+                                                        uint32_t *med_list, uint32_t *big_list, uint32_t *counts) {
+    bin_canon_group(ids, off, nb, (int64_t)blockIdx.x * dev::kWave, med_list, big_list, counts, 0u);
+}
+
+__global__ __launch_bounds__(kMedThreads) void k_bin_canon_medium(int32_t *ids, const uint32_t *off,
+                                                                  const uint32_t *med_list, const uint32_t *counts) {
+    const uint32_t nmed = counts[0];
+    for (uint32_t i = blockIdx.x; i < nmed; i += gridDim.x) bin_canon_medium(ids, off, med_list[i]);
 }
 
 template <int D>
 __global__ __launch_bounds__(kBigThreads) void k_bin_canon_big(const float *aabb, int64_t F, dev::BinGrid g,
                                                                const uint32_t *off, int32_t *ids,
-                                                               const uint32_t *big_list, const uint32_t *big_count) {
-    const uint32_t nbig = *big_count;
+                                                               const uint32_t *big_list, const uint32_t *big_count /* counts */) {
+    const uint32_t nbig = big_count[1];
     for (uint32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) bin_canon_big_bin<D>(aabb, F, g, off, ids, big_list[bi]);
 }
 
@@ -81,12 +88,12 @@ agal_status grid_spec(const char *what, int D, const float lo[3], const float hi
 }
 
 // Work words of one binning call over nb bins: per-bin counts, per-bin
-// scatter cursors, the oversized-bin counter (+ one pad word), then the
-// scan's look-back status words (64-bit).  All start at zero.
+// scatter cursors, the medium- and big-bin list counters, then the scan's
+// look-back status words (64-bit).  All start at zero.
 int64_t bin_work_words(int64_t nb) { return 2 * nb + 2 + 2 * (scan_tiles(nb) + 1); }
 
 struct BinWork {
-    uint32_t *count, *cursor, *big_count;
+    uint32_t *count, *cursor, *lists;   // lists[0], lists[1]: medium and big bin counts
     uint64_t *scan_status;
 };
 
@@ -114,9 +121,10 @@ agal_status bin_count_scan(agal_context ctx, agal_context ctx_timed, agal_geom g
 }
 
 // Scatter and canonical order into ids[0..P) (offsets from bin_count_scan);
-// big: room for P / kCanonCap + 1 oversized-bin indices.
+// med: room for nb bin indices, big: for P / kCanonCap + 1.
 agal_status bin_scatter_canon(agal_context ctx_timed, agal_geom g, const GridSpec &gs, uint32_t *work,
-                              const uint32_t *off, int32_t *ids, uint32_t P, uint32_t *big, hipStream_t s) {
+                              const uint32_t *off, int32_t *ids, uint32_t P, uint32_t *med, uint32_t *big,
+                              hipStream_t s) {
     const int64_t nb = gs.nb;
     const BinWork w = bin_work(work, nb);
     {
@@ -131,18 +139,20 @@ agal_status bin_scatter_canon(agal_context ctx_timed, agal_geom g, const GridSpe
     const int64_t groups = (nb + dev::kWave - 1) / dev::kWave;
     {
         ProfScope prof(ctx_timed, "bin_canon", s);
-        hipLaunchKernelGGL(k_bin_canon_small, dim3((unsigned)groups), dim3(dev::kWave), 0, s, ids, off, nb, big,
-                           w.big_count);
+        hipLaunchKernelGGL(k_bin_canon_small, dim3((unsigned)groups), dim3(dev::kWave), 0, s, ids, off, nb, med, big,
+                           w.lists);
+        hipLaunchKernelGGL(k_bin_canon_medium, dim3((unsigned)std::min<int64_t>(nb, 8192)), dim3(kMedThreads), 0, s,
+                           ids, off, med, w.lists);
     }
     const unsigned big_grid = (unsigned)std::min<int64_t>((int64_t)P / kCanonCap + 1, 256);
     {
         ProfScope prof(ctx_timed, "bin_canon_big", s);
         if (g->dim == 3)
             hipLaunchKernelGGL(k_bin_canon_big<3>, dim3(big_grid), dim3(kBigThreads), 0, s, g->aabb, g->F, gs.grid,
-                               off, ids, big, w.big_count);
+                               off, ids, big, w.lists);
         else
             hipLaunchKernelGGL(k_bin_canon_big<2>, dim3(big_grid), dim3(kBigThreads), 0, s, g->aabb, g->F, gs.grid,
-                               off, ids, big, w.big_count);
+                               off, ids, big, w.lists);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(AGAL_EHIP, "binning: launch failed: %s", hipGetErrorString(e));
@@ -203,9 +213,10 @@ agal_status agal_bin_faces(agal_geom g, const float lo[3], const float hi[3], in
         bn->hi[a] = gs.hi[a];
         bn->s[a] = gs.s[a];
     }
-    uint32_t *work = nullptr, *big = nullptr;
+    uint32_t *work = nullptr, *med = nullptr, *big = nullptr;
     auto cleanup = [&](agal_status st) {
         dev_free(ctx->mem, work, s);
+        dev_free(ctx->mem, med, s);
         dev_free(ctx->mem, big, s);
         if (st != AGAL_OK) agal_destroy_bins(bn);
         return st;
@@ -217,8 +228,9 @@ agal_status agal_bin_faces(agal_geom g, const float lo[3], const float hi[3], in
     if (st != AGAL_OK) return cleanup(st);
     bn->P = P;
     st = dev_alloc(ctx->mem, &bn->ids, (size_t)std::max<uint32_t>(P, 1u), s);
+    if (st == AGAL_OK) st = dev_alloc(ctx->mem, &med, (size_t)nb, s);
     if (st == AGAL_OK) st = dev_alloc(ctx->mem, &big, (size_t)P / kCanonCap + 1, s);
-    if (st == AGAL_OK) st = bin_scatter_canon(ctx, g, gs, work, bn->off, bn->ids, P, big, s);
+    if (st == AGAL_OK) st = bin_scatter_canon(ctx, g, gs, work, bn->off, bn->ids, P, med, big, s);
     if (cleanup(st) != AGAL_OK) return st;
     *out = bn;
     return AGAL_OK;
@@ -241,16 +253,17 @@ agal_status agal_bin_faces_noalloc(agal_geom g, const float lo[3], const float h
     if (!base)
         return fail(AGAL_EHIP, "agal_bin_faces_noalloc: the scratch address of device %d is unknown (%s)", dev_id,
                     "hipGetSymbolAddress failed when the context was created");
-    // scratch: the work words, then the oversized-bin list (at most
-    // ids_capacity / kCanonCap + 1 bins hold more than kCanonCap ids)
+    // scratch: the work words, the medium-bin list (one word per bin), then
+    // the big-bin list (at most ids_capacity / kCanonCap + 1 bins hold more
+    // than kCanonCap ids)
     const int64_t work_words = bin_work_words(gs.nb);
     const int64_t big_words = std::min<int64_t>(ids_capacity, (int64_t)UINT32_MAX) / kCanonCap + 1;
-    if (work_words + big_words > kNoallocScratchWords)
+    if (work_words + gs.nb + big_words > kNoallocScratchWords)
         return fail(AGAL_EINVAL,
                     "agal_bin_faces_noalloc: %lld bins and %lld id slots need %lld scratch words; the fixed scratch "
                     "holds %lld (at most about %lld bins)",
-                    (long long)gs.nb, (long long)ids_capacity, (long long)(work_words + big_words),
-                    (long long)kNoallocScratchWords, (long long)((kNoallocScratchWords - big_words) / 2 - 2048));
+                    (long long)gs.nb, (long long)ids_capacity, (long long)(work_words + gs.nb + big_words),
+                    (long long)kNoallocScratchWords, (long long)((kNoallocScratchWords - big_words) / 3 - 2048));
     hipStream_t s = (hipStream_t)stream;
     uint32_t P = 0;
     AGAL_TRY(bin_count_scan(ctx, nullptr, g, gs, base, d_offsets, &P, s));
@@ -258,7 +271,8 @@ agal_status agal_bin_faces_noalloc(agal_geom g, const float lo[3], const float h
     if ((int64_t)P > ids_capacity)
         return fail(AGAL_ECAPACITY, "agal_bin_faces_noalloc: %u (face, bin) entries exceed ids_capacity %lld", P,
                     (long long)ids_capacity);
-    return bin_scatter_canon(nullptr, g, gs, base, d_offsets, d_face_ids, P, base + work_words, s);
+    return bin_scatter_canon(nullptr, g, gs, base, d_offsets, d_face_ids, P, base + work_words,
+                             base + work_words + gs.nb, s);
 }
 
 agal_status agal_bins_view(agal_bins b, const uint32_t **d_offsets, const int32_t **d_face_ids, int64_t *n_bins,

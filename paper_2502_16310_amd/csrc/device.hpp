@@ -209,6 +209,94 @@ __device__ __forceinline__ bool sat_segment(const float v[4], const float m[2], 
     return true;
 }
 
+
+// Euclidean near test of the paper's face detection (Sec. II-C-2, Algorithm
+// 1): is the point p within distance R of the closed face?  Decided in FP32
+// as one fixed sequence of rounded operations, without divisions (a squared
+// distance c / m is compared as c <= R^2 m):
+//   R2 = R * R; for each closed edge [a, b] (2D: the segment; 3D: the three
+//   edges (v0,v1), (v1,v2), (v2,v0)), with w = p - a, e = b - a, we = w.e:
+//     we <= 0   -> near when w.w <= R2 (the nearest point is a);
+//     we >= e.e -> near when u.u <= R2, u = p - b (the nearest point is b);
+//     otherwise -> near when |e x w|^2 <= R2 (e.e) (2D: (e0 w1 - e1 w0)^2);
+//   3D, the face itself: n = (v1 - v0) x (v2 - v0); when n.n > 0 and p
+//   projects inside (((v_{k+1} - v_k) x (p - v_k)) . n >= 0 for all three
+//   edges), near when ((p - v0) . n)^2 <= R2 (n.n).
+// Dot products are (x0 y0 + x1 y1) + x2 y2, cross products
+// (a1 b2 - a2 b1, a2 b0 - a0 b2, a0 b1 - a1 b0).
+__device__ __forceinline__ float dot3_(const float *a, const float *b) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+__device__ __forceinline__ void cross3_(const float *a, const float *b, float *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+template <int D>
+__device__ __forceinline__ bool edge_near_l2(const float *a, const float *b, const float *p, float R2) {
+    float w[3] = {0.0f, 0.0f, 0.0f}, e[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        w[k] = p[k] - a[k];
+        e[k] = b[k] - a[k];
+    }
+    const float we = D == 3 ? dot3_(w, e) : w[0] * e[0] + w[1] * e[1];
+    if (we <= 0.0f) return (D == 3 ? dot3_(w, w) : w[0] * w[0] + w[1] * w[1]) <= R2;
+    const float ee = D == 3 ? dot3_(e, e) : e[0] * e[0] + e[1] * e[1];
+    if (we >= ee) {
+        float u[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int k = 0; k < D; ++k) u[k] = p[k] - b[k];
+        return (D == 3 ? dot3_(u, u) : u[0] * u[0] + u[1] * u[1]) <= R2;
+    }
+    float cc;
+    if constexpr (D == 3) {
+        float c[3];
+        cross3_(e, w, c);
+        cc = dot3_(c, c);
+    } else {
+        const float cr = e[0] * w[1] - e[1] * w[0];
+        cc = cr * cr;
+    }
+    return cc <= R2 * ee;
+}
+
+template <int D>
+__device__ __forceinline__ bool near_l2(const float *v, const float *p, float R) {
+    const float R2 = R * R;
+    if constexpr (D == 2) {
+        return edge_near_l2<2>(v, v + 2, p, R2);
+    } else {
+        if (edge_near_l2<3>(v, v + 3, p, R2) || edge_near_l2<3>(v + 3, v + 6, p, R2) ||
+            edge_near_l2<3>(v + 6, v, p, R2))
+            return true;
+        float e1[3], e2[3], n[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            e1[a] = v[3 + a] - v[a];
+            e2[a] = v[6 + a] - v[a];
+        }
+        cross3_(e1, e2, n);
+        const float nn = dot3_(n, n);
+        if (!(nn > 0.0f)) return false;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float *a = v + 3 * k, *b = v + 3 * ((k + 1) % 3);
+            float e[3], w[3], c[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                e[j] = b[j] - a[j];
+                w[j] = p[j] - a[j];
+            }
+            cross3_(e, w, c);
+            if (!(dot3_(c, n) >= 0.0f)) return false;
+        }
+        float w0[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) w0[j] = p[j] - v[j];
+        const float hh = dot3_(w0, n);
+        return hh * hh <= R2 * nn;
+    }
+}
 // ---------------------------------------------------------------------------
 // Wave helpers
 // ---------------------------------------------------------------------------

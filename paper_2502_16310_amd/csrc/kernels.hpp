@@ -90,6 +90,38 @@ __device__ __forceinline__ void face_bin_range(const float *aabb, int64_t F, int
     }
 }
 
+// atomicAdd(p, 1) for every active lane, returning its old value, with the
+// lanes whose counter is the first active lane's combined into one atomic (up
+// to four such rounds; the rest add alone).  With few bins many faces of a
+// wave share one, and same-address atomics from every face would serialise.
+// Lanes are matched by address, so lanes of different arrays never combine.
+// Slots of combined lanes follow the lane order.
+__device__ __forceinline__ uint32_t add_one_combined(uint32_t *p) {
+    const int lane = dev::lane_id();
+    const uint64_t a = (uint64_t)(uintptr_t)p;
+    bool pending = true;
+    uint32_t slot = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint64_t act = __ballot(pending);
+        if (!act) break;
+        const int leader = __builtin_ctzll(act);
+        const uint64_t la = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(a >> 32), leader) << 32) |
+                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)a, leader);
+        const bool mine = pending && a == la;
+        const uint64_t m = __ballot(mine);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(p, (uint32_t)__popcll(m));
+        base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+        if (mine) {
+            slot = base + (uint32_t)dev::lanes_below(m);
+            pending = false;
+        }
+    }
+    if (pending) slot = atomicAdd(p, 1u);
+    return slot;
+}
+
 template <int D>
 __device__ __forceinline__ void bin_count_item(const float *aabb, int64_t F, const dev::BinGrid &g, uint32_t *count,
                                                int64_t f) {
@@ -99,7 +131,7 @@ __device__ __forceinline__ void bin_count_item(const float *aabb, int64_t F, con
         for (int z = lo[2]; z <= hi[2]; ++z)
             for (int y = lo[1]; y <= hi[1]; ++y)
                 for (int x = lo[0]; x <= hi[0]; ++x)
-                    atomicAdd(&count[((int64_t)z * g.B + y) * g.B + x], 1u);
+                    (void)add_one_combined(count + ((int64_t)z * g.B + y) * g.B + x);
     }
 }
 
@@ -113,7 +145,7 @@ __device__ __forceinline__ void bin_scatter_item(const float *aabb, int64_t F, c
             for (int y = lo[1]; y <= hi[1]; ++y)
                 for (int x = lo[0]; x <= hi[0]; ++x) {
                     int64_t b = ((int64_t)z * g.B + y) * g.B + x;
-                    uint32_t pos = off[b] + atomicAdd(&cursor[b], 1u);
+                    uint32_t pos = off[b] + add_one_combined(cursor + b);
                     ids[pos] = (int32_t)f;
                 }
     }
@@ -146,10 +178,15 @@ __device__ void rank_sort_segment(int32_t *ids, const uint32_t *s_off, int nbins
     __syncthreads();
 }
 
-// One wave: the group of 64 consecutive bins starting at b0.  Oversized bins
-// are appended to big_list as big_tag + bin.
+// One wave: the group of 64 consecutive bins starting at b0.  A group whose
+// ids fit the LDS segment is rank-sorted here in one go; otherwise each of
+// its bins with more than one id goes to a list of its own: the medium list
+// (at most kCanonCap ids: rank-sorted by a workgroup per bin) or, tagged with
+// big_tag, the big list (rebuilt by an ordered sweep).  Lists are appended
+// through counters (lists[0], lists[1] = medium and big counts).
 __device__ __forceinline__ void bin_canon_group(int32_t *ids, const uint32_t *off, int64_t nb, int64_t b0,
-                                                uint32_t *big_list, uint32_t *big_count, uint32_t big_tag) {
+                                                uint32_t *med_list, uint32_t *big_list, uint32_t *counts,
+                                                uint32_t big_tag) {
     __shared__ uint32_t s_off[dev::kWave + 1];
     __shared__ int32_t s_val[kCanonCap];
     const int nbins = (int)std::min<int64_t>(dev::kWave, nb - b0);
@@ -165,19 +202,29 @@ __device__ __forceinline__ void bin_canon_group(int32_t *ids, const uint32_t *of
         rank_sort_segment(ids, s_off, nbins, g0, g1, s_val);
         return;
     }
-    // group too large: bin by bin
-    for (int b = 0; b < nbins; ++b) {
-        const uint32_t a0 = s_off[b], a1 = s_off[b + 1];
-        if (a1 - a0 <= 1) continue;
-        if (a1 - a0 <= (uint32_t)kCanonCap) {
-            __shared__ uint32_t s_one[2];
-            if (lane == 0) { s_one[0] = a0; s_one[1] = a1; }
-            __syncthreads();
-            rank_sort_segment(ids, s_one, 1, a0, a1, s_val);
-        } else if (lane == 0) {
-            uint32_t k = atomicAdd(big_count, 1u);
-            big_list[k] = big_tag + (uint32_t)(b0 + b);
-        }
+    // group too large: each bin on its own (one lane per bin of the group)
+    if (lane < nbins) {
+        const uint32_t a0 = s_off[lane], a1 = s_off[lane + 1];
+        if (a1 - a0 > (uint32_t)kCanonCap) big_list[atomicAdd(counts + 1, 1u)] = big_tag + (uint32_t)(b0 + lane);
+        else if (a1 - a0 > 1) med_list[atomicAdd(counts, 1u)] = (uint32_t)(b0 + lane);
+    }
+    __syncthreads();
+}
+
+// One workgroup of kMedThreads threads: bin b's segment (at most kCanonCap
+// ids) sorted by rank in LDS.
+constexpr int kMedThreads = 256;
+__device__ __forceinline__ void bin_canon_medium(int32_t *ids, const uint32_t *off, int64_t b) {
+    __shared__ int32_t s_val[kCanonCap];
+    const uint32_t s0 = off[b], s1 = off[b + 1];
+    const int n = (int)(s1 - s0);
+    for (int e = threadIdx.x; e < n; e += kMedThreads) s_val[e] = ids[s0 + e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < n; e += kMedThreads) {
+        const int32_t v = s_val[e];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) rank += s_val[j] < v ? 1 : 0;
+        ids[s0 + rank] = v;
     }
     __syncthreads();
 }
@@ -591,6 +638,104 @@ __device__ __forceinline__ void flag_wave(const FlagArgs<D> &A, int64_t first) {
         if constexpr (CELLS < 64) bm = (fm >> (lane & ~(CELLS - 1))) & ((1ull << CELLS) - 1);
         A.pmark[blk] = bm ? 1 : 0;
     }
+}
+
+// Own-bin flag pass, the paper's face detection as printed (Sec. II-C-2 with
+// Algorithm 1, bins of Sec. II-C-3): a cell looks only at the faces of the one
+// bin that holds its centre (bin index function of the binning) and is
+// flagged when its centre lies within Euclidean distance h of one of them
+// (near_l2).  One wave: blocks first .. first + 64/4^D - 1 (one lane per
+// cell).  The wave takes the distinct own bins of its lanes one after the
+// other; each bin's faces are staged 64 at a time (one record per lane, in
+// LDS) and the lanes of that bin test them, each stopping at its first near
+// face.  Writes every cell flag and the block's pass mark (0 or 1).
+template <int D>
+__device__ __forceinline__ void flag_own_bin_wave(const FlagArgs<D> &A, int64_t first) {
+    constexpr int CELLS = D == 3 ? 64 : 16;
+    constexpr int RF = dev::kRecFloats<D>;
+    __shared__ float s_v[64][D * D];
+    const int lane = dev::lane_id();
+    const int64_t blk = first + lane / CELLS;
+    const bool valid = blk < A.n;
+    const int cell = lane % CELLS;
+    int bc[3] = {0, 0, 0};
+    if (valid) dev::decode_key<D>(A.keys[blk], A.level, A.R[0], A.R[1], bc);
+    float m[3] = {0.0f, 0.0f, 0.0f};
+    m[0] = dev::cell_centre(A.lo[0], 4 * bc[0] + (cell & 3), A.dx[0]);
+    m[1] = dev::cell_centre(A.lo[1], 4 * bc[1] + ((cell >> 2) & 3), A.dx[1]);
+    if constexpr (D == 3) m[2] = dev::cell_centre(A.lo[2], 4 * bc[2] + (cell >> 4), A.dx[2]);
+    int ib[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) ib[a] = dev::bin_of(m[a], A.bins.lo[a], A.bins.s[a], A.bins.B);
+    const int mybin = (ib[2] * A.bins.B + ib[1]) * A.bins.B + ib[0];   // B^D < 2^31 (checked when binning)
+    bool flagged = false;
+    bool done = !valid;
+    while (true) {
+        const uint64_t open = __ballot(!done);
+        if (!open) break;
+        const int leader = __builtin_ctzll(open);
+        const int bin = __builtin_amdgcn_readlane(mybin, leader);
+        const bool mine = !done && mybin == bin;
+        const uint32_t s0 = A.bins.off[bin], s1 = A.bins.off[bin + 1];
+        for (uint32_t c0 = s0; c0 < s1; c0 += dev::kWave) {
+            if (!__ballot(mine && !flagged)) break;   // every cell of this bin decided
+            const uint32_t e = c0 + (uint32_t)lane;
+            if (e < s1) {
+                float r[RF];
+                dev::load_rec<D>(A.faces.rec, A.bins.ids[e], r);
+#pragma unroll
+                for (int k = 0; k < D * D; ++k) s_v[lane][k] = r[k];
+            }
+            dev::wave_sync();
+            const int nf = (int)min(s1 - c0, (uint32_t)dev::kWave);
+            if (mine && !flagged)
+                for (int j = 0; j < nf; ++j) {
+                    float v[D * D];
+#pragma unroll
+                    for (int k = 0; k < D * D; ++k) v[k] = s_v[j][k];
+                    if (dev::near_l2<D>(v, m, A.h)) {
+                        flagged = true;
+                        break;
+                    }
+                }
+            dev::wave_sync();
+        }
+        done = done || mine;
+    }
+    if (valid) A.cf[blk * CELLS + cell] = flagged ? 1 : 0;
+    const uint64_t fm = __ballot(valid && flagged);
+    if (valid && cell == 0) {
+        uint64_t bm = fm;
+        if constexpr (CELLS < 64) bm = (fm >> (lane & ~(CELLS - 1))) & ((1ull << CELLS) - 1);
+        A.pmark[blk] = bm ? 1 : 0;
+    }
+}
+
+// Mark propagation of the own-bin pass (Sec. II-C-3), one step in two
+// launches so that a step grows the marked set by exactly one ring whatever
+// the order of the threads: (1) every unmarked level-l neighbour (faces,
+// edges, corners; inside the domain; present at level l) of a block whose
+// pass mark is 1 (flagged) or 3 (propagated) gets the intermediate value 4;
+// (2) every 4 becomes 3.  One thread per (block, neighbour position).
+template <int D>
+__device__ __forceinline__ void prop_spread_item(const uint32_t *keys, int64_t n, uint8_t *pm, int l, int R0, int R1,
+                                                 int R2, int64_t t) {
+    constexpr int NNB = D == 3 ? 26 : 8;
+    const int64_t i = t / NNB;
+    const uint8_t p = pm[i];
+    if (p != 1 && p != 3) return;
+    int k = (int)(t % NNB);
+    k += k >= NNB / 2 ? 1 : 0;   // skip the centre of the 3^D stencil
+    const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = D == 3 ? k / 9 - 1 : 0;
+    int c[3];
+    dev::decode_key<D>(keys[i], l, R0, R1, c);
+    const int ext[3] = {R0 << l, R1 << l, R2 << l};
+    int nc[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+    if (nc[0] < 0 || nc[0] >= ext[0] || nc[1] < 0 || nc[1] >= ext[1]) return;
+    if (D == 3 && (nc[2] < 0 || nc[2] >= ext[2])) return;
+    const uint32_t kn = dev::encode_key<D>(nc, l, R0, R1);
+    const int64_t j = dev::lower_bound_u32(keys, n, kn);
+    if (j < n && keys[j] == kn && pm[j] == 0) pm[j] = 4;
 }
 
 // Face-centric flag pass.  A cell's flag is an OR over faces of one FP32 test

@@ -34,6 +34,20 @@ __global__ __launch_bounds__(64) void k_flag(FlagArgs<D> A) {
     flag_wave<D, kDedup>(A, (int64_t)blockIdx.x * (D == 3 ? 1 : 4));
 }
 
+template <int D>
+__global__ __launch_bounds__(64) void k_flag_own_bin(FlagArgs<D> A) {
+    flag_own_bin_wave<D>(A, (int64_t)blockIdx.x * (D == 3 ? 1 : 4));
+}
+
+template <int D>
+__global__ void k_prop_spread(const uint32_t *keys, int64_t n, uint8_t *pm, int l, int R0, int R1, int R2) {
+    AGAL_GRID_STRIDE(t, n * (D == 3 ? 26 : 8)) prop_spread_item<D>(keys, n, pm, l, R0, R1, R2, t);
+}
+
+__global__ void k_prop_commit(uint8_t *pm, int64_t n) {
+    AGAL_GRID_STRIDE(i, n) if (pm[i] == 4) pm[i] = 3;
+}
+
 template <int D, int G>
 __global__ __launch_bounds__(64 * kFaceFlagWaves) void k_flag_faces(FaceFlagArgs<D> A) {
     __shared__ float s_rec[kFaceFlagWaves][G][dev::kRecFloats<D>];
@@ -197,8 +211,21 @@ int64_t block_grid_size(const agal_forest_t *fo, int l) {
     return e;
 }
 
+// Propagation steps of an own-bin pass (Sec. II-C-3): one more than the whole
+// number of block lengths in the distance, 1 + floor(d / (4 dx)) with the
+// smallest cell size over the axes (FP32); none with one bin, where every cell
+// sees every face.  n_prop >= 0 overrides the rule.
+inline int prop_steps(const agal_forest_t *fo, int l, int B, int n_prop) {
+    if (n_prop >= 0) return n_prop;
+    if (B <= 1) return 0;
+    float dxm = fo->dx[l][0];
+    for (int a = 1; a < fo->dim; ++a) dxm = std::min(dxm, fo->dx[l][a]);
+    return 1 + (int)std::floor(fo->d[l] / (4.0f * dxm));
+}
+
 template <int D>
-agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s) {
+agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s, bool own_bin = false,
+                        int n_prop = -1) {
     constexpr int CELLS = D == 3 ? 64 : 16;
     constexpr int BPW = 64 / CELLS;
     agal_context ctx = g->ctx;
@@ -255,7 +282,7 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
         agal::Level &Ll = fo->lev[l];
         float eps_l[3];
         for (int a = 0; a < 3; ++a) eps_l[a] = dev::kEps * std::max(1.0f, std::max(std::fabs(fo->lo[a]), std::fabs(fo->hi[a])));
-        const bool by_face = block_grid_size<D>(fo, l) <= ctx->flag_table_max &&
+        const bool by_face = !own_bin && block_grid_size<D>(fo, l) <= ctx->flag_table_max &&
                              face_flag_pairs(D, g->max_extent, fo->d[l], fo->dx[l], eps_l) <= kFaceFlagMaxPairs;
         // the block table of level l (face-centric step above level 0): never
         // cleared, its entries are checked against the level's keys
@@ -298,7 +325,9 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
             const int64_t waves = (Ll.n + BPW - 1) / BPW;
             ProfScope prof(ctx, "flag_sat", s);
             const bool dedup = flag_dedup<D>(bn, fo->dx[l], A.h, Ll.n, ctx->n_cu);
-            if (by_face) {
+            if (own_bin) {
+                hipLaunchKernelGGL((k_flag_own_bin<D>), dim3((unsigned)waves), dim3(64), 0, s, A);
+            } else if (by_face) {
                 FaceFlagArgs<D> B{};
                 B.rec = g->rec;
                 B.F = g->F;
@@ -333,6 +362,16 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
                 hipLaunchKernelGGL((k_flag<D, true>), dim3((unsigned)waves), dim3(64), 0, s, A);
             } else {
                 hipLaunchKernelGGL((k_flag<D, false>), dim3((unsigned)waves), dim3(64), 0, s, A);
+            }
+        }
+        // (i') own-bin pass: the marks spread over prop_steps rings of level-l blocks
+        if (own_bin && Ll.n > 0) {
+            const int steps = prop_steps(fo, l, bn->B, n_prop);
+            ProfScope prof(ctx, "mark_propagation", s);
+            for (int st = 0; st < steps; ++st) {
+                hipLaunchKernelGGL(k_prop_spread<D>, dim3(grid_for(Ll.n * (D == 3 ? 26 : 8))), dim3(256), 0, s,
+                                   Ll.keys, Ll.n, pm[l], l, fo->roots[0], fo->roots[1], fo->roots[2]);
+                hipLaunchKernelGGL(k_prop_commit, dim3(grid_for(Ll.n)), dim3(256), 0, s, pm[l], Ll.n);
             }
         }
         // (ii) balance ripple, level l down to 1
@@ -437,8 +476,8 @@ using namespace agal;
 
 extern "C" {
 
-agal_status agal_near_wall_refine(agal_geom g, agal_bins b, const agal_forest_desc *desc, void *stream,
-                                  agal_forest *out) {
+static agal_status near_wall_refine(agal_geom g, agal_bins b, const agal_forest_desc *desc, void *stream,
+                                    agal_forest *out, bool own_bin, int n_prop) {
     if (!g || !b || !desc || !out) return fail(AGAL_EINVAL, "agal_near_wall_refine: NULL argument");
     if (b->geom_id != g->id) return fail(AGAL_ESTATE, "agal_near_wall_refine: bins were built from another geometry");
     const int D = desc->dim;
@@ -473,13 +512,24 @@ agal_status agal_near_wall_refine(agal_geom g, agal_bins b, const agal_forest_de
     for (int l = 0; l <= fo->L; ++l)
         for (int a = 0; a < 3; ++a) fo->dx[l][a] = (fo->hi[a] - fo->lo[a]) / (float)(4 * fo->roots[a] * (1 << l));
     for (int l = 0; l < fo->L; ++l) fo->d[l] = desc->d_spec[l];
-    agal_status st = D == 3 ? refine_impl<3>(g, b, fo, (hipStream_t)stream) : refine_impl<2>(g, b, fo, (hipStream_t)stream);
+    agal_status st = D == 3 ? refine_impl<3>(g, b, fo, (hipStream_t)stream, own_bin, n_prop)
+                            : refine_impl<2>(g, b, fo, (hipStream_t)stream, own_bin, n_prop);
     if (st != AGAL_OK) {
         agal_destroy_forest(fo);
         return st;
     }
     *out = fo;
     return AGAL_OK;
+}
+
+agal_status agal_near_wall_refine(agal_geom g, agal_bins b, const agal_forest_desc *desc, void *stream,
+                                  agal_forest *out) {
+    return near_wall_refine(g, b, desc, stream, out, false, -1);
+}
+
+agal_status agal_near_wall_refine_own_bin(agal_geom g, agal_bins b, const agal_forest_desc *desc, int n_prop,
+                                          void *stream, agal_forest *out) {
+    return near_wall_refine(g, b, desc, stream, out, true, n_prop);
 }
 
 agal_status agal_forest_level_view(agal_forest f, int level, const uint32_t **d_keys, const uint8_t **d_leaf,

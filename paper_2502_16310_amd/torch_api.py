@@ -18,7 +18,8 @@ from . import (AgalError, agal_batch_body_view, agal_batch_info, agal_batch_leve
                agal_context_set_flag_table_limit, agal_context_set_link_list_limit,
                agal_context_destroy, agal_destroy_batch, agal_destroy_bins, agal_destroy_forest, agal_destroy_geom,
                agal_destroy_links, agal_forest_info, agal_forest_level_view, agal_geom_view, agal_import_faces,
-               agal_link_fractions, agal_link_fractions_backward, agal_links_view, agal_near_wall_refine, body_desc,
+               agal_link_fractions, agal_link_fractions_backward, agal_links_view, agal_near_wall_refine,
+               agal_near_wall_refine_own_bin, body_desc,
                forest_desc, tune_opts)
 
 _hip = None
@@ -208,10 +209,18 @@ class Bins:
 
 
 class Forest:
-    def __init__(self, geom: Geometry, bins: Bins, dim, roots, n_levels, d_spec, lo, hi):
+    """Near-wall refinement.  own_bin=True takes the paper's own form: a cell
+    looks at the faces of its own bin with the Euclidean test, and marks
+    spread over n_prop rings of blocks (n_prop < 0: the paper's rule)."""
+
+    def __init__(self, geom: Geometry, bins: Bins, dim, roots, n_levels, d_spec, lo, hi, own_bin: bool = False,
+                 n_prop: int = -1):
         self.geom, self.bins = geom, bins
         self.desc = forest_desc(dim, roots, n_levels, d_spec, lo, hi)
-        self.h = agal_near_wall_refine(geom.h, bins.h, self.desc, current_stream())
+        if own_bin:
+            self.h = agal_near_wall_refine_own_bin(geom.h, bins.h, self.desc, n_prop, current_stream())
+        else:
+            self.h = agal_near_wall_refine(geom.h, bins.h, self.desc, current_stream())
         self.dim, self.n_levels = agal_forest_info(self.h)
 
     def __del__(self):
@@ -272,6 +281,8 @@ class NearWallConfig:
     lo: Sequence[float] = (0.0, 0.0, 0.0)
     hi: Sequence[float] = (1.0, 1.0, 1.0)
     d_spec: Optional[Sequence[float]] = None
+    own_bin: bool = False     # the paper's own-bin Euclidean flags with mark propagation
+    n_prop: int = -1          # propagation steps of the own-bin form (< 0: the paper's rule)
 
     def distances(self) -> List[float]:
         if self.d_spec is not None:
@@ -291,7 +302,8 @@ def near_wall(vertices: torch.Tensor, faces: Optional[torch.Tensor], cfg: NearWa
     ctx = ctx or default_context()
     geom = ctx.import_faces(vertices, faces)
     bins = geom.bin_faces(cfg.lo[:cfg.dim], cfg.hi[:cfg.dim], cfg.bins)
-    forest = Forest(geom, bins, cfg.dim, cfg.roots, cfg.n_levels, cfg.distances(), cfg.lo, cfg.hi)
+    forest = Forest(geom, bins, cfg.dim, cfg.roots, cfg.n_levels, cfg.distances(), cfg.lo, cfg.hi, cfg.own_bin,
+                    cfg.n_prop)
     links = forest.link_fractions(cfg.lattice) if with_links else None
     return geom, bins, forest, links
 

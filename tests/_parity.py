@@ -16,7 +16,7 @@ def log(msg):
     sys.stdout.flush()
 
 
-def gpu_run(wl, B=None, with_links=True, lattice=None, d_spec=None, levels=None, ctx=None):
+def gpu_run(wl, B=None, with_links=True, lattice=None, d_spec=None, levels=None, ctx=None, own_bin=False, n_prop=-1):
     import torch
     import paper_2502_16310_amd as agal
     dev = torch.device("cuda", 0)
@@ -25,7 +25,8 @@ def gpu_run(wl, B=None, with_links=True, lattice=None, d_spec=None, levels=None,
     L = wl.levels if levels is None else levels
     cfg = agal.NearWallConfig(dim=wl.dim, roots=wl.roots[:wl.dim], n_levels=L, bins=B or wl.bins,
                               lattice=lattice or wl.lattice, lo=wl.lo[:wl.dim], hi=wl.hi[:wl.dim],
-                              d_spec=list(wl.d_spec()[:L]) if d_spec is None else list(d_spec))
+                              d_spec=list(wl.d_spec()[:L]) if d_spec is None else list(d_spec), own_bin=own_bin,
+                              n_prop=n_prop)
     geom, bins, forest, links = agal.near_wall(v, f, cfg, ctx=ctx, with_links=with_links)
     off, ids = bins.tensors()
     out = {"handles": (geom, bins, forest, links), "cfg": cfg,
