@@ -78,6 +78,7 @@ def lib():
             "orc_links_face": (i32p, [P]),
             "orc_links_tests": (C.c_int64, [P]),
             "orc_link_grad": (None, [P, P, fp, i32p, dp, dp]),
+            "orc_classify_nodes": (None, [C.c_int, C.c_int, C.c_int64, i32p, fp, u8p]),
             "orc_link_stable": (None, [P, P, fp, C.c_int64, P, C.c_double, C.c_double, C.c_double,
                                        C.c_double, C.c_double, u8p]),
             "orc_link_t": (C.c_int, [P, C.c_uint64, C.c_int, C.c_int, fp, C.c_int32, dp]),
@@ -276,6 +277,16 @@ def link_grad(forest: Forest, links: Links, coords, fidx, w, n_vertices) -> np.n
     lib().orc_link_grad(forest.h, links.h, _ptr(coords, C.c_float), _ptr(fidx, C.c_int32),
                         _ptr(w, C.c_double), _ptr(g, C.c_double))
     return g
+
+
+def classify_nodes(dim: int, Q: int, face: np.ndarray, coords) -> np.ndarray:
+    """Per node 1 (fluid), 2 (solid) or 3 (its links disagree), from the orientation of each link's face."""
+    face = np.ascontiguousarray(face, dtype=np.int32).reshape(-1, Q)
+    coords = np.ascontiguousarray(coords, dtype=np.float32)
+    out = np.zeros(face.shape[0], dtype=np.uint8)
+    lib().orc_classify_nodes(dim, Q, face.shape[0], _ptr(face, C.c_int32), _ptr(coords, C.c_float),
+                             _ptr(out, C.c_uint8))
+    return out
 
 
 def link_stable(forest, links, coords, bins, h=1e-4, eta_max=0.025, bary_min=0.1, t_lo=0.1, gap=0.1):

@@ -970,6 +970,51 @@ static void face_normal(int dim, const double *p, double *n) {
     }
 }
 
+/*
+ * Node classification: the step after the link fractions that the paper
+ * leaves to future work (Results discussion, Conclusion).  With the faces
+ * oriented so that n = (b - a) x (c - a) (3D) or n = (e_y, -e_x), e = b - a
+ * (2D) points out of the solid, a link from a node outside the solid first
+ * meets a face it enters (c_i . n < 0), a link from a node inside first meets
+ * a face it leaves (c_i . n > 0).  Per node: 1 (fluid) when every link
+ * enters, 2 (solid) when every link leaves, 3 when its links disagree.
+ * s_i = (c_i0 n0 + c_i1 n1) + c_i2 n2 in FP64, n from the face's FP32 corners
+ * (components a1 b2 - a2 b1, a2 b0 - a0 b2, a0 b1 - a1 b0).
+ *   face: n_nodes x Q face ids (-1 = no link), coords: F x dim x dim.
+ */
+void orc_classify_nodes(int dim, int Q, int64_t n_nodes, const int32_t *face, const float *coords, uint8_t *cls) {
+    int c[27 * 3];
+    orc_lattice(Q, c);
+    for (int64_t k = 0; k < n_nodes; ++k) {
+        int enter = 0, leave = 0;
+        for (int i = 1; i < Q; ++i) {
+            int32_t f = face[k * Q + i];
+            if (f < 0) continue;
+            const float *v = coords + (int64_t)f * dim * dim;
+            double nrm[3] = {0, 0, 0};
+            if (dim == 3) {
+                double e1[3], e2[3];
+                for (int a = 0; a < 3; ++a) {
+                    e1[a] = (double)v[3 + a] - (double)v[a];
+                    e2[a] = (double)v[6 + a] - (double)v[a];
+                }
+                nrm[0] = e1[1] * e2[2] - e1[2] * e2[1];
+                nrm[1] = e1[2] * e2[0] - e1[0] * e2[2];
+                nrm[2] = e1[0] * e2[1] - e1[1] * e2[0];
+            } else {
+                double e0 = (double)v[2] - (double)v[0], e1 = (double)v[3] - (double)v[1];
+                nrm[0] = e1;
+                nrm[1] = -e0;
+            }
+            double sgn = ((double)c[3 * i] * nrm[0] + (double)c[3 * i + 1] * nrm[1]) + (double)c[3 * i + 2] * nrm[2];
+            if (sgn < 0.0) enter = 1;
+            else if (sgn > 0.0) leave = 1;
+            else { enter = 1; leave = 1; }   /* a hit along the face's plane has no side */
+        }
+        cls[k] = (uint8_t)(enter && leave ? 3 : (leave ? 2 : 1));
+    }
+}
+
 void orc_link_grad(const orc_forest *fo, const orc_links *lk, const float *coords, const int32_t *fidx,
                    const double *w, double *grad) {
     int dim = lk->dim, Q = lk->Q;

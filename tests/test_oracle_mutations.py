@@ -83,6 +83,19 @@ MUTANTS = [
     ("one propagation step too few",
      "return 1 + (int)floorf(fo->d[l] / (4.0f * dxm));", "return (int)floorf(fo->d[l] / (4.0f * dxm));",
      "test_own_bin_flags_and_propagation_brute_force"),
+    ("2D classification with the segment normal reversed",
+     "nrm[0] = e1;\n                nrm[1] = -e0;", "nrm[0] = -e1;\n                nrm[1] = e0;",
+     "test_classify_circle_matches_winding_number"),
+    ("3D classification with a transposed cross-product component",
+     "nrm[1] = e1[2] * e2[0] - e1[0] * e2[2];", "nrm[1] = e1[0] * e2[2] - e1[2] * e2[0];",
+     "test_classify_3d_matches_winding_number"),
+    ("classification never reports disagreeing links",
+     "cls[k] = (uint8_t)(enter && leave ? 3", "cls[k] = (uint8_t)(0 ? 3",
+     "test_classify_dyadic_box_exact"),
+    ("classification reads the lattice one direction off",
+     "double sgn = ((double)c[3 * i] * nrm[0] + (double)c[3 * i + 1] * nrm[1]) + (double)c[3 * i + 2] * nrm[2];",
+     "double sgn = ((double)c[3 * i - 3] * nrm[0] + (double)c[3 * i - 2] * nrm[1]) + (double)c[3 * i - 1] * nrm[2];",
+     "test_classify_3d_matches_winding_number or test_classify_circle_matches_winding_number"),
 ]
 
 
@@ -99,6 +112,7 @@ def test_pins_catch_mutant(tmp_path, name, old, new, tests):
     env = dict(os.environ, AGAL_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         os.path.join(HERE, "test_oracle_pins.py"), os.path.join(HERE, "test_oracle_own_bin.py"),
+                        os.path.join(HERE, "test_oracle_classify.py"),
                         "-k", tests],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"pins did not catch: {name}\n{r.stdout[-2000:]}"
