@@ -249,6 +249,22 @@ AGAL_API agal_status agal_context_set_link_list_limit(agal_context ctx, int64_t 
 AGAL_API agal_status agal_link_fractions_backward(agal_geom g, agal_links l, const float *d_grad_q,
                                                   float *d_grad_vertices, void *stream);
 
+/* ---- node classification ---------------------------------------------------
+ * The step after the link fractions that the paper leaves to future work
+ * (Results discussion, Conclusion): the side of every boundary node of `l`,
+ * read from the orientation of the faces its links meet.  The surface must be
+ * closed and oriented so that n = (b - a) x (c - a) (3D) or n = (e_y, -e_x),
+ * e = b - a (2D) points out of the solid (counter-clockwise loops in 2D).  A
+ * link entering the solid has c_i . n < 0, one leaving it c_i . n > 0; the
+ * sign is evaluated in FP64 from the FP32 corners.
+ *   d_class  n_nodes uint8, caller-owned, in the order of agal_links_view:
+ *            1 fluid (every link enters), 2 solid (every link leaves),
+ *            3 mixed (links disagree, or one meets its face along the face's
+ *            plane: a link grazing an edge or corner of the solid).
+ * Errors: AGAL_ESTATE when `l` was not computed from `g`; AGAL_EINVAL for a
+ * NULL handle or output. */
+AGAL_API agal_status agal_classify_nodes(agal_geom g, agal_links l, uint8_t *d_class, void *stream);
+
 /* ---- batched form: many bodies, one graph launch --------------------------
  * Each body is a complete near-wall problem (import, bins, refinement, link
  * fractions and optionally the adjoint) with its own geometry, forest, bins

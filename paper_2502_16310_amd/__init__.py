@@ -79,6 +79,7 @@ def _load():
         "agal_link_fractions": [P, P, P, C.c_int, vp, PP],
         "agal_links_view": [P, PP, PP, PP, C.POINTER(i64), C.POINTER(C.c_int)],
         "agal_link_fractions_backward": [P, P, vp, vp, vp],
+        "agal_classify_nodes": [P, P, vp, vp],
         "agal_lattice_vectors": [C.c_int, C.POINTER(i32)],
         "agal_profile_enable": [P, C.c_int],
         "agal_context_set_flag_table_limit": [P, C.c_int64],
@@ -246,6 +247,10 @@ def agal_links_view(links):
 def agal_link_fractions_backward(geom, links, d_grad_q: int, d_grad_vertices: int, stream: int = 0):
     _check(_lib.agal_link_fractions_backward(_h(geom), _h(links), d_grad_q, d_grad_vertices, stream or None),
            "agal_link_fractions_backward")
+
+
+def agal_classify_nodes(geom, links, d_class: int, stream: int = 0):
+    _check(_lib.agal_classify_nodes(_h(geom), _h(links), d_class, stream or None), "agal_classify_nodes")
 
 
 def agal_lattice_vectors(lattice: int):

@@ -489,6 +489,71 @@ agal_status links_backward(agal_geom g, agal_links lk, const Lattice &lat, const
     return AGAL_OK;
 }
 
+// ---- node classification ---------------------------------------------------
+// Side of each boundary node from the faces its links meet: the faces are
+// oriented so that n = (b - a) x (c - a) (3D) or n = (e_y, -e_x) (2D) points
+// out of the solid, so a link entering the solid has c_i . n < 0 and one
+// leaving it c_i . n > 0.  The sign is taken in FP64 from the face's FP32
+// corners (edge differences and the two-term products exact, one rounding per
+// normal component and per sum, in a fixed order), so it is the same on every
+// device.  One workgroup takes 256 nodes; its threads walk the nodes' rows as
+// one flat, coalesced run of slots and OR each slot's code (1 enter, 2 leave,
+// 3 on the face's plane) into the node's LDS word.
+constexpr int kClassThreads = 256;
+
+template <int D, int Q>
+__global__ __launch_bounds__(kClassThreads) void k_classify_nodes(const float *rec, const int32_t *face, int64_t n,
+                                                                  uint8_t *cls) {
+    __shared__ uint32_t s_code[kClassThreads];
+    const int tid = threadIdx.x;
+    const int64_t node0 = (int64_t)blockIdx.x * kClassThreads;
+    const int nn = (int)min((int64_t)kClassThreads, n - node0);
+    s_code[tid] = 0u;
+    __syncthreads();
+    const int span = nn * Q;
+    const int32_t *row = face + node0 * Q;
+    for (int sl = tid; sl < span; sl += kClassThreads) {
+        const int32_t f = row[sl];
+        const int i = sl % Q;
+        if (f < 0 || i == 0) continue;
+        float v[dev::kRecFloats<D>];
+        dev::load_rec<D>(rec, f, v);
+        double nrm[3] = {0.0, 0.0, 0.0};
+        if constexpr (D == 3) {
+            const double e1[3] = {(double)v[3] - (double)v[0], (double)v[4] - (double)v[1], (double)v[5] - (double)v[2]};
+            const double e2[3] = {(double)v[6] - (double)v[0], (double)v[7] - (double)v[1], (double)v[8] - (double)v[2]};
+            nrm[0] = e1[1] * e2[2] - e1[2] * e2[1];
+            nrm[1] = e1[2] * e2[0] - e1[0] * e2[2];
+            nrm[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        } else {
+            nrm[0] = (double)v[3] - (double)v[1];
+            nrm[1] = -((double)v[2] - (double)v[0]);
+        }
+        const double sg = ((double)dir_c<D>(i, 0) * nrm[0] + (double)dir_c<D>(i, 1) * nrm[1]) +
+                          (double)dir_c<D>(i, 2) * nrm[2];
+        const uint32_t code = sg < 0.0 ? 1u : (sg > 0.0 ? 2u : 3u);
+        atomicOr(&s_code[sl / Q], code);
+    }
+    __syncthreads();
+    if (tid < nn) {
+        const uint32_t c = s_code[tid];
+        cls[node0 + tid] = (uint8_t)(c == 3u ? 3u : (c == 2u ? 2u : 1u));
+    }
+}
+
+template <int D, int Q>
+agal_status classify_nodes(agal_geom g, agal_links lk, uint8_t *cls, hipStream_t s) {
+    if (lk->n == 0) return AGAL_OK;
+    const int64_t blocks = (lk->n + kClassThreads - 1) / kClassThreads;
+    {
+        ProfScope prof(g->ctx, "classify", s);
+        hipLaunchKernelGGL((k_classify_nodes<D, Q>), dim3((unsigned)blocks), dim3(kClassThreads), 0, s, g->rec,
+                           lk->face, lk->n, cls);
+    }
+    AGAL_TRY_HIP(hipGetLastError());
+    return AGAL_OK;
+}
+
 }  // namespace
 }  // namespace agal
 
@@ -553,6 +618,17 @@ agal_status agal_link_fractions_backward(agal_geom g, agal_links l, const float 
     if (l->Q == AGAL_D2Q9) return links_backward<2, 9>(g, l, lat, d_grad_q, d_grad_vertices, s);
     if (l->Q == AGAL_D3Q19) return links_backward<3, 19>(g, l, lat, d_grad_q, d_grad_vertices, s);
     return links_backward<3, 27>(g, l, lat, d_grad_q, d_grad_vertices, s);
+}
+
+agal_status agal_classify_nodes(agal_geom g, agal_links l, uint8_t *d_class, void *stream) {
+    if (!g || !l) return fail(AGAL_EINVAL, "agal_classify_nodes: NULL handle");
+    if (l->geom_id != g->id) return fail(AGAL_ESTATE, "agal_classify_nodes: links were computed from another geometry");
+    if (l->n > 0 && !d_class) return fail(AGAL_EINVAL, "agal_classify_nodes: NULL output");
+    if (l->n > (int64_t)kClassThreads * INT32_MAX) return fail(AGAL_EINVAL, "agal_classify_nodes: too many nodes");
+    hipStream_t s = (hipStream_t)stream;
+    if (l->Q == AGAL_D2Q9) return classify_nodes<2, 9>(g, l, d_class, s);
+    if (l->Q == AGAL_D3Q19) return classify_nodes<3, 19>(g, l, d_class, s);
+    return classify_nodes<3, 27>(g, l, d_class, s);
 }
 
 void agal_destroy_links(agal_links l) {

@@ -18,7 +18,7 @@ from . import (AgalError, agal_batch_body_view, agal_batch_info, agal_batch_leve
                agal_context_set_flag_table_limit, agal_context_set_link_list_limit,
                agal_context_destroy, agal_destroy_batch, agal_destroy_bins, agal_destroy_forest, agal_destroy_geom,
                agal_destroy_links, agal_forest_info, agal_forest_level_view, agal_geom_view, agal_import_faces,
-               agal_link_fractions, agal_link_fractions_backward, agal_links_view, agal_near_wall_refine,
+               agal_classify_nodes, agal_link_fractions, agal_link_fractions_backward, agal_links_view, agal_near_wall_refine,
                agal_near_wall_refine_own_bin, body_desc,
                forest_desc, tune_opts)
 
@@ -267,6 +267,15 @@ class Links:
             grad_vertices = torch.zeros((self.geom.n_vertices, self.geom.dim), dtype=torch.float32, device=g.device)
         agal_link_fractions_backward(self.geom.h, self.h, g.data_ptr(), grad_vertices.data_ptr(), current_stream())
         return grad_vertices
+
+    def classify(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Side of every boundary node from its links' faces: 1 fluid, 2 solid, 3 mixed (uint8, node order)."""
+        if out is None:
+            out = torch.empty(self.n_nodes, dtype=torch.uint8, device=torch.device("cuda", torch.cuda.current_device()))
+        if not out.is_cuda or out.dtype != torch.uint8 or not out.is_contiguous() or out.numel() != self.n_nodes:
+            raise ValueError("out must be a contiguous uint8 device tensor of n_nodes values")
+        agal_classify_nodes(self.geom.h, self.h, out.data_ptr(), current_stream())
+        return out
 
 
 @dataclass

@@ -1,5 +1,5 @@
 """Full-size parity: the 327,680-triangle star body (bins and flags bit-exact, q on
-sampled finest-level blocks) and the differentiated jittered sphere (GPU adjoint
+sampled finest-level blocks, the side of every boundary node) and the differentiated jittered sphere (GPU adjoint
 against the FP64 analytic adjoint and against central finite differences)."""
 import numpy as np
 import pytest
@@ -31,6 +31,11 @@ def test_star_c2_bins_flags_exact_and_sampled_q(orc):
     nd, bad = check_face_ties(orc, of, coords, wl.lattice, *arrs)
     log(f"  face ids differing at ties: {nd}, not a tie: {bad}")
     assert bad == 0
+    # node classification over every boundary node, against the oracle on the GPU's own link rows
+    cls = g["handles"][3].classify().cpu().numpy()
+    exp = orc.classify_nodes(3, wl.lattice, g["face"], coords)
+    assert np.array_equal(cls, exp), f"{int((cls != exp).sum())} node classes differ"
+    log(f"  classes fluid / solid / mixed {np.bincount(cls, minlength=4)[1:].tolist()}")
 
 
 def _rel_checks(g, ref, comp_tol, norm_tol):
