@@ -197,6 +197,8 @@ def main():
     ap.add_argument("--config", default="C2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the one-body graph timing")
+    ap.add_argument("--no-grad-leg", action="store_true",
+                    help="skip the gradient leg on the jittered 20,480-face sphere (profiling runs of one workload)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the reference kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters into bytes")
@@ -282,6 +284,7 @@ def main():
     T = sum(t_flag) + t_q
     n_links = int((agal.device_copy(agal.agal_links_view(lk)[2], n_nodes * Q, torch.int32) >= 0).sum().item())
     n_blocks = [len(l["keys"]) for l in levels]
+    classify = classify_leg(args, agal, torch, g, lk, n_nodes, Q, dim, len(wl.faces), stream)
     for h, fn in ((lk, agal.agal_destroy_links), (fo, agal.agal_destroy_forest), (b, agal.agal_destroy_bins),
                   (g, agal.agal_destroy_geom)):
         fn(h)
@@ -359,9 +362,9 @@ def main():
                             if "flag_sat" in kern else None,
                             "q_per_s": t_q / (q_ms * 1e-3) if q_ms > 0 else None},
         "forest_blocks_per_level": n_blocks, "boundary_nodes": n_nodes, "links": n_links,
-        "kernels": kern, "roofline": roof,
+        "kernels": kern, "roofline": roof, "classify": classify,
     }
-    if wl.name != "C3":
+    if wl.name != "C3" and not args.no_grad_leg:
         out["grad_C3"] = grad_c3(args, agal, torch, dev)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on the same workload", file=sys.stderr, flush=True)
@@ -370,6 +373,32 @@ def main():
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+def classify_leg(args, agal, torch, g, lk, n_nodes, Q, dim, F, stream):
+    """The step after q: the side of every boundary node (agal_classify_nodes), timed on its own with HIP
+    events on the launch stream over 20 launches on this step's links.  Algorithmic HBM bytes: the face-id
+    rows (n_nodes x Q x 4 B) read once, one class byte per node written, and every face record (16 FP32 in
+    3D, 8 in 2D) read at most once."""
+    if n_nodes == 0:
+        return None
+    dev = torch.device("cuda", torch.cuda.current_device())
+    out = torch.empty(n_nodes, dtype=torch.uint8, device=dev)
+    agal.agal_classify_nodes(g, lk, out.data_ptr(), stream)
+    torch.cuda.synchronize()
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        agal.agal_classify_nodes(g, lk, out.data_ptr(), stream)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = n_nodes * Q * 4 + n_nodes + F * (64 if dim == 3 else 32)
+    counts = torch.bincount(out.long(), minlength=4)[1:].tolist()
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"ms": ms, "algorithmic_bytes": nbytes, "GBps": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+            "nodes_fluid_solid_mixed": counts}
 
 
 def grad_c3(args, agal, torch, dev):
@@ -682,11 +711,13 @@ OPS_PER_PAIR = {"q_step": 8, "flag_sat": 24}
 # and walk mode (the bin walk, then the compaction).
 Q_STEP = ("q_lists", "q_nodes", "q_links", "q_compact")
 
-# Library timing names -> kernel symbols as profilers list them, and the sources each kernel is built from.
-KERNEL_SYMBOL = {"flag_sat": ("k_flag_faces", "refine.hip"), "q_links": ("k_links_rows", "links.hip"),
-                 "q_nodes": ("k_links_nodes", "links.hip"), "q_lists": ("k_link_faces", "links.hip"),
-                 "q_adjoint": ("k_adjoint", "links.hip"), "q_compact": ("k_compact_nodes", "links.hip"),
-                 "bin_canon": ("k_bin_canon_small", "bins.hip")}
+# Library timing names -> the kernel symbols (as profilers list them) launched under that name, and the source
+# each is built from.
+KERNEL_SYMBOL = {"flag_sat": (("k_flag_faces",), "refine.hip"), "q_links": (("k_node_map", "k_links_rows"), "links.hip"),
+                 "q_nodes": (("k_links_nodes",), "links.hip"), "q_lists": (("k_link_blocks", "k_link_faces"), "links.hip"),
+                 "q_adjoint": (("k_adjoint",), "links.hip"), "q_compact": (("k_compact_nodes",), "links.hip"),
+                 "bin_canon": (("k_bin_canon_small", "k_bin_canon_medium"), "bins.hip"),
+                 "classify": (("k_classify_nodes",), "links.hip")}
 
 
 def kernel_source_hash(name):
@@ -703,9 +734,9 @@ def kernel_source_hash(name):
 
 
 def measured_traffic(name, workload):
-    """HBM bytes per launch of kernel `name` on `workload` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary (profiles/traffic.json, counters scaled by a plain copy of known size); None when there is none or
-    the kernel's sources changed since the counters were taken."""
+    """HBM bytes per launch of timing name `name` (all the kernels launched under it) on `workload` from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (profiles/traffic.json, counters scaled by a plain copy of
+    known size); None when there is none or the kernels' sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
