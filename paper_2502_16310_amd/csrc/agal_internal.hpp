@@ -244,6 +244,25 @@ agal_status scan_popc64_total(agal_context ctx, const unsigned long long *masks,
 // agal_context_create.
 agal_status bin_scratch_resolve(int device);
 
+// Candidate blocks per face along each axis at most, from the largest face box
+// extent (bound of the list length); +2 covers the FP64 rounding of the range.
+inline double link_blocks_per_face(int D, const float ext[3], const float dx[3], const float eps[3]) {
+    double p = 1.0;
+    for (int a = 0; a < D; ++a)
+        p *= std::floor(((double)ext[a] * (1.0 + 1e-6) + 5.0 * dx[a] + 4.0 * (double)eps[a]) / (4.0 * dx[a])) + 2.0;
+    return p;
+}
+
+// Link step of one body as agal_link_fractions would take it (used to size
+// the batched form): list mode or not, the candidate blocks per face at most,
+// and the exact number of candidate-list entries (synchronises s).
+struct LinkListPlan {
+    bool lists = false;
+    int64_t per_face = 0;
+    int64_t entries = 0;
+};
+agal_status link_list_plan(agal_geom g, agal_forest fo, hipStream_t s, LinkListPlan *out);
+
 // Look-back scratch: status words + ticket for `tiles` tiles, cleared.
 agal_status lookback_alloc(agal_context ctx, int64_t tiles, uint64_t **status, uint32_t **ticket, hipStream_t s);
 

@@ -61,6 +61,18 @@ struct BodyDev {
     uint64_t *skey;
     float *sq;
     int32_t *sface;
+    // list mode of the link step (lists != 0): parent table (null at level 0),
+    // per-block node masks, candidate counts and cursors (2 x cap[L]), list
+    // offsets, the lists, and each node's block
+    int lists;
+    int64_t per_face;
+    unsigned long long *hash;
+    uint32_t hmask;
+    int hshift;
+    unsigned long long *nmask;
+    uint32_t *lwork, *loff, *lblk, *nblk;
+    int32_t *list;
+    uint32_t list_cap;
     uint32_t *blk_start, *blk_count, *blk_off;
     int64_t cap_nodes;
     uint64_t *key;
@@ -81,7 +93,7 @@ __host__ __device__ inline int64_t row_range(int64_t cap) {
 }
 
 struct Ctl {
-    uint32_t overflow;   // bit 0 bins, bit 1 forest level, bit 2 nodes
+    uint32_t overflow;   // bit 0 bins, bit 1 forest level, bit 2 nodes, bit 3 candidate lists
     uint32_t err;        // bit 0 non-finite coordinate, bit 1 face index
     uint32_t balance;    // nonzero: a forest lost 2:1 balance
     uint32_t lists[2];   // medium- and big-bin list counts of the canonical order
@@ -578,7 +590,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         const BodyDev &B = bodies[b];
         const int L = B.L;
         const uint32_t local = it - wg_pre[b];
-        if (B.Q != Q || local >= (cnt[b * kLv + L] + BPW - 1) / BPW) return;
+        if (B.Q != Q || B.lists || local >= (cnt[b * kLv + L] + BPW - 1) / BPW) return;
         LinkArgs<D, Q> A{};
         A.faces = dev::Faces{B.coords, B.aabb, B.rec, B.F};
         A.bins = B.bins;
@@ -604,15 +616,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
 __global__ void k_b_nodes(const BodyDev *bodies, int nb, const uint32_t *cnt, uint32_t *nodes, Ctl *ctl) {
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
         const uint32_t n = bodies[b].blk_off[cnt[b * kLv + bodies[b].L]];
-        if ((int64_t)n > bodies[b].cap_nodes) atomicOr(&ctl->overflow, 4u);
-        nodes[b] = (uint32_t)std::min<int64_t>(n, bodies[b].cap_nodes);
+        const bool over = (int64_t)n > bodies[b].cap_nodes;
+        if (over) atomicOr(&ctl->overflow, 4u);
+        // list mode writes rows by node index: a body over capacity gets none
+        nodes[b] = bodies[b].lists ? (over ? 0u : n) : (uint32_t)std::min<int64_t>(n, bodies[b].cap_nodes);
     }
 }
 
 template <int D, int Q>
 __global__ __launch_bounds__(64) void k_b_compact(const BodyDev *bodies, int nb, const uint32_t *cnt) {
     __shared__ uint32_t s_pre[kMaxBodies + 1];
-    const uint32_t total = lds_prefix(nb, [&](int b) { return bodies[b].Q == Q ? cnt[b * kLv + bodies[b].L] : 0u; }, s_pre);
+    const uint32_t total = lds_prefix(nb, [&](int b) {
+        return bodies[b].Q == Q && !bodies[b].lists ? cnt[b * kLv + bodies[b].L] : 0u; }, s_pre);
     for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
         const int b = find_seg(s_pre, nb, it);
         const BodyDev &B = bodies[b];
@@ -621,6 +636,129 @@ __global__ __launch_bounds__(64) void k_b_compact(const BodyDev *bodies, int nb,
         if ((int64_t)dst + c > B.cap_nodes) continue;   // over capacity (reported by k_b_nodes)
         compact_block<Q>((int)c, B.blk_start[i], dst, B.skey, B.sq, B.sface, B.key, B.q, B.face);
     }
+}
+
+// ---- list mode ------------------------------------------------------------
+// The single-body list build and passes (kernels.hpp), body by body: blocks
+// and faces are mapped to bodies through per-body prefixes, the wave-per-unit
+// kernels through workgroup offsets laid out at plan time.
+template <int D>
+__device__ __forceinline__ BlockFind body_find(const BodyDev &X, uint32_t n) {
+    BlockFind B{};
+    B.hash = X.hash;
+    B.hmask = X.hmask;
+    B.hshift = X.hshift;
+    B.level = X.L;
+    for (int a = 0; a < 3; ++a) B.R[a] = X.R[a];
+    B.keys = X.keys[X.L][final_buf(X.L, X.L)];
+    B.n = n;
+    return B;
+}
+
+template <int D, int Q>
+__device__ __forceinline__ LinkArgs<D, Q> body_link_args(const BodyDev &X, uint32_t n) {
+    LinkArgs<D, Q> A{};
+    A.faces = dev::Faces{X.coords, X.aabb, X.rec, X.F};
+    A.bins = X.bins;
+    A.keys = X.keys[X.L][final_buf(X.L, X.L)];
+    A.n = n;
+    A.level = X.L;
+    for (int a = 0; a < 3; ++a) {
+        A.R[a] = X.R[a];
+        A.lo[a] = X.lo[a];
+        A.dx[a] = X.dx[X.L][a];
+        A.eps[a] = X.eps[a];
+    }
+    A.loff = X.loff;
+    A.list = X.list;
+    A.list_cap = X.list_cap;
+    A.node_key = X.key;
+    A.q = X.q;
+    A.face = X.face;
+    return A;
+}
+
+template <int D>
+__global__ void k_b_link_blocks(const BodyDev *bodies, int nb, const uint32_t *cnt) {
+    __shared__ uint32_t s_pre[kMaxBodies + 1];
+    const uint32_t total = lds_prefix(nb, [&](int b) {
+        return bodies[b].lists ? cnt[b * kLv + bodies[b].L] : 0u; }, s_pre);
+    AGAL_THREAD_ITEMS(it, total) {
+        const int b = find_seg(s_pre, nb, it);
+        const BodyDev &X = bodies[b];
+        link_block_item<D>(X.keys[X.L][final_buf(X.L, X.L)], it - s_pre[b], X.hash, X.hmask, X.hshift, X.nmask);
+    }
+}
+
+template <int D, bool kScatter>
+__global__ __launch_bounds__(64) void k_b_link_faces(const BodyDev *bodies, int nb, const uint32_t *cnt, Ctl *ctl,
+                                                     const uint32_t *wg_pre) {
+    const uint32_t it = blockIdx.x;
+    const int b = body_of_wg(wg_pre, nb, it);
+    const BodyDev &X = bodies[b];
+    if (!X.lists) return;
+    const uint32_t n = cnt[b * kLv + X.L];
+    LinkFaceGrid G{};
+    for (int a = 0; a < 3; ++a) {
+        G.lo[a] = X.lo[a];
+        G.dx[a] = X.dx[X.L][a];
+        G.m[a] = 2.0 * (double)X.eps[a];
+        G.NB[a] = a < D ? (X.R[a] << X.L) : 1;
+    }
+    const BlockFind B = body_find<D>(X, n);
+    const int64_t f0 = (int64_t)(it - wg_pre[b]) * kLinkFaceG;
+    link_faces_wave<D, kScatter>(X.aabb, X.F, G, B, X.per_face, X.lwork, X.loff, X.lwork + X.cap[X.L], X.list,
+                                 X.lblk, X.list_cap, f0, kScatter ? nullptr : &ctl->overflow);
+}
+
+template <int D, int Q>
+__global__ __launch_bounds__(64) void k_b_links_nodes(const BodyDev *bodies, int nb, const uint32_t *cnt,
+                                                      const uint32_t *wg_pre) {
+    const uint32_t it = blockIdx.x;
+    const int b = body_of_wg(wg_pre, nb, it);
+    const BodyDev &X = bodies[b];
+    if (X.Q != Q || !X.lists) return;
+    const LinkArgs<D, Q> A = body_link_args<D, Q>(X, cnt[b * kLv + X.L]);
+    links_nodes_entries<D, Q>(A, X.lblk, X.nmask, it - wg_pre[b], wg_pre[b + 1] - wg_pre[b]);
+}
+
+// Node counts per block (the links scan lays out the rows), and the list
+// length checked against its capacity.
+__global__ void k_b_popc(const BodyDev *bodies, int nb, const uint32_t *cnt, Ctl *ctl) {
+    __shared__ uint32_t s_pre[kMaxBodies + 1];
+    const uint32_t total = lds_prefix(nb, [&](int b) {
+        return bodies[b].lists ? cnt[b * kLv + bodies[b].L] : 0u; }, s_pre);
+    AGAL_THREAD_ITEMS(it, total) {
+        const int b = find_seg(s_pre, nb, it);
+        const BodyDev &X = bodies[b];
+        const uint32_t i = it - s_pre[b];
+        X.blk_count[i] = (uint32_t)__popcll(X.nmask[i]);
+        if (i == 0 && X.loff[cnt[b * kLv + X.L]] > X.list_cap) atomicOr(&ctl->overflow, 8u);
+    }
+}
+
+template <int D>
+__global__ void k_b_node_map(const BodyDev *bodies, int nb, const uint32_t *cnt, const uint32_t *nodes) {
+    __shared__ uint32_t s_pre[kMaxBodies + 1];
+    const uint32_t total = lds_prefix(nb, [&](int b) {
+        return bodies[b].lists && nodes[b] ? cnt[b * kLv + bodies[b].L] : 0u; }, s_pre);
+    AGAL_THREAD_ITEMS(it, total) {
+        const int b = find_seg(s_pre, nb, it);
+        const BodyDev &X = bodies[b];
+        node_map_block<D>(X.nmask, X.blk_off, X.keys[X.L][final_buf(X.L, X.L)], it - s_pre[b], X.nblk, X.key);
+    }
+}
+
+template <int D, int Q>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_b_links_rows(
+    const BodyDev *bodies, int nb, const uint32_t *cnt, const uint32_t *nodes, const uint32_t *wg_pre) {
+    const uint32_t it = blockIdx.x;
+    const int b = body_of_wg(wg_pre, nb, it);
+    const BodyDev &X = bodies[b];
+    const uint32_t local = it - wg_pre[b];
+    if (X.Q != Q || !X.lists || (int64_t)local * 64 >= (int64_t)nodes[b]) return;
+    const LinkArgs<D, Q> A = body_link_args<D, Q>(X, cnt[b * kLv + X.L]);
+    links_rows_nodes<D, Q>(A, X.lblk, X.nblk, X.key, nodes[b], local);
 }
 
 template <int D, int Q>
@@ -669,6 +807,8 @@ struct BodyHost {
     int64_t nodes = 0;
     double tune_ms = 0;
     float max_extent[3] = {};   // largest face box extent per axis (from the sizing run)
+    bool lists = false;         // the single-body link step takes list mode
+    int64_t list_entries = 0;   // candidate-list entries of the sizing run
 };
 
 }  // namespace batch
@@ -695,7 +835,7 @@ struct agal_batch_t {
     int n_fill_init = 0;
     std::vector<int> pass_seg_off, pass_seg_n;
     uint32_t *d_tickets = nullptr;   // one look-back ticket per scan of a run
-    int links_seg_off = 0, bins_seg_off = 0;
+    int links_seg_off = 0, bins_seg_off = 0, lists_seg_off = 0;
     int fill_pass_base = 0;
     int wg_per_cu = 4, n_cu = 256;
     bool with_adjoint = false;
@@ -704,7 +844,11 @@ struct agal_batch_t {
     bool flag_faces[agal::kMaxLevels] = {};      // the flag pass is face-centric (every body's table fits)
     unsigned fflag_grid = 0;                     // workgroups of the face-centric flag kernel (4 G faces each)
     int fflag_g = 16;                            // faces per wave of that kernel (face_flag_g of all faces)
-    unsigned links_grid[28] = {};                // workgroups of the q kernel per lattice
+    unsigned links_grid[28] = {};                // workgroups of the walk-mode q kernel per lattice
+    bool any_lists = false;                      // some body takes list mode
+    unsigned lfaces_grid = 0;                    // waves of the list build (kLinkFaceG faces each)
+    unsigned nodes_grid[28] = {};                // waves of the node pass per lattice
+    unsigned rows_grid[28] = {};                 // waves of the row pass per lattice
     uint32_t *d_wg_pre = nullptr;   // per flag pass, per lattice (9, 19, 27), then per face group: nb + 1 offsets
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -804,6 +948,10 @@ static agal_status size_body(agal_context ctx, const agal_body_desc &d, int B, h
         for (int l = 0; l <= fo->L; ++l) h.n[l] = fo->lev[l].n;
         h.nodes = lk->n;
         for (int a = 0; a < 3; ++a) h.max_extent[a] = g->max_extent[a];
+        LinkListPlan lp;
+        st = link_list_plan(g, fo, s, &lp);
+        h.lists = lp.lists;
+        h.list_entries = lp.entries;
     }
     agal_destroy_links(lk);
     agal_destroy_forest(fo);
@@ -876,6 +1024,27 @@ static agal_status capture(agal_batch bt) {
         hipLaunchKernelGGL(k_b_children<D>, dim3(G), dim3(256), 0, s, B, nb, p, bt->d_cnt);
         hipLaunchKernelGGL(k_b_counts<D>, dim3(1), dim3(256), 0, s, B, nb, p, bt->d_cnt, bt->d_ctl);
     }
+    if (bt->any_lists) {
+        const uint32_t *fpre = bt->d_wg_pre + (size_t)(kLv + 4) * (nb + 1);
+        hipLaunchKernelGGL(k_b_link_blocks<D>, dim3(G), dim3(256), 0, s, B, nb, bt->d_cnt);
+        hipLaunchKernelGGL((k_b_link_faces<D, false>), dim3(bt->lfaces_grid), dim3(64), 0, s, B, nb, bt->d_cnt,
+                           bt->d_ctl, fpre);
+        scan(2 + bt->Lmax, bt->lists_seg_off, nb, false);
+        hipLaunchKernelGGL((k_b_link_faces<D, true>), dim3(bt->lfaces_grid), dim3(64), 0, s, B, nb, bt->d_cnt,
+                           bt->d_ctl, fpre);
+        if (D == 3) {
+            if (bt->nodes_grid[19])
+                hipLaunchKernelGGL((k_b_links_nodes<3, 19>), dim3(bt->nodes_grid[19]), dim3(64), 0, s, B, nb,
+                                   bt->d_cnt, bt->d_wg_pre + (size_t)(kLv + 6) * (nb + 1));
+            if (bt->nodes_grid[27])
+                hipLaunchKernelGGL((k_b_links_nodes<3, 27>), dim3(bt->nodes_grid[27]), dim3(64), 0, s, B, nb,
+                                   bt->d_cnt, bt->d_wg_pre + (size_t)(kLv + 7) * (nb + 1));
+        } else if (bt->nodes_grid[9]) {
+            hipLaunchKernelGGL((k_b_links_nodes<2, 9>), dim3(bt->nodes_grid[9]), dim3(64), 0, s, B, nb, bt->d_cnt,
+                               bt->d_wg_pre + (size_t)(kLv + 5) * (nb + 1));
+        }
+        hipLaunchKernelGGL(k_b_popc, dim3(G), dim3(256), 0, s, B, nb, bt->d_cnt, bt->d_ctl);
+    }
     if (D == 3) {
         if (bt->links_grid[19])
             hipLaunchKernelGGL((k_b_links<3, 19>), dim3(bt->links_grid[19]), dim3(64), 0, s, B, nb, bt->d_cnt,
@@ -890,6 +1059,20 @@ static agal_status capture(agal_batch bt) {
     }
     scan(1 + bt->Lmax, bt->links_seg_off, nb, false);
     hipLaunchKernelGGL(k_b_nodes, dim3(1), dim3(256), 0, s, B, nb, bt->d_cnt, bt->d_nodes, bt->d_ctl);
+    if (bt->any_lists) {
+        hipLaunchKernelGGL(k_b_node_map<D>, dim3(G), dim3(256), 0, s, B, nb, bt->d_cnt, bt->d_nodes);
+        if (D == 3) {
+            if (bt->rows_grid[19])
+                hipLaunchKernelGGL((k_b_links_rows<3, 19>), dim3(bt->rows_grid[19]), dim3(64), 0, s, B, nb,
+                                   bt->d_cnt, bt->d_nodes, bt->d_wg_pre + (size_t)(kLv + 9) * (nb + 1));
+            if (bt->rows_grid[27])
+                hipLaunchKernelGGL((k_b_links_rows<3, 27>), dim3(bt->rows_grid[27]), dim3(64), 0, s, B, nb,
+                                   bt->d_cnt, bt->d_nodes, bt->d_wg_pre + (size_t)(kLv + 10) * (nb + 1));
+        } else if (bt->rows_grid[9]) {
+            hipLaunchKernelGGL((k_b_links_rows<2, 9>), dim3(bt->rows_grid[9]), dim3(64), 0, s, B, nb, bt->d_cnt,
+                               bt->d_nodes, bt->d_wg_pre + (size_t)(kLv + 8) * (nb + 1));
+        }
+    }
     if (D == 3) {
         hipLaunchKernelGGL((k_b_compact<3, 19>), dim3(G64), dim3(64), 0, s, B, nb, bt->d_cnt);
         hipLaunchKernelGGL((k_b_compact<3, 27>), dim3(G64), dim3(64), 0, s, B, nb, bt->d_cnt);
@@ -1046,11 +1229,39 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
         }
         X.cap_nodes = margin(h.nodes, mg);
         const int64_t nL = X.cap[X.L];
-        const int64_t stage_rows = kRowCursors * row_range(X.cap_nodes);
-        AGAL_TRY(own(bt, &X.skey, (size_t)stage_rows));
-        AGAL_TRY(own(bt, &X.sq, (size_t)stage_rows * X.Q));
-        AGAL_TRY(own(bt, &X.sface, (size_t)stage_rows * X.Q));
-        AGAL_TRY(own(bt, &X.blk_start, (size_t)nL));
+        // list mode as the single-body call takes it, with the face bound taken
+        // over extents grown by the margin (a face beyond it is reported)
+        const int64_t list_cap = margin(h.list_entries, mg);
+        X.lists = h.lists && list_cap <= (int64_t)UINT32_MAX ? 1 : 0;
+        if (X.lists) {
+            float ext[3];
+            for (int a = 0; a < 3; ++a) ext[a] = h.max_extent[a] * (1.0f + mg);
+            X.per_face = (int64_t)link_blocks_per_face(D, ext, X.dx[X.L], X.eps);
+            X.list_cap = (uint32_t)list_cap;
+            X.hash = nullptr;
+            X.hmask = 0;
+            X.hshift = 0;
+            if (X.L > 0) {
+                int bits = 6;
+                while (bits < 31 && (int64_t(1) << bits) < 2 * ((nL + (1 << D) - 1) >> D)) ++bits;
+                X.hmask = (uint32_t)((int64_t(1) << bits) - 1);
+                X.hshift = 32 - bits;
+                AGAL_TRY(own(bt, &X.hash, (size_t)X.hmask + 1));
+            }
+            AGAL_TRY(own(bt, &X.nmask, (size_t)nL));
+            AGAL_TRY(own(bt, &X.lwork, (size_t)2 * nL));
+            AGAL_TRY(own(bt, &X.loff, (size_t)nL + 1));
+            AGAL_TRY(own(bt, &X.list, (size_t)list_cap));
+            AGAL_TRY(own(bt, &X.lblk, (size_t)list_cap));
+            AGAL_TRY(own(bt, &X.nblk, (size_t)X.cap_nodes));
+            bt->any_lists = true;
+        } else {
+            const int64_t stage_rows = kRowCursors * row_range(X.cap_nodes);
+            AGAL_TRY(own(bt, &X.skey, (size_t)stage_rows));
+            AGAL_TRY(own(bt, &X.sq, (size_t)stage_rows * X.Q));
+            AGAL_TRY(own(bt, &X.sface, (size_t)stage_rows * X.Q));
+            AGAL_TRY(own(bt, &X.blk_start, (size_t)nL));
+        }
         AGAL_TRY(own(bt, &X.blk_count, (size_t)nL));
         AGAL_TRY(own(bt, &X.blk_off, (size_t)nL + 1));
         AGAL_TRY(own(bt, &X.key, (size_t)X.cap_nodes));
@@ -1064,8 +1275,9 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
     }
     bt->nb_total = bin_base;
     bt->cap_ids = cap_ids;
-    // workgroup offsets per body of the one-block-per-workgroup kernels (flag per pass, q per lattice)
-    std::vector<uint32_t> wg_pre((size_t)(kLv + 4) * (bt->nb + 1), 0u);
+    // workgroup offsets per body of the kernels laid out body by body; groups: flag passes (kLv), walk q per lattice (3), face-centric flags (1), list build (1), node pass per
+    // lattice (3), row pass per lattice (3)
+    std::vector<uint32_t> wg_pre((size_t)(kLv + 11) * (bt->nb + 1), 0u);
     for (int b = 0; b < bt->nb; ++b) {
         const BodyDev &X = bt->bodies[b];
         for (int p = 0; p < kLv; ++p) {
@@ -1075,8 +1287,17 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
         for (int k = 0; k < 3; ++k) {
             const int q = k == 0 ? 9 : (k == 1 ? 19 : 27);
             wg_pre[(size_t)(kLv + k) * (bt->nb + 1) + b] = bt->links_grid[q];
-            if (X.Q == q) bt->links_grid[X.Q] += (unsigned)((X.cap[X.L] + (64 / CELLS) - 1) / (64 / CELLS));
+            if (X.Q == q && !X.lists) bt->links_grid[X.Q] += (unsigned)((X.cap[X.L] + (64 / CELLS) - 1) / (64 / CELLS));
+            wg_pre[(size_t)(kLv + 5 + k) * (bt->nb + 1) + b] = bt->nodes_grid[q];
+            wg_pre[(size_t)(kLv + 8 + k) * (bt->nb + 1) + b] = bt->rows_grid[q];
+            if (X.Q == q && X.lists) {
+                // node pass: about eight chunks of 64 entries per wave; rows: 64 nodes per wave
+                bt->nodes_grid[q] += (unsigned)std::max<int64_t>(1, ((int64_t)X.list_cap + 511) / 512);
+                bt->rows_grid[q] += (unsigned)((X.cap_nodes + 63) / 64);
+            }
         }
+        wg_pre[(size_t)(kLv + 4) * (bt->nb + 1) + b] = bt->lfaces_grid;
+        if (X.lists) bt->lfaces_grid += (unsigned)((X.F + kLinkFaceG - 1) / kLinkFaceG);
     }
     for (int p = 0; p < kLv; ++p) wg_pre[(size_t)p * (bt->nb + 1) + bt->nb] = bt->flag_grid[p < agal::kMaxLevels ? p : 0];
     // as in the single-body pass: the deduplicating walker when some body's query boxes span more than 64 bins
@@ -1100,8 +1321,13 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
             bt->flag_dedup[p] = most > 64.0 && bt->flag_grid[p] < 32u * (unsigned)ncu;
         }
     }
-    for (int k = 0; k < 3; ++k)
-        wg_pre[(size_t)(kLv + k) * (bt->nb + 1) + bt->nb] = bt->links_grid[k == 0 ? 9 : (k == 1 ? 19 : 27)];
+    for (int k = 0; k < 3; ++k) {
+        const int q = k == 0 ? 9 : (k == 1 ? 19 : 27);
+        wg_pre[(size_t)(kLv + k) * (bt->nb + 1) + bt->nb] = bt->links_grid[q];
+        wg_pre[(size_t)(kLv + 5 + k) * (bt->nb + 1) + bt->nb] = bt->nodes_grid[q];
+        wg_pre[(size_t)(kLv + 8 + k) * (bt->nb + 1) + bt->nb] = bt->rows_grid[q];
+    }
+    wg_pre[(size_t)(kLv + 4) * (bt->nb + 1) + bt->nb] = bt->lfaces_grid;
     // face-centric flag step: 4 G faces per workgroup, body by body; a pass takes it when every body refining
     // in it has a block grid within the context's table limit (level 0 needs no table); tables are never
     // cleared (entries are checked against the level's keys)
@@ -1191,6 +1417,14 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
         add_seg(X.blk_count, X.blk_off, bt->d_cnt + b * kLv + X.L, 0, X.cap[X.L]);
     }
     max_sw = std::max(max_sw, sw);
+    sw = 0;
+    bt->lists_seg_off = (int)bt->seg_store.size();
+    for (int b = 0; b < bt->nb; ++b) {
+        const BodyDev &X = bt->bodies[b];
+        if (X.lists) add_seg(X.lwork, X.loff, bt->d_cnt + b * kLv + X.L, 0, X.cap[X.L]);
+        else add_seg(nullptr, nullptr, nullptr, 0, 0);
+    }
+    max_sw = std::max(max_sw, sw);
     // placeholders of finished bodies must not be scanned: give them n = 0 and a
     // harmless output word
     uint32_t *dummy = nullptr;
@@ -1203,7 +1437,7 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
             sg.n_dev = nullptr;
         }
     bt->status_words = max_sw + 1;
-    const int n_scans = bt->Lmax + 2;   // bins, one per pass, links
+    const int n_scans = bt->Lmax + 3;   // bins, one per pass, links, candidate lists
     AGAL_TRY(own(bt, &bt->d_status, (size_t)bt->status_words * n_scans));
     AGAL_TRY(own(bt, &bt->d_tickets, (size_t)n_scans));
     AGAL_TRY(own(bt, &bt->d_segs, bt->seg_store.size()));
@@ -1220,6 +1454,10 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
         for (int m = 0; m < X.L; ++m) fills.push_back({reinterpret_cast<uint32_t *>(X.pm[m]), words(X.cap[m]), 0u});
         if (bt->with_adjoint)
             fills.push_back({reinterpret_cast<uint32_t *>(X.grad_v), words(X.Nv * D * 4), 0u});
+        if (X.lists) {
+            if (X.hash) fills.push_back({reinterpret_cast<uint32_t *>(X.hash), 2 * ((int64_t)X.hmask + 1), ~0u});
+            fills.push_back({X.lwork, 2 * X.cap[X.L], 0u});
+        }
     }
     bt->n_fill_init = (int)fills.size();
     AGAL_TRY(own(bt, &bt->d_fills, fills.size()));
@@ -1337,7 +1575,7 @@ agal_status agal_batch_status(agal_batch b, void *stream) {
                                          "bit 1: vertex index out of range): %u", ctl.err);
     if (ctl.overflow)
         return fail(AGAL_ECAPACITY, "agal_batch_status: capacity exceeded (bit 0: bins, bit 1: forest level, "
-                                    "bit 2: nodes): %u", ctl.overflow);
+                                    "bit 2: nodes, bit 3: candidate lists): %u", ctl.overflow);
     if (ctl.balance) return fail(AGAL_ESTATE, "agal_batch_status: a forest lost 2:1 balance");
     return AGAL_OK;
 }

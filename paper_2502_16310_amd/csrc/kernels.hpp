@@ -1544,7 +1544,7 @@ __device__ __forceinline__ int nth_bit4(uint32_t m, int k) {
 // mask: one 64-bit word per block, zeroed; lblk: the block of each entry.
 template <int D, int Q>
 __device__ __forceinline__ void links_nodes_entries(const LinkArgs<D, Q> &A, const uint32_t *lblk,
-                                                    unsigned long long *mask) {
+                                                    unsigned long long *mask, int64_t wg, int64_t nwg) {
     constexpr int NP = (Q - 1) / 2;
     constexpr int RF = dev::kRecFloats<D>;
     __shared__ LinkStaged<D, 64> S;
@@ -1561,7 +1561,7 @@ __device__ __forceinline__ void links_nodes_entries(const LinkArgs<D, Q> &A, con
     const uint32_t total = min(A.loff[A.n], A.list_cap);
     int nq = 0;   // wave-uniform queue length
 
-    for (int64_t w = blockIdx.x; w * 64 < (int64_t)total; w += gridDim.x) {
+    for (int64_t w = wg; w * 64 < (int64_t)total; w += nwg) {
         const uint32_t e = (uint32_t)(w * 64) + (uint32_t)lane;
         uint32_t bits = 0, cnt = 0, b = 0;
         int bc[3] = {0, 0, 0};
@@ -2262,6 +2262,168 @@ __device__ __forceinline__ void compact_block(int c, int64_t src, int64_t dst, c
     }
 }
 
+
+// ---- link fractions, list mode: candidate blocks per face ------------------
+// Finest-level block of integer block coordinates c: at level 0 the root's
+// linear index; above, the parent's first child (hash table of parent keys,
+// linear probing; slot = parent key << 32 | index of its first child, ~0
+// empty) plus the child index.  -1: no such block.
+struct BlockFind {
+    const unsigned long long *hash;
+    uint32_t hmask;   // slots - 1
+    int hshift;       // 32 - log2(slots)
+    int level;
+    int R[3];
+    const uint32_t *keys;   // the level's sorted keys (a found index is checked against them)
+    int64_t n;
+};
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t key, int shift) { return (key * 2654435761u) >> shift; }
+
+template <int D>
+__device__ __forceinline__ int64_t find_block(const BlockFind &B, const int c[3]) {
+    if (B.level == 0) {
+        const int64_t i = ((int64_t)c[2] * B.R[1] + c[1]) * B.R[0] + c[0];
+        return i < B.n ? i : -1;
+    }
+    const int p[3] = {c[0] >> 1, c[1] >> 1, D == 3 ? c[2] >> 1 : 0};
+    const uint32_t pk = dev::encode_key<D>(p, B.level - 1, B.R[0], B.R[1]);
+    uint32_t ci = (uint32_t)(c[0] & 1) | ((uint32_t)(c[1] & 1) << 1);
+    if (D == 3) ci |= (uint32_t)(c[2] & 1) << 2;
+    uint32_t s = hash_slot(pk, B.hshift);
+    for (uint32_t probe = 0; probe <= B.hmask; ++probe) {
+        const unsigned long long v = B.hash[s];
+        if (v == ~0ull) return -1;
+        if ((uint32_t)(v >> 32) == pk) {
+            const int64_t i = (int64_t)(uint32_t)v + ci;
+            return i < B.n && B.keys[i] == ((pk << D) | ci) ? i : -1;
+        }
+        s = (s + 1) & B.hmask;
+    }
+    return -1;
+}
+
+// Block i of the level: its node mask zeroed and, above level 0, the parent
+// of every first child (child index 0) inserted into the table.
+template <int D>
+__device__ __forceinline__ void link_block_item(const uint32_t *keys, int64_t i, unsigned long long *hash,
+                                                uint32_t hmask, int hshift, unsigned long long *mask) {
+    mask[i] = 0ull;
+    if (!hash) return;
+    const uint32_t key = keys[i];
+    if (key & ((1u << D) - 1u)) return;
+    const uint32_t pk = key >> D;
+    const unsigned long long v = ((unsigned long long)pk << 32) | (uint32_t)i;
+    uint32_t s = hash_slot(pk, hshift);
+    for (uint32_t probe = 0; probe <= hmask; ++probe) {
+        if (atomicCAS(&hash[s], ~0ull, v) == ~0ull) break;
+        s = (s + 1) & hmask;
+    }
+}
+
+// Block ranges of a face's candidate blocks, per axis in FP64: block b is a
+// candidate when its link box [lo + (4b - 0.5) dx - eps, lo + (4b + 4.5) dx +
+// eps] (FP32 in the link kernels) meets the face box widened by m = 2 eps,
+// a margin above the FP32 rounding of those bounds, so the list holds every
+// face the kernels' own FP32 box test keeps (and a few more, which it drops).
+struct LinkFaceGrid {
+    double lo[3], dx[3], m[3];
+    int NB[3];
+};
+
+// One wave per kLinkFaceG faces: count (kScatter false) or write (true) each
+// face into the list of every existing candidate block.  The (face, block
+// position) pairs of the wave's faces are taken 64 at a time, one per lane,
+// so the hash probes of many pairs are in flight together.  A face with more
+// than max_coords candidate positions is skipped by both passes (the bound
+// the list was sized with makes that impossible for the geometry it was
+// measured on; the test keeps the writes inside the list whatever happens, and
+// `over`, when given, records the skip), and so is a write at or past cap.
+constexpr int kLinkFaceG = 16;
+
+template <int D, bool kScatter>
+__device__ __forceinline__ void link_faces_wave(const float *aabb, int64_t F, const LinkFaceGrid &G,
+                                                const BlockFind &B, int64_t max_coords, uint32_t *cnt,
+                                                const uint32_t *loff, uint32_t *cursor, int32_t *list, uint32_t *lblk,
+                                                uint32_t cap, int64_t f0, uint32_t *over = nullptr) {
+    __shared__ int s_i[kLinkFaceG][8];   // per face: first block per axis, positions per axis, pair prefix
+    const int lane = dev::lane_id();
+    uint32_t npos = 0;
+    if (lane < kLinkFaceG) {
+        const int64_t f = f0 + lane;
+        int b0[3] = {0, 0, 0}, nb[3] = {1, 1, 1};
+        bool any = f < F;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            if (!any) break;
+            const double mn = aabb[(int64_t)a * F + f], mx = aabb[(int64_t)(D + a) * F + f];
+            double l = ceil((mn - G.lo[a] - G.m[a] - 4.5 * G.dx[a]) / (4.0 * G.dx[a]));
+            double h = floor((mx - G.lo[a] + G.m[a] + 0.5 * G.dx[a]) / (4.0 * G.dx[a]));
+            l = l < 0.0 ? 0.0 : l;
+            h = h > (double)(G.NB[a] - 1) ? (double)(G.NB[a] - 1) : h;
+            if (!(l <= h)) {   // outside the grid, or a non-finite coordinate
+                any = false;
+                break;
+            }
+            b0[a] = (int)l;
+            nb[a] = (int)(h - l) + 1;
+        }
+        if (any && (int64_t)nb[0] * nb[1] * nb[2] <= max_coords) npos = (uint32_t)(nb[0] * nb[1] * nb[2]);
+        else if (any && over) atomicOr(over, 8u);   // beyond the bound the lists were sized with
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            s_i[lane][a] = b0[a];
+            s_i[lane][3 + a] = nb[a];
+        }
+    }
+    const uint32_t incl = dev::wave_inclusive_sum(npos);
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, dev::kWave - 1);
+    if (lane < kLinkFaceG) s_i[lane][6] = (int)(incl - npos);
+    dev::wave_sync();
+    for (uint32_t c0 = 0; c0 < total; c0 += dev::kWave) {
+        const uint32_t v = c0 + (uint32_t)lane;
+        if (v >= total) break;
+        int k = 0;   // the last face whose pairs start at or before v
+#pragma unroll
+        for (int step = kLinkFaceG / 2; step >= 1; step >>= 1)
+            if ((uint32_t)s_i[k + step][6] <= v) k += step;
+        uint32_t u = v - (uint32_t)s_i[k][6];
+        int c[3];
+        c[0] = s_i[k][0] + (int)(u % (uint32_t)s_i[k][3]);
+        u /= (uint32_t)s_i[k][3];
+        c[1] = s_i[k][1] + (int)(u % (uint32_t)s_i[k][4]);
+        c[2] = s_i[k][2] + (int)(u / (uint32_t)s_i[k][4]);
+        const int64_t idx = find_block<D>(B, c);
+        if (idx < 0) continue;
+        if constexpr (kScatter) {
+            const uint32_t pos = loff[idx] + atomicAdd(&cursor[idx], 1u);
+            if (pos < cap) {
+                list[pos] = (int32_t)(f0 + k);
+                lblk[pos] = (uint32_t)idx;
+            }
+        } else {
+            atomicAdd(&cnt[idx], 1u);
+        }
+    }
+}
+
+// Nodes of block b in cell order: node k -> its block (nblk) and node key,
+// from the block's mask and first row noff[b].
+template <int D>
+__device__ __forceinline__ void node_map_block(const unsigned long long *mask, const uint32_t *noff,
+                                               const uint32_t *keys, int64_t b, uint32_t *nblk, uint64_t *node_key) {
+    constexpr int CELLS = D == 3 ? 64 : 16;
+    unsigned long long m = mask[b];
+    int64_t k = noff[b];
+    const uint64_t base = (uint64_t)keys[b] * CELLS;
+    while (m) {
+        const int cell = __builtin_ctzll(m);
+        m &= m - 1ull;
+        nblk[k] = (uint32_t)b;
+        node_key[k] = base + (uint64_t)cell;
+        ++k;
+    }
+}
 
 }  // namespace kern
 }  // namespace agal

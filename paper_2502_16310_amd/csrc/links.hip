@@ -72,189 +72,39 @@ __global__ __launch_bounds__(64) void k_compact_nodes(const uint32_t *count, con
 }
 
 // ---- list mode ------------------------------------------------------------
-// Finest-level block of integer block coordinates c: at level 0 the root's
-// linear index; above, the parent's first child (hash table of parent keys,
-// linear probing; slot = parent key << 32 | index of its first child, ~0
-// empty) plus the child index.  -1: no such block.
-struct BlockFind {
-    const unsigned long long *hash;
-    uint32_t hmask;   // slots - 1
-    int hshift;       // 32 - log2(slots)
-    int level;
-    int R[3];
-    const uint32_t *keys;   // the level's sorted keys (a found index is checked against them)
-    int64_t n;
-};
-
-__device__ __forceinline__ uint32_t hash_slot(uint32_t key, int shift) { return (key * 2654435761u) >> shift; }
-
-template <int D>
-__device__ __forceinline__ int64_t find_block(const BlockFind &B, const int c[3]) {
-    if (B.level == 0) {
-        const int64_t i = ((int64_t)c[2] * B.R[1] + c[1]) * B.R[0] + c[0];
-        return i < B.n ? i : -1;
-    }
-    const int p[3] = {c[0] >> 1, c[1] >> 1, D == 3 ? c[2] >> 1 : 0};
-    const uint32_t pk = dev::encode_key<D>(p, B.level - 1, B.R[0], B.R[1]);
-    uint32_t ci = (uint32_t)(c[0] & 1) | ((uint32_t)(c[1] & 1) << 1);
-    if (D == 3) ci |= (uint32_t)(c[2] & 1) << 2;
-    uint32_t s = hash_slot(pk, B.hshift);
-    for (uint32_t probe = 0; probe <= B.hmask; ++probe) {
-        const unsigned long long v = B.hash[s];
-        if (v == ~0ull) return -1;
-        if ((uint32_t)(v >> 32) == pk) {
-            const int64_t i = (int64_t)(uint32_t)v + ci;
-            return i < B.n && B.keys[i] == ((pk << D) | ci) ? i : -1;
-        }
-        s = (s + 1) & B.hmask;
-    }
-    return -1;
-}
-
-// One thread per block of the level: its node mask zeroed and, above level
-// 0, the parent of every first child (child index 0) inserted.
 template <int D>
 __global__ void k_link_blocks(const uint32_t *keys, int64_t n, unsigned long long *hash, uint32_t hmask, int hshift,
                               unsigned long long *mask) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        mask[i] = 0ull;
-        if (!hash) continue;
-        const uint32_t key = keys[i];
-        if (key & ((1u << D) - 1u)) continue;
-        const uint32_t pk = key >> D;
-        const unsigned long long v = ((unsigned long long)pk << 32) | (uint32_t)i;
-        uint32_t s = hash_slot(pk, hshift);
-        for (uint32_t probe = 0; probe <= hmask; ++probe) {
-            if (atomicCAS(&hash[s], ~0ull, v) == ~0ull) break;
-            s = (s + 1) & hmask;
-        }
-    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        link_block_item<D>(keys, i, hash, hmask, hshift, mask);
 }
-
-// Block ranges of a face's candidate blocks, per axis in FP64: block b is a
-// candidate when its link box [lo + (4b - 0.5) dx - eps, lo + (4b + 4.5) dx +
-// eps] (FP32 in the link kernels) meets the face box widened by m = 2 eps,
-// a margin above the FP32 rounding of those bounds, so the list holds every
-// face the kernels' own FP32 box test keeps (and a few more, which it drops).
-struct LinkFaceGrid {
-    double lo[3], dx[3], m[3];
-    int NB[3];
-};
-
-// One wave per kLinkFaceG faces: count (kScatter false) or write (true) each
-// face into the list of every existing candidate block.  The (face, block
-// position) pairs of the wave's faces are taken 64 at a time, one per lane,
-// so the hash probes of many pairs are in flight together.  A face with more
-// than max_coords candidate positions is skipped by both passes (the bound
-// the list was sized with makes that impossible; the test keeps the writes
-// inside the list whatever happens), and so is a write at or past cap.
-constexpr int kLinkFaceG = 16;
 
 template <int D, bool kScatter>
 __global__ __launch_bounds__(64) void k_link_faces(const float *aabb, int64_t F, LinkFaceGrid G, BlockFind B,
                                                    int64_t max_coords, uint32_t *cnt, const uint32_t *loff,
                                                    uint32_t *cursor, int32_t *list, uint32_t *lblk, uint32_t cap) {
-    __shared__ int s_i[kLinkFaceG][8];   // per face: first block per axis, positions per axis, pair prefix
-    const int lane = dev::lane_id();
-    const int64_t f0 = (int64_t)blockIdx.x * kLinkFaceG;
-    uint32_t npos = 0;
-    if (lane < kLinkFaceG) {
-        const int64_t f = f0 + lane;
-        int b0[3] = {0, 0, 0}, nb[3] = {1, 1, 1};
-        bool any = f < F;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            if (!any) break;
-            const double mn = aabb[(int64_t)a * F + f], mx = aabb[(int64_t)(D + a) * F + f];
-            double l = ceil((mn - G.lo[a] - G.m[a] - 4.5 * G.dx[a]) / (4.0 * G.dx[a]));
-            double h = floor((mx - G.lo[a] + G.m[a] + 0.5 * G.dx[a]) / (4.0 * G.dx[a]));
-            l = l < 0.0 ? 0.0 : l;
-            h = h > (double)(G.NB[a] - 1) ? (double)(G.NB[a] - 1) : h;
-            if (!(l <= h)) {   // outside the grid, or a non-finite coordinate
-                any = false;
-                break;
-            }
-            b0[a] = (int)l;
-            nb[a] = (int)(h - l) + 1;
-        }
-        if (any && (int64_t)nb[0] * nb[1] * nb[2] <= max_coords) npos = (uint32_t)(nb[0] * nb[1] * nb[2]);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            s_i[lane][a] = b0[a];
-            s_i[lane][3 + a] = nb[a];
-        }
-    }
-    const uint32_t incl = dev::wave_inclusive_sum(npos);
-    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, dev::kWave - 1);
-    if (lane < kLinkFaceG) s_i[lane][6] = (int)(incl - npos);
-    dev::wave_sync();
-    for (uint32_t c0 = 0; c0 < total; c0 += dev::kWave) {
-        const uint32_t v = c0 + (uint32_t)lane;
-        if (v >= total) break;
-        int k = 0;   // the last face whose pairs start at or before v
-#pragma unroll
-        for (int step = kLinkFaceG / 2; step >= 1; step >>= 1)
-            if ((uint32_t)s_i[k + step][6] <= v) k += step;
-        uint32_t u = v - (uint32_t)s_i[k][6];
-        int c[3];
-        c[0] = s_i[k][0] + (int)(u % (uint32_t)s_i[k][3]);
-        u /= (uint32_t)s_i[k][3];
-        c[1] = s_i[k][1] + (int)(u % (uint32_t)s_i[k][4]);
-        c[2] = s_i[k][2] + (int)(u / (uint32_t)s_i[k][4]);
-        const int64_t idx = find_block<D>(B, c);
-        if (idx < 0) continue;
-        if constexpr (kScatter) {
-            const uint32_t pos = loff[idx] + atomicAdd(&cursor[idx], 1u);
-            if (pos < cap) {
-                list[pos] = (int32_t)(f0 + k);
-                lblk[pos] = (uint32_t)idx;
-            }
-        } else {
-            atomicAdd(&cnt[idx], 1u);
-        }
-    }
+    link_faces_wave<D, kScatter>(aabb, F, G, B, max_coords, cnt, loff, cursor, list, lblk, cap,
+                                 (int64_t)blockIdx.x * kLinkFaceG);
 }
 
 template <int D, int Q>
 __global__ __launch_bounds__(64) void k_links_nodes(LinkArgs<D, Q> A, const uint32_t *lblk,
                                                     unsigned long long *mask) {
-    links_nodes_entries<D, Q>(A, lblk, mask);
+    links_nodes_entries<D, Q>(A, lblk, mask, blockIdx.x, gridDim.x);
 }
 
-// Node k -> its block (nblk) and node key, from the blocks' masks and first
-// rows: one thread per block writes its nodes in cell order.
 template <int D>
 __global__ __launch_bounds__(256) void k_node_map(const unsigned long long *mask, const uint32_t *noff,
                                                   const uint32_t *keys, int64_t n, uint32_t *nblk,
                                                   uint64_t *node_key) {
-    constexpr int CELLS = D == 3 ? 64 : 16;
-    for (int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x; b < n; b += (int64_t)gridDim.x * 256) {
-        unsigned long long m = mask[b];
-        int64_t k = noff[b];
-        const uint64_t base = (uint64_t)keys[b] * CELLS;
-        while (m) {
-            const int cell = __builtin_ctzll(m);
-            m &= m - 1ull;
-            nblk[k] = (uint32_t)b;
-            node_key[k] = base + (uint64_t)cell;
-            ++k;
-        }
-    }
+    for (int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x; b < n; b += (int64_t)gridDim.x * 256)
+        node_map_block<D>(mask, noff, keys, b, nblk, node_key);
 }
 
 template <int D, int Q>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_links_rows(
     LinkArgs<D, Q> A, const uint32_t *lblk, const uint32_t *nblk, uint32_t nn) {
     links_rows_nodes<D, Q>(A, lblk, nblk, A.node_key, nn, (int64_t)blockIdx.x);
-}
-
-// Candidate blocks per face along each axis at most, from the largest face box
-// extent (bound of the list length); +2 covers the FP64 rounding of the range.
-inline double link_blocks_per_face(int D, const float ext[3], const float dx[3], const float eps[3]) {
-    double p = 1.0;
-    for (int a = 0; a < D; ++a)
-        p *= std::floor(((double)ext[a] * (1.0 + 1e-6) + 5.0 * dx[a] + 4.0 * (double)eps[a]) / (4.0 * dx[a])) + 2.0;
-    return p;
 }
 
 template <int D, int Q>
@@ -348,6 +198,82 @@ agal_status links_forward_walk(agal_geom g, agal_bins bn, agal_forest fo, agal_l
     return AGAL_OK;
 }
 
+// First half of the list build: the parent table, the zeroed node masks and
+// every block's candidate count (lwork[0 .. n); lwork[n .. 2n) zeroed for the
+// scatter cursors).
+template <int D>
+struct ListBuild {
+    BlockFind B{};
+    LinkFaceGrid G{};
+    unsigned long long *nmask = nullptr;
+    uint32_t *lwork = nullptr;
+};
+
+template <int D>
+agal_status list_count(agal_geom g, agal_forest fo, const float eps[3], int64_t max_coords, CallScratch &st,
+                       ListBuild<D> &LB, hipStream_t s) {
+    const agal::Level &LL = fo->lev[fo->L];
+    const int64_t n = LL.n;
+    const int L = fo->L;
+    BlockFind &B = LB.B;
+    B.level = L;
+    B.keys = LL.keys;
+    B.n = n;
+    for (int a = 0; a < 3; ++a) B.R[a] = fo->roots[a];
+    unsigned long long *hash = nullptr;
+    const unsigned fgrid = (unsigned)((g->F + kLinkFaceG - 1) / kLinkFaceG);
+    const unsigned bgrid = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+    AGAL_TRY(st.get(&LB.nmask, (size_t)n));
+    if (L > 0) {
+        // parents: n / 2^D (complete families); at most half the slots used
+        int bits = 6;
+        while (bits < 31 && (int64_t(1) << bits) < 2 * ((n + (1 << D) - 1) >> D)) ++bits;
+        B.hmask = (uint32_t)((int64_t(1) << bits) - 1);
+        B.hshift = 32 - bits;
+        AGAL_TRY(st.get(&hash, (size_t)B.hmask + 1));
+        fill_u64(reinterpret_cast<uint64_t *>(hash), ~0ull, (int64_t)B.hmask + 1, s);
+    }
+    hipLaunchKernelGGL((k_link_blocks<D>), dim3(bgrid), dim3(256), 0, s, LL.keys, n, hash, B.hmask, B.hshift,
+                       LB.nmask);
+    B.hash = hash;
+    LinkFaceGrid &G = LB.G;
+    for (int a = 0; a < 3; ++a) {
+        G.lo[a] = fo->lo[a];
+        G.dx[a] = fo->dx[L][a];
+        G.m[a] = 2.0 * (double)eps[a];
+        G.NB[a] = a < D ? (fo->roots[a] << L) : 1;
+    }
+    AGAL_TRY(st.get(&LB.lwork, (size_t)2 * n));   // counts, then scatter cursors
+    fill_u32(LB.lwork, 0u, 2 * n, s);
+    hipLaunchKernelGGL((k_link_faces<D, false>), dim3(fgrid), dim3(64), 0, s, g->aabb, g->F, G, B, max_coords,
+                       LB.lwork, nullptr, nullptr, nullptr, nullptr, 0u);
+    AGAL_TRY_HIP(hipGetLastError());
+    return AGAL_OK;
+}
+
+// Link step mode of (g, fo): list mode while every face has few candidate
+// blocks and the list fits 32-bit offsets.
+struct LinkMode {
+    bool lists = false;
+    int64_t per_face = 0;   // candidate blocks per face at most
+    double cap = 0.0;       // list length bound
+    float eps[3] = {0, 0, 0};
+};
+
+inline LinkMode link_mode(agal_geom g, agal_forest fo) {
+    LinkMode m;
+    float dx[3];
+    for (int a = 0; a < 3; ++a) {
+        dx[a] = fo->dx[fo->L][a];
+        m.eps[a] = dev::kEps * std::max(1.0f, std::max(std::fabs(fo->lo[a]), std::fabs(fo->hi[a])));
+    }
+    const double per_face = link_blocks_per_face(g->dim, g->max_extent, dx, m.eps);
+    m.cap = per_face * (double)g->F;
+    m.lists = per_face <= (double)g->ctx->link_list_max && m.cap <= (double)UINT32_MAX;
+    m.per_face = m.lists ? (int64_t)per_face : 0;
+    return m;
+}
+
 // List mode: candidate lists, node pass, scan, row pass (rows written once).
 // A list bound above kListNoWait entries is replaced by the exact length (one
 // more host wait) rather than allocated.
@@ -356,67 +282,38 @@ constexpr int64_t kListNoWait = int64_t(1) << 26;
 template <int D, int Q>
 agal_status links_forward_lists(agal_geom g, agal_bins bn, agal_forest fo, agal_links lk, int64_t max_coords,
                                 int64_t list_cap, hipStream_t s) {
-    constexpr int CELLS = D == 3 ? 64 : 16;
     agal_context ctx = g->ctx;
     const agal::Level &LL = fo->lev[fo->L];
     const int64_t n = LL.n;
-    const int L = fo->L;
     LinkArgs<D, Q> A = link_args<D, Q>(g, bn, fo);
     CallScratch st{ctx, s};
-    BlockFind B{};
-    B.level = L;
-    B.keys = LL.keys;
-    B.n = n;
-    for (int a = 0; a < 3; ++a) B.R[a] = fo->roots[a];
-    unsigned long long *hash = nullptr, *nmask = nullptr;
-    uint32_t *lwork = nullptr, *loff = nullptr, *lblk = nullptr, *noff = nullptr, *nblk = nullptr;
+    ListBuild<D> LB;
+    uint32_t *loff = nullptr, *lblk = nullptr, *noff = nullptr, *nblk = nullptr;
     int32_t *list = nullptr;
     const unsigned fgrid = (unsigned)((g->F + kLinkFaceG - 1) / kLinkFaceG);
     const unsigned bgrid = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
-    AGAL_TRY(st.get(&nmask, (size_t)n));
     {
         ProfScope prof(ctx, "q_lists", s);
-        if (L > 0) {
-            // parents: n / 2^D (complete families); at most half the slots used
-            int bits = 6;
-            while (bits < 31 && (int64_t(1) << bits) < 2 * ((n + (1 << D) - 1) >> D)) ++bits;
-            B.hmask = (uint32_t)((int64_t(1) << bits) - 1);
-            B.hshift = 32 - bits;
-            AGAL_TRY(st.get(&hash, (size_t)B.hmask + 1));
-            fill_u64(reinterpret_cast<uint64_t *>(hash), ~0ull, (int64_t)B.hmask + 1, s);
-        }
-        hipLaunchKernelGGL((k_link_blocks<D>), dim3(bgrid), dim3(256), 0, s, LL.keys, n, hash, B.hmask, B.hshift,
-                           nmask);
-        B.hash = hash;
-        LinkFaceGrid G{};
-        for (int a = 0; a < 3; ++a) {
-            G.lo[a] = fo->lo[a];
-            G.dx[a] = fo->dx[L][a];
-            G.m[a] = 2.0 * (double)A.eps[a];
-            G.NB[a] = a < D ? (fo->roots[a] << L) : 1;
-        }
-        AGAL_TRY(st.get(&lwork, (size_t)2 * n));   // counts, then scatter cursors
+        AGAL_TRY(list_count<D>(g, fo, A.eps, max_coords, st, LB, s));
         AGAL_TRY(st.get(&loff, (size_t)n + 1));
-        fill_u32(lwork, 0u, 2 * n, s);
-        hipLaunchKernelGGL((k_link_faces<D, false>), dim3(fgrid), dim3(64), 0, s, g->aabb, g->F, G, B,
-                           max_coords, lwork, nullptr, nullptr, nullptr, nullptr, 0u);
         if (list_cap <= kListNoWait) {
             // the bound is small enough to allocate: no host wait
-            AGAL_TRY(scan_u32(ctx, lwork, loff, n, s));
+            AGAL_TRY(scan_u32(ctx, LB.lwork, loff, n, s));
         } else {
             uint32_t total = 0;
-            AGAL_TRY(scan_u32_total(ctx, lwork, loff, n, nullptr, &total, s));
+            AGAL_TRY(scan_u32_total(ctx, LB.lwork, loff, n, nullptr, &total, s));
             list_cap = total;
         }
         AGAL_TRY(st.get(&list, (size_t)std::max<int64_t>(list_cap, 1)));
         AGAL_TRY(st.get(&lblk, (size_t)std::max<int64_t>(list_cap, 1)));
-        hipLaunchKernelGGL((k_link_faces<D, true>), dim3(fgrid), dim3(64), 0, s, g->aabb, g->F, G, B,
-                           max_coords, nullptr, loff, lwork + n, list, lblk, (uint32_t)list_cap);
+        hipLaunchKernelGGL((k_link_faces<D, true>), dim3(fgrid), dim3(64), 0, s, g->aabb, g->F, LB.G, LB.B,
+                           max_coords, nullptr, loff, LB.lwork + n, list, lblk, (uint32_t)list_cap);
     }
     AGAL_TRY_HIP(hipGetLastError());
     A.loff = loff;
     A.list = list;
     A.list_cap = (uint32_t)list_cap;
+    unsigned long long *nmask = LB.nmask;
     {
         // persistent waves over the list entries: eight per SIMD at most
         const int64_t want = (list_cap + 63) / 64;
@@ -445,21 +342,25 @@ agal_status links_forward_lists(agal_geom g, agal_bins bn, agal_forest fo, agal_
 
 template <int D, int Q>
 agal_status links_forward(agal_geom g, agal_bins bn, agal_forest fo, const Lattice &, agal_links lk, hipStream_t s) {
-    agal_context ctx = g->ctx;
     const agal::Level &LL = fo->lev[fo->L];
     if (LL.n == 0) return alloc_link_outputs<D, Q>(lk, 0u, s);
-    // list mode while every face has few candidate blocks and the list fits
-    // 32-bit offsets
-    float dx[3], eps[3];
-    for (int a = 0; a < 3; ++a) {
-        dx[a] = fo->dx[fo->L][a];
-        eps[a] = dev::kEps * std::max(1.0f, std::max(std::fabs(fo->lo[a]), std::fabs(fo->hi[a])));
-    }
-    const double per_face = link_blocks_per_face(D, g->max_extent, dx, eps);
-    const double cap = per_face * (double)g->F;
-    if (per_face <= (double)ctx->link_list_max && cap <= (double)UINT32_MAX)
-        return links_forward_lists<D, Q>(g, bn, fo, lk, (int64_t)per_face, (int64_t)cap, s);
+    const LinkMode m = link_mode(g, fo);
+    if (m.lists) return links_forward_lists<D, Q>(g, bn, fo, lk, m.per_face, (int64_t)m.cap, s);
     return links_forward_walk<D, Q>(g, bn, fo, lk, s);
+}
+
+template <int D>
+agal_status list_entries_impl(agal_geom g, agal_forest fo, const LinkMode &m, int64_t *entries, hipStream_t s) {
+    CallScratch st{g->ctx, s};
+    ListBuild<D> LB;
+    const int64_t n = fo->lev[fo->L].n;
+    uint32_t *loff = nullptr;
+    AGAL_TRY(list_count<D>(g, fo, m.eps, m.per_face, st, LB, s));
+    AGAL_TRY(st.get(&loff, (size_t)n + 1));
+    uint32_t total = 0;
+    AGAL_TRY(scan_u32_total(g->ctx, LB.lwork, loff, n, nullptr, &total, s, false));
+    *entries = total;
+    return AGAL_OK;
 }
 
 template <int D, int Q>
@@ -496,43 +397,77 @@ agal_status links_backward(agal_geom g, agal_links lk, const Lattice &lat, const
 // leaving it c_i . n > 0.  The sign is taken in FP64 from the face's FP32
 // corners (edge differences and the two-term products exact, one rounding per
 // normal component and per sum, in a fixed order), so it is the same on every
-// device.  One workgroup takes 256 nodes; its threads walk the nodes' rows as
-// one flat, coalesced run of slots and OR each slot's code (1 enter, 2 leave,
-// 3 on the face's plane) into the node's LDS word.
+// device.  One workgroup takes 256 nodes; its waves walk the nodes' rows as
+// one flat run of slots, 64 consecutive slots per wave and kClassU runs in
+// flight per thread (face ids, then records, loaded together).  Each slot has
+// a code (1 enter, 2 leave, 3 on the face's plane); two ballots combine the
+// codes of a node's slots within the wave, and the node's first lane ORs them
+// into its LDS word (two or three LDS atomics per wave).
 constexpr int kClassThreads = 256;
+constexpr int kClassU = 4;
 
 template <int D, int Q>
 __global__ __launch_bounds__(kClassThreads) void k_classify_nodes(const float *rec, const int32_t *face, int64_t n,
                                                                   uint8_t *cls) {
     __shared__ uint32_t s_code[kClassThreads];
     const int tid = threadIdx.x;
+    const int lane = dev::lane_id();
     const int64_t node0 = (int64_t)blockIdx.x * kClassThreads;
     const int nn = (int)min((int64_t)kClassThreads, n - node0);
     s_code[tid] = 0u;
     __syncthreads();
     const int span = nn * Q;
     const int32_t *row = face + node0 * Q;
-    for (int sl = tid; sl < span; sl += kClassThreads) {
-        const int32_t f = row[sl];
-        const int i = sl % Q;
-        if (f < 0 || i == 0) continue;
-        float v[dev::kRecFloats<D>];
-        dev::load_rec<D>(rec, f, v);
-        double nrm[3] = {0.0, 0.0, 0.0};
-        if constexpr (D == 3) {
-            const double e1[3] = {(double)v[3] - (double)v[0], (double)v[4] - (double)v[1], (double)v[5] - (double)v[2]};
-            const double e2[3] = {(double)v[6] - (double)v[0], (double)v[7] - (double)v[1], (double)v[8] - (double)v[2]};
-            nrm[0] = e1[1] * e2[2] - e1[2] * e2[1];
-            nrm[1] = e1[2] * e2[0] - e1[0] * e2[2];
-            nrm[2] = e1[0] * e2[1] - e1[1] * e2[0];
-        } else {
-            nrm[0] = (double)v[3] - (double)v[1];
-            nrm[1] = -((double)v[2] - (double)v[0]);
+    for (int k0 = 0; k0 < span; k0 += kClassU * kClassThreads) {
+        int32_t f[kClassU];
+#pragma unroll
+        for (int u = 0; u < kClassU; ++u) {
+            const int sl = k0 + u * kClassThreads + tid;
+            f[u] = sl < span && sl % Q != 0 ? row[sl] : -1;
         }
-        const double sg = ((double)dir_c<D>(i, 0) * nrm[0] + (double)dir_c<D>(i, 1) * nrm[1]) +
-                          (double)dir_c<D>(i, 2) * nrm[2];
-        const uint32_t code = sg < 0.0 ? 1u : (sg > 0.0 ? 2u : 3u);
-        atomicOr(&s_code[sl / Q], code);
+        float v[kClassU][dev::kRecFloats<D>];
+#pragma unroll
+        for (int u = 0; u < kClassU; ++u)
+            if (f[u] >= 0) dev::load_rec<D>(rec, f[u], v[u]);
+#pragma unroll
+        for (int u = 0; u < kClassU; ++u) {
+            const int base = k0 + u * kClassThreads + (tid - lane);   // first slot of this wave's run
+            if (base >= span) break;                                   // wave-uniform
+            const int sl = base + lane;
+            uint32_t code = 0u;
+            if (f[u] >= 0) {
+                const float *w = v[u];
+                double nrm[3] = {0.0, 0.0, 0.0};
+                if constexpr (D == 3) {
+                    const double e1[3] = {(double)w[3] - (double)w[0], (double)w[4] - (double)w[1],
+                                          (double)w[5] - (double)w[2]};
+                    const double e2[3] = {(double)w[6] - (double)w[0], (double)w[7] - (double)w[1],
+                                          (double)w[8] - (double)w[2]};
+                    nrm[0] = e1[1] * e2[2] - e1[2] * e2[1];
+                    nrm[1] = e1[2] * e2[0] - e1[0] * e2[2];
+                    nrm[2] = e1[0] * e2[1] - e1[1] * e2[0];
+                } else {
+                    nrm[0] = (double)w[3] - (double)w[1];
+                    nrm[1] = -((double)w[2] - (double)w[0]);
+                }
+                const int i = sl % Q;
+                const double sg = ((double)dir_c<D>(i, 0) * nrm[0] + (double)dir_c<D>(i, 1) * nrm[1]) +
+                                  (double)dir_c<D>(i, 2) * nrm[2];
+                code = sg < 0.0 ? 1u : (sg > 0.0 ? 2u : 3u);
+            }
+            const uint64_t enter = __ballot((code & 1u) != 0u);
+            const uint64_t leave = __ballot((code & 2u) != 0u);
+            if (sl < span) {
+                const int node = sl / Q;
+                const int lo = max(node * Q - base, 0);
+                if (lane == lo) {
+                    const int hi = min(node * Q + Q - 1 - base, dev::kWave - 1);
+                    const uint64_t range = (hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1ull)) & ~((1ull << lo) - 1ull);
+                    const uint32_t c = ((enter & range) ? 1u : 0u) | ((leave & range) ? 2u : 0u);
+                    if (c) atomicOr(&s_code[node], c);
+                }
+            }
+        }
     }
     __syncthreads();
     if (tid < nn) {
@@ -555,6 +490,17 @@ agal_status classify_nodes(agal_geom g, agal_links lk, uint8_t *cls, hipStream_t
 }
 
 }  // namespace
+
+agal_status link_list_plan(agal_geom g, agal_forest fo, hipStream_t s, LinkListPlan *out) {
+    *out = LinkListPlan{};
+    const LinkMode m = link_mode(g, fo);
+    out->lists = m.lists && fo->lev[fo->L].n > 0;
+    if (!out->lists) return AGAL_OK;
+    out->per_face = m.per_face;
+    if (g->dim == 3) return list_entries_impl<3>(g, fo, m, &out->entries, s);
+    return list_entries_impl<2>(g, fo, m, &out->entries, s);
+}
+
 }  // namespace agal
 
 using namespace agal;

@@ -4,7 +4,8 @@ cell flags, node keys, q and face ids bit-identical; vertex gradients equal up
 to the order of floating-point atomics), including mixed lattices, zero
 levels, empty refinement, tuned bin densities, reruns of the same plan,
 capacity overflow and invalid input -- and, body by body, what the oracle
-gives (forest bit-exact, q within 1e-5 of FP64)."""
+gives (forest bit-exact, q within 1e-5 of FP64); the link step in list mode, walk mode or both
+within one plan."""
 import numpy as np
 import pytest
 
@@ -121,6 +122,25 @@ def test_batch_mixed_3d_equals_plain(orc):
     bt.status()
     for i, w in enumerate(wls):
         _same_as_plain(bt, i, w, plain[i])
+
+
+@pytest.mark.parametrize("limit", [0, 1 << 30])
+def test_batch_link_modes_equal_plain(limit):
+    """The batched link step with every body in walk mode (limit 0) or in list mode (every body, the box
+    of large faces included): identical to the single-body calls at their default mode."""
+    import paper_2502_16310_amd as agal
+    ctx = agal.Context()
+    ctx.set_link_list_limit(limit)
+    wls = _mixed_3d()
+    ts = [_tensors(w) for w in wls]
+    bt = agal.Batch([(v, f, _cfg(w, w.bins)) for w, (v, f) in zip(wls, ts)], tune_bins=False, tune_grid=False,
+                    ctx=ctx)
+    log(f"case batch link list limit {limit}: {len(wls)} bodies")
+    for _ in range(2):
+        bt.run()
+        bt.status()
+        for i, w in enumerate(wls):
+            _same_as_plain(bt, i, w)
 
 
 @pytest.mark.parametrize("limit", [0, 512])
