@@ -540,6 +540,7 @@ def bench_batch(args):
     torch.cuda.synchronize()
     # workload size per body from the single-body results (identical to the batch's)
     T = 0
+    T_flag = T_q = 0
     kept = plain_all(keep=True)
     torch.cuda.synchronize()
     n_nodes = 0
@@ -554,6 +555,8 @@ def bench_batch(args):
         tf, tq = cell_face_tests(off, bins[i], 3, levels, w.roots, w.levels, [float(x) for x in w.d_spec()],
                                  w.lo, w.hi)
         T += sum(tf) + tq
+        T_flag += sum(tf)
+        T_q += tq
         n_nodes += agal.agal_links_view(lk)[3]
         for h, fn in ((lk, agal.agal_destroy_links), (fo, agal.agal_destroy_forest), (b, agal.agal_destroy_bins),
                       (g, agal.agal_destroy_geom)):
@@ -590,9 +593,30 @@ def bench_batch(args):
         "batch_graph_ms": ms, "batch_graph_event_us": graph_us, "plain_sum_ms": plain_ms,
         "speedup_vs_plain": plain_ms / ms, "plan_s": plan_s, "workgroups_per_cu": bt.workgroups_per_cu,
         "bins_per_body": bins, "cell_face_tests": T, "boundary_nodes": n_nodes,
-        "roofline": None, "cpu_baseline": None,
+        "roofline": batch_roofline(T_flag, T_q, graph_us if graph_us else 1e3 * ms),
+        "cpu_baseline": None,
     }
+    if not args.no_cpu_baseline:
+        # the oracle on one subdivision-4 body of the batch (its rate in the batch's unit)
+        i = next(i for i, d in enumerate(draws) if d["s"] == 4)
+        print(f"bench: timing the CPU oracle on body {i} of the batch", file=sys.stderr, flush=True)
+        import dataclasses
+        wl_i = dataclasses.replace(wls[i], bins=bins[i])   # the bin density the plan chose for it
+        cb = cpu_baseline(wl_i, geomgen.weights(4 ** 3 * 4 * 10 ** 6, 2 + i).astype(np.float64), None)
+        cb["sample"] = f"body {i} of the batch ({len(wls[i].faces)} faces): " + cb["sample"]
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
+
+
+def batch_roofline(t_flag, t_q, graph_us):
+    """Roofline of the whole batched graph as one unit: its arithmetic work is the flag tests (24 ops per
+    (cell, candidate face) pair) plus the link step (8 ops per pair), against the non-packed FP32 VALU peak;
+    the graph's other kernels (bins, scans, balance, adjoint) count as time but not as work."""
+    ops = OPS_PER_PAIR["flag_sat"] * t_flag + OPS_PER_PAIR["q_step"] * t_q
+    tops = ops / (graph_us * 1e-6) / 1e12
+    return {"bound": "alu", "achieved": tops, "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
+            "frac": tops / VALU_PEAK_TOPS, "traffic": None, "kernel": "batch_graph (whole graph)",
+            "ops_per_launch": ops, "flag_pairs": t_flag, "q_pairs": t_q, "avg_launch_us": graph_us}
 
 
 def bench_bin_density(args):

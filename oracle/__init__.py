@@ -137,6 +137,8 @@ class Bins:
         F = self._coords.shape[0]
         self.h = lib().orc_bin_faces(dim, _ptr(self._coords, C.c_float), F, _ptr(self.lo, C.c_float),
                                      _ptr(self.hi, C.c_float), B)
+        if not self.h:
+            raise ValueError(f"bins per axis must be at least 1 (got {B}) and dim 2 or 3")
         nb = lib().orc_bins_nb(self.h)
         P = lib().orc_bins_P(self.h)
         self.nb, self.P = nb, P

@@ -149,6 +149,7 @@ static void face_bin_range(const orc_bins *bn, const float *fc, int lo_i[3], int
 }
 
 orc_bins *orc_bin_faces(int dim, const float *coords, int64_t F, const float *lo, const float *hi, int B) {
+    if (B < 1 || (dim != 2 && dim != 3)) return NULL;
     orc_bins *bn = (orc_bins *)xcalloc(1, sizeof(orc_bins));
     bn->dim = dim;
     bn->B = B;

@@ -846,3 +846,11 @@ def test_adjoint_matches_finite_differences(orc):
         tm = segment_triangle(o[n_], D, qs[1][fi])
         num += w[n_, i] * float((tp[0] - tm[0]) / (2 * Fr(hstep)))
     assert abs(num - lin) <= 1e-4 * max(1.0, abs(lin))
+
+
+def test_bins_reject_fewer_than_one_bin(orc):
+    """A bin density below one per axis (or a dimension other than 2 and 3) is refused, not binned."""
+    coords = np.zeros((1, 3, 3), dtype=np.float32)
+    for dim, B in ((3, 0), (3, -2), (4, 8)):
+        with pytest.raises(ValueError):
+            orc.bin_faces(dim, coords, (0, 0, 0), (1, 1, 1), B)
