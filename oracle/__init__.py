@@ -79,6 +79,8 @@ def lib():
             "orc_links_tests": (C.c_int64, [P]),
             "orc_link_grad": (None, [P, P, fp, i32p, dp, dp]),
             "orc_classify_nodes": (None, [C.c_int, C.c_int, C.c_int64, i32p, fp, u8p]),
+            "orc_forest_diff": (None, [C.POINTER(C.c_uint32), u8p, C.c_int64, C.POINTER(C.c_uint32), u8p,
+                                       C.c_int64, i32p, u8p, u8p]),
             "orc_link_stable": (None, [P, P, fp, C.c_int64, P, C.c_double, C.c_double, C.c_double,
                                        C.c_double, C.c_double, u8p]),
             "orc_link_t": (C.c_int, [P, C.c_uint64, C.c_int, C.c_int, fp, C.c_int32, dp]),
@@ -288,6 +290,25 @@ def classify_nodes(dim: int, Q: int, face: np.ndarray, coords) -> np.ndarray:
     out = np.zeros(face.shape[0], dtype=np.uint8)
     lib().orc_classify_nodes(dim, Q, face.shape[0], _ptr(face, C.c_int32), _ptr(coords, C.c_float),
                              _ptr(out, C.c_uint8))
+    return out
+
+
+def forest_diff(old_levels, new_levels):
+    """Per level of two forests over the same root grid: (old_index, state, removed) of orc_forest_diff.
+    Levels are dicts with "keys" (sorted uint32) and "leaf" (uint8), as Forest.levels holds them."""
+    out = []
+    for lo_, ln_ in zip(old_levels, new_levels):
+        ok = np.ascontiguousarray(lo_["keys"], dtype=np.uint32)
+        ol = np.ascontiguousarray(lo_["leaf"], dtype=np.uint8)
+        nk = np.ascontiguousarray(ln_["keys"], dtype=np.uint32)
+        nl = np.ascontiguousarray(ln_["leaf"], dtype=np.uint8)
+        idx = np.zeros(len(nk), dtype=np.int32)
+        st = np.zeros(len(nk), dtype=np.uint8)
+        rm = np.zeros(len(ok), dtype=np.uint8)
+        lib().orc_forest_diff(_ptr(ok, C.c_uint32), _ptr(ol, C.c_uint8), len(ok), _ptr(nk, C.c_uint32),
+                              _ptr(nl, C.c_uint8), len(nk), _ptr(idx, C.c_int32), _ptr(st, C.c_uint8),
+                              _ptr(rm, C.c_uint8))
+        out.append((idx, st, rm))
     return out
 
 

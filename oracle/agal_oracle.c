@@ -972,6 +972,46 @@ static void face_normal(int dim, const double *p, double *n) {
 }
 
 /*
+ * Re-adaptation bookkeeping (the refine-and-coarsen step that a moving body
+ * needs each time its geometry changes; the paper refines only once, before
+ * the solver, and names moving geometry as the case to come, Results
+ * discussion).  The re-adapted forest itself is the near-wall refinement of
+ * the new geometry; what a solver also needs is how it relates to the old
+ * forest, level by level, over the same root grid.  Per block of the new
+ * level: old_index = its position in the old level (-1: absent) and state
+ *   0 kept (present in both with the same leaf bit),
+ *   1 created (absent from the old level),
+ *   2 refined (a leaf before, now with children),
+ *   3 coarsened (children before, now a leaf: its children are removed);
+ * per block of the old level: removed = 1 when its key is absent from the new
+ * level.  Keys of a level are sorted ascending; each lookup is a binary search.
+ */
+static int64_t key_search(const uint32_t *keys, int64_t n, uint32_t k) {
+    int64_t lo = 0, hi = n - 1;
+    while (lo <= hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (keys[mid] == k) return mid;
+        if (keys[mid] < k) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+void orc_forest_diff(const uint32_t *old_keys, const uint8_t *old_leaf, int64_t n_old, const uint32_t *new_keys,
+                     const uint8_t *new_leaf, int64_t n_new, int32_t *old_index, uint8_t *state,
+                     uint8_t *removed) {
+    for (int64_t i = 0; i < n_new; ++i) {
+        int64_t j = key_search(old_keys, n_old, new_keys[i]);
+        old_index[i] = (int32_t)j;
+        if (j < 0) state[i] = 1;
+        else if (old_leaf[j] && !new_leaf[i]) state[i] = 2;
+        else if (!old_leaf[j] && new_leaf[i]) state[i] = 3;
+        else state[i] = 0;
+    }
+    for (int64_t j = 0; j < n_old; ++j) removed[j] = key_search(new_keys, n_new, old_keys[j]) < 0 ? 1 : 0;
+}
+
+/*
  * Node classification: the step after the link fractions that the paper
  * leaves to future work (Results discussion, Conclusion).  With the faces
  * oriented so that n = (b - a) x (c - a) (3D) or n = (e_y, -e_x), e = b - a

@@ -96,6 +96,17 @@ MUTANTS = [
      "double sgn = ((double)c[3 * i] * nrm[0] + (double)c[3 * i + 1] * nrm[1]) + (double)c[3 * i + 2] * nrm[2];",
      "double sgn = ((double)c[3 * i - 3] * nrm[0] + (double)c[3 * i - 2] * nrm[1]) + (double)c[3 * i - 1] * nrm[2];",
      "test_classify_3d_matches_winding_number or test_classify_circle_matches_winding_number"),
+    ("re-adaptation with refined and coarsened swapped",
+     "state[i] = 2;\n        else if (!old_leaf[j] && new_leaf[i]) state[i] = 3;",
+     "state[i] = 3;\n        else if (!old_leaf[j] && new_leaf[i]) state[i] = 2;",
+     "test_diff_matches_brute_force"),
+    ("re-adaptation looks removed blocks up in the old level",
+     "removed[j] = key_search(new_keys, n_new, old_keys[j]) < 0 ? 1 : 0;",
+     "removed[j] = key_search(old_keys, n_old, old_keys[j]) < 0 ? 1 : 0;",
+     "test_diff_family_structure"),
+    ("re-adaptation maps a kept block to its own index",
+     "old_index[i] = (int32_t)j;", "old_index[i] = j < 0 ? -1 : (int32_t)i;",
+     "test_diff_family_structure or test_diff_matches_brute_force"),
 ]
 
 
@@ -112,7 +123,7 @@ def test_pins_catch_mutant(tmp_path, name, old, new, tests):
     env = dict(os.environ, AGAL_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         os.path.join(HERE, "test_oracle_pins.py"), os.path.join(HERE, "test_oracle_own_bin.py"),
-                        os.path.join(HERE, "test_oracle_classify.py"),
+                        os.path.join(HERE, "test_oracle_classify.py"), os.path.join(HERE, "test_oracle_readapt.py"),
                         "-k", tests],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"pins did not catch: {name}\n{r.stdout[-2000:]}"
