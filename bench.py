@@ -378,8 +378,8 @@ def main():
 def classify_leg(args, agal, torch, g, lk, n_nodes, Q, dim, F, stream):
     """The step after q: the side of every boundary node (agal_classify_nodes), timed on its own with HIP
     events on the launch stream over 20 launches on this step's links.  Algorithmic HBM bytes: the face-id
-    rows (n_nodes x Q x 4 B) read once, one class byte per node written, and every face record (16 FP32 in
-    3D, 8 in 2D) read at most once."""
+    rows (n_nodes x Q x 4 B) read once, one class byte per node written, every face record (16 FP32 in 3D,
+    8 in 2D) read once for the per-face sign words, which are written and read back once (8 B each way)."""
     if n_nodes == 0:
         return None
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -394,7 +394,7 @@ def classify_leg(args, agal, torch, g, lk, n_nodes, Q, dim, F, stream):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    nbytes = n_nodes * Q * 4 + n_nodes + F * (64 if dim == 3 else 32)
+    nbytes = n_nodes * Q * 4 + n_nodes + F * ((64 if dim == 3 else 32) + 16)
     counts = torch.bincount(out.long(), minlength=4)[1:].tolist()
     gbs = nbytes / (ms * 1e-3) / 1e9
     return {"ms": ms, "algorithmic_bytes": nbytes, "GBps": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,

@@ -397,18 +397,48 @@ agal_status links_backward(agal_geom g, agal_links lk, const Lattice &lat, const
 // leaving it c_i . n > 0.  The sign is taken in FP64 from the face's FP32
 // corners (edge differences and the two-term products exact, one rounding per
 // normal component and per sum, in a fixed order), so it is the same on every
-// device.  One workgroup takes 256 nodes; its waves walk the nodes' rows as
-// one flat run of slots, 64 consecutive slots per wave and kClassU runs in
-// flight per thread (face ids, then records, loaded together).  Each slot has
-// a code (1 enter, 2 leave, 3 on the face's plane); two ballots combine the
-// codes of a node's slots within the wave, and the node's first lane ORs them
-// into its LDS word (two or three LDS atomics per wave).
+// device.  First every face gets its signs for all directions at once (bit i:
+// c_i . n < 0, bit 32 + i: c_i . n > 0, both for 0), 8 bytes per face; then
+// the nodes' rows are read as one flat run of slots, 64 consecutive slots per
+// wave and kClassU runs in flight per thread (face ids, then the faces' sign
+// words, loaded together).  Two ballots combine the codes of a node's slots
+// within the wave, and the node's first lane ORs them into its LDS word (two
+// or three LDS atomics per wave).
+template <int D, int Q>
+__global__ __launch_bounds__(256) void k_face_signs(const float *rec, int64_t F, unsigned long long *sign) {
+    static_assert(Q <= 32, "direction bits in 32-bit halves");
+    for (int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x; f < F; f += (int64_t)gridDim.x * 256) {
+        float w[dev::kRecFloats<D>];
+        dev::load_rec<D>(rec, f, w);
+        double nrm[3] = {0.0, 0.0, 0.0};
+        if constexpr (D == 3) {
+            const double e1[3] = {(double)w[3] - (double)w[0], (double)w[4] - (double)w[1], (double)w[5] - (double)w[2]};
+            const double e2[3] = {(double)w[6] - (double)w[0], (double)w[7] - (double)w[1], (double)w[8] - (double)w[2]};
+            nrm[0] = e1[1] * e2[2] - e1[2] * e2[1];
+            nrm[1] = e1[2] * e2[0] - e1[0] * e2[2];
+            nrm[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        } else {
+            nrm[0] = (double)w[3] - (double)w[1];
+            nrm[1] = -((double)w[2] - (double)w[0]);
+        }
+        uint32_t enter = 0u, leave = 0u;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const double sg = ((double)dir_c<D>(i, 0) * nrm[0] + (double)dir_c<D>(i, 1) * nrm[1]) +
+                              (double)dir_c<D>(i, 2) * nrm[2];
+            enter |= sg <= 0.0 ? (1u << i) : 0u;
+            leave |= sg >= 0.0 ? (1u << i) : 0u;
+        }
+        sign[f] = ((unsigned long long)leave << 32) | enter;
+    }
+}
+
 constexpr int kClassThreads = 256;
 constexpr int kClassU = 4;
 
-template <int D, int Q>
-__global__ __launch_bounds__(kClassThreads) void k_classify_nodes(const float *rec, const int32_t *face, int64_t n,
-                                                                  uint8_t *cls) {
+template <int Q>
+__global__ __launch_bounds__(kClassThreads) void k_classify_nodes(const unsigned long long *sign, int64_t F,
+                                                                  const int32_t *face, int64_t n, uint8_t *cls) {
     __shared__ uint32_t s_code[kClassThreads];
     const int tid = threadIdx.x;
     const int lane = dev::lane_id();
@@ -423,40 +453,19 @@ __global__ __launch_bounds__(kClassThreads) void k_classify_nodes(const float *r
 #pragma unroll
         for (int u = 0; u < kClassU; ++u) {
             const int sl = k0 + u * kClassThreads + tid;
-            f[u] = sl < span && sl % Q != 0 ? row[sl] : -1;
+            f[u] = sl < span ? row[sl] : -1;
         }
-        float v[kClassU][dev::kRecFloats<D>];
+        unsigned long long t[kClassU];
 #pragma unroll
-        for (int u = 0; u < kClassU; ++u)
-            if (f[u] >= 0) dev::load_rec<D>(rec, f[u], v[u]);
+        for (int u = 0; u < kClassU; ++u) t[u] = f[u] >= 0 && f[u] < F ? sign[f[u]] : 0ull;
 #pragma unroll
         for (int u = 0; u < kClassU; ++u) {
             const int base = k0 + u * kClassThreads + (tid - lane);   // first slot of this wave's run
             if (base >= span) break;                                   // wave-uniform
             const int sl = base + lane;
-            uint32_t code = 0u;
-            if (f[u] >= 0) {
-                const float *w = v[u];
-                double nrm[3] = {0.0, 0.0, 0.0};
-                if constexpr (D == 3) {
-                    const double e1[3] = {(double)w[3] - (double)w[0], (double)w[4] - (double)w[1],
-                                          (double)w[5] - (double)w[2]};
-                    const double e2[3] = {(double)w[6] - (double)w[0], (double)w[7] - (double)w[1],
-                                          (double)w[8] - (double)w[2]};
-                    nrm[0] = e1[1] * e2[2] - e1[2] * e2[1];
-                    nrm[1] = e1[2] * e2[0] - e1[0] * e2[2];
-                    nrm[2] = e1[0] * e2[1] - e1[1] * e2[0];
-                } else {
-                    nrm[0] = (double)w[3] - (double)w[1];
-                    nrm[1] = -((double)w[2] - (double)w[0]);
-                }
-                const int i = sl % Q;
-                const double sg = ((double)dir_c<D>(i, 0) * nrm[0] + (double)dir_c<D>(i, 1) * nrm[1]) +
-                                  (double)dir_c<D>(i, 2) * nrm[2];
-                code = sg < 0.0 ? 1u : (sg > 0.0 ? 2u : 3u);
-            }
-            const uint64_t enter = __ballot((code & 1u) != 0u);
-            const uint64_t leave = __ballot((code & 2u) != 0u);
+            const int i = sl % Q;   // the rest direction (i = 0) has bit 0 clear in both halves
+            const uint64_t enter = __ballot(((t[u] >> i) & 1ull) != 0ull);
+            const uint64_t leave = __ballot(((t[u] >> (32 + i)) & 1ull) != 0ull);
             if (sl < span) {
                 const int node = sl / Q;
                 const int lo = max(node * Q - base, 0);
@@ -479,10 +488,15 @@ __global__ __launch_bounds__(kClassThreads) void k_classify_nodes(const float *r
 template <int D, int Q>
 agal_status classify_nodes(agal_geom g, agal_links lk, uint8_t *cls, hipStream_t s) {
     if (lk->n == 0) return AGAL_OK;
+    CallScratch st{g->ctx, s};
+    unsigned long long *sign = nullptr;
+    AGAL_TRY(st.get(&sign, (size_t)std::max<int64_t>(g->F, 1)));
     const int64_t blocks = (lk->n + kClassThreads - 1) / kClassThreads;
     {
         ProfScope prof(g->ctx, "classify", s);
-        hipLaunchKernelGGL((k_classify_nodes<D, Q>), dim3((unsigned)blocks), dim3(kClassThreads), 0, s, g->rec,
+        hipLaunchKernelGGL((k_face_signs<D, Q>), dim3((unsigned)std::min<int64_t>((g->F + 255) / 256, 8192)),
+                           dim3(256), 0, s, g->rec, g->F, sign);
+        hipLaunchKernelGGL((k_classify_nodes<Q>), dim3((unsigned)blocks), dim3(kClassThreads), 0, s, sign, g->F,
                            lk->face, lk->n, cls);
     }
     AGAL_TRY_HIP(hipGetLastError());
