@@ -51,6 +51,7 @@ def lib():
             "orc_lattice": (C.c_int, [C.c_int, i32p]),
             "orc_gather": (None, [C.c_int, fp, i32p, C.c_int64, fp]),
             "orc_bin_faces": (P, [C.c_int, fp, C.c_int64, fp, fp, C.c_int]),
+            "orc_bin_faces_discrete": (P, [C.c_int, fp, C.c_int64, fp, fp, C.c_int, C.c_float]),
             "orc_bins_free": (None, [P]),
             "orc_bins_nb": (C.c_int64, [P]),
             "orc_bins_P": (C.c_int64, [P]),
@@ -132,15 +133,21 @@ def _vec3(x, fill) -> np.ndarray:
 
 
 class Bins:
-    def __init__(self, dim: int, coords: np.ndarray, lo, hi, B: int):
+    """Bins of the faces: by bounding box (spacing None), or by the paper's sampled points at `spacing`."""
+
+    def __init__(self, dim: int, coords: np.ndarray, lo, hi, B: int, spacing: Optional[float] = None):
         self._coords = np.ascontiguousarray(coords, dtype=np.float32)
         self.dim, self.B = dim, B
         self.lo, self.hi = _vec3(lo, 0.0), _vec3(hi, 1.0)
         F = self._coords.shape[0]
-        self.h = lib().orc_bin_faces(dim, _ptr(self._coords, C.c_float), F, _ptr(self.lo, C.c_float),
-                                     _ptr(self.hi, C.c_float), B)
+        if spacing is None:
+            self.h = lib().orc_bin_faces(dim, _ptr(self._coords, C.c_float), F, _ptr(self.lo, C.c_float),
+                                         _ptr(self.hi, C.c_float), B)
+        else:
+            self.h = lib().orc_bin_faces_discrete(dim, _ptr(self._coords, C.c_float), F, _ptr(self.lo, C.c_float),
+                                                  _ptr(self.hi, C.c_float), B, C.c_float(spacing))
         if not self.h:
-            raise ValueError(f"bins per axis must be at least 1 (got {B}) and dim 2 or 3")
+            raise ValueError(f"bins per axis must be at least 1 (got {B}), dim 2 or 3, spacing positive")
         nb = lib().orc_bins_nb(self.h)
         P = lib().orc_bins_P(self.h)
         self.nb, self.P = nb, P
@@ -156,6 +163,11 @@ class Bins:
 
 def bin_faces(dim, coords, lo, hi, B) -> Bins:
     return Bins(dim, coords, lo, hi, B)
+
+
+def bin_faces_discrete(dim, coords, lo, hi, B, spacing) -> Bins:
+    """The paper's binning: each face in every bin holding one of its sampled points."""
+    return Bins(dim, coords, lo, hi, B, spacing)
 
 
 def sat(dim: int, face: np.ndarray, m: Sequence[float], h: float) -> bool:

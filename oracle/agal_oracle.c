@@ -193,6 +193,125 @@ orc_bins *orc_bin_faces(int dim, const float *coords, int64_t F, const float *lo
     return bn;
 }
 
+/*
+ * The paper's own binning (Sec. II-C-3, spatial binning and its
+ * discretization figure): every face is sampled at points whose number grows
+ * with its size, and it is assigned to each bin holding at least one point.
+ * An edge from a to b, e = b - a, is cut into 2^k equal pieces, k the least
+ * integer >= 0 with max_a |e_a| <= spacing * 2^k (k at most ORC_DISC_KMAX); its
+ * points are a + e * (j * 2^-k), j = 0 .. 2^k, each component one FP32
+ * product and one FP32 sum.  A triangle (a, b, c) takes the points q_j of its
+ * edge a -> b, and every segment q_j -> c is sampled the same way (its own k).
+ * A 2D face is its edge.  Points go to bins by the same index function as the
+ * box binning.  Output layout as orc_bin_faces: per bin, ascending face ids.
+ */
+#define ORC_DISC_KMAX 12
+
+static int disc_k(const float *e, int dim, float spacing) {
+    float s = 0.0f;
+    for (int a = 0; a < dim; ++a) s = fmax2(s, fabsf(e[a]));
+    int k = 0;
+    while (k < ORC_DISC_KMAX && !(s <= ldexpf(spacing, k))) ++k;
+    return k;
+}
+
+/* visits every sample point of face fc, calling add(bin) */
+static void disc_visit(const orc_bins *bn, const float *fc, float spacing, int64_t *list, int64_t *nlist,
+                       int64_t *stamp, int64_t mark) {
+    int dim = bn->dim, B = bn->B;
+    const float *a = fc, *b = fc + dim;
+    float e[3] = {0, 0, 0};
+    for (int x = 0; x < dim; ++x) e[x] = b[x] - a[x];
+    int k1 = disc_k(e, dim, spacing);
+    int64_t n1 = (int64_t)1 << k1;
+    for (int64_t j = 0; j <= n1; ++j) {
+        float t = ldexpf((float)j, -k1);
+        float q[3] = {0, 0, 0};
+        for (int x = 0; x < dim; ++x) q[x] = a[x] + e[x] * t;
+        float g[3] = {0, 0, 0};
+        int k2 = 0;
+        if (dim == 3) {
+            for (int x = 0; x < 3; ++x) g[x] = fc[6 + x] - q[x];
+            k2 = disc_k(g, 3, spacing);
+        }
+        int64_t n2 = dim == 3 ? ((int64_t)1 << k2) : 0;
+        for (int64_t i = 0; i <= n2; ++i) {
+            float p[3] = {0, 0, 0};
+            if (dim == 3) {
+                float u = ldexpf((float)i, -k2);
+                for (int x = 0; x < 3; ++x) p[x] = q[x] + g[x] * u;
+            } else {
+                p[0] = q[0];
+                p[1] = q[1];
+            }
+            int ix[3] = {0, 0, 0};
+            for (int x = 0; x < dim; ++x) ix[x] = bin_index(p[x], bn->lo[x], bn->s[x], B);
+            int64_t bb = ((int64_t)ix[2] * B + ix[1]) * B + ix[0];
+            if (stamp[bb] != mark) {
+                stamp[bb] = mark;
+                list[(*nlist)++] = bb;
+            }
+        }
+    }
+}
+
+static int cmp_i64(const void *x, const void *y) {
+    int64_t a = *(const int64_t *)x, b = *(const int64_t *)y;
+    return (a > b) - (a < b);
+}
+
+orc_bins *orc_bin_faces_discrete(int dim, const float *coords, int64_t F, const float *lo, const float *hi, int B,
+                                 float spacing) {
+    if (B < 1 || (dim != 2 && dim != 3) || !(spacing > 0.0f)) return NULL;
+    orc_bins *bn = (orc_bins *)xcalloc(1, sizeof(orc_bins));
+    bn->dim = dim;
+    bn->B = B;
+    bn->nb = 1;
+    for (int a = 0; a < 3; ++a) {
+        bn->lo[a] = a < dim ? lo[a] : 0.0f;
+        bn->hi[a] = a < dim ? hi[a] : 1.0f;
+        bn->s[a] = (float)B / (bn->hi[a] - bn->lo[a]);
+        if (a < dim) bn->nb *= B;
+    }
+    bn->count = (uint32_t *)xcalloc((size_t)bn->nb, sizeof(uint32_t));
+    bn->off = (uint32_t *)xcalloc((size_t)bn->nb + 1, sizeof(uint32_t));
+    int64_t *stamp = (int64_t *)xmalloc((size_t)bn->nb * sizeof(int64_t));
+    for (int64_t b = 0; b < bn->nb; ++b) stamp[b] = -1;
+    /* the distinct bins of each face, face by face */
+    int64_t cap = 1024, n = 0;
+    int64_t *pairs_bin = (int64_t *)xmalloc((size_t)cap * sizeof(int64_t));
+    int64_t *pairs_face = (int64_t *)xmalloc((size_t)cap * sizeof(int64_t));
+    int64_t *list = (int64_t *)xmalloc((size_t)bn->nb * sizeof(int64_t));
+    for (int64_t f = 0; f < F; ++f) {
+        int64_t nl = 0;
+        disc_visit(bn, coords + f * dim * dim, spacing, list, &nl, stamp, f);
+        qsort(list, (size_t)nl, sizeof(int64_t), cmp_i64);
+        for (int64_t i = 0; i < nl; ++i) {
+            if (n == cap) {
+                cap *= 2;
+                pairs_bin = (int64_t *)xrealloc(pairs_bin, (size_t)cap * sizeof(int64_t));
+                pairs_face = (int64_t *)xrealloc(pairs_face, (size_t)cap * sizeof(int64_t));
+            }
+            pairs_bin[n] = list[i];
+            pairs_face[n] = f;
+            ++n;
+            bn->count[list[i]] += 1;
+        }
+    }
+    uint64_t run = 0;
+    for (int64_t b = 0; b < bn->nb; ++b) { bn->off[b] = (uint32_t)run; run += bn->count[b]; }
+    bn->off[bn->nb] = (uint32_t)run;
+    bn->P = (int64_t)run;
+    bn->ids = (int32_t *)xmalloc((size_t)(bn->P > 0 ? bn->P : 1) * sizeof(int32_t));
+    uint32_t *cur = (uint32_t *)xcalloc((size_t)bn->nb, sizeof(uint32_t));
+    for (int64_t i = 0; i < n; ++i) {   /* pairs are in ascending face order */
+        int64_t b = pairs_bin[i];
+        bn->ids[bn->off[b] + cur[b]++] = (int32_t)pairs_face[i];
+    }
+    free(cur); free(stamp); free(list); free(pairs_bin); free(pairs_face);
+    return bn;
+}
+
 void orc_bins_free(orc_bins *bn) {
     if (!bn) return;
     free(bn->count); free(bn->off); free(bn->ids); free(bn);

@@ -107,6 +107,19 @@ MUTANTS = [
     ("re-adaptation maps a kept block to its own index",
      "old_index[i] = (int32_t)j;", "old_index[i] = j < 0 ? -1 : (int32_t)i;",
      "test_diff_family_structure or test_diff_matches_brute_force"),
+    ("sampled binning fans its segments towards the wrong vertex",
+     "g[x] = fc[6 + x] - q[x];", "g[x] = fc[x] - q[x];",
+     "test_assigned_bins_meet_the_face_and_hold_its_vertices or test_spacing_above_the_face_samples_its_vertices_only"),
+    ("sampled binning one subdivision too coarse",
+     "while (k < ORC_DISC_KMAX && !(s <= ldexpf(spacing, k))) ++k;",
+     "while (k < ORC_DISC_KMAX && !(s <= ldexpf(spacing, k + 1))) ++k;",
+     "test_segments_cover_every_bin_they_cross_by_more_than_the_spacing"),
+    ("sampled binning stops half way along the first edge",
+     "float t = ldexpf((float)j, -k1);", "float t = ldexpf((float)j, -k1 - 1);",
+     "test_assigned_bins_meet_the_face_and_hold_its_vertices or test_spacing_above_the_face_samples_its_vertices_only"),
+    ("sampled binning with the bin index transposed",
+     "int64_t bb = ((int64_t)ix[2] * B + ix[1]) * B + ix[0];", "int64_t bb = ((int64_t)ix[2] * B + ix[0]) * B + ix[1];",
+     "test_assigned_bins_meet_the_face_and_hold_its_vertices"),
 ]
 
 
@@ -124,6 +137,7 @@ def test_pins_catch_mutant(tmp_path, name, old, new, tests):
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         os.path.join(HERE, "test_oracle_pins.py"), os.path.join(HERE, "test_oracle_own_bin.py"),
                         os.path.join(HERE, "test_oracle_classify.py"), os.path.join(HERE, "test_oracle_readapt.py"),
+                        os.path.join(HERE, "test_oracle_discrete_bins.py"),
                         "-k", tests],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"pins did not catch: {name}\n{r.stdout[-2000:]}"
