@@ -227,6 +227,8 @@ def main():
         return bench_batch(args)
     if args.config.upper() in ("P0", "P1"):
         return bench_bin_density(args)
+    if args.config.upper() == "M0":
+        return bench_moving(args)
     wl = geomgen.workload(args.config)
     dim, Q = wl.dim, wl.lattice
     print(f"bench: {wl.name} faces={len(wl.faces)} roots={wl.roots[:dim]} levels={wl.levels} bins={wl.bins} "
@@ -617,6 +619,103 @@ def batch_roofline(t_flag, t_q, graph_us):
     return {"bound": "alu", "achieved": tops, "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
             "frac": tops / VALU_PEAK_TOPS, "traffic": None, "kernel": "batch_graph (whole graph)",
             "ops_per_launch": ops, "flag_pairs": t_flag, "q_pairs": t_q, "avg_launch_us": graph_us}
+
+
+def bench_moving(args):
+    """A moving body: the 327,680-face star translated by (0.37, 0.21, -0.13) finest cells per step.  Each step
+    re-adapts from the moved faces: import, bins, refinement from the roots, the relation to the previous
+    step's forest (kept / created / refined / coarsened / removed blocks), link fractions and node classes.
+    The vertex positions of every step are prepared on the device before the timed region; HIP events on the
+    launch stream bracket each step; per-kernel times come from a second, profiled pass."""
+    import torch
+    import geomgen
+    import paper_2502_16310_amd as agal
+
+    dev = torch.device("cuda", 0)
+    wl = geomgen.workload("C2")
+    dim, Q = wl.dim, wl.lattice
+    dx = float(wl.cell_size(wl.levels))
+    step = np.array([0.37, 0.21, -0.13]) * dx
+    K, W = args.steps, args.warmup
+    print(f"bench: M0 moving star, {len(wl.faces)} faces, {K} steps of {step.tolist()}", file=sys.stderr, flush=True)
+    f = torch.from_numpy(wl.faces).to(dev)
+    vs = [torch.from_numpy((wl.vertices + (step * k).astype(np.float32)).astype(np.float32)).to(dev)
+          for k in range(W + 2 * K + 1)]
+    d_spec = [float(x) for x in wl.d_spec()]
+    ctx = agal.agal_context_create()
+    stream = torch.cuda.current_stream().cuda_stream
+    desc = agal.forest_desc(dim, wl.roots[:dim], wl.levels, d_spec, wl.lo[:dim], wl.hi[:dim])
+    cls = torch.empty(8 << 20, dtype=torch.uint8, device=dev)
+
+    def build(k):
+        v = vs[k]
+        g = agal.agal_import_faces(ctx, dim, v.data_ptr(), v.shape[0], f.data_ptr(), f.shape[0], stream)
+        b = agal.agal_bin_faces(g, wl.lo[:dim], wl.hi[:dim], wl.bins, stream)
+        fo = agal.agal_near_wall_refine(g, b, desc, stream)
+        return g, b, fo
+
+    def step_once(prev, k, ev=None):
+        nonlocal cls
+        if ev:
+            ev[0].record()
+        g, b, fo = build(k)
+        d = agal.agal_forest_diff_create(prev[2], fo, stream)
+        lk = agal.agal_link_fractions(g, b, fo, Q, stream)
+        n = agal.agal_links_view(lk)[3]
+        if n > cls.numel():
+            cls = torch.empty(2 * n, dtype=torch.uint8, device=dev)
+        agal.agal_classify_nodes(g, lk, cls.data_ptr(), stream)
+        if ev:
+            ev[1].record()
+        counts = [agal.agal_forest_diff_view(d, l)[5] for l in range(wl.levels + 1)]
+        agal.agal_destroy_forest_diff(d)
+        agal.agal_destroy_links(lk)
+        for h, fn in ((prev[2], agal.agal_destroy_forest), (prev[1], agal.agal_destroy_bins),
+                      (prev[0], agal.agal_destroy_geom)):
+            fn(h)
+        return (g, b, fo), counts, n
+
+    cur = build(0)
+    k = 1
+    for _ in range(W):
+        cur, _, _ = step_once(cur, k)
+        k += 1
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(K)]
+    all_counts, nodes = [], []
+    t0 = time.perf_counter()
+    for i in range(K):
+        cur, c, n = step_once(cur, k, evs[i])
+        all_counts.append(c)
+        nodes.append(n)
+        k += 1
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / K
+    ev_ms = sorted(e[0].elapsed_time(e[1]) for e in evs)
+    agal.agal_profile_read(ctx)
+    agal.agal_profile_enable(ctx, True)
+    for _ in range(K):
+        cur, _, _ = step_once(cur, k)
+        k += 1
+    torch.cuda.synchronize()
+    agal.agal_profile_enable(ctx, False)
+    prof = agal.agal_profile_read(ctx)
+    for h, fn in ((cur[2], agal.agal_destroy_forest), (cur[1], agal.agal_destroy_bins), (cur[0], agal.agal_destroy_geom)):
+        fn(h)
+    kern = {name: {"ms_per_step": t / K, "launches_per_step": n / K} for name, (n, t) in prof.items()}
+    tot = np.array(all_counts).sum(axis=0)   # levels x 4
+    out = {
+        "metric": "moving-body re-adaptation steps/s", "value": 1e3 / ms, "unit": "steps/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "M0: C2 star body translated by (0.37, 0.21, -0.13) finest cells per step; per step "
+                               "import, bins, refinement, forest relation, D3Q27 link fractions, node classes",
+                   "faces": len(wl.faces), "roots": list(wl.roots[:dim]), "levels": wl.levels, "bins": wl.bins},
+        "step_event_ms_median": ev_ms[len(ev_ms) // 2], "boundary_nodes_mean": float(np.mean(nodes)),
+        "blocks_per_step_created_refined_coarsened_removed": (tot / K).tolist(),
+        "kernels": kern,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_bin_density(args):

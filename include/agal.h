@@ -53,6 +53,7 @@ typedef struct agal_bins_t *agal_bins;
 typedef struct agal_forest_t *agal_forest;
 typedef struct agal_links_t *agal_links;
 typedef struct agal_batch_t *agal_batch;
+typedef struct agal_forest_diff_t *agal_forest_diff;
 
 /* Optional device allocator.  alloc returns device memory usable on `stream`
  * (or NULL on failure); free releases it in stream order.  A NULL allocator
@@ -144,6 +145,32 @@ AGAL_API agal_status agal_bins_view(agal_bins b, const uint32_t **d_offsets, con
 AGAL_API agal_status agal_bin_faces_noalloc(agal_geom g, const float lo[3], const float hi[3], int32_t B,
                                             uint32_t *d_offsets, int32_t *d_face_ids, int64_t ids_capacity,
                                             void *stream, int64_t *n_entries);
+/* The paper's own binning (Sec. II-C-3 and its discretization figure): each
+ * face is sampled at points and goes to every bin holding one of them.  An
+ * edge a -> b, e = b - a, is cut into 2^k equal pieces, k the least integer
+ * >= 0 (at most 12) with max_a |e_a| <= spacing * 2^k; its points are
+ * a + e * (j 2^-k), j = 0..2^k (FP32, one product and one sum per component).
+ * A triangle (a, b, c) takes the points q_j of edge a -> b and samples every
+ * segment q_j -> c the same way; a 2D face is its edge.  A point's bin is
+ * idx() of agal_bin_faces per axis.  Output: the same CSR layout (ascending
+ * face ids per bin), a subset of the bounding-box bins.
+ *   spacing       sample spacing in domain units; <= 0 selects half the
+ *                 smallest bin edge.
+ *   bin_fraction  0: the (face, bin) pairs are counted, scanned and
+ *                 scattered; B_f >= 1: the paper's form, B^D / B_f bins at a
+ *                 time (rounded up) through an indicator array of that many
+ *                 rows of n_faces words, each row then compacted in face
+ *                 order (memory ~ 4 n_faces B^D / B_f bytes).
+ * Sampled-point bins serve the own-bin refinement and the list-mode link
+ * step; the box-test refinement and the bin walk of the link step need the
+ * bounding-box bins and refuse these (AGAL_EINVAL).
+ * Errors: those of agal_bin_faces; AGAL_EINVAL for a negative bin_fraction
+ * or a NaN or infinite spacing; AGAL_ECAPACITY when one fraction's indicator
+ * array would exceed 32 GiB.  Synchronises `stream` (the pairs form once, the
+ * fraction form once more when its first guess of ten entries per face was
+ * short). */
+AGAL_API agal_status agal_bin_faces_discrete(agal_geom g, const float lo[3], const float hi[3], int32_t B,
+                                             float spacing, int32_t bin_fraction, void *stream, agal_bins *out);
 
 /* ---- near-wall refinement (Sec. II-C-1, II-C-2, II-A) --------------------
  * For pass l = 0..n_levels-1, every cell of every block present at level l
@@ -203,6 +230,35 @@ AGAL_API agal_status agal_forest_level_view(agal_forest f, int level, const uint
                                             const uint8_t **d_leaf, const uint8_t **d_mark,
                                             const uint8_t **d_cell_flag, int64_t *n_blocks);
 AGAL_API agal_status agal_forest_info(agal_forest f, int *dim, int *n_levels);
+
+/* ---- re-adaptation of a moving body ---------------------------------------
+ * The paper refines once, before the solver, and names moving geometry as the
+ * case where rebuilding the bins every step weighs on the choice of bin
+ * density (Results discussion); refinement and coarsening of the blocks are
+ * those of the forest-of-octrees scheme (Sec. II-C-1).  A step of a moving
+ * body imports the moved faces, bins them and refines from the roots (the
+ * re-adapted forest is the near-wall forest of the new geometry); this call
+ * then relates it to the previous forest, level by level, for a solver to
+ * carry its block data over.  Both forests must share dimension, root grid,
+ * domain and level count; they may come from different geometries.
+ * Per level l, device arrays owned by the diff (valid until it is destroyed):
+ *   d_old_index[n_new] int32  position of each new block in the old level l,
+ *                             -1 when the old level has no such key;
+ *   d_state[n_new]     uint8  0 kept (same key and leaf bit), 1 created,
+ *                             2 refined (a leaf before, now with children),
+ *                             3 coarsened (children before, now a leaf: they
+ *                             are removed at level l + 1);
+ *   d_removed[n_old]   uint8  1 when the old block's key is absent from the
+ *                             new level l;
+ *   counts[4]                 created, refined, coarsened, removed blocks.
+ * Synchronises `stream` once (to read the counts).
+ * Errors: AGAL_EINVAL for NULL arguments or forests over different grids. */
+AGAL_API agal_status agal_forest_diff_create(agal_forest old_forest, agal_forest new_forest, void *stream,
+                                             agal_forest_diff *out);
+AGAL_API agal_status agal_forest_diff_view(agal_forest_diff d, int level, const int32_t **d_old_index,
+                                           const uint8_t **d_state, const uint8_t **d_removed, int64_t *n_new,
+                                           int64_t *n_old, int64_t counts[4]);
+AGAL_API void agal_destroy_forest_diff(agal_forest_diff d);
 
 /* ---- link fractions (Sec. II-C-1) ----------------------------------------
  * For every cell of every block of the finest level and every non-rest

@@ -70,6 +70,7 @@ def _load():
         "agal_geom_view": [P, C.POINTER(C.c_int), C.POINTER(i64), C.POINTER(i64), PP, PP],
         "agal_bin_faces": [P, C.POINTER(C.c_float), C.POINTER(C.c_float), i32, vp, PP],
         "agal_bins_view": [P, PP, PP, C.POINTER(i64), C.POINTER(i64)],
+        "agal_bin_faces_discrete": [P, C.POINTER(C.c_float), C.POINTER(C.c_float), i32, C.c_float, i32, vp, PP],
         "agal_bin_faces_noalloc": [P, C.POINTER(C.c_float), C.POINTER(C.c_float), i32, vp, vp, i64, vp,
                                    C.POINTER(i64)],
         "agal_near_wall_refine": [P, P, C.POINTER(_ForestDesc), vp, PP],
@@ -80,6 +81,9 @@ def _load():
         "agal_links_view": [P, PP, PP, PP, C.POINTER(i64), C.POINTER(C.c_int)],
         "agal_link_fractions_backward": [P, P, vp, vp, vp],
         "agal_classify_nodes": [P, P, vp, vp],
+        "agal_forest_diff_create": [P, P, vp, PP],
+        "agal_forest_diff_view": [P, C.c_int, PP, PP, PP, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
+        "agal_destroy_forest_diff": [P],
         "agal_lattice_vectors": [C.c_int, C.POINTER(i32)],
         "agal_profile_enable": [P, C.c_int],
         "agal_context_set_flag_table_limit": [P, C.c_int64],
@@ -106,7 +110,7 @@ def _load():
         fn.argtypes = args
         fn.restype = C.c_int
     for name in ("agal_context_destroy", "agal_destroy_geom", "agal_destroy_bins", "agal_destroy_forest",
-                 "agal_destroy_links", "agal_destroy_batch"):
+                 "agal_destroy_links", "agal_destroy_batch", "agal_destroy_forest_diff"):
         getattr(lib, name).restype = None
     lib.agal_status_string.restype = C.c_char_p
     lib.agal_last_error.restype = C.c_char_p
@@ -170,6 +174,14 @@ def agal_bin_faces(geom, lo: Sequence[float], hi: Sequence[float], B: int, strea
     return out
 
 
+def agal_bin_faces_discrete(geom, lo: Sequence[float], hi: Sequence[float], B: int, spacing: float = 0.0,
+                            bin_fraction: int = 0, stream: int = 0) -> C.c_void_p:
+    out = C.c_void_p()
+    _check(_lib.agal_bin_faces_discrete(_h(geom), _f3(lo, 0.0), _f3(hi, 1.0), int(B), C.c_float(spacing),
+                                        int(bin_fraction), stream or None, C.byref(out)), "agal_bin_faces_discrete")
+    return out
+
+
 def agal_bin_faces_noalloc(geom, lo: Sequence[float], hi: Sequence[float], B: int, d_offsets: int,
                            d_face_ids: Optional[int], ids_capacity: int, stream: int = 0) -> int:
     """Bins into caller buffers without device allocation; returns the entry count P."""
@@ -221,6 +233,27 @@ def agal_forest_level_view(forest, level: int):
     _check(_lib.agal_forest_level_view(_h(forest), level, C.byref(k), C.byref(lf), C.byref(mk), C.byref(cf),
                                        C.byref(n)), "agal_forest_level_view")
     return k.value, lf.value, mk.value, cf.value, n.value
+
+
+def agal_forest_diff_create(old_forest, new_forest, stream: int = 0):
+    out = C.c_void_p()
+    _check(_lib.agal_forest_diff_create(_h(old_forest), _h(new_forest), stream or None, C.byref(out)),
+           "agal_forest_diff_create")
+    return out.value
+
+
+def agal_forest_diff_view(diff, level: int):
+    """(old_index ptr, state ptr, removed ptr, n_new, n_old, [created, refined, coarsened, removed])."""
+    oi, st, rm = C.c_void_p(), C.c_void_p(), C.c_void_p()
+    nn, no = C.c_int64(), C.c_int64()
+    cnt = (C.c_int64 * 4)()
+    _check(_lib.agal_forest_diff_view(_h(diff), level, C.byref(oi), C.byref(st), C.byref(rm), C.byref(nn),
+                                      C.byref(no), cnt), "agal_forest_diff_view")
+    return oi.value, st.value, rm.value, nn.value, no.value, list(cnt)
+
+
+def agal_destroy_forest_diff(h):
+    _lib.agal_destroy_forest_diff(_h(h))
 
 
 def agal_forest_info(forest):
@@ -371,9 +404,9 @@ def agal_last_error() -> str:
     return _lib.agal_last_error().decode(errors="replace")
 
 
-from .torch_api import (Batch, Bins, Context, Forest, Geometry, LinkFractions, Links, NearWallConfig,  # noqa: E402
-                        device_copy, device_write, near_wall)
+from .torch_api import (Batch, Bins, Context, Forest, ForestDiff, Geometry, LinkFractions, Links,  # noqa: E402
+                        NearWallConfig, device_copy, device_write, near_wall)
 
 __all__ = [n for n in dir() if n.startswith("agal_")] + [
-    "AgalError", "Batch", "device_write", "Context", "Geometry", "Bins", "Forest", "Links", "LinkFractions", "NearWallConfig", "near_wall",
+    "AgalError", "Batch", "device_write", "Context", "Geometry", "Bins", "Forest", "ForestDiff", "Links", "LinkFractions", "NearWallConfig", "near_wall",
     "forest_desc", "body_desc", "tune_opts", "device_copy", "LIB_PATH"]

@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libagal.so")
-SOURCES = ["runtime.hip", "import.hip", "bins.hip", "refine.hip", "links.hip", "batch.hip"]
+SOURCES = ["runtime.hip", "import.hip", "bins.hip", "refine.hip", "links.hip", "batch.hip", "readapt.hip", "discrete.hip"]
 
 HIPCC = os.environ.get("HIPCC") or shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = "gfx950"

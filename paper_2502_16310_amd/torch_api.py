@@ -14,11 +14,12 @@ from typing import List, Optional, Sequence, Tuple
 import torch
 
 from . import (AgalError, agal_batch_body_view, agal_batch_info, agal_batch_level_view, agal_batch_plan_create,
-               agal_batch_run, agal_batch_status, agal_bin_faces, agal_bins_view, agal_context_create,
+               agal_batch_run, agal_batch_status, agal_bin_faces, agal_bin_faces_discrete, agal_bins_view, agal_context_create,
                agal_context_set_flag_table_limit, agal_context_set_link_list_limit,
                agal_context_destroy, agal_destroy_batch, agal_destroy_bins, agal_destroy_forest, agal_destroy_geom,
                agal_destroy_links, agal_forest_info, agal_forest_level_view, agal_geom_view, agal_import_faces,
-               agal_classify_nodes, agal_link_fractions, agal_link_fractions_backward, agal_links_view, agal_near_wall_refine,
+               agal_classify_nodes, agal_destroy_forest_diff, agal_forest_diff_create, agal_forest_diff_view,
+               agal_link_fractions, agal_link_fractions_backward, agal_links_view, agal_near_wall_refine,
                agal_near_wall_refine_own_bin, body_desc,
                forest_desc, tune_opts)
 
@@ -189,11 +190,20 @@ class Geometry:
     def bin_faces(self, lo, hi, B: int) -> "Bins":
         return Bins(self, lo, hi, B)
 
+    def bin_faces_discrete(self, lo, hi, B: int, spacing: float = 0.0, bin_fraction: int = 0) -> "Bins":
+        """The paper's binning by sampled points (spacing <= 0: half the smallest bin edge; bin_fraction >= 1:
+        the paper's indicator-array form, B^D / bin_fraction bins at a time)."""
+        return Bins(self, lo, hi, B, discrete=True, spacing=spacing, bin_fraction=bin_fraction)
+
 
 class Bins:
-    def __init__(self, geom: Geometry, lo, hi, B: int):
+    def __init__(self, geom: Geometry, lo, hi, B: int, discrete: bool = False, spacing: float = 0.0,
+                 bin_fraction: int = 0):
         self.geom = geom
-        self.h = agal_bin_faces(geom.h, lo, hi, B, current_stream())
+        if discrete:
+            self.h = agal_bin_faces_discrete(geom.h, lo, hi, B, spacing, bin_fraction, current_stream())
+        else:
+            self.h = agal_bin_faces(geom.h, lo, hi, B, current_stream())
         self.B = B
         _, _, self.n_bins, self.n_entries = agal_bins_view(self.h)
 
@@ -239,6 +249,34 @@ class Forest:
 
     def link_fractions(self, lattice: int) -> "Links":
         return Links(self, lattice)
+
+    def diff(self, old: "Forest") -> "ForestDiff":
+        """How this forest relates to `old` (the same body's forest before it moved), level by level."""
+        return ForestDiff(old, self)
+
+
+class ForestDiff:
+    """Re-adaptation bookkeeping between two forests over the same root grid: per level, for every new block
+    its index in the old level (-1: none) and its state (0 kept, 1 created, 2 refined, 3 coarsened), for every
+    old block whether it was removed, and the counts [created, refined, coarsened, removed]."""
+
+    def __init__(self, old: Forest, new: Forest):
+        self.old, self.new = old, new
+        self.h = agal_forest_diff_create(old.h, new.h, current_stream())
+        self.n_levels = new.n_levels
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None:
+            agal_destroy_forest_diff(self.h)
+            self.h = None
+
+    def level(self, l: int) -> dict:
+        oi, st, rm, nn, no, cnt = agal_forest_diff_view(self.h, l)
+        return {"old_index": device_view(oi, (nn,), torch.int32, self), "state": device_view(st, (nn,), torch.uint8, self),
+                "removed": device_view(rm, (no,), torch.uint8, self), "counts": cnt}
+
+    def counts(self) -> List[List[int]]:
+        return [agal_forest_diff_view(self.h, l)[5] for l in range(self.n_levels + 1)]
 
 
 class Links:
