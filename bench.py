@@ -741,10 +741,13 @@ def bench_bin_density(args):
                             wl.hi[:dim])
     g = agal.agal_import_faces(ctx, dim, v.data_ptr(), v.shape[0], f.data_ptr(), f.shape[0], stream)
 
-    def run(B, own_bin):
+    def run(B, own_bin, binning="box", bf=0):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         e[0].record()
-        b = agal.agal_bin_faces(g, wl.lo[:dim], wl.hi[:dim], B, stream)
+        if binning == "box":
+            b = agal.agal_bin_faces(g, wl.lo[:dim], wl.hi[:dim], B, stream)
+        else:
+            b = agal.agal_bin_faces_discrete(g, wl.lo[:dim], wl.hi[:dim], B, 0.0, bf, stream)
         e[1].record()
         fo = (agal.agal_near_wall_refine_own_bin(g, b, desc, -1, stream) if own_bin
               else agal.agal_near_wall_refine(g, b, desc, stream))
@@ -760,27 +763,35 @@ def bench_bin_density(args):
         return e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), levels
 
     curve = []
-    for own_bin, Bs in ((True, (1, 2, 8, 16)), (False, (8,))):
-        for B in Bs:
-            for _ in range(args.warmup):
-                run(B, own_bin)
-            t_bin, t_ref = [], []
-            for _ in range(args.steps):
-                tb, tr, levels = run(B, own_bin)
-                t_bin.append(tb)
-                t_ref.append(tr)
-            t_bin.sort()
-            t_ref.sort()
-            blocks = [n for n, _ in levels]
-            curve.append({"form": "own-bin Euclidean + propagation" if own_bin else "closed box (all bins under it)",
-                          "B": B, "bin_ms": t_bin[len(t_bin) // 2], "refine_ms": t_ref[len(t_ref) // 2],
-                          "blocks_per_level": blocks, "inserted_blocks": int(sum(blocks[1:])),
-                          "marks_flag_balance_propagation": [m[1:4] for _, m in levels[:-1]]})
-            print(f"bench: {curve[-1]['form']} B={B}: bins {curve[-1]['bin_ms']:.3f} ms, refinement "
-                  f"{curve[-1]['refine_ms']:.3f} ms, blocks {blocks}", file=sys.stderr, flush=True)
+    # own-bin refinement on bounding-box bins and on the paper's sampled-point bins (the pairs form) over the
+    # paper's bin densities; the closed-box refinement; then the paper's bin-fraction form at one density
+    paper_Bs = (1, 2, 4, 6, 7, 8, 9, 10, 12, 14, 16)
+    plan = [(True, B, "box", 0) for B in (1, 2, 8, 16)] + [(True, B, "sampled", 0) for B in paper_Bs] + \
+           [(False, 8, "box", 0)] + [(True, 16, "sampled", bf) for bf in (1, 2, 4, 8, 16)]
+    for own_bin, B, binning, bf in plan:
+        for _ in range(args.warmup):
+            run(B, own_bin, binning, bf)
+        t_bin, t_ref = [], []
+        for _ in range(args.steps):
+            tb, tr, levels = run(B, own_bin, binning, bf)
+            t_bin.append(tb)
+            t_ref.append(tr)
+        t_bin.sort()
+        t_ref.sort()
+        blocks = [n for n, _ in levels]
+        form = "own-bin Euclidean + propagation" if own_bin else "closed box (all bins under it)"
+        bins_kind = ("bounding-box bins" if binning == "box" else
+                     "sampled-point bins" + (f", bin fraction {bf}" if bf else ", pairs form"))
+        curve.append({"form": form, "bins": bins_kind, "B": B, "bin_fraction": bf,
+                      "bin_ms": t_bin[len(t_bin) // 2], "refine_ms": t_ref[len(t_ref) // 2],
+                      "blocks_per_level": blocks, "inserted_blocks": int(sum(blocks[1:])),
+                      "marks_flag_balance_propagation": [m[1:4] for _, m in levels[:-1]]})
+        print(f"bench: {form}, {bins_kind}, B={B}: bins {curve[-1]['bin_ms']:.3f} ms, refinement "
+              f"{curve[-1]['refine_ms']:.3f} ms, blocks {blocks}", file=sys.stderr, flush=True)
     agal.agal_destroy_geom(g)
     agal.agal_context_destroy(ctx)
-    best = min((c for c in curve if c["form"].startswith("own")), key=lambda c: c["bin_ms"] + c["refine_ms"])
+    best = min((c for c in curve if c["form"].startswith("own") and c["bins"] == "bounding-box bins"),
+               key=lambda c: c["bin_ms"] + c["refine_ms"])
     out = {"metric": "near-wall refinement ms (bins + passes) vs bin density, own-bin form", "value":
            best["bin_ms"] + best["refine_ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": best["bin_ms"] + best["refine_ms"], "higher_is_better": False, "scaling": "weak",

@@ -130,6 +130,8 @@ struct agal_bins_t {
     int64_t nb = 0, P = 0;
     uint32_t *off = nullptr;   // nb + 1
     int32_t *ids = nullptr;    // P
+    bool discrete = false;     // faces binned by their sampled points (not a superset of the box bins)
+    float spacing = 0.0f;      // sample spacing of the discrete binning
 };
 
 namespace agal {

@@ -346,6 +346,9 @@ agal_status links_forward(agal_geom g, agal_bins bn, agal_forest fo, const Latti
     if (LL.n == 0) return alloc_link_outputs<D, Q>(lk, 0u, s);
     const LinkMode m = link_mode(g, fo);
     if (m.lists) return links_forward_lists<D, Q>(g, bn, fo, lk, m.per_face, (int64_t)m.cap, s);
+    if (bn->discrete)
+        return fail(AGAL_EINVAL, "agal_link_fractions: the faces are too large for candidate lists and the bin walk "
+                                 "needs bins by bounding box, not by sampled points");
     return links_forward_walk<D, Q>(g, bn, fo, lk, s);
 }
 

@@ -480,6 +480,9 @@ static agal_status near_wall_refine(agal_geom g, agal_bins b, const agal_forest_
                                     agal_forest *out, bool own_bin, int n_prop) {
     if (!g || !b || !desc || !out) return fail(AGAL_EINVAL, "agal_near_wall_refine: NULL argument");
     if (b->geom_id != g->id) return fail(AGAL_ESTATE, "agal_near_wall_refine: bins were built from another geometry");
+    if (b->discrete && !own_bin)
+        return fail(AGAL_EINVAL, "agal_near_wall_refine: the box test needs bins by bounding box (sampled-point bins "
+                                 "can miss a face that crosses a bin between its points); use the own-bin form");
     const int D = desc->dim;
     if (D != g->dim) return fail(AGAL_EINVAL, "agal_near_wall_refine: desc->dim %d != geometry dim %d", D, g->dim);
     if (desc->n_levels < 0 || desc->n_levels > kMaxLevels)
