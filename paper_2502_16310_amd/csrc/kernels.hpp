@@ -1113,10 +1113,28 @@ __device__ __forceinline__ uint32_t link_filter(const LinkStaged<D, CAP> &S, int
         for (int p = 0; p < NP; ++p) {
             const int i = 1 + 2 * p;
             const int c0 = dir_c<D>(i, 0), c1 = dir_c<D>(i, 1), c2 = dir_c<D>(i, 2);
+            // signed sums over the direction's non-zero components, started at the first of them (an
+            // addition to 0.0f would stay in the code: it only changes the sign of a zero, which no
+            // comparison below sees)
             float den = 0.0f, nu = 0.0f, nv = 0.0f;
-            if (c0) { den += c0 > 0 ? d0 : -d0; nu += c0 > 0 ? p10 : -p10; nv += c0 > 0 ? p20 : -p20; }
-            if (c1) { den += c1 > 0 ? d1 : -d1; nu += c1 > 0 ? p11 : -p11; nv += c1 > 0 ? p21 : -p21; }
-            if (c2) { den += c2 > 0 ? d2 : -d2; nu += c2 > 0 ? p12 : -p12; nv += c2 > 0 ? p22 : -p22; }
+            bool started = false;
+            auto term = [&](int c, float d, float pu, float pv) {
+                if (!c) return;
+                const float sd = c > 0 ? d : -d, su_ = c > 0 ? pu : -pu, sv_ = c > 0 ? pv : -pv;
+                if (started) {
+                    den += sd;
+                    nu += su_;
+                    nv += sv_;
+                } else {
+                    den = sd;
+                    nu = su_;
+                    nv = sv_;
+                    started = true;
+                }
+            };
+            term(c0, d0, p10, p20);
+            term(c1, d1, p11, p21);
+            term(c2, d2, p12, p22);
             const float ad = fabsf(den);
             const bool neg = den < 0.0f;
             const float su = neg ? -nu : nu;
