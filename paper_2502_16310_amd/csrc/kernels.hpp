@@ -1787,9 +1787,24 @@ __device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const 
     auto test_staged = [&](int n) {
         dev::wave_sync();
         uint32_t nm = 0;
-        if (valid)
-            for (int j = 0; j < n; ++j)
-                nm |= (s_sblk[j] == myb && (S.code[j] & lbits) == lbits) ? (1u << j) : 0u;
+        if (valid) {
+            // staged entries keep the lists' block order: the lane's own block is one range, found by two
+            // binary searches, and only that range is tested
+            int lo = 0, hi = n;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_sblk[mid] < myb) lo = mid + 1;
+                else hi = mid;
+            }
+            const int jlo = lo;
+            hi = n;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_sblk[mid] <= myb) lo = mid + 1;
+                else hi = mid;
+            }
+            for (int j = jlo; j < lo; ++j) nm |= ((S.code[j] & lbits) == lbits) ? (1u << j) : 0u;
+        }
         while (__ballot(nm != 0)) {
             bool pass = false;
             int j = 0;
