@@ -126,7 +126,7 @@ __global__ void k_disc_small(const float *rec, int64_t F, DiscGrid G, uint32_t *
         dev::load_rec<D>(rec, f, r);
         int lo[3], n[3];
         disc_range<D>(r, G.g, lo, n);
-        if (n[0] * n[1] * n[2] > 64) {
+        if ((int64_t)n[0] * n[1] * n[2] > 64) {
             if (!kScatter) big_list[atomicAdd(nbig, 1u)] = (uint32_t)f;
             continue;
         }
