@@ -5,7 +5,7 @@ forest level by level near the wall, compute the link fractions q and run
 the adjoint for a weighted sum of q -- every row of the hot path, on
 synthetic seeded geometry (see geomgen).  Prints ONE JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--config C2|C1|C4|P0|P1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--config C2|C1|C4|P0|P1|M0] [--no-cpu-baseline]
 
 The default workload is C2 (327,680-face star body, 32^3 roots, 4 passes,
 D3Q27), the largest single-body configuration.
@@ -14,6 +14,9 @@ D3Q27), the largest single-body configuration.
 adjoint) against the same bodies through the single-body calls.  --config P0 /
 P1 runs the paper's bin-density study on its own refinement form (own-bin
 Euclidean flags with mark propagation) for B = 1, 2, 8, 16.
+
+Beside the GPU line: the FP64 oracle on one host core (`cpu_baseline`) and the same sample with its q phase
+split over 16 oracle processes (`cpu_baseline_all_cores`; `--cpu-workers`).
 
 `value` is cell-face tests per second: the number of (cell, face) pairs the
 bins put in front of the cells (tested cells of every pass against the faces
@@ -186,7 +189,63 @@ def cpu_baseline(wl, w_slots, T_total):
                       f"(FP32 flags, {t1 - t0:.1f} s), then FP64 q and the FP64 adjoint for {what} "
                       f"({t2 - t1:.1f} s); rate = cell-face tests performed / time",
             "seconds": dt, "tests": int(T_orc), "refine_seconds": t1 - t0, "q_seconds": t2 - t1,
+            "refine_tests": int(sum(fo.tests)), "q_tests": int(lk.tests),
             "q_blocks": n_fin if sub is None else len(sub), "finest_blocks": n_fin}
+
+
+CPU_WORKERS = 16   # host cores that go with one GPU on the GPU machine
+
+
+def _oracle_q_chunk(job):
+    """One worker of the all-cores baseline: the oracle's bins and refinement of the workload, then FP64 q and the
+    FP64 adjoint for one chunk of the sampled finest-level blocks; returns (q tests, q + adjoint seconds)."""
+    name, sub = job
+    import geomgen
+    import oracle
+    oracle.build(force=False)
+    wl = geomgen.workload(name)
+    r = oracle.run_plain(wl, with_links=False)
+    t0 = time.perf_counter()
+    lk = oracle.link_fractions(wl.dim, r["coords"], r["bins"], r["forest"], wl.lattice, sub)
+    w = np.zeros((lk.n, wl.lattice))
+    w_slots = geomgen.weights(max(1, lk.n * wl.lattice), 2)
+    w.reshape(-1)[:] = w_slots[: lk.n * wl.lattice]
+    w[lk.face < 0] = 0.0
+    oracle.link_grad(r["forest"], lk, r["coords"], wl.faces, w, len(wl.vertices))
+    return int(lk.tests), time.perf_counter() - t0
+
+
+def cpu_all_cores(wl, serial, workers=CPU_WORKERS):
+    """The serial baseline's sample with its q + adjoint phase split over `workers` processes, each running the
+    oracle as it stands on one core (bins and refinement are one serial call in the oracle: their measured serial
+    time is kept).  Rate = (refinement tests + q tests) / (serial refinement time + the slowest worker's q time)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    n_fin = serial["finest_blocks"]
+    if n_fin > Q_SAMPLE_BLOCKS:
+        sub = np.sort(np.random.default_rng(Q_SAMPLE_SEED).choice(n_fin, Q_SAMPLE_BLOCKS, replace=False))
+    else:
+        sub = np.arange(n_fin)
+    chunks = [c for c in np.array_split(sub, min(workers, len(sub))) if len(c)]
+    # fresh interpreters (spawn): the parent holds the GPU; a worker that dies ends the pool with an error
+    # instead of being restarted, and the whole leg is bounded in time
+    try:
+        with cf.ProcessPoolExecutor(max_workers=len(chunks), mp_context=mp.get_context("spawn")) as ex:
+            res = list(ex.map(_oracle_q_chunk, [(wl.name, c) for c in chunks], timeout=600))
+    except Exception as e:   # noqa: BLE001 -- the baseline is reported as missing, with the reason
+        print(f"bench: all-cores CPU baseline failed: {e!r}", file=sys.stderr, flush=True)
+        return None
+    q_tests = sum(t for t, _ in res)
+    q_wall = max(dt for _, dt in res)
+    T = serial["refine_tests"] + q_tests
+    dt = serial["refine_seconds"] + q_wall
+    model, _ = host_info()
+    return {"value": T / dt, "unit": "cell-face tests/s", "cores": len(chunks), "kind": "oracle",
+            "sample": f"{wl.name} on {len(chunks)} host cores ({model}): the serial sample's bins and refinement "
+                      f"({serial['refine_seconds']:.1f} s, one core: the oracle refines in one call), then FP64 q "
+                      f"and the FP64 adjoint of its {len(sub)} blocks split over {len(chunks)} processes "
+                      f"(slowest {q_wall:.2f} s); rate = cell-face tests performed / time",
+            "q_rate": q_tests / q_wall, "q_rate_one_core": serial["q_tests"] / serial["q_seconds"]}
 
 
 def main():
@@ -196,6 +255,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="C2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=CPU_WORKERS,
+                    help="host processes for the all-cores CPU baseline (1: the one-core baseline only)")
     ap.add_argument("--no-graph", action="store_true", help="skip the one-body graph timing")
     ap.add_argument("--no-grad-leg", action="store_true",
                     help="skip the gradient leg on the jittered 20,480-face sphere (profiling runs of one workload)")
@@ -372,6 +433,9 @@ def main():
         print("bench: timing the CPU oracle on the same workload", file=sys.stderr, flush=True)
         cb = cpu_baseline(wl, w_host.astype(np.float64), T)
         out["cpu_baseline"] = cb
+        if args.cpu_workers > 1:
+            print(f"bench: the same sample on {args.cpu_workers} host cores", file=sys.stderr, flush=True)
+            out["cpu_baseline_all_cores"] = cpu_all_cores(wl, cb, args.cpu_workers)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
