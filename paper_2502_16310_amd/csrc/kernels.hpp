@@ -1868,21 +1868,44 @@ __device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const 
     dev::wave_sync();
 
     // rows k0 .. k0 + nnodes - 1 of q and face ids: element e of the span is
-    // node e / Q, direction e % Q
+    // node e / Q, direction e % Q.  Each lane writes four consecutive elements
+    // with 16-byte stores (the span starts on a 16-byte boundary: 64 Q words
+    // per wave), the last few elements one at a time.
     float *qd = A.q + k0 * Q;
     int32_t *fd = A.face + k0 * Q;
-    int l = lane / Q, i = lane % Q;   // node and direction of element e, advanced by 64 elements a step
-    for (int e = lane; e < nnodes * Q; e += 64) {
-        const unsigned long long key = i == 0 ? ~0ull : s_best[l][i - 1];
-        const bool hit = key != ~0ull;
-        qd[e] = hit ? __uint_as_float((uint32_t)(key >> 32)) : -1.0f;
-        fd[e] = hit ? (int32_t)(uint32_t)key : -1;
-        i += 64 % Q;
-        l += 64 / Q;
+    const int total = nnodes * Q, total4 = total & ~3;
+    int l = (4 * lane) / Q, i = (4 * lane) % Q;   // node and direction of element 4 lane, advanced 256 a step
+    for (int e = 4 * lane; e < total4; e += 256) {
+        float qv[4];
+        int32_t fv[4];
+        int ll = l, ii = i;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const unsigned long long key = ii == 0 ? ~0ull : s_best[ll][ii - 1];
+            const bool hit = key != ~0ull;
+            qv[k] = hit ? __uint_as_float((uint32_t)(key >> 32)) : -1.0f;
+            fv[k] = hit ? (int32_t)(uint32_t)key : -1;
+            if (++ii == Q) {
+                ii = 0;
+                ++ll;
+            }
+        }
+        *reinterpret_cast<float4 *>(qd + e) = make_float4(qv[0], qv[1], qv[2], qv[3]);
+        *reinterpret_cast<int4 *>(fd + e) = make_int4(fv[0], fv[1], fv[2], fv[3]);
+        i += 256 % Q;
+        l += 256 / Q;
         if (i >= Q) {
             i -= Q;
             ++l;
         }
+    }
+    if (lane < total - total4) {
+        const int e = total4 + lane;
+        const int le = e / Q, ie = e % Q;
+        const unsigned long long key = ie == 0 ? ~0ull : s_best[le][ie - 1];
+        const bool hit = key != ~0ull;
+        qd[e] = hit ? __uint_as_float((uint32_t)(key >> 32)) : -1.0f;
+        fd[e] = hit ? (int32_t)(uint32_t)key : -1;
     }
 }
 
