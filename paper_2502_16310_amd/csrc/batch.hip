@@ -756,7 +756,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     const int b = body_of_wg(wg_pre, nb, it);
     const BodyDev &X = bodies[b];
     const uint32_t local = it - wg_pre[b];
-    if (X.Q != Q || !X.lists || (int64_t)local * 64 >= (int64_t)nodes[b]) return;
+    if (X.Q != Q || !X.lists || (int64_t)local * kRowNodes >= (int64_t)nodes[b]) return;
     const LinkArgs<D, Q> A = body_link_args<D, Q>(X, cnt[b * kLv + X.L]);
     links_rows_nodes<D, Q>(A, X.lblk, X.nblk, X.key, nodes[b], local);
 }
@@ -1291,9 +1291,9 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
             wg_pre[(size_t)(kLv + 5 + k) * (bt->nb + 1) + b] = bt->nodes_grid[q];
             wg_pre[(size_t)(kLv + 8 + k) * (bt->nb + 1) + b] = bt->rows_grid[q];
             if (X.Q == q && X.lists) {
-                // node pass: about eight chunks of 64 entries per wave; rows: 64 nodes per wave
+                // node pass: about eight chunks of 64 entries per wave; rows: kRowNodes nodes per wave
                 bt->nodes_grid[q] += (unsigned)std::max<int64_t>(1, ((int64_t)X.list_cap + 511) / 512);
-                bt->rows_grid[q] += (unsigned)((X.cap_nodes + 63) / 64);
+                bt->rows_grid[q] += (unsigned)((X.cap_nodes + kRowNodes - 1) / kRowNodes);
             }
         }
         wg_pre[(size_t)(kLv + 4) * (bt->nb + 1) + b] = bt->lfaces_grid;

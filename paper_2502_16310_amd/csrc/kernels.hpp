@@ -1684,13 +1684,17 @@ __device__ __forceinline__ void links_nodes_entries(const LinkArgs<D, Q> &A, con
     }
 }
 
-// Row pass of list mode: one wave per 64 consecutive nodes (node k: block
-// nblk[k], node key written beforehand), one lane per node.  The wave stages
+// Row pass of list mode: one wave per kRowNodes consecutive nodes (node k:
+// block nblk[k], node key written beforehand), one lane per node.  32 nodes
+// per wave keep the best-key table at 6.7 KB of LDS, so that 14 waves fit a CU
+// (64 nodes: 9 waves, 10 % slower; 16 and 48 were slower as well).  The wave stages
 // the candidate entries of its blocks -- one contiguous range of the lists,
 // blocks being in node order -- and every lane tests the staged faces of its
 // own block near its cell; the best hit per direction is kept as in
 // links_wave, in a node-major table from which the wave writes its rows of q
 // and face ids as flat coalesced runs.
+constexpr int kRowNodes = 32;   // nodes per wave of the row pass
+
 template <int D, int Q>
 __device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const uint32_t *lblk, const uint32_t *nblk,
                                                  const uint64_t *node_key, uint32_t nn, int64_t chunk) {
@@ -1704,8 +1708,8 @@ __device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const 
     const int lane = dev::lane_id();
     if (lane < NP)
         for (int a = 0; a < 3; ++a) s_dir[lane][a] = (float)dir_c<D>(1 + 2 * lane, a) * A.dx[a];
-    const int64_t k0 = chunk * 64;
-    const int nnodes = (int)min<int64_t>(64, (int64_t)nn - k0);
+    const int64_t k0 = chunk * kRowNodes;
+    const int nnodes = (int)min<int64_t>(kRowNodes, (int64_t)nn - k0);
     const bool valid = lane < nnodes;
     const uint32_t myb = valid ? nblk[k0 + lane] : 0xFFFFFFFFu;
     const uint64_t nkey = valid ? node_key[k0 + lane] : 0ull;
@@ -1723,15 +1727,17 @@ __device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const 
         for (int a = 0; a < D; ++a) lbits |= 1u << (4 * a + pos3[a]);
     }
     // node-major best keys: a row of Q - 1 keys per node, read back in row order
-    __shared__ unsigned long long s_best[64][Q - 1];
-    __shared__ float s_o[64][3];
+    __shared__ unsigned long long s_best[kRowNodes][Q - 1];
+    __shared__ float s_o[kRowNodes][3];
     constexpr int TCAP = 128;
     __shared__ uint32_t s_qa[TCAP];
     __shared__ uint32_t s_qb[TCAP];
+    if (lane < kRowNodes) {
 #pragma unroll
-    for (int i = 0; i < Q - 1; ++i) s_best[lane][i] = ~0ull;
+        for (int i = 0; i < Q - 1; ++i) s_best[lane][i] = ~0ull;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) s_o[lane][a] = o[a];
+        for (int a = 0; a < 3; ++a) s_o[lane][a] = o[a];
+    }
     int na = 0, nb = 0;
 
     auto consider = [&](int i, int l, double t64, int32_t f) {
@@ -1869,8 +1875,8 @@ __device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const 
 
     // rows k0 .. k0 + nnodes - 1 of q and face ids: element e of the span is
     // node e / Q, direction e % Q.  Each lane writes four consecutive elements
-    // with 16-byte stores (the span starts on a 16-byte boundary: 64 Q words
-    // per wave), the last few elements one at a time.
+    // with 16-byte stores (the span starts on a 16-byte boundary: kRowNodes Q
+    // words per wave), the last few elements one at a time.
     float *qd = A.q + k0 * Q;
     int32_t *fd = A.face + k0 * Q;
     const int total = nnodes * Q, total4 = total & ~3;

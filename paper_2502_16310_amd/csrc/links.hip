@@ -333,7 +333,7 @@ agal_status links_forward_lists(agal_geom g, agal_bins bn, agal_forest fo, agal_
         A.face = lk->face;
         ProfScope prof(ctx, "q_links", s);
         hipLaunchKernelGGL((k_node_map<D>), dim3(bgrid), dim3(256), 0, s, nmask, noff, LL.keys, n, nblk, lk->key);
-        hipLaunchKernelGGL((k_links_rows<D, Q>), dim3((unsigned)(((int64_t)nn + 63) / 64)), dim3(64), 0, s, A, lblk,
+        hipLaunchKernelGGL((k_links_rows<D, Q>), dim3((unsigned)(((int64_t)nn + kRowNodes - 1) / kRowNodes)), dim3(64), 0, s, A, lblk,
                            nblk, nn);
     }
     AGAL_TRY_HIP(hipGetLastError());
