@@ -1685,15 +1685,17 @@ __device__ __forceinline__ void links_nodes_entries(const LinkArgs<D, Q> &A, con
 }
 
 // Row pass of list mode: one wave per kRowNodes consecutive nodes (node k:
-// block nblk[k], node key written beforehand), one lane per node.  32 nodes
-// per wave keep the best-key table at 6.7 KB of LDS, so that 14 waves fit a CU
-// (64 nodes: 9 waves, 10 % slower; 16 and 48 were slower as well).  The wave stages
+// block nblk[k], node key written beforehand), one lane per node.  28 nodes
+// per wave keep the best-key table at 5.8 KB of LDS, so that 16 waves fit a
+// CU (64 nodes: 9 waves and 14 % slower; 16, 24, 32 and 48 measured too).
+// kRowNodes * Q words stay a multiple of four for the 16-byte row stores.  The wave stages
 // the candidate entries of its blocks -- one contiguous range of the lists,
 // blocks being in node order -- and every lane tests the staged faces of its
 // own block near its cell; the best hit per direction is kept as in
 // links_wave, in a node-major table from which the wave writes its rows of q
 // and face ids as flat coalesced runs.
-constexpr int kRowNodes = 32;   // nodes per wave of the row pass
+constexpr int kRowNodes = 28;   // nodes per wave of the row pass
+static_assert(kRowNodes % 4 == 0 && kRowNodes <= 64, "16-byte row stores, one lane per node");
 
 template <int D, int Q>
 __device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const uint32_t *lblk, const uint32_t *nblk,
