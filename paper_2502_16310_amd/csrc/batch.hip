@@ -297,23 +297,54 @@ __global__ __launch_bounds__(1024) void k_b_canon_big(const BodyDev *bodies, int
 // ---------------------------------------------------------------------------
 // segmented exclusive scan (decoupled look-back inside each segment)
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t seg_len(const Seg &S) { return S.n_dev ? (int64_t)*S.n_dev : S.n_const; }
+
+// Tiles per segment of one scan and their exclusive prefix, pre[0..nseg]
+// (one workgroup; each thread takes consecutive segments), so that the scan's
+// workgroups only look their tile up instead of each forming the prefix.
+__global__ __launch_bounds__(kScanThreads) void k_b_seg_prefix(const Seg *segs, int nseg, uint32_t *pre) {
+    constexpr int PER = (kMaxSeg + kScanThreads - 1) / kScanThreads;
+    __shared__ uint32_t s_wsum[kScanThreads / dev::kWave];
+    const int i0 = threadIdx.x * PER;
+    uint32_t v[PER], sum = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = i0 + k;
+        // every segment has at least one tile (it writes out[n] even when n = 0)
+        v[k] = i < nseg ? (uint32_t)((seg_len(segs[i]) + kScanTile) / kScanTile) : 0u;
+        sum += v[k];
+    }
+    const int w = threadIdx.x / dev::kWave, lane = threadIdx.x % dev::kWave;
+    const uint32_t incl = dev::wave_inclusive_sum(sum);
+    if (lane == dev::kWave - 1) s_wsum[w] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum, tot = 0;
+    for (int j = 0; j < kScanThreads / dev::kWave; ++j) {
+        if (j < w) run += s_wsum[j];
+        tot += s_wsum[j];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        if (i0 + k < nseg) pre[i0 + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) pre[nseg] = tot;
+}
+
 template <bool FLAGS>
-__global__ __launch_bounds__(kScanThreads) void k_b_scan(const Seg *segs, int nseg, uint64_t *status,
-                                                         uint32_t *ticket) {
-    __shared__ uint32_t s_pre[kMaxSeg + 1];
+__global__ __launch_bounds__(kScanThreads) void k_b_scan(const Seg *segs, int nseg, const uint32_t *pre,
+                                                         uint64_t *status, uint32_t *ticket) {
     __shared__ uint32_t s_tile, s_prefix;
     __shared__ uint32_t s_wsum[kScanThreads / dev::kWave];
-    auto seg_n = [&](int s) -> int64_t { return segs[s].n_dev ? (int64_t)*segs[s].n_dev : segs[s].n_const; };
-    const uint32_t total = lds_prefix(nseg, [&](int s) { return (uint32_t)((seg_n(s) + kScanTile) / kScanTile); }, s_pre);
-    // every segment has at least one tile (it writes out[n] even when n = 0)
+    const uint32_t total = pre[nseg];
     if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
     const uint32_t t = s_tile;
     if (t >= total) return;
-    const int s = find_seg(s_pre, nseg, t);
+    const int s = find_seg(pre, nseg, t);
     const Seg &S = segs[s];
-    const int64_t n = seg_n(s);
-    const uint32_t lt = t - s_pre[s];
+    const int64_t n = seg_len(S);
+    const uint32_t lt = t - pre[s];
     const int64_t base = (int64_t)lt * kScanTile + (int64_t)threadIdx.x * 8;
     uint32_t v[8];
     uint32_t sum = 0;
@@ -835,6 +866,7 @@ struct agal_batch_t {
     int n_fill_init = 0;
     std::vector<int> pass_seg_off, pass_seg_n;
     uint32_t *d_tickets = nullptr;   // one look-back ticket per scan of a run
+    uint32_t *d_segpre = nullptr;    // per scan: tile prefix over its segments (kMaxSeg + 1 words)
     int links_seg_off = 0, bins_seg_off = 0, lists_seg_off = 0;
     int fill_pass_base = 0;
     int wg_per_cu = 4, n_cu = 256;
@@ -980,12 +1012,14 @@ static agal_status capture(agal_batch bt) {
         const unsigned grid = (unsigned)bt->status_words;
         uint64_t *st = bt->d_status + (size_t)idx * bt->status_words;
         uint32_t *tk = bt->d_tickets + idx;
+        uint32_t *pre = bt->d_segpre + (size_t)idx * (kMaxSeg + 1);
+        hipLaunchKernelGGL(k_b_seg_prefix, dim3(1), dim3(kScanThreads), 0, s, bt->d_segs + seg_off, nseg, pre);
         if (flags)
-            hipLaunchKernelGGL(k_b_scan<true>, dim3(grid), dim3(kScanThreads), 0, s, bt->d_segs + seg_off, nseg, st,
-                               tk);
+            hipLaunchKernelGGL(k_b_scan<true>, dim3(grid), dim3(kScanThreads), 0, s, bt->d_segs + seg_off, nseg, pre,
+                               st, tk);
         else
-            hipLaunchKernelGGL(k_b_scan<false>, dim3(grid), dim3(kScanThreads), 0, s, bt->d_segs + seg_off, nseg, st,
-                               tk);
+            hipLaunchKernelGGL(k_b_scan<false>, dim3(grid), dim3(kScanThreads), 0, s, bt->d_segs + seg_off, nseg, pre,
+                               st, tk);
     };
     scan(0, bt->bins_seg_off, 1, false);
     hipLaunchKernelGGL(k_b_bin_scatter<D>, dim3(G), dim3(256), 0, s, B, nb, bt->d_bin_off, bt->d_bin_cursor, bt->d_ids,
@@ -1440,6 +1474,7 @@ static agal_status plan(agal_batch bt, const agal_tune_opts &opt, hipStream_t us
     const int n_scans = bt->Lmax + 3;   // bins, one per pass, links, candidate lists
     AGAL_TRY(own(bt, &bt->d_status, (size_t)bt->status_words * n_scans));
     AGAL_TRY(own(bt, &bt->d_tickets, (size_t)n_scans));
+    AGAL_TRY(own(bt, &bt->d_segpre, (size_t)n_scans * (kMaxSeg + 1)));
     AGAL_TRY(own(bt, &bt->d_segs, bt->seg_store.size()));
 
     // ---- fill table: everything a run needs cleared, in the run's first launch --
