@@ -1559,6 +1559,11 @@ __device__ __forceinline__ int nth_bit4(uint32_t m, int k) {
 // its margins: a certain hit sets the cell's bit in its block's mask, a
 // possible one is decided in FP64 exactly as the row pass decides it.  So a
 // block's mask is the set of its cells for which the row pass finds a hit.
+// The 64 entries of a window belong to a few blocks (the lists are in block
+// order): each block's mask is read once into LDS, hits are ORed there, and
+// the new bits go out with one device atomic per block at the window's end
+// (device-scope atomics are performed past the per-XCD L2, so one per hit
+// costs memory-side traffic).
 // mask: one 64-bit word per block, zeroed; lblk: the block of each entry.
 template <int D, int Q>
 __device__ __forceinline__ void links_nodes_entries(const LinkArgs<D, Q> &A, const uint32_t *lblk,
@@ -1569,8 +1574,9 @@ __device__ __forceinline__ void links_nodes_entries(const LinkArgs<D, Q> &A, con
     __shared__ float s_dir[NP][3];
     __shared__ uint32_t s_pre[64];     // exclusive prefix of the entries' pair counts
     __shared__ uint32_t s_bits[64];    // code bits of each entry
-    __shared__ uint32_t s_blk[64];     // block of each entry
     __shared__ int s_bc[64][3];        // its block coordinates
+    __shared__ uint32_t s_head[64];    // first entry of the window with the same block
+    __shared__ unsigned long long s_m[64];   // at a block's first entry: its mask as known to the wave
     constexpr int QCAP = 128;
     __shared__ uint32_t s_q[QCAP];     // queued pairs: entry << 8 | cell
     const int lane = dev::lane_id();
@@ -1601,10 +1607,18 @@ __device__ __forceinline__ void links_nodes_entries(const LinkArgs<D, Q> &A, con
         const uint32_t npairs = (uint32_t)__builtin_amdgcn_readlane((int)incl, dev::kWave - 1);
         s_pre[lane] = incl - cnt;
         s_bits[lane] = bits;
-        s_blk[lane] = b;
         s_bc[lane][0] = bc[0];
         s_bc[lane][1] = bc[1];
         s_bc[lane][2] = bc[2];
+        const bool live = e < total && (int64_t)b < A.n;
+        const uint32_t prev_b = (uint32_t)__shfl_up((int)b, 1, dev::kWave);
+        const bool head = live && (lane == 0 || prev_b != b);
+        const uint64_t heads = __ballot(head);
+        const uint64_t upto = lane == dev::kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
+        const uint64_t hb = heads & upto;
+        s_head[lane] = hb ? (uint32_t)(63 - __clzll((long long)hb)) : (uint32_t)lane;
+        const unsigned long long m0 = head ? mask[b] : 0ull;
+        s_m[lane] = m0;
         dev::wave_sync();
         // one work loop: enumerate 64 pairs, queueing those still open, and
         // decide 64 queued pairs whenever the queue holds that many (or the
@@ -1638,7 +1652,7 @@ __device__ __forceinline__ void links_nodes_entries(const LinkArgs<D, Q> &A, con
                             }
                         }
                     }
-                    if (hit) atomicOr(&mask[s_blk[j]], 1ull << cell);
+                    if (hit) atomicOr(&s_m[s_head[j]], 1ull << cell);
                 }
             } else if (c0 < npairs) {
                 const uint32_t v = c0 + (uint32_t)lane;
@@ -1664,7 +1678,7 @@ __device__ __forceinline__ void links_nodes_entries(const LinkArgs<D, Q> &A, con
                         iy = nth_bit4(my, (int)u);
                     }
                     const int cell = ix | (iy << 2) | (iz << 4);
-                    if (!((mask[s_blk[k]] >> cell) & 1ull)) {
+                    if (!((s_m[s_head[k]] >> cell) & 1ull)) {
                         float o[3] = {0.0f, 0.0f, 0.0f};
                         o[0] = dev::cell_centre(A.lo[0], 4 * s_bc[k][0] + ix, A.dx[0]);
                         o[1] = dev::cell_centre(A.lo[1], 4 * s_bc[k][1] + iy, A.dx[1]);
@@ -1679,6 +1693,11 @@ __device__ __forceinline__ void links_nodes_entries(const LinkArgs<D, Q> &A, con
             } else {
                 break;
             }
+        }
+        dev::wave_sync();
+        if (head) {
+            const unsigned long long m1 = s_m[lane];
+            if (m1 != m0) atomicOr(&mask[b], m1 & ~m0);
         }
         dev::wave_sync();
     }
