@@ -1028,16 +1028,20 @@ struct LinkArgs {
 // normal n = (b - a) x (c - a), |E1|_1, |E2|_1 and S = sum |n_a dx_a|), the
 // face id and the face's near code (one bit per (axis, cell position) of the
 // block it was staged for).
-template <int D, int CAP = kLinkCap>
+// With kNorms (3D) the face's L1 norms |E1|_1, |E2|_1 and sum_a |n_a dx_a|
+// are staged too (f[12..14]); without them the filter forms them again from
+// the staged corners and normal, with the same expressions, so the results are
+// the same and the staging area is a fifth smaller.
+template <int D, int CAP = kLinkCap, bool kNorms = true>
 struct LinkStaged {
-    static constexpr int NF = D == 3 ? 15 : 4;
+    static constexpr int NF = D == 3 ? (kNorms ? 15 : 12) : 4;
     float f[NF][CAP];
     int32_t id[CAP];
     uint32_t code[CAP];
 };
 
-template <int D, int CAP>
-__device__ __forceinline__ void link_stage(LinkStaged<D, CAP> &S, int pos, int32_t f, const float *r, const float dx[3],
+template <int D, int CAP, bool kN>
+__device__ __forceinline__ void link_stage(LinkStaged<D, CAP, kN> &S, int pos, int32_t f, const float *r, const float dx[3],
                                            uint32_t code) {
     S.id[pos] = f;
     if constexpr (D == 3) {
@@ -1052,9 +1056,11 @@ __device__ __forceinline__ void link_stage(LinkStaged<D, CAP> &S, int pos, int32
         S.f[9][pos] = n0;
         S.f[10][pos] = n1;
         S.f[11][pos] = n2;
-        S.f[12][pos] = fabsf(e10) + fabsf(e11) + fabsf(e12);
-        S.f[13][pos] = fabsf(e20) + fabsf(e21) + fabsf(e22);
-        S.f[14][pos] = fabsf(n0 * dx[0]) + fabsf(n1 * dx[1]) + fabsf(n2 * dx[2]);
+        if constexpr (kN) {
+            S.f[12][pos] = fabsf(e10) + fabsf(e11) + fabsf(e12);
+            S.f[13][pos] = fabsf(e20) + fabsf(e21) + fabsf(e22);
+            S.f[14][pos] = fabsf(n0 * dx[0]) + fabsf(n1 * dx[1]) + fabsf(n2 * dx[2]);
+        }
     } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k) S.f[k][pos] = r[k];
@@ -1077,8 +1083,8 @@ __device__ __forceinline__ void link_stage(LinkStaged<D, CAP> &S, int pos, int32
 // certainly meets it (the same tests narrowed by the margins: the exact u, v,
 // 1 - u - v and 1 - |t| are then positive by at least half a margin, so the
 // FP64 decision finds a hit for one of the pair's two directions).
-template <int D, int NP, bool kSure, int CAP>
-__device__ __forceinline__ uint32_t link_filter(const LinkStaged<D, CAP> &S, int j, const float o[3], const float dx[3],
+template <int D, int NP, bool kSure, int CAP, bool kN>
+__device__ __forceinline__ uint32_t link_filter(const LinkStaged<D, CAP, kN> &S, int j, const float o[3], const float dx[3],
                                                 bool *sure) {
     // The pair-independent sums of margins are formed once: comparing
     // atn - (MD + MT) <= ad instead of atn <= (ad + MD) + MT (and so on) moves
@@ -1091,7 +1097,14 @@ __device__ __forceinline__ uint32_t link_filter(const LinkStaged<D, CAP> &S, int
         const float e10 = S.f[3][j] - S.f[0][j], e11 = S.f[4][j] - S.f[1][j], e12 = S.f[5][j] - S.f[2][j];
         const float e20 = S.f[6][j] - S.f[0][j], e21 = S.f[7][j] - S.f[1][j], e22 = S.f[8][j] - S.f[2][j];
         const float n0 = S.f[9][j], n1 = S.f[10][j], n2 = S.f[11][j];
-        const float n1n = S.f[12][j], n2n = S.f[13][j];
+        float n1n, n2n;
+        if constexpr (kN) {
+            n1n = S.f[12][j];
+            n2n = S.f[13][j];
+        } else {
+            n1n = fabsf(e10) + fabsf(e11) + fabsf(e12);
+            n2n = fabsf(e20) + fabsf(e21) + fabsf(e22);
+        }
         const float nT = fabsf(T0) + fabsf(T1) + fabsf(T2);
         const float mx_ = fmaxf(fmaxf(dx[0], dx[1]), dx[2]) * 9.5367431640625e-07f;  // dx * 2^-20
         const float MU = mx_ * nT * n2n;
@@ -1174,12 +1187,21 @@ __device__ __forceinline__ uint32_t link_filter(const LinkStaged<D, CAP> &S, int
 // Whether any direction pair can pass the filter for staged face j and origin
 // o: the filter's |t| test with the largest |D . n| of any direction,
 // S = sum |n_a dx_a| (3D; always in 2D).
-template <int D, int CAP>
-__device__ __forceinline__ bool link_reach(const LinkStaged<D, CAP> &S, int j, const float o[3], const float dx[3]) {
+template <int D, int CAP, bool kN>
+__device__ __forceinline__ bool link_reach(const LinkStaged<D, CAP, kN> &S, int j, const float o[3], const float dx[3]) {
     if constexpr (D == 3) {
         const float T0 = o[0] - S.f[0][j], T1 = o[1] - S.f[1][j], T2 = o[2] - S.f[2][j];
         const float n0 = S.f[9][j], n1 = S.f[10][j], n2 = S.f[11][j];
-        const float n1n = S.f[12][j], n2n = S.f[13][j], Sn = S.f[14][j];
+        float n1n, n2n, Sn;
+        if constexpr (kN) {
+            n1n = S.f[12][j];
+            n2n = S.f[13][j];
+            Sn = S.f[14][j];
+        } else {
+            n1n = (fabsf(S.f[3][j] - S.f[0][j]) + fabsf(S.f[4][j] - S.f[1][j])) + fabsf(S.f[5][j] - S.f[2][j]);
+            n2n = (fabsf(S.f[6][j] - S.f[0][j]) + fabsf(S.f[7][j] - S.f[1][j])) + fabsf(S.f[8][j] - S.f[2][j]);
+            Sn = (fabsf(n0 * dx[0]) + fabsf(n1 * dx[1])) + fabsf(n2 * dx[2]);
+        }
         const float nT = fabsf(T0) + fabsf(T1) + fabsf(T2);
         const float mx_ = fmaxf(fmaxf(dx[0], dx[1]), dx[2]) * 9.5367431640625e-07f;
         const float MD = mx_ * n1n * n2n;
@@ -1196,8 +1218,8 @@ __device__ __forceinline__ bool link_reach(const LinkStaged<D, CAP> &S, int j, c
 // or NaN when the line misses the face or det = 0.  The opposite direction
 // hits at -t (negating D negates P, det and t exactly), so the pair has a
 // link in direction Dv when t is in [0, 1] and in -Dv when -t is.
-template <int D, int CAP>
-__device__ __forceinline__ double link_decide(const LinkStaged<D, CAP> &S, int j, const double o[3], const float dir[3]) {
+template <int D, int CAP, bool kN>
+__device__ __forceinline__ double link_decide(const LinkStaged<D, CAP, kN> &S, int j, const double o[3], const float dir[3]) {
     const double nan = __builtin_nan("");
     if constexpr (D == 3) {
         const double a0 = S.f[0][j], a1 = S.f[1][j], a2 = S.f[2][j];
@@ -1705,8 +1727,10 @@ __device__ __forceinline__ void links_nodes_entries(const LinkArgs<D, Q> &A, con
 
 // Row pass of list mode: one wave per kRowNodes consecutive nodes (node k:
 // block nblk[k], node key written beforehand), one lane per node.  28 nodes
-// per wave keep the best-key table at 5.8 KB of LDS, so that 16 waves fit a
-// CU (64 nodes: 9 waves and 14 % slower; 16, 24, 32 and 48 measured too).
+// per wave keep the best-key table at 5.8 KB and the wave's LDS at 8.75 KB, so
+// that 18 waves fit a CU (64 nodes: 9 waves and 14 % slower; 16, 20, 24, 32
+// and 48 measured too: fewer nodes per wave stage the same entries more often,
+// which costs more than the extra waves gain).
 // kRowNodes * Q words stay a multiple of four for the 16-byte row stores.  The wave stages
 // the candidate entries of its blocks -- one contiguous range of the lists,
 // blocks being in node order -- and every lane tests the staged faces of its
@@ -1722,10 +1746,10 @@ __device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const 
     constexpr int CELLS = D == 3 ? 64 : 16;
     constexpr int NP = (Q - 1) / 2;
     constexpr int RF = dev::kRecFloats<D>;
-    __shared__ LinkStaged<D> S;
+    __shared__ LinkStaged<D, kLinkCap, false> S;
     __shared__ uint32_t s_sblk[kLinkCap];   // block of each staged entry
     __shared__ float s_dir[NP][3];
-    static_assert(kLinkCap <= 32, "near masks are 32-bit");
+    static_assert(kLinkCap <= 32 && kRowNodes <= 32 && NP <= 32, "near masks are 32-bit; queue items 16-bit");
     const int lane = dev::lane_id();
     if (lane < NP)
         for (int a = 0; a < 3; ++a) s_dir[lane][a] = (float)dir_c<D>(1 + 2 * lane, a) * A.dx[a];
@@ -1751,8 +1775,8 @@ __device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const 
     __shared__ unsigned long long s_best[kRowNodes][Q - 1];
     __shared__ float s_o[kRowNodes][3];
     constexpr int TCAP = 128;
-    __shared__ uint32_t s_qa[TCAP];
-    __shared__ uint32_t s_qb[TCAP];
+    __shared__ uint16_t s_qa[TCAP];   // (node, staged entry) pairs to filter: l << 5 | j
+    __shared__ uint16_t s_qb[TCAP];   // direction pairs to decide: l << 10 | j << 5 | p
     if (lane < kRowNodes) {
 #pragma unroll
         for (int i = 0; i < Q - 1; ++i) s_best[lane][i] = ~0ull;
@@ -1769,13 +1793,13 @@ __device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const 
     };
     auto take_b = [&](int take) {
         dev::wave_sync();
-        const uint32_t item = lane < take ? s_qb[lane] : 0u;
+        const uint32_t item = lane < take ? (uint32_t)s_qb[lane] : 0u;
         dev::wave_sync();
         if (lane < nb - take) s_qb[lane] = s_qb[take + lane];
         nb -= take;
         if (lane < take) {
-            const int l = (int)(item >> 20);
-            const int j = (int)((item >> 13) & 127u);
+            const int l = (int)(item >> 10);
+            const int j = (int)((item >> 5) & 31u);
             const int p = (int)(item & 31u);
             const double ol[3] = {s_o[l][0], s_o[l][1], s_o[l][2]};
             const double t = link_decide<D>(S, j, ol, s_dir[p]);
@@ -1785,11 +1809,11 @@ __device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const 
     };
     auto take_a = [&](int take) {
         dev::wave_sync();
-        const uint32_t item = lane < take ? s_qa[lane] : 0u;
+        const uint32_t item = lane < take ? (uint32_t)s_qa[lane] : 0u;
         dev::wave_sync();
         if (lane < na - take) s_qa[lane] = s_qa[take + lane];
         na -= take;
-        const int l = (int)(item >> 7), j = (int)(item & 127u);
+        const int l = (int)(item >> 5), j = (int)(item & 31u);
         uint32_t cm = 0;
         if (lane < take) {
             const float ol[3] = {s_o[l][0], s_o[l][1], s_o[l][2]};
@@ -1803,7 +1827,7 @@ __device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const 
                 cm &= cm - 1u;
             }
             const uint64_t m = __ballot(has);
-            if (has) s_qb[nb + dev::lanes_below(m)] = ((uint32_t)l << 20) | ((uint32_t)j << 13) | (uint32_t)p;
+            if (has) s_qb[nb + dev::lanes_below(m)] = (uint16_t)((l << 10) | (j << 5) | p);
             nb += __popcll(m);
             if (nb >= 64) take_b(64);
         }
@@ -1841,7 +1865,7 @@ __device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const 
                 pass = link_reach<D>(S, j, o, A.dx);
             }
             const uint64_t m = __ballot(pass);
-            if (pass) s_qa[na + dev::lanes_below(m)] = ((uint32_t)lane << 7) | (uint32_t)j;
+            if (pass) s_qa[na + dev::lanes_below(m)] = (uint16_t)((lane << 5) | j);
             na += __popcll(m);
             if (na >= 64) take_a(64);
         }
