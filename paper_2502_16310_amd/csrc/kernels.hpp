@@ -1559,16 +1559,23 @@ __device__ __forceinline__ uint32_t link_code_at(const LinkArgs<D, Q> &A, const 
     return c;
 }
 
-// Position of the k-th set bit (k < popcount) of a 4-bit mask.
-__device__ __forceinline__ int nth_bit4(uint32_t m, int k) {
-    int i = 0, seen = 0;
+// The set bits of a 4-bit mask in ascending order, two bits each (entry k
+// of the list is (list >> 2k) & 3).
+__device__ __forceinline__ uint32_t bit_list4(uint32_t m) {
+    uint32_t list = 0, n = 0;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const bool set = (m >> b) & 1u;
-        if (set && seen == k) i = b;
-        seen += set ? 1 : 0;
-    }
-    return i;
+    for (uint32_t b = 0; b < 4; ++b)
+        if ((m >> b) & 1u) {
+            list |= b << (2 * n);
+            ++n;
+        }
+    return list;
+}
+
+// u / n for n in 1 .. 4 and u < 4096 as (u * 2^16 / n) >> 16 (exact there:
+// the multiplier for 3 is 2^16 / 3 rounded up, off by less than 2^-17 of u).
+__device__ __forceinline__ uint32_t div_1to4(uint32_t u, uint32_t n) {
+    return (u * (n == 3u ? 21846u : 65536u >> (n >> 1))) >> 16;
 }
 
 // Node pass of list mode: which finest-level cells have at least one link.
@@ -1595,7 +1602,7 @@ __device__ __forceinline__ void links_nodes_entries(const LinkArgs<D, Q> &A, con
     __shared__ LinkStaged<D, 64> S;
     __shared__ float s_dir[NP][3];
     __shared__ uint32_t s_pre[64];     // exclusive prefix of the entries' pair counts
-    __shared__ uint32_t s_bits[64];    // code bits of each entry
+    __shared__ uint32_t s_enum[64];    // each entry's cells per axis: bit lists x, y, z and counts
     __shared__ int s_bc[64][3];        // its block coordinates
     __shared__ uint32_t s_head[64];    // first entry of the window with the same block
     __shared__ unsigned long long s_m[64];   // at a block's first entry: its mask as known to the wave
@@ -1628,7 +1635,14 @@ __device__ __forceinline__ void links_nodes_entries(const LinkArgs<D, Q> &A, con
         const uint32_t incl = dev::wave_inclusive_sum(cnt);
         const uint32_t npairs = (uint32_t)__builtin_amdgcn_readlane((int)incl, dev::kWave - 1);
         s_pre[lane] = incl - cnt;
-        s_bits[lane] = bits;
+        {
+            const uint32_t mx = bits & 15u, my = (bits >> 4) & 15u, mz = (bits >> 8) & 15u;
+            const uint32_t nx = (uint32_t)__popc(mx), ny = (uint32_t)__popc(my);
+            // bit lists (8 bits each) and the x and y counts less one (2 bits each)
+            s_enum[lane] = cnt ? (bit_list4(mx) | (bit_list4(my) << 8) | (bit_list4(mz) << 16) | ((nx - 1u) << 24) |
+                                  ((D == 3 ? ny - 1u : 0u) << 26))
+                               : 0u;
+        }
         s_bc[lane][0] = bc[0];
         s_bc[lane][1] = bc[1];
         s_bc[lane][2] = bc[2];
@@ -1686,19 +1700,20 @@ __device__ __forceinline__ void links_nodes_entries(const LinkArgs<D, Q> &A, con
 #pragma unroll
                     for (int step = 32; step >= 1; step >>= 1)
                         if (s_pre[k + step] <= v) k += step;
-                    uint32_t u = v - s_pre[k];
-                    const uint32_t bk = s_bits[k];
-                    const uint32_t mx = bk & 15u, my = (bk >> 4) & 15u, mz = (bk >> 8) & 15u;
-                    const uint32_t nx = (uint32_t)__popc(mx), ny = (uint32_t)__popc(my);
-                    const int ix = nth_bit4(mx, (int)(u % nx));
-                    u /= nx;
-                    int iy, iz = 0;
+                    // pair u of entry k: x fastest, then y, then z over the entry's cells
+                    const uint32_t u = v - s_pre[k];
+                    const uint32_t en = s_enum[k];
+                    const uint32_t nx = ((en >> 24) & 3u) + 1u, ny = ((en >> 26) & 3u) + 1u;
+                    const uint32_t q1 = div_1to4(u, nx);
+                    const uint32_t ux = u - q1 * nx;
+                    uint32_t uy = q1, uz = 0;
                     if constexpr (D == 3) {
-                        iy = nth_bit4(my, (int)(u % ny));
-                        iz = nth_bit4(mz, (int)(u / ny));
-                    } else {
-                        iy = nth_bit4(my, (int)u);
+                        uz = div_1to4(q1, ny);
+                        uy = q1 - uz * ny;
                     }
+                    const int ix = (int)((en >> (2 * ux)) & 3u);
+                    const int iy = (int)((en >> (8 + 2 * uy)) & 3u);
+                    const int iz = D == 3 ? (int)((en >> (16 + 2 * uz)) & 3u) : 0;
                     const int cell = ix | (iy << 2) | (iz << 4);
                     if (!((s_m[s_head[k]] >> cell) & 1ull)) {
                         float o[3] = {0.0f, 0.0f, 0.0f};
