@@ -773,10 +773,12 @@ __global__ void k_b_node_map(const BodyDev *bodies, int nb, const uint32_t *cnt,
     __shared__ uint32_t s_pre[kMaxBodies + 1];
     const uint32_t total = lds_prefix(nb, [&](int b) {
         return bodies[b].lists && nodes[b] ? cnt[b * kLv + bodies[b].L] : 0u; }, s_pre);
-    AGAL_THREAD_ITEMS(it, total) {
+    // one (body, block) item per wave at a time
+    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) / 64u));
+    for (uint32_t it = w0; it < total; it += gridDim.x * (blockDim.x / 64u)) {
         const int b = find_seg(s_pre, nb, it);
         const BodyDev &X = bodies[b];
-        node_map_block<D>(X.nmask, X.blk_off, X.keys[X.L][final_buf(X.L, X.L)], it - s_pre[b], X.nblk, X.key);
+        node_map_wave<D>(X.nmask, X.blk_off, X.keys[X.L][final_buf(X.L, X.L)], it - s_pre[b], X.nblk, X.key);
     }
 }
 

@@ -2531,19 +2531,19 @@ __device__ __forceinline__ void link_faces_wave(const float *aabb, int64_t F, co
 
 // Nodes of block b in cell order: node k -> its block (nblk) and node key,
 // from the block's mask and first row noff[b].
+// Nodes of block b (wave-uniform): lane i writes cell i when it is set, at
+// noff[b] + (set cells below i), so the block's nodes go out as one
+// coalesced run of keys and block indices.
 template <int D>
-__device__ __forceinline__ void node_map_block(const unsigned long long *mask, const uint32_t *noff,
-                                               const uint32_t *keys, int64_t b, uint32_t *nblk, uint64_t *node_key) {
+__device__ __forceinline__ void node_map_wave(const unsigned long long *mask, const uint32_t *noff,
+                                              const uint32_t *keys, int64_t b, uint32_t *nblk, uint64_t *node_key) {
     constexpr int CELLS = D == 3 ? 64 : 16;
-    unsigned long long m = mask[b];
-    int64_t k = noff[b];
-    const uint64_t base = (uint64_t)keys[b] * CELLS;
-    while (m) {
-        const int cell = __builtin_ctzll(m);
-        m &= m - 1ull;
+    const unsigned long long m = mask[b];
+    const int lane = dev::lane_id();
+    if (lane < CELLS && ((m >> lane) & 1ull)) {
+        const int64_t k = (int64_t)noff[b] + dev::lanes_below(m);
         nblk[k] = (uint32_t)b;
-        node_key[k] = base + (uint64_t)cell;
-        ++k;
+        node_key[k] = (uint64_t)keys[b] * CELLS + (uint64_t)lane;
     }
 }
 

@@ -97,8 +97,10 @@ template <int D>
 __global__ __launch_bounds__(256) void k_node_map(const unsigned long long *mask, const uint32_t *noff,
                                                   const uint32_t *keys, int64_t n, uint32_t *nblk,
                                                   uint64_t *node_key) {
-    for (int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x; b < n; b += (int64_t)gridDim.x * 256)
-        node_map_block<D>(mask, noff, keys, b, nblk, node_key);
+    // one block per wave at a time
+    const int64_t w0 = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * 256u + threadIdx.x) / 64u));
+    for (int64_t b = w0; b < n; b += (int64_t)gridDim.x * 4)
+        node_map_wave<D>(mask, noff, keys, b, nblk, node_key);
 }
 
 template <int D, int Q>
@@ -332,7 +334,8 @@ agal_status links_forward_lists(agal_geom g, agal_bins bn, agal_forest fo, agal_
         A.q = lk->q;
         A.face = lk->face;
         ProfScope prof(ctx, "q_links", s);
-        hipLaunchKernelGGL((k_node_map<D>), dim3(bgrid), dim3(256), 0, s, nmask, noff, LL.keys, n, nblk, lk->key);
+        const unsigned mgrid = (unsigned)std::min<int64_t>((n + 3) / 4, 16384);
+        hipLaunchKernelGGL((k_node_map<D>), dim3(mgrid), dim3(256), 0, s, nmask, noff, LL.keys, n, nblk, lk->key);
         hipLaunchKernelGGL((k_links_rows<D, Q>), dim3((unsigned)(((int64_t)nn + kRowNodes - 1) / kRowNodes)), dim3(64), 0, s, A, lblk,
                            nblk, nn);
     }
