@@ -905,7 +905,12 @@ __device__ __forceinline__ void flag_faces_wave(const FaceFlagArgs<D> &A, int64_
 // 2:1 balance: a block of level m marked in this pass needs every neighbour
 // position (faces, edges, corners) inside the domain to exist at level m;
 // where it does not, the covering level-(m-1) leaf is marked.  One thread per
-// (block, neighbour position), so each thread does two binary searches.
+// (block, neighbour position).  Blocks are created as whole sibling groups,
+// the children of a refined parent, so a level-m position exists exactly when
+// its level-(m-1) parent exists and is not a leaf: a neighbour with the
+// block's own parent exists, and any other takes one binary search, for its
+// parent in level m-1 (refined: it exists; a leaf: marked; missing: the 2:1
+// rule was broken below, an error).
 template <int D>
 __device__ __forceinline__ void ripple_item(const uint32_t *keys_m, int64_t n_m, const uint8_t *pm_m, int m,
                                             const uint32_t *keys_p, int64_t n_p, const uint8_t *leaf_p, uint8_t *pm_p,
@@ -923,14 +928,15 @@ __device__ __forceinline__ void ripple_item(const uint32_t *keys_m, int64_t n_m,
         int nc[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
         if (nc[0] < 0 || nc[0] >= ext[0] || nc[1] < 0 || nc[1] >= ext[1]) return;
         if (D == 3 && (nc[2] < 0 || nc[2] >= ext[2])) return;
-        const uint32_t kn = dev::encode_key<D>(nc, m, R0, R1);
-        const int64_t jn = dev::lower_bound_u32(keys_m, n_m, kn);
-        if (jn < n_m && keys_m[jn] == kn) return;
         int pc[3] = {nc[0] >> 1, nc[1] >> 1, D == 3 ? nc[2] >> 1 : 0};
+        if (pc[0] == c[0] >> 1 && pc[1] == c[1] >> 1 && (D == 2 || pc[2] == c[2] >> 1)) return;   // a sibling
         const uint32_t kp = dev::encode_key<D>(pc, m - 1, R0, R1);
         const int64_t jp = dev::lower_bound_u32(keys_p, n_p, kp);
-        if (jp < n_p && keys_p[jp] == kp && leaf_p[jp]) pm_p[jp] = 2;
-        else atomicOr(err, 1u);
+        if (jp < n_p && keys_p[jp] == kp) {
+            if (leaf_p[jp]) pm_p[jp] = 2;
+        } else {
+            atomicOr(err, 1u);
+        }
     }
 }
 
