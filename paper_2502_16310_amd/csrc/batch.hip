@@ -337,6 +337,11 @@ __global__ __launch_bounds__(kScanThreads) void k_b_scan(const Seg *segs, int ns
     __shared__ uint32_t s_tile, s_prefix;
     __shared__ uint32_t s_wsum[kScanThreads / dev::kWave];
     const uint32_t total = pre[nseg];
+    // the grid is sized for the largest scan of the plan: workgroups past this
+    // scan's tiles leave before taking a ticket (tickets are one device atomic
+    // on one word each, and those serialise), and the first `total` take
+    // tickets 0 .. total - 1
+    if (blockIdx.x >= total) return;
     if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
     const uint32_t t = s_tile;
@@ -402,6 +407,7 @@ __global__ __launch_bounds__(64) void k_b_flag(const BodyDev *bodies, int nb, in
         FlagArgs<D> A{};
         A.faces = dev::Faces{B.coords, B.aabb, B.rec, B.F};
         A.bins = B.bins;
+        A.bins.F = B.F;
         A.keys = B.keys[p][0];
         A.n = cnt[b * kLv + p];
         A.level = p;
@@ -625,6 +631,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         LinkArgs<D, Q> A{};
         A.faces = dev::Faces{B.coords, B.aabb, B.rec, B.F};
         A.bins = B.bins;
+        A.bins.F = B.F;
         A.keys = B.keys[L][final_buf(L, L)];
         A.n = cnt[b * kLv + L];
         A.level = L;
@@ -691,6 +698,7 @@ __device__ __forceinline__ LinkArgs<D, Q> body_link_args(const BodyDev &X, uint3
     LinkArgs<D, Q> A{};
     A.faces = dev::Faces{X.coords, X.aabb, X.rec, X.F};
     A.bins = X.bins;
+    A.bins.F = X.F;
     A.keys = X.keys[X.L][final_buf(X.L, X.L)];
     A.n = n;
     A.level = X.L;
@@ -771,14 +779,15 @@ __global__ void k_b_popc(const BodyDev *bodies, int nb, const uint32_t *cnt, Ctl
 template <int D>
 __global__ void k_b_node_map(const BodyDev *bodies, int nb, const uint32_t *cnt, const uint32_t *nodes) {
     __shared__ uint32_t s_pre[kMaxBodies + 1];
+    // items: chunks of 64 blocks of one body, one per wave at a time
     const uint32_t total = lds_prefix(nb, [&](int b) {
-        return bodies[b].lists && nodes[b] ? cnt[b * kLv + bodies[b].L] : 0u; }, s_pre);
-    // one (body, block) item per wave at a time
+        return bodies[b].lists && nodes[b] ? (cnt[b * kLv + bodies[b].L] + 63u) / 64u : 0u; }, s_pre);
     const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) / 64u));
     for (uint32_t it = w0; it < total; it += gridDim.x * (blockDim.x / 64u)) {
         const int b = find_seg(s_pre, nb, it);
         const BodyDev &X = bodies[b];
-        node_map_wave<D>(X.nmask, X.blk_off, X.keys[X.L][final_buf(X.L, X.L)], it - s_pre[b], X.nblk, X.key);
+        node_map_chunk<D>(X.nmask, X.blk_off, X.keys[X.L][final_buf(X.L, X.L)], (int64_t)(it - s_pre[b]) * 64,
+                          cnt[b * kLv + X.L], X.nblk, X.key);
     }
 }
 

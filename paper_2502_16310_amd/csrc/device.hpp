@@ -59,6 +59,7 @@ struct BinGrid {
     float lo[3];
     float s[3];
     int B;
+    int64_t F;   // face count: the candidate walkers skip ids outside [0, F)
 };
 
 // A value known to be equal on every lane, moved to a scalar register.

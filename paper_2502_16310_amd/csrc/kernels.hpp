@@ -308,7 +308,8 @@ __device__ __forceinline__ void for_candidates(const dev::BinGrid &g, const int 
             const uint32_t s0k = __shfl(s0, k, dev::kWave);
             const uint32_t prek = __shfl(pre, k, dev::kWave);
             if (v >= total) return -1;
-            return g.ids[s0k + (v - prek)];
+            const int32_t id = g.ids[s0k + (v - prek)];
+            return id >= 0 && (int64_t)id < g.F ? id : -1;
         };
         int k = 0;
         int32_t f = fetch(0, k);
@@ -393,7 +394,8 @@ __device__ __forceinline__ void for_unique_candidates(const dev::BinGrid &g, con
                         if (s_bpre[mid] <= v) lo = mid;
                         else hi = mid - 1;
                     }
-                    id[q] = g.ids[s_bs0[lo] + (v - s_bpre[lo])];
+                    const int32_t f = g.ids[s_bs0[lo] + (v - s_bpre[lo])];
+                    id[q] = f >= 0 && (int64_t)f < g.F ? f : -1;
                 }
             }
 #pragma unroll
@@ -681,8 +683,14 @@ __device__ __forceinline__ void flag_own_bin_wave(const FlagArgs<D> &A, int64_t 
             if (!__ballot(mine && !flagged)) break;   // every cell of this bin decided
             const uint32_t e = c0 + (uint32_t)lane;
             if (e < s1) {
+                const int32_t f = A.bins.ids[e];
                 float r[RF];
-                dev::load_rec<D>(A.faces.rec, A.bins.ids[e], r);
+                if (f >= 0 && (int64_t)f < A.bins.F) {
+                    dev::load_rec<D>(A.faces.rec, f, r);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < RF; ++k) r[k] = __builtin_nanf("");   // never near
+                }
 #pragma unroll
                 for (int k = 0; k < D * D; ++k) s_v[lane][k] = r[k];
             }
@@ -2537,19 +2545,36 @@ __device__ __forceinline__ void link_faces_wave(const float *aabb, int64_t F, co
 
 // Nodes of block b in cell order: node k -> its block (nblk) and node key,
 // from the block's mask and first row noff[b].
-// Nodes of block b (wave-uniform): lane i writes cell i when it is set, at
-// noff[b] + (set cells below i), so the block's nodes go out as one
-// coalesced run of keys and block indices.
+// Nodes of blocks b0 .. b0 + 63 (below n; b0 wave-uniform): every lane loads
+// one block's mask, first node index and key, then the wave writes the
+// blocks' nodes block by block, lane i writing cell i when it is set at
+// noff + (set cells below i), so each block's nodes go out as one coalesced
+// run of keys and block indices.
 template <int D>
-__device__ __forceinline__ void node_map_wave(const unsigned long long *mask, const uint32_t *noff,
-                                              const uint32_t *keys, int64_t b, uint32_t *nblk, uint64_t *node_key) {
+__device__ __forceinline__ void node_map_chunk(const unsigned long long *mask, const uint32_t *noff,
+                                               const uint32_t *keys, int64_t b0, int64_t n, uint32_t *nblk,
+                                               uint64_t *node_key) {
     constexpr int CELLS = D == 3 ? 64 : 16;
-    const unsigned long long m = mask[b];
     const int lane = dev::lane_id();
-    if (lane < CELLS && ((m >> lane) & 1ull)) {
-        const int64_t k = (int64_t)noff[b] + dev::lanes_below(m);
-        nblk[k] = (uint32_t)b;
-        node_key[k] = (uint64_t)keys[b] * CELLS + (uint64_t)lane;
+    const int64_t b = b0 + lane;
+    unsigned long long m = 0ull;
+    uint32_t off = 0, key = 0;
+    if (b < n) {
+        m = mask[b];
+        off = noff[b];
+        key = keys[b];
+    }
+    for (uint64_t live = __ballot(m != 0ull); live; live &= live - 1ull) {
+        const int j = __builtin_ctzll(live);
+        const unsigned long long mj = ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(m >> 32), j) << 32) |
+                                      (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)m, j);
+        const uint32_t oj = (uint32_t)__builtin_amdgcn_readlane((int)off, j);
+        const uint32_t kj = (uint32_t)__builtin_amdgcn_readlane((int)key, j);
+        if (lane < CELLS && ((mj >> lane) & 1ull)) {
+            const int64_t k = (int64_t)oj + dev::lanes_below(mj);
+            nblk[k] = (uint32_t)(b0 + j);
+            node_key[k] = (uint64_t)kj * CELLS + (uint64_t)lane;
+        }
     }
 }
 

@@ -97,10 +97,10 @@ template <int D>
 __global__ __launch_bounds__(256) void k_node_map(const unsigned long long *mask, const uint32_t *noff,
                                                   const uint32_t *keys, int64_t n, uint32_t *nblk,
                                                   uint64_t *node_key) {
-    // one block per wave at a time
+    // 64 blocks per wave at a time
     const int64_t w0 = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * 256u + threadIdx.x) / 64u));
-    for (int64_t b = w0; b < n; b += (int64_t)gridDim.x * 4)
-        node_map_wave<D>(mask, noff, keys, b, nblk, node_key);
+    for (int64_t c = w0; c * 64 < n; c += (int64_t)gridDim.x * 4)
+        node_map_chunk<D>(mask, noff, keys, c * 64, n, nblk, node_key);
 }
 
 template <int D, int Q>
@@ -117,6 +117,7 @@ LinkArgs<D, Q> link_args(agal_geom g, agal_bins bn, agal_forest fo) {
     A.bins.off = bn->off;
     A.bins.ids = bn->ids;
     A.bins.B = bn->B;
+    A.bins.F = g->F;
     for (int a = 0; a < 3; ++a) {
         A.bins.lo[a] = bn->lo[a];
         A.bins.s[a] = bn->s[a];
@@ -334,7 +335,7 @@ agal_status links_forward_lists(agal_geom g, agal_bins bn, agal_forest fo, agal_
         A.q = lk->q;
         A.face = lk->face;
         ProfScope prof(ctx, "q_links", s);
-        const unsigned mgrid = (unsigned)std::min<int64_t>((n + 3) / 4, 16384);
+        const unsigned mgrid = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
         hipLaunchKernelGGL((k_node_map<D>), dim3(mgrid), dim3(256), 0, s, nmask, noff, LL.keys, n, nblk, lk->key);
         hipLaunchKernelGGL((k_links_rows<D, Q>), dim3((unsigned)(((int64_t)nn + kRowNodes - 1) / kRowNodes)), dim3(64), 0, s, A, lblk,
                            nblk, nn);

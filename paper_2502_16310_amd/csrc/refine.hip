@@ -271,6 +271,7 @@ agal_status refine_impl(agal_geom g, agal_bins bn, agal_forest fo, hipStream_t s
     bins.off = bn->off;
     bins.ids = bn->ids;
     bins.B = bn->B;
+    bins.F = g->F;
     for (int a = 0; a < 3; ++a) {
         bins.lo[a] = bn->lo[a];
         bins.s[a] = bn->s[a];
