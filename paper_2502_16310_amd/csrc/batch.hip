@@ -751,7 +751,7 @@ __global__ __launch_bounds__(64) void k_b_link_faces(const BodyDev *bodies, int 
 }
 
 template <int D, int Q>
-__global__ __launch_bounds__(64) void k_b_links_nodes(const BodyDev *bodies, int nb, const uint32_t *cnt,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_b_links_nodes(const BodyDev *bodies, int nb, const uint32_t *cnt,
                                                       const uint32_t *wg_pre) {
     const uint32_t it = blockIdx.x;
     const int b = body_of_wg(wg_pre, nb, it);

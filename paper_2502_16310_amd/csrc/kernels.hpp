@@ -2543,8 +2543,6 @@ __device__ __forceinline__ void link_faces_wave(const float *aabb, int64_t F, co
     }
 }
 
-// Nodes of block b in cell order: node k -> its block (nblk) and node key,
-// from the block's mask and first row noff[b].
 // Nodes of blocks b0 .. b0 + 63 (below n; b0 wave-uniform): every lane loads
 // one block's mask, first node index and key, then the wave writes the
 // blocks' nodes block by block, lane i writing cell i when it is set at

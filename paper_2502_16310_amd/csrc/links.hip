@@ -88,7 +88,7 @@ __global__ __launch_bounds__(64) void k_link_faces(const float *aabb, int64_t F,
 }
 
 template <int D, int Q>
-__global__ __launch_bounds__(64) void k_links_nodes(LinkArgs<D, Q> A, const uint32_t *lblk,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_links_nodes(LinkArgs<D, Q> A, const uint32_t *lblk,
                                                     unsigned long long *mask) {
     links_nodes_entries<D, Q>(A, lblk, mask, blockIdx.x, gridDim.x);
 }
