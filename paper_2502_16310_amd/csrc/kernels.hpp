@@ -2137,6 +2137,20 @@ __device__ __forceinline__ void link_scalars(const float o[3], const LinkFace<D>
     for (int k = 0; k < D; ++k) s[k] = w * lam[k] * inv;
 }
 
+// s += the DPP-moved s (control CTRL: row_shr:n = 0x110 + n, row_bcast:15 =
+// 0x142, row_bcast:31 = 0x143; ROWS: the rows written) on the lanes with use;
+// lanes without a source, or in rows not written, move 0.  Every lane active.
+template <int CTRL, int ROWS, int N>
+__device__ __forceinline__ void dpp_add(float (&s)[N], bool use) {
+    float up[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        up[k] = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s[k]), CTRL, ROWS, 0xF, false));
+    if (use)
+#pragma unroll
+        for (int k = 0; k < N; ++k) s[k] += up[k];
+}
+
 // The links of a tile of kAdjThreads nodes: the tile's face and weight rows
 // are one contiguous span, read in 64-slot chunks with coalesced loads, the
 // waves taking every kAdjWaves-th chunk, kAdjGroup chunks at a time with the
@@ -2254,21 +2268,30 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs<D, Q> &A, int64_t nod
 #pragma unroll
             for (int a = 0; a < 3; ++a) n[a] = R.n[a];
         }
-        // segmented inclusive sum over runs of equal f (every lane active here)
+        // segmented inclusive sum over runs of equal f (every lane active
+        // here), on DPP: within each row of 16 lanes by row shifts, then
+        // lane 15 of the previous row to rows 1 and 3, then lane 31 to rows 2
+        // and 3, each step taken by the lanes whose run reaches its source
         const int32_t fp = __shfl_up(f, 1, dev::kWave);
         const uint64_t heads = __ballot(lane == 0 || fp != f);
         const uint64_t upto = (2ull << lane) - 1ull;   // lanes 0 .. lane (all 64 at lane 63)
         const int start = 63 - __clzll(heads & upto);
-        for (int d = 1; d < dev::kWave; d <<= 1) {
-            const bool use = lane - d >= start;
-            if (!__ballot(use)) break;
-            float up[D];
-#pragma unroll
-            for (int k = 0; k < D; ++k) up[k] = __shfl_up(s[k], d, dev::kWave);
-            if (use)
-#pragma unroll
-                for (int k = 0; k < D; ++k) s[k] += up[k];
+        const int rl = lane & 15;
+        // within rows (row_shr:d); once no lane can use a shift, no longer one can
+        if (__ballot(rl >= 1 && lane - 1 >= start)) {
+            dpp_add<0x111, 0xF>(s, rl >= 1 && lane - 1 >= start);
+            if (__ballot(rl >= 2 && lane - 2 >= start)) {
+                dpp_add<0x112, 0xF>(s, rl >= 2 && lane - 2 >= start);
+                if (__ballot(rl >= 4 && lane - 4 >= start)) {
+                    dpp_add<0x114, 0xF>(s, rl >= 4 && lane - 4 >= start);
+                    if (__ballot(rl >= 8 && lane - 8 >= start)) dpp_add<0x118, 0xF>(s, rl >= 8 && lane - 8 >= start);
+                }
+            }
         }
+        const bool b15 = (lane & 16) && (lane & ~15) - 1 >= start;   // row_bcast:15 into rows 1 and 3
+        if (__ballot(b15)) dpp_add<0x142, 0xA>(s, b15);
+        const bool b31 = lane >= 32 && start <= 31;   // row_bcast:31 into rows 2 and 3
+        if (__ballot(b31)) dpp_add<0x143, 0xC>(s, b31);
         const bool tail = lane == dev::kWave - 1 || (((heads >> lane) >> 1) & 1ull);
         if (tail && f >= 0) to_lds(f, s, n);
     };
