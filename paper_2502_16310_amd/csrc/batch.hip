@@ -451,7 +451,7 @@ template <int D, int G>
 __global__ __launch_bounds__(64 * kFaceFlagWaves) void k_b_flag_faces(const BodyDev *bodies, int nb, int p,
                                                                      const uint32_t *cnt, const uint32_t *wg_pre) {
     __shared__ float s_rec[kFaceFlagWaves][G][dev::kRecFloats<D>];
-    __shared__ int s_i[kFaceFlagWaves][G][8];
+    __shared__ int s_i[kFaceFlagWaves][G][kFaceFlagInts];
     const uint32_t it = blockIdx.x;
     const int b = body_of_wg(wg_pre, nb, it);
     const BodyDev &B = bodies[b];

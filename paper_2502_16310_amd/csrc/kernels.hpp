@@ -766,6 +766,7 @@ __device__ __forceinline__ void prop_spread_item(const uint32_t *keys, int64_t n
 // and flag reads (measured on MI355X: 20,480 faces 68 -> 54 us with G = 4;
 // 327,680 faces 295 us with G = 16, 438 us with G = 4).
 constexpr int kFaceFlagWaves = 4;   // waves per workgroup
+constexpr int kFaceFlagInts = 10;   // per-face words of the wave's face table
 inline int face_flag_g(int64_t faces, int n_cu) {
     const int64_t want = 8 * 4 * (int64_t)n_cu;   // waves: eight per SIMD
     return faces >= 16 * want ? 16 : (faces >= 8 * want ? 8 : 4);
@@ -797,7 +798,7 @@ struct FaceFlagArgs {
 // pairs; index arithmetic stays 32-bit while the wave's total fits.
 template <int D, int G>
 __device__ __forceinline__ void flag_faces_wave(const FaceFlagArgs<D> &A, int64_t face0,
-                                                float (*s_rec)[dev::kRecFloats<D>], int (*s_i)[8]) {
+                                                float (*s_rec)[dev::kRecFloats<D>], int (*s_i)[kFaceFlagInts]) {
     constexpr int RF = dev::kRecFloats<D>;
     constexpr int CELLS = D == 3 ? 64 : 16;
     static_assert(G >= 2 && G <= 64 && (G & (G - 1)) == 0, "face search takes log2(G) steps");
@@ -834,7 +835,13 @@ __device__ __forceinline__ void flag_faces_wave(const FaceFlagArgs<D> &A, int64_
             s_i[lane][a] = ilo[a];
             s_i[lane][3 + a] = n[a];
         }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+            s_i[lane][8 + a] = n[a] > 1 ? (int)(uint32_t)((0x100000000ull + (uint64_t)n[a] - 1u) / (uint64_t)n[a]) : 0;
     }
+    // pair indices below 2^16 (every face of the wave): quotients by the
+    // per-axis cell counts as multiply-high by ceil(2^32 / n), exact there
+    const bool small = __ballot(cnt > 65536u) == 0ull;
     // 64-bit inclusive wave prefix of the pair counts
     uint64_t incl = cnt;
 #pragma unroll
@@ -850,7 +857,51 @@ __device__ __forceinline__ void flag_faces_wave(const FaceFlagArgs<D> &A, int64_
         s_i[lane][7] = (int)(uint32_t)(pre >> 32);
     }
     dev::wave_sync();
-    auto pair = [&](auto v) {
+    // A pair that needs the separating-axis test (its block exists at the
+    // level, its cell is not flagged yet) is queued with its cell centre,
+    // block and face; the queue is tested 64 pairs at a time, one per lane, so
+    // that the lanes of a step whose pairs were dropped do not idle through the
+    // test.  The test and what it writes are those of the pair itself.
+    constexpr int QCAP = 128;   // below 64 between steps, at most 64 added per step
+    __shared__ float s_qm[kFaceFlagWaves][3][QCAP];
+    __shared__ uint32_t s_qb[kFaceFlagWaves][QCAP];
+    __shared__ uint32_t s_qk[kFaceFlagWaves][QCAP];
+    const int wq = (int)(threadIdx.x / dev::kWave);
+    int nq = 0;   // wave-uniform
+    auto test = [&](int take) {
+        dev::wave_sync();
+        float m[3] = {0.0f, 0.0f, 0.0f};
+        uint32_t blk = 0, kc = 0;
+        if (lane < take) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) m[a] = s_qm[wq][a][lane];
+            blk = s_qb[wq][lane];
+            kc = s_qk[wq][lane];
+        }
+        dev::wave_sync();
+        if (lane < nq - take) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) s_qm[wq][a][lane] = s_qm[wq][a][take + lane];
+            s_qb[wq][lane] = s_qb[wq][take + lane];
+            s_qk[wq][lane] = s_qk[wq][take + lane];
+        }
+        nq -= take;
+        if (lane < take) {
+            const int k = (int)(kc >> 8), cell = (int)(kc & 255u);
+            float vv[D * D];
+#pragma unroll
+            for (int j = 0; j < D * D; ++j) vv[j] = s_rec[k][j];
+            bool hit;
+            if constexpr (D == 3) hit = dev::sat_triangle(vv, m, A.h);
+            else hit = dev::sat_segment(vv, m, A.h);
+            if (hit) {
+                A.cf[(int64_t)blk * CELLS + cell] = 1;
+                A.pmark[blk] = 1;
+            }
+        }
+    };
+    // pair v: its cell, then whether it is queued
+    auto pair = [&](auto v, float (&m)[3], uint32_t &qblk, uint32_t &qkc) -> bool {
         using T = decltype(v);
         auto pre_of = [&](int k) -> T {
             return (T)(((uint64_t)(uint32_t)s_i[k][7] << 32) | (uint32_t)s_i[k][6]);
@@ -859,19 +910,24 @@ __device__ __forceinline__ void flag_faces_wave(const FaceFlagArgs<D> &A, int64_
 #pragma unroll
         for (int step = G / 2; step >= 1; step >>= 1)
             if (pre_of(k + step) <= v) k += step;
-        T u = v - pre_of(k);
+        const T u = v - pre_of(k);
         int g[3] = {0, 0, 0};
-        const T n0 = (T)s_i[k][3];
-        g[0] = s_i[k][0] + (int)(u % n0);
-        u /= n0;
-        if constexpr (D == 3) {
-            const T n1 = (T)s_i[k][4];
-            g[1] = s_i[k][1] + (int)(u % n1);
-            g[2] = s_i[k][2] + (int)(u / n1);
+        const T n0 = (T)s_i[k][3], n1 = (T)s_i[k][4];
+        T q0, q1;
+        if (sizeof(T) == 4 && small) {
+            q0 = n0 > 1 ? (T)__umulhi((uint32_t)u, (uint32_t)s_i[k][8]) : u;
+            q1 = n1 > 1 ? (T)__umulhi((uint32_t)q0, (uint32_t)s_i[k][9]) : q0;
         } else {
-            g[1] = s_i[k][1] + (int)u;
+            q0 = u / n0;
+            q1 = q0 / n1;
         }
-        float m[3] = {0.0f, 0.0f, 0.0f};
+        g[0] = s_i[k][0] + (int)(u - q0 * n0);
+        if constexpr (D == 3) {
+            g[1] = s_i[k][1] + (int)(q0 - q1 * n1);
+            g[2] = s_i[k][2] + (int)q1;
+        } else {
+            g[1] = s_i[k][1] + (int)q0;
+        }
 #pragma unroll
         for (int a = 0; a < D; ++a) m[a] = dev::cell_centre(A.lo[a], g[a], A.dx[a]);
         int64_t blk = (int64_t)(g[1] >> 2) * A.NB[0] + (g[0] >> 2);
@@ -884,30 +940,36 @@ __device__ __forceinline__ void flag_faces_wave(const FaceFlagArgs<D> &A, int64_
             const uint32_t t = A.table[blk];
             const int bc[3] = {g[0] >> 2, g[1] >> 2, D == 3 ? g[2] >> 2 : 0};
             if ((int64_t)t >= A.n || A.keys[t] != dev::encode_key<D>(bc, A.level, A.R[0], A.R[1]))
-                return;   // no such block at this level
+                return false;   // no such block at this level
             blk = t;
         }
-        uint8_t *cp = A.cf + blk * CELLS + cell;
-        if (*cp) return;   // flagged already
-        float vv[D * D];
+        if (A.cf[blk * CELLS + cell]) return false;   // flagged already
+        qblk = (uint32_t)blk;   // a block index of the level (below 2^32)
+        qkc = ((uint32_t)k << 8) | (uint32_t)cell;
+        return true;
+    };
+    auto step = [&](bool valid, auto v) {
+        float m[3] = {0.0f, 0.0f, 0.0f};
+        uint32_t qblk = 0, qkc = 0;
+        const bool want = valid && pair(v, m, qblk, qkc);
+        const uint64_t bm = __ballot(want);
+        if (want) {
+            const int at = nq + dev::lanes_below(bm);
 #pragma unroll
-        for (int j = 0; j < D * D; ++j) vv[j] = s_rec[k][j];
-        bool hit;
-        if constexpr (D == 3) hit = dev::sat_triangle(vv, m, A.h);
-        else hit = dev::sat_segment(vv, m, A.h);
-        if (hit) {
-            *cp = 1;
-            A.pmark[blk] = 1;
+            for (int a = 0; a < 3; ++a) s_qm[wq][a][at] = m[a];
+            s_qb[wq][at] = qblk;
+            s_qk[wq][at] = qkc;
         }
+        nq += __popcll(bm);
+        if (nq >= dev::kWave) test(dev::kWave);
     };
     if (total <= 0xFFFFFFFFull) {
         const uint32_t tot = (uint32_t)total;
-        for (uint32_t c0 = 0; c0 < tot; c0 += dev::kWave)
-            if (c0 + lane < tot) pair((uint32_t)(c0 + lane));
+        for (uint32_t c0 = 0; c0 < tot; c0 += dev::kWave) step(c0 + lane < tot, (uint32_t)(c0 + lane));
     } else {
-        for (uint64_t c0 = 0; c0 < total; c0 += dev::kWave)
-            if (c0 + lane < total) pair((uint64_t)(c0 + lane));
+        for (uint64_t c0 = 0; c0 < total; c0 += dev::kWave) step(c0 + lane < total, (uint64_t)(c0 + lane));
     }
+    if (nq > 0) test(nq);
 }
 
 // 2:1 balance: a block of level m marked in this pass needs every neighbour

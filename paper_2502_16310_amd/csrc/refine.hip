@@ -51,7 +51,7 @@ __global__ void k_prop_commit(uint8_t *pm, int64_t n) {
 template <int D, int G>
 __global__ __launch_bounds__(64 * kFaceFlagWaves) void k_flag_faces(FaceFlagArgs<D> A) {
     __shared__ float s_rec[kFaceFlagWaves][G][dev::kRecFloats<D>];
-    __shared__ int s_i[kFaceFlagWaves][G][8];
+    __shared__ int s_i[kFaceFlagWaves][G][kFaceFlagInts];
     const int w = (int)threadIdx.x / dev::kWave;
     flag_faces_wave<D, G>(A, ((int64_t)blockIdx.x * kFaceFlagWaves + w) * G, s_rec[w], s_i[w]);
 }
