@@ -2072,7 +2072,7 @@ struct AdjArgs {
 
 constexpr int kAdjThreads = 256;   // nodes per tile = threads per workgroup
 constexpr int kAdjWaves = kAdjThreads / 64;
-constexpr int kAdjGroup = 4;      // chunks of 64 slots per wave per step
+constexpr int kAdjGroup = 4;      // slots per lane per wave step (queued between takes: up to 64 x this)
 constexpr int kAdjHashBits = 9;
 constexpr int kAdjHash = 1 << kAdjHashBits;   // per-workgroup face accumulators
 
@@ -2213,10 +2213,23 @@ __device__ __forceinline__ void dpp_add(float (&s)[N], bool use) {
         for (int k = 0; k < N; ++k) s[k] += up[k];
 }
 
+// Inclusive sum over the wave on DPP (every lane active): row shifts by 1, 2,
+// 4 and 8, then lane 15 of the previous row into rows 1 and 3 and lane 31
+// into rows 2 and 3; lanes without a source add 0.
+__device__ __forceinline__ uint32_t dpp_inclusive_sum(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);
+    return v;
+}
+
 // The links of a tile of kAdjThreads nodes: the tile's face and weight rows
-// are one contiguous span, read in 64-slot chunks with coalesced loads, the
-// waves taking every kAdjWaves-th chunk, kAdjGroup chunks at a time with the
-// next group's loads in flight.  Each wave appends the live slots it reads (a
+// are one contiguous span, read kAdjGroup slots per lane with 16-byte loads,
+// the waves taking every kAdjWaves-th step of 64 kAdjGroup slots with the
+// next step's loads in flight.  Each wave appends the live slots it reads (a
 // face and a non-zero weight) to a queue of its own and takes 64 at a time,
 // one link per lane, whatever the per-node link counts.  Queue order is slot
 // order, so the links of one face tend to sit in neighbouring lanes: a
@@ -2231,7 +2244,7 @@ __device__ __forceinline__ void dpp_add(float (&s)[N], bool use) {
 template <int D, int Q>
 __device__ __forceinline__ void adjoint_tile(const AdjArgs<D, Q> &A, int64_t node0) {
     constexpr int CELLS = D == 3 ? 64 : 16;
-    constexpr int QCAP = (kAdjGroup + 1) * dev::kWave;   // below 64 after the takes, 64 per chunk added
+    constexpr int QCAP = (kAdjGroup + 1) * dev::kWave;   // below 64 after the takes, 64 kAdjGroup per step added
     static_assert(Q <= 32, "direction index packed in 5 bits");
     __shared__ int32_t s_key[kAdjHash];
     __shared__ float s_acc[kAdjHash][D];
@@ -2359,45 +2372,70 @@ __device__ __forceinline__ void adjoint_tile(const AdjArgs<D, Q> &A, int64_t nod
     };
 
     const int span = nn * Q;
-    const int nch = (span + dev::kWave - 1) / dev::kWave;
-    constexpr int STEP = kAdjWaves * kAdjGroup;   // chunks per group over the workgroup
-    int32_t nf[kAdjGroup];
-    float nw[kAdjGroup];
-    auto load = [&](int c0) {   // chunks c0, c0 + kAdjWaves, ... of this wave
+    // Slots are read four per lane (16-byte loads of face ids and weights,
+    // 256 slots per wave step; the tile's span starts on a 16-byte boundary
+    // as kAdjThreads * Q is a multiple of four), the waves taking every
+    // kAdjWaves-th step with the next step's loads in flight; a partial step at
+    // the span's end, or rows not 16-byte aligned, go slot by slot.  Live
+    // slots are queued in slot order (a lane's at its prefix of the wave's
+    // live counts).
+    constexpr int kV = kAdjGroup;
+    static_assert(kV == 4, "int4 / float4 loads");
+    static_assert((kAdjThreads * Q) % kV == 0, "tile spans start on 16-byte boundaries");
+    const bool vec = ((reinterpret_cast<uintptr_t>(A.gq) | reinterpret_cast<uintptr_t>(A.face)) & 15u) == 0;
+    const int nst = (span + kV * dev::kWave - 1) / (kV * dev::kWave);
+    int4 nf;
+    float4 nw;
+    auto load = [&](int st) {
+        const int s0 = st * kV * dev::kWave + kV * lane;
+        if (vec && s0 + kV <= span) {
+            nf = *reinterpret_cast<const int4 *>(A.face + base + s0);
+            nw = *reinterpret_cast<const float4 *>(A.gq + base + s0);
+        } else {
+            int32_t lf[kV];
+            float lw[kV];
 #pragma unroll
-        for (int g = 0; g < kAdjGroup; ++g) {
-            const int s = (c0 + g * kAdjWaves) * dev::kWave + lane;
-            nf[g] = -1;
-            nw[g] = 0.0f;
-            if (s < span) {
-                nf[g] = A.face[base + s];
-                nw[g] = A.gq[base + s];
+            for (int k = 0; k < kV; ++k) {
+                lf[k] = -1;
+                lw[k] = 0.0f;
+                if (s0 + k < span) {
+                    lf[k] = A.face[base + s0 + k];
+                    lw[k] = A.gq[base + s0 + k];
+                }
             }
+            nf = make_int4(lf[0], lf[1], lf[2], lf[3]);
+            nw = make_float4(lw[0], lw[1], lw[2], lw[3]);
         }
     };
-    load(wv);
-    for (int c0 = wv; c0 < nch; c0 += STEP) {
-        int32_t f[kAdjGroup];
-        float w[kAdjGroup];
+    if (wv < nst) load(wv);
+    for (int st = wv; st < nst; st += kAdjWaves) {
+        const int32_t f[kV] = {nf.x, nf.y, nf.z, nf.w};
+        const float w[kV] = {nw.x, nw.y, nw.z, nw.w};
+        if (st + kAdjWaves < nst) load(st + kAdjWaves);
+        const int s0 = st * kV * dev::kWave + kV * lane;
+        int nl = s0 / Q, i = s0 - nl * Q;
+        uint32_t meta[kV], live = 0;
 #pragma unroll
-        for (int g = 0; g < kAdjGroup; ++g) {
-            f[g] = nf[g];
-            w[g] = nw[g];
-        }
-        if (c0 + STEP < nch) load(c0 + STEP);
-#pragma unroll
-        for (int g = 0; g < kAdjGroup; ++g) {
-            const int s = (c0 + g * kAdjWaves) * dev::kWave + lane;
-            const int nl = s / Q, i = s - nl * Q;
-            const bool live = i != 0 && f[g] >= 0 && w[g] != 0.0f;   // false past the span (f = -1)
-            const uint64_t m = __ballot(live);
-            if (live) {
-                const int at = qn + dev::lanes_below(m);
-                qm[at] = ((uint32_t)nl << 5) | (uint32_t)i;
-                qf[at] = f[g];
+        for (int k = 0; k < kV; ++k) {
+            // false past the span (f = -1)
+            live |= (i != 0 && f[k] >= 0 && w[k] != 0.0f) ? 1u << k : 0u;
+            meta[k] = ((uint32_t)nl << 5) | (uint32_t)i;
+            if (++i == Q) {
+                i = 0;
+                ++nl;
             }
-            qn += __popcll(m);
         }
+        const uint32_t cnt = (uint32_t)__popc(live);
+        const uint32_t incl = dpp_inclusive_sum(cnt);
+        int at = qn + (int)(incl - cnt);
+#pragma unroll
+        for (int k = 0; k < kV; ++k)
+            if ((live >> k) & 1u) {
+                qm[at] = meta[k];
+                qf[at] = f[k];
+                ++at;
+            }
+        qn += __builtin_amdgcn_readlane((int)incl, dev::kWave - 1);
         while (qn >= dev::kWave) take(qn);
     }
     if (qn > 0) take(qn);
