@@ -2032,8 +2032,11 @@ __device__ __forceinline__ void links_rows_nodes(const LinkArgs<D, Q> &A, const 
                 ++ll;
             }
         }
-        *reinterpret_cast<float4 *>(qd + e) = make_float4(qv[0], qv[1], qv[2], qv[3]);
-        *reinterpret_cast<int4 *>(fd + e) = make_int4(fv[0], fv[1], fv[2], fv[3]);
+        // rows are not read again by this pass: stored past the caches' keep policy
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        typedef int i4 __attribute__((ext_vector_type(4)));
+        __builtin_nontemporal_store(f4{qv[0], qv[1], qv[2], qv[3]}, reinterpret_cast<f4 *>(qd + e));
+        __builtin_nontemporal_store(i4{fv[0], fv[1], fv[2], fv[3]}, reinterpret_cast<i4 *>(fd + e));
         i += 256 % Q;
         l += 256 / Q;
         if (i >= Q) {
