@@ -1649,7 +1649,7 @@ __device__ __forceinline__ uint32_t bit_list4(uint32_t m) {
 }
 
 // u / n for n in 1 .. 4 and u < 4096 as (u * 2^16 / n) >> 16 (exact there:
-// the multiplier for 3 is 2^16 / 3 rounded up, off by less than 2^-17 of u).
+// the multiplier for 3 is 2^16 / 3 rounded up, off by less than 2^-16 of u).
 __device__ __forceinline__ uint32_t div_1to4(uint32_t u, uint32_t n) {
     return (u * (n == 3u ? 21846u : 65536u >> (n >> 1))) >> 16;
 }
