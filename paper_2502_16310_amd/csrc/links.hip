@@ -408,9 +408,10 @@ agal_status links_backward(agal_geom g, agal_links lk, const Lattice &lat, const
 // c_i . n < 0, bit 32 + i: c_i . n > 0, both for 0), 8 bytes per face; then
 // the nodes' rows are read as one flat run of slots, 64 consecutive slots per
 // wave and kClassU runs in flight per thread (face ids, then the faces' sign
-// words, loaded together).  Two ballots combine the codes of a node's slots
-// within the wave, and the node's first lane ORs them into its LDS word (two
-// or three LDS atomics per wave).
+// words, loaded together).  Every slot whose face has a sign bit for its
+// direction ORs its code (1 entering, 2 leaving) into its node's LDS word:
+// one LDS atomic instruction per run, its lanes those slots (a node's few
+// links meet at one word).
 template <int D, int Q>
 __global__ __launch_bounds__(256) void k_face_signs(const float *rec, int64_t F, unsigned long long *sign) {
     static_assert(Q <= 32, "direction bits in 32-bit halves");
@@ -455,6 +456,10 @@ __global__ __launch_bounds__(kClassThreads) void k_classify_nodes(const unsigned
     __syncthreads();
     const int span = nn * Q;
     const int32_t *row = face + node0 * Q;
+    // slot sl = k0 + u kClassThreads + tid: node sl / Q, direction sl % Q,
+    // advanced by kClassThreads slots a step
+    constexpr int SN = kClassThreads / Q, SI = kClassThreads % Q;
+    int node = tid / Q, i = tid - (tid / Q) * Q;
     for (int k0 = 0; k0 < span; k0 += kClassU * kClassThreads) {
         int32_t f[kClassU];
 #pragma unroll
@@ -467,21 +472,15 @@ __global__ __launch_bounds__(kClassThreads) void k_classify_nodes(const unsigned
         for (int u = 0; u < kClassU; ++u) t[u] = f[u] >= 0 && f[u] < F ? sign[f[u]] : 0ull;
 #pragma unroll
         for (int u = 0; u < kClassU; ++u) {
-            const int base = k0 + u * kClassThreads + (tid - lane);   // first slot of this wave's run
-            if (base >= span) break;                                   // wave-uniform
-            const int sl = base + lane;
-            const int i = sl % Q;   // the rest direction (i = 0) has bit 0 clear in both halves
-            const uint64_t enter = __ballot(((t[u] >> i) & 1ull) != 0ull);
-            const uint64_t leave = __ballot(((t[u] >> (32 + i)) & 1ull) != 0ull);
-            if (sl < span) {
-                const int node = sl / Q;
-                const int lo = max(node * Q - base, 0);
-                if (lane == lo) {
-                    const int hi = min(node * Q + Q - 1 - base, dev::kWave - 1);
-                    const uint64_t range = (hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1ull)) & ~((1ull << lo) - 1ull);
-                    const uint32_t c = ((enter & range) ? 1u : 0u) | ((leave & range) ? 2u : 0u);
-                    if (c) atomicOr(&s_code[node], c);
-                }
+            // the slot's code: 1 when its link enters the body through the face, 2 when it leaves
+            // (the rest direction, i = 0, has bit 0 clear in both halves; slots past the span have t = 0)
+            const uint32_t c = (uint32_t)((t[u] >> i) & 1ull) | ((uint32_t)((t[u] >> (32 + i)) & 1ull) << 1);
+            if (c) atomicOr(&s_code[node], c);
+            node += SN;
+            i += SI;
+            if (i >= Q) {
+                i -= Q;
+                ++node;
             }
         }
     }
