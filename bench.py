@@ -13,7 +13,11 @@ D3Q27), the largest single-body configuration.
 --config C4 times the batched form (64 bodies, one graph launch, forward and
 adjoint) against the same bodies through the single-body calls.  --config P0 /
 P1 runs the paper's bin-density study on its own refinement form (own-bin
-Euclidean flags with mark propagation) for B = 1, 2, 8, 16.
+Euclidean flags with mark propagation) for B = 1, 2, 8, 16.  --config M0 moves
+the C2 body by a fraction of a cell per step and times the whole re-adaptation
+step (import, bins, refinement, forest relation to the previous step, q, node
+classes).  The C2 line also reports node classification (`classify`) and the
+adjoint on the jittered 20,480-face sphere (`grad_C3`).
 
 Beside the GPU line: the FP64 oracle on one host core (`cpu_baseline`) and the same sample with its q phase
 split over 16 oracle processes (`cpu_baseline_all_cores`; `--cpu-workers`).
